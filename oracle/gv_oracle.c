@@ -1,0 +1,848 @@
+/*
+ * gv_oracle.c -- plain CPU FP64 reference for the general-voting
+ * maximum-depth search (Aiger et al., ICCV 2021, Sec. 3.2, Alg. 2).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline of the benchmark; never by the product path.  It shares no code
+ * with the HIP library.  Build: gcc -O2 -ffp-contract=off -fPIC -shared.
+ *
+ * What it computes (each step cites the paper):
+ *   - Surfaces in parametric form x_q = F_q(x_P; t) + f_q in the unit cube
+ *     (Sec. 3, Eq. 1).  Families: 2D line fitting by duality (Eq. 2),
+ *     hyperplanes in 3-space (Eq. 3), rays in 3-space (Sec. 4.3, the
+ *     two-equation line form, generalized to the dominant axis), and the
+ *     known-gravity calibrated pose (the 5DoF surface of Sec. 4.2.1 with
+ *     focal length 1).
+ *   - Canonization (Sec. 3.2.1): translate to the cell's minimum corner,
+ *     round essential parameters to eps'/((l+1) delta) and free parameters
+ *     to eps'/(l+1), group equal results and keep their multiplicity.
+ *   - Alg. 2: recursive 2^a subdivision, keep the surfaces that meet each
+ *     child, stop when every side is at most eps, return the argmax.
+ *     Pruning against the best leaf found so far (the Branch&Bound remark at
+ *     the end of Sec. 3.3) never changes the result because counts only
+ *     shrink down the tree.
+ *   - Inliers: the original surfaces whose canonization chain reaches the
+ *     chosen leaf (member tracking, Sec. 3.2.1).
+ *
+ * Parity pins: none of this code is checked against itself; see tests/.
+ */
+#include "gv_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+#define MAXD 4
+#define MAXL 48
+
+typedef struct {
+  /* linear: t[q][i] at p[2q+i], f[q] at p[4+q]; pose: W1,W2,W3,xi,eta,0 */
+  double p[6];
+  int32_t tag;
+  uint32_t w;
+} rec;
+
+typedef struct {
+  const or_problem *prob;
+  int fam, d, ell, exact;
+  double c;
+  double lo[MAXD], E[MAXD], inv[MAXD], epsn[MAXD];
+  int L[MAXD], Lstar, B, Bcell;
+  int abits[MAXL + 1], rem[MAXL + 2];
+  /* linear families */
+  double sf[MAXD];
+  double pad[MAXL][MAXD];
+  /* pose */
+  double sW, sW3, sXi, sEta, Rg2, padz, padk, epsk, ce;
+  /* search state */
+  uint64_t best;
+  uint64_t tests, expanded, pruned, merged, budget;
+  int over;
+} ctx;
+
+const char *or_status_str(int st) {
+  switch (st) {
+    case OR_OK: return "ok";
+    case OR_EINVAL: return "invalid argument";
+    case OR_ENOMEM: return "out of memory";
+    case OR_EBUFSZ: return "inlier buffer too small";
+    case OR_ERANGE: return "lattice too fine for exact binary64 arithmetic";
+    case OR_EBUDGET: return "test budget exhausted";
+  }
+  return "unknown status";
+}
+
+/* largest power of two <= x (x > 0, finite) */
+static double p2floor(double x) {
+  int e;
+  (void)frexp(x, &e); /* x = m * 2^e, m in [0.5, 1) */
+  return ldexp(1.0, e - 1);
+}
+
+static int imin(int a, int b) { return a < b ? a : b; }
+
+/* side of axis j at level m in the unit cube: 2^-min(m, L_j) */
+static double side(const ctx *C, int j, int m) { return ldexp(1.0, -imin(m, C->L[j])); }
+
+static void lin_axes(const ctx *C, int tag, int *nP, int P[2], int *nQ, int Q[2]) {
+  if (C->fam == OR_LINE2D) {
+    *nP = 1; P[0] = 0; *nQ = 1; Q[0] = 1;
+  } else if (C->fam == OR_PLANE3D) {
+    *nP = 2; P[0] = 0; P[1] = 1; *nQ = 1; Q[0] = 2;
+  } else { /* RAY3D: parameter axis = tag, dependents ascending */
+    int k = 0;
+    *nP = 1; P[0] = tag; *nQ = 2;
+    for (int j = 0; j < 3; j++)
+      if (j != tag) Q[k++] = j;
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Set-up: axes, levels, lattice steps, pads (normalization w.l.o.g. to  */
+/* the unit cube, Sec. 3; per-coordinate eps, Sec. 3.2).                 */
+/* ------------------------------------------------------------------ */
+static int ctx_init(ctx *C, const or_problem *p) {
+  memset(C, 0, sizeof(*C));
+  C->prob = p;
+  C->fam = p->family;
+  if (p->n < 0 || p->n > 0x7fffffffLL) return OR_EINVAL;
+  switch (C->fam) {
+    case OR_LINE2D: C->d = 2; C->ell = 1; break;
+    case OR_PLANE3D: C->d = 3; C->ell = 2; break;
+    case OR_RAY3D: C->d = 3; C->ell = 2; break;
+    case OR_POSE4DOF: C->d = 4; C->ell = 4; break;
+    default: return OR_EINVAL;
+  }
+  C->c = p->canon_c == 0.0 ? 1.0 : p->canon_c;
+  if (!(C->c > 0.0) || isnan(C->c)) return OR_EINVAL;
+  C->exact = isinf(C->c) ? 1 : 0;
+
+  int nuser = C->fam == OR_POSE4DOF ? 3 : C->d;
+  for (int j = 0; j < nuser; j++) {
+    if (!isfinite(p->lo[j]) || !isfinite(p->hi[j]) || !(p->hi[j] > p->lo[j])) return OR_EINVAL;
+    if (!isfinite(p->eps[j]) || !(p->eps[j] > 0.0)) return OR_EINVAL;
+    C->lo[j] = p->lo[j];
+    C->E[j] = p->hi[j] - p->lo[j];
+    C->inv[j] = 1.0 / C->E[j];
+    C->epsn[j] = p->eps[j] * C->inv[j];
+  }
+  if (C->fam == OR_POSE4DOF) {
+    /* x and y share one scale so that horizontal distances stay Euclidean */
+    if (C->E[0] != C->E[1]) return OR_EINVAL;
+    if (!isfinite(p->eps[3]) || !(p->eps[3] > 0.0)) return OR_EINVAL;
+    /* kappa axis: tan of the yaw offset inside one sector, fixed [-1, 1] */
+    C->lo[3] = -1.0; C->E[3] = 2.0; C->inv[3] = 0.5;
+    C->epsk = p->eps[3];
+    C->epsn[3] = C->epsk * 0.5;
+  }
+  /* L_j: smallest L >= 0 with E_j 2^-L <= eps_j (leaf sides at most eps) */
+  int Lstar = 0, Bcell = 0;
+  for (int j = 0; j < C->d; j++) {
+    double ej = (C->fam == OR_POSE4DOF && j == 3) ? C->epsk : p->eps[j];
+    int L = 0;
+    while (ldexp(C->E[j], -L) > ej) {
+      L++;
+      if (L > 40) return OR_EINVAL;
+    }
+    C->L[j] = L;
+    if (L > Lstar) Lstar = L;
+    Bcell += L;
+  }
+  if (Lstar < 1) return OR_EINVAL; /* the root alone would already be a leaf */
+  C->Lstar = Lstar;
+  C->Bcell = Bcell;
+  C->B = Bcell + (C->fam == OR_POSE4DOF ? 2 : 0);
+  if (C->B > 62) return OR_EINVAL;
+  /* key = count * 2^B + low bits must fit 64 bits */
+  if ((uint64_t)p->n >= (1ULL << (64 - C->B))) return OR_EINVAL;
+  for (int m = 0; m < Lstar; m++) {
+    int a = 0;
+    for (int j = 0; j < C->d; j++)
+      if (m < C->L[j]) a++;
+    C->abits[m] = a;
+  }
+  C->rem[Lstar] = 0;
+  for (int m = Lstar - 1; m >= 0; m--) C->rem[m] = C->rem[m + 1] + C->abits[m];
+
+  if (C->fam != OR_POSE4DOF) {
+    /* free step: largest power of two <= eps'/(l+1), eps' = eps/(c(L*+1));
+     * essential step at level m: free step * 2^min(m, L_P) = eps'/((l+1) delta) */
+    for (int q = 0; q < C->d; q++) {
+      if (C->exact) {
+        C->sf[q] = ldexp(1.0, -36);
+      } else {
+        double ep = C->epsn[q] / (C->c * (double)(Lstar + 1));
+        C->sf[q] = p2floor(ep / (double)(C->ell + 1));
+      }
+      if (!(C->sf[q] > 0.0)) return OR_EINVAL;
+      for (int m = 0; m < Lstar; m++) {
+        /* accumulated canonization deviation after levels 0..m */
+        double Em = C->exact ? 0.0 : (double)((m + 1) * (C->ell + 1)) * C->sf[q] * 0.5;
+        C->pad[m][q] = ceil((C->epsn[q] + Em) / C->sf[q]) * C->sf[q];
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Front end: observation -> normalized surface parameters (Eq. 1-3,    */
+/* Sec. 4.2.1, Sec. 4.3).                                               */
+/* ------------------------------------------------------------------ */
+static int front(const ctx *C, int64_t i, rec *r) {
+  const or_problem *p = C->prob;
+  memset(r, 0, sizeof(*r));
+  r->w = 1;
+  for (int k = 0; k < (C->fam == OR_RAY3D ? 6 : C->fam == OR_POSE4DOF ? 5 : C->d); k++)
+    if (!isfinite(p->col[k][i])) return OR_EINVAL;
+  if (C->fam == OR_LINE2D) {
+    /* point (x, y) -> dual line b = y - x a (vertical distance preserved) */
+    double x = p->col[0][i], y = p->col[1][i];
+    r->p[0] = -((x * C->E[0]) * C->inv[1]);
+    r->p[4] = ((y - x * C->lo[0]) - C->lo[1]) * C->inv[1];
+  } else if (C->fam == OR_PLANE3D) {
+    /* point (x, y, z) -> dual plane a0 = z - x a1 - y a2 */
+    double x = p->col[0][i], y = p->col[1][i], z = p->col[2][i];
+    r->p[0] = -((x * C->E[0]) * C->inv[2]);
+    r->p[1] = -((y * C->E[1]) * C->inv[2]);
+    r->p[4] = (((z - x * C->lo[0]) - y * C->lo[1]) - C->lo[2]) * C->inv[2];
+  } else if (C->fam == OR_RAY3D) {
+    /* ray w + s u -> x_q = w_q + (u_q/u_pi)(x_pi - w_pi), pi the dominant axis */
+    double w[3], u[3];
+    for (int k = 0; k < 3; k++) { w[k] = p->col[k][i]; u[k] = p->col[3 + k][i]; }
+    int pi = 0;
+    for (int k = 1; k < 3; k++)
+      if (fabs(u[k]) > fabs(u[pi])) pi = k;
+    if (u[pi] == 0.0) return OR_EINVAL;
+    r->tag = pi;
+    int qi = 0;
+    for (int q = 0; q < 3; q++) {
+      if (q == pi) continue;
+      double s = u[q] / u[pi];
+      r->p[2 * qi] = (s * C->E[pi]) * C->inv[q];
+      r->p[4 + qi] = ((w[q] - C->lo[q]) + s * (C->lo[pi] - w[pi])) * C->inv[q];
+      qi++;
+    }
+  } else {
+    /* correspondence (w, xi, eta) in normalized units; eta is the elevation
+     * tangent so that z = w3 - eta * horizontal distance */
+    r->p[0] = (p->col[0][i] - C->lo[0]) * C->inv[0];
+    r->p[1] = (p->col[1][i] - C->lo[1]) * C->inv[1];
+    r->p[2] = (p->col[2][i] - C->lo[2]) * C->inv[2];
+    r->p[3] = p->col[3][i];
+    r->p[4] = p->col[4][i] * C->ce;
+  }
+  return OR_OK;
+}
+
+/* POSE4DOF lattice: needs data bounds, so it runs after the front end. */
+static int pose_lattice(ctx *C) {
+  const or_problem *p = C->prob;
+  C->ce = C->E[0] * C->inv[2];
+  double Hmax = 0.0, R2 = 0.0;
+  for (int64_t i = 0; i < p->n; i++) {
+    rec r;
+    int st = front(C, i, &r);
+    if (st) return st;
+    double h = fabs(r.p[4]);
+    if (h > Hmax) Hmax = h;
+    double a0 = r.p[0] * r.p[0], a1 = (r.p[0] - 1.0) * (r.p[0] - 1.0);
+    double b0 = r.p[1] * r.p[1], b1 = (r.p[1] - 1.0) * (r.p[1] - 1.0);
+    double r2 = (a0 > a1 ? a0 : a1) + (b0 > b1 ? b0 : b1);
+    if (r2 > R2) R2 = r2;
+  }
+  int Lxy = C->L[0] > C->L[1] ? C->L[0] : C->L[1];
+  double Rg = ldexp(1.0, -Lxy); /* apex guard: one leaf xy side */
+  C->Rg2 = Rg * Rg;
+  if (C->exact) {
+    C->sW = C->sW3 = C->sXi = C->sEta = ldexp(1.0, -36);
+    C->padz = ceil(C->epsn[2] / C->sW3) * C->sW3;
+    C->padk = ceil(C->epsk / C->sXi) * C->sXi;
+    return OR_OK;
+  }
+  double l1 = (double)(C->ell + 1);
+  double ez = C->epsn[2] / (C->c * (double)(C->Lstar + 1));
+  double ek = C->epsk / (C->c * (double)(C->Lstar + 1));
+  double Hb = (Hmax > 0x1p-10 ? Hmax : 0x1p-10) * (1.0 + 0x1p-20);
+  double Rb = (sqrt(R2) + 0x1p-20) * (1.0 + 0x1p-20);
+  double pk0 = C->epsk + ek * 0.5;
+  double Bk = 1.0 + (1.0 + pk0) * (1.0 + pk0); /* bound on 1 + kappa^2 */
+  C->sW3 = p2floor(ez / l1);
+  C->sEta = p2floor(ez / (l1 * Rb));
+  double wz = ez / (l1 * Hb), wk = (ek * Rg) / (l1 * Bk);
+  C->sW = p2floor(wz < wk ? wz : wk);
+  C->sXi = p2floor(ek / (l1 * Bk));
+  C->padz = ceil((C->epsn[2] + ez * 0.5) / C->sW3) * C->sW3;
+  C->padk = ceil((C->epsk + ek * 0.5) / C->sXi) * C->sXi;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Canonization (Sec. 3.2.1).                                           */
+/* ------------------------------------------------------------------ */
+static void canon(const ctx *C, rec *r, int m, const int32_t *cc) {
+  if (C->fam == OR_POSE4DOF) {
+    /* fixed global lattice, applied once at the root */
+    if (m != 0) return;
+    r->p[0] = nearbyint(r->p[0] / C->sW) * C->sW;
+    r->p[1] = nearbyint(r->p[1] / C->sW) * C->sW;
+    r->p[2] = nearbyint(r->p[2] / C->sW3) * C->sW3;
+    r->p[3] = nearbyint(r->p[3] / C->sXi) * C->sXi;
+    r->p[4] = nearbyint(r->p[4] / C->sEta) * C->sEta;
+    r->p[5] = 0.0;
+    return;
+  }
+  if (C->exact && m != 0) return; /* exact mode: quantize once */
+  int nP, P[2], nQ, Q[2];
+  lin_axes(C, r->tag, &nP, P, &nQ, Q);
+  double u[MAXD];
+  for (int j = 0; j < C->d; j++) u[j] = (double)cc[j] * side(C, j, m);
+  for (int qi = 0; qi < nQ; qi++) {
+    int q = Q[qi];
+    double sf = C->sf[q];
+    /* 1. translate: value at the cell's min corner, relative to its q floor */
+    double floc = r->p[4 + qi];
+    for (int k = 0; k < nP; k++) floc = floc + r->p[2 * qi + k] * u[P[k]];
+    floc = floc - u[q];
+    /* 2. round each essential parameter to sf * 2^min(m, L_P) */
+    double tn[2];
+    for (int k = 0; k < nP; k++) {
+      double st = ldexp(sf, imin(m, C->L[P[k]]));
+      tn[k] = nearbyint(r->p[2 * qi + k] / st) * st;
+    }
+    /* 3. round the translated free parameter to sf */
+    double fl = nearbyint(floc / sf) * sf;
+    /* 4. translate back */
+    double fn = fl;
+    for (int k = 0; k < nP; k++) fn = fn - tn[k] * u[P[k]];
+    fn = fn + u[q];
+    for (int k = 0; k < nP; k++) r->p[2 * qi + k] = tn[k];
+    r->p[4 + qi] = fn;
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Surface / box predicate (Sec. 3.2.1 "two functions"; the subset of   */
+/* conditions of the Surface-Box paragraph: one interval test per      */
+/* dependent axis).  Surface canonized at level m, cell at level m+1.  */
+/* ------------------------------------------------------------------ */
+static double cross2(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
+
+static int meets_pose(const ctx *C, const rec *r, int m1, int sector, const int32_t *cc) {
+  double hx = side(C, 0, m1), hy = side(C, 1, m1), hz = side(C, 2, m1), hk = side(C, 3, m1);
+  double Xlo = (double)cc[0] * hx, Xhi = (double)(cc[0] + 1) * hx;
+  double Ylo = (double)cc[1] * hy, Yhi = (double)(cc[1] + 1) * hy;
+  double Zlo = (double)cc[2] * hz, Zhi = (double)(cc[2] + 1) * hz;
+  double Klo = 2.0 * ((double)cc[3] * hk) - 1.0, Khi = 2.0 * ((double)(cc[3] + 1) * hk) - 1.0;
+  double W1 = r->p[0], W2 = r->p[1], W3 = r->p[2], xi = r->p[3], eta = r->p[4];
+  double Alo = W1 - Xhi, Ahi = W1 - Xlo, Blo = W2 - Yhi, Bhi = W2 - Ylo;
+  double x0, x1, y0, y1; /* V = Rot_s(box of (W1 - X, W2 - Y)) */
+  switch (sector) {
+    case 0: x0 = Alo; x1 = Ahi; y0 = Blo; y1 = Bhi; break;
+    case 1: x0 = Blo; x1 = Bhi; y0 = -Ahi; y1 = -Alo; break;
+    case 2: x0 = -Ahi; x1 = -Alo; y0 = -Bhi; y1 = -Blo; break;
+    default: x0 = -Bhi; x1 = -Blo; y0 = Alo; y1 = Ahi; break;
+  }
+  /* z = W3 - eta * |v| over V: |v| spans [r_min, r_max] */
+  double dx = x0 > 0.0 ? x0 : (x1 < 0.0 ? -x1 : 0.0);
+  double dy = y0 > 0.0 ? y0 : (y1 < 0.0 ? -y1 : 0.0);
+  double rmin2 = dx * dx + dy * dy;
+  double mx0 = x0 * x0, mx1 = x1 * x1, my0 = y0 * y0, my1 = y1 * y1;
+  double rmax2 = (mx0 > mx1 ? mx0 : mx1) + (my0 > my1 ? my0 : my1);
+  double Glo = W3 - (Zhi + C->padz), Ghi = W3 - (Zlo - C->padz);
+  double Tlo, Thi, a;
+  if (eta >= 0.0) { Tlo = Glo; Thi = Ghi; a = eta; }
+  else { Tlo = -Ghi; Thi = -Glo; a = -eta; }
+  double a2 = a * a;
+  int zlo_ok = (Tlo <= 0.0) || (a2 * rmax2 >= Tlo * Tlo); /* a r_max >= Tlo */
+  int zhi_ok = (Thi >= 0.0) && (a2 * rmin2 <= Thi * Thi); /* a r_min <= Thi */
+  if (!(zlo_ok && zhi_ok)) return 0;
+  /* kappa = (v2 - xi v1)/(v1 + xi v2) with v1 + xi v2 > 0, over V */
+  if (rmin2 < C->Rg2) return 1; /* apex guard: kappa unbounded near the apex */
+  double Llo = Klo - C->padk, Lhi = Khi + C->padk;
+  double elx = 1.0 - Llo * xi, ely = Llo + xi; /* direction with kappa = Llo */
+  double ehx = 1.0 - Lhi * xi, ehy = Lhi + xi; /* direction with kappa = Lhi */
+  double ax, ay, bx, by; /* silhouette corners: V's angular span from a CCW to b */
+  if (x0 > 0.0) {
+    if (y0 > 0.0) { ax = x1; ay = y0; bx = x0; by = y1; }
+    else if (y1 < 0.0) { ax = x0; ay = y0; bx = x1; by = y1; }
+    else { ax = x0; ay = y0; bx = x0; by = y1; }
+  } else if (x1 < 0.0) {
+    if (y0 > 0.0) { ax = x1; ay = y1; bx = x0; by = y0; }
+    else if (y1 < 0.0) { ax = x0; ay = y1; bx = x1; by = y0; }
+    else { ax = x1; ay = y1; bx = x1; by = y0; }
+  } else {
+    if (y0 > 0.0) { ax = x1; ay = y0; bx = x0; by = y0; }
+    else if (y1 < 0.0) { ax = x0; ay = y1; bx = x1; by = y1; }
+    else return 1; /* apex inside V (not reachable: r_min >= R_g > 0) */
+  }
+  /* two arcs shorter than pi meet iff one holds an endpoint of the other */
+  if (cross2(elx, ely, ax, ay) >= 0.0 && cross2(ax, ay, ehx, ehy) >= 0.0) return 1;
+  if (cross2(elx, ely, bx, by) >= 0.0 && cross2(bx, by, ehx, ehy) >= 0.0) return 1;
+  if (cross2(ax, ay, elx, ely) >= 0.0 && cross2(elx, ely, bx, by) >= 0.0) return 1;
+  if (cross2(ax, ay, ehx, ehy) >= 0.0 && cross2(ehx, ehy, bx, by) >= 0.0) return 1;
+  return 0;
+}
+
+static int meets(const ctx *C, const rec *r, int m, int sector, const int32_t *cc) {
+  int m1 = m + 1;
+  if (C->fam == OR_POSE4DOF) return meets_pose(C, r, m1, sector, cc);
+  int nP, P[2], nQ, Q[2];
+  lin_axes(C, r->tag, &nP, P, &nQ, Q);
+  for (int qi = 0; qi < nQ; qi++) {
+    int q = Q[qi];
+    double gmin = r->p[4 + qi], gmax = r->p[4 + qi];
+    for (int k = 0; k < nP; k++) {
+      int j = P[k];
+      double h = side(C, j, m1);
+      double lo = (double)cc[j] * h, hi = (double)(cc[j] + 1) * h;
+      double a = r->p[2 * qi + k] * lo, b = r->p[2 * qi + k] * hi;
+      gmin = gmin + (a < b ? a : b);
+      gmax = gmax + (a < b ? b : a);
+    }
+    double h = side(C, q, m1);
+    double clo = (double)cc[q] * h, chi = (double)(cc[q] + 1) * h;
+    if (gmax < clo - C->pad[m][q]) return 0;
+    if (gmin > chi + C->pad[m][q]) return 0;
+  }
+  return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Grouping: equal canonical surfaces merge, multiplicities add.        */
+/* ------------------------------------------------------------------ */
+static int rec_cmp(const void *a, const void *b) {
+  const rec *x = (const rec *)a, *y = (const rec *)b;
+  if (x->tag != y->tag) return x->tag < y->tag ? -1 : 1;
+  for (int k = 0; k < 6; k++)
+    if (x->p[k] != y->p[k]) return x->p[k] < y->p[k] ? -1 : 1;
+  return 0;
+}
+
+static int64_t group(ctx *C, rec *S, int64_t n) {
+  if (C->prob->no_group || n < 2) return n;
+  qsort(S, (size_t)n, sizeof(rec), rec_cmp);
+  int64_t k = 0;
+  for (int64_t i = 1; i < n; i++) {
+    if (rec_cmp(&S[k], &S[i]) == 0) {
+      S[k].w += S[i].w;
+      C->merged++;
+    } else {
+      S[++k] = S[i];
+    }
+  }
+  return k + 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Cell tree: child digits in axis order, MSB first; leaf index =       */
+/* [sector] || digits of levels 0..L*-1.                                */
+/* ------------------------------------------------------------------ */
+static void child_coords(const ctx *C, int m, const int32_t *cc, int digit, int32_t *out) {
+  int a = C->abits[m], k = 0;
+  for (int j = 0; j < C->d; j++) {
+    if (m < C->L[j]) {
+      int b = (digit >> (a - 1 - k)) & 1;
+      out[j] = 2 * cc[j] + b;
+      k++;
+    } else {
+      out[j] = cc[j];
+    }
+  }
+}
+
+static uint64_t key_of(const ctx *C, uint64_t count, uint64_t idx) {
+  uint64_t mask = (C->B == 64) ? ~0ULL : ((1ULL << C->B) - 1ULL);
+  return (count << C->B) | (mask - idx);
+}
+
+/* filter S against one child; returns count, writes survivors */
+static uint64_t filter(ctx *C, const rec *S, int64_t n, int m, int sector, const int32_t *child,
+                       rec *out, int64_t *nout) {
+  uint64_t cnt = 0;
+  int64_t k = 0;
+  for (int64_t i = 0; i < n; i++) {
+    C->tests++;
+    if (meets(C, &S[i], m, sector, child)) {
+      cnt += S[i].w;
+      if (out) out[k] = S[i];
+      k++;
+    }
+  }
+  if (nout) *nout = k;
+  return cnt;
+}
+
+/* Alg. 2 with pruning: depth-first over children in index order. */
+static int expand(ctx *C, int m, int sector, const int32_t *cc, uint64_t prefix, const rec *S,
+                  int64_t n) {
+  int a = C->abits[m];
+  C->expanded++;
+  rec *buf = (rec *)malloc(sizeof(rec) * (size_t)(n > 0 ? n : 1));
+  if (!buf) return OR_ENOMEM;
+  for (int digit = 0; digit < (1 << a); digit++) {
+    if (C->budget && C->tests > C->budget) { free(buf); return OR_EBUDGET; }
+    int32_t ch[MAXD];
+    child_coords(C, m, cc, digit, ch);
+    int64_t nc;
+    uint64_t cnt = filter(C, S, n, m, sector, ch, buf, &nc);
+    uint64_t cpre = (prefix << a) | (uint64_t)digit;
+    uint64_t key = key_of(C, cnt, cpre << C->rem[m + 1]);
+    if (!C->prob->no_prune && key <= C->best) { C->pruned++; continue; }
+    if (m + 1 == C->Lstar) {
+      if (key > C->best) C->best = key;
+      continue;
+    }
+    for (int64_t i = 0; i < nc; i++) canon(C, &buf[i], m + 1, ch);
+    nc = group(C, buf, nc);
+    int st = expand(C, m + 1, sector, ch, cpre, buf, nc);
+    if (st) { free(buf); return st; }
+  }
+  free(buf);
+  return OR_OK;
+}
+
+/* Greedy dive: follow the best child (count, then lowest index) to a leaf;
+ * its key is an achieved leaf key, hence a valid starting lower bound. */
+static int dive(ctx *C, int sector, const rec *S0, int64_t n0) {
+  rec *cur = (rec *)malloc(sizeof(rec) * (size_t)(n0 > 0 ? n0 : 1));
+  rec *nxt = (rec *)malloc(sizeof(rec) * (size_t)(n0 > 0 ? n0 : 1));
+  if (!cur || !nxt) { free(cur); free(nxt); return OR_ENOMEM; }
+  memcpy(cur, S0, sizeof(rec) * (size_t)n0);
+  int64_t n = n0;
+  int32_t cc[MAXD] = {0, 0, 0, 0};
+  uint64_t prefix = (uint64_t)sector;
+  for (int m = 0; m < C->Lstar; m++) {
+    int a = C->abits[m], bestd = 0;
+    uint64_t bestc = 0;
+    for (int digit = 0; digit < (1 << a); digit++) {
+      int32_t ch[MAXD];
+      child_coords(C, m, cc, digit, ch);
+      uint64_t cnt = filter(C, cur, n, m, sector, ch, NULL, NULL);
+      if (digit == 0 || cnt > bestc) { bestc = cnt; bestd = digit; }
+    }
+    int32_t ch[MAXD];
+    child_coords(C, m, cc, bestd, ch);
+    int64_t nc;
+    filter(C, cur, n, m, sector, ch, nxt, &nc);
+    prefix = (prefix << a) | (uint64_t)bestd;
+    memcpy(cc, ch, sizeof(cc));
+    if (m + 1 < C->Lstar) {
+      for (int64_t i = 0; i < nc; i++) canon(C, &nxt[i], m + 1, ch);
+      nc = group(C, nxt, nc);
+    }
+    rec *t = cur; cur = nxt; nxt = t;
+    n = nc;
+    if (m + 1 == C->Lstar) {
+      uint64_t key = key_of(C, bestc, prefix);
+      if (key > C->best) C->best = key;
+    }
+  }
+  free(cur);
+  free(nxt);
+  return OR_OK;
+}
+
+/* decode a leaf index into the per-level path of cell coordinates */
+static int leaf_path(const ctx *C, uint64_t idx, int *sector, int32_t path[][MAXD]) {
+  if (C->B < 64 && idx >= (1ULL << C->B)) return OR_EINVAL;
+  *sector = C->fam == OR_POSE4DOF ? (int)(idx >> C->Bcell) : 0;
+  for (int j = 0; j < MAXD; j++) path[0][j] = 0;
+  for (int m = 0; m < C->Lstar; m++) {
+    int a = C->abits[m];
+    int digit = (int)((idx >> C->rem[m + 1]) & ((1ULL << a) - 1ULL));
+    child_coords(C, m, path[m], digit, path[m + 1]);
+  }
+  return OR_OK;
+}
+
+/* per-surface chain along a fixed path (member tracking by replay) */
+static int chain_passes(const ctx *C, rec r, int sector, int32_t path[][MAXD]) {
+  canon(C, &r, 0, path[0]);
+  for (int m = 0; m < C->Lstar; m++) {
+    if (!meets(C, &r, m, sector, path[m + 1])) return 0;
+    if (m + 1 < C->Lstar) canon(C, &r, m + 1, path[m + 1]);
+  }
+  return 1;
+}
+
+static int check_range(ctx *C, const rec *S, int64_t n) {
+  if (C->fam == OR_POSE4DOF) return OR_OK;
+  /* every value stays a multiple of sf/2 below 2^52 sf/2: exact in binary64 */
+  for (int64_t i = 0; i < n; i++) {
+    int nP, P[2], nQ, Q[2];
+    lin_axes(C, S[i].tag, &nP, P, &nQ, Q);
+    for (int qi = 0; qi < nQ; qi++) {
+      double M = fabs(S[i].p[4 + qi]) + 4.0;
+      for (int k = 0; k < nP; k++) M += fabs(S[i].p[2 * qi + k]);
+      if (!(M < ldexp(C->sf[Q[qi]], 48))) return OR_ERANGE;
+    }
+  }
+  return OR_OK;
+}
+
+static int build_root(ctx *C, rec **out, int64_t *nout) {
+  const or_problem *p = C->prob;
+  if (C->fam == OR_POSE4DOF) {
+    int st = pose_lattice(C);
+    if (st) return st;
+  }
+  rec *S = (rec *)malloc(sizeof(rec) * (size_t)(p->n > 0 ? p->n : 1));
+  if (!S) return OR_ENOMEM;
+  int32_t zero[MAXD] = {0, 0, 0, 0};
+  for (int64_t i = 0; i < p->n; i++) {
+    int st = front(C, i, &S[i]);
+    if (st) { free(S); return st; }
+    canon(C, &S[i], 0, zero);
+  }
+  int st = check_range(C, S, p->n);
+  if (st) { free(S); return st; }
+  *out = S;
+  *nout = p->n;
+  return OR_OK;
+}
+
+static void leaf_point(const ctx *C, int sector, const int32_t *lc, double *pt) {
+  for (int j = 0; j < C->d; j++) {
+    /* centre of the leaf cell: lo + E ((2c+1) 2^-(L+1)) */
+    double u = (double)(2 * lc[j] + 1) * ldexp(1.0, -(C->L[j] + 1));
+    pt[j] = C->lo[j] + C->E[j] * u;
+  }
+  if (C->fam == OR_POSE4DOF) {
+    double yaw = (double)sector * (M_PI / 2.0) + atan(pt[3]);
+    if (yaw < 0.0) yaw += 2.0 * M_PI;
+    if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
+    pt[3] = yaw;
+  }
+}
+
+static double now_s(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+static int replay_inliers(const ctx *C, uint64_t idx, uint64_t *count, int64_t *inl, int64_t cap,
+                          int64_t *ninl) {
+  int sector;
+  int32_t path[MAXL + 1][MAXD];
+  int st = leaf_path(C, idx, &sector, path);
+  if (st) return st;
+  int64_t k = 0;
+  for (int64_t i = 0; i < C->prob->n; i++) {
+    rec r;
+    st = front(C, i, &r);
+    if (st) return st;
+    if (chain_passes(C, r, sector, path)) {
+      if (inl && k < cap) inl[k] = i;
+      k++;
+    }
+  }
+  *count = (uint64_t)k;
+  if (ninl) *ninl = k;
+  return OR_OK;
+}
+
+int or_solve(const or_problem *p, or_result *res, int64_t *inliers, int64_t cap) {
+  ctx C;
+  memset(res, 0, sizeof(*res));
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  C.budget = p->test_budget;
+  rec *S;
+  int64_t n;
+  st = build_root(&C, &S, &n);
+  if (st) return st;
+  double t0 = now_s();
+  n = group(&C, S, n);
+  int nsec = C.fam == OR_POSE4DOF ? 4 : 1;
+  C.best = 0;
+  if (!p->no_dive)
+    for (int s = 0; s < nsec && !st; s++) st = dive(&C, s, S, n);
+  int32_t zero[MAXD] = {0, 0, 0, 0};
+  for (int s = 0; s < nsec && !st; s++) st = expand(&C, 0, s, zero, (uint64_t)s, S, n);
+  free(S);
+  res->tests = C.tests;
+  res->cells_expanded = C.expanded;
+  res->cells_pruned = C.pruned;
+  res->groups_merged = C.merged;
+  res->seconds = now_s() - t0;
+  if (st) return st;
+  uint64_t mask = (1ULL << C.B) - 1ULL;
+  res->key = C.best;
+  res->count = C.best >> C.B;
+  res->leaf_index = mask - (C.best & mask);
+  res->lstar = C.Lstar;
+  res->index_bits = C.B;
+  for (int j = 0; j < 4; j++) res->levels[j] = j < C.d ? C.L[j] : 0;
+  int sector;
+  int32_t path[MAXL + 1][MAXD];
+  leaf_path(&C, res->leaf_index, &sector, path);
+  res->sector = sector;
+  for (int j = 0; j < 4; j++) res->leaf_coords[j] = j < C.d ? path[C.Lstar][j] : 0;
+  leaf_point(&C, sector, path[C.Lstar], res->point);
+  uint64_t cnt;
+  int64_t ninl;
+  st = replay_inliers(&C, res->leaf_index, &cnt, inliers, cap, &ninl);
+  if (st) return st;
+  res->n_inliers = ninl;
+  if (cnt != res->count) return OR_EINVAL; /* internal consistency: never expected */
+  if (ninl > cap) return OR_EBUFSZ;
+  return OR_OK;
+}
+
+static void to_tf(const ctx *C, const rec *r, double *t, double *f, int32_t *tag) {
+  if (C->fam == OR_POSE4DOF) {
+    t[0] = r->p[0]; t[1] = r->p[1]; t[2] = r->p[3]; t[3] = r->p[4];
+    f[0] = r->p[2]; f[1] = r->p[5];
+  } else {
+    for (int k = 0; k < 4; k++) t[k] = r->p[k];
+    f[0] = r->p[4]; f[1] = r->p[5];
+  }
+  *tag = r->tag;
+}
+
+static void from_tf(const ctx *C, const double *t, const double *f, int32_t tag, rec *r) {
+  memset(r, 0, sizeof(*r));
+  r->w = 1;
+  r->tag = tag;
+  if (C->fam == OR_POSE4DOF) {
+    r->p[0] = t[0]; r->p[1] = t[1]; r->p[3] = t[2]; r->p[4] = t[3];
+    r->p[2] = f[0]; r->p[5] = f[1];
+  } else {
+    for (int k = 0; k < 4; k++) r->p[k] = t[k];
+    r->p[4] = f[0]; r->p[5] = f[1];
+  }
+}
+
+int or_parametrize(const or_problem *p, double *t, double *f, int32_t *tag) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (C.fam == OR_POSE4DOF) C.ce = C.E[0] * C.inv[2];
+  for (int64_t i = 0; i < p->n; i++) {
+    rec r;
+    st = front(&C, i, &r);
+    if (st) return st;
+    to_tf(&C, &r, t + 4 * i, f + 2 * i, tag + i);
+  }
+  return OR_OK;
+}
+
+int or_root_canon(const or_problem *p, double *t, double *f, int32_t *tag) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  rec *S;
+  int64_t n;
+  st = build_root(&C, &S, &n);
+  if (st) return st;
+  for (int64_t i = 0; i < n; i++) to_tf(&C, &S[i], t + 4 * i, f + 2 * i, tag + i);
+  free(S);
+  return OR_OK;
+}
+
+int or_leaf_count(const or_problem *p, uint64_t leaf_index, uint64_t *count, int64_t *inliers,
+                  int64_t cap) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (C.fam == OR_POSE4DOF) {
+    st = pose_lattice(&C);
+    if (st) return st;
+  }
+  int64_t ninl;
+  st = replay_inliers(&C, leaf_index, count, inliers, cap, &ninl);
+  if (st) return st;
+  if (inliers && ninl > cap) return OR_EBUFSZ;
+  return OR_OK;
+}
+
+int or_all_leaf_counts(const or_problem *p, uint32_t *out, uint64_t out_len) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (C.B > 24 || out_len < (1ULL << C.B)) return OR_EINVAL;
+  if (C.fam == OR_POSE4DOF) {
+    st = pose_lattice(&C);
+    if (st) return st;
+  }
+  rec *S = (rec *)malloc(sizeof(rec) * (size_t)(p->n > 0 ? p->n : 1));
+  if (!S) return OR_ENOMEM;
+  for (int64_t i = 0; i < p->n; i++) {
+    st = front(&C, i, &S[i]);
+    if (st) { free(S); return st; }
+  }
+  for (uint64_t idx = 0; idx < (1ULL << C.B); idx++) {
+    int sector;
+    int32_t path[MAXL + 1][MAXD];
+    leaf_path(&C, idx, &sector, path);
+    uint32_t k = 0;
+    for (int64_t i = 0; i < p->n; i++) k += (uint32_t)chain_passes(&C, S[i], sector, path);
+    out[idx] = k;
+  }
+  free(S);
+  return OR_OK;
+}
+
+int or_meets(const or_problem *p, const double *t, const double *f, int32_t tag, int level,
+             int32_t sector, const int32_t *coords) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (level < 0 || level >= C.Lstar) return OR_EINVAL;
+  if (C.fam == OR_POSE4DOF) {
+    st = pose_lattice(&C);
+    if (st) return st;
+  }
+  rec r;
+  from_tf(&C, t, f, tag, &r);
+  return meets(&C, &r, level, sector, coords);
+}
+
+int or_canon_at(const or_problem *p, const double *t, const double *f, int32_t tag, int level,
+                const int32_t *coords, double *t_out, double *f_out) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (level < 0 || level > C.Lstar) return OR_EINVAL;
+  if (C.fam == OR_POSE4DOF) {
+    st = pose_lattice(&C);
+    if (st) return st;
+  }
+  rec r;
+  from_tf(&C, t, f, tag, &r);
+  canon(&C, &r, level, coords);
+  int32_t tg;
+  to_tf(&C, &r, t_out, f_out, &tg);
+  return OR_OK;
+}
+
+int or_constants(const or_problem *p, double *out, int out_len) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (out_len < 24) return OR_EINVAL;
+  if (C.fam == OR_POSE4DOF) {
+    st = pose_lattice(&C);
+    if (st) return st;
+  }
+  memset(out, 0, sizeof(double) * (size_t)out_len);
+  out[0] = C.Lstar;
+  out[1] = C.B;
+  for (int j = 0; j < 4; j++) out[2 + j] = j < C.d ? C.L[j] : 0;
+  if (C.fam == OR_POSE4DOF) {
+    out[6] = C.sW; out[7] = C.sW3; out[8] = C.sXi; out[9] = C.sEta;
+    out[10] = C.padz; out[11] = C.padk;
+    out[14] = C.padz; out[15] = C.padk;
+  } else {
+    for (int j = 0; j < 4; j++) out[6 + j] = j < C.d ? C.sf[j] : 0;
+    for (int j = 0; j < 4; j++) out[10 + j] = j < C.d ? C.pad[0][j] : 0;
+    for (int j = 0; j < 4; j++) out[14 + j] = j < C.d ? C.pad[C.Lstar - 1][j] : 0;
+  }
+  out[18] = sqrt(C.Rg2);
+  out[19] = C.epsn[0]; out[20] = C.epsn[1]; out[21] = C.epsn[2]; out[22] = C.epsn[3];
+  out[23] = C.exact;
+  return OR_OK;
+}
