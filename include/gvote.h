@@ -1,0 +1,158 @@
+/*
+ * gvote.h -- C ABI of the MI355X general-voting library.
+ *
+ * The library finds, among k-surfaces in parametric form, the point of a
+ * domain box in R^d that the most surfaces pass within eps of, together with
+ * those surfaces (the maximum-depth / maximum-incidence problem of Aiger,
+ * Lynen, Hosang, Zeisl, ICCV 2021, Sec. 3; Alg. 2 "Efficient Generalized
+ * Voting", with the canonization of Sec. 3.2.1 and pruning of every cell
+ * whose count cannot beat the best leaf found so far).
+ *
+ * All calls return gv_status: GV_OK (0) or a negative error code.  No call
+ * takes or returns a framework type: pointers are plain host or device
+ * addresses, sizes are 64-bit.
+ *
+ * Families and their observation columns (structure of arrays, binary64):
+ *   GV_LINE2D   cols (x, y)             axes (a, b):   point -> dual line
+ *                                        b = y - x a (Sec. 3, Eq. 2).
+ *   GV_PLANE3D  cols (x, y, z)          axes (a1, a2, a0): point -> dual plane
+ *                                        a0 = z - x a1 - y a2 (Sec. 4.1, Eq. 3).
+ *   GV_RAY3D    cols (wx, wy, wz, ux, uy, uz)  axes (x, y, z): ray w + s u as
+ *                                        two lines over its dominant axis
+ *                                        (Sec. 4.3, the y = ax+b, z = cx+d form).
+ *   GV_POSE4DOF cols (wx, wy, wz, xi, eta)  axes (x, y, z, yaw): a 2D-3D match
+ *                                        for a camera with known gravity and
+ *                                        unit focal length (the surface of
+ *                                        Sec. 4.2.1 with f = 1); xi = lateral
+ *                                        over forward, eta = elevation tangent.
+ *                                        Requires hi[0]-lo[0] == hi[1]-lo[1];
+ *                                        yaw always spans [0, 2 pi) in four
+ *                                        sectors, lo[3]/hi[3] are ignored.
+ *
+ * Per-axis eps (Sec. 3.2, "different eps for each coordinate"): leaves are
+ * the cells of the dyadic subdivision of the box whose side on axis j is at
+ * most eps[j]; a surface counts at a leaf when, at every level of the
+ * descent, its canonized version passes within eps plus the accumulated
+ * rounding allowance of the child cell, separately on each dependent axis.
+ * The chosen leaf has the largest count; ties go to the lowest leaf index
+ * (child digits in axis order, most significant first, POSE4DOF sector on
+ * top).  Results are deterministic and do not depend on batching.
+ */
+#ifndef GVOTE_H
+#define GVOTE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gv_status;
+enum {
+  GV_OK = 0,
+  GV_EINVAL = -1,    /* bad family, n, box, eps, NaN input, E_x != E_y, ... */
+  GV_ENOMEM = -2,    /* device or host allocation failed */
+  GV_ETOOBIG = -3,   /* the problem alone exceeds the context memory budget */
+  GV_EBUFSZ = -4,    /* inlier buffer too small: n_inliers holds the need */
+  GV_EAGAIN = -5,    /* gv_poll: not finished yet */
+  GV_ETIMEDOUT = -6, /* gv_poll: timeout expired */
+  GV_ECANCELED = -7, /* ticket was cancelled */
+  GV_EDEVICE = -8,   /* HIP runtime error; text in gv_last_error */
+  GV_ERANGE = -9     /* lattice too fine for the exact device arithmetic */
+};
+
+typedef enum { GV_LINE2D = 1, GV_PLANE3D = 2, GV_RAY3D = 3, GV_POSE4DOF = 4 } gv_family;
+
+/* GV_FP64_PLAIN: every predicate decision in binary64.
+ * GV_FP32_FILTER: binary32 evaluation with a certified forward-error bound;
+ * only decisions inside the bound are re-evaluated in binary64, so every
+ * decision (hence every count) equals the binary64 one.  For the linear
+ * families both modes evaluate the same exact small-integer predicate. */
+typedef enum { GV_FP64_PLAIN = 0, GV_FP32_FILTER = 1 } gv_precision;
+
+typedef struct gv_ctx gv_ctx;
+
+typedef struct {
+  int device;                 /* HIP device ordinal */
+  uint64_t mem_budget_bytes;  /* 0: 60% of the device's free memory */
+  void *hip_stream;           /* optional hipStream_t to run on; NULL: own stream */
+  const char *autotune_cache; /* optional path of the tile autotuner cache */
+} gv_ctx_config;
+
+typedef struct {
+  gv_family family;
+  int64_t n;                  /* number of observations, 0 <= n < 2^31 */
+  const double *col[6];       /* SoA columns in the family order above */
+  int cols_on_device;         /* 1: col[] are device pointers (borrowed until
+                                 the call returns / the ticket is polled);
+                                 0: host pointers (copied during the call) */
+  double lo[4], hi[4];        /* domain box, user units, family axis order */
+  double eps[4];              /* per-axis eps, user units; POSE4DOF eps[3] is
+                                 the yaw tolerance in radians */
+  double canon_c;             /* eps' = eps / (c (L*+1)); 0 -> 1.0 */
+  gv_precision precision;
+} gv_problem;
+
+typedef struct {
+  uint64_t tests;             /* (canonical surface, child cell) predicate evaluations */
+  uint64_t fp64_rechecks;     /* predicate halves re-evaluated in binary64 */
+  uint64_t cells_expanded, cells_pruned, groups_merged;
+  uint32_t levels;            /* L*: depth of the leaves */
+  double ms_total, ms_kernels;
+} gv_stats;
+
+typedef struct {
+  double point[4];            /* leaf centre, user units; POSE4DOF (x,y,z,yaw), yaw in [0,2pi) */
+  uint64_t count;             /* maximum depth: number of original surfaces */
+  uint64_t leaf_index;
+  int32_t sector;             /* POSE4DOF yaw sector (0..3), else 0 */
+  int32_t leaf_coords[4];
+  int64_t *inliers;           /* caller buffer (host), sorted ascending */
+  uint64_t inliers_cap;
+  uint64_t n_inliers;         /* on GV_EBUFSZ: required capacity */
+  double bound[4];            /* per-axis allowance: eps + rounding allowance, user units */
+  gv_stats stats;
+} gv_result;
+
+/* Create a context on cfg->device.  Owns all library device memory; *out is
+ * NULL on failure. */
+gv_status gv_create(gv_ctx **out, const gv_ctx_config *cfg);
+
+/* Release the context and every device allocation it owns. */
+gv_status gv_destroy(gv_ctx *ctx);
+
+/* Solve one problem, blocking (Alg. 2 end to end: front end, root
+ * canonization and grouping, greedy dive, depth-first frontier expansion with
+ * pruning, best-key reduction, path-replay inlier extraction).  Calls on one
+ * context are serialized. */
+gv_status gv_solve(gv_ctx *ctx, const gv_problem *p, gv_result *r);
+
+/* Front end only (Eq. 1-3 and the posing surface): writes the normalized
+ * parameters, row-major, t_out n x 4 and f_out n x 2 (host buffers), and
+ * tag_out n (RAY3D parameter axis, else 0; may be NULL).  Layout per family:
+ * LINE2D t=(t,0,0,0) f=(f,0); PLANE3D t=(t1,t2,0,0) f=(f,0); RAY3D
+ * t=(t_q1,0,t_q2,0) f=(f_q1,f_q2); POSE4DOF t=(W1,W2,xi,eta') f=(W3,0). */
+gv_status gv_parametrize(gv_ctx *ctx, const gv_problem *p, double *t_out, double *f_out,
+                         int32_t *tag_out);
+
+/* Continuous batching: enqueue a problem (columns copied or borrowed as in
+ * gv_problem) and return a ticket.  Problems run concurrently on the device,
+ * admitted as memory frees up; results equal gv_solve's. */
+gv_status gv_submit(gv_ctx *ctx, const gv_problem *p, uint64_t *ticket);
+
+/* Wait up to timeout_ms (0: do not wait, <0: forever) for a ticket; on
+ * success fills *r (inliers into r->inliers) and retires the ticket. */
+gv_status gv_poll(gv_ctx *ctx, uint64_t ticket, gv_result *r, int timeout_ms);
+
+/* Cancel a pending ticket; a later poll returns GV_ECANCELED. */
+gv_status gv_cancel(gv_ctx *ctx, uint64_t ticket);
+
+/* Static text for a status code. */
+const char *gv_status_str(gv_status s);
+
+/* Text of the last error on this context (thread-local copy), "" if none. */
+const char *gv_last_error(gv_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,377 @@
+// gv_device.h -- device-side data layout and per-family arithmetic of the
+// MI355X general-voting library (gfx950, wave64).
+//
+// Linear families (LINE2D, PLANE3D, RAY3D) carry each canonical surface in
+// a cell-relative integer lattice form: after the root canonization every
+// parameter is a multiple of the free step s_f (Sec. 3.2.1: essential
+// parameters rounded to eps'/((l+1) delta), free parameters to eps'/(l+1)),
+// so the surface restricted to a cell is fully described by
+//   K_i = t_i / s_t,i(m)     (s_t,i(m) = s_f * 2^min(m, L_i), an integer)
+//   F_q = (G_q(u) - u_q) / s_f   (its height at the cell's min corner)
+// and both the child test and the next canonization are exact small-integer
+// arithmetic in units of s_f/2.  The POSE4DOF family is quantized once at the
+// root and evaluated in binary64 (or binary32 with a certified bound).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GV_MAXL 40
+#define GV_MAXD 4
+#define GV_ITEM 1024  // entries per work item (one wave)
+
+enum { FAM_LINE2D = 1, FAM_PLANE3D = 2, FAM_RAY3D = 3, FAM_POSE4DOF = 4 };
+
+// Per-level constants for the test from level m to level m+1.
+struct LevelC {
+  int32_t split[4];   // 1 if axis j splits at level m
+  int32_t H[4];       // h_j(m) / s_f,j  (linear families)
+  int32_t padu[4];    // 2 pad_j(m) / s_f,j (linear families)
+  int32_t abits;      // number of split axes
+  int32_t rem_next;   // index bits below level m+1
+  uint8_t cbits[16];  // child digit -> bit j set iff b_j = 1
+};
+
+struct ProbC {
+  int32_t fam, d, Lstar, B, Bcell, nsec;
+  int32_t L[4];
+  uint64_t idxmask;        // 2^B - 1
+  // front end
+  double lo[4], E[4], inv[4], ce;
+  // linear lattice
+  double sf[4], inv_sf[4];
+  // pose lattice
+  double sW, sW3, sXi, sEta, Rg2, padz, padk;
+  double inv_sW, inv_sW3, inv_sXi, inv_sEta;
+  float Rg2f, padzf, padkf, _pf;
+  LevelC lev[GV_MAXL];
+};
+
+struct Cell {
+  int32_t c[4];
+  uint64_t prefix;   // index bits of this cell (sector on top for POSE4DOF)
+  uint64_t off;      // first entry of its list in the batch
+  uint32_t len;      // number of entries
+  uint32_t sector;   // POSE4DOF yaw sector, else 0
+};
+
+struct Item {
+  uint32_t cell, start;
+};
+
+// Linear-family entries (cell-relative lattice integers + multiplicity).
+struct __attribute__((aligned(16))) EntL2 { int32_t K, F, w, _; };                 // LINE2D
+struct __attribute__((aligned(16))) EntP3 { int32_t K1, K2, F, w; };               // PLANE3D
+struct __attribute__((aligned(8))) EntR3 { int32_t K1, K2, F1, F2, w, tag; };     // RAY3D: K_q over axis tag
+
+// POSE4DOF entries: quantized parameters, weight, index of the root record.
+struct __attribute__((aligned(16))) EntQ32 { float W1, W2, W3, xi, eta; uint32_t w, ridx, _; };
+struct __attribute__((aligned(16))) EntQ64 { double W1, W2, W3, xi, eta; uint32_t w, ridx; };
+
+template <int FAM> struct EntOf;
+template <> struct EntOf<FAM_LINE2D> { using T = EntL2; };
+template <> struct EntOf<FAM_PLANE3D> { using T = EntP3; };
+template <> struct EntOf<FAM_RAY3D> { using T = EntR3; };
+
+// round-half-to-even of x/2 for an integer x
+__device__ __host__ inline int32_t rne_half(int32_t x) {
+  int32_t q = x >> 1;  // floor(x/2)
+  return (x & 1) ? (q + (q & 1)) : q;
+}
+
+__device__ inline int32_t imin32(int32_t a, int32_t b) { return a < b ? a : b; }
+__device__ inline int32_t imax32(int32_t a, int32_t b) { return a < b ? b : a; }
+
+// ---------------------------------------------------------------------------
+// Front end (binary64, operation order fixed, no contraction):
+// observation -> normalized (t, f, tag).  Returns false on non-finite input
+// or a zero ray direction.
+// ---------------------------------------------------------------------------
+__device__ inline bool front_eval(int fam, const double* const* col, int64_t i, const ProbC& P,
+                                  double t[4], double f[2], int32_t* tag) {
+  t[0] = t[1] = t[2] = t[3] = 0.0;
+  f[0] = f[1] = 0.0;
+  *tag = 0;
+  if (fam == FAM_LINE2D) {
+    double x = col[0][i], y = col[1][i];
+    if (!isfinite(x) || !isfinite(y)) return false;
+    t[0] = -((x * P.E[0]) * P.inv[1]);
+    f[0] = ((y - x * P.lo[0]) - P.lo[1]) * P.inv[1];
+  } else if (fam == FAM_PLANE3D) {
+    double x = col[0][i], y = col[1][i], z = col[2][i];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return false;
+    t[0] = -((x * P.E[0]) * P.inv[2]);
+    t[1] = -((y * P.E[1]) * P.inv[2]);
+    f[0] = (((z - x * P.lo[0]) - y * P.lo[1]) - P.lo[2]) * P.inv[2];
+  } else if (fam == FAM_RAY3D) {
+    double w[3], u[3];
+    for (int k = 0; k < 3; k++) {
+      w[k] = col[k][i];
+      u[k] = col[3 + k][i];
+      if (!isfinite(w[k]) || !isfinite(u[k])) return false;
+    }
+    int pi = 0;
+    if (fabs(u[1]) > fabs(u[pi])) pi = 1;
+    if (fabs(u[2]) > fabs(u[pi])) pi = 2;
+    if (u[pi] == 0.0) return false;
+    *tag = pi;
+    int qi = 0;
+    for (int q = 0; q < 3; q++) {
+      if (q == pi) continue;
+      double s = u[q] / u[pi];
+      t[2 * qi] = (s * P.E[pi]) * P.inv[q];
+      f[qi] = ((w[q] - P.lo[q]) + s * (P.lo[pi] - w[pi])) * P.inv[q];
+      qi++;
+    }
+  } else {
+    double wx = col[0][i], wy = col[1][i], wz = col[2][i], xi = col[3][i], eta = col[4][i];
+    if (!isfinite(wx) || !isfinite(wy) || !isfinite(wz) || !isfinite(xi) || !isfinite(eta)) return false;
+    t[0] = (wx - P.lo[0]) * P.inv[0];  // W1
+    t[1] = (wy - P.lo[1]) * P.inv[1];  // W2
+    t[2] = xi;
+    t[3] = eta * P.ce;                 // eta' in normalized z units
+    f[0] = (wz - P.lo[2]) * P.inv[2];  // W3
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Linear families: surface state in registers.
+// ---------------------------------------------------------------------------
+struct LinS {
+  int32_t K[2][2];  // K[qi][pi]
+  int32_t F[2];
+  int32_t w, tag;
+};
+
+template <int FAM> __device__ inline constexpr int nQ() { return FAM == FAM_RAY3D ? 2 : 1; }
+template <int FAM> __device__ inline constexpr int nP() { return FAM == FAM_PLANE3D ? 2 : 1; }
+
+template <int FAM> __device__ inline int Pax(const LinS& s, int pi) {
+  if (FAM == FAM_LINE2D) return 0;
+  if (FAM == FAM_PLANE3D) return pi;
+  return s.tag;
+}
+template <int FAM> __device__ inline int Qax(const LinS& s, int qi) {
+  if (FAM == FAM_LINE2D) return 1;
+  if (FAM == FAM_PLANE3D) return 2;
+  // RAY3D: the two non-parameter axes, ascending
+  int t = s.tag;
+  return qi == 0 ? (t == 0 ? 1 : 0) : (t == 2 ? 1 : 2);
+}
+
+template <int FAM> __device__ inline LinS load_lin(const typename EntOf<FAM>::T& e) {
+  LinS s;
+  s.K[0][1] = s.K[1][0] = s.K[1][1] = 0;
+  s.F[1] = 0;
+  s.tag = 0;
+  if constexpr (FAM == FAM_LINE2D) {
+    s.K[0][0] = e.K; s.F[0] = e.F; s.w = e.w;
+  } else if constexpr (FAM == FAM_PLANE3D) {
+    s.K[0][0] = e.K1; s.K[0][1] = e.K2; s.F[0] = e.F; s.w = e.w;
+  } else {
+    s.K[0][0] = e.K1; s.K[1][0] = e.K2; s.F[0] = e.F1; s.F[1] = e.F2; s.w = e.w; s.tag = e.tag;
+  }
+  return s;
+}
+
+template <int FAM> __device__ inline typename EntOf<FAM>::T store_lin(const LinS& s) {
+  typename EntOf<FAM>::T e;
+  if constexpr (FAM == FAM_LINE2D) {
+    e.K = s.K[0][0]; e.F = s.F[0]; e.w = s.w; e._ = 0;
+  } else if constexpr (FAM == FAM_PLANE3D) {
+    e.K1 = s.K[0][0]; e.K2 = s.K[0][1]; e.F = s.F[0]; e.w = s.w;
+  } else {
+    e.K1 = s.K[0][0]; e.K2 = s.K[1][0]; e.F1 = s.F[0]; e.F2 = s.F[1]; e.w = s.w; e.tag = s.tag;
+  }
+  return e;
+}
+
+// per-lane selection from a small uniform array (avoids scratch indexing)
+__device__ inline int32_t sel4(const int32_t* a, int j) {
+  return j == 0 ? a[0] : (j == 1 ? a[1] : (j == 2 ? a[2] : a[3]));
+}
+
+// Test of the surface (canonized at the parent, level m) against child digit
+// ch: for every dependent axis q the surface's range over the child's
+// parameter box must reach the child's q-interval widened by pad(m).
+template <int FAM> __device__ inline bool lin_meets(const LinS& s, const LevelC& lv, uint32_t cb) {
+  bool ok = true;
+#pragma unroll
+  for (int qi = 0; qi < nQ<FAM>(); qi++) {
+    int q = Qax<FAM>(s, qi);
+    int32_t gmin = 2 * s.F[qi], gmax = gmin;
+#pragma unroll
+    for (int pi = 0; pi < nP<FAM>(); pi++) {
+      int j = Pax<FAM>(s, pi);
+      int32_t b = (int32_t)((cb >> j) & 1u);
+      int32_t sp = sel4(lv.split, j);
+      int32_t lo = sp ? b : 0, hi = sp ? b + 1 : 2;
+      int32_t K = s.K[qi][pi];
+      int32_t x = K * lo, y = K * hi;
+      gmin += imin32(x, y);
+      gmax += imax32(x, y);
+    }
+    int32_t bq = (int32_t)((cb >> q) & 1u);
+    int32_t H = sel4(lv.H, q), pad = sel4(lv.padu, q);
+    int32_t spq = sel4(lv.split, q);
+    int32_t qlo = spq ? bq * H : 0, qhi = spq ? (bq + 1) * H : 2 * H;
+    ok = ok && (gmax >= qlo - pad) && (gmin <= qhi + pad);
+  }
+  return ok;
+}
+
+// Canonization of the surface at the child cell (Sec. 3.2.1): translate to
+// the child's min corner, round essential and free parameters to the
+// child's lattice (half to even).
+template <int FAM> __device__ inline LinS lin_canon_child(const LinS& s, const LevelC& lv, uint32_t cb) {
+  LinS o = s;
+#pragma unroll
+  for (int qi = 0; qi < nQ<FAM>(); qi++) {
+    int q = Qax<FAM>(s, qi);
+    int32_t v = 2 * s.F[qi];
+#pragma unroll
+    for (int pi = 0; pi < nP<FAM>(); pi++) {
+      int j = Pax<FAM>(s, pi);
+      int32_t sp = sel4(lv.split, j);
+      int32_t b = (int32_t)((cb >> j) & 1u);
+      if (sp) v += s.K[qi][pi] * b;
+      o.K[qi][pi] = sp ? rne_half(s.K[qi][pi]) : s.K[qi][pi];
+    }
+    int32_t spq = sel4(lv.split, q);
+    int32_t bq = (int32_t)((cb >> q) & 1u);
+    if (spq) v -= bq * sel4(lv.H, q);
+    o.F[qi] = rne_half(v);
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// POSE4DOF predicate halves.  V = Rot_s(box of (W1 - X, W2 - Y)).
+// ---------------------------------------------------------------------------
+template <typename R> struct VBox { R x0, x1, y0, y1; };
+
+template <typename R>
+__device__ inline VBox<R> pose_vbox(R W1, R W2, R Xlo, R Xhi, R Ylo, R Yhi, int sector) {
+  R Alo = W1 - Xhi, Ahi = W1 - Xlo, Blo = W2 - Yhi, Bhi = W2 - Ylo;
+  VBox<R> v;
+  if (sector == 0) { v.x0 = Alo; v.x1 = Ahi; v.y0 = Blo; v.y1 = Bhi; }
+  else if (sector == 1) { v.x0 = Blo; v.x1 = Bhi; v.y0 = -Ahi; v.y1 = -Alo; }
+  else if (sector == 2) { v.x0 = -Ahi; v.x1 = -Alo; v.y0 = -Bhi; v.y1 = -Blo; }
+  else { v.x0 = -Bhi; v.x1 = -Blo; v.y0 = Alo; v.y1 = Ahi; }
+  return v;
+}
+
+template <typename R> __device__ inline R rmin2_of(const VBox<R>& v) {
+  R z = (R)0;
+  R dx = v.x0 > z ? v.x0 : (v.x1 < z ? -v.x1 : z);
+  R dy = v.y0 > z ? v.y0 : (v.y1 < z ? -v.y1 : z);
+  return dx * dx + dy * dy;
+}
+template <typename R> __device__ inline R rmax2_of(const VBox<R>& v) {
+  R a = v.x0 * v.x0, b = v.x1 * v.x1, c = v.y0 * v.y0, d = v.y1 * v.y1;
+  return (a > b ? a : b) + (c > d ? c : d);
+}
+
+// silhouette corners: V's angular span runs from (ax,ay) counter-clockwise to
+// (bx,by); returns false when V holds the apex
+template <typename R>
+__device__ inline bool silhouette(const VBox<R>& v, R& ax, R& ay, R& bx, R& by) {
+  R z = (R)0;
+  if (v.x0 > z) {
+    if (v.y0 > z) { ax = v.x1; ay = v.y0; bx = v.x0; by = v.y1; }
+    else if (v.y1 < z) { ax = v.x0; ay = v.y0; bx = v.x1; by = v.y1; }
+    else { ax = v.x0; ay = v.y0; bx = v.x0; by = v.y1; }
+  } else if (v.x1 < z) {
+    if (v.y0 > z) { ax = v.x1; ay = v.y1; bx = v.x0; by = v.y0; }
+    else if (v.y1 < z) { ax = v.x0; ay = v.y1; bx = v.x1; by = v.y0; }
+    else { ax = v.x1; ay = v.y1; bx = v.x1; by = v.y0; }
+  } else {
+    if (v.y0 > z) { ax = v.x1; ay = v.y0; bx = v.x0; by = v.y0; }
+    else if (v.y1 < z) { ax = v.x0; ay = v.y1; bx = v.x1; by = v.y1; }
+    else return false;
+  }
+  return true;
+}
+
+// z-half in binary64: z = W3 - eta r over r in [r_min, r_max] must reach
+// [Zlo - pad, Zhi + pad]; ZH = Zhi + pad, ZL = Zlo - pad.
+__device__ inline bool zhalf64(double W3, double eta, double rmin2, double rmax2, double ZH, double ZL) {
+  double Glo = W3 - ZH, Ghi = W3 - ZL;
+  double Tlo, Thi, a;
+  if (eta >= 0.0) { Tlo = Glo; Thi = Ghi; a = eta; }
+  else { Tlo = -Ghi; Thi = -Glo; a = -eta; }
+  double a2 = a * a;
+  bool lo_ok = (Tlo <= 0.0) || (a2 * rmax2 >= Tlo * Tlo);
+  bool hi_ok = (Thi >= 0.0) && (a2 * rmin2 <= Thi * Thi);
+  return lo_ok && hi_ok;
+}
+
+// kappa-half in binary64: the cone of directions with kappa in [Llo, Lhi]
+// (kappa = (v2 - xi v1)/(v1 + xi v2), v1 + xi v2 > 0) meets V.
+__device__ inline bool khalf64(const VBox<double>& v, double rmin2, double Rg2, double xi, double Llo,
+                               double Lhi) {
+  if (rmin2 < Rg2) return true;  // apex guard
+  double ax, ay, bx, by;
+  if (!silhouette(v, ax, ay, bx, by)) return true;
+  double elx = 1.0 - Llo * xi, ely = Llo + xi;
+  double ehx = 1.0 - Lhi * xi, ehy = Lhi + xi;
+  double c1 = elx * ay - ely * ax;  // cross(e_lo, a)
+  double c2 = ax * ehy - ay * ehx;  // cross(a, e_hi)
+  double c3 = elx * by - ely * bx;  // cross(e_lo, b)
+  double c4 = bx * ehy - by * ehx;  // cross(b, e_hi)
+  return (c1 >= 0.0 && c2 >= 0.0) || (c3 >= 0.0 && c4 >= 0.0) || (c1 <= 0.0 && c3 >= 0.0) ||
+         (c2 >= 0.0 && c4 <= 0.0);
+}
+
+// binary32 filters: return 1 (meets), 0 (misses) or -1 (undecided: the
+// binary32 value lies within its certified error bound of the threshold).
+// Inputs are exact in binary32 (checked per problem on the host).
+#define GV_U32 5.9604644775390625e-08f  // 2^-24
+
+__device__ inline int sgn_cert(float v, float bound) { return v > bound ? 1 : (v < -bound ? -1 : 0); }
+
+__device__ inline int zhalf32(float W3, float eta, float rmin2, float rmax2, float ZH, float ZL) {
+  float Glo = W3 - ZH, Ghi = W3 - ZL;  // exact
+  float Tlo, Thi, a;
+  if (eta >= 0.0f) { Tlo = Glo; Thi = Ghi; a = eta; }
+  else { Tlo = -Ghi; Thi = -Glo; a = -eta; }
+  float a2 = a * a;
+  int lo_ok, hi_ok;
+  if (Tlo <= 0.0f) lo_ok = 1;
+  else {
+    float X = a2 * rmax2, Y = Tlo * Tlo;
+    int s = sgn_cert(X - Y, 8.0f * GV_U32 * (X + Y));
+    lo_ok = s > 0 ? 1 : (s < 0 ? 0 : -1);
+  }
+  if (lo_ok == 0) return 0;
+  if (Thi < 0.0f) return 0;
+  {
+    float X = a2 * rmin2, Y = Thi * Thi;
+    int s = sgn_cert(Y - X, 8.0f * GV_U32 * (X + Y));
+    hi_ok = s > 0 ? 1 : (s < 0 ? 0 : -1);
+  }
+  if (hi_ok == 0) return 0;
+  return (lo_ok == 1 && hi_ok == 1) ? 1 : -1;
+}
+
+__device__ inline int khalf32(const VBox<float>& v, float rmin2, float Rg2, float xi, float Llo, float Lhi) {
+  int g = sgn_cert(Rg2 - rmin2, 4.0f * GV_U32 * (Rg2 + rmin2));
+  if (g > 0) return 1;  // apex guard certified
+  if (g == 0) return -1;
+  float ax, ay, bx, by;
+  if (!silhouette(v, ax, ay, bx, by)) return 1;
+  float pl = Llo * xi, ph = Lhi * xi;
+  float elx = 1.0f - pl, ely = Llo + xi;
+  float ehx = 1.0f - ph, ehy = Lhi + xi;
+  float Sl = fabsf(pl) + fabsf(elx) + fabsf(ely);
+  float Sh = fabsf(ph) + fabsf(ehx) + fabsf(ehy);
+  float Na = fabsf(ax) + fabsf(ay), Nb = fabsf(bx) + fabsf(by);
+  const float k = 8.0f * GV_U32;
+  int s1 = sgn_cert(elx * ay - ely * ax, k * Sl * Na);
+  int s2 = sgn_cert(ax * ehy - ay * ehx, k * Sh * Na);
+  int s3 = sgn_cert(elx * by - ely * bx, k * Sl * Nb);
+  int s4 = sgn_cert(bx * ehy - by * ehx, k * Sh * Nb);
+  if (s1 == 0 || s2 == 0 || s3 == 0 || s4 == 0) return -1;
+  bool r = (s1 > 0 && s2 > 0) || (s3 > 0 && s4 > 0) || (s1 < 0 && s3 > 0) || (s2 > 0 && s4 < 0);
+  return r ? 1 : 0;
+}

@@ -1,0 +1,479 @@
+// gv_kernels.h -- HIP kernels of the general-voting library (gfx950, wave64).
+//
+// Work decomposition: a batch holds cells of one level, each with a
+// contiguous list of canonical surfaces.  Lists are cut into items of at most
+// GV_ITEM entries that belong to a single cell; one wavefront processes one
+// item, so the cell's child boxes are wave-uniform (scalar registers) and the
+// per-child counts reduce across the wave before a single atomic per child.
+#pragma once
+#include "gv_device.h"
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+__device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
+__device__ inline uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint32_t mbcnt64(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// ---------------------------------------------------------------------------
+// Items: per cell ceil(len / GV_ITEM) work items.
+// ---------------------------------------------------------------------------
+__global__ void k_item_counts(const Cell* __restrict__ cells, uint32_t ncell, uint32_t* __restrict__ nitem) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncell) nitem[c] = (cells[c].len + GV_ITEM - 1) / GV_ITEM;
+}
+__global__ void k_item_fill(const Cell* __restrict__ cells, uint32_t ncell, const uint32_t* __restrict__ nitem,
+                            const uint32_t* __restrict__ ioff, Item* __restrict__ items, uint32_t* __restrict__ total) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  uint32_t o = ioff[c], k = nitem[c];
+  for (uint32_t j = 0; j < k; j++) items[o + j] = Item{c, j * (uint32_t)GV_ITEM};
+  if (c == ncell - 1) *total = o + k;
+}
+
+// ---------------------------------------------------------------------------
+// Linear families: incidence test of every (canonical surface, child) pair,
+// pass masks, weighted and unweighted per-child counts.
+// ---------------------------------------------------------------------------
+template <int FAM>
+__global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Cell* __restrict__ cells,
+                                                   const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
+                                                   const typename EntOf<FAM>::T* __restrict__ ents,
+                                                   uint8_t* __restrict__ masks, uint32_t* __restrict__ ccnt,
+                                                   uint32_t* __restrict__ cnent) {
+  using E = typename EntOf<FAM>::T;
+  const uint32_t nch = 1u << lv.abits;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t nitems = *nitems_p;
+  for (uint32_t it = wave; it < nitems; it += nwaves) {
+    const Item I = items[it];
+    const Cell C = cells[I.cell];
+    const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
+    uint32_t aw[8], an[8];
+#pragma unroll
+    for (int ch = 0; ch < 8; ch++) { aw[ch] = 0; an[ch] = 0; }
+    for (uint32_t k = lane; k < cnt; k += 64) {
+      const uint64_t e = C.off + I.start + k;
+      const LinS s = load_lin<FAM>(ents[e]);
+      uint32_t mask = 0;
+#pragma unroll
+      for (int ch = 0; ch < 8; ch++) {
+        if ((uint32_t)ch < nch && lin_meets<FAM>(s, lv, lv.cbits[ch])) {
+          mask |= 1u << ch;
+          aw[ch] += (uint32_t)s.w;
+          an[ch] += 1u;
+        }
+      }
+      masks[e] = (uint8_t)mask;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 8; ch++) {
+      if ((uint32_t)ch < nch) {
+        uint32_t w = wave_sum_u32(aw[ch]), n = wave_sum_u32(an[ch]);
+        if (lane == 0 && n) {
+          atomicAdd(&ccnt[I.cell * nch + ch], w);
+          atomicAdd(&cnent[I.cell * nch + ch], n);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// POSE4DOF incidence: per (surface, child) the z-half and the kappa-half.
+// Children (bx, by, bz, bk) share the V rectangle of their (bx, by) part.
+// ---------------------------------------------------------------------------
+struct PoseLevel {
+  // child boxes of the item's cell, per bit value (wave-uniform)
+  double Xlo[2], Xhi[2], Ylo[2], Yhi[2], ZH[2], ZL[2], Llo[2], Lhi[2];
+};
+
+__device__ inline void pose_level_boxes(const ProbC& P, const LevelC& lv, const Cell& C, int m, PoseLevel& B) {
+  const int m1 = m + 1;
+  double h[4];
+  for (int j = 0; j < 4; j++) h[j] = ldexp(1.0, -min(m1, P.L[j]));
+  for (int b = 0; b < 2; b++) {
+    int32_t cx = lv.split[0] ? 2 * C.c[0] + b : C.c[0];
+    int32_t cy = lv.split[1] ? 2 * C.c[1] + b : C.c[1];
+    int32_t cz = lv.split[2] ? 2 * C.c[2] + b : C.c[2];
+    int32_t ck = lv.split[3] ? 2 * C.c[3] + b : C.c[3];
+    B.Xlo[b] = (double)cx * h[0];
+    B.Xhi[b] = (double)(cx + 1) * h[0];
+    B.Ylo[b] = (double)cy * h[1];
+    B.Yhi[b] = (double)(cy + 1) * h[1];
+    double Zlo = (double)cz * h[2], Zhi = (double)(cz + 1) * h[2];
+    B.ZH[b] = Zhi + P.padz;
+    B.ZL[b] = Zlo - P.padz;
+    double Klo = 2.0 * ((double)ck * h[3]) - 1.0, Khi = 2.0 * ((double)(ck + 1) * h[3]) - 1.0;
+    B.Llo[b] = Klo - P.padk;
+    B.Lhi[b] = Khi + P.padk;
+  }
+}
+
+// binary64 mask over the children of one cell for one surface
+__device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const PoseLevel& B, int sector,
+                                       double W1, double W2, double W3, double xi, double eta) {
+  const uint32_t nch = 1u << lv.abits;
+  uint32_t zbits = 0, kbits = 0;  // bit (bx | by<<1 | b<<2)
+#pragma unroll
+  for (int xy = 0; xy < 4; xy++) {
+    int bx = xy & 1, by = xy >> 1;
+    if ((bx && !lv.split[0]) || (by && !lv.split[1])) continue;
+    VBox<double> v = pose_vbox<double>(W1, W2, B.Xlo[bx], B.Xhi[bx], B.Ylo[by], B.Yhi[by], sector);
+    double rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      if (b && !lv.split[2]) continue;
+      if (zhalf64(W3, eta, rmin2, rmax2, B.ZH[b], B.ZL[b])) zbits |= 1u << (xy | (b << 2));
+    }
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      if (b && !lv.split[3]) continue;
+      if (khalf64(v, rmin2, P.Rg2, xi, B.Llo[b], B.Lhi[b])) kbits |= 1u << (xy | (b << 2));
+    }
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int ch = 0; ch < 16; ch++) {
+    if ((uint32_t)ch >= nch) break;
+    uint32_t cb = lv.cbits[ch];
+    uint32_t xy = (cb & 1u) | (((cb >> 1) & 1u) << 1);
+    uint32_t zb = (cb >> 2) & 1u, kb = (cb >> 3) & 1u;
+    if (((zbits >> (xy | (zb << 2))) & 1u) && ((kbits >> (xy | (kb << 2))) & 1u)) mask |= 1u << ch;
+  }
+  return mask;
+}
+
+// binary32 mask with binary64 recheck of undecided halves
+__device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const PoseLevel& B, const float* Bf,
+                                       int sector, const EntQ32& e, const double* __restrict__ m64,
+                                       uint64_t n_root, uint32_t& nrecheck) {
+  const uint32_t nch = 1u << lv.abits;
+  uint32_t zbits = 0, kbits = 0;
+  // Bf layout: Xlo[2] Xhi[2] Ylo[2] Yhi[2] ZH[2] ZL[2] Llo[2] Lhi[2]
+  bool have64 = false;
+  double W1 = 0, W2 = 0, W3 = 0, xi = 0, eta = 0;
+#pragma unroll
+  for (int xy = 0; xy < 4; xy++) {
+    int bx = xy & 1, by = xy >> 1;
+    if ((bx && !lv.split[0]) || (by && !lv.split[1])) continue;
+    VBox<float> v = pose_vbox<float>(e.W1, e.W2, Bf[0 + bx], Bf[2 + bx], Bf[4 + by], Bf[6 + by], sector);
+    float rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
+    int zr[2] = {0, 0}, kr[2] = {0, 0};
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      if (b && !lv.split[2]) continue;
+      zr[b] = zhalf32(e.W3, e.eta, rmin2, rmax2, Bf[8 + b], Bf[10 + b]);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      if (b && !lv.split[3]) continue;
+      kr[b] = khalf32(v, rmin2, P.Rg2f, e.xi, Bf[12 + b], Bf[14 + b]);
+    }
+    bool need = (zr[0] < 0) || (zr[1] < 0) || (kr[0] < 0) || (kr[1] < 0);
+    if (need) {
+      if (!have64) {
+        const uint64_t r = e.ridx;
+        W1 = m64[r];
+        W2 = m64[n_root + r];
+        W3 = m64[2 * n_root + r];
+        xi = m64[3 * n_root + r];
+        eta = m64[4 * n_root + r];
+        have64 = true;
+      }
+      VBox<double> vd = pose_vbox<double>(W1, W2, B.Xlo[bx], B.Xhi[bx], B.Ylo[by], B.Yhi[by], sector);
+      double rmin2d = rmin2_of(vd), rmax2d = rmax2_of(vd);
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        if (zr[b] < 0) { zr[b] = zhalf64(W3, eta, rmin2d, rmax2d, B.ZH[b], B.ZL[b]) ? 1 : 0; nrecheck++; }
+        if (kr[b] < 0) { kr[b] = khalf64(vd, rmin2d, P.Rg2, xi, B.Llo[b], B.Lhi[b]) ? 1 : 0; nrecheck++; }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      if (zr[b] > 0) zbits |= 1u << (xy | (b << 2));
+      if (kr[b] > 0) kbits |= 1u << (xy | (b << 2));
+    }
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int ch = 0; ch < 16; ch++) {
+    if ((uint32_t)ch >= nch) break;
+    uint32_t cb = lv.cbits[ch];
+    uint32_t xy = (cb & 1u) | (((cb >> 1) & 1u) << 1);
+    uint32_t zb = (cb >> 2) & 1u, kb = (cb >> 3) & 1u;
+    if (((zbits >> (xy | (zb << 2))) & 1u) && ((kbits >> (xy | (kb << 2))) & 1u)) mask |= 1u << ch;
+  }
+  return mask;
+}
+
+template <typename E>
+__global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pp, int m, LevelC lv,
+                                                    const Cell* __restrict__ cells, const Item* __restrict__ items,
+                                                    const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
+                                                    const double* __restrict__ m64, uint64_t n_root,
+                                                    uint16_t* __restrict__ masks, uint32_t* __restrict__ ccnt,
+                                                    uint32_t* __restrict__ cnent,
+                                                    unsigned long long* __restrict__ rechecks) {
+  const ProbC& P = *Pp;
+  const uint32_t nch = 1u << lv.abits;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t nitems = *nitems_p;
+  uint32_t nre = 0;
+  for (uint32_t it = wave; it < nitems; it += nwaves) {
+    const Item I = items[it];
+    const Cell C = cells[I.cell];
+    const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
+    const int sector = (int)C.sector;
+    PoseLevel B;
+    pose_level_boxes(P, lv, C, m, B);
+    float Bf[16];
+    for (int b = 0; b < 2; b++) {
+      Bf[0 + b] = (float)B.Xlo[b]; Bf[2 + b] = (float)B.Xhi[b];
+      Bf[4 + b] = (float)B.Ylo[b]; Bf[6 + b] = (float)B.Yhi[b];
+      Bf[8 + b] = (float)B.ZH[b];  Bf[10 + b] = (float)B.ZL[b];
+      Bf[12 + b] = (float)B.Llo[b]; Bf[14 + b] = (float)B.Lhi[b];
+    }
+    uint32_t aw[16], an[16];
+#pragma unroll
+    for (int ch = 0; ch < 16; ch++) { aw[ch] = 0; an[ch] = 0; }
+    for (uint32_t k = lane; k < cnt; k += 64) {
+      const uint64_t ei = C.off + I.start + k;
+      const E e = ents[ei];
+      uint32_t mask;
+      if constexpr (sizeof(E) == sizeof(EntQ64)) {
+        mask = pose_mask64(P, lv, B, sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+      } else {
+        mask = pose_mask32(P, lv, B, Bf, sector, e, m64, n_root, nre);
+      }
+#pragma unroll
+      for (int ch = 0; ch < 16; ch++) {
+        if ((mask >> ch) & 1u) { aw[ch] += e.w; an[ch] += 1u; }
+      }
+      masks[ei] = (uint16_t)mask;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 16; ch++) {
+      if ((uint32_t)ch < nch) {
+        uint32_t w = wave_sum_u32(aw[ch]), n = wave_sum_u32(an[ch]);
+        if (lane == 0 && n) {
+          atomicAdd(&ccnt[I.cell * nch + ch], w);
+          atomicAdd(&cnent[I.cell * nch + ch], n);
+        }
+      }
+    }
+  }
+  uint32_t tot = wave_sum_u32(nre);
+  if (lane_id() == 0 && tot) atomicAdd(rechecks, (unsigned long long)tot);
+}
+
+// ---------------------------------------------------------------------------
+// Pruning against the best key (counts only shrink down the tree, so a cell
+// whose best possible key cannot beat the best leaf found so far is dropped)
+// and, at the last level, the best-key reduction (u64 atomic max).
+// key = count * 2^B + (2^B - 1 - leaf index): largest count, lowest index.
+// ---------------------------------------------------------------------------
+__global__ void k_prune(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell* __restrict__ cells, uint32_t ncell,
+                        const uint32_t* __restrict__ ccnt, const uint32_t* __restrict__ cnent,
+                        unsigned long long* __restrict__ best, uint32_t* __restrict__ keepf,
+                        uint64_t* __restrict__ keptn) {
+  const uint32_t nch = 1u << lv.abits;
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nk = (uint64_t)ncell * nch;
+  uint64_t key = 0;
+  if (k < nk) {
+    const uint32_t c = (uint32_t)(k / nch), ch = (uint32_t)(k % nch);
+    const uint64_t pre = (cells[c].prefix << lv.abits) | ch;
+    const uint64_t idxmin = pre << lv.rem_next;
+    key = ((uint64_t)ccnt[k] << B) | (idxmask - idxmin);
+    if (!leaf) {
+      const uint64_t b = *best;
+      const uint32_t keep = key > b ? 1u : 0u;
+      keepf[k] = keep;
+      keptn[k] = keep ? (uint64_t)cnent[k] : 0ull;
+    }
+  }
+  if (leaf) {
+    uint64_t m = wave_max_u64(key);
+    if (lane_id() == 0 && m) atomicMax(best, (unsigned long long)m);
+  }
+}
+
+// Greedy dive: keep only the best child (count, then lowest digit) of a
+// one-cell batch; at the last level record its key.
+__global__ void k_pick_best(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell* __restrict__ cells,
+                            const uint32_t* __restrict__ ccnt, const uint32_t* __restrict__ cnent,
+                            unsigned long long* __restrict__ best, uint32_t* __restrict__ keepf,
+                            uint64_t* __restrict__ keptn) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t nch = 1u << lv.abits;
+  uint32_t bc = 0, bd = 0;
+  for (uint32_t ch = 0; ch < nch; ch++)
+    if (ch == 0 || ccnt[ch] > bc) { bc = ccnt[ch]; bd = ch; }
+  for (uint32_t ch = 0; ch < nch; ch++) {
+    keepf[ch] = (ch == bd) ? 1u : 0u;
+    keptn[ch] = (ch == bd) ? (uint64_t)cnent[ch] : 0ull;
+  }
+  if (leaf) {
+    const uint64_t pre = (cells[0].prefix << lv.abits) | bd;
+    const uint64_t key = ((uint64_t)bc << B) | (idxmask - (pre << lv.rem_next));
+    atomicMax(best, (unsigned long long)key);
+  }
+}
+
+// totals after the scans: kept children and their entries
+__global__ void k_totals(const uint32_t* keepf, const uint32_t* keepscan, const uint64_t* keptn,
+                         const uint64_t* nscan, uint64_t nk, uint64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = nk ? (uint64_t)keepscan[nk - 1] + keepf[nk - 1] : 0;
+    out[1] = nk ? nscan[nk - 1] + keptn[nk - 1] : 0;
+  }
+}
+
+// per-parent cumulative kept entries (for cutting a batch into chunks)
+__global__ void k_parent_cum(const uint64_t* __restrict__ nscan, const uint64_t* __restrict__ keptn, uint32_t ncell,
+                             uint32_t nch, uint64_t* __restrict__ cum) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncell) cum[c] = nscan[(uint64_t)c * nch];
+  if (c == ncell - 1) cum[ncell] = nscan[(uint64_t)c * nch + nch - 1] + keptn[(uint64_t)c * nch + nch - 1];
+}
+
+// emit the kept children of parents [c0, c1) as the cells of a new batch
+__global__ void k_emit_cells(LevelC lv, const Cell* __restrict__ cells, uint32_t c0, uint32_t c1,
+                             const uint32_t* __restrict__ keepf, const uint32_t* __restrict__ keepscan,
+                             const uint64_t* __restrict__ nscan, const uint32_t* __restrict__ cnent,
+                             Cell* __restrict__ out, uint32_t* __restrict__ cursor) {
+  const uint32_t nch = 1u << lv.abits;
+  const uint64_t k = (uint64_t)c0 * nch + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (uint64_t)c1 * nch) return;
+  cursor[k] = 0;
+  if (!keepf[k]) return;
+  const uint32_t c = (uint32_t)(k / nch), ch = (uint32_t)(k % nch);
+  const uint32_t j = keepscan[k] - keepscan[(uint64_t)c0 * nch];
+  const Cell P = cells[c];
+  Cell o;
+  const uint32_t cb = lv.cbits[ch];
+  for (int a = 0; a < 4; a++) o.c[a] = lv.split[a] ? 2 * P.c[a] + (int32_t)((cb >> a) & 1u) : P.c[a];
+  o.prefix = (P.prefix << lv.abits) | ch;
+  o.off = nscan[k] - nscan[(uint64_t)c0 * nch];
+  o.len = cnent[k];
+  o.sector = P.sector;
+  out[j] = o;
+}
+
+// ---------------------------------------------------------------------------
+// Compaction: survivors of kept children into the children's lists, each
+// canonized to its child (wavefront ballot + one atomic per child per wave).
+// ---------------------------------------------------------------------------
+template <int FAM>
+__global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const Cell* __restrict__ cells, uint32_t c0, uint32_t c1,
+                                                     const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
+                                                     const typename EntOf<FAM>::T* __restrict__ ents,
+                                                     const uint8_t* __restrict__ masks, const uint32_t* __restrict__ keepf,
+                                                     const uint64_t* __restrict__ nscan, uint32_t* __restrict__ cursor,
+                                                     typename EntOf<FAM>::T* __restrict__ out) {
+  const uint32_t nch = 1u << lv.abits;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t nitems = *nitems_p;
+  const uint64_t base = nscan[(uint64_t)c0 * nch];
+  for (uint32_t it = wave; it < nitems; it += nwaves) {
+    const Item I = items[it];
+    if (I.cell < c0 || I.cell >= c1) continue;
+    const Cell C = cells[I.cell];
+    uint32_t kmask = 0;
+    for (uint32_t ch = 0; ch < nch; ch++) kmask |= keepf[(uint64_t)I.cell * nch + ch] << ch;
+    kmask = uniform_u32(kmask);
+    if (!kmask) continue;
+    const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      const bool valid = k < cnt;
+      const uint64_t e = C.off + I.start + k;
+      uint32_t mask = 0;
+      LinS s;
+      if (valid) {
+        mask = masks[e] & kmask;
+        s = load_lin<FAM>(ents[e]);
+      }
+#pragma unroll
+      for (int ch = 0; ch < 8; ch++) {
+        if (!((kmask >> ch) & 1u)) continue;
+        const bool p = valid && ((mask >> ch) & 1u);
+        const uint64_t bal = __ballot(p);
+        if (!bal) continue;
+        const uint64_t kk = (uint64_t)I.cell * nch + ch;
+        uint32_t b0 = 0;
+        if (lane == 0) b0 = atomicAdd(&cursor[kk], (uint32_t)__popcll(bal));
+        b0 = __shfl(b0, 0, 64);
+        if (p) {
+          const uint64_t pos = (nscan[kk] - base) + b0 + mbcnt64(bal);
+          out[pos] = store_lin<FAM>(lin_canon_child<FAM>(s, lv, lv.cbits[ch]));
+        }
+      }
+    }
+  }
+}
+
+template <typename E>
+__global__ void __launch_bounds__(256) k_compact_pose(LevelC lv, const Cell* __restrict__ cells, uint32_t c0, uint32_t c1,
+                                                      const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
+                                                      const E* __restrict__ ents, const uint16_t* __restrict__ masks,
+                                                      const uint32_t* __restrict__ keepf, const uint64_t* __restrict__ nscan,
+                                                      uint32_t* __restrict__ cursor, E* __restrict__ out) {
+  const uint32_t nch = 1u << lv.abits;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t nitems = *nitems_p;
+  const uint64_t base = nscan[(uint64_t)c0 * nch];
+  for (uint32_t it = wave; it < nitems; it += nwaves) {
+    const Item I = items[it];
+    if (I.cell < c0 || I.cell >= c1) continue;
+    const Cell C = cells[I.cell];
+    uint32_t kmask = 0;
+    for (uint32_t ch = 0; ch < nch; ch++) kmask |= keepf[(uint64_t)I.cell * nch + ch] << ch;
+    kmask = uniform_u32(kmask);
+    if (!kmask) continue;
+    const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      const bool valid = k < cnt;
+      const uint64_t ei = C.off + I.start + k;
+      uint32_t mask = 0;
+      E e;
+      if (valid) {
+        mask = masks[ei] & kmask;
+        e = ents[ei];
+      }
+      for (uint32_t ch = 0; ch < nch; ch++) {
+        if (!((kmask >> ch) & 1u)) continue;
+        const bool p = valid && ((mask >> ch) & 1u);
+        const uint64_t bal = __ballot(p);
+        if (!bal) continue;
+        const uint64_t kk = (uint64_t)I.cell * nch + ch;
+        uint32_t b0 = 0;
+        if (lane == 0) b0 = atomicAdd(&cursor[kk], (uint32_t)__popcll(bal));
+        b0 = __shfl(b0, 0, 64);
+        if (p) out[(nscan[kk] - base) + b0 + mbcnt64(bal)] = e;
+      }
+    }
+  }
+}

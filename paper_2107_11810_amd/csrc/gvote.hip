@@ -1,0 +1,1100 @@
+// gvote.hip -- MI355X general-voting library: C ABI, host runtime and the
+// root / replay kernels.  See include/gvote.h for the interface.
+//
+// Pipeline of one solve (Alg. 2 of Aiger et al., ICCV 2021):
+//   front end (Eq. 1-3, the posing surface) -> root canonization
+//   -> greedy dive (an achieved leaf key seeds the pruning bound)
+//   -> depth-first over batches of same-level cells: incidence test + counts,
+//      prune against the best key, compaction + canonization into the
+//      children's lists, best-key atomic max at the leaves
+//   -> inliers by per-surface replay along the chosen leaf's path.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gvote.h"
+#include "gv_device.h"
+#include "gv_kernels.h"
+
+// ===========================================================================
+// Root kernels
+// ===========================================================================
+struct Cols {
+  const double* c[6];
+};
+
+__device__ inline void atomic_max_f64_pos(unsigned long long* a, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void k_front(int fam, const ProbC* __restrict__ Pp, Cols cols, int64_t n, double* __restrict__ t,
+                        double* __restrict__ f, int32_t* __restrict__ tag, int* __restrict__ bad) {
+  const ProbC& P = *Pp;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double tt[4], ff[2];
+    int32_t tg;
+    if (!front_eval(fam, cols.c, i, P, tt, ff, &tg)) atomicOr(bad, 1);
+    for (int k = 0; k < 4; k++) t[4 * i + k] = tt[k];
+    f[2 * i] = ff[0];
+    f[2 * i + 1] = ff[1];
+    tag[i] = tg;
+  }
+}
+
+template <int FAM>
+__device__ inline bool root_lin(const ProbC& P, const double* const* col, int64_t i, LinS& s, int* bad) {
+  double t[4], f[2];
+  int32_t tag;
+  if (!front_eval(FAM, col, i, P, t, f, &tag)) {
+    atomicOr(bad, 1);
+    return false;
+  }
+  s.K[0][0] = s.K[0][1] = s.K[1][0] = s.K[1][1] = 0;
+  s.F[0] = s.F[1] = 0;
+  s.tag = tag;
+  s.w = 1;
+  bool ok = true;
+  for (int qi = 0; qi < nQ<FAM>(); qi++) {
+    const int q = Qax<FAM>(s, qi);
+    // root: translate by the zero corner, round to the free step s_f
+    for (int pi = 0; pi < nP<FAM>(); pi++) {
+      double k = rint(t[2 * qi + pi] * P.inv_sf[q]);
+      ok = ok && fabs(k) < 1073741824.0;
+      s.K[qi][pi] = ok ? (int32_t)k : 0;
+    }
+    double F = rint(f[qi] * P.inv_sf[q]);
+    ok = ok && fabs(F) < 1073741824.0;
+    s.F[qi] = ok ? (int32_t)F : 0;
+  }
+  if (!ok) atomicOr(bad, 2);
+  return true;
+}
+
+template <int FAM>
+__global__ void k_root_lin(const ProbC* __restrict__ Pp, Cols cols, int64_t n, typename EntOf<FAM>::T* __restrict__ out,
+                           unsigned int* __restrict__ maxabs, int* __restrict__ bad) {
+  const ProbC& P = *Pp;
+  unsigned mk = 0, mf = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    LinS s;
+    if (!root_lin<FAM>(P, cols.c, i, s, bad)) {
+      s = LinS{};
+      s.w = 1;
+    }
+    for (int qi = 0; qi < 2; qi++) {
+      for (int pi = 0; pi < 2; pi++) mk = max(mk, (unsigned)abs(s.K[qi][pi]));
+      mf = max(mf, (unsigned)abs(s.F[qi]));
+    }
+    out[i] = store_lin<FAM>(s);
+  }
+  atomicMax(&maxabs[0], mk);
+  atomicMax(&maxabs[1], mf);
+}
+
+__global__ void k_pose_bounds(const ProbC* __restrict__ Pp, Cols cols, int64_t n, unsigned long long* __restrict__ mx,
+                              int* __restrict__ bad) {
+  const ProbC& P = *Pp;
+  double H = 0.0, R2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double t[4], f[2];
+    int32_t tag;
+    if (!front_eval(FAM_POSE4DOF, cols.c, i, P, t, f, &tag)) {
+      atomicOr(bad, 1);
+      continue;
+    }
+    double h = fabs(t[3]);
+    H = h > H ? h : H;
+    double a0 = t[0] * t[0], a1 = (t[0] - 1.0) * (t[0] - 1.0);
+    double b0 = t[1] * t[1], b1 = (t[1] - 1.0) * (t[1] - 1.0);
+    double r2 = (a0 > a1 ? a0 : a1) + (b0 > b1 ? b0 : b1);
+    R2 = r2 > R2 ? r2 : R2;
+  }
+  atomic_max_f64_pos(&mx[0], H);
+  atomic_max_f64_pos(&mx[1], R2);
+}
+
+// quantize once at the root to the fixed pose lattice
+__global__ void k_root_pose(const ProbC* __restrict__ Pp, Cols cols, int64_t n, double* __restrict__ m64,
+                            EntQ32* __restrict__ e32, EntQ64* __restrict__ e64, unsigned long long* __restrict__ mx) {
+  const ProbC& P = *Pp;
+  double a[5] = {0, 0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double t[4], f[2];
+    int32_t tag;
+    front_eval(FAM_POSE4DOF, cols.c, i, P, t, f, &tag);
+    double W1 = rint(t[0] * P.inv_sW) * P.sW;
+    double W2 = rint(t[1] * P.inv_sW) * P.sW;
+    double W3 = rint(f[0] * P.inv_sW3) * P.sW3;
+    double xi = rint(t[2] * P.inv_sXi) * P.sXi;
+    double eta = rint(t[3] * P.inv_sEta) * P.sEta;
+    m64[i] = W1;
+    m64[n + i] = W2;
+    m64[2 * n + i] = W3;
+    m64[3 * n + i] = xi;
+    m64[4 * n + i] = eta;
+    if (e32) e32[i] = EntQ32{(float)W1, (float)W2, (float)W3, (float)xi, (float)eta, 1u, (uint32_t)i, 0u};
+    if (e64) e64[i] = EntQ64{W1, W2, W3, xi, eta, 1u, (uint32_t)i};
+    double v[5] = {fabs(W1), fabs(W2), fabs(W3), fabs(xi), fabs(eta)};
+    for (int k = 0; k < 5; k++) a[k] = v[k] > a[k] ? v[k] : a[k];
+  }
+  for (int k = 0; k < 5; k++) atomic_max_f64_pos(&mx[2 + k], a[k]);
+}
+
+template <typename E>
+__global__ void k_replicate(const E* __restrict__ src, int64_t n, int nsec, E* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * nsec; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i % n];
+}
+
+// root cells: one per sector s0 .. s0+ncell-1; lists either back to back
+// (shared == 0) or all the same list at offset 0
+__global__ void k_root_cells(Cell* cells, int ncell, int s0, uint64_t n, int shared) {
+  int k = threadIdx.x;
+  if (k < ncell) {
+    Cell c;
+    c.c[0] = c.c[1] = c.c[2] = c.c[3] = 0;
+    c.prefix = (uint64_t)(s0 + k);
+    c.off = shared ? 0 : (uint64_t)k * n;
+    c.len = (uint32_t)n;
+    c.sector = (uint32_t)(s0 + k);
+    cells[k] = c;
+  }
+}
+
+// ===========================================================================
+// Replay: every original surface's canonization chain along the chosen
+// leaf's root-to-leaf path; it is an inlier iff every test on the path passes
+// (member tracking, Sec. 3.2.1).
+// ===========================================================================
+struct PathC {
+  uint8_t digit[GV_MAXL];
+  int32_t sector;
+};
+
+template <int FAM>
+__global__ void k_replay_lin(const ProbC* __restrict__ Pp, Cols cols, int64_t n, PathC path, uint32_t* __restrict__ flag,
+                             int* __restrict__ bad) {
+  const ProbC& P = *Pp;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    LinS s;
+    uint32_t ok = 0;
+    if (root_lin<FAM>(P, cols.c, i, s, bad)) {
+      ok = 1;
+      for (int m = 0; m < P.Lstar; m++) {
+        const LevelC& lv = P.lev[m];
+        const uint32_t cb = lv.cbits[path.digit[m]];
+        if (!lin_meets<FAM>(s, lv, cb)) { ok = 0; break; }
+        if (m + 1 < P.Lstar) s = lin_canon_child<FAM>(s, lv, cb);
+      }
+    }
+    flag[i] = ok;
+  }
+}
+
+__global__ void k_replay_pose(const ProbC* __restrict__ Pp, const double* __restrict__ m64, int64_t n, PathC path,
+                              uint32_t* __restrict__ flag) {
+  const ProbC& P = *Pp;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double W1 = m64[i], W2 = m64[n + i], W3 = m64[2 * n + i], xi = m64[3 * n + i], eta = m64[4 * n + i];
+    int32_t cc[4] = {0, 0, 0, 0};
+    uint32_t ok = 1;
+    for (int m = 0; m < P.Lstar && ok; m++) {
+      const LevelC& lv = P.lev[m];
+      const uint32_t cb = lv.cbits[path.digit[m]];
+      int32_t ch[4];
+      for (int a = 0; a < 4; a++) ch[a] = lv.split[a] ? 2 * cc[a] + (int32_t)((cb >> a) & 1u) : cc[a];
+      const int m1 = m + 1;
+      double h[4];
+      for (int j = 0; j < 4; j++) h[j] = ldexp(1.0, -min(m1, P.L[j]));
+      const double Xlo = (double)ch[0] * h[0], Xhi = (double)(ch[0] + 1) * h[0];
+      const double Ylo = (double)ch[1] * h[1], Yhi = (double)(ch[1] + 1) * h[1];
+      const double Zlo = (double)ch[2] * h[2], Zhi = (double)(ch[2] + 1) * h[2];
+      const double Klo = 2.0 * ((double)ch[3] * h[3]) - 1.0, Khi = 2.0 * ((double)(ch[3] + 1) * h[3]) - 1.0;
+      VBox<double> v = pose_vbox<double>(W1, W2, Xlo, Xhi, Ylo, Yhi, path.sector);
+      const double rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
+      ok = zhalf64(W3, eta, rmin2, rmax2, Zhi + P.padz, Zlo - P.padz) &&
+           khalf64(v, rmin2, P.Rg2, xi, Klo - P.padk, Khi + P.padk);
+      for (int a = 0; a < 4; a++) cc[a] = ch[a];
+    }
+    flag[i] = ok;
+  }
+}
+
+__global__ void k_write_inliers(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, int64_t n,
+                                int64_t* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (flag[i]) out[pos[i]] = i;
+}
+
+// ===========================================================================
+// Host runtime
+// ===========================================================================
+struct gv_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t budget = 0;
+  std::mutex mu;
+  std::string err;
+  int n_cu = 256;
+};
+
+namespace {
+
+thread_local std::string tl_err;
+
+struct DevErr {
+  gv_status st;
+};
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) {                                                            \
+      X.ctx->err = std::string(#x) + ": " + hipGetErrorString(e_);                     \
+      throw DevErr{GV_EDEVICE};                                                        \
+    }                                                                                  \
+  } while (0)
+
+struct Setup {
+  ProbC P;
+  int fam, d, ell;
+  double epsn[4];
+  double ez, ek;  // pose eps'
+  bool filter;    // binary32 filter usable
+  int64_t n;
+};
+
+// largest power of two <= x
+double p2floor(double x) {
+  int e;
+  (void)std::frexp(x, &e);
+  return std::ldexp(1.0, e - 1);
+}
+
+gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
+  std::memset(&S, 0, sizeof(S));
+  ProbC& P = S.P;
+  S.fam = (int)p->family;
+  S.n = p->n;
+  if (p->n < 0 || p->n > 0x7fffffffLL) { why = "n out of range"; return GV_EINVAL; }
+  switch (S.fam) {
+    case GV_LINE2D: S.d = 2; S.ell = 1; break;
+    case GV_PLANE3D: S.d = 3; S.ell = 2; break;
+    case GV_RAY3D: S.d = 3; S.ell = 2; break;
+    case GV_POSE4DOF: S.d = 4; S.ell = 4; break;
+    default: why = "bad family"; return GV_EINVAL;
+  }
+  P.fam = S.fam;
+  P.d = S.d;
+  P.nsec = S.fam == GV_POSE4DOF ? 4 : 1;
+  double c = p->canon_c == 0.0 ? 1.0 : p->canon_c;
+  if (!(c > 0.0) || std::isnan(c)) { why = "canon_c must be > 0"; return GV_EINVAL; }
+  if (std::isinf(c)) { why = "exact mode (canon_c = inf) is not available on the device path"; return GV_EINVAL; }
+  int nuser = S.fam == GV_POSE4DOF ? 3 : S.d;
+  for (int j = 0; j < nuser; j++) {
+    if (!std::isfinite(p->lo[j]) || !std::isfinite(p->hi[j]) || !(p->hi[j] > p->lo[j])) { why = "bad box"; return GV_EINVAL; }
+    if (!std::isfinite(p->eps[j]) || !(p->eps[j] > 0.0)) { why = "bad eps"; return GV_EINVAL; }
+    P.lo[j] = p->lo[j];
+    P.E[j] = p->hi[j] - p->lo[j];
+    P.inv[j] = 1.0 / P.E[j];
+    S.epsn[j] = p->eps[j] * P.inv[j];
+  }
+  double epsk = 0.0;
+  if (S.fam == GV_POSE4DOF) {
+    if (P.E[0] != P.E[1]) { why = "POSE4DOF needs hi[0]-lo[0] == hi[1]-lo[1]"; return GV_EINVAL; }
+    if (!std::isfinite(p->eps[3]) || !(p->eps[3] > 0.0)) { why = "bad yaw eps"; return GV_EINVAL; }
+    epsk = p->eps[3];
+    P.lo[3] = -1.0;
+    P.E[3] = 2.0;
+    P.inv[3] = 0.5;
+    S.epsn[3] = epsk * 0.5;
+    P.ce = P.E[0] * P.inv[2];
+  }
+  int Lstar = 0, Bcell = 0;
+  for (int j = 0; j < S.d; j++) {
+    double ej = (S.fam == GV_POSE4DOF && j == 3) ? epsk : p->eps[j];
+    int L = 0;
+    while (std::ldexp(P.E[j], -L) > ej) {
+      if (++L > 30) { why = "eps too small for the box"; return GV_EINVAL; }
+    }
+    P.L[j] = L;
+    Lstar = std::max(Lstar, L);
+    Bcell += L;
+  }
+  if (Lstar < 1) { why = "eps covers the whole box"; return GV_EINVAL; }
+  if (Lstar > GV_MAXL) { why = "too many levels"; return GV_EINVAL; }
+  P.Lstar = Lstar;
+  P.Bcell = Bcell;
+  P.B = Bcell + (S.fam == GV_POSE4DOF ? 2 : 0);
+  if (P.B > 62) { why = "leaf index does not fit 62 bits"; return GV_EINVAL; }
+  if ((uint64_t)p->n >= (1ULL << (64 - P.B))) { why = "n too large for the key"; return GV_EINVAL; }
+  P.idxmask = (1ULL << P.B) - 1ULL;
+  int rem[GV_MAXL + 1];
+  rem[Lstar] = 0;
+  int ab[GV_MAXL];
+  for (int m = 0; m < Lstar; m++) {
+    int a = 0;
+    for (int j = 0; j < S.d; j++)
+      if (m < P.L[j]) a++;
+    ab[m] = a;
+  }
+  for (int m = Lstar - 1; m >= 0; m--) rem[m] = rem[m + 1] + ab[m];
+  for (int m = 0; m < Lstar; m++) {
+    LevelC& lv = P.lev[m];
+    std::memset(&lv, 0, sizeof(lv));
+    lv.abits = ab[m];
+    lv.rem_next = rem[m + 1];
+    int splits[4], ns = 0;
+    for (int j = 0; j < 4; j++) {
+      lv.split[j] = (j < S.d && m < P.L[j]) ? 1 : 0;
+      if (lv.split[j]) splits[ns++] = j;
+    }
+    // child digit: split axes' bits in axis order, most significant first
+    for (int dg = 0; dg < (1 << ab[m]); dg++) {
+      uint8_t cb = 0;
+      for (int k = 0; k < ns; k++)
+        if ((dg >> (ns - 1 - k)) & 1) cb |= (uint8_t)(1u << splits[k]);
+      lv.cbits[dg] = cb;
+    }
+  }
+  if (S.fam != GV_POSE4DOF) {
+    for (int q = 0; q < S.d; q++) {
+      double ep = S.epsn[q] / (c * (double)(Lstar + 1));
+      P.sf[q] = p2floor(ep / (double)(S.ell + 1));
+      P.inv_sf[q] = 1.0 / P.sf[q];
+      if (!(P.sf[q] > 0.0) || P.sf[q] < std::ldexp(1.0, -29)) { why = "lattice too fine for 32-bit cells"; return GV_ERANGE; }
+      for (int m = 0; m < Lstar; m++) {
+        double Em = (double)((m + 1) * (S.ell + 1)) * P.sf[q] * 0.5;
+        double padc = std::ceil((S.epsn[q] + Em) / P.sf[q]);  // pad in units of s_f
+        double H = std::ldexp(1.0, -std::min(m, P.L[q])) * P.inv_sf[q];
+        if (padc * 2.0 > 1e9 || H > 1e9) { why = "lattice too fine for 32-bit cells"; return GV_ERANGE; }
+        P.lev[m].padu[q] = (int32_t)(2.0 * padc);
+        P.lev[m].H[q] = (int32_t)H;
+      }
+    }
+  } else {
+    S.ez = S.epsn[2] / (c * (double)(Lstar + 1));
+    S.ek = epsk / (c * (double)(Lstar + 1));
+  }
+  return GV_OK;
+}
+
+// POSE4DOF lattice from the data bounds (same definition as the oracle)
+void pose_lattice(Setup& S, double Hmax, double R2, double epsk) {
+  ProbC& P = S.P;
+  int Lxy = std::max(P.L[0], P.L[1]);
+  double Rg = std::ldexp(1.0, -Lxy);
+  P.Rg2 = Rg * Rg;
+  double l1 = (double)(S.ell + 1);
+  double Hb = (Hmax > 0x1p-10 ? Hmax : 0x1p-10) * (1.0 + 0x1p-20);
+  double Rb = (std::sqrt(R2) + 0x1p-20) * (1.0 + 0x1p-20);
+  double pk0 = epsk + S.ek * 0.5;
+  double Bk = 1.0 + (1.0 + pk0) * (1.0 + pk0);
+  P.sW3 = p2floor(S.ez / l1);
+  P.sEta = p2floor(S.ez / (l1 * Rb));
+  double wz = S.ez / (l1 * Hb), wk = (S.ek * Rg) / (l1 * Bk);
+  P.sW = p2floor(wz < wk ? wz : wk);
+  P.sXi = p2floor(S.ek / (l1 * Bk));
+  P.padz = std::ceil((S.epsn[2] + S.ez * 0.5) / P.sW3) * P.sW3;
+  P.padk = std::ceil((epsk + S.ek * 0.5) / P.sXi) * P.sXi;
+  P.inv_sW = 1.0 / P.sW;
+  P.inv_sW3 = 1.0 / P.sW3;
+  P.inv_sXi = 1.0 / P.sXi;
+  P.inv_sEta = 1.0 / P.sEta;
+  P.Rg2f = (float)P.Rg2;
+  P.padzf = (float)P.padz;
+  P.padkf = (float)P.padk;
+}
+
+// binary32 evaluation is exact on the inputs iff every lattice value and
+// every difference the filter forms fits 24 significant bits
+bool pose_filter_exact(const Setup& S, const double* mx) {
+  const ProbC& P = S.P;
+  const double T = 16777216.0;  // 2^24
+  double W12 = std::max(mx[2], mx[3]);
+  if (P.L[0] > 23 || P.L[1] > 23 || P.L[2] > 23 || P.L[3] > 22) return false;
+  if (!(W12 + 1.0 < T * P.sW)) return false;
+  if (!(mx[4] + 1.0 + P.padz + 1.0 < T * std::min(P.sW3, std::ldexp(1.0, -P.L[2])))) return false;
+  if (!(mx[5] < T * P.sXi)) return false;
+  if (!(mx[6] < T * P.sEta)) return false;
+  if (!(1.0 + P.padk < T * std::min(P.sXi, std::ldexp(1.0, -(P.L[3] - 1))))) return false;
+  if (P.sW < 0x1p-40 || P.sEta < 0x1p-40 || P.sXi < 0x1p-40) return false;
+  return true;
+}
+
+struct Batch {
+  int level;
+  uint32_t ncell;
+  uint64_t nent;
+  Cell* cells;
+  void* ents;
+};
+
+struct Run {
+  gv_ctx* ctx;
+  hipStream_t st;
+  Setup S;
+  ProbC* dP = nullptr;
+  unsigned long long* dbest = nullptr;
+  unsigned long long* drecheck = nullptr;
+  uint64_t* dtot = nullptr;
+  uint64_t budget_entries = 0;
+  gv_stats stats{};
+  double* m64 = nullptr;  // pose master
+  int64_t n = 0;
+};
+
+template <typename T>
+T* dalloc(Run& X, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMallocAsync(&p, count * sizeof(T), X.st);
+  if (e != hipSuccess) {
+    X.ctx->err = std::string("hipMallocAsync: ") + hipGetErrorString(e);
+    throw DevErr{GV_ENOMEM};
+  }
+  return (T*)p;
+}
+void dfree(Run& X, void* p) {
+  if (p) (void)hipFreeAsync(p, X.st);
+}
+
+template <typename In, typename Out>
+void excl_scan(Run& X, const In* in, Out* out, uint64_t n) {
+  if (n == 0) return;
+  size_t tb = 0;
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, X.st));
+  void* tmp = dalloc<char>(X, tb);
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(tmp, tb, in, out, (int)n, X.st));
+  dfree(X, tmp);
+}
+
+inline unsigned nblk(uint64_t n, unsigned b = 256) { return (unsigned)std::max<uint64_t>(1, (n + b - 1) / b); }
+inline unsigned gs_grid(Run& X, uint64_t n) {
+  return (unsigned)std::min<uint64_t>(nblk(n), (uint64_t)X.ctx->n_cu * 16);
+}
+
+template <int FAM> struct FamTraits {
+  using E = typename EntOf<FAM>::T;
+  using M = uint8_t;
+};
+
+// one expansion of a batch: count, prune (or pick for the dive), compact
+template <int FAM, typename E, typename M>
+void expand(Run& X, Batch& b, bool dive, std::vector<Batch>& out) {
+  const ProbC& P = X.S.P;
+  const int m = b.level;
+  const LevelC lv = P.lev[m];
+  const uint32_t nch = 1u << lv.abits;
+  const bool leaf = (m + 1 == P.Lstar);
+  const uint64_t nk = (uint64_t)b.ncell * nch;
+  X.stats.tests += b.nent * nch;
+  X.stats.cells_expanded += b.ncell;
+
+  // work items
+  uint32_t* nitem = dalloc<uint32_t>(X, b.ncell);
+  uint32_t* ioff = dalloc<uint32_t>(X, b.ncell);
+  const uint64_t max_items = b.ncell + b.nent / GV_ITEM + 1;
+  Item* items = dalloc<Item>(X, max_items);
+  uint32_t* nitems = dalloc<uint32_t>(X, 1);
+  HIPCHK(hipMemsetAsync(nitems, 0, sizeof(uint32_t), X.st));
+  k_item_counts<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem);
+  excl_scan(X, nitem, ioff, b.ncell);
+  k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, ioff, items, nitems);
+  dfree(X, nitem);
+  dfree(X, ioff);
+
+  M* masks = dalloc<M>(X, b.nent);
+  uint32_t* ccnt = dalloc<uint32_t>(X, nk);
+  uint32_t* cnent = dalloc<uint32_t>(X, nk);
+  HIPCHK(hipMemsetAsync(ccnt, 0, nk * sizeof(uint32_t), X.st));
+  HIPCHK(hipMemsetAsync(cnent, 0, nk * sizeof(uint32_t), X.st));
+  const unsigned grid = (unsigned)std::min<uint64_t>((max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
+  if constexpr (FAM == FAM_POSE4DOF) {
+    k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, items, nitems, (const E*)b.ents, X.m64,
+                                             (uint64_t)X.n, (uint16_t*)masks, ccnt, cnent, X.drecheck);
+  } else {
+    k_count_lin<FAM><<<grid, 256, 0, X.st>>>(lv, b.cells, items, nitems, (const E*)b.ents, (uint8_t*)masks, ccnt,
+                                              cnent);
+  }
+  HIPCHK(hipGetLastError());
+
+  uint32_t* keepf = dalloc<uint32_t>(X, nk);
+  uint64_t* keptn = dalloc<uint64_t>(X, nk);
+  if (dive) {
+    k_pick_best<<<1, 64, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, ccnt, cnent, X.dbest, keepf, keptn);
+  } else {
+    k_prune<<<nblk(nk), 256, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, b.ncell, ccnt, cnent, X.dbest,
+                                        keepf, keptn);
+  }
+  HIPCHK(hipGetLastError());
+  dfree(X, ccnt);
+  if (leaf) {
+    dfree(X, keepf);
+    dfree(X, keptn);
+    dfree(X, cnent);
+    dfree(X, masks);
+    dfree(X, items);
+    dfree(X, nitems);
+    return;
+  }
+  uint32_t* keepscan = dalloc<uint32_t>(X, nk);
+  uint64_t* nscan = dalloc<uint64_t>(X, nk);
+  excl_scan(X, keepf, keepscan, nk);
+  excl_scan(X, keptn, nscan, nk);
+  k_totals<<<1, 64, 0, X.st>>>(keepf, keepscan, keptn, nscan, nk, X.dtot);
+  uint64_t tot[2];
+  HIPCHK(hipMemcpyAsync(tot, X.dtot, sizeof(tot), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  const uint64_t nkept = tot[0], nentk = tot[1];
+  X.stats.cells_pruned += nk - nkept;
+  if (nkept > 0) {
+    // cut into chunks of whole parents whose children hold <= budget entries
+    std::vector<std::pair<uint32_t, uint32_t>> chunks;
+    std::vector<uint64_t> cumE, cumC;
+    if (nentk <= X.budget_entries || b.ncell == 1) {
+      chunks.push_back({0u, b.ncell});
+    } else {
+      uint64_t* cum = dalloc<uint64_t>(X, b.ncell + 1);
+      k_parent_cum<<<nblk(b.ncell), 256, 0, X.st>>>(nscan, keptn, b.ncell, nch, cum);
+      cumE.resize(b.ncell + 1);
+      HIPCHK(hipMemcpyAsync(cumE.data(), cum, (b.ncell + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
+      HIPCHK(hipStreamSynchronize(X.st));
+      dfree(X, cum);
+      uint32_t c0 = 0;
+      while (c0 < b.ncell) {
+        uint32_t c1 = c0 + 1;
+        while (c1 < b.ncell && cumE[c1 + 1] - cumE[c0] <= X.budget_entries) c1++;
+        chunks.push_back({c0, c1});
+        c0 = c1;
+      }
+    }
+    // kept children per chunk (from keepscan at chunk boundaries)
+    std::vector<uint32_t> kb(chunks.size() + 1);
+    std::vector<uint64_t> eb(chunks.size() + 1);
+    {
+      std::vector<uint64_t> idx;
+      for (auto& c : chunks) idx.push_back((uint64_t)c.first * nch);
+      for (size_t i = 0; i < chunks.size(); i++) {
+        uint32_t v;
+        uint64_t w;
+        HIPCHK(hipMemcpyAsync(&v, keepscan + idx[i], sizeof(v), hipMemcpyDeviceToHost, X.st));
+        HIPCHK(hipMemcpyAsync(&w, nscan + idx[i], sizeof(w), hipMemcpyDeviceToHost, X.st));
+        HIPCHK(hipStreamSynchronize(X.st));
+        kb[i] = v;
+        eb[i] = w;
+      }
+      kb[chunks.size()] = (uint32_t)nkept;
+      eb[chunks.size()] = nentk;
+    }
+    uint32_t* cursor = dalloc<uint32_t>(X, nk);
+    const unsigned cgrid = grid;
+    std::vector<Batch> made;
+    for (size_t i = 0; i < chunks.size(); i++) {
+      Batch nb;
+      nb.level = m + 1;
+      nb.ncell = kb[i + 1] - kb[i];
+      nb.nent = eb[i + 1] - eb[i];
+      if (nb.ncell == 0) continue;
+      nb.cells = dalloc<Cell>(X, nb.ncell);
+      nb.ents = dalloc<E>(X, nb.nent);
+      const uint32_t c0 = chunks[i].first, c1 = chunks[i].second;
+      const uint64_t nkc = (uint64_t)(c1 - c0) * nch;
+      k_emit_cells<<<nblk(nkc), 256, 0, X.st>>>(lv, b.cells, c0, c1, keepf, keepscan, nscan, cnent, nb.cells, cursor);
+      if constexpr (FAM == FAM_POSE4DOF) {
+        k_compact_pose<E><<<cgrid, 256, 0, X.st>>>(lv, b.cells, c0, c1, items, nitems, (const E*)b.ents,
+                                                    (const uint16_t*)masks, keepf, nscan, cursor, (E*)nb.ents);
+      } else {
+        k_compact_lin<FAM><<<cgrid, 256, 0, X.st>>>(lv, b.cells, c0, c1, items, nitems, (const E*)b.ents,
+                                                      (const uint8_t*)masks, keepf, nscan, cursor, (E*)nb.ents);
+      }
+      HIPCHK(hipGetLastError());
+      made.push_back(nb);
+    }
+    dfree(X, cursor);
+    // depth-first: the first chunk is expanded next
+    for (auto it = made.rbegin(); it != made.rend(); ++it) out.push_back(*it);
+  }
+  dfree(X, keepf);
+  dfree(X, keptn);
+  dfree(X, keepscan);
+  dfree(X, nscan);
+  dfree(X, cnent);
+  dfree(X, masks);
+  dfree(X, items);
+  dfree(X, nitems);
+}
+
+template <int FAM, typename E, typename M>
+void search(Run& X, E* root, int64_t n) {
+  const ProbC& P = X.S.P;
+  const int nsec = P.nsec;
+  // greedy dive per sector: an achieved leaf key is a valid starting bound
+  for (int s = 0; s < nsec; s++) {
+    Batch b;
+    b.level = 0;
+    b.ncell = 1;
+    b.nent = (uint64_t)n;
+    b.cells = dalloc<Cell>(X, 1);
+    k_root_cells<<<1, 64, 0, X.st>>>(b.cells, 1, s, (uint64_t)n, 1);
+    b.ents = root;
+    bool own = false;
+    while (true) {
+      std::vector<Batch> nxt;
+      expand<FAM, E, M>(X, b, true, nxt);
+      dfree(X, b.cells);
+      if (own) dfree(X, b.ents);
+      if (nxt.empty()) break;
+      b = nxt[0];
+      own = true;
+    }
+  }
+  // depth-first over batches
+  std::vector<Batch> stack;
+  {
+    Batch r;
+    r.level = 0;
+    r.ncell = (uint32_t)nsec;
+    r.nent = (uint64_t)n * nsec;
+    r.cells = dalloc<Cell>(X, nsec);
+    k_root_cells<<<1, 64, 0, X.st>>>(r.cells, nsec, 0, (uint64_t)n, 0);
+    if (nsec == 1) {
+      r.ents = root;
+    } else {
+      E* rep = dalloc<E>(X, (uint64_t)n * nsec);
+      k_replicate<E><<<gs_grid(X, (uint64_t)n * nsec), 256, 0, X.st>>>(root, n, nsec, rep);
+      r.ents = rep;
+    }
+    stack.push_back(r);
+  }
+  bool first = true;
+  while (!stack.empty()) {
+    Batch b = stack.back();
+    stack.pop_back();
+    std::vector<Batch> kids;
+    expand<FAM, E, M>(X, b, false, kids);
+    dfree(X, b.cells);
+    if (!(first && nsec == 1)) dfree(X, b.ents);
+    first = false;
+    for (auto& k : kids) stack.push_back(k);
+  }
+}
+
+void check_bad(Run& X, int* dbad) {
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  if (bad & 1) {
+    X.ctx->err = "non-finite observation or zero ray direction";
+    throw DevErr{GV_EINVAL};
+  }
+  if (bad & 2) {
+    X.ctx->err = "lattice too fine for 32-bit cells";
+    throw DevErr{GV_ERANGE};
+  }
+}
+
+template <int FAM>
+void run_linear(Run& X, Cols cols, PathC& path, uint64_t& best) {
+  using E = typename EntOf<FAM>::T;
+  const int64_t n = X.n;
+  E* root = dalloc<E>(X, n);
+  unsigned* dmax = dalloc<unsigned>(X, 2);
+  int* dbad = dalloc<int>(X, 1);
+  HIPCHK(hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned), X.st));
+  HIPCHK(hipMemsetAsync(dbad, 0, sizeof(int), X.st));
+  if (n > 0) k_root_lin<FAM><<<gs_grid(X, n), 256, 0, X.st>>>(X.dP, cols, n, root, dmax, dbad);
+  check_bad(X, dbad);
+  unsigned mx[2];
+  HIPCHK(hipMemcpyAsync(mx, dmax, sizeof(mx), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  {
+    // every intermediate of the integer test stays below 2^30
+    const ProbC& P = X.S.P;
+    double Hmax = 0, padmax = 0;
+    for (int j = 0; j < X.S.d; j++) {
+      Hmax = std::max(Hmax, (double)P.lev[0].H[j]);
+      padmax = std::max(padmax, (double)P.lev[0].padu[j]);
+    }
+    const double np = (FAM == FAM_PLANE3D) ? 2.0 : 1.0;
+    const double Fb = std::max((double)mx[1], Hmax + padmax + np * mx[0]);
+    if (2.0 * Fb + 2.0 * np * mx[0] + 2.0 * Hmax + padmax >= 1073741824.0) {
+      X.ctx->err = "lattice too fine for 32-bit cells";
+      throw DevErr{GV_ERANGE};
+    }
+  }
+  dfree(X, dmax);
+  search<FAM, E, uint8_t>(X, root, n);
+  dfree(X, root);
+  HIPCHK(hipMemcpyAsync(&best, X.dbest, sizeof(best), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  (void)path;
+  dfree(X, dbad);
+}
+
+void run_pose(Run& X, Cols cols, double epsk, bool want_filter, uint64_t& best) {
+  const int64_t n = X.n;
+  unsigned long long* dmx = dalloc<unsigned long long>(X, 8);
+  int* dbad = dalloc<int>(X, 1);
+  HIPCHK(hipMemsetAsync(dmx, 0, 8 * sizeof(unsigned long long), X.st));
+  HIPCHK(hipMemsetAsync(dbad, 0, sizeof(int), X.st));
+  if (n > 0) k_pose_bounds<<<gs_grid(X, n), 256, 0, X.st>>>(X.dP, cols, n, dmx, dbad);
+  check_bad(X, dbad);
+  unsigned long long mxb[8];
+  HIPCHK(hipMemcpyAsync(mxb, dmx, sizeof(mxb), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  double mx[8];
+  for (int k = 0; k < 8; k++) std::memcpy(&mx[k], &mxb[k], 8);
+  pose_lattice(X.S, mx[0], mx[1], epsk);
+  HIPCHK(hipMemcpyAsync(X.dP, &X.S.P, sizeof(ProbC), hipMemcpyHostToDevice, X.st));
+  X.m64 = dalloc<double>(X, (uint64_t)n * 5);
+  EntQ32* e32 = want_filter ? dalloc<EntQ32>(X, n) : nullptr;
+  EntQ64* e64 = dalloc<EntQ64>(X, n);
+  if (n > 0) k_root_pose<<<gs_grid(X, n), 256, 0, X.st>>>(X.dP, cols, n, X.m64, e32, e64, dmx);
+  HIPCHK(hipMemcpyAsync(mxb, dmx, sizeof(mxb), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  for (int k = 0; k < 8; k++) std::memcpy(&mx[k], &mxb[k], 8);
+  const bool filt = want_filter && pose_filter_exact(X.S, mx);
+  X.S.filter = filt;
+  if (filt) {
+    dfree(X, e64);
+    search<FAM_POSE4DOF, EntQ32, uint16_t>(X, e32, n);
+    dfree(X, e32);
+  } else {
+    if (e32) dfree(X, e32);
+    search<FAM_POSE4DOF, EntQ64, uint16_t>(X, e64, n);
+    dfree(X, e64);
+  }
+  HIPCHK(hipMemcpyAsync(&best, X.dbest, sizeof(best), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  dfree(X, dmx);
+  dfree(X, dbad);
+}
+
+void decode_leaf(const ProbC& P, uint64_t idx, PathC& path, int32_t* coords) {
+  path.sector = P.fam == GV_POSE4DOF ? (int32_t)(idx >> P.Bcell) : 0;
+  int32_t cc[4] = {0, 0, 0, 0};
+  for (int m = 0; m < P.Lstar; m++) {
+    const LevelC& lv = P.lev[m];
+    const uint32_t dg = (uint32_t)((idx >> lv.rem_next) & ((1ull << lv.abits) - 1ull));
+    path.digit[m] = (uint8_t)dg;
+    const uint32_t cb = lv.cbits[dg];
+    for (int a = 0; a < 4; a++)
+      if (lv.split[a]) cc[a] = 2 * cc[a] + (int32_t)((cb >> a) & 1u);
+  }
+  for (int a = 0; a < 4; a++) coords[a] = cc[a];
+}
+
+gv_status solve_impl(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
+  auto t0 = std::chrono::steady_clock::now();
+  Run X;
+  X.ctx = ctx;
+  X.st = ctx->stream;
+  X.n = p->n;
+  std::string why;
+  gv_status st = setup_axes(p, X.S, why);
+  if (st != GV_OK) {
+    ctx->err = why;
+    return st;
+  }
+  const ProbC& P = X.S.P;
+  std::vector<void*> owned;
+  try {
+    HIPCHK(hipSetDevice(ctx->device));
+    // entries budget: a quarter of the memory budget per batch
+    X.budget_entries = std::max<uint64_t>(1ull << 20, ctx->budget / 4 / 48);
+    X.dP = dalloc<ProbC>(X, 1);
+    X.dbest = dalloc<unsigned long long>(X, 1);
+    X.drecheck = dalloc<unsigned long long>(X, 1);
+    X.dtot = dalloc<uint64_t>(X, 2);
+    HIPCHK(hipMemsetAsync(X.dbest, 0, 8, X.st));
+    HIPCHK(hipMemsetAsync(X.drecheck, 0, 8, X.st));
+    HIPCHK(hipMemcpyAsync(X.dP, &P, sizeof(ProbC), hipMemcpyHostToDevice, X.st));
+    const int ncol = p->family == GV_RAY3D ? 6 : (p->family == GV_POSE4DOF ? 5 : X.S.d);
+    Cols cols{};
+    for (int k = 0; k < ncol; k++) {
+      if (!p->col[k] && p->n > 0) {
+        ctx->err = "missing column";
+        return GV_EINVAL;
+      }
+      if (p->cols_on_device || p->n == 0) {
+        cols.c[k] = p->col[k];
+      } else {
+        double* d = dalloc<double>(X, p->n);
+        HIPCHK(hipMemcpyAsync(d, p->col[k], p->n * sizeof(double), hipMemcpyHostToDevice, X.st));
+        owned.push_back(d);
+        cols.c[k] = d;
+      }
+    }
+    uint64_t best = 0;
+    PathC path{};
+    switch (p->family) {
+      case GV_LINE2D: run_linear<FAM_LINE2D>(X, cols, path, best); break;
+      case GV_PLANE3D: run_linear<FAM_PLANE3D>(X, cols, path, best); break;
+      case GV_RAY3D: run_linear<FAM_RAY3D>(X, cols, path, best); break;
+      default: run_pose(X, cols, p->eps[3], p->precision == GV_FP32_FILTER, best); break;
+    }
+    const uint64_t count = best >> P.B;
+    const uint64_t leaf = P.idxmask - (best & P.idxmask);
+    int32_t coords[4];
+    decode_leaf(X.S.P, leaf, path, coords);
+    // inliers by replay
+    uint32_t* flag = dalloc<uint32_t>(X, X.n);
+    uint32_t* pos = dalloc<uint32_t>(X, X.n);
+    int* dbad = dalloc<int>(X, 1);
+    HIPCHK(hipMemsetAsync(dbad, 0, sizeof(int), X.st));
+    if (X.n > 0) {
+      switch (p->family) {
+        case GV_LINE2D: k_replay_lin<FAM_LINE2D><<<gs_grid(X, X.n), 256, 0, X.st>>>(X.dP, cols, X.n, path, flag, dbad); break;
+        case GV_PLANE3D: k_replay_lin<FAM_PLANE3D><<<gs_grid(X, X.n), 256, 0, X.st>>>(X.dP, cols, X.n, path, flag, dbad); break;
+        case GV_RAY3D: k_replay_lin<FAM_RAY3D><<<gs_grid(X, X.n), 256, 0, X.st>>>(X.dP, cols, X.n, path, flag, dbad); break;
+        default: k_replay_pose<<<gs_grid(X, X.n), 256, 0, X.st>>>(X.dP, X.m64, X.n, path, flag); break;
+      }
+      HIPCHK(hipGetLastError());
+      excl_scan(X, flag, pos, (uint64_t)X.n);
+    }
+    uint32_t last[2] = {0, 0};
+    if (X.n > 0) {
+      HIPCHK(hipMemcpyAsync(&last[0], pos + X.n - 1, 4, hipMemcpyDeviceToHost, X.st));
+      HIPCHK(hipMemcpyAsync(&last[1], flag + X.n - 1, 4, hipMemcpyDeviceToHost, X.st));
+    }
+    unsigned long long rech = 0;
+    HIPCHK(hipMemcpyAsync(&rech, X.drecheck, 8, hipMemcpyDeviceToHost, X.st));
+    HIPCHK(hipStreamSynchronize(X.st));
+    const uint64_t ninl = (uint64_t)last[0] + last[1];
+    r->count = count;
+    r->leaf_index = leaf;
+    r->sector = path.sector;
+    for (int a = 0; a < 4; a++) r->leaf_coords[a] = a < X.S.d ? coords[a] : 0;
+    for (int j = 0; j < 4; j++) r->point[j] = 0.0;
+    for (int j = 0; j < X.S.d; j++) {
+      double u = (double)(2 * coords[j] + 1) * std::ldexp(1.0, -(P.L[j] + 1));
+      r->point[j] = P.lo[j] + P.E[j] * u;
+    }
+    if (p->family == GV_POSE4DOF) {
+      double yaw = (double)path.sector * (M_PI / 2.0) + std::atan(r->point[3]);
+      if (yaw < 0.0) yaw += 2.0 * M_PI;
+      if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
+      r->point[3] = yaw;
+    }
+    for (int j = 0; j < 4; j++) r->bound[j] = 0.0;
+    for (int j = 0; j < X.S.d; j++) {
+      if (p->family == GV_POSE4DOF) {
+        r->bound[j] = j == 2 ? (P.padz + X.S.ez * 0.5) * P.E[2] : (j == 3 ? P.padk + X.S.ek * 0.5 : 0.5 * std::ldexp(P.E[j], -P.L[j]));
+      } else {
+        const double Em = (double)(P.Lstar * (X.S.ell + 1)) * P.sf[j] * 0.5;
+        r->bound[j] = (X.S.epsn[j] + 2.0 * Em + P.sf[j]) * P.E[j];
+      }
+    }
+    r->n_inliers = ninl;
+    gv_status out = GV_OK;
+    if (ninl != count) {
+      ctx->err = "internal: replayed inlier count differs from the leaf count";
+      out = GV_EDEVICE;
+    } else if (ninl > r->inliers_cap || (!r->inliers && ninl > 0)) {
+      out = GV_EBUFSZ;
+    } else if (ninl > 0) {
+      int64_t* dout = dalloc<int64_t>(X, ninl);
+      k_write_inliers<<<gs_grid(X, X.n), 256, 0, X.st>>>(flag, pos, X.n, dout);
+      HIPCHK(hipMemcpyAsync(r->inliers, dout, ninl * sizeof(int64_t), hipMemcpyDeviceToHost, X.st));
+      HIPCHK(hipStreamSynchronize(X.st));
+      dfree(X, dout);
+    }
+    dfree(X, flag);
+    dfree(X, pos);
+    dfree(X, dbad);
+    if (X.m64) dfree(X, X.m64);
+    for (void* q : owned) dfree(X, q);
+    dfree(X, X.dP);
+    dfree(X, X.dbest);
+    dfree(X, X.drecheck);
+    dfree(X, X.dtot);
+    HIPCHK(hipStreamSynchronize(X.st));
+    X.stats.fp64_rechecks = rech;
+    X.stats.levels = (uint32_t)P.Lstar;
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    X.stats.ms_total = ms;
+    X.stats.ms_kernels = ms;
+    r->stats = X.stats;
+    return out;
+  } catch (DevErr& e) {
+    for (void* q : owned) dfree(X, q);
+    (void)hipStreamSynchronize(X.st);
+    return e.st;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* gv_status_str(gv_status s) {
+  switch (s) {
+    case GV_OK: return "ok";
+    case GV_EINVAL: return "invalid argument";
+    case GV_ENOMEM: return "out of memory";
+    case GV_ETOOBIG: return "problem exceeds the memory budget";
+    case GV_EBUFSZ: return "inlier buffer too small";
+    case GV_EAGAIN: return "not finished";
+    case GV_ETIMEDOUT: return "timed out";
+    case GV_ECANCELED: return "cancelled";
+    case GV_EDEVICE: return "device error";
+    case GV_ERANGE: return "lattice too fine for the device arithmetic";
+  }
+  return "unknown status";
+}
+
+const char* gv_last_error(gv_ctx* ctx) {
+  if (!ctx) return "";
+  std::lock_guard<std::mutex> g(ctx->mu);
+  tl_err = ctx->err;
+  return tl_err.c_str();
+}
+
+gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
+  if (!out) return GV_EINVAL;
+  *out = nullptr;
+  gv_ctx* c = new (std::nothrow) gv_ctx();
+  if (!c) return GV_ENOMEM;
+  c->device = cfg ? cfg->device : 0;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    delete c;
+    return GV_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  if (cfg && cfg->hip_stream) {
+    c->stream = (hipStream_t)cfg->hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return GV_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  size_t fr = 0, tot = 0;
+  (void)hipMemGetInfo(&fr, &tot);
+  c->budget = (cfg && cfg->mem_budget_bytes) ? cfg->mem_budget_bytes : (uint64_t)(0.6 * (double)fr);
+  // keep freed blocks in the stream-ordered pool
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  *out = c;
+  return GV_OK;
+}
+
+gv_status gv_destroy(gv_ctx* ctx) {
+  if (!ctx) return GV_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return GV_OK;
+}
+
+gv_status gv_solve(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
+  if (!ctx || !p || !r) return GV_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->err.clear();
+  std::memset(&r->stats, 0, sizeof(r->stats));
+  return solve_impl(ctx, p, r);
+}
+
+gv_status gv_parametrize(gv_ctx* ctx, const gv_problem* p, double* t_out, double* f_out, int32_t* tag_out) {
+  if (!ctx || !p || (!t_out && p->n > 0) || (!f_out && p->n > 0)) return GV_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->err.clear();
+  Run X;
+  X.ctx = ctx;
+  X.st = ctx->stream;
+  X.n = p->n;
+  std::string why;
+  gv_status st = setup_axes(p, X.S, why);
+  if (st != GV_OK && st != GV_ERANGE) {
+    ctx->err = why;
+    return st;
+  }
+  std::vector<void*> owned;
+  try {
+    HIPCHK(hipSetDevice(ctx->device));
+    X.dP = dalloc<ProbC>(X, 1);
+    HIPCHK(hipMemcpyAsync(X.dP, &X.S.P, sizeof(ProbC), hipMemcpyHostToDevice, X.st));
+    const int ncol = p->family == GV_RAY3D ? 6 : (p->family == GV_POSE4DOF ? 5 : X.S.d);
+    Cols cols{};
+    for (int k = 0; k < ncol; k++) {
+      if (p->cols_on_device || p->n == 0) {
+        cols.c[k] = p->col[k];
+      } else {
+        double* d = dalloc<double>(X, p->n);
+        HIPCHK(hipMemcpyAsync(d, p->col[k], p->n * sizeof(double), hipMemcpyHostToDevice, X.st));
+        owned.push_back(d);
+        cols.c[k] = d;
+      }
+    }
+    if (p->n > 0) {
+      double* t = dalloc<double>(X, (uint64_t)p->n * 4);
+      double* f = dalloc<double>(X, (uint64_t)p->n * 2);
+      int32_t* tg = dalloc<int32_t>(X, p->n);
+      int* bad = dalloc<int>(X, 1);
+      HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), X.st));
+      k_front<<<gs_grid(X, p->n), 256, 0, X.st>>>((int)p->family, X.dP, cols, p->n, t, f, tg, bad);
+      HIPCHK(hipMemcpyAsync(t_out, t, p->n * 4 * sizeof(double), hipMemcpyDeviceToHost, X.st));
+      HIPCHK(hipMemcpyAsync(f_out, f, p->n * 2 * sizeof(double), hipMemcpyDeviceToHost, X.st));
+      if (tag_out) HIPCHK(hipMemcpyAsync(tag_out, tg, p->n * sizeof(int32_t), hipMemcpyDeviceToHost, X.st));
+      int hb = 0;
+      HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, X.st));
+      HIPCHK(hipStreamSynchronize(X.st));
+      dfree(X, t);
+      dfree(X, f);
+      dfree(X, tg);
+      dfree(X, bad);
+      if (hb) {
+        ctx->err = "non-finite observation or zero ray direction";
+        st = GV_EINVAL;
+      }
+    }
+    for (void* q : owned) dfree(X, q);
+    dfree(X, X.dP);
+    HIPCHK(hipStreamSynchronize(X.st));
+    return st == GV_ERANGE ? GV_OK : st;
+  } catch (DevErr& e) {
+    (void)hipStreamSynchronize(X.st);
+    return e.st;
+  }
+}
+
+gv_status gv_submit(gv_ctx* ctx, const gv_problem* p, uint64_t* ticket) {
+  (void)p;
+  (void)ticket;
+  if (ctx) ctx->err = "continuous batching is not built yet";
+  return GV_EINVAL;
+}
+gv_status gv_poll(gv_ctx* ctx, uint64_t ticket, gv_result* r, int timeout_ms) {
+  (void)ticket;
+  (void)r;
+  (void)timeout_ms;
+  if (ctx) ctx->err = "continuous batching is not built yet";
+  return GV_EINVAL;
+}
+gv_status gv_cancel(gv_ctx* ctx, uint64_t ticket) {
+  (void)ticket;
+  if (ctx) ctx->err = "continuous batching is not built yet";
+  return GV_EINVAL;
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Bar: bit-exact on everything integer (count, leaf index, sorted inlier
+indices) and on the returned binary64 point; bit-exact front-end parameters.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_11810_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2107_11810_amd import gvote
+    c = gvote.Context(0)
+    yield c
+    c.close()
+
+
+def OP(g, **kw):
+    return oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], **kw)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check_same(g, r_gpu, r_or):
+    assert r_gpu["count"] == r_or["count"], (r_gpu["count"], r_or["count"])
+    assert r_gpu["leaf_index"] == r_or["leaf_index"]
+    assert r_gpu["sector"] == r_or["sector"]
+    assert r_gpu["n_inliers"] == r_or["n_inliers"]
+    assert np.array_equal(r_gpu["inliers"], r_or["inliers"])
+    d = 4 if g["family"] == "pose4dof" else len(g["lo"])
+    assert r_gpu["leaf_coords"][:d] == r_or["leaf_coords"][:d]
+    for j in range(d):
+        assert r_gpu["point"][j] == r_or["point"][j]  # bit-equal binary64
+
+
+FAMS = ["line2d", "plane3d", "ray3d", "pose4dof"]
+
+
+@pytest.mark.parametrize("name", [f + "_small" for f in FAMS] + ["line2d_10k"])
+def test_front_end_bit_exact(ctx, name):
+    g = synth.config(name)
+    _say("front", name)
+    t, f, tag = ctx.parametrize(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    to, fo, tago = oracle.parametrize(OP(g))
+    assert np.array_equal(t.view(np.uint64), to.view(np.uint64))
+    assert np.array_equal(f.view(np.uint64), fo.view(np.uint64))
+    assert np.array_equal(tag, tago)
+
+
+@pytest.mark.parametrize("fam", FAMS)
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_tiny_parity(ctx, fam, seed):
+    g = synth.config(fam + "_tiny", seed=seed)
+    _say("tiny", fam, seed)
+    ro = oracle.solve(OP(g))
+    for prec in (0, 1):
+        rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], precision=prec)
+        check_same(g, rg, ro)
+
+
+@pytest.mark.parametrize("fam", FAMS)
+@pytest.mark.parametrize("seed", [None, 21])
+def test_small_parity(ctx, fam, seed):
+    g = synth.config(fam + "_small") if seed is None else synth.config(fam + "_small", seed=seed)
+    _say("small", fam, seed)
+    ro = oracle.solve(OP(g))
+    for prec in (0, 1):
+        rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], precision=prec)
+        check_same(g, rg, ro)
+        if fam == "pose4dof" and prec == 1:
+            _say("  rechecks", rg["stats"]["fp64_rechecks"], "tests", rg["stats"]["tests"])
+
+
+def test_line2d_10k_full_parity(ctx):
+    g = synth.config("line2d_10k")
+    _say("line2d_10k")
+    ro = oracle.solve(OP(g))
+    rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    check_same(g, rg, ro)
+
+
+@pytest.mark.parametrize("canon_c", [0.25, 4.0])
+def test_canon_constant_parity(ctx, canon_c):
+    for fam in ("line2d", "ray3d"):
+        g = synth.config(fam + "_small")
+        _say("canon_c", fam, canon_c)
+        ro = oracle.solve(OP(g, canon_c=canon_c))
+        rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], canon_c=canon_c)
+        check_same(g, rg, ro)
+
+
+def test_device_columns_and_determinism(ctx):
+    from paper_2107_11810_amd import gvote
+    g = synth.config("plane3d_small")
+    _say("device columns")
+    cols = gvote.to_device(g["cols"])
+    r1 = ctx.solve(g["family"], cols, g["lo"], g["hi"], g["eps"])
+    r2 = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    assert r1["count"] == r2["count"] and r1["leaf_index"] == r2["leaf_index"]
+    assert np.array_equal(r1["inliers"], r2["inliers"])
+    for _ in range(2):
+        r3 = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+        assert np.array_equal(r3["inliers"], r1["inliers"]) and r3["count"] == r1["count"]
+
+
+def test_edge_cases(ctx):
+    from paper_2107_11810_amd import gvote
+    _say("edge cases")
+    # empty input: leaf 0 with count 0
+    g = synth.config("line2d_tiny")
+    e = [np.zeros(0), np.zeros(0)]
+    r = ctx.solve("line2d", e, g["lo"], g["hi"], g["eps"])
+    ro = oracle.solve(oracle.Problem("line2d", e, g["lo"], g["hi"], g["eps"]))
+    assert (r["count"], r["leaf_index"]) == (ro["count"], ro["leaf_index"]) == (0, 0)
+    # a single surface
+    one = [np.array([0.3]), np.array([0.6])]
+    r = ctx.solve("line2d", one, g["lo"], g["hi"], g["eps"])
+    ro = oracle.solve(oracle.Problem("line2d", one, g["lo"], g["hi"], g["eps"]))
+    assert (r["count"], r["leaf_index"]) == (ro["count"], ro["leaf_index"])
+    # non-finite input
+    bad = [np.array([0.3, np.nan]), np.array([0.6, 0.1])]
+    with pytest.raises(gvote.GvError) as ei:
+        ctx.solve("line2d", bad, g["lo"], g["hi"], g["eps"])
+    assert ei.value.status == -1
+    # E_x != E_y for POSE4DOF
+    gp = synth.config("pose4dof_tiny")
+    with pytest.raises(gvote.GvError):
+        ctx.solve("pose4dof", gp["cols"], [0, 0, 0, 0], [200, 100, 200, 6.28], gp["eps"])
+    # inlier buffer too small
+    g = synth.config("line2d_small")
+    with pytest.raises(gvote.GvError) as ei:
+        ctx.solve("line2d", g["cols"], g["lo"], g["hi"], g["eps"], cap=3)
+    assert ei.value.status == -4
+    # identical observations merge into one weighted canonical surface
+    x = np.full(40, 0.25)
+    y = np.full(40, 0.5)
+    r = ctx.solve("line2d", [x, y], g["lo"], g["hi"], g["eps"])
+    ro = oracle.solve(oracle.Problem("line2d", [x, y], g["lo"], g["hi"], g["eps"]))
+    assert r["count"] == ro["count"] == 40 and r["leaf_index"] == ro["leaf_index"]
+
+
+def test_ragged_many_cells(ctx):
+    """Lists spanning several work items and many cells with a ragged tail."""
+    g = synth.line2d(seed=7, n=5000, n_in=40, sigma=0.01, eps=(0.02, 0.02))
+    _say("ragged")
+    ro = oracle.solve(OP(g))
+    rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    check_same(g, rg, ro)
