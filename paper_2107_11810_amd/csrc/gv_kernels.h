@@ -337,121 +337,112 @@ __global__ void k_pick_best(LevelC lv, int B, uint64_t idxmask, int leaf, const 
   }
 }
 
-// totals after the scans: kept children and their entries
-__global__ void k_totals(const uint32_t* keepf, const uint32_t* keepscan, const uint64_t* keptn,
-                         const uint64_t* nscan, uint64_t nk, uint64_t* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    out[0] = nk ? (uint64_t)keepscan[nk - 1] + keepf[nk - 1] : 0;
-    out[1] = nk ? nscan[nk - 1] + keptn[nk - 1] : 0;
+// ---------------------------------------------------------------------------
+// Ordering of kept children: highest count first (radix sort on the host
+// side), so the first descent of the depth-first search follows the most
+// promising cells like a beam and reaches a strong lower bound early.
+// ---------------------------------------------------------------------------
+__global__ void k_select_kept(const uint32_t* __restrict__ keepf, const uint32_t* __restrict__ keepscan,
+                              const uint32_t* __restrict__ ccnt, uint64_t nk, uint32_t* __restrict__ kcnt,
+                              uint32_t* __restrict__ kid) {
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nk && keepf[k]) {
+    kcnt[keepscan[k]] = ccnt[k];
+    kid[keepscan[k]] = (uint32_t)k;
   }
 }
 
-// per-parent cumulative kept entries (for cutting a batch into chunks)
-__global__ void k_parent_cum(const uint64_t* __restrict__ nscan, const uint64_t* __restrict__ keptn, uint32_t ncell,
-                             uint32_t nch, uint64_t* __restrict__ cum) {
-  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < ncell) cum[c] = nscan[(uint64_t)c * nch];
-  if (c == ncell - 1) cum[ncell] = nscan[(uint64_t)c * nch + nch - 1] + keptn[(uint64_t)c * nch + nch - 1];
+__global__ void k_kept_total(const uint32_t* keepf, const uint32_t* keepscan, uint64_t nk, uint64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = nk ? (uint64_t)keepscan[nk - 1] + keepf[nk - 1] : 0;
 }
 
-// emit the kept children of parents [c0, c1) as the cells of a new batch
-__global__ void k_emit_cells(LevelC lv, const Cell* __restrict__ cells, uint32_t c0, uint32_t c1,
-                             const uint32_t* __restrict__ keepf, const uint32_t* __restrict__ keepscan,
-                             const uint64_t* __restrict__ nscan, const uint32_t* __restrict__ cnent,
-                             Cell* __restrict__ out, uint32_t* __restrict__ cursor) {
+// rank_of[k] = position of child k in the sorted order; sn[r] = its entries
+__global__ void k_rank(const uint32_t* __restrict__ order, uint32_t nkept, const uint32_t* __restrict__ cnent,
+                       uint32_t* __restrict__ rank_of, uint32_t* __restrict__ sn) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nkept) {
+    const uint32_t k = order[r];
+    rank_of[k] = r;
+    sn[r] = cnent[k];
+  }
+}
+__global__ void k_soff_last(uint64_t* soff, const uint32_t* sn, uint32_t nkept) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) soff[nkept] = nkept ? soff[nkept - 1] + sn[nkept - 1] : 0;
+}
+__global__ void k_gather_u64(const uint64_t* __restrict__ a, uint64_t n, uint64_t stride, uint64_t* __restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t m = (n + stride - 1) / stride;
+  if (i < m) out[i] = a[i * stride];
+  if (i == 0) out[m] = a[n];
+}
+
+// Re-cut a pending chunk [r0, r1) against the current best: children are
+// sorted by count descending, so those that can still beat it are a prefix
+// (every child whose count is at least the best count is kept).
+__global__ void k_chunk_cut(const uint32_t* __restrict__ scount, const uint64_t* __restrict__ soff, uint32_t r0,
+                            uint32_t r1, const unsigned long long* __restrict__ best, int B, uint64_t* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint64_t bc = (uint64_t)(*best >> B);
+  uint32_t lo = r0, hi = r1;  // first r with scount[r] < bc
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if ((uint64_t)scount[mid] >= bc) lo = mid + 1;
+    else hi = mid;
+  }
+  out[0] = lo;
+  out[1] = soff[lo] - soff[r0];
+}
+
+// cells of a materialized chunk, in rank order
+__global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const uint32_t* __restrict__ order,
+                              const uint64_t* __restrict__ soff, uint32_t r0, uint32_t r1,
+                              const uint32_t* __restrict__ cnent, Cell* __restrict__ out, uint32_t* __restrict__ cursor) {
+  const uint32_t r = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= r1) return;
   const uint32_t nch = 1u << lv.abits;
-  const uint64_t k = (uint64_t)c0 * nch + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (uint64_t)c1 * nch) return;
-  cursor[k] = 0;
-  if (!keepf[k]) return;
-  const uint32_t c = (uint32_t)(k / nch), ch = (uint32_t)(k % nch);
-  const uint32_t j = keepscan[k] - keepscan[(uint64_t)c0 * nch];
+  const uint32_t k = order[r];
+  const uint32_t c = k / nch, ch = k % nch;
   const Cell P = cells[c];
   Cell o;
   const uint32_t cb = lv.cbits[ch];
   for (int a = 0; a < 4; a++) o.c[a] = lv.split[a] ? 2 * P.c[a] + (int32_t)((cb >> a) & 1u) : P.c[a];
   o.prefix = (P.prefix << lv.abits) | ch;
-  o.off = nscan[k] - nscan[(uint64_t)c0 * nch];
+  o.off = soff[r] - soff[r0];
   o.len = cnent[k];
   o.sector = P.sector;
-  out[j] = o;
+  out[r - r0] = o;
+  cursor[r - r0] = 0;
 }
 
 // ---------------------------------------------------------------------------
-// Compaction: survivors of kept children into the children's lists, each
-// canonized to its child (wavefront ballot + one atomic per child per wave).
+// Compaction of one chunk: survivors whose child's rank lies in [r0, r1) go
+// into that child's list, canonized to it (wavefront ballot, one atomic per
+// child per wave).
 // ---------------------------------------------------------------------------
-template <int FAM>
-__global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const Cell* __restrict__ cells, uint32_t c0, uint32_t c1,
-                                                     const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
-                                                     const typename EntOf<FAM>::T* __restrict__ ents,
-                                                     const uint8_t* __restrict__ masks, const uint32_t* __restrict__ keepf,
-                                                     const uint64_t* __restrict__ nscan, uint32_t* __restrict__ cursor,
-                                                     typename EntOf<FAM>::T* __restrict__ out) {
+template <int FAM, typename E, typename M, bool POSE>
+__global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restrict__ cells,
+                                                 const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
+                                                 const E* __restrict__ ents, const M* __restrict__ masks,
+                                                 const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
+                                                 const uint64_t* __restrict__ soff, uint32_t* __restrict__ cursor,
+                                                 E* __restrict__ out) {
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t nitems = *nitems_p;
-  const uint64_t base = nscan[(uint64_t)c0 * nch];
+  const uint64_t base = soff[r0];
   for (uint32_t it = wave; it < nitems; it += nwaves) {
     const Item I = items[it];
-    if (I.cell < c0 || I.cell >= c1) continue;
-    const Cell C = cells[I.cell];
-    uint32_t kmask = 0;
-    for (uint32_t ch = 0; ch < nch; ch++) kmask |= keepf[(uint64_t)I.cell * nch + ch] << ch;
-    kmask = uniform_u32(kmask);
-    if (!kmask) continue;
-    const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
-    for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
-      const uint32_t k = k0 + lane;
-      const bool valid = k < cnt;
-      const uint64_t e = C.off + I.start + k;
-      uint32_t mask = 0;
-      LinS s;
-      if (valid) {
-        mask = masks[e] & kmask;
-        s = load_lin<FAM>(ents[e]);
-      }
-#pragma unroll
-      for (int ch = 0; ch < 8; ch++) {
-        if (!((kmask >> ch) & 1u)) continue;
-        const bool p = valid && ((mask >> ch) & 1u);
-        const uint64_t bal = __ballot(p);
-        if (!bal) continue;
-        const uint64_t kk = (uint64_t)I.cell * nch + ch;
-        uint32_t b0 = 0;
-        if (lane == 0) b0 = atomicAdd(&cursor[kk], (uint32_t)__popcll(bal));
-        b0 = __shfl(b0, 0, 64);
-        if (p) {
-          const uint64_t pos = (nscan[kk] - base) + b0 + mbcnt64(bal);
-          out[pos] = store_lin<FAM>(lin_canon_child<FAM>(s, lv, lv.cbits[ch]));
-        }
-      }
+    uint32_t kmask = 0, rk[16];
+    for (uint32_t ch = 0; ch < nch; ch++) {
+      const uint32_t r = rank_of[(uint64_t)I.cell * nch + ch];
+      rk[ch] = r;
+      if (r >= r0 && r < r1) kmask |= 1u << ch;
     }
-  }
-}
-
-template <typename E>
-__global__ void __launch_bounds__(256) k_compact_pose(LevelC lv, const Cell* __restrict__ cells, uint32_t c0, uint32_t c1,
-                                                      const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
-                                                      const E* __restrict__ ents, const uint16_t* __restrict__ masks,
-                                                      const uint32_t* __restrict__ keepf, const uint64_t* __restrict__ nscan,
-                                                      uint32_t* __restrict__ cursor, E* __restrict__ out) {
-  const uint32_t nch = 1u << lv.abits;
-  const uint32_t lane = lane_id();
-  const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-  const uint32_t nitems = *nitems_p;
-  const uint64_t base = nscan[(uint64_t)c0 * nch];
-  for (uint32_t it = wave; it < nitems; it += nwaves) {
-    const Item I = items[it];
-    if (I.cell < c0 || I.cell >= c1) continue;
-    const Cell C = cells[I.cell];
-    uint32_t kmask = 0;
-    for (uint32_t ch = 0; ch < nch; ch++) kmask |= keepf[(uint64_t)I.cell * nch + ch] << ch;
     kmask = uniform_u32(kmask);
     if (!kmask) continue;
+    const Cell C = cells[I.cell];
     const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
     for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
       const uint32_t k = k0 + lane;
@@ -460,7 +451,7 @@ __global__ void __launch_bounds__(256) k_compact_pose(LevelC lv, const Cell* __r
       uint32_t mask = 0;
       E e;
       if (valid) {
-        mask = masks[ei] & kmask;
+        mask = (uint32_t)masks[ei] & kmask;
         e = ents[ei];
       }
       for (uint32_t ch = 0; ch < nch; ch++) {
@@ -468,11 +459,18 @@ __global__ void __launch_bounds__(256) k_compact_pose(LevelC lv, const Cell* __r
         const bool p = valid && ((mask >> ch) & 1u);
         const uint64_t bal = __ballot(p);
         if (!bal) continue;
-        const uint64_t kk = (uint64_t)I.cell * nch + ch;
+        const uint32_t r = uniform_u32(rk[ch]);
         uint32_t b0 = 0;
-        if (lane == 0) b0 = atomicAdd(&cursor[kk], (uint32_t)__popcll(bal));
+        if (lane == 0) b0 = atomicAdd(&cursor[r - r0], (uint32_t)__popcll(bal));
         b0 = __shfl(b0, 0, 64);
-        if (p) out[(nscan[kk] - base) + b0 + mbcnt64(bal)] = e;
+        if (p) {
+          const uint64_t pos = (soff[r] - base) + b0 + mbcnt64(bal);
+          if constexpr (POSE) {
+            out[pos] = e;
+          } else {
+            out[pos] = store_lin<FAM>(lin_canon_child<FAM>(load_lin<FAM>(e), lv, lv.cbits[ch]));
+          }
+        }
       }
     }
   }

@@ -12,9 +12,11 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -238,6 +240,66 @@ __global__ void k_write_inliers(const uint32_t* __restrict__ flag, const uint32_
 // ===========================================================================
 // Host runtime
 // ===========================================================================
+// Caching device allocator owned by a context.  All library work on a
+// context is ordered on its stream, so a block released after its last use
+// was enqueued can be handed to any later allocation on that stream without a
+// synchronization.  Sizes are rounded to 8 classes per power of two.
+struct DevCache {
+  std::multimap<size_t, void*> free_blocks;
+  std::map<void*, size_t> live;
+  uint64_t cached = 0, in_use = 0, peak = 0;
+
+  static size_t round(size_t b) {
+    if (b <= 4096) return 4096;
+    int e = 63 - __builtin_clzll((unsigned long long)b);  // 2^e <= b < 2^(e+1)
+    size_t step = (size_t)1 << (e >= 3 ? e - 3 : 0);
+    return (b + step - 1) / step * step;
+  }
+  void* get(size_t bytes, hipStream_t st, std::string& err) {
+    const size_t r = round(bytes);
+    auto it = free_blocks.lower_bound(r);
+    if (it != free_blocks.end() && it->first <= r + r / 4) {
+      void* p = it->second;
+      live[p] = it->first;
+      in_use += it->first;
+      cached -= it->first;
+      free_blocks.erase(it);
+      peak = std::max(peak, in_use);
+      return p;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim(st);
+      e = hipMalloc(&p, r);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        err = std::string("hipMalloc: ") + hipGetErrorString(e);
+        return nullptr;
+      }
+    }
+    live[p] = r;
+    in_use += r;
+    peak = std::max(peak, in_use);
+    return p;
+  }
+  void put(void* p) {
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    free_blocks.emplace(it->second, p);
+    cached += it->second;
+    in_use -= it->second;
+    live.erase(it);
+  }
+  void trim(hipStream_t st) {
+    (void)hipStreamSynchronize(st);
+    for (auto& kv : free_blocks) (void)hipFree(kv.second);
+    free_blocks.clear();
+    cached = 0;
+  }
+};
+
 struct gv_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -246,6 +308,7 @@ struct gv_ctx {
   std::mutex mu;
   std::string err;
   int n_cu = 256;
+  DevCache cache;
 };
 
 namespace {
@@ -448,7 +511,9 @@ struct Run {
   unsigned long long* dbest = nullptr;
   unsigned long long* drecheck = nullptr;
   uint64_t* dtot = nullptr;
-  uint64_t budget_entries = 0;
+  uint64_t budget_entries = 0;  // max entries of one materialized chunk
+  uint64_t first_cells = 4096;   // cells in the first chunk of every expansion
+  bool trace = false;            // GV_TRACE=1: one stderr line per expansion
   gv_stats stats{};
   double* m64 = nullptr;  // pose master
   int64_t n = 0;
@@ -456,17 +521,13 @@ struct Run {
 
 template <typename T>
 T* dalloc(Run& X, size_t count) {
-  void* p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMallocAsync(&p, count * sizeof(T), X.st);
-  if (e != hipSuccess) {
-    X.ctx->err = std::string("hipMallocAsync: ") + hipGetErrorString(e);
-    throw DevErr{GV_ENOMEM};
-  }
+  void* p = X.ctx->cache.get(count * sizeof(T), X.st, X.ctx->err);
+  if (!p) throw DevErr{GV_ENOMEM};
   return (T*)p;
 }
 void dfree(Run& X, void* p) {
-  if (p) (void)hipFreeAsync(p, X.st);
+  if (p) X.ctx->cache.put(p);
 }
 
 template <typename In, typename Out>
@@ -484,14 +545,64 @@ inline unsigned gs_grid(Run& X, uint64_t n) {
   return (unsigned)std::min<uint64_t>(nblk(n), (uint64_t)X.ctx->n_cu * 16);
 }
 
-template <int FAM> struct FamTraits {
-  using E = typename EntOf<FAM>::T;
-  using M = uint8_t;
+// Expansion state of a batch whose kept children are materialized later,
+// one chunk of the count-sorted order at a time.
+struct Parent {
+  int level = 0;
+  uint32_t ncell = 0;
+  uint64_t nent = 0;
+  Cell* cells = nullptr;
+  void* ents = nullptr;
+  bool own_ents = false;
+  void* masks = nullptr;
+  Item* items = nullptr;
+  uint32_t* nitems = nullptr;
+  uint64_t max_items = 0;
+  uint32_t nkept = 0;
+  uint32_t* order = nullptr;    // rank -> child (cell * nch + digit)
+  uint32_t* scount = nullptr;   // rank -> count (descending)
+  uint32_t* rank_of = nullptr;  // child -> rank (or ~0)
+  uint64_t* soff = nullptr;     // rank -> first entry (nkept + 1 values)
+  uint32_t* cnent = nullptr;    // child -> entries
+  int pending = 0;
 };
 
-// one expansion of a batch: count, prune (or pick for the dive), compact
+struct Task {
+  bool chunk;
+  Batch b;
+  Parent* par;
+  uint32_t r0, r1;
+};
+
+void free_parent(Run& X, Parent* pa) {
+  dfree(X, pa->cells);
+  if (pa->own_ents) dfree(X, pa->ents);
+  dfree(X, pa->masks);
+  dfree(X, pa->items);
+  dfree(X, pa->nitems);
+  dfree(X, pa->order);
+  dfree(X, pa->scount);
+  dfree(X, pa->rank_of);
+  dfree(X, pa->soff);
+  dfree(X, pa->cnent);
+  delete pa;
+}
+
+template <typename T>
+uint64_t d2h1(Run& X, const T* p) {
+  T v{};
+  HIPCHK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  return (uint64_t)v;
+}
+
+// One expansion: incidence test and per-child counts, pruning against the
+// best key (or, for the greedy dive, keeping only the best child), then the
+// kept children sorted by count.  Returns nullptr when nothing is kept (or at
+// the last level, where the leaf keys went into the best-key reduction).
+// The batch's cells/entries are handed over to the Parent (or freed).
 template <int FAM, typename E, typename M>
-void expand(Run& X, Batch& b, bool dive, std::vector<Batch>& out) {
+Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   const ProbC& P = X.S.P;
   const int m = b.level;
   const LevelC lv = P.lev[m];
@@ -501,138 +612,180 @@ void expand(Run& X, Batch& b, bool dive, std::vector<Batch>& out) {
   X.stats.tests += b.nent * nch;
   X.stats.cells_expanded += b.ncell;
 
-  // work items
+  Parent* pa = new Parent();
+  pa->level = m;
+  pa->ncell = b.ncell;
+  pa->nent = b.nent;
+  pa->cells = b.cells;
+  pa->ents = b.ents;
+  pa->own_ents = own_ents;
+
+  // work items: at most GV_ITEM entries of one cell each
   uint32_t* nitem = dalloc<uint32_t>(X, b.ncell);
   uint32_t* ioff = dalloc<uint32_t>(X, b.ncell);
-  const uint64_t max_items = b.ncell + b.nent / GV_ITEM + 1;
-  Item* items = dalloc<Item>(X, max_items);
-  uint32_t* nitems = dalloc<uint32_t>(X, 1);
-  HIPCHK(hipMemsetAsync(nitems, 0, sizeof(uint32_t), X.st));
+  pa->max_items = b.ncell + b.nent / GV_ITEM + 1;
+  pa->items = dalloc<Item>(X, pa->max_items);
+  pa->nitems = dalloc<uint32_t>(X, 1);
+  HIPCHK(hipMemsetAsync(pa->nitems, 0, sizeof(uint32_t), X.st));
   k_item_counts<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem);
   excl_scan(X, nitem, ioff, b.ncell);
-  k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, ioff, items, nitems);
+  k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, ioff, pa->items, pa->nitems);
   dfree(X, nitem);
   dfree(X, ioff);
 
-  M* masks = dalloc<M>(X, b.nent);
+  pa->masks = dalloc<M>(X, b.nent);
   uint32_t* ccnt = dalloc<uint32_t>(X, nk);
-  uint32_t* cnent = dalloc<uint32_t>(X, nk);
+  pa->cnent = dalloc<uint32_t>(X, nk);
   HIPCHK(hipMemsetAsync(ccnt, 0, nk * sizeof(uint32_t), X.st));
-  HIPCHK(hipMemsetAsync(cnent, 0, nk * sizeof(uint32_t), X.st));
-  const unsigned grid = (unsigned)std::min<uint64_t>((max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
+  HIPCHK(hipMemsetAsync(pa->cnent, 0, nk * sizeof(uint32_t), X.st));
+  const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
   if constexpr (FAM == FAM_POSE4DOF) {
-    k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, items, nitems, (const E*)b.ents, X.m64,
-                                             (uint64_t)X.n, (uint16_t*)masks, ccnt, cnent, X.drecheck);
+    k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, X.m64,
+                                             (uint64_t)X.n, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck);
   } else {
-    k_count_lin<FAM><<<grid, 256, 0, X.st>>>(lv, b.cells, items, nitems, (const E*)b.ents, (uint8_t*)masks, ccnt,
-                                              cnent);
+    k_count_lin<FAM><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
+                                              (uint8_t*)pa->masks, ccnt, pa->cnent);
   }
   HIPCHK(hipGetLastError());
 
   uint32_t* keepf = dalloc<uint32_t>(X, nk);
   uint64_t* keptn = dalloc<uint64_t>(X, nk);
   if (dive) {
-    k_pick_best<<<1, 64, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, ccnt, cnent, X.dbest, keepf, keptn);
+    k_pick_best<<<1, 64, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, ccnt, pa->cnent, X.dbest, keepf, keptn);
   } else {
-    k_prune<<<nblk(nk), 256, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, b.ncell, ccnt, cnent, X.dbest,
-                                        keepf, keptn);
+    k_prune<<<nblk(nk), 256, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, b.ncell, ccnt, pa->cnent,
+                                        X.dbest, keepf, keptn);
   }
   HIPCHK(hipGetLastError());
-  dfree(X, ccnt);
+  dfree(X, keptn);
   if (leaf) {
     dfree(X, keepf);
-    dfree(X, keptn);
-    dfree(X, cnent);
-    dfree(X, masks);
-    dfree(X, items);
-    dfree(X, nitems);
-    return;
+    dfree(X, ccnt);
+    pa->pending = 0;
+    free_parent(X, pa);
+    return nullptr;
   }
   uint32_t* keepscan = dalloc<uint32_t>(X, nk);
-  uint64_t* nscan = dalloc<uint64_t>(X, nk);
   excl_scan(X, keepf, keepscan, nk);
-  excl_scan(X, keptn, nscan, nk);
-  k_totals<<<1, 64, 0, X.st>>>(keepf, keepscan, keptn, nscan, nk, X.dtot);
-  uint64_t tot[2];
-  HIPCHK(hipMemcpyAsync(tot, X.dtot, sizeof(tot), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
-  const uint64_t nkept = tot[0], nentk = tot[1];
+  k_kept_total<<<1, 64, 0, X.st>>>(keepf, keepscan, nk, X.dtot);
+  const uint64_t nkept = d2h1(X, X.dtot);
   X.stats.cells_pruned += nk - nkept;
-  if (nkept > 0) {
-    // cut into chunks of whole parents whose children hold <= budget entries
-    std::vector<std::pair<uint32_t, uint32_t>> chunks;
-    std::vector<uint64_t> cumE, cumC;
-    if (nentk <= X.budget_entries || b.ncell == 1) {
-      chunks.push_back({0u, b.ncell});
-    } else {
-      uint64_t* cum = dalloc<uint64_t>(X, b.ncell + 1);
-      k_parent_cum<<<nblk(b.ncell), 256, 0, X.st>>>(nscan, keptn, b.ncell, nch, cum);
-      cumE.resize(b.ncell + 1);
-      HIPCHK(hipMemcpyAsync(cumE.data(), cum, (b.ncell + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
-      HIPCHK(hipStreamSynchronize(X.st));
-      dfree(X, cum);
-      uint32_t c0 = 0;
-      while (c0 < b.ncell) {
-        uint32_t c1 = c0 + 1;
-        while (c1 < b.ncell && cumE[c1 + 1] - cumE[c0] <= X.budget_entries) c1++;
-        chunks.push_back({c0, c1});
-        c0 = c1;
-      }
-    }
-    // kept children per chunk (from keepscan at chunk boundaries)
-    std::vector<uint32_t> kb(chunks.size() + 1);
-    std::vector<uint64_t> eb(chunks.size() + 1);
-    {
-      std::vector<uint64_t> idx;
-      for (auto& c : chunks) idx.push_back((uint64_t)c.first * nch);
-      for (size_t i = 0; i < chunks.size(); i++) {
-        uint32_t v;
-        uint64_t w;
-        HIPCHK(hipMemcpyAsync(&v, keepscan + idx[i], sizeof(v), hipMemcpyDeviceToHost, X.st));
-        HIPCHK(hipMemcpyAsync(&w, nscan + idx[i], sizeof(w), hipMemcpyDeviceToHost, X.st));
-        HIPCHK(hipStreamSynchronize(X.st));
-        kb[i] = v;
-        eb[i] = w;
-      }
-      kb[chunks.size()] = (uint32_t)nkept;
-      eb[chunks.size()] = nentk;
-    }
-    uint32_t* cursor = dalloc<uint32_t>(X, nk);
-    const unsigned cgrid = grid;
-    std::vector<Batch> made;
-    for (size_t i = 0; i < chunks.size(); i++) {
-      Batch nb;
-      nb.level = m + 1;
-      nb.ncell = kb[i + 1] - kb[i];
-      nb.nent = eb[i + 1] - eb[i];
-      if (nb.ncell == 0) continue;
-      nb.cells = dalloc<Cell>(X, nb.ncell);
-      nb.ents = dalloc<E>(X, nb.nent);
-      const uint32_t c0 = chunks[i].first, c1 = chunks[i].second;
-      const uint64_t nkc = (uint64_t)(c1 - c0) * nch;
-      k_emit_cells<<<nblk(nkc), 256, 0, X.st>>>(lv, b.cells, c0, c1, keepf, keepscan, nscan, cnent, nb.cells, cursor);
-      if constexpr (FAM == FAM_POSE4DOF) {
-        k_compact_pose<E><<<cgrid, 256, 0, X.st>>>(lv, b.cells, c0, c1, items, nitems, (const E*)b.ents,
-                                                    (const uint16_t*)masks, keepf, nscan, cursor, (E*)nb.ents);
-      } else {
-        k_compact_lin<FAM><<<cgrid, 256, 0, X.st>>>(lv, b.cells, c0, c1, items, nitems, (const E*)b.ents,
-                                                      (const uint8_t*)masks, keepf, nscan, cursor, (E*)nb.ents);
-      }
-      HIPCHK(hipGetLastError());
-      made.push_back(nb);
-    }
-    dfree(X, cursor);
-    // depth-first: the first chunk is expanded next
-    for (auto it = made.rbegin(); it != made.rend(); ++it) out.push_back(*it);
+  if (X.trace) {
+    const uint64_t bst = d2h1(X, X.dbest);
+    std::fprintf(stderr, "gv: level %d cells %u entries %llu kept %llu best %llu%s\n", m, b.ncell,
+                 (unsigned long long)b.nent, (unsigned long long)nkept, (unsigned long long)(bst >> P.B),
+                 dive ? " (dive)" : "");
   }
+  if (nkept == 0) {
+    dfree(X, keepf);
+    dfree(X, keepscan);
+    dfree(X, ccnt);
+    free_parent(X, pa);
+    return nullptr;
+  }
+  pa->nkept = (uint32_t)nkept;
+  uint32_t* kcnt = dalloc<uint32_t>(X, nkept);
+  uint32_t* kid = dalloc<uint32_t>(X, nkept);
+  k_select_kept<<<nblk(nk), 256, 0, X.st>>>(keepf, keepscan, ccnt, nk, kcnt, kid);
   dfree(X, keepf);
-  dfree(X, keptn);
   dfree(X, keepscan);
-  dfree(X, nscan);
-  dfree(X, cnent);
-  dfree(X, masks);
-  dfree(X, items);
-  dfree(X, nitems);
+  dfree(X, ccnt);
+  pa->scount = dalloc<uint32_t>(X, nkept);
+  pa->order = dalloc<uint32_t>(X, nkept);
+  {
+    size_t tb = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, kcnt, pa->scount, kid, pa->order, (int)nkept, 0,
+                                                         32, X.st));
+    void* tmp = dalloc<char>(X, tb);
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, kcnt, pa->scount, kid, pa->order, (int)nkept, 0, 32,
+                                                         X.st));
+    dfree(X, tmp);
+  }
+  dfree(X, kcnt);
+  dfree(X, kid);
+  pa->rank_of = dalloc<uint32_t>(X, nk);
+  HIPCHK(hipMemsetAsync(pa->rank_of, 0xff, nk * sizeof(uint32_t), X.st));
+  uint32_t* sn = dalloc<uint32_t>(X, nkept);
+  k_rank<<<nblk(nkept), 256, 0, X.st>>>(pa->order, (uint32_t)nkept, pa->cnent, pa->rank_of, sn);
+  pa->soff = dalloc<uint64_t>(X, nkept + 1);
+  excl_scan(X, sn, pa->soff, nkept);
+  k_soff_last<<<1, 64, 0, X.st>>>(pa->soff, sn, (uint32_t)nkept);
+  dfree(X, sn);
+  return pa;
+}
+
+// Chunk schedule over the sorted children: chunk j holds at most
+// first_cells * 4^j cells and at most budget entries, so the first descent
+// follows a narrow beam of the highest-count cells.
+void plan_chunks(Run& X, Parent* pa, std::vector<std::pair<uint32_t, uint32_t>>& chunks) {
+  const uint32_t nk = pa->nkept;
+  const uint64_t stride = std::max<uint64_t>(1, (nk + (1u << 20) - 1) >> 20);
+  const uint64_t ns = (nk + stride - 1) / stride;  // samples soff[i*stride], plus soff[nk]
+  uint64_t* d = dalloc<uint64_t>(X, ns + 1);
+  k_gather_u64<<<nblk(ns + 1), 256, 0, X.st>>>(pa->soff, nk, stride, d);
+  std::vector<uint64_t> s(ns + 1);
+  HIPCHK(hipMemcpyAsync(s.data(), d, (ns + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  dfree(X, d);
+  auto at = [&](uint64_t i) { return i >= ns ? s[ns] : s[i]; };  // sample i -> soff[min(i*stride, nk)]
+  auto rk = [&](uint64_t i) { return (uint32_t)std::min<uint64_t>(i * stride, nk); };
+  uint64_t i0 = 0, cap = X.first_cells;
+  while (rk(i0) < nk) {
+    uint64_t i1 = i0 + 1;
+    while (i1 < ns && (rk(i1 + 1) - rk(i0)) <= cap && at(i1 + 1) - at(i0) <= X.budget_entries) i1++;
+    chunks.push_back({rk(i0), rk(i1)});
+    i0 = i1;
+    cap = std::min<uint64_t>(cap * 4, 1ull << 30);
+  }
+}
+
+// Materialize one chunk [r0, r1) of a parent as a new batch (after cutting it
+// against the current best).  Returns false when nothing remains.
+template <int FAM, typename E, typename M>
+bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
+  const ProbC& P = X.S.P;
+  const LevelC lv = P.lev[pa->level];
+  k_chunk_cut<<<1, 64, 0, X.st>>>(pa->scount, pa->soff, r0, r1, X.dbest, P.B, X.dtot);
+  uint64_t cut[2];
+  HIPCHK(hipMemcpyAsync(cut, X.dtot, sizeof(cut), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  const uint32_t rc = (uint32_t)cut[0];
+  bool made = false;
+  X.stats.cells_pruned += r1 - rc;
+  if (rc > r0) {
+    nb.level = pa->level + 1;
+    nb.ncell = rc - r0;
+    nb.nent = cut[1];
+    nb.cells = dalloc<Cell>(X, nb.ncell);
+    nb.ents = dalloc<E>(X, nb.nent);
+    uint32_t* cursor = dalloc<uint32_t>(X, nb.ncell);
+    k_emit_ranked<<<nblk(nb.ncell), 256, 0, X.st>>>(lv, pa->cells, pa->order, pa->soff, r0, rc, pa->cnent, nb.cells,
+                                                   cursor);
+    const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
+    k_compact<FAM, E, M, FAM == FAM_POSE4DOF><<<grid, 256, 0, X.st>>>(
+        lv, pa->cells, pa->items, pa->nitems, (const E*)pa->ents, (const M*)pa->masks, pa->rank_of, r0, rc, pa->soff,
+        cursor, (E*)nb.ents);
+    HIPCHK(hipGetLastError());
+    dfree(X, cursor);
+    made = true;
+  }
+  if (--pa->pending == 0) free_parent(X, pa);
+  return made;
+}
+
+template <int FAM, typename E, typename M>
+void push_children(Run& X, Parent* pa, std::vector<Task>& stack) {
+  std::vector<std::pair<uint32_t, uint32_t>> chunks;
+  plan_chunks(X, pa, chunks);
+  pa->pending = (int)chunks.size();
+  for (auto it = chunks.rbegin(); it != chunks.rend(); ++it) {
+    Task t{};
+    t.chunk = true;
+    t.par = pa;
+    t.r0 = it->first;
+    t.r1 = it->second;
+    stack.push_back(t);
+  }
 }
 
 template <int FAM, typename E, typename M>
@@ -650,19 +803,19 @@ void search(Run& X, E* root, int64_t n) {
     b.ents = root;
     bool own = false;
     while (true) {
-      std::vector<Batch> nxt;
-      expand<FAM, E, M>(X, b, true, nxt);
-      dfree(X, b.cells);
-      if (own) dfree(X, b.ents);
-      if (nxt.empty()) break;
-      b = nxt[0];
+      Parent* pa = expand<FAM, E, M>(X, b, own, true);
+      if (!pa) break;
+      pa->pending = 1;
+      if (!materialize<FAM, E, M>(X, pa, 0, pa->nkept, b)) break;
       own = true;
     }
   }
-  // depth-first over batches
-  std::vector<Batch> stack;
+  // depth-first over batches; children of a batch in count order
+  std::vector<Task> stack;
   {
-    Batch r;
+    Task t{};
+    t.chunk = false;
+    Batch& r = t.b;
     r.level = 0;
     r.ncell = (uint32_t)nsec;
     r.nent = (uint64_t)n * nsec;
@@ -675,18 +828,22 @@ void search(Run& X, E* root, int64_t n) {
       k_replicate<E><<<gs_grid(X, (uint64_t)n * nsec), 256, 0, X.st>>>(root, n, nsec, rep);
       r.ents = rep;
     }
-    stack.push_back(r);
+    stack.push_back(t);
   }
   bool first = true;
   while (!stack.empty()) {
-    Batch b = stack.back();
+    Task t = stack.back();
     stack.pop_back();
-    std::vector<Batch> kids;
-    expand<FAM, E, M>(X, b, false, kids);
-    dfree(X, b.cells);
-    if (!(first && nsec == 1)) dfree(X, b.ents);
+    Batch b;
+    if (t.chunk) {
+      if (!materialize<FAM, E, M>(X, t.par, t.r0, t.r1, b)) continue;
+    } else {
+      b = t.b;
+    }
+    const bool own = !(first && nsec == 1);
     first = false;
-    for (auto& k : kids) stack.push_back(k);
+    Parent* pa = expand<FAM, E, M>(X, b, own, false);
+    if (pa) push_children<FAM, E, M>(X, pa, stack);
   }
 }
 
@@ -801,6 +958,8 @@ gv_status solve_impl(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
   X.ctx = ctx;
   X.st = ctx->stream;
   X.n = p->n;
+  X.trace = std::getenv("GV_TRACE") != nullptr;
+  if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
   std::string why;
   gv_status st = setup_axes(p, X.S, why);
   if (st != GV_OK) {
@@ -811,8 +970,8 @@ gv_status solve_impl(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
   std::vector<void*> owned;
   try {
     HIPCHK(hipSetDevice(ctx->device));
-    // entries budget: a quarter of the memory budget per batch
-    X.budget_entries = std::max<uint64_t>(1ull << 20, ctx->budget / 4 / 48);
+    // one chunk per level can be alive along the depth-first path
+    X.budget_entries = std::max<uint64_t>(1ull << 22, ctx->budget / (uint64_t)(P.Lstar + 2) / 64);
     X.dP = dalloc<ProbC>(X, 1);
     X.dbest = dalloc<unsigned long long>(X, 1);
     X.drecheck = dalloc<unsigned long long>(X, 1);
@@ -988,12 +1147,6 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
   size_t fr = 0, tot = 0;
   (void)hipMemGetInfo(&fr, &tot);
   c->budget = (cfg && cfg->mem_budget_bytes) ? cfg->mem_budget_bytes : (uint64_t)(0.6 * (double)fr);
-  // keep freed blocks in the stream-ordered pool
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
   *out = c;
   return GV_OK;
 }
@@ -1002,6 +1155,9 @@ gv_status gv_destroy(gv_ctx* ctx) {
   if (!ctx) return GV_EINVAL;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  ctx->cache.trim(ctx->stream);
+  for (auto& kv : ctx->cache.live) (void)hipFree(kv.first);
+  ctx->cache.live.clear();
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return GV_OK;
