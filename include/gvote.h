@@ -76,6 +76,9 @@ typedef struct {
   uint64_t mem_budget_bytes;  /* 0: 60% of the device's free memory */
   void *hip_stream;           /* optional hipStream_t to run on; NULL: own stream */
   const char *autotune_cache; /* optional path of the tile autotuner cache */
+  int kernel_timing;          /* 1: time the incidence and compaction kernels
+                                 with HIP events on the solve stream (adds
+                                 one event pair per launch) */
 } gv_ctx_config;
 
 typedef struct {
@@ -98,6 +101,12 @@ typedef struct {
   uint64_t cells_expanded, cells_pruned, groups_merged;
   uint32_t levels;            /* L*: depth of the leaves */
   double ms_total, ms_kernels;
+  /* with kernel_timing: summed event time, launches and algorithmic bytes
+   * (entries read + masks written) of the incidence-test kernel, and the
+   * same for the compaction kernel (entries + masks read, children written) */
+  double test_ms, compact_ms;
+  uint64_t test_launches, compact_launches;
+  uint64_t test_bytes, compact_bytes;
 } gv_stats;
 
 typedef struct {

@@ -309,6 +309,8 @@ struct gv_ctx {
   std::string err;
   int n_cu = 256;
   DevCache cache;
+  bool kernel_timing = false;
+  std::vector<hipEvent_t> ev_pool;
 };
 
 namespace {
@@ -512,8 +514,11 @@ struct Run {
   unsigned long long* drecheck = nullptr;
   uint64_t* dtot = nullptr;
   uint64_t budget_entries = 0;  // max entries of one materialized chunk
-  uint64_t first_cells = 4096;   // cells in the first chunk of every expansion
+  uint64_t first_cells = 65536;  // cells in the first chunk of every expansion
   bool trace = false;            // GV_TRACE=1: one stderr line per expansion
+  // kernel timing: (start, stop, kind 0 test / 1 compact)
+  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
+  size_t ev_used = 0;
   gv_stats stats{};
   double* m64 = nullptr;  // pose master
   int64_t n = 0;
@@ -596,6 +601,26 @@ uint64_t d2h1(Run& X, const T* p) {
   return (uint64_t)v;
 }
 
+std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind) {
+  gv_ctx* c = X.ctx;
+  std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
+  if (!c->kernel_timing) return p;
+  while (c->ev_pool.size() < 2 * (X.ev_used + 1)) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  p.first = c->ev_pool[2 * X.ev_used];
+  p.second = c->ev_pool[2 * X.ev_used + 1];
+  X.ev_used++;
+  HIPCHK(hipEventRecord(p.first, X.st));
+  X.ev.push_back({p, kind});
+  return p;
+}
+void ev_end(Run& X, std::pair<hipEvent_t, hipEvent_t> p) {
+  if (p.second) HIPCHK(hipEventRecord(p.second, X.st));
+}
+
 // One expansion: incidence test and per-child counts, pruning against the
 // best key (or, for the greedy dive, keeping only the best child), then the
 // kept children sorted by count.  Returns nullptr when nothing is kept (or at
@@ -639,6 +664,9 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   HIPCHK(hipMemsetAsync(ccnt, 0, nk * sizeof(uint32_t), X.st));
   HIPCHK(hipMemsetAsync(pa->cnent, 0, nk * sizeof(uint32_t), X.st));
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
+  auto evp = ev_begin(X, 0);
+  X.stats.test_launches++;
+  X.stats.test_bytes += b.nent * (sizeof(E) + sizeof(M));
   if constexpr (FAM == FAM_POSE4DOF) {
     k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, X.m64,
                                              (uint64_t)X.n, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck);
@@ -646,6 +674,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     k_count_lin<FAM><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
                                               (uint8_t*)pa->masks, ccnt, pa->cnent);
   }
+  ev_end(X, evp);
   HIPCHK(hipGetLastError());
 
   uint32_t* keepf = dalloc<uint32_t>(X, nk);
@@ -762,9 +791,13 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     k_emit_ranked<<<nblk(nb.ncell), 256, 0, X.st>>>(lv, pa->cells, pa->order, pa->soff, r0, rc, pa->cnent, nb.cells,
                                                    cursor);
     const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
+    auto evp = ev_begin(X, 1);
+    X.stats.compact_launches++;
+    X.stats.compact_bytes += pa->nent * (sizeof(E) + sizeof(M)) + nb.nent * sizeof(E);
     k_compact<FAM, E, M, FAM == FAM_POSE4DOF><<<grid, 256, 0, X.st>>>(
         lv, pa->cells, pa->items, pa->nitems, (const E*)pa->ents, (const M*)pa->masks, pa->rank_of, r0, rc, pa->soff,
         cursor, (E*)nb.ents);
+    ev_end(X, evp);
     HIPCHK(hipGetLastError());
     dfree(X, cursor);
     made = true;
@@ -1081,6 +1114,11 @@ gv_status solve_impl(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
     HIPCHK(hipStreamSynchronize(X.st));
     X.stats.fp64_rechecks = rech;
     X.stats.levels = (uint32_t)P.Lstar;
+    for (auto& e : X.ev) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e.first.first, e.first.second));
+      (e.second == 0 ? X.stats.test_ms : X.stats.compact_ms) += (double)ms;
+    }
     double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     X.stats.ms_total = ms;
     X.stats.ms_kernels = ms;
@@ -1129,6 +1167,7 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
   gv_ctx* c = new (std::nothrow) gv_ctx();
   if (!c) return GV_ENOMEM;
   c->device = cfg ? cfg->device : 0;
+  c->kernel_timing = cfg && cfg->kernel_timing;
   if (hipSetDevice(c->device) != hipSuccess) {
     delete c;
     return GV_EDEVICE;
@@ -1156,6 +1195,7 @@ gv_status gv_destroy(gv_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   ctx->cache.trim(ctx->stream);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (auto& kv : ctx->cache.live) (void)hipFree(kv.first);
   ctx->cache.live.clear();
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);

@@ -29,7 +29,8 @@ EXPORTS = ["gv_create", "gv_destroy", "gv_solve", "gv_parametrize", "gv_submit",
 
 class CtxConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("mem_budget_bytes", ctypes.c_uint64),
-                ("hip_stream", ctypes.c_void_p), ("autotune_cache", ctypes.c_char_p)]
+                ("hip_stream", ctypes.c_void_p), ("autotune_cache", ctypes.c_char_p),
+                ("kernel_timing", ctypes.c_int)]
 
 
 class Problem(ctypes.Structure):
@@ -42,7 +43,10 @@ class Stats(ctypes.Structure):
     _fields_ = [("tests", ctypes.c_uint64), ("fp64_rechecks", ctypes.c_uint64),
                 ("cells_expanded", ctypes.c_uint64), ("cells_pruned", ctypes.c_uint64),
                 ("groups_merged", ctypes.c_uint64), ("levels", ctypes.c_uint32),
-                ("ms_total", ctypes.c_double), ("ms_kernels", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_kernels", ctypes.c_double),
+                ("test_ms", ctypes.c_double), ("compact_ms", ctypes.c_double),
+                ("test_launches", ctypes.c_uint64), ("compact_launches", ctypes.c_uint64),
+                ("test_bytes", ctypes.c_uint64), ("compact_bytes", ctypes.c_uint64)]
 
 
 class Result(ctypes.Structure):
@@ -123,13 +127,14 @@ def make_problem(family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER):
 
 
 class Context:
-    def __init__(self, device=0, mem_budget_bytes=0, hip_stream=None):
+    def __init__(self, device=0, mem_budget_bytes=0, hip_stream=None, kernel_timing=False):
         self._h = ctypes.c_void_p()
         cfg = CtxConfig()
         cfg.device = device
         cfg.mem_budget_bytes = mem_budget_bytes
         cfg.hip_stream = hip_stream
         cfg.autotune_cache = None
+        cfg.kernel_timing = 1 if kernel_timing else 0
         st = lib().gv_create(ctypes.byref(self._h), ctypes.byref(cfg))
         if st != 0:
             raise GvError(st, "gv_create")
@@ -165,7 +170,10 @@ class Context:
             "inliers": buf[: r.n_inliers].copy(), "bound": list(r.bound),
             "stats": {"tests": s.tests, "fp64_rechecks": s.fp64_rechecks, "cells_expanded": s.cells_expanded,
                       "cells_pruned": s.cells_pruned, "groups_merged": s.groups_merged, "levels": s.levels,
-                      "ms_total": s.ms_total, "ms_kernels": s.ms_kernels},
+                      "ms_total": s.ms_total, "ms_kernels": s.ms_kernels,
+                      "test_ms": s.test_ms, "compact_ms": s.compact_ms, "test_launches": s.test_launches,
+                      "compact_launches": s.compact_launches, "test_bytes": s.test_bytes,
+                      "compact_bytes": s.compact_bytes},
         }
 
     def parametrize(self, family, cols, lo, hi, eps):
