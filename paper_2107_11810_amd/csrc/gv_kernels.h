@@ -47,13 +47,49 @@ __global__ void k_item_fill(const Cell* __restrict__ cells, uint32_t ncell, cons
 // Linear families: incidence test of every (canonical surface, child) pair,
 // pass masks, weighted and unweighted per-child counts.
 // ---------------------------------------------------------------------------
-template <int FAM>
+// PLANE3D with all three axes splitting: the per-axis ranges K*{b, b+1} of
+// the two slopes are shared by the 8 children (digit = b_a1 b_a2 b_a0).
+__device__ inline uint32_t plane_mask_all(const LinS& s, const LevelC& lv) {
+  const int32_t K1 = s.K[0][0], K2 = s.K[0][1], F2 = 2 * s.F[0];
+  const int32_t a1 = imin32(K1, 0), c1 = imax32(K1, 0);
+  const int32_t a2 = imin32(K2, 0), c2 = imax32(K2, 0);
+  const int32_t H = lv.H[2], pad = lv.padu[2];
+  const int32_t lo0 = -pad, hi0 = H + pad, lo1 = H - pad, hi1 = 2 * H + pad;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int b1 = 0; b1 < 2; b1++) {
+#pragma unroll
+    for (int b2 = 0; b2 < 2; b2++) {
+      const int32_t gmin = F2 + (b1 ? K1 + a1 : a1) + (b2 ? K2 + a2 : a2);
+      const int32_t gmax = F2 + (b1 ? K1 + c1 : c1) + (b2 ? K2 + c2 : c2);
+      const int d = (b1 << 2) | (b2 << 1);
+      mask |= (uint32_t)(gmax >= lo0 && gmin <= hi0) << d;
+      mask |= (uint32_t)(gmax >= lo1 && gmin <= hi1) << (d | 1);
+    }
+  }
+  return mask;
+}
+
+template <int FAM> __device__ inline uint32_t lin_mask(const LinS& s, const LevelC& lv, uint32_t nch) {
+  if constexpr (FAM == FAM_PLANE3D) {
+    if (lv.abits == 3) return plane_mask_all(s, lv);
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int ch = 0; ch < 8; ch++)
+    if ((uint32_t)ch < nch && lin_meets<FAM>(s, lv, lv.cbits[ch])) mask |= 1u << ch;
+  return mask;
+}
+
+// UNIT: every multiplicity is 1 (no merged surfaces), so a child's count is
+// the popcount of the wave's ballot, accumulated in scalar registers.
+template <int FAM, bool UNIT>
 __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Cell* __restrict__ cells,
                                                    const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
                                                    const typename EntOf<FAM>::T* __restrict__ ents,
                                                    uint8_t* __restrict__ masks, uint32_t* __restrict__ ccnt,
-                                                   uint32_t* __restrict__ cnent) {
-  using E = typename EntOf<FAM>::T;
+                                                   uint32_t* __restrict__ cnent, uint32_t* __restrict__ itemcnt,
+                                                   uint32_t istride) {
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -66,28 +102,49 @@ __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Cell* __rest
     uint32_t aw[8], an[8];
 #pragma unroll
     for (int ch = 0; ch < 8; ch++) { aw[ch] = 0; an[ch] = 0; }
-    for (uint32_t k = lane; k < cnt; k += 64) {
-      const uint64_t e = C.off + I.start + k;
-      const LinS s = load_lin<FAM>(ents[e]);
-      uint32_t mask = 0;
+    // four entries per lane in flight
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 256) {
+      typename EntOf<FAM>::T ev[4];
 #pragma unroll
-      for (int ch = 0; ch < 8; ch++) {
-        if ((uint32_t)ch < nch && lin_meets<FAM>(s, lv, lv.cbits[ch])) {
-          mask |= 1u << ch;
-          aw[ch] += (uint32_t)s.w;
-          an[ch] += 1u;
+      for (int j = 0; j < 4; j++) {
+        const uint32_t k = k0 + 64 * j + lane;
+        if (k < cnt) ev[j] = ents[C.off + I.start + k];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const uint32_t k = k0 + 64 * j + lane;
+        const bool valid = k < cnt;
+        const LinS s = load_lin<FAM>(ev[j]);
+        const uint32_t mask = valid ? lin_mask<FAM>(s, lv, nch) : 0u;
+        if (valid) masks[C.off + I.start + k] = (uint8_t)mask;
+#pragma unroll
+        for (int ch = 0; ch < 8; ch++) {
+          if ((uint32_t)ch >= nch) break;
+          if constexpr (UNIT) {
+            an[ch] += (uint32_t)__popcll(__ballot((mask >> ch) & 1u));
+          } else {
+            const uint32_t p = (mask >> ch) & 1u;
+            aw[ch] += p ? (uint32_t)s.w : 0u;
+            an[ch] += p;
+          }
         }
       }
-      masks[e] = (uint8_t)mask;
     }
 #pragma unroll
     for (int ch = 0; ch < 8; ch++) {
-      if ((uint32_t)ch < nch) {
-        uint32_t w = wave_sum_u32(aw[ch]), n = wave_sum_u32(an[ch]);
-        if (lane == 0 && n) {
-          atomicAdd(&ccnt[I.cell * nch + ch], w);
-          atomicAdd(&cnent[I.cell * nch + ch], n);
-        }
+      if ((uint32_t)ch >= nch) break;
+      uint32_t w, n;
+      if constexpr (UNIT) {
+        n = an[ch];
+        w = n;
+      } else {
+        w = wave_sum_u32(aw[ch]);
+        n = wave_sum_u32(an[ch]);
+      }
+      if (lane == 0 && n) {
+        atomicAdd(&ccnt[I.cell * nch + ch], w);
+        atomicAdd(&cnent[I.cell * nch + ch], n);
+        if (istride) itemcnt[(uint64_t)ch * istride + it] = n;
       }
     }
   }
@@ -228,7 +285,8 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pp
                                                     const double* __restrict__ m64, uint64_t n_root,
                                                     uint16_t* __restrict__ masks, uint32_t* __restrict__ ccnt,
                                                     uint32_t* __restrict__ cnent,
-                                                    unsigned long long* __restrict__ rechecks) {
+                                                    unsigned long long* __restrict__ rechecks,
+                                                    uint32_t* __restrict__ itemcnt, uint32_t istride) {
   const ProbC& P = *Pp;
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
@@ -275,6 +333,7 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pp
         if (lane == 0 && n) {
           atomicAdd(&ccnt[I.cell * nch + ch], w);
           atomicAdd(&cnent[I.cell * nch + ch], n);
+          if (istride) itemcnt[(uint64_t)ch * istride + it] = n;
         }
       }
     }
@@ -380,10 +439,11 @@ __global__ void k_gather_u64(const uint64_t* __restrict__ a, uint64_t n, uint64_
 // sorted by count descending, so those that can still beat it are a prefix
 // (every child whose count is at least the best count is kept).
 __global__ void k_chunk_cut(const uint32_t* __restrict__ scount, const uint64_t* __restrict__ soff, uint32_t r0,
-                            uint32_t r1, const unsigned long long* __restrict__ best, int B, uint64_t* out) {
+                            uint32_t r1, const unsigned long long* __restrict__ best, int B, int sorted,
+                            uint64_t* out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const uint64_t bc = (uint64_t)(*best >> B);
-  uint32_t lo = r0, hi = r1;  // first r with scount[r] < bc
+  uint32_t lo = sorted ? r0 : r1, hi = r1;  // first r with scount[r] < bc
   while (lo < hi) {
     const uint32_t mid = lo + (hi - lo) / 2;
     if ((uint64_t)scount[mid] >= bc) lo = mid + 1;
@@ -393,10 +453,29 @@ __global__ void k_chunk_cut(const uint32_t* __restrict__ scount, const uint64_t*
   out[1] = soff[lo] - soff[r0];
 }
 
+// entries of the parent cells that have a child in [r0, r1): what one
+// compaction pass must read
+__global__ void k_chunk_reads(const Cell* __restrict__ cells, uint32_t ncell, uint32_t nch,
+                              const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
+                              unsigned long long* __restrict__ acc) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t v = 0;
+  if (c < ncell) {
+    bool hit = false;
+    for (uint32_t ch = 0; ch < nch; ch++) {
+      const uint32_t r = rank_of[(uint64_t)c * nch + ch];
+      hit = hit || (r >= r0 && r < r1);
+    }
+    v = hit ? cells[c].len : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63u) == 0 && v) atomicAdd(acc, (unsigned long long)v);
+}
+
 // cells of a materialized chunk, in rank order
 __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const uint32_t* __restrict__ order,
                               const uint64_t* __restrict__ soff, uint32_t r0, uint32_t r1,
-                              const uint32_t* __restrict__ cnent, Cell* __restrict__ out, uint32_t* __restrict__ cursor) {
+                              const uint32_t* __restrict__ cnent, Cell* __restrict__ out) {
   const uint32_t r = r0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= r1) return;
   const uint32_t nch = 1u << lv.abits;
@@ -411,20 +490,22 @@ __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const u
   o.len = cnent[k];
   o.sector = P.sector;
   out[r - r0] = o;
-  cursor[r - r0] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // Compaction of one chunk: survivors whose child's rank lies in [r0, r1) go
-// into that child's list, canonized to it (wavefront ballot, one atomic per
-// child per wave).
+// into that child's list, canonized to it.  Write positions are known in
+// advance: the count pass recorded every item's per-child survivors, and
+// their exclusive scan (itemoff, child-major) gives each item's offset inside
+// the child's list; within an item, a wavefront ballot ranks the lanes.
 // ---------------------------------------------------------------------------
 template <int FAM, typename E, typename M, bool POSE>
 __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restrict__ cells,
                                                  const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
-                                                 const E* __restrict__ ents, const M* __restrict__ masks,
-                                                 const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
-                                                 const uint64_t* __restrict__ soff, uint32_t* __restrict__ cursor,
+                                                 const uint32_t* __restrict__ ioff, const uint64_t* __restrict__ itemoff,
+                                                 uint32_t istride, const E* __restrict__ ents,
+                                                 const M* __restrict__ masks, const uint32_t* __restrict__ rank_of,
+                                                 uint32_t r0, uint32_t r1, const uint64_t* __restrict__ soff,
                                                  E* __restrict__ out) {
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
@@ -434,11 +515,18 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
   const uint64_t base = soff[r0];
   for (uint32_t it = wave; it < nitems; it += nwaves) {
     const Item I = items[it];
-    uint32_t kmask = 0, rk[16];
-    for (uint32_t ch = 0; ch < nch; ch++) {
+    uint32_t kmask = 0;
+    uint64_t wpos[16];
+    const uint32_t first = ioff[I.cell];
+#pragma unroll
+    for (uint32_t ch = 0; ch < (POSE ? 16u : 8u); ch++) {
+      wpos[ch] = 0;
+      if (ch >= nch) continue;
       const uint32_t r = rank_of[(uint64_t)I.cell * nch + ch];
-      rk[ch] = r;
-      if (r >= r0 && r < r1) kmask |= 1u << ch;
+      if (r >= r0 && r < r1) {
+        kmask |= 1u << ch;
+        wpos[ch] = (soff[r] - base) + (itemoff[(uint64_t)ch * istride + it] - itemoff[(uint64_t)ch * istride + first]);
+      }
     }
     kmask = uniform_u32(kmask);
     if (!kmask) continue;
@@ -452,25 +540,22 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
       E e;
       if (valid) {
         mask = (uint32_t)masks[ei] & kmask;
-        e = ents[ei];
+        if (mask) e = ents[ei];
       }
-      for (uint32_t ch = 0; ch < nch; ch++) {
+#pragma unroll
+      for (uint32_t ch = 0; ch < (POSE ? 16u : 8u); ch++) {
         if (!((kmask >> ch) & 1u)) continue;
-        const bool p = valid && ((mask >> ch) & 1u);
+        const bool p = (mask >> ch) & 1u;
         const uint64_t bal = __ballot(p);
-        if (!bal) continue;
-        const uint32_t r = uniform_u32(rk[ch]);
-        uint32_t b0 = 0;
-        if (lane == 0) b0 = atomicAdd(&cursor[r - r0], (uint32_t)__popcll(bal));
-        b0 = __shfl(b0, 0, 64);
         if (p) {
-          const uint64_t pos = (soff[r] - base) + b0 + mbcnt64(bal);
+          const uint64_t pos = wpos[ch] + mbcnt64(bal);
           if constexpr (POSE) {
             out[pos] = e;
           } else {
             out[pos] = store_lin<FAM>(lin_canon_child<FAM>(load_lin<FAM>(e), lv, lv.cbits[ch]));
           }
         }
+        wpos[ch] += (uint64_t)__popcll(bal);
       }
     }
   }

@@ -513,9 +513,13 @@ struct Run {
   unsigned long long* dbest = nullptr;
   unsigned long long* drecheck = nullptr;
   uint64_t* dtot = nullptr;
+  uint32_t* dummy = nullptr;    // sink for outputs a leaf-level pass does not need
+  unsigned long long* dreads = nullptr;  // parent entries read by compaction passes
+  size_t ent_bytes = 0;                  // entry + mask bytes of this run
   uint64_t budget_entries = 0;  // max entries of one materialized chunk
   uint64_t first_cells = 65536;  // cells in the first chunk of every expansion
   bool trace = false;            // GV_TRACE=1: one stderr line per expansion
+  bool beam = true;              // progressive chunks until the first leaf level
   // kernel timing: (start, stop, kind 0 test / 1 compact)
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
   size_t ev_used = 0;
@@ -569,7 +573,11 @@ struct Parent {
   uint32_t* rank_of = nullptr;  // child -> rank (or ~0)
   uint64_t* soff = nullptr;     // rank -> first entry (nkept + 1 values)
   uint32_t* cnent = nullptr;    // child -> entries
+  uint32_t* ioff = nullptr;     // cell -> its first item
+  uint64_t* itemoff = nullptr;  // child-major exclusive scan of per-item survivors
+  uint32_t istride = 0;
   int pending = 0;
+  bool sorted = true;           // children in descending count order
 };
 
 struct Task {
@@ -590,6 +598,8 @@ void free_parent(Run& X, Parent* pa) {
   dfree(X, pa->rank_of);
   dfree(X, pa->soff);
   dfree(X, pa->cnent);
+  dfree(X, pa->ioff);
+  dfree(X, pa->itemoff);
   delete pa;
 }
 
@@ -647,16 +657,18 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
 
   // work items: at most GV_ITEM entries of one cell each
   uint32_t* nitem = dalloc<uint32_t>(X, b.ncell);
-  uint32_t* ioff = dalloc<uint32_t>(X, b.ncell);
+  pa->ioff = dalloc<uint32_t>(X, b.ncell);
   pa->max_items = b.ncell + b.nent / GV_ITEM + 1;
   pa->items = dalloc<Item>(X, pa->max_items);
   pa->nitems = dalloc<uint32_t>(X, 1);
   HIPCHK(hipMemsetAsync(pa->nitems, 0, sizeof(uint32_t), X.st));
   k_item_counts<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem);
-  excl_scan(X, nitem, ioff, b.ncell);
-  k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, ioff, pa->items, pa->nitems);
+  excl_scan(X, nitem, pa->ioff, b.ncell);
+  k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, pa->ioff, pa->items, pa->nitems);
   dfree(X, nitem);
-  dfree(X, ioff);
+  pa->istride = (uint32_t)pa->max_items;
+  uint32_t* itemcnt = leaf ? nullptr : dalloc<uint32_t>(X, (uint64_t)nch * pa->istride);
+  if (itemcnt) HIPCHK(hipMemsetAsync(itemcnt, 0, (uint64_t)nch * pa->istride * sizeof(uint32_t), X.st));
 
   pa->masks = dalloc<M>(X, b.nent);
   uint32_t* ccnt = dalloc<uint32_t>(X, nk);
@@ -669,10 +681,12 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   X.stats.test_bytes += b.nent * (sizeof(E) + sizeof(M));
   if constexpr (FAM == FAM_POSE4DOF) {
     k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, X.m64,
-                                             (uint64_t)X.n, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck);
+                                             (uint64_t)X.n, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck,
+                                             itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
   } else {
-    k_count_lin<FAM><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
-                                              (uint8_t*)pa->masks, ccnt, pa->cnent);
+    k_count_lin<FAM, true><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
+                                                    (uint8_t*)pa->masks, ccnt, pa->cnent,
+                                                    itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
   }
   ev_end(X, evp);
   HIPCHK(hipGetLastError());
@@ -688,6 +702,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   HIPCHK(hipGetLastError());
   dfree(X, keptn);
   if (leaf) {
+    if (!dive) X.beam = false;
     dfree(X, keepf);
     dfree(X, ccnt);
     pa->pending = 0;
@@ -709,9 +724,13 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     dfree(X, keepf);
     dfree(X, keepscan);
     dfree(X, ccnt);
+    dfree(X, itemcnt);
     free_parent(X, pa);
     return nullptr;
   }
+  pa->itemoff = dalloc<uint64_t>(X, (uint64_t)nch * pa->istride);
+  excl_scan(X, itemcnt, pa->itemoff, (uint64_t)nch * pa->istride);
+  dfree(X, itemcnt);
   pa->nkept = (uint32_t)nkept;
   uint32_t* kcnt = dalloc<uint32_t>(X, nkept);
   uint32_t* kid = dalloc<uint32_t>(X, nkept);
@@ -719,9 +738,18 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   dfree(X, keepf);
   dfree(X, keepscan);
   dfree(X, ccnt);
-  pa->scount = dalloc<uint32_t>(X, nkept);
-  pa->order = dalloc<uint32_t>(X, nkept);
-  {
+  // POSE4DOF keeps count order throughout: its bound keeps improving after
+  // the first descent, and its incidence test (not the list traffic) dominates
+  pa->sorted = X.beam || dive || FAM == FAM_POSE4DOF;
+  if (!pa->sorted) {
+    // after the first descent the bound is strong: keep parent order so that
+    // a chunk is a contiguous range of parents, each read once
+    pa->scount = kcnt;
+    pa->order = kid;
+    kcnt = kid = nullptr;
+  } else {
+    pa->scount = dalloc<uint32_t>(X, nkept);
+    pa->order = dalloc<uint32_t>(X, nkept);
     size_t tb = 0;
     HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, kcnt, pa->scount, kid, pa->order, (int)nkept, 0,
                                                          32, X.st));
@@ -758,13 +786,13 @@ void plan_chunks(Run& X, Parent* pa, std::vector<std::pair<uint32_t, uint32_t>>&
   dfree(X, d);
   auto at = [&](uint64_t i) { return i >= ns ? s[ns] : s[i]; };  // sample i -> soff[min(i*stride, nk)]
   auto rk = [&](uint64_t i) { return (uint32_t)std::min<uint64_t>(i * stride, nk); };
-  uint64_t i0 = 0, cap = X.first_cells;
+  uint64_t i0 = 0, cap = X.beam ? X.first_cells : (1ull << 30);
   while (rk(i0) < nk) {
     uint64_t i1 = i0 + 1;
     while (i1 < ns && (rk(i1 + 1) - rk(i0)) <= cap && at(i1 + 1) - at(i0) <= X.budget_entries) i1++;
     chunks.push_back({rk(i0), rk(i1)});
     i0 = i1;
-    cap = std::min<uint64_t>(cap * 4, 1ull << 30);
+    cap = X.beam ? std::min<uint64_t>(cap * 4, 1ull << 30) : (1ull << 30);
   }
 }
 
@@ -774,7 +802,7 @@ template <int FAM, typename E, typename M>
 bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   const ProbC& P = X.S.P;
   const LevelC lv = P.lev[pa->level];
-  k_chunk_cut<<<1, 64, 0, X.st>>>(pa->scount, pa->soff, r0, r1, X.dbest, P.B, X.dtot);
+  k_chunk_cut<<<1, 64, 0, X.st>>>(pa->scount, pa->soff, r0, r1, X.dbest, P.B, pa->sorted ? 1 : 0, X.dtot);
   uint64_t cut[2];
   HIPCHK(hipMemcpyAsync(cut, X.dtot, sizeof(cut), hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipStreamSynchronize(X.st));
@@ -787,19 +815,19 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     nb.nent = cut[1];
     nb.cells = dalloc<Cell>(X, nb.ncell);
     nb.ents = dalloc<E>(X, nb.nent);
-    uint32_t* cursor = dalloc<uint32_t>(X, nb.ncell);
-    k_emit_ranked<<<nblk(nb.ncell), 256, 0, X.st>>>(lv, pa->cells, pa->order, pa->soff, r0, rc, pa->cnent, nb.cells,
-                                                   cursor);
+    k_emit_ranked<<<nblk(nb.ncell), 256, 0, X.st>>>(lv, pa->cells, pa->order, pa->soff, r0, rc, pa->cnent, nb.cells);
     const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
     auto evp = ev_begin(X, 1);
     X.stats.compact_launches++;
-    X.stats.compact_bytes += pa->nent * (sizeof(E) + sizeof(M)) + nb.nent * sizeof(E);
+    X.stats.compact_bytes += nb.nent * sizeof(E);
+    if (X.ctx->kernel_timing)
+      k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(pa->cells, pa->ncell, 1u << lv.abits, pa->rank_of, r0, rc,
+                                                       X.dreads);
     k_compact<FAM, E, M, FAM == FAM_POSE4DOF><<<grid, 256, 0, X.st>>>(
-        lv, pa->cells, pa->items, pa->nitems, (const E*)pa->ents, (const M*)pa->masks, pa->rank_of, r0, rc, pa->soff,
-        cursor, (E*)nb.ents);
+        lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, (const E*)pa->ents,
+        (const M*)pa->masks, pa->rank_of, r0, rc, pa->soff, (E*)nb.ents);
     ev_end(X, evp);
     HIPCHK(hipGetLastError());
-    dfree(X, cursor);
     made = true;
   }
   if (--pa->pending == 0) free_parent(X, pa);
@@ -824,6 +852,7 @@ void push_children(Run& X, Parent* pa, std::vector<Task>& stack) {
 template <int FAM, typename E, typename M>
 void search(Run& X, E* root, int64_t n) {
   const ProbC& P = X.S.P;
+  X.ent_bytes = sizeof(E) + sizeof(M);
   const int nsec = P.nsec;
   // greedy dive per sector: an achieved leaf key is a valid starting bound
   for (int s = 0; s < nsec; s++) {
@@ -1009,6 +1038,9 @@ gv_status solve_impl(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
     X.dbest = dalloc<unsigned long long>(X, 1);
     X.drecheck = dalloc<unsigned long long>(X, 1);
     X.dtot = dalloc<uint64_t>(X, 2);
+    X.dummy = dalloc<uint32_t>(X, 64);
+    X.dreads = dalloc<unsigned long long>(X, 1);
+    HIPCHK(hipMemsetAsync(X.dreads, 0, 8, X.st));
     HIPCHK(hipMemsetAsync(X.dbest, 0, 8, X.st));
     HIPCHK(hipMemsetAsync(X.drecheck, 0, 8, X.st));
     HIPCHK(hipMemcpyAsync(X.dP, &P, sizeof(ProbC), hipMemcpyHostToDevice, X.st));
@@ -1111,6 +1143,14 @@ gv_status solve_impl(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
     dfree(X, X.dbest);
     dfree(X, X.drecheck);
     dfree(X, X.dtot);
+    if (X.ctx->kernel_timing) {
+      unsigned long long rd = 0;
+      HIPCHK(hipMemcpyAsync(&rd, X.dreads, 8, hipMemcpyDeviceToHost, X.st));
+      HIPCHK(hipStreamSynchronize(X.st));
+      X.stats.compact_bytes += rd * X.ent_bytes;
+    }
+    dfree(X, X.dummy);
+    dfree(X, X.dreads);
     HIPCHK(hipStreamSynchronize(X.st));
     X.stats.fp64_rechecks = rech;
     X.stats.levels = (uint32_t)P.Lstar;
