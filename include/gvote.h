@@ -93,6 +93,10 @@ typedef struct {
                                  the yaw tolerance in radians */
   double canon_c;             /* eps' = eps / (c (L*+1)); 0 -> 1.0 */
   gv_precision precision;
+  int group;                  /* merging of equal canonical surfaces (never
+                                 changes a result): 0 at the root and in cells
+                                 whose list outgrows their lattice, 1 in every
+                                 cell, -1 never */
 } gv_problem;
 
 typedef struct {

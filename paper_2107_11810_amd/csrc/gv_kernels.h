@@ -560,3 +560,139 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Grouping (Sec. 3.2.1: surfaces that canonize to the same surface in a cell
+// merge, their multiplicities add).  Sort key = (cell, 64-bit hash of the
+// canonical tuple); adjacent entries with the same key AND the same tuple
+// merge.  A hash collision can only leave duplicates unmerged, which never
+// changes a count.
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+__device__ inline uint64_t hcomb(uint64_t h, uint64_t v) { return mix64(h ^ (v + 0x9e3779b97f4a7c15ull + (h << 6))); }
+
+template <typename E> struct Tuple;
+template <> struct Tuple<EntL2> {
+  __device__ static uint64_t hash(const EntL2& e) { return hcomb(hcomb(1, (uint32_t)e.K), (uint32_t)e.F); }
+  __device__ static bool same(const EntL2& a, const EntL2& b) { return a.K == b.K && a.F == b.F; }
+  __device__ static void setw(EntL2& e, uint32_t w) { e.w = (int32_t)w; }
+  __device__ static uint32_t w(const EntL2& e) { return (uint32_t)e.w; }
+};
+template <> struct Tuple<EntP3> {
+  __device__ static uint64_t hash(const EntP3& e) {
+    return hcomb(hcomb(hcomb(2, (uint32_t)e.K1), (uint32_t)e.K2), (uint32_t)e.F);
+  }
+  __device__ static bool same(const EntP3& a, const EntP3& b) { return a.K1 == b.K1 && a.K2 == b.K2 && a.F == b.F; }
+  __device__ static void setw(EntP3& e, uint32_t w) { e.w = (int32_t)w; }
+  __device__ static uint32_t w(const EntP3& e) { return (uint32_t)e.w; }
+};
+template <> struct Tuple<EntR3> {
+  __device__ static uint64_t hash(const EntR3& e) {
+    uint64_t h = hcomb(3, (uint32_t)e.tag);
+    h = hcomb(h, (uint32_t)e.K1);
+    h = hcomb(h, (uint32_t)e.K2);
+    h = hcomb(h, (uint32_t)e.F1);
+    return hcomb(h, (uint32_t)e.F2);
+  }
+  __device__ static bool same(const EntR3& a, const EntR3& b) {
+    return a.tag == b.tag && a.K1 == b.K1 && a.K2 == b.K2 && a.F1 == b.F1 && a.F2 == b.F2;
+  }
+  __device__ static void setw(EntR3& e, uint32_t w) { e.w = (int32_t)w; }
+  __device__ static uint32_t w(const EntR3& e) { return (uint32_t)e.w; }
+};
+template <> struct Tuple<EntQ32> {
+  __device__ static uint64_t hash(const EntQ32& e) {
+    uint64_t h = hcomb(4, __float_as_uint(e.W1));
+    h = hcomb(h, __float_as_uint(e.W2));
+    h = hcomb(h, __float_as_uint(e.W3));
+    h = hcomb(h, __float_as_uint(e.xi));
+    return hcomb(h, __float_as_uint(e.eta));
+  }
+  __device__ static bool same(const EntQ32& a, const EntQ32& b) {
+    return __float_as_uint(a.W1) == __float_as_uint(b.W1) && __float_as_uint(a.W2) == __float_as_uint(b.W2) &&
+           __float_as_uint(a.W3) == __float_as_uint(b.W3) && __float_as_uint(a.xi) == __float_as_uint(b.xi) &&
+           __float_as_uint(a.eta) == __float_as_uint(b.eta);
+  }
+  __device__ static void setw(EntQ32& e, uint32_t w) { e.w = w; }
+  __device__ static uint32_t w(const EntQ32& e) { return e.w; }
+};
+template <> struct Tuple<EntQ64> {
+  __device__ static uint64_t hash(const EntQ64& e) {
+    uint64_t h = hcomb(5, (uint64_t)__double_as_longlong(e.W1));
+    h = hcomb(h, (uint64_t)__double_as_longlong(e.W2));
+    h = hcomb(h, (uint64_t)__double_as_longlong(e.W3));
+    h = hcomb(h, (uint64_t)__double_as_longlong(e.xi));
+    return hcomb(h, (uint64_t)__double_as_longlong(e.eta));
+  }
+  __device__ static bool same(const EntQ64& a, const EntQ64& b) {
+    return __double_as_longlong(a.W1) == __double_as_longlong(b.W1) &&
+           __double_as_longlong(a.W2) == __double_as_longlong(b.W2) &&
+           __double_as_longlong(a.W3) == __double_as_longlong(b.W3) &&
+           __double_as_longlong(a.xi) == __double_as_longlong(b.xi) &&
+           __double_as_longlong(a.eta) == __double_as_longlong(b.eta);
+  }
+  __device__ static void setw(EntQ64& e, uint32_t w) { e.w = w; }
+  __device__ static uint32_t w(const EntQ64& e) { return e.w; }
+};
+
+// key = cell << hb | top hb bits of the tuple hash (cells ordered by offset)
+template <typename E>
+__global__ void k_group_keys(const Cell* __restrict__ cells, uint32_t ncell, const E* __restrict__ ents, uint64_t n,
+                             int hb, uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t lo = 0, hi = ncell;  // last cell with off <= i
+  while (hi - lo > 1) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (cells[mid].off <= i) lo = mid;
+    else hi = mid;
+  }
+  const uint64_t h = Tuple<E>::hash(ents[i]);
+  keys[i] = hb >= 64 ? h : (((uint64_t)lo << hb) | (h >> (64 - hb)));
+  idx[i] = (uint32_t)i;
+}
+
+template <typename E>
+__global__ void k_group_heads(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ idx,
+                              const E* __restrict__ ents, uint64_t n, uint32_t* __restrict__ head) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  head[i] = (i == 0 || keys[i] != keys[i - 1] || !Tuple<E>::same(ents[idx[i]], ents[idx[i - 1]])) ? 1u : 0u;
+}
+
+// one thread per run head: the merged entry carries the run's summed weight
+template <typename E>
+__global__ void k_group_write(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ idx,
+                              const E* __restrict__ ents, uint64_t n, const uint32_t* __restrict__ head,
+                              const uint32_t* __restrict__ hscan, int hb, E* __restrict__ out,
+                              uint32_t* __restrict__ newlen) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !head[i]) return;
+  uint32_t w = 0;
+  uint64_t j = i;
+  do {
+    w += Tuple<E>::w(ents[idx[j]]);
+    j++;
+  } while (j < n && !head[j]);
+  E e = ents[idx[i]];
+  Tuple<E>::setw(e, w);
+  out[hscan[i]] = e;
+  const uint32_t c = hb >= 64 ? 0u : (uint32_t)(keys[i] >> hb);
+  atomicAdd(&newlen[c], 1u);
+}
+
+__global__ void k_group_cells(Cell* __restrict__ cells, uint32_t ncell, const uint32_t* __restrict__ newlen,
+                              const uint32_t* __restrict__ newoff) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncell) {
+    cells[c].off = newoff[c];
+    cells[c].len = newlen[c];
+  }
+}

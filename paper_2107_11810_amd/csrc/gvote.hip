@@ -503,12 +503,15 @@ struct Batch {
   uint64_t nent;
   Cell* cells;
   void* ents;
+  bool unit = true;  // every multiplicity is 1
 };
 
 struct Run {
   gv_ctx* ctx;
   hipStream_t st;
   Setup S;
+  int group_mode = 0;
+  double lat_bound[GV_MAXL + 1];  // canonical surfaces a cell of level m can hold (linear)
   ProbC* dP = nullptr;
   unsigned long long* dbest = nullptr;
   unsigned long long* drecheck = nullptr;
@@ -578,6 +581,7 @@ struct Parent {
   uint32_t istride = 0;
   int pending = 0;
   bool sorted = true;           // children in descending count order
+  bool unit = true;             // every multiplicity is 1
 };
 
 struct Task {
@@ -631,6 +635,70 @@ void ev_end(Run& X, std::pair<hipEvent_t, hipEvent_t> p) {
   if (p.second) HIPCHK(hipEventRecord(p.second, X.st));
 }
 
+// Grouping of a batch's lists: sort by (cell, tuple hash), merge equal
+// tuples, sum multiplicities.  Replaces b.ents (freed if owned) and the
+// cells' offsets and lengths.
+template <typename E>
+void group_batch(Run& X, Batch& b, bool own_ents) {
+  const uint64_t n = b.nent;
+  if (n < 2) return;
+  const int cbits = b.ncell <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(b.ncell - 1));
+  const int hb = 64 - cbits;
+  uint64_t* k0 = dalloc<uint64_t>(X, n);
+  uint32_t* i0 = dalloc<uint32_t>(X, n);
+  uint64_t* k1 = dalloc<uint64_t>(X, n);
+  uint32_t* i1 = dalloc<uint32_t>(X, n);
+  k_group_keys<E><<<nblk(n), 256, 0, X.st>>>(b.cells, b.ncell, (const E*)b.ents, n, hb, k0, i0);
+  {
+    size_t tb = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k0, k1, i0, i1, (int)n, 0, 64, X.st));
+    void* tmp = dalloc<char>(X, tb);
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k0, k1, i0, i1, (int)n, 0, 64, X.st));
+    dfree(X, tmp);
+  }
+  dfree(X, k0);
+  dfree(X, i0);
+  uint32_t* head = dalloc<uint32_t>(X, n);
+  uint32_t* hscan = dalloc<uint32_t>(X, n);
+  k_group_heads<E><<<nblk(n), 256, 0, X.st>>>(k1, i1, (const E*)b.ents, n, head);
+  excl_scan(X, head, hscan, n);
+  uint32_t last[2];
+  HIPCHK(hipMemcpyAsync(&last[0], hscan + n - 1, 4, hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipMemcpyAsync(&last[1], head + n - 1, 4, hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  const uint64_t U = (uint64_t)last[0] + last[1];
+  if (U < n) {
+    E* out = dalloc<E>(X, U);
+    uint32_t* newlen = dalloc<uint32_t>(X, b.ncell);
+    uint32_t* newoff = dalloc<uint32_t>(X, b.ncell);
+    HIPCHK(hipMemsetAsync(newlen, 0, b.ncell * sizeof(uint32_t), X.st));
+    k_group_write<E><<<nblk(n), 256, 0, X.st>>>(k1, i1, (const E*)b.ents, n, head, hscan, hb, out, newlen);
+    excl_scan(X, newlen, newoff, b.ncell);
+    k_group_cells<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, newlen, newoff);
+    dfree(X, newlen);
+    dfree(X, newoff);
+    if (own_ents) dfree(X, b.ents);
+    b.ents = out;
+    b.nent = U;
+    b.unit = false;
+    X.stats.groups_merged += n - U;
+  }
+  dfree(X, k1);
+  dfree(X, i1);
+  dfree(X, head);
+  dfree(X, hscan);
+}
+
+// merge when the lists outgrow the number of canonical surfaces their cells
+// can hold (linear families; POSE4DOF surfaces do not change below the root)
+bool want_group(const Run& X, const Batch& b) {
+  if (X.group_mode < 0 || b.nent < 2) return false;
+  if (X.group_mode > 0) return true;
+  if (X.S.fam == GV_POSE4DOF) return false;
+  const double avg = (double)b.nent / (double)std::max<uint32_t>(1, b.ncell);
+  return avg >= 0.5 * X.lat_bound[b.level];
+}
+
 // One expansion: incidence test and per-child counts, pruning against the
 // best key (or, for the greedy dive, keeping only the best child), then the
 // kept children sorted by count.  Returns nullptr when nothing is kept (or at
@@ -654,6 +722,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   pa->cells = b.cells;
   pa->ents = b.ents;
   pa->own_ents = own_ents;
+  pa->unit = b.unit;
 
   // work items: at most GV_ITEM entries of one cell each
   uint32_t* nitem = dalloc<uint32_t>(X, b.ncell);
@@ -684,9 +753,14 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
                                              (uint64_t)X.n, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck,
                                              itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
   } else {
-    k_count_lin<FAM, true><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
-                                                    (uint8_t*)pa->masks, ccnt, pa->cnent,
-                                                    itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
+    if (b.unit)
+      k_count_lin<FAM, true><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
+                                                      (uint8_t*)pa->masks, ccnt, pa->cnent,
+                                                      itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
+    else
+      k_count_lin<FAM, false><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
+                                                       (uint8_t*)pa->masks, ccnt, pa->cnent,
+                                                       itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
   }
   ev_end(X, evp);
   HIPCHK(hipGetLastError());
@@ -828,9 +902,11 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
         (const M*)pa->masks, pa->rank_of, r0, rc, pa->soff, (E*)nb.ents);
     ev_end(X, evp);
     HIPCHK(hipGetLastError());
+    nb.unit = pa->unit;
     made = true;
   }
   if (--pa->pending == 0) free_parent(X, pa);
+  if (made && want_group(X, nb)) group_batch<E>(X, nb, true);
   return made;
 }
 
@@ -850,18 +926,40 @@ void push_children(Run& X, Parent* pa, std::vector<Task>& stack) {
 }
 
 template <int FAM, typename E, typename M>
-void search(Run& X, E* root, int64_t n) {
+void search(Run& X, E* root0, int64_t n0) {
   const ProbC& P = X.S.P;
   X.ent_bytes = sizeof(E) + sizeof(M);
   const int nsec = P.nsec;
+  // root canonization is done; group equal root surfaces once for all sectors
+  E* root = root0;
+  uint64_t n = (uint64_t)n0;
+  bool unit = true, own_root = false;
+  if (X.group_mode >= 0 && n > 1) {
+    Batch rb;
+    rb.level = 0;
+    rb.ncell = 1;
+    rb.nent = n;
+    rb.cells = dalloc<Cell>(X, 1);
+    k_root_cells<<<1, 64, 0, X.st>>>(rb.cells, 1, 0, n, 1);
+    rb.ents = root;
+    group_batch<E>(X, rb, false);
+    dfree(X, rb.cells);
+    if (rb.ents != (void*)root) {
+      root = (E*)rb.ents;
+      n = rb.nent;
+      own_root = true;
+    }
+    unit = rb.unit;
+  }
   // greedy dive per sector: an achieved leaf key is a valid starting bound
   for (int s = 0; s < nsec; s++) {
     Batch b;
     b.level = 0;
     b.ncell = 1;
-    b.nent = (uint64_t)n;
+    b.nent = n;
+    b.unit = unit;
     b.cells = dalloc<Cell>(X, 1);
-    k_root_cells<<<1, 64, 0, X.st>>>(b.cells, 1, s, (uint64_t)n, 1);
+    k_root_cells<<<1, 64, 0, X.st>>>(b.cells, 1, s, n, 1);
     b.ents = root;
     bool own = false;
     while (true) {
@@ -874,21 +972,26 @@ void search(Run& X, E* root, int64_t n) {
   }
   // depth-first over batches; children of a batch in count order
   std::vector<Task> stack;
+  bool root_owned_by_batch = false;
   {
     Task t{};
     t.chunk = false;
     Batch& r = t.b;
     r.level = 0;
     r.ncell = (uint32_t)nsec;
-    r.nent = (uint64_t)n * nsec;
+    r.nent = n * nsec;
+    r.unit = unit;
     r.cells = dalloc<Cell>(X, nsec);
-    k_root_cells<<<1, 64, 0, X.st>>>(r.cells, nsec, 0, (uint64_t)n, 0);
+    k_root_cells<<<1, 64, 0, X.st>>>(r.cells, nsec, 0, n, 0);
     if (nsec == 1) {
       r.ents = root;
+      root_owned_by_batch = own_root;
     } else {
-      E* rep = dalloc<E>(X, (uint64_t)n * nsec);
-      k_replicate<E><<<gs_grid(X, (uint64_t)n * nsec), 256, 0, X.st>>>(root, n, nsec, rep);
+      E* rep = dalloc<E>(X, n * nsec);
+      k_replicate<E><<<gs_grid(X, n * nsec), 256, 0, X.st>>>(root, (int64_t)n, nsec, rep);
       r.ents = rep;
+      root_owned_by_batch = true;
+      if (own_root) dfree(X, root);
     }
     stack.push_back(t);
   }
@@ -897,12 +1000,13 @@ void search(Run& X, E* root, int64_t n) {
     Task t = stack.back();
     stack.pop_back();
     Batch b;
+    bool own = true;
     if (t.chunk) {
       if (!materialize<FAM, E, M>(X, t.par, t.r0, t.r1, b)) continue;
     } else {
       b = t.b;
+      own = first ? root_owned_by_batch : true;
     }
-    const bool own = !(first && nsec == 1);
     first = false;
     Parent* pa = expand<FAM, E, M>(X, b, own, false);
     if (pa) push_children<FAM, E, M>(X, pa, stack);
@@ -953,6 +1057,29 @@ void run_linear(Run& X, Cols cols, PathC& path, uint64_t& best) {
     }
   }
   dfree(X, dmax);
+  {
+    // canonical surfaces a cell of level m can hold: slopes shrink by 2 per
+    // split of their parameter axis, heights span the cell plus its pads
+    const ProbC& P = X.S.P;
+    X.lat_bound[0] = 1e300;
+    for (int m = 1; m <= P.Lstar; m++) {
+      double D = (FAM == FAM_RAY3D) ? 3.0 : 1.0;
+      const int nq = (FAM == FAM_RAY3D) ? 2 : 1, np = (FAM == FAM_PLANE3D) ? 2 : 1;
+      for (int qi = 0; qi < nq; qi++) {
+        const int q = (FAM == FAM_LINE2D) ? 1 : 2;
+        double ks = 0.0, kprod = 1.0;
+        for (int pi = 0; pi < np; pi++) {
+          const int pax = (FAM == FAM_PLANE3D) ? pi : 0;
+          const double km = std::ceil((double)mx[0] / std::ldexp(1.0, std::min(m, P.L[pax]))) + 1.0;
+          ks += km;
+          kprod *= 2.0 * km + 1.0;
+        }
+        const double Hm = std::ldexp(1.0, -std::min(m, P.L[q])) * P.inv_sf[q];
+        D *= (Hm + (double)P.lev[m - 1].padu[q] + 4.0 * ks + 2.0) * kprod;
+      }
+      X.lat_bound[m] = D;
+    }
+  }
   search<FAM, E, uint8_t>(X, root, n);
   dfree(X, root);
   HIPCHK(hipMemcpyAsync(&best, X.dbest, sizeof(best), hipMemcpyDeviceToHost, X.st));
@@ -1020,6 +1147,7 @@ gv_status solve_impl(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
   X.ctx = ctx;
   X.st = ctx->stream;
   X.n = p->n;
+  X.group_mode = p->group;
   X.trace = std::getenv("GV_TRACE") != nullptr;
   if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
   std::string why;

@@ -36,7 +36,8 @@ class CtxConfig(ctypes.Structure):
 class Problem(ctypes.Structure):
     _fields_ = [("family", ctypes.c_int), ("n", ctypes.c_int64), ("col", ctypes.c_void_p * 6),
                 ("cols_on_device", ctypes.c_int), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
-                ("eps", ctypes.c_double * 4), ("canon_c", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("eps", ctypes.c_double * 4), ("canon_c", ctypes.c_double), ("precision", ctypes.c_int),
+                ("group", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -97,7 +98,7 @@ def _col_ptr(c, on_device):
     return ctypes.c_void_p(c.ctypes.data)
 
 
-def make_problem(family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER):
+def make_problem(family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, group=0):
     """Fill a gv_problem from numpy arrays or device tensors (kept alive by
     the returned tuple)."""
     fam = FAMILIES[family] if isinstance(family, str) else int(family)
@@ -123,6 +124,7 @@ def make_problem(family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER):
         p.eps[j] = float(eps[j]) if j < len(eps) else 0.0
     p.canon_c = float(canon_c)
     p.precision = int(precision)
+    p.group = int(group)
     return p, keep
 
 
@@ -153,8 +155,8 @@ class Context:
     def last_error(self):
         return lib().gv_last_error(self._h).decode()
 
-    def solve(self, family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, cap=None):
-        p, keep = make_problem(family, cols, lo, hi, eps, canon_c, precision)
+    def solve(self, family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, cap=None, group=0):
+        p, keep = make_problem(family, cols, lo, hi, eps, canon_c, precision, group)
         cap = p.n if cap is None else cap
         buf = np.zeros(max(1, cap), dtype=np.int64)
         r = Result()

@@ -157,3 +157,34 @@ def test_ragged_many_cells(ctx):
     ro = oracle.solve(OP(g))
     rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
     check_same(g, rg, ro)
+
+
+@pytest.mark.parametrize("fam", FAMS)
+def test_grouping_every_level_parity(ctx, fam):
+    """Merging equal canonical surfaces in every cell (weights > 1 flow down
+    the tree) leaves count, leaf and inliers unchanged."""
+    for seed in (1, 2):
+        g = synth.config(fam + "_tiny", seed=seed)
+        _say("group-all", fam, seed)
+        ro = oracle.solve(OP(g))
+        for prec in (0, 1):
+            rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], precision=prec, group=1)
+            check_same(g, rg, ro)
+    g = synth.config(fam + "_small")
+    ro = oracle.solve(OP(g, canon_c=0.25))
+    for mode in (-1, 0, 1):
+        rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], canon_c=0.25, group=mode)
+        check_same(g, rg, ro)
+        if mode == 1 and fam != "pose4dof":
+            assert rg["stats"]["groups_merged"] > 0
+
+
+def test_grouping_duplicates_at_root(ctx):
+    """Repeated observations merge at the root into weighted surfaces."""
+    g = synth.config("plane3d_small")
+    cols = [np.concatenate([c, c[:500], c[:500]]) for c in g["cols"]]
+    ro = oracle.solve(oracle.Problem("plane3d", cols, g["lo"], g["hi"], g["eps"]))
+    rg = ctx.solve("plane3d", cols, g["lo"], g["hi"], g["eps"])
+    assert rg["stats"]["groups_merged"] >= 1000
+    assert rg["count"] == ro["count"] and rg["leaf_index"] == ro["leaf_index"]
+    assert np.array_equal(rg["inliers"], ro["inliers"])
