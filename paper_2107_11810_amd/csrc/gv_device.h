@@ -52,6 +52,8 @@ struct Cell {
   uint64_t off;      // first entry of its list in the batch
   uint32_t len;      // number of entries
   uint32_t sector;   // POSE4DOF yaw sector, else 0
+  uint32_t prob;     // problem of this cell within the batch
+  uint32_t _pad;
 };
 
 struct Item {

@@ -279,7 +279,7 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const P
 }
 
 template <typename E>
-__global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pp, int m, LevelC lv,
+__global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Ptab, int m, LevelC lv,
                                                     const Cell* __restrict__ cells, const Item* __restrict__ items,
                                                     const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
                                                     const double* __restrict__ m64, uint64_t n_root,
@@ -287,7 +287,6 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pp
                                                     uint32_t* __restrict__ cnent,
                                                     unsigned long long* __restrict__ rechecks,
                                                     uint32_t* __restrict__ itemcnt, uint32_t istride) {
-  const ProbC& P = *Pp;
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -297,6 +296,7 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pp
   for (uint32_t it = wave; it < nitems; it += nwaves) {
     const Item I = items[it];
     const Cell C = cells[I.cell];
+    const ProbC& P = Ptab[C.prob];
     const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
     const int sector = (int)C.sector;
     PoseLevel B;
@@ -355,44 +355,43 @@ __global__ void k_prune(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell
   const uint32_t nch = 1u << lv.abits;
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nk = (uint64_t)ncell * nch;
-  uint64_t key = 0;
-  if (k < nk) {
-    const uint32_t c = (uint32_t)(k / nch), ch = (uint32_t)(k % nch);
-    const uint64_t pre = (cells[c].prefix << lv.abits) | ch;
-    const uint64_t idxmin = pre << lv.rem_next;
-    key = ((uint64_t)ccnt[k] << B) | (idxmask - idxmin);
-    if (!leaf) {
-      const uint64_t b = *best;
-      const uint32_t keep = key > b ? 1u : 0u;
-      keepf[k] = keep;
-      keptn[k] = keep ? (uint64_t)cnent[k] : 0ull;
-    }
-  }
+  if (k >= nk) return;
+  const uint32_t c = (uint32_t)(k / nch), ch = (uint32_t)(k % nch);
+  const Cell& C = cells[c];
+  const uint64_t pre = (C.prefix << lv.abits) | ch;
+  const uint64_t idxmin = pre << lv.rem_next;
+  const uint64_t key = ((uint64_t)ccnt[k] << B) | (idxmask - idxmin);
+  unsigned long long* bp = &best[C.prob];
   if (leaf) {
-    uint64_t m = wave_max_u64(key);
-    if (lane_id() == 0 && m) atomicMax(best, (unsigned long long)m);
+    if (key > *bp) atomicMax(bp, (unsigned long long)key);
+  } else {
+    const uint32_t keep = key > *bp ? 1u : 0u;
+    keepf[k] = keep;
+    keptn[k] = keep ? (uint64_t)cnent[k] : 0ull;
   }
 }
 
-// Greedy dive: keep only the best child (count, then lowest digit) of a
-// one-cell batch; at the last level record its key.
+// Greedy dive: in every cell keep only the best child (count, then lowest
+// digit); at the last level record its key.
 __global__ void k_pick_best(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell* __restrict__ cells,
-                            const uint32_t* __restrict__ ccnt, const uint32_t* __restrict__ cnent,
+                            uint32_t ncell, const uint32_t* __restrict__ ccnt, const uint32_t* __restrict__ cnent,
                             unsigned long long* __restrict__ best, uint32_t* __restrict__ keepf,
                             uint64_t* __restrict__ keptn) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
   const uint32_t nch = 1u << lv.abits;
+  const uint64_t o = (uint64_t)c * nch;
   uint32_t bc = 0, bd = 0;
   for (uint32_t ch = 0; ch < nch; ch++)
-    if (ch == 0 || ccnt[ch] > bc) { bc = ccnt[ch]; bd = ch; }
+    if (ch == 0 || ccnt[o + ch] > bc) { bc = ccnt[o + ch]; bd = ch; }
   for (uint32_t ch = 0; ch < nch; ch++) {
-    keepf[ch] = (ch == bd) ? 1u : 0u;
-    keptn[ch] = (ch == bd) ? (uint64_t)cnent[ch] : 0ull;
+    keepf[o + ch] = (ch == bd) ? 1u : 0u;
+    keptn[o + ch] = (ch == bd) ? (uint64_t)cnent[o + ch] : 0ull;
   }
   if (leaf) {
-    const uint64_t pre = (cells[0].prefix << lv.abits) | bd;
+    const uint64_t pre = (cells[c].prefix << lv.abits) | bd;
     const uint64_t key = ((uint64_t)bc << B) | (idxmask - (pre << lv.rem_next));
-    atomicMax(best, (unsigned long long)key);
+    atomicMax(&best[cells[c].prob], (unsigned long long)key);
   }
 }
 
@@ -442,7 +441,7 @@ __global__ void k_chunk_cut(const uint32_t* __restrict__ scount, const uint64_t*
                             uint32_t r1, const unsigned long long* __restrict__ best, int B, int sorted,
                             uint64_t* out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const uint64_t bc = (uint64_t)(*best >> B);
+  const uint64_t bc = (uint64_t)(best[0] >> B);
   uint32_t lo = sorted ? r0 : r1, hi = r1;  // first r with scount[r] < bc
   while (lo < hi) {
     const uint32_t mid = lo + (hi - lo) / 2;
@@ -489,6 +488,8 @@ __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const u
   o.off = soff[r] - soff[r0];
   o.len = cnent[k];
   o.sector = P.sector;
+  o.prob = P.prob;
+  o._pad = 0;
   out[r - r0] = o;
 }
 

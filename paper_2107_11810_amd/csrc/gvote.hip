@@ -1,245 +1,38 @@
-// gvote.hip -- MI355X general-voting library: C ABI, host runtime and the
-// root / replay kernels.  See include/gvote.h for the interface.
+// gvote.hip -- MI355X general-voting library: C ABI and host runtime.
+// See include/gvote.h for the interface.
 //
-// Pipeline of one solve (Alg. 2 of Aiger et al., ICCV 2021):
-//   front end (Eq. 1-3, the posing surface) -> root canonization
-//   -> greedy dive (an achieved leaf key seeds the pruning bound)
+// Pipeline (Alg. 2 of Aiger et al., ICCV 2021), for one problem or an epoch
+// of compatible problems whose cells share every batch:
+//   front end (Eq. 1-3, the posing surface) -> root canonization + grouping
+//   -> greedy dive (achieved leaf keys seed the pruning bounds)
 //   -> depth-first over batches of same-level cells: incidence test + counts,
-//      prune against the best key, compaction + canonization into the
-//      children's lists, best-key atomic max at the leaves
-//   -> inliers by per-surface replay along the chosen leaf's path.
+//      prune against the best key, count-ordered chunks, compaction +
+//      canonization into the children's lists, best-key atomic max at leaves
+//   -> inliers by per-surface replay along each problem's chosen path.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
-#include <map>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <functional>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/gvote.h"
 #include "gv_device.h"
 #include "gv_kernels.h"
+#include "gv_root.h"
 
-// ===========================================================================
-// Root kernels
-// ===========================================================================
-struct Cols {
-  const double* c[6];
-};
-
-__device__ inline void atomic_max_f64_pos(unsigned long long* a, double v) {
-  // non-negative doubles order like their bit patterns
-  atomicMax(a, (unsigned long long)__double_as_longlong(v));
-}
-
-__global__ void k_front(int fam, const ProbC* __restrict__ Pp, Cols cols, int64_t n, double* __restrict__ t,
-                        double* __restrict__ f, int32_t* __restrict__ tag, int* __restrict__ bad) {
-  const ProbC& P = *Pp;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double tt[4], ff[2];
-    int32_t tg;
-    if (!front_eval(fam, cols.c, i, P, tt, ff, &tg)) atomicOr(bad, 1);
-    for (int k = 0; k < 4; k++) t[4 * i + k] = tt[k];
-    f[2 * i] = ff[0];
-    f[2 * i + 1] = ff[1];
-    tag[i] = tg;
-  }
-}
-
-template <int FAM>
-__device__ inline bool root_lin(const ProbC& P, const double* const* col, int64_t i, LinS& s, int* bad) {
-  double t[4], f[2];
-  int32_t tag;
-  if (!front_eval(FAM, col, i, P, t, f, &tag)) {
-    atomicOr(bad, 1);
-    return false;
-  }
-  s.K[0][0] = s.K[0][1] = s.K[1][0] = s.K[1][1] = 0;
-  s.F[0] = s.F[1] = 0;
-  s.tag = tag;
-  s.w = 1;
-  bool ok = true;
-  for (int qi = 0; qi < nQ<FAM>(); qi++) {
-    const int q = Qax<FAM>(s, qi);
-    // root: translate by the zero corner, round to the free step s_f
-    for (int pi = 0; pi < nP<FAM>(); pi++) {
-      double k = rint(t[2 * qi + pi] * P.inv_sf[q]);
-      ok = ok && fabs(k) < 1073741824.0;
-      s.K[qi][pi] = ok ? (int32_t)k : 0;
-    }
-    double F = rint(f[qi] * P.inv_sf[q]);
-    ok = ok && fabs(F) < 1073741824.0;
-    s.F[qi] = ok ? (int32_t)F : 0;
-  }
-  if (!ok) atomicOr(bad, 2);
-  return true;
-}
-
-template <int FAM>
-__global__ void k_root_lin(const ProbC* __restrict__ Pp, Cols cols, int64_t n, typename EntOf<FAM>::T* __restrict__ out,
-                           unsigned int* __restrict__ maxabs, int* __restrict__ bad) {
-  const ProbC& P = *Pp;
-  unsigned mk = 0, mf = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    LinS s;
-    if (!root_lin<FAM>(P, cols.c, i, s, bad)) {
-      s = LinS{};
-      s.w = 1;
-    }
-    for (int qi = 0; qi < 2; qi++) {
-      for (int pi = 0; pi < 2; pi++) mk = max(mk, (unsigned)abs(s.K[qi][pi]));
-      mf = max(mf, (unsigned)abs(s.F[qi]));
-    }
-    out[i] = store_lin<FAM>(s);
-  }
-  atomicMax(&maxabs[0], mk);
-  atomicMax(&maxabs[1], mf);
-}
-
-__global__ void k_pose_bounds(const ProbC* __restrict__ Pp, Cols cols, int64_t n, unsigned long long* __restrict__ mx,
-                              int* __restrict__ bad) {
-  const ProbC& P = *Pp;
-  double H = 0.0, R2 = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double t[4], f[2];
-    int32_t tag;
-    if (!front_eval(FAM_POSE4DOF, cols.c, i, P, t, f, &tag)) {
-      atomicOr(bad, 1);
-      continue;
-    }
-    double h = fabs(t[3]);
-    H = h > H ? h : H;
-    double a0 = t[0] * t[0], a1 = (t[0] - 1.0) * (t[0] - 1.0);
-    double b0 = t[1] * t[1], b1 = (t[1] - 1.0) * (t[1] - 1.0);
-    double r2 = (a0 > a1 ? a0 : a1) + (b0 > b1 ? b0 : b1);
-    R2 = r2 > R2 ? r2 : R2;
-  }
-  atomic_max_f64_pos(&mx[0], H);
-  atomic_max_f64_pos(&mx[1], R2);
-}
-
-// quantize once at the root to the fixed pose lattice
-__global__ void k_root_pose(const ProbC* __restrict__ Pp, Cols cols, int64_t n, double* __restrict__ m64,
-                            EntQ32* __restrict__ e32, EntQ64* __restrict__ e64, unsigned long long* __restrict__ mx) {
-  const ProbC& P = *Pp;
-  double a[5] = {0, 0, 0, 0, 0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double t[4], f[2];
-    int32_t tag;
-    front_eval(FAM_POSE4DOF, cols.c, i, P, t, f, &tag);
-    double W1 = rint(t[0] * P.inv_sW) * P.sW;
-    double W2 = rint(t[1] * P.inv_sW) * P.sW;
-    double W3 = rint(f[0] * P.inv_sW3) * P.sW3;
-    double xi = rint(t[2] * P.inv_sXi) * P.sXi;
-    double eta = rint(t[3] * P.inv_sEta) * P.sEta;
-    m64[i] = W1;
-    m64[n + i] = W2;
-    m64[2 * n + i] = W3;
-    m64[3 * n + i] = xi;
-    m64[4 * n + i] = eta;
-    if (e32) e32[i] = EntQ32{(float)W1, (float)W2, (float)W3, (float)xi, (float)eta, 1u, (uint32_t)i, 0u};
-    if (e64) e64[i] = EntQ64{W1, W2, W3, xi, eta, 1u, (uint32_t)i};
-    double v[5] = {fabs(W1), fabs(W2), fabs(W3), fabs(xi), fabs(eta)};
-    for (int k = 0; k < 5; k++) a[k] = v[k] > a[k] ? v[k] : a[k];
-  }
-  for (int k = 0; k < 5; k++) atomic_max_f64_pos(&mx[2 + k], a[k]);
-}
-
-template <typename E>
-__global__ void k_replicate(const E* __restrict__ src, int64_t n, int nsec, E* __restrict__ dst) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * nsec; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i % n];
-}
-
-// root cells: one per sector s0 .. s0+ncell-1; lists either back to back
-// (shared == 0) or all the same list at offset 0
-__global__ void k_root_cells(Cell* cells, int ncell, int s0, uint64_t n, int shared) {
-  int k = threadIdx.x;
-  if (k < ncell) {
-    Cell c;
-    c.c[0] = c.c[1] = c.c[2] = c.c[3] = 0;
-    c.prefix = (uint64_t)(s0 + k);
-    c.off = shared ? 0 : (uint64_t)k * n;
-    c.len = (uint32_t)n;
-    c.sector = (uint32_t)(s0 + k);
-    cells[k] = c;
-  }
-}
-
-// ===========================================================================
-// Replay: every original surface's canonization chain along the chosen
-// leaf's root-to-leaf path; it is an inlier iff every test on the path passes
-// (member tracking, Sec. 3.2.1).
-// ===========================================================================
-struct PathC {
-  uint8_t digit[GV_MAXL];
-  int32_t sector;
-};
-
-template <int FAM>
-__global__ void k_replay_lin(const ProbC* __restrict__ Pp, Cols cols, int64_t n, PathC path, uint32_t* __restrict__ flag,
-                             int* __restrict__ bad) {
-  const ProbC& P = *Pp;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    LinS s;
-    uint32_t ok = 0;
-    if (root_lin<FAM>(P, cols.c, i, s, bad)) {
-      ok = 1;
-      for (int m = 0; m < P.Lstar; m++) {
-        const LevelC& lv = P.lev[m];
-        const uint32_t cb = lv.cbits[path.digit[m]];
-        if (!lin_meets<FAM>(s, lv, cb)) { ok = 0; break; }
-        if (m + 1 < P.Lstar) s = lin_canon_child<FAM>(s, lv, cb);
-      }
-    }
-    flag[i] = ok;
-  }
-}
-
-__global__ void k_replay_pose(const ProbC* __restrict__ Pp, const double* __restrict__ m64, int64_t n, PathC path,
-                              uint32_t* __restrict__ flag) {
-  const ProbC& P = *Pp;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double W1 = m64[i], W2 = m64[n + i], W3 = m64[2 * n + i], xi = m64[3 * n + i], eta = m64[4 * n + i];
-    int32_t cc[4] = {0, 0, 0, 0};
-    uint32_t ok = 1;
-    for (int m = 0; m < P.Lstar && ok; m++) {
-      const LevelC& lv = P.lev[m];
-      const uint32_t cb = lv.cbits[path.digit[m]];
-      int32_t ch[4];
-      for (int a = 0; a < 4; a++) ch[a] = lv.split[a] ? 2 * cc[a] + (int32_t)((cb >> a) & 1u) : cc[a];
-      const int m1 = m + 1;
-      double h[4];
-      for (int j = 0; j < 4; j++) h[j] = ldexp(1.0, -min(m1, P.L[j]));
-      const double Xlo = (double)ch[0] * h[0], Xhi = (double)(ch[0] + 1) * h[0];
-      const double Ylo = (double)ch[1] * h[1], Yhi = (double)(ch[1] + 1) * h[1];
-      const double Zlo = (double)ch[2] * h[2], Zhi = (double)(ch[2] + 1) * h[2];
-      const double Klo = 2.0 * ((double)ch[3] * h[3]) - 1.0, Khi = 2.0 * ((double)(ch[3] + 1) * h[3]) - 1.0;
-      VBox<double> v = pose_vbox<double>(W1, W2, Xlo, Xhi, Ylo, Yhi, path.sector);
-      const double rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
-      ok = zhalf64(W3, eta, rmin2, rmax2, Zhi + P.padz, Zlo - P.padz) &&
-           khalf64(v, rmin2, P.Rg2, xi, Klo - P.padk, Khi + P.padk);
-      for (int a = 0; a < 4; a++) cc[a] = ch[a];
-    }
-    flag[i] = ok;
-  }
-}
-
-__global__ void k_write_inliers(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, int64_t n,
-                                int64_t* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    if (flag[i]) out[pos[i]] = i;
-}
-
-// ===========================================================================
-// Host runtime
-// ===========================================================================
 // Caching device allocator owned by a context.  All library work on a
 // context is ordered on its stream, so a block released after its last use
 // was enqueued can be handed to any later allocation on that stream without a
@@ -300,20 +93,37 @@ struct DevCache {
   }
 };
 
+namespace gvi {
+struct ProbRec;
+}
+
 struct gv_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   uint64_t budget = 0;
-  std::mutex mu;
-  std::string err;
+  std::mutex mu;           // serializes all device work of the context
+  std::string err;         // error text of the running device operation
+  std::mutex emu;
+  std::string last_err;    // what gv_last_error reports
   int n_cu = 256;
   DevCache cache;
   bool kernel_timing = false;
   std::vector<hipEvent_t> ev_pool;
+  // continuous batching
+  std::mutex qmu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<gvi::ProbRec*> queue;
+  std::map<uint64_t, gvi::ProbRec*> tickets;
+  uint64_t next_ticket = 1;
+  uint64_t inflight = 0;   // estimated bytes of admitted problems
+  std::thread worker;
+  bool stop = false;
+  int max_epochs = 4;      // epochs stepped round-robin
+  size_t max_batch = 1024; // problems per epoch
 };
 
-namespace {
+namespace gvi {
 
 thread_local std::string tl_err;
 
@@ -497,6 +307,33 @@ bool pose_filter_exact(const Setup& S, const double* mx) {
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// One problem inside an epoch (also the record behind a ticket).
+// ---------------------------------------------------------------------------
+struct ProbRec {
+  gv_problem p{};
+  Setup S{};
+  Cols cols{};
+  std::vector<double> host_cols[6];  // submitted host columns (copied at submit)
+  std::vector<void*> dev_owned;      // device copies of host columns
+  int64_t n = 0;
+  double epsk = 0.0;
+  bool filter_ok = false;
+  unsigned maxK = 0, maxF = 0;
+  uint64_t est_bytes = 0;
+  // outcome
+  gv_status st = GV_OK;
+  std::string err;
+  uint64_t count = 0, leaf = 0;
+  PathC path{};
+  int32_t coords[4] = {0, 0, 0, 0};
+  std::vector<int64_t> inliers;
+  gv_stats stats{};
+  // serving
+  uint64_t ticket = 0;
+  bool done = false, canceled = false;
+};
+
 struct Batch {
   int level;
   uint32_t ncell;
@@ -506,29 +343,75 @@ struct Batch {
   bool unit = true;  // every multiplicity is 1
 };
 
+// Expansion state of a batch whose kept children are materialized later,
+// one chunk of the count-sorted order at a time.
+struct Parent {
+  int level = 0;
+  uint32_t ncell = 0;
+  uint64_t nent = 0;
+  Cell* cells = nullptr;
+  void* ents = nullptr;
+  bool own_ents = false;
+  void* masks = nullptr;
+  Item* items = nullptr;
+  uint32_t* nitems = nullptr;
+  uint64_t max_items = 0;
+  uint32_t nkept = 0;
+  uint32_t* order = nullptr;    // rank -> child (cell * nch + digit)
+  uint32_t* scount = nullptr;   // rank -> count
+  uint32_t* rank_of = nullptr;  // child -> rank (or ~0)
+  uint64_t* soff = nullptr;     // rank -> first entry (nkept + 1 values)
+  uint32_t* cnent = nullptr;    // child -> entries
+  uint32_t* ioff = nullptr;     // cell -> its first item
+  uint64_t* itemoff = nullptr;  // child-major exclusive scan of per-item survivors
+  uint32_t istride = 0;
+  int pending = 0;
+  bool sorted = true;  // children in descending count order
+  bool unit = true;    // every multiplicity is 1
+};
+
+struct Task {
+  bool chunk;
+  Batch b;
+  Parent* par;
+  uint32_t r0, r1;
+};
+
+// An epoch: a set of problems of one family and one level structure whose
+// cells share every batch.  Per-problem constants, best keys and paths live
+// in device tables indexed by the cell's problem id.
 struct Run {
-  gv_ctx* ctx;
-  hipStream_t st;
-  Setup S;
+  gv_ctx* ctx = nullptr;
+  hipStream_t st = nullptr;
+  std::vector<ProbRec*> probs;
+  int fam = 0;
+  ProbC P0{};  // level structure shared by the epoch (first problem's constants)
   int group_mode = 0;
-  double lat_bound[GV_MAXL + 1];  // canonical surfaces a cell of level m can hold (linear)
-  ProbC* dP = nullptr;
-  unsigned long long* dbest = nullptr;
+  double lat_bound[GV_MAXL + 1];
+  ProbC* dP = nullptr;                    // [nprob]
+  unsigned long long* dbest = nullptr;    // [nprob]
   unsigned long long* drecheck = nullptr;
   uint64_t* dtot = nullptr;
-  uint32_t* dummy = nullptr;    // sink for outputs a leaf-level pass does not need
-  unsigned long long* dreads = nullptr;  // parent entries read by compaction passes
-  size_t ent_bytes = 0;                  // entry + mask bytes of this run
-  uint64_t budget_entries = 0;  // max entries of one materialized chunk
-  uint64_t first_cells = 65536;  // cells in the first chunk of every expansion
-  bool trace = false;            // GV_TRACE=1: one stderr line per expansion
-  bool beam = true;              // progressive chunks until the first leaf level
-  // kernel timing: (start, stop, kind 0 test / 1 compact)
+  uint32_t* dummy = nullptr;              // sink for outputs a leaf-level pass does not need
+  unsigned long long* dreads = nullptr;   // parent entries read by compaction passes
+  size_t ent_bytes = 0;
+  uint64_t budget_entries = 0;            // max entries of one materialized chunk
+  uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
+  bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
+  bool beam = true;                       // progressive chunks until the first leaf level
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
   size_t ev_used = 0;
   gv_stats stats{};
-  double* m64 = nullptr;  // pose master
-  int64_t n = 0;
+  // originals and roots
+  uint64_t Ntot = 0;
+  std::vector<uint64_t> ooff;             // [nprob + 1]
+  uint64_t* dooff = nullptr;
+  double* m64 = nullptr;                  // POSE4DOF binary64 master, SoA stride Ntot
+  void* root = nullptr;                   // root entries (grouped), owned
+  // search state
+  std::vector<Task> stack;
+  bool own_first = true;
+  std::chrono::steady_clock::time_point t0;
 };
 
 template <typename T>
@@ -556,40 +439,6 @@ inline unsigned nblk(uint64_t n, unsigned b = 256) { return (unsigned)std::max<u
 inline unsigned gs_grid(Run& X, uint64_t n) {
   return (unsigned)std::min<uint64_t>(nblk(n), (uint64_t)X.ctx->n_cu * 16);
 }
-
-// Expansion state of a batch whose kept children are materialized later,
-// one chunk of the count-sorted order at a time.
-struct Parent {
-  int level = 0;
-  uint32_t ncell = 0;
-  uint64_t nent = 0;
-  Cell* cells = nullptr;
-  void* ents = nullptr;
-  bool own_ents = false;
-  void* masks = nullptr;
-  Item* items = nullptr;
-  uint32_t* nitems = nullptr;
-  uint64_t max_items = 0;
-  uint32_t nkept = 0;
-  uint32_t* order = nullptr;    // rank -> child (cell * nch + digit)
-  uint32_t* scount = nullptr;   // rank -> count (descending)
-  uint32_t* rank_of = nullptr;  // child -> rank (or ~0)
-  uint64_t* soff = nullptr;     // rank -> first entry (nkept + 1 values)
-  uint32_t* cnent = nullptr;    // child -> entries
-  uint32_t* ioff = nullptr;     // cell -> its first item
-  uint64_t* itemoff = nullptr;  // child-major exclusive scan of per-item survivors
-  uint32_t istride = 0;
-  int pending = 0;
-  bool sorted = true;           // children in descending count order
-  bool unit = true;             // every multiplicity is 1
-};
-
-struct Task {
-  bool chunk;
-  Batch b;
-  Parent* par;
-  uint32_t r0, r1;
-};
 
 void free_parent(Run& X, Parent* pa) {
   dfree(X, pa->cells);
@@ -694,7 +543,7 @@ void group_batch(Run& X, Batch& b, bool own_ents) {
 bool want_group(const Run& X, const Batch& b) {
   if (X.group_mode < 0 || b.nent < 2) return false;
   if (X.group_mode > 0) return true;
-  if (X.S.fam == GV_POSE4DOF) return false;
+  if (X.fam == GV_POSE4DOF) return false;
   const double avg = (double)b.nent / (double)std::max<uint32_t>(1, b.ncell);
   return avg >= 0.5 * X.lat_bound[b.level];
 }
@@ -706,7 +555,7 @@ bool want_group(const Run& X, const Batch& b) {
 // The batch's cells/entries are handed over to the Parent (or freed).
 template <int FAM, typename E, typename M>
 Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
-  const ProbC& P = X.S.P;
+  const ProbC& P = X.P0;
   const int m = b.level;
   const LevelC lv = P.lev[m];
   const uint32_t nch = 1u << lv.abits;
@@ -750,7 +599,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   X.stats.test_bytes += b.nent * (sizeof(E) + sizeof(M));
   if constexpr (FAM == FAM_POSE4DOF) {
     k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, X.m64,
-                                             (uint64_t)X.n, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck,
+                                             X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck,
                                              itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
   } else {
     if (b.unit)
@@ -768,7 +617,8 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   uint32_t* keepf = dalloc<uint32_t>(X, nk);
   uint64_t* keptn = dalloc<uint64_t>(X, nk);
   if (dive) {
-    k_pick_best<<<1, 64, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, ccnt, pa->cnent, X.dbest, keepf, keptn);
+    k_pick_best<<<nblk(b.ncell), 256, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, b.ncell, ccnt,
+                                                 pa->cnent, X.dbest, keepf, keptn);
   } else {
     k_prune<<<nblk(nk), 256, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, b.ncell, ccnt, pa->cnent,
                                         X.dbest, keepf, keptn);
@@ -874,9 +724,12 @@ void plan_chunks(Run& X, Parent* pa, std::vector<std::pair<uint32_t, uint32_t>>&
 // against the current best).  Returns false when nothing remains.
 template <int FAM, typename E, typename M>
 bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
-  const ProbC& P = X.S.P;
+  const ProbC& P = X.P0;
   const LevelC lv = P.lev[pa->level];
-  k_chunk_cut<<<1, 64, 0, X.st>>>(pa->scount, pa->soff, r0, r1, X.dbest, P.B, pa->sorted ? 1 : 0, X.dtot);
+  // the cut needs one bound: with several problems stale children are pruned
+  // at their own expansion instead
+  const int cut_on = (pa->sorted && X.probs.size() == 1) ? 1 : 0;
+  k_chunk_cut<<<1, 64, 0, X.st>>>(pa->scount, pa->soff, r0, r1, X.dbest, P.B, cut_on, X.dtot);
   uint64_t cut[2];
   HIPCHK(hipMemcpyAsync(cut, X.dtot, sizeof(cut), hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipStreamSynchronize(X.st));
@@ -925,208 +778,10 @@ void push_children(Run& X, Parent* pa, std::vector<Task>& stack) {
   }
 }
 
-template <int FAM, typename E, typename M>
-void search(Run& X, E* root0, int64_t n0) {
-  const ProbC& P = X.S.P;
-  X.ent_bytes = sizeof(E) + sizeof(M);
-  const int nsec = P.nsec;
-  // root canonization is done; group equal root surfaces once for all sectors
-  E* root = root0;
-  uint64_t n = (uint64_t)n0;
-  bool unit = true, own_root = false;
-  if (X.group_mode >= 0 && n > 1) {
-    Batch rb;
-    rb.level = 0;
-    rb.ncell = 1;
-    rb.nent = n;
-    rb.cells = dalloc<Cell>(X, 1);
-    k_root_cells<<<1, 64, 0, X.st>>>(rb.cells, 1, 0, n, 1);
-    rb.ents = root;
-    group_batch<E>(X, rb, false);
-    dfree(X, rb.cells);
-    if (rb.ents != (void*)root) {
-      root = (E*)rb.ents;
-      n = rb.nent;
-      own_root = true;
-    }
-    unit = rb.unit;
-  }
-  // greedy dive per sector: an achieved leaf key is a valid starting bound
-  for (int s = 0; s < nsec; s++) {
-    Batch b;
-    b.level = 0;
-    b.ncell = 1;
-    b.nent = n;
-    b.unit = unit;
-    b.cells = dalloc<Cell>(X, 1);
-    k_root_cells<<<1, 64, 0, X.st>>>(b.cells, 1, s, n, 1);
-    b.ents = root;
-    bool own = false;
-    while (true) {
-      Parent* pa = expand<FAM, E, M>(X, b, own, true);
-      if (!pa) break;
-      pa->pending = 1;
-      if (!materialize<FAM, E, M>(X, pa, 0, pa->nkept, b)) break;
-      own = true;
-    }
-  }
-  // depth-first over batches; children of a batch in count order
-  std::vector<Task> stack;
-  bool root_owned_by_batch = false;
-  {
-    Task t{};
-    t.chunk = false;
-    Batch& r = t.b;
-    r.level = 0;
-    r.ncell = (uint32_t)nsec;
-    r.nent = n * nsec;
-    r.unit = unit;
-    r.cells = dalloc<Cell>(X, nsec);
-    k_root_cells<<<1, 64, 0, X.st>>>(r.cells, nsec, 0, n, 0);
-    if (nsec == 1) {
-      r.ents = root;
-      root_owned_by_batch = own_root;
-    } else {
-      E* rep = dalloc<E>(X, n * nsec);
-      k_replicate<E><<<gs_grid(X, n * nsec), 256, 0, X.st>>>(root, (int64_t)n, nsec, rep);
-      r.ents = rep;
-      root_owned_by_batch = true;
-      if (own_root) dfree(X, root);
-    }
-    stack.push_back(t);
-  }
-  bool first = true;
-  while (!stack.empty()) {
-    Task t = stack.back();
-    stack.pop_back();
-    Batch b;
-    bool own = true;
-    if (t.chunk) {
-      if (!materialize<FAM, E, M>(X, t.par, t.r0, t.r1, b)) continue;
-    } else {
-      b = t.b;
-      own = first ? root_owned_by_batch : true;
-    }
-    first = false;
-    Parent* pa = expand<FAM, E, M>(X, b, own, false);
-    if (pa) push_children<FAM, E, M>(X, pa, stack);
-  }
-}
 
-void check_bad(Run& X, int* dbad) {
-  int bad = 0;
-  HIPCHK(hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
-  if (bad & 1) {
-    X.ctx->err = "non-finite observation or zero ray direction";
-    throw DevErr{GV_EINVAL};
-  }
-  if (bad & 2) {
-    X.ctx->err = "lattice too fine for 32-bit cells";
-    throw DevErr{GV_ERANGE};
-  }
-}
-
-template <int FAM>
-void run_linear(Run& X, Cols cols, PathC& path, uint64_t& best) {
-  using E = typename EntOf<FAM>::T;
-  const int64_t n = X.n;
-  E* root = dalloc<E>(X, n);
-  unsigned* dmax = dalloc<unsigned>(X, 2);
-  int* dbad = dalloc<int>(X, 1);
-  HIPCHK(hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned), X.st));
-  HIPCHK(hipMemsetAsync(dbad, 0, sizeof(int), X.st));
-  if (n > 0) k_root_lin<FAM><<<gs_grid(X, n), 256, 0, X.st>>>(X.dP, cols, n, root, dmax, dbad);
-  check_bad(X, dbad);
-  unsigned mx[2];
-  HIPCHK(hipMemcpyAsync(mx, dmax, sizeof(mx), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
-  {
-    // every intermediate of the integer test stays below 2^30
-    const ProbC& P = X.S.P;
-    double Hmax = 0, padmax = 0;
-    for (int j = 0; j < X.S.d; j++) {
-      Hmax = std::max(Hmax, (double)P.lev[0].H[j]);
-      padmax = std::max(padmax, (double)P.lev[0].padu[j]);
-    }
-    const double np = (FAM == FAM_PLANE3D) ? 2.0 : 1.0;
-    const double Fb = std::max((double)mx[1], Hmax + padmax + np * mx[0]);
-    if (2.0 * Fb + 2.0 * np * mx[0] + 2.0 * Hmax + padmax >= 1073741824.0) {
-      X.ctx->err = "lattice too fine for 32-bit cells";
-      throw DevErr{GV_ERANGE};
-    }
-  }
-  dfree(X, dmax);
-  {
-    // canonical surfaces a cell of level m can hold: slopes shrink by 2 per
-    // split of their parameter axis, heights span the cell plus its pads
-    const ProbC& P = X.S.P;
-    X.lat_bound[0] = 1e300;
-    for (int m = 1; m <= P.Lstar; m++) {
-      double D = (FAM == FAM_RAY3D) ? 3.0 : 1.0;
-      const int nq = (FAM == FAM_RAY3D) ? 2 : 1, np = (FAM == FAM_PLANE3D) ? 2 : 1;
-      for (int qi = 0; qi < nq; qi++) {
-        const int q = (FAM == FAM_LINE2D) ? 1 : 2;
-        double ks = 0.0, kprod = 1.0;
-        for (int pi = 0; pi < np; pi++) {
-          const int pax = (FAM == FAM_PLANE3D) ? pi : 0;
-          const double km = std::ceil((double)mx[0] / std::ldexp(1.0, std::min(m, P.L[pax]))) + 1.0;
-          ks += km;
-          kprod *= 2.0 * km + 1.0;
-        }
-        const double Hm = std::ldexp(1.0, -std::min(m, P.L[q])) * P.inv_sf[q];
-        D *= (Hm + (double)P.lev[m - 1].padu[q] + 4.0 * ks + 2.0) * kprod;
-      }
-      X.lat_bound[m] = D;
-    }
-  }
-  search<FAM, E, uint8_t>(X, root, n);
-  dfree(X, root);
-  HIPCHK(hipMemcpyAsync(&best, X.dbest, sizeof(best), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
-  (void)path;
-  dfree(X, dbad);
-}
-
-void run_pose(Run& X, Cols cols, double epsk, bool want_filter, uint64_t& best) {
-  const int64_t n = X.n;
-  unsigned long long* dmx = dalloc<unsigned long long>(X, 8);
-  int* dbad = dalloc<int>(X, 1);
-  HIPCHK(hipMemsetAsync(dmx, 0, 8 * sizeof(unsigned long long), X.st));
-  HIPCHK(hipMemsetAsync(dbad, 0, sizeof(int), X.st));
-  if (n > 0) k_pose_bounds<<<gs_grid(X, n), 256, 0, X.st>>>(X.dP, cols, n, dmx, dbad);
-  check_bad(X, dbad);
-  unsigned long long mxb[8];
-  HIPCHK(hipMemcpyAsync(mxb, dmx, sizeof(mxb), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
-  double mx[8];
-  for (int k = 0; k < 8; k++) std::memcpy(&mx[k], &mxb[k], 8);
-  pose_lattice(X.S, mx[0], mx[1], epsk);
-  HIPCHK(hipMemcpyAsync(X.dP, &X.S.P, sizeof(ProbC), hipMemcpyHostToDevice, X.st));
-  X.m64 = dalloc<double>(X, (uint64_t)n * 5);
-  EntQ32* e32 = want_filter ? dalloc<EntQ32>(X, n) : nullptr;
-  EntQ64* e64 = dalloc<EntQ64>(X, n);
-  if (n > 0) k_root_pose<<<gs_grid(X, n), 256, 0, X.st>>>(X.dP, cols, n, X.m64, e32, e64, dmx);
-  HIPCHK(hipMemcpyAsync(mxb, dmx, sizeof(mxb), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
-  for (int k = 0; k < 8; k++) std::memcpy(&mx[k], &mxb[k], 8);
-  const bool filt = want_filter && pose_filter_exact(X.S, mx);
-  X.S.filter = filt;
-  if (filt) {
-    dfree(X, e64);
-    search<FAM_POSE4DOF, EntQ32, uint16_t>(X, e32, n);
-    dfree(X, e32);
-  } else {
-    if (e32) dfree(X, e32);
-    search<FAM_POSE4DOF, EntQ64, uint16_t>(X, e64, n);
-    dfree(X, e64);
-  }
-  HIPCHK(hipMemcpyAsync(&best, X.dbest, sizeof(best), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
-  dfree(X, dmx);
-  dfree(X, dbad);
-}
-
+// ===========================================================================
+// Epochs
+// ===========================================================================
 void decode_leaf(const ProbC& P, uint64_t idx, PathC& path, int32_t* coords) {
   path.sector = P.fam == GV_POSE4DOF ? (int32_t)(idx >> P.Bcell) : 0;
   int32_t cc[4] = {0, 0, 0, 0};
@@ -1141,165 +796,632 @@ void decode_leaf(const ProbC& P, uint64_t idx, PathC& path, int32_t* coords) {
   for (int a = 0; a < 4; a++) coords[a] = cc[a];
 }
 
-gv_status solve_impl(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
-  auto t0 = std::chrono::steady_clock::now();
-  Run X;
-  X.ctx = ctx;
-  X.st = ctx->stream;
-  X.n = p->n;
-  X.group_mode = p->group;
-  X.trace = std::getenv("GV_TRACE") != nullptr;
-  if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
+int ncols_of(int fam, int d) { return fam == GV_RAY3D ? 6 : (fam == GV_POSE4DOF ? 5 : d); }
+
+// host-side validation and constants of one problem
+gv_status prepare_problem(ProbRec* pr) {
   std::string why;
-  gv_status st = setup_axes(p, X.S, why);
+  gv_status st = setup_axes(&pr->p, pr->S, why);
   if (st != GV_OK) {
-    ctx->err = why;
+    pr->err = why;
     return st;
   }
-  const ProbC& P = X.S.P;
-  std::vector<void*> owned;
-  try {
-    HIPCHK(hipSetDevice(ctx->device));
-    // one chunk per level can be alive along the depth-first path
-    X.budget_entries = std::max<uint64_t>(1ull << 22, ctx->budget / (uint64_t)(P.Lstar + 2) / 64);
-    X.dP = dalloc<ProbC>(X, 1);
-    X.dbest = dalloc<unsigned long long>(X, 1);
-    X.drecheck = dalloc<unsigned long long>(X, 1);
-    X.dtot = dalloc<uint64_t>(X, 2);
-    X.dummy = dalloc<uint32_t>(X, 64);
-    X.dreads = dalloc<unsigned long long>(X, 1);
-    HIPCHK(hipMemsetAsync(X.dreads, 0, 8, X.st));
-    HIPCHK(hipMemsetAsync(X.dbest, 0, 8, X.st));
-    HIPCHK(hipMemsetAsync(X.drecheck, 0, 8, X.st));
-    HIPCHK(hipMemcpyAsync(X.dP, &P, sizeof(ProbC), hipMemcpyHostToDevice, X.st));
-    const int ncol = p->family == GV_RAY3D ? 6 : (p->family == GV_POSE4DOF ? 5 : X.S.d);
-    Cols cols{};
-    for (int k = 0; k < ncol; k++) {
-      if (!p->col[k] && p->n > 0) {
-        ctx->err = "missing column";
-        return GV_EINVAL;
-      }
-      if (p->cols_on_device || p->n == 0) {
-        cols.c[k] = p->col[k];
+  pr->n = pr->p.n;
+  pr->epsk = pr->p.eps[3];
+  const int nc = ncols_of(pr->S.fam, pr->S.d);
+  for (int k = 0; k < nc; k++)
+    if (!pr->p.col[k] && pr->n > 0) {
+      pr->err = "missing column";
+      return GV_EINVAL;
+    }
+  const uint64_t eb = pr->S.fam == GV_POSE4DOF ? 4 * (80 + 2 * 34) : (pr->S.fam == GV_RAY3D ? 4 * 26 : 4 * 18);
+  pr->est_bytes = (uint64_t)std::max<int64_t>(pr->n, 1) * eb + (64ull << 20);
+  return GV_OK;
+}
+
+// problems can share an epoch when their level structure is identical
+bool same_structure(const ProbRec* a, const ProbRec* b) {
+  const ProbC &A = a->S.P, &B = b->S.P;
+  if (a->S.fam != b->S.fam || A.Lstar != B.Lstar || A.B != B.B) return false;
+  if (a->p.precision != b->p.precision || a->p.group != b->p.group) return false;
+  for (int j = 0; j < 4; j++)
+    if (A.L[j] != B.L[j]) return false;
+  return std::memcmp(A.lev, B.lev, sizeof(LevelC) * A.Lstar) == 0;
+}
+
+void fail_all(Run& X, gv_status st) {
+  for (ProbRec* pr : X.probs)
+    if (pr->st == GV_OK) {
+      pr->st = st;
+      pr->err = X.ctx->err;
+    }
+}
+
+// tables, columns, counters of a new epoch
+void epoch_begin(Run& X) {
+  X.t0 = std::chrono::steady_clock::now();
+  X.trace = std::getenv("GV_TRACE") != nullptr;
+  if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
+  ProbRec* p0 = X.probs[0];
+  X.P0 = p0->S.P;
+  X.fam = p0->S.fam;
+  X.group_mode = p0->p.group;
+  X.budget_entries = std::max<uint64_t>(1ull << 22, X.ctx->budget / (uint64_t)(X.P0.Lstar + 2) / 64);
+  const uint32_t np = (uint32_t)X.probs.size();
+  X.ooff.assign(np + 1, 0);
+  for (uint32_t p = 0; p < np; p++) X.ooff[p + 1] = X.ooff[p] + (uint64_t)X.probs[p]->n;
+  X.Ntot = X.ooff[np];
+  HIPCHK(hipSetDevice(X.ctx->device));
+  X.dP = dalloc<ProbC>(X, np);
+  X.dbest = dalloc<unsigned long long>(X, np);
+  X.drecheck = dalloc<unsigned long long>(X, 1);
+  X.dtot = dalloc<uint64_t>(X, 2);
+  X.dummy = dalloc<uint32_t>(X, 64);
+  X.dreads = dalloc<unsigned long long>(X, 1);
+  X.dooff = dalloc<uint64_t>(X, np + 1);
+  HIPCHK(hipMemsetAsync(X.dbest, 0, np * 8, X.st));
+  HIPCHK(hipMemsetAsync(X.drecheck, 0, 8, X.st));
+  HIPCHK(hipMemsetAsync(X.dreads, 0, 8, X.st));
+  HIPCHK(hipMemcpyAsync(X.dooff, X.ooff.data(), (np + 1) * 8, hipMemcpyHostToDevice, X.st));
+  std::vector<ProbC> tab(np);
+  for (uint32_t p = 0; p < np; p++) tab[p] = X.probs[p]->S.P;
+  HIPCHK(hipMemcpyAsync(X.dP, tab.data(), np * sizeof(ProbC), hipMemcpyHostToDevice, X.st));
+  for (ProbRec* pr : X.probs) {
+    const int nc = ncols_of(pr->S.fam, pr->S.d);
+    for (int k = 0; k < nc; k++) {
+      if (pr->p.cols_on_device || pr->n == 0) {
+        pr->cols.c[k] = pr->p.col[k];
       } else {
-        double* d = dalloc<double>(X, p->n);
-        HIPCHK(hipMemcpyAsync(d, p->col[k], p->n * sizeof(double), hipMemcpyHostToDevice, X.st));
-        owned.push_back(d);
-        cols.c[k] = d;
+        double* d = dalloc<double>(X, pr->n);
+        HIPCHK(hipMemcpyAsync(d, pr->p.col[k], pr->n * sizeof(double), hipMemcpyHostToDevice, X.st));
+        pr->dev_owned.push_back(d);
+        pr->cols.c[k] = d;
       }
     }
-    uint64_t best = 0;
-    PathC path{};
-    switch (p->family) {
-      case GV_LINE2D: run_linear<FAM_LINE2D>(X, cols, path, best); break;
-      case GV_PLANE3D: run_linear<FAM_PLANE3D>(X, cols, path, best); break;
-      case GV_RAY3D: run_linear<FAM_RAY3D>(X, cols, path, best); break;
-      default: run_pose(X, cols, p->eps[3], p->precision == GV_FP32_FILTER, best); break;
+  }
+  HIPCHK(hipStreamSynchronize(X.st));  // tables and copied columns are read below
+}
+
+// Root cells of every valid problem, grouping of equal root surfaces, one
+// private list per (problem, sector), greedy dive, first task of the search.
+template <int FAM, typename E, typename M>
+void start_search(Run& X) {
+  const ProbC& P = X.P0;
+  X.ent_bytes = sizeof(E) + sizeof(M);
+  const uint32_t np = (uint32_t)X.probs.size();
+  const int nsec = P.nsec;
+  std::vector<Cell> rc;
+  for (uint32_t p = 0; p < np; p++) {
+    if (X.probs[p]->st != GV_OK) continue;
+    Cell c{};
+    c.off = X.ooff[p];
+    c.len = (uint32_t)X.probs[p]->n;
+    c.prob = p;
+    rc.push_back(c);
+  }
+  if (rc.empty()) return;
+  bool unit = true;
+  {
+    Batch rb;
+    rb.level = 0;
+    rb.ncell = (uint32_t)rc.size();
+    rb.nent = X.Ntot;
+    rb.cells = dalloc<Cell>(X, rc.size());
+    HIPCHK(hipMemcpyAsync(rb.cells, rc.data(), rc.size() * sizeof(Cell), hipMemcpyHostToDevice, X.st));
+    HIPCHK(hipStreamSynchronize(X.st));
+    rb.ents = X.root;
+    if (X.group_mode >= 0) group_batch<E>(X, rb, true);
+    X.root = rb.ents;
+    unit = rb.unit;
+    HIPCHK(hipMemcpyAsync(rc.data(), rb.cells, rc.size() * sizeof(Cell), hipMemcpyDeviceToHost, X.st));
+    HIPCHK(hipStreamSynchronize(X.st));
+    dfree(X, rb.cells);
+  }
+  // one list per (problem, sector): the pass masks are written per entry
+  std::vector<Cell> cells;
+  uint64_t tot = 0;
+  for (const Cell& c : rc)
+    for (int s = 0; s < nsec; s++) {
+      Cell o = c;
+      o.prefix = (uint64_t)s;
+      o.sector = (uint32_t)s;
+      o.off = tot;
+      tot += c.len;
+      cells.push_back(o);
     }
-    const uint64_t count = best >> P.B;
-    const uint64_t leaf = P.idxmask - (best & P.idxmask);
-    int32_t coords[4];
-    decode_leaf(X.S.P, leaf, path, coords);
-    // inliers by replay
-    uint32_t* flag = dalloc<uint32_t>(X, X.n);
-    uint32_t* pos = dalloc<uint32_t>(X, X.n);
+  E* ents = (E*)X.root;
+  if (nsec > 1) {
+    ents = dalloc<E>(X, tot);
+    for (size_t i = 0; i < cells.size(); i++) {
+      const Cell& src = rc[i / nsec];
+      if (src.len)
+        HIPCHK(hipMemcpyAsync(ents + cells[i].off, (E*)X.root + src.off, (size_t)src.len * sizeof(E),
+                              hipMemcpyDeviceToDevice, X.st));
+    }
+    dfree(X, X.root);
+  }
+  X.root = nullptr;
+  Cell* dcells = dalloc<Cell>(X, cells.size());
+  HIPCHK(hipMemcpyAsync(dcells, cells.data(), cells.size() * sizeof(Cell), hipMemcpyHostToDevice, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  // greedy dive in every cell: achieved leaf keys are valid starting bounds
+  {
+    Batch b;
+    b.level = 0;
+    b.ncell = (uint32_t)cells.size();
+    b.nent = tot;
+    b.unit = unit;
+    b.cells = dalloc<Cell>(X, cells.size());
+    HIPCHK(hipMemcpyAsync(b.cells, dcells, cells.size() * sizeof(Cell), hipMemcpyDeviceToDevice, X.st));
+    b.ents = ents;
+    bool own = false;
+    while (true) {
+      Parent* pa = expand<FAM, E, M>(X, b, own, true);
+      if (!pa) break;
+      pa->pending = 1;
+      if (!materialize<FAM, E, M>(X, pa, 0, pa->nkept, b)) break;
+      own = true;
+    }
+  }
+  Task t{};
+  t.chunk = false;
+  t.b.level = 0;
+  t.b.ncell = (uint32_t)cells.size();
+  t.b.nent = tot;
+  t.b.unit = unit;
+  t.b.cells = dcells;
+  t.b.ents = ents;
+  X.stack.push_back(t);
+  X.own_first = true;
+}
+
+// one expansion of the epoch's depth-first search; false when finished
+template <int FAM, typename E, typename M>
+bool epoch_step(Run& X) {
+  if (X.stack.empty()) return false;
+  Task t = X.stack.back();
+  X.stack.pop_back();
+  Batch b;
+  if (t.chunk) {
+    if (!materialize<FAM, E, M>(X, t.par, t.r0, t.r1, b)) return !X.stack.empty();
+  } else {
+    b = t.b;
+  }
+  Parent* pa = expand<FAM, E, M>(X, b, true, false);
+  if (pa) push_children<FAM, E, M>(X, pa, X.stack);
+  return !X.stack.empty();
+}
+
+template <int FAM>
+void build_linear(Run& X) {
+  using E = typename EntOf<FAM>::T;
+  const uint32_t np = (uint32_t)X.probs.size();
+  E* root = dalloc<E>(X, X.Ntot);
+  unsigned* dmax = dalloc<unsigned>(X, 2 * np);
+  int* dbad = dalloc<int>(X, np);
+  HIPCHK(hipMemsetAsync(dmax, 0, 2 * np * sizeof(unsigned), X.st));
+  HIPCHK(hipMemsetAsync(dbad, 0, np * sizeof(int), X.st));
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    if (pr->n > 0)
+      k_root_lin<FAM><<<gs_grid(X, pr->n), 256, 0, X.st>>>(X.dP + p, pr->cols, pr->n, root + X.ooff[p], dmax + 2 * p,
+                                                           dbad + p);
+  }
+  std::vector<unsigned> mx(2 * np);
+  std::vector<int> bad(np);
+  HIPCHK(hipMemcpyAsync(mx.data(), dmax, 2 * np * sizeof(unsigned), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipMemcpyAsync(bad.data(), dbad, np * sizeof(int), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  dfree(X, dmax);
+  dfree(X, dbad);
+  const ProbC& P = X.P0;
+  double Hmax = 0, padmax = 0;
+  for (int j = 0; j < X.probs[0]->S.d; j++) {
+    Hmax = std::max(Hmax, (double)P.lev[0].H[j]);
+    padmax = std::max(padmax, (double)P.lev[0].padu[j]);
+  }
+  const double npar = (FAM == FAM_PLANE3D) ? 2.0 : 1.0;
+  unsigned mk_all = 0;
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    pr->maxK = mx[2 * p];
+    pr->maxF = mx[2 * p + 1];
+    if (bad[p] & 1) {
+      pr->st = GV_EINVAL;
+      pr->err = "non-finite observation or zero ray direction";
+      continue;
+    }
+    // every intermediate of the integer test stays below 2^30
+    const double Fb = std::max((double)pr->maxF, Hmax + padmax + npar * pr->maxK);
+    if ((bad[p] & 2) || 2.0 * Fb + 2.0 * npar * pr->maxK + 2.0 * Hmax + padmax >= 1073741824.0) {
+      pr->st = GV_ERANGE;
+      pr->err = "lattice too fine for 32-bit cells";
+      continue;
+    }
+    mk_all = std::max(mk_all, pr->maxK);
+  }
+  // canonical surfaces a cell of level m can hold: slopes shrink by 2 per
+  // split of their parameter axis, heights span the cell plus its pads
+  X.lat_bound[0] = 1e300;
+  for (int m = 1; m <= P.Lstar; m++) {
+    double D = (FAM == FAM_RAY3D) ? 3.0 : 1.0;
+    const int nq = (FAM == FAM_RAY3D) ? 2 : 1, npp = (FAM == FAM_PLANE3D) ? 2 : 1;
+    for (int qi = 0; qi < nq; qi++) {
+      const int q = (FAM == FAM_LINE2D) ? 1 : 2;
+      double ks = 0.0, kprod = 1.0;
+      for (int pi = 0; pi < npp; pi++) {
+        const int pax = (FAM == FAM_PLANE3D) ? pi : 0;
+        const double km = std::ceil((double)mk_all / std::ldexp(1.0, std::min(m, P.L[pax]))) + 1.0;
+        ks += km;
+        kprod *= 2.0 * km + 1.0;
+      }
+      const double Hm = std::ldexp(1.0, -std::min(m, P.L[q])) * P.inv_sf[q];
+      D *= (Hm + (double)P.lev[m - 1].padu[q] + 4.0 * ks + 2.0) * kprod;
+    }
+    X.lat_bound[m] = D;
+  }
+  X.root = root;
+  start_search<FAM, E, uint8_t>(X);
+}
+
+template <typename E>
+bool step_pose(Run& X) { return epoch_step<FAM_POSE4DOF, E, uint16_t>(X); }
+
+// returns true when the binary32 filter is used
+bool build_pose(Run& X) {
+  const uint32_t np = (uint32_t)X.probs.size();
+  unsigned long long* dmx = dalloc<unsigned long long>(X, 8 * np);
+  int* dbad = dalloc<int>(X, np);
+  HIPCHK(hipMemsetAsync(dmx, 0, 8 * np * sizeof(unsigned long long), X.st));
+  HIPCHK(hipMemsetAsync(dbad, 0, np * sizeof(int), X.st));
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    if (pr->n > 0)
+      k_pose_bounds<<<gs_grid(X, pr->n), 256, 0, X.st>>>(X.dP + p, pr->cols, pr->n, dmx + 8 * p, dbad + p);
+  }
+  std::vector<unsigned long long> mxb(8 * np);
+  std::vector<int> bad(np);
+  HIPCHK(hipMemcpyAsync(mxb.data(), dmx, mxb.size() * 8, hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipMemcpyAsync(bad.data(), dbad, np * sizeof(int), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  std::vector<ProbC> tab(np);
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    double H, R2;
+    std::memcpy(&H, &mxb[8 * p], 8);
+    std::memcpy(&R2, &mxb[8 * p + 1], 8);
+    pose_lattice(pr->S, H, R2, pr->epsk);
+    if (bad[p] & 1) {
+      pr->st = GV_EINVAL;
+      pr->err = "non-finite observation";
+    }
+    tab[p] = pr->S.P;
+  }
+  X.P0 = X.probs[0]->S.P;
+  HIPCHK(hipMemcpyAsync(X.dP, tab.data(), np * sizeof(ProbC), hipMemcpyHostToDevice, X.st));
+  X.m64 = dalloc<double>(X, X.Ntot * 5);
+  EntQ32* e32 = dalloc<EntQ32>(X, X.Ntot);
+  EntQ64* e64 = dalloc<EntQ64>(X, X.Ntot);
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    if (pr->n > 0 && pr->st == GV_OK)
+      k_root_pose<<<gs_grid(X, pr->n), 256, 0, X.st>>>(X.dP + p, pr->cols, pr->n, X.ooff[p], X.Ntot, X.m64, e32, e64,
+                                                       dmx + 8 * p);
+  }
+  HIPCHK(hipMemcpyAsync(mxb.data(), dmx, mxb.size() * 8, hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  dfree(X, dmx);
+  dfree(X, dbad);
+  bool all32 = true;
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    double mx[8];
+    std::memcpy(mx, &mxb[8 * p], 64);
+    pr->filter_ok = pr->p.precision == GV_FP32_FILTER && pose_filter_exact(pr->S, mx);
+    if (pr->st == GV_OK && !pr->filter_ok) all32 = false;
+  }
+  if (all32) {
+    dfree(X, e64);
+    X.root = e32;
+    start_search<FAM_POSE4DOF, EntQ32, uint16_t>(X);
+  } else {
+    dfree(X, e32);
+    X.root = e64;
+    start_search<FAM_POSE4DOF, EntQ64, uint16_t>(X);
+  }
+  return all32;
+}
+
+// per-problem winner, replay, inliers, point; releases the epoch's memory
+void epoch_finish(Run& X) {
+  const uint32_t np = (uint32_t)X.probs.size();
+  const ProbC& P = X.P0;
+  std::vector<unsigned long long> best(np);
+  unsigned long long rech = 0;
+  HIPCHK(hipMemcpyAsync(best.data(), X.dbest, np * 8, hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipMemcpyAsync(&rech, X.drecheck, 8, hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  std::vector<PathC> paths(np);
+  std::vector<Cols> ctab(np);
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    ctab[p] = pr->cols;
+    pr->count = best[p] >> P.B;
+    pr->leaf = P.idxmask - (best[p] & P.idxmask);
+    decode_leaf(P, pr->leaf, pr->path, pr->coords);
+    paths[p] = pr->path;
+  }
+  PathC* dpaths = dalloc<PathC>(X, np);
+  Cols* dctab = dalloc<Cols>(X, np);
+  HIPCHK(hipMemcpyAsync(dpaths, paths.data(), np * sizeof(PathC), hipMemcpyHostToDevice, X.st));
+  HIPCHK(hipMemcpyAsync(dctab, ctab.data(), np * sizeof(Cols), hipMemcpyHostToDevice, X.st));
+  std::vector<uint64_t> bnd(np + 1, 0);
+  std::vector<int64_t> all;
+  if (X.Ntot > 0) {
+    uint32_t* flag = dalloc<uint32_t>(X, X.Ntot);
+    uint32_t* pos = dalloc<uint32_t>(X, X.Ntot + 1);
     int* dbad = dalloc<int>(X, 1);
     HIPCHK(hipMemsetAsync(dbad, 0, sizeof(int), X.st));
-    if (X.n > 0) {
-      switch (p->family) {
-        case GV_LINE2D: k_replay_lin<FAM_LINE2D><<<gs_grid(X, X.n), 256, 0, X.st>>>(X.dP, cols, X.n, path, flag, dbad); break;
-        case GV_PLANE3D: k_replay_lin<FAM_PLANE3D><<<gs_grid(X, X.n), 256, 0, X.st>>>(X.dP, cols, X.n, path, flag, dbad); break;
-        case GV_RAY3D: k_replay_lin<FAM_RAY3D><<<gs_grid(X, X.n), 256, 0, X.st>>>(X.dP, cols, X.n, path, flag, dbad); break;
-        default: k_replay_pose<<<gs_grid(X, X.n), 256, 0, X.st>>>(X.dP, X.m64, X.n, path, flag); break;
-      }
-      HIPCHK(hipGetLastError());
-      excl_scan(X, flag, pos, (uint64_t)X.n);
+    const unsigned gg = gs_grid(X, X.Ntot);
+    switch (X.fam) {
+      case GV_LINE2D: k_replay_lin<FAM_LINE2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+      case GV_PLANE3D: k_replay_lin<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+      case GV_RAY3D: k_replay_lin<FAM_RAY3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+      default: k_replay_pose<<<gg, 256, 0, X.st>>>(X.dP, X.m64, X.Ntot, X.dooff, np, dpaths, flag); break;
     }
-    uint32_t last[2] = {0, 0};
-    if (X.n > 0) {
-      HIPCHK(hipMemcpyAsync(&last[0], pos + X.n - 1, 4, hipMemcpyDeviceToHost, X.st));
-      HIPCHK(hipMemcpyAsync(&last[1], flag + X.n - 1, 4, hipMemcpyDeviceToHost, X.st));
-    }
-    unsigned long long rech = 0;
-    HIPCHK(hipMemcpyAsync(&rech, X.drecheck, 8, hipMemcpyDeviceToHost, X.st));
+    HIPCHK(hipGetLastError());
+    excl_scan(X, flag, pos, X.Ntot);
+    uint32_t lastf = 0;
+    HIPCHK(hipMemcpyAsync(&lastf, flag + X.Ntot - 1, 4, hipMemcpyDeviceToHost, X.st));
+    std::vector<uint32_t> pb(np + 1);
+    for (uint32_t p = 0; p < np; p++)
+      HIPCHK(hipMemcpyAsync(&pb[p], pos + std::min<uint64_t>(X.ooff[p], X.Ntot - 1), 4, hipMemcpyDeviceToHost, X.st));
+    HIPCHK(hipMemcpyAsync(&pb[np], pos + X.Ntot - 1, 4, hipMemcpyDeviceToHost, X.st));
     HIPCHK(hipStreamSynchronize(X.st));
-    const uint64_t ninl = (uint64_t)last[0] + last[1];
-    r->count = count;
-    r->leaf_index = leaf;
-    r->sector = path.sector;
-    for (int a = 0; a < 4; a++) r->leaf_coords[a] = a < X.S.d ? coords[a] : 0;
-    for (int j = 0; j < 4; j++) r->point[j] = 0.0;
-    for (int j = 0; j < X.S.d; j++) {
-      double u = (double)(2 * coords[j] + 1) * std::ldexp(1.0, -(P.L[j] + 1));
-      r->point[j] = P.lo[j] + P.E[j] * u;
-    }
-    if (p->family == GV_POSE4DOF) {
-      double yaw = (double)path.sector * (M_PI / 2.0) + std::atan(r->point[3]);
-      if (yaw < 0.0) yaw += 2.0 * M_PI;
-      if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
-      r->point[3] = yaw;
-    }
-    for (int j = 0; j < 4; j++) r->bound[j] = 0.0;
-    for (int j = 0; j < X.S.d; j++) {
-      if (p->family == GV_POSE4DOF) {
-        r->bound[j] = j == 2 ? (P.padz + X.S.ez * 0.5) * P.E[2] : (j == 3 ? P.padk + X.S.ek * 0.5 : 0.5 * std::ldexp(P.E[j], -P.L[j]));
-      } else {
-        const double Em = (double)(P.Lstar * (X.S.ell + 1)) * P.sf[j] * 0.5;
-        r->bound[j] = (X.S.epsn[j] + 2.0 * Em + P.sf[j]) * P.E[j];
-      }
-    }
-    r->n_inliers = ninl;
-    gv_status out = GV_OK;
-    if (ninl != count) {
-      ctx->err = "internal: replayed inlier count differs from the leaf count";
-      out = GV_EDEVICE;
-    } else if (ninl > r->inliers_cap || (!r->inliers && ninl > 0)) {
-      out = GV_EBUFSZ;
-    } else if (ninl > 0) {
-      int64_t* dout = dalloc<int64_t>(X, ninl);
-      k_write_inliers<<<gs_grid(X, X.n), 256, 0, X.st>>>(flag, pos, X.n, dout);
-      HIPCHK(hipMemcpyAsync(r->inliers, dout, ninl * sizeof(int64_t), hipMemcpyDeviceToHost, X.st));
+    pb[np] += lastf;
+    for (uint32_t p = 0; p < np; p++)
+      if (X.ooff[p] >= X.Ntot) pb[p] = pb[np];
+    for (uint32_t p = 0; p <= np; p++) bnd[p] = pb[p];
+    const uint64_t tot = bnd[np];
+    if (tot > 0) {
+      int64_t* dout = dalloc<int64_t>(X, tot);
+      k_write_inliers<<<gg, 256, 0, X.st>>>(flag, pos, X.dooff, np, X.Ntot, dout);
+      all.resize(tot);
+      HIPCHK(hipMemcpyAsync(all.data(), dout, tot * sizeof(int64_t), hipMemcpyDeviceToHost, X.st));
       HIPCHK(hipStreamSynchronize(X.st));
       dfree(X, dout);
     }
     dfree(X, flag);
     dfree(X, pos);
     dfree(X, dbad);
-    if (X.m64) dfree(X, X.m64);
-    for (void* q : owned) dfree(X, q);
-    dfree(X, X.dP);
-    dfree(X, X.dbest);
-    dfree(X, X.drecheck);
-    dfree(X, X.dtot);
-    if (X.ctx->kernel_timing) {
-      unsigned long long rd = 0;
-      HIPCHK(hipMemcpyAsync(&rd, X.dreads, 8, hipMemcpyDeviceToHost, X.st));
-      HIPCHK(hipStreamSynchronize(X.st));
-      X.stats.compact_bytes += rd * X.ent_bytes;
+  }
+  // kernel timing
+  for (auto& e : X.ev) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e.first.first, e.first.second));
+    (e.second == 0 ? X.stats.test_ms : X.stats.compact_ms) += (double)ms;
+  }
+  if (X.ctx->kernel_timing) X.stats.compact_bytes += d2h1(X, X.dreads) * X.ent_bytes;
+  X.stats.fp64_rechecks = rech;
+  X.stats.levels = (uint32_t)P.Lstar;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - X.t0).count();
+  X.stats.ms_total = ms;
+  X.stats.ms_kernels = ms;
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    pr->stats = X.stats;
+    if (pr->st != GV_OK) continue;
+    pr->inliers.assign(all.begin() + (int64_t)bnd[p], all.begin() + (int64_t)bnd[p + 1]);
+    if ((uint64_t)pr->inliers.size() != pr->count) {
+      pr->st = GV_EDEVICE;
+      pr->err = "internal: replayed inlier count differs from the leaf count";
     }
-    dfree(X, X.dummy);
-    dfree(X, X.dreads);
-    HIPCHK(hipStreamSynchronize(X.st));
-    X.stats.fp64_rechecks = rech;
-    X.stats.levels = (uint32_t)P.Lstar;
-    for (auto& e : X.ev) {
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e.first.first, e.first.second));
-      (e.second == 0 ? X.stats.test_ms : X.stats.compact_ms) += (double)ms;
+  }
+  dfree(X, dpaths);
+  dfree(X, dctab);
+}
+
+// free everything an epoch may still hold (also after an error)
+void epoch_release(Run& X) {
+  (void)hipStreamSynchronize(X.st);
+  while (!X.stack.empty()) {
+    Task t = X.stack.back();
+    X.stack.pop_back();
+    if (t.chunk) {
+      if (--t.par->pending == 0) free_parent(X, t.par);
+    } else {
+      dfree(X, t.b.cells);
+      dfree(X, t.b.ents);
     }
-    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    X.stats.ms_total = ms;
-    X.stats.ms_kernels = ms;
-    r->stats = X.stats;
-    return out;
-  } catch (DevErr& e) {
-    for (void* q : owned) dfree(X, q);
-    (void)hipStreamSynchronize(X.st);
-    return e.st;
+  }
+  dfree(X, X.root);
+  X.root = nullptr;
+  dfree(X, X.m64);
+  X.m64 = nullptr;
+  for (ProbRec* pr : X.probs) {
+    for (void* q : pr->dev_owned) dfree(X, q);
+    pr->dev_owned.clear();
+  }
+  dfree(X, X.dP);
+  dfree(X, X.dbest);
+  dfree(X, X.drecheck);
+  dfree(X, X.dtot);
+  dfree(X, X.dummy);
+  dfree(X, X.dreads);
+  dfree(X, X.dooff);
+  X.dP = nullptr;
+  X.dbest = nullptr;
+  X.drecheck = nullptr;
+  X.dtot = nullptr;
+  X.dummy = nullptr;
+  X.dreads = nullptr;
+  X.dooff = nullptr;
+}
+
+// build an epoch and return its step function
+std::function<bool(Run&)> epoch_build(Run& X) {
+  epoch_begin(X);
+  switch (X.fam) {
+    case GV_LINE2D: build_linear<FAM_LINE2D>(X); return epoch_step<FAM_LINE2D, EntL2, uint8_t>;
+    case GV_PLANE3D: build_linear<FAM_PLANE3D>(X); return epoch_step<FAM_PLANE3D, EntP3, uint8_t>;
+    case GV_RAY3D: build_linear<FAM_RAY3D>(X); return epoch_step<FAM_RAY3D, EntR3, uint8_t>;
+    default:
+      if (build_pose(X)) return step_pose<EntQ32>;
+      return step_pose<EntQ64>;
   }
 }
 
-}  // namespace
+void fill_result(const ProbRec* pr, gv_result* r) {
+  const ProbC& P = pr->S.P;
+  r->count = pr->count;
+  r->leaf_index = pr->leaf;
+  r->sector = pr->path.sector;
+  for (int a = 0; a < 4; a++) r->leaf_coords[a] = a < pr->S.d ? pr->coords[a] : 0;
+  for (int j = 0; j < 4; j++) r->point[j] = 0.0;
+  for (int j = 0; j < pr->S.d; j++) {
+    double u = (double)(2 * pr->coords[j] + 1) * std::ldexp(1.0, -(P.L[j] + 1));
+    r->point[j] = P.lo[j] + P.E[j] * u;
+  }
+  if (pr->S.fam == GV_POSE4DOF) {
+    double yaw = (double)pr->path.sector * (M_PI / 2.0) + std::atan(r->point[3]);
+    if (yaw < 0.0) yaw += 2.0 * M_PI;
+    if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
+    r->point[3] = yaw;
+  }
+  for (int j = 0; j < 4; j++) r->bound[j] = 0.0;
+  for (int j = 0; j < pr->S.d; j++) {
+    if (pr->S.fam == GV_POSE4DOF) {
+      r->bound[j] = j == 2 ? (P.padz + pr->S.ez * 0.5) * P.E[2]
+                           : (j == 3 ? P.padk + pr->S.ek * 0.5 : 0.5 * std::ldexp(P.E[j], -P.L[j]));
+    } else {
+      const double Em = (double)(P.Lstar * (pr->S.ell + 1)) * P.sf[j] * 0.5;
+      r->bound[j] = (pr->S.epsn[j] + 2.0 * Em + P.sf[j]) * P.E[j];
+    }
+  }
+  r->stats = pr->stats;
+  r->n_inliers = pr->inliers.size();
+}
+
+// copy the inliers out; GV_EBUFSZ (with n_inliers set) if they do not fit
+gv_status deliver(const ProbRec* pr, gv_result* r) {
+  fill_result(pr, r);
+  if (pr->inliers.size() > r->inliers_cap || (!r->inliers && !pr->inliers.empty())) return GV_EBUFSZ;
+  if (!pr->inliers.empty()) std::memcpy(r->inliers, pr->inliers.data(), pr->inliers.size() * sizeof(int64_t));
+  return GV_OK;
+}
+
+// run an epoch to completion on the calling thread (ctx->mu held)
+void run_epoch(gv_ctx* ctx, std::vector<ProbRec*>& probs) {
+  Run X;
+  X.ctx = ctx;
+  X.st = ctx->stream;
+  X.probs = probs;
+  try {
+    auto step = epoch_build(X);
+    while (step(X)) {
+    }
+    epoch_finish(X);
+  } catch (DevErr& e) {
+    fail_all(X, e.st);
+  }
+  epoch_release(X);
+}
+
+// ===========================================================================
+// Continuous batching: a worker thread admits queued problems into epochs
+// (compatible problems, within the memory budget, up to max_epochs live at
+// once) and steps the live epochs round-robin, one expansion at a time, so a
+// request that arrives while others run starts at the next step.
+// ===========================================================================
+void publish(gv_ctx* ctx, std::vector<ProbRec*>& probs) {
+  std::lock_guard<std::mutex> g(ctx->qmu);
+  for (ProbRec* pr : probs) {
+    pr->done = true;
+    ctx->inflight -= std::min(ctx->inflight, pr->est_bytes);
+  }
+  ctx->cv_done.notify_all();
+}
+
+void worker_main(gv_ctx* ctx) {
+  struct Live {
+    std::unique_ptr<Run> X;
+    std::function<bool(Run&)> step;
+  };
+  std::vector<Live> live;
+  size_t rr = 0;
+  while (true) {
+    std::vector<ProbRec*> admit;
+    {
+      std::unique_lock<std::mutex> lk(ctx->qmu);
+      if (live.empty()) ctx->cv_work.wait(lk, [&] { return ctx->stop || !ctx->queue.empty(); });
+      if (ctx->stop && ctx->queue.empty() && live.empty()) break;
+      if (!ctx->queue.empty() && (int)live.size() < ctx->max_epochs) {
+        ProbRec* first = ctx->queue.front();
+        for (auto it = ctx->queue.begin(); it != ctx->queue.end() && admit.size() < ctx->max_batch;) {
+          ProbRec* pr = *it;
+          if (pr->canceled) {
+            it = ctx->queue.erase(it);
+            pr->done = true;
+            continue;
+          }
+          const bool fits = ctx->inflight + pr->est_bytes <= ctx->budget / 2 || (live.empty() && admit.empty());
+          if (same_structure(first, pr) && fits) {
+            admit.push_back(pr);
+            ctx->inflight += pr->est_bytes;
+            it = ctx->queue.erase(it);
+          } else {
+            ++it;
+          }
+        }
+        ctx->cv_done.notify_all();
+      }
+    }
+    if (!admit.empty()) {
+      Live L;
+      L.X.reset(new Run());
+      L.X->ctx = ctx;
+      L.X->st = ctx->stream;
+      L.X->probs = admit;
+      bool ok = true;
+      {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        try {
+          L.step = epoch_build(*L.X);
+        } catch (DevErr& e) {
+          fail_all(*L.X, e.st);
+          epoch_release(*L.X);
+          ok = false;
+        }
+      }
+      if (ok) live.push_back(std::move(L));
+      else publish(ctx, admit);
+    }
+    if (!live.empty()) {
+      const size_t i = rr++ % live.size();
+      Live& L = live[i];
+      bool more = false;
+      {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        try {
+          more = L.step(*L.X);
+          if (!more) epoch_finish(*L.X);
+        } catch (DevErr& e) {
+          fail_all(*L.X, e.st);
+          more = false;
+        }
+        if (!more) epoch_release(*L.X);
+      }
+      if (!more) {
+        publish(ctx, L.X->probs);
+        live.erase(live.begin() + (long)i);
+      }
+    }
+  }
+}
+
+}  // namespace gvi
+
+using namespace gvi;
 
 // ===========================================================================
 // C ABI
@@ -1324,8 +1446,8 @@ const char* gv_status_str(gv_status s) {
 
 const char* gv_last_error(gv_ctx* ctx) {
   if (!ctx) return "";
-  std::lock_guard<std::mutex> g(ctx->mu);
-  tl_err = ctx->err;
+  std::lock_guard<std::mutex> g(ctx->emu);
+  tl_err = ctx->last_err;
   return tl_err.c_str();
 }
 
@@ -1360,6 +1482,15 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
 
 gv_status gv_destroy(gv_ctx* ctx) {
   if (!ctx) return GV_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(ctx->qmu);
+    ctx->stop = true;
+    for (ProbRec* pr : ctx->queue) pr->canceled = true;
+  }
+  ctx->cv_work.notify_all();
+  if (ctx->worker.joinable()) ctx->worker.join();
+  for (auto& kv : ctx->tickets) delete kv.second;
+  ctx->tickets.clear();
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   ctx->cache.trim(ctx->stream);
@@ -1371,34 +1502,140 @@ gv_status gv_destroy(gv_ctx* ctx) {
   return GV_OK;
 }
 
+static void set_err(gv_ctx* ctx, const std::string& e) {
+  std::lock_guard<std::mutex> g(ctx->emu);
+  ctx->last_err = e;
+}
+
 gv_status gv_solve(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
   if (!ctx || !p || !r) return GV_EINVAL;
-  std::lock_guard<std::mutex> g(ctx->mu);
-  ctx->err.clear();
   std::memset(&r->stats, 0, sizeof(r->stats));
-  return solve_impl(ctx, p, r);
+  ProbRec pr;
+  pr.p = *p;
+  gv_status st = prepare_problem(&pr);
+  if (st != GV_OK) {
+    set_err(ctx, pr.err);
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->err.clear();
+    std::vector<ProbRec*> v{&pr};
+    run_epoch(ctx, v);
+  }
+  if (pr.st != GV_OK) {
+    set_err(ctx, pr.err.empty() ? ctx->err : pr.err);
+    return pr.st;
+  }
+  set_err(ctx, "");
+  return deliver(&pr, r);
+}
+
+gv_status gv_submit(gv_ctx* ctx, const gv_problem* p, uint64_t* ticket) {
+  if (!ctx || !p || !ticket) return GV_EINVAL;
+  ProbRec* pr = new (std::nothrow) ProbRec();
+  if (!pr) return GV_ENOMEM;
+  pr->p = *p;
+  gv_status st = prepare_problem(pr);
+  if (st != GV_OK) {
+    set_err(ctx, pr->err);
+    delete pr;
+    return st;
+  }
+  if (pr->est_bytes > ctx->budget) {
+    set_err(ctx, "problem exceeds the memory budget");
+    delete pr;
+    return GV_ETOOBIG;
+  }
+  if (!p->cols_on_device && p->n > 0) {
+    // host columns are borrowed only for this call
+    const int nc = ncols_of(pr->S.fam, pr->S.d);
+    for (int k = 0; k < nc; k++) {
+      pr->host_cols[k].assign(p->col[k], p->col[k] + p->n);
+      pr->p.col[k] = pr->host_cols[k].data();
+    }
+  }
+  std::lock_guard<std::mutex> g(ctx->qmu);
+  pr->ticket = ctx->next_ticket++;
+  ctx->tickets[pr->ticket] = pr;
+  ctx->queue.push_back(pr);
+  if (!ctx->worker.joinable()) ctx->worker = std::thread(worker_main, ctx);
+  ctx->cv_work.notify_one();
+  *ticket = pr->ticket;
+  return GV_OK;
+}
+
+gv_status gv_poll(gv_ctx* ctx, uint64_t ticket, gv_result* r, int timeout_ms) {
+  if (!ctx || !r) return GV_EINVAL;
+  std::unique_lock<std::mutex> lk(ctx->qmu);
+  auto it = ctx->tickets.find(ticket);
+  if (it == ctx->tickets.end()) return GV_EINVAL;
+  ProbRec* pr = it->second;
+  if (!pr->done) {
+    if (timeout_ms == 0) return GV_EAGAIN;
+    auto pred = [&] { return pr->done; };
+    if (timeout_ms < 0) ctx->cv_done.wait(lk, pred);
+    else if (!ctx->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred)) return GV_ETIMEDOUT;
+  }
+  if (pr->canceled) {
+    ctx->tickets.erase(it);
+    delete pr;
+    return GV_ECANCELED;
+  }
+  if (pr->st != GV_OK) {
+    gv_status st = pr->st;
+    std::string e = pr->err;
+    ctx->tickets.erase(it);
+    delete pr;
+    lk.unlock();
+    set_err(ctx, e);
+    return st;
+  }
+  gv_status st = deliver(pr, r);
+  if (st == GV_OK) {
+    ctx->tickets.erase(it);
+    delete pr;
+  }
+  return st;
+}
+
+gv_status gv_cancel(gv_ctx* ctx, uint64_t ticket) {
+  if (!ctx) return GV_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->qmu);
+  auto it = ctx->tickets.find(ticket);
+  if (it == ctx->tickets.end()) return GV_EINVAL;
+  ProbRec* pr = it->second;
+  pr->canceled = true;
+  auto q = std::find(ctx->queue.begin(), ctx->queue.end(), pr);
+  if (q != ctx->queue.end()) {
+    ctx->queue.erase(q);
+    pr->done = true;
+    ctx->cv_done.notify_all();
+  }
+  return GV_OK;
 }
 
 gv_status gv_parametrize(gv_ctx* ctx, const gv_problem* p, double* t_out, double* f_out, int32_t* tag_out) {
   if (!ctx || !p || (!t_out && p->n > 0) || (!f_out && p->n > 0)) return GV_EINVAL;
+  ProbRec pr;
+  pr.p = *p;
+  std::string why;
+  gv_status st = setup_axes(p, pr.S, why);
+  if (st != GV_OK && st != GV_ERANGE) {
+    set_err(ctx, why);
+    return st;
+  }
   std::lock_guard<std::mutex> g(ctx->mu);
-  ctx->err.clear();
   Run X;
   X.ctx = ctx;
   X.st = ctx->stream;
-  X.n = p->n;
-  std::string why;
-  gv_status st = setup_axes(p, X.S, why);
-  if (st != GV_OK && st != GV_ERANGE) {
-    ctx->err = why;
-    return st;
-  }
+  st = GV_OK;
   std::vector<void*> owned;
   try {
     HIPCHK(hipSetDevice(ctx->device));
     X.dP = dalloc<ProbC>(X, 1);
-    HIPCHK(hipMemcpyAsync(X.dP, &X.S.P, sizeof(ProbC), hipMemcpyHostToDevice, X.st));
-    const int ncol = p->family == GV_RAY3D ? 6 : (p->family == GV_POSE4DOF ? 5 : X.S.d);
+    HIPCHK(hipMemcpyAsync(X.dP, &pr.S.P, sizeof(ProbC), hipMemcpyHostToDevice, X.st));
+    const int ncol = ncols_of(pr.S.fam, pr.S.d);
     Cols cols{};
     for (int k = 0; k < ncol; k++) {
       if (p->cols_on_device || p->n == 0) {
@@ -1428,37 +1665,17 @@ gv_status gv_parametrize(gv_ctx* ctx, const gv_problem* p, double* t_out, double
       dfree(X, tg);
       dfree(X, bad);
       if (hb) {
-        ctx->err = "non-finite observation or zero ray direction";
+        set_err(ctx, "non-finite observation or zero ray direction");
         st = GV_EINVAL;
       }
     }
-    for (void* q : owned) dfree(X, q);
-    dfree(X, X.dP);
-    HIPCHK(hipStreamSynchronize(X.st));
-    return st == GV_ERANGE ? GV_OK : st;
   } catch (DevErr& e) {
-    (void)hipStreamSynchronize(X.st);
-    return e.st;
+    st = e.st;
   }
-}
-
-gv_status gv_submit(gv_ctx* ctx, const gv_problem* p, uint64_t* ticket) {
-  (void)p;
-  (void)ticket;
-  if (ctx) ctx->err = "continuous batching is not built yet";
-  return GV_EINVAL;
-}
-gv_status gv_poll(gv_ctx* ctx, uint64_t ticket, gv_result* r, int timeout_ms) {
-  (void)ticket;
-  (void)r;
-  (void)timeout_ms;
-  if (ctx) ctx->err = "continuous batching is not built yet";
-  return GV_EINVAL;
-}
-gv_status gv_cancel(gv_ctx* ctx, uint64_t ticket) {
-  (void)ticket;
-  if (ctx) ctx->err = "continuous batching is not built yet";
-  return GV_EINVAL;
+  for (void* q : owned) dfree(X, q);
+  dfree(X, X.dP);
+  (void)hipStreamSynchronize(X.st);
+  return st;
 }
 
 }  // extern "C"

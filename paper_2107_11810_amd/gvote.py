@@ -250,3 +250,40 @@ class DeviceArray:
 
 def to_device(cols):
     return [DeviceArray(c) for c in cols]
+
+
+# ---------------------------------------------------------------------------
+# Continuous batching
+# ---------------------------------------------------------------------------
+def _result_dict(r, buf):
+    s = r.stats
+    return {"count": int(r.count), "leaf_index": int(r.leaf_index), "sector": int(r.sector),
+            "leaf_coords": list(r.leaf_coords), "point": list(r.point), "n_inliers": int(r.n_inliers),
+            "inliers": buf[: r.n_inliers].copy(), "bound": list(r.bound),
+            "stats": {"tests": s.tests, "fp64_rechecks": s.fp64_rechecks, "ms_total": s.ms_total}}
+
+
+def submit(ctx, family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, group=0):
+    """Enqueue a problem; returns its ticket (host columns are copied)."""
+    p, keep = make_problem(family, cols, lo, hi, eps, canon_c, precision, group)
+    t = ctypes.c_uint64(0)
+    st = lib().gv_submit(ctx._h, ctypes.byref(p), ctypes.byref(t))
+    if st != 0:
+        raise GvError(st, ctx.last_error())
+    return t.value
+
+
+def poll(ctx, ticket, cap, timeout_ms=-1):
+    """Wait for a ticket; returns (status, result dict or None)."""
+    buf = np.zeros(max(1, cap), dtype=np.int64)
+    r = Result()
+    r.inliers = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    r.inliers_cap = cap
+    st = lib().gv_poll(ctx._h, ctypes.c_uint64(ticket), ctypes.byref(r), int(timeout_ms))
+    if st != 0:
+        return st, ({"n_inliers": int(r.n_inliers)} if st == -4 else None)
+    return 0, _result_dict(r, buf)
+
+
+def cancel(ctx, ticket):
+    return lib().gv_cancel(ctx._h, ctypes.c_uint64(ticket))
