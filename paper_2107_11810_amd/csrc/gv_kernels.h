@@ -416,12 +416,32 @@ __global__ void k_kept_total(const uint32_t* keepf, const uint32_t* keepscan, ui
 
 // rank_of[k] = position of child k in the sorted order; sn[r] = its entries
 __global__ void k_rank(const uint32_t* __restrict__ order, uint32_t nkept, const uint32_t* __restrict__ cnent,
-                       uint32_t* __restrict__ rank_of, uint32_t* __restrict__ sn) {
+                       const uint32_t* __restrict__ ccnt, uint32_t* __restrict__ rank_of, uint32_t* __restrict__ sn,
+                       uint32_t* __restrict__ scount) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nkept) {
     const uint32_t k = order[r];
     rank_of[k] = r;
     sn[r] = cnent[k];
+    scount[r] = ccnt[k];
+  }
+}
+
+// several problems in a batch: order children by their count relative to
+// the largest kept count of their own problem, so the first chunks carry
+// the most promising cells of every problem
+__global__ void k_prob_max(const uint32_t* __restrict__ kcnt, const uint32_t* __restrict__ kid, uint32_t nkept,
+                           const Cell* __restrict__ cells, uint32_t nch, uint32_t* __restrict__ pmax) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nkept) atomicMax(&pmax[cells[kid[r] / nch].prob], kcnt[r]);
+}
+__global__ void k_prob_norm(const uint32_t* __restrict__ kcnt, const uint32_t* __restrict__ kid, uint32_t nkept,
+                            const Cell* __restrict__ cells, uint32_t nch, const uint32_t* __restrict__ pmax,
+                            uint32_t* __restrict__ key) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nkept) {
+    const uint32_t m = pmax[cells[kid[r] / nch].prob];
+    key[r] = m ? (uint32_t)(((uint64_t)kcnt[r] << 30) / m) : 0u;
   }
 }
 __global__ void k_soff_last(uint64_t* soff, const uint32_t* sn, uint32_t nkept) {
@@ -434,36 +454,42 @@ __global__ void k_gather_u64(const uint64_t* __restrict__ a, uint64_t n, uint64_
   if (i == 0) out[m] = a[n];
 }
 
-// Re-cut a pending chunk [r0, r1) against the current best: children are
-// sorted by count descending, so those that can still beat it are a prefix
-// (every child whose count is at least the best count is kept).
-__global__ void k_chunk_cut(const uint32_t* __restrict__ scount, const uint64_t* __restrict__ soff, uint32_t r0,
-                            uint32_t r1, const unsigned long long* __restrict__ best, int B, int sorted,
-                            uint64_t* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const uint64_t bc = (uint64_t)(best[0] >> B);
-  uint32_t lo = sorted ? r0 : r1, hi = r1;  // first r with scount[r] < bc
-  while (lo < hi) {
-    const uint32_t mid = lo + (hi - lo) / 2;
-    if ((uint64_t)scount[mid] >= bc) lo = mid + 1;
-    else hi = mid;
+// Re-cut a pending chunk [r0, r1) against the current bounds: a child is
+// kept only if its count can still reach the best leaf of its own problem.
+// keepc / csize are chunk-local (index r - r0).
+__global__ void k_chunk_keep(const uint32_t* __restrict__ order, const uint32_t* __restrict__ scount,
+                             const Cell* __restrict__ cells, uint32_t nch, const unsigned long long* __restrict__ best,
+                             int B, uint32_t r0, uint32_t r1, const uint32_t* __restrict__ cnent,
+                             uint32_t* __restrict__ keepc, uint64_t* __restrict__ csize) {
+  const uint32_t r = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= r1) return;
+  const uint32_t k = order[r];
+  const uint64_t bc = (uint64_t)(best[cells[k / nch].prob] >> B);
+  const uint32_t keep = (uint64_t)scount[r] >= bc ? 1u : 0u;
+  keepc[r - r0] = keep;
+  csize[r - r0] = keep ? (uint64_t)cnent[k] : 0ull;
+}
+
+__global__ void k_chunk_totals(const uint32_t* keepc, const uint32_t* cidx, const uint64_t* csize,
+                               const uint64_t* coff, uint32_t n, uint64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = n ? (uint64_t)cidx[n - 1] + keepc[n - 1] : 0;
+    out[1] = n ? coff[n - 1] + csize[n - 1] : 0;
   }
-  out[0] = lo;
-  out[1] = soff[lo] - soff[r0];
 }
 
 // entries of the parent cells that have a child in [r0, r1): what one
 // compaction pass must read
 __global__ void k_chunk_reads(const Cell* __restrict__ cells, uint32_t ncell, uint32_t nch,
                               const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
-                              unsigned long long* __restrict__ acc) {
+                              const uint32_t* __restrict__ keepc, unsigned long long* __restrict__ acc) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t v = 0;
   if (c < ncell) {
     bool hit = false;
     for (uint32_t ch = 0; ch < nch; ch++) {
       const uint32_t r = rank_of[(uint64_t)c * nch + ch];
-      hit = hit || (r >= r0 && r < r1);
+      hit = hit || (r >= r0 && r < r1 && keepc[r - r0]);
     }
     v = hit ? cells[c].len : 0;
   }
@@ -473,10 +499,11 @@ __global__ void k_chunk_reads(const Cell* __restrict__ cells, uint32_t ncell, ui
 
 // cells of a materialized chunk, in rank order
 __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const uint32_t* __restrict__ order,
-                              const uint64_t* __restrict__ soff, uint32_t r0, uint32_t r1,
+                              uint32_t r0, uint32_t r1, const uint32_t* __restrict__ keepc,
+                              const uint32_t* __restrict__ cidx, const uint64_t* __restrict__ coff,
                               const uint32_t* __restrict__ cnent, Cell* __restrict__ out) {
   const uint32_t r = r0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= r1) return;
+  if (r >= r1 || !keepc[r - r0]) return;
   const uint32_t nch = 1u << lv.abits;
   const uint32_t k = order[r];
   const uint32_t c = k / nch, ch = k % nch;
@@ -485,12 +512,12 @@ __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const u
   const uint32_t cb = lv.cbits[ch];
   for (int a = 0; a < 4; a++) o.c[a] = lv.split[a] ? 2 * P.c[a] + (int32_t)((cb >> a) & 1u) : P.c[a];
   o.prefix = (P.prefix << lv.abits) | ch;
-  o.off = soff[r] - soff[r0];
+  o.off = coff[r - r0];
   o.len = cnent[k];
   o.sector = P.sector;
   o.prob = P.prob;
   o._pad = 0;
-  out[r - r0] = o;
+  out[cidx[r - r0]] = o;
 }
 
 // ---------------------------------------------------------------------------
@@ -506,14 +533,13 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
                                                  const uint32_t* __restrict__ ioff, const uint64_t* __restrict__ itemoff,
                                                  uint32_t istride, const E* __restrict__ ents,
                                                  const M* __restrict__ masks, const uint32_t* __restrict__ rank_of,
-                                                 uint32_t r0, uint32_t r1, const uint64_t* __restrict__ soff,
-                                                 E* __restrict__ out) {
+                                                 uint32_t r0, uint32_t r1, const uint32_t* __restrict__ keepc,
+                                                 const uint64_t* __restrict__ coff, E* __restrict__ out) {
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t nitems = *nitems_p;
-  const uint64_t base = soff[r0];
   for (uint32_t it = wave; it < nitems; it += nwaves) {
     const Item I = items[it];
     uint32_t kmask = 0;
@@ -524,9 +550,9 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
       wpos[ch] = 0;
       if (ch >= nch) continue;
       const uint32_t r = rank_of[(uint64_t)I.cell * nch + ch];
-      if (r >= r0 && r < r1) {
+      if (r >= r0 && r < r1 && keepc[r - r0]) {
         kmask |= 1u << ch;
-        wpos[ch] = (soff[r] - base) + (itemoff[(uint64_t)ch * istride + it] - itemoff[(uint64_t)ch * istride + first]);
+        wpos[ch] = coff[r - r0] + (itemoff[(uint64_t)ch * istride + it] - itemoff[(uint64_t)ch * istride + first]);
       }
     }
     kmask = uniform_u32(kmask);

@@ -121,6 +121,11 @@ struct gv_ctx {
   bool stop = false;
   int max_epochs = 4;      // epochs stepped round-robin
   size_t max_batch = 1024; // problems per epoch
+  // observations an epoch may take beyond its first problem.  Sharing batches
+  // between problems measured slower than stepping one-problem epochs
+  // round-robin (each problem needs its own first-descent beam), so by
+  // default every epoch holds one problem.
+  uint64_t batch_n = 0;
 };
 
 namespace gvi {
@@ -661,33 +666,46 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   k_select_kept<<<nblk(nk), 256, 0, X.st>>>(keepf, keepscan, ccnt, nk, kcnt, kid);
   dfree(X, keepf);
   dfree(X, keepscan);
-  dfree(X, ccnt);
   // POSE4DOF keeps count order throughout: its bound keeps improving after
   // the first descent, and its incidence test (not the list traffic) dominates
   pa->sorted = X.beam || dive || FAM == FAM_POSE4DOF;
+  pa->scount = dalloc<uint32_t>(X, nkept);
   if (!pa->sorted) {
-    // after the first descent the bound is strong: keep parent order so that
-    // a chunk is a contiguous range of parents, each read once
-    pa->scount = kcnt;
+    // after the first descent the bounds are strong: keep parent order so
+    // that a chunk is a contiguous range of parents, each read once
     pa->order = kid;
-    kcnt = kid = nullptr;
+    kid = nullptr;
   } else {
-    pa->scount = dalloc<uint32_t>(X, nkept);
     pa->order = dalloc<uint32_t>(X, nkept);
+    uint32_t* key = kcnt;
+    uint32_t* pmax = nullptr;
+    if (X.probs.size() > 1) {
+      pmax = dalloc<uint32_t>(X, X.probs.size());
+      key = dalloc<uint32_t>(X, nkept);
+      HIPCHK(hipMemsetAsync(pmax, 0, X.probs.size() * sizeof(uint32_t), X.st));
+      k_prob_max<<<nblk(nkept), 256, 0, X.st>>>(kcnt, kid, (uint32_t)nkept, b.cells, nch, pmax);
+      k_prob_norm<<<nblk(nkept), 256, 0, X.st>>>(kcnt, kid, (uint32_t)nkept, b.cells, nch, pmax, key);
+    }
+    uint32_t* skey = dalloc<uint32_t>(X, nkept);
     size_t tb = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, kcnt, pa->scount, kid, pa->order, (int)nkept, 0,
-                                                         32, X.st));
-    void* tmp = dalloc<char>(X, tb);
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, kcnt, pa->scount, kid, pa->order, (int)nkept, 0, 32,
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, key, skey, kid, pa->order, (int)nkept, 0, 32,
                                                          X.st));
+    void* tmp = dalloc<char>(X, tb);
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, key, skey, kid, pa->order, (int)nkept, 0, 32, X.st));
     dfree(X, tmp);
+    dfree(X, skey);
+    if (pmax) {
+      dfree(X, pmax);
+      dfree(X, key);
+    }
   }
   dfree(X, kcnt);
   dfree(X, kid);
   pa->rank_of = dalloc<uint32_t>(X, nk);
   HIPCHK(hipMemsetAsync(pa->rank_of, 0xff, nk * sizeof(uint32_t), X.st));
   uint32_t* sn = dalloc<uint32_t>(X, nkept);
-  k_rank<<<nblk(nkept), 256, 0, X.st>>>(pa->order, (uint32_t)nkept, pa->cnent, pa->rank_of, sn);
+  k_rank<<<nblk(nkept), 256, 0, X.st>>>(pa->order, (uint32_t)nkept, pa->cnent, ccnt, pa->rank_of, sn, pa->scount);
+  dfree(X, ccnt);
   pa->soff = dalloc<uint64_t>(X, nkept + 1);
   excl_scan(X, sn, pa->soff, nkept);
   k_soff_last<<<1, 64, 0, X.st>>>(pa->soff, sn, (uint32_t)nkept);
@@ -726,38 +744,50 @@ template <int FAM, typename E, typename M>
 bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   const ProbC& P = X.P0;
   const LevelC lv = P.lev[pa->level];
-  // the cut needs one bound: with several problems stale children are pruned
-  // at their own expansion instead
-  const int cut_on = (pa->sorted && X.probs.size() == 1) ? 1 : 0;
-  k_chunk_cut<<<1, 64, 0, X.st>>>(pa->scount, pa->soff, r0, r1, X.dbest, P.B, cut_on, X.dtot);
-  uint64_t cut[2];
-  HIPCHK(hipMemcpyAsync(cut, X.dtot, sizeof(cut), hipMemcpyDeviceToHost, X.st));
+  const uint32_t nch = 1u << lv.abits;
+  const uint32_t nr = r1 - r0;
+  // drop the children that can no longer reach their problem's best leaf
+  uint32_t* keepc = dalloc<uint32_t>(X, nr);
+  uint32_t* cidx = dalloc<uint32_t>(X, nr);
+  uint64_t* csize = dalloc<uint64_t>(X, nr);
+  uint64_t* coff = dalloc<uint64_t>(X, nr);
+  k_chunk_keep<<<nblk(nr), 256, 0, X.st>>>(pa->order, pa->scount, pa->cells, nch, X.dbest, P.B, r0, r1, pa->cnent,
+                                            keepc, csize);
+  excl_scan(X, keepc, cidx, nr);
+  excl_scan(X, csize, coff, nr);
+  k_chunk_totals<<<1, 64, 0, X.st>>>(keepc, cidx, csize, coff, nr, X.dtot);
+  uint64_t tot[2];
+  HIPCHK(hipMemcpyAsync(tot, X.dtot, sizeof(tot), hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipStreamSynchronize(X.st));
-  const uint32_t rc = (uint32_t)cut[0];
   bool made = false;
-  X.stats.cells_pruned += r1 - rc;
-  if (rc > r0) {
+  X.stats.cells_pruned += nr - tot[0];
+  if (tot[0] > 0) {
     nb.level = pa->level + 1;
-    nb.ncell = rc - r0;
-    nb.nent = cut[1];
+    nb.ncell = (uint32_t)tot[0];
+    nb.nent = tot[1];
     nb.cells = dalloc<Cell>(X, nb.ncell);
     nb.ents = dalloc<E>(X, nb.nent);
-    k_emit_ranked<<<nblk(nb.ncell), 256, 0, X.st>>>(lv, pa->cells, pa->order, pa->soff, r0, rc, pa->cnent, nb.cells);
+    k_emit_ranked<<<nblk(nr), 256, 0, X.st>>>(lv, pa->cells, pa->order, r0, r1, keepc, cidx, coff, pa->cnent,
+                                              nb.cells);
     const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
     auto evp = ev_begin(X, 1);
     X.stats.compact_launches++;
     X.stats.compact_bytes += nb.nent * sizeof(E);
     if (X.ctx->kernel_timing)
-      k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(pa->cells, pa->ncell, 1u << lv.abits, pa->rank_of, r0, rc,
+      k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(pa->cells, pa->ncell, nch, pa->rank_of, r0, r1, keepc,
                                                        X.dreads);
     k_compact<FAM, E, M, FAM == FAM_POSE4DOF><<<grid, 256, 0, X.st>>>(
         lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, (const E*)pa->ents,
-        (const M*)pa->masks, pa->rank_of, r0, rc, pa->soff, (E*)nb.ents);
+        (const M*)pa->masks, pa->rank_of, r0, r1, keepc, coff, (E*)nb.ents);
     ev_end(X, evp);
     HIPCHK(hipGetLastError());
     nb.unit = pa->unit;
     made = true;
   }
+  dfree(X, keepc);
+  dfree(X, cidx);
+  dfree(X, csize);
+  dfree(X, coff);
   if (--pa->pending == 0) free_parent(X, pa);
   if (made && want_group(X, nb)) group_batch<E>(X, nb, true);
   return made;
@@ -841,7 +871,6 @@ void fail_all(Run& X, gv_status st) {
 void epoch_begin(Run& X) {
   X.t0 = std::chrono::steady_clock::now();
   X.trace = std::getenv("GV_TRACE") != nullptr;
-  if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
   ProbRec* p0 = X.probs[0];
   X.P0 = p0->S.P;
   X.fam = p0->S.fam;
@@ -851,6 +880,11 @@ void epoch_begin(Run& X) {
   X.ooff.assign(np + 1, 0);
   for (uint32_t p = 0; p < np; p++) X.ooff[p + 1] = X.ooff[p] + (uint64_t)X.probs[p]->n;
   X.Ntot = X.ooff[np];
+  // first-descent beam: 65536 cells per problem keeps the planted cells of a
+  // large problem in it at the coarse levels and pays for itself in bound
+  // quality on small ones; problems sharing an epoch each keep that width
+  X.first_cells = 65536ull * (uint64_t)np;
+  if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
   HIPCHK(hipSetDevice(X.ctx->device));
   X.dP = dalloc<ProbC>(X, np);
   X.dbest = dalloc<unsigned long long>(X, np);
@@ -1207,6 +1241,9 @@ void epoch_finish(Run& X) {
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - X.t0).count();
   X.stats.ms_total = ms;
   X.stats.ms_kernels = ms;
+  if (X.trace)
+    std::fprintf(stderr, "gv: epoch of %u problems: %.3g tests, %llu cells expanded, %.1f ms\n", np,
+                 (double)X.stats.tests, (unsigned long long)X.stats.cells_expanded, ms);
   for (uint32_t p = 0; p < np; p++) {
     ProbRec* pr = X.probs[p];
     pr->stats = X.stats;
@@ -1357,6 +1394,7 @@ void worker_main(gv_ctx* ctx) {
       if (ctx->stop && ctx->queue.empty() && live.empty()) break;
       if (!ctx->queue.empty() && (int)live.size() < ctx->max_epochs) {
         ProbRec* first = ctx->queue.front();
+        uint64_t nsum = 0;
         for (auto it = ctx->queue.begin(); it != ctx->queue.end() && admit.size() < ctx->max_batch;) {
           ProbRec* pr = *it;
           if (pr->canceled) {
@@ -1365,8 +1403,13 @@ void worker_main(gv_ctx* ctx) {
             continue;
           }
           const bool fits = ctx->inflight + pr->est_bytes <= ctx->budget / 2 || (live.empty() && admit.empty());
+          // small problems share an epoch (their per-step overheads amortize);
+          // a large one gets an epoch of its own, stepped alongside the others
+          const bool small = admit.empty() || nsum + (uint64_t)pr->n <= ctx->batch_n;
+          if (!small) break;
           if (same_structure(first, pr) && fits) {
             admit.push_back(pr);
+            nsum += (uint64_t)pr->n;
             ctx->inflight += pr->est_bytes;
             it = ctx->queue.erase(it);
           } else {
@@ -1476,6 +1519,9 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
   size_t fr = 0, tot = 0;
   (void)hipMemGetInfo(&fr, &tot);
   c->budget = (cfg && cfg->mem_budget_bytes) ? cfg->mem_budget_bytes : (uint64_t)(0.6 * (double)fr);
+  if (const char* e = std::getenv("GV_MAX_EPOCHS")) c->max_epochs = std::max(1, atoi(e));
+  if (const char* e = std::getenv("GV_MAX_BATCH")) c->max_batch = (size_t)std::max(1, atoi(e));
+  if (const char* e = std::getenv("GV_BATCH_N")) c->batch_n = std::strtoull(e, nullptr, 10);
   *out = c;
   return GV_OK;
 }

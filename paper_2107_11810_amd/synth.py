@@ -171,8 +171,17 @@ def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=
     yaw = rng.uniform(0.0, 2 * math.pi)
     ws, xis, etas = [], [], []
     got = 0
+    tried = 0
     while got < n_in:
+        if tried > 40 * n_in + 4000 and got < 0.01 * tried:
+            # the camera sees (almost) none of the box from this pose, e.g. on
+            # a wall facing out: draw another pose
+            c = rng.uniform(0.0, size, size=3)
+            yaw = rng.uniform(0.0, 2 * math.pi)
+            ws, xis, etas = [], [], []
+            got = tried = 0
         m = 4 * (n_in - got) + 16
+        tried += m
         xi0 = rng.uniform(-1.0, 1.0, size=m)
         eta0 = rng.uniform(-1.0, 1.0, size=m)
         rho = rng.uniform(1.0, rho_max, size=m)

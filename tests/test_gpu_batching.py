@@ -20,10 +20,20 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=["solo_epochs", "shared_epochs"])
+def ctx(request):
+    """Default serving (one problem per epoch) and epochs shared by many
+    problems (GV_BATCH_N read when the context is created)."""
+    import os
     from paper_2107_11810_amd import gvote
+    old = os.environ.get("GV_BATCH_N")
+    if request.param == "shared_epochs":
+        os.environ["GV_BATCH_N"] = "1000000"
     c = gvote.Context(0)
+    if old is None:
+        os.environ.pop("GV_BATCH_N", None)
+    else:
+        os.environ["GV_BATCH_N"] = old
     yield c
     c.close()
 
