@@ -139,6 +139,24 @@ def serve_bench(args):
 
 
 
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """Device-to-device copies of a known size: the scale for the memory
+    counters (bytes a counter reports per byte a plain copy must move)."""
+    import ctypes
+    from paper_2107_11810_amd import gvote
+    hip = gvote.hip()
+    src, dst = ctypes.c_void_p(), ctypes.c_void_p()
+    if hip.hipMalloc(ctypes.byref(src), nbytes) or hip.hipMalloc(ctypes.byref(dst), nbytes):
+        raise RuntimeError("hipMalloc failed")
+    for _ in range(reps):
+        if hip.hipMemcpy(dst, src, nbytes, 3):  # device -> device
+            raise RuntimeError("hipMemcpy failed")
+    hip.hipDeviceSynchronize()
+    hip.hipFree(src)
+    hip.hipFree(dst)
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
+
+
 def cpu_baseline(g, budget_tests):
     """The oracle as it stands, single thread, stopped after a fixed number
     of incidence tests of the same solve."""
@@ -159,7 +177,12 @@ def main():
     ap.add_argument("--cpu-tests", type=float, default=2.5e8, help="oracle sample size (incidence tests)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, default=1, help="0 binary64, 1 binary32 filter")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 1 GiB device copies (scale for the memory counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)

@@ -56,8 +56,11 @@ struct Cell {
   uint32_t _pad;
 };
 
+// A work item: entries [off, off + cnt) of one cell's list, cnt <= GV_ITEM,
+// off - cell offset a multiple of GV_ITEM.
 struct Item {
-  uint32_t cell, start;
+  uint64_t off;
+  uint32_t cell, cnt;
 };
 
 // Linear-family entries (cell-relative lattice integers + multiplicity).
@@ -73,6 +76,32 @@ template <int FAM> struct EntOf;
 template <> struct EntOf<FAM_LINE2D> { using T = EntL2; };
 template <> struct EntOf<FAM_PLANE3D> { using T = EntP3; };
 template <> struct EntOf<FAM_RAY3D> { using T = EntR3; };
+
+// Packed linear entries for the deeper levels, once the host has shown
+// that every lattice value of a level fits (8 bytes instead of 16):
+//   LINE2D : int16 K, int16 F, u32 w
+//   PLANE3D: lo = K1 (13 bits, signed) | K2 (13, signed) | w bits 0..5,
+//            hi = F (16, signed) | w bits 6..21
+// RAY3D keeps its full entry.
+#define GV_P3_KMAX 4095    // |K| limit of a packed PLANE3D entry
+#define GV_P3_FMAX 32767   // |F| limit
+#define GV_P3_WMAX 4194303 // weight limit (22 bits)
+#define GV_L2_MAX 32767    // |K|, |F| limit of a packed LINE2D entry
+struct __attribute__((aligned(8))) EntL2p { int16_t K, F; uint32_t w; };
+struct __attribute__((aligned(8))) EntP3p { uint32_t lo, hi; };
+template <int FAM> struct PackOf { using T = void; };  // no packed entry
+template <> struct PackOf<FAM_LINE2D> { using T = EntL2p; };
+template <> struct PackOf<FAM_PLANE3D> { using T = EntP3p; };
+
+__device__ __host__ inline int32_t sext_field(uint32_t x, int pos, int bits) {
+  return (int32_t)(x << (32 - pos - bits)) >> (32 - bits);
+}
+__device__ __host__ inline EntP3p pack_p3(int32_t K1, int32_t K2, int32_t F, uint32_t w) {
+  EntP3p e;
+  e.lo = ((uint32_t)K1 & 0x1fffu) | (((uint32_t)K2 & 0x1fffu) << 13) | ((w & 0x3fu) << 26);
+  e.hi = ((uint32_t)F & 0xffffu) | ((w >> 6) << 16);
+  return e;
+}
 
 // round-half-to-even of x/2 for an integer x
 __device__ __host__ inline int32_t rne_half(int32_t x) {
@@ -161,31 +190,78 @@ template <int FAM> __device__ inline int Qax(const LinS& s, int qi) {
   return qi == 0 ? (t == 0 ? 1 : 0) : (t == 2 ? 1 : 2);
 }
 
-template <int FAM> __device__ inline LinS load_lin(const typename EntOf<FAM>::T& e) {
+template <int FAM> __device__ inline LinS lin_zero() {
   LinS s;
-  s.K[0][1] = s.K[1][0] = s.K[1][1] = 0;
-  s.F[1] = 0;
+  s.K[0][0] = s.K[0][1] = s.K[1][0] = s.K[1][1] = 0;
+  s.F[0] = s.F[1] = 0;
+  s.w = 0;
   s.tag = 0;
-  if constexpr (FAM == FAM_LINE2D) {
-    s.K[0][0] = e.K; s.F[0] = e.F; s.w = e.w;
-  } else if constexpr (FAM == FAM_PLANE3D) {
-    s.K[0][0] = e.K1; s.K[0][1] = e.K2; s.F[0] = e.F; s.w = e.w;
-  } else {
-    s.K[0][0] = e.K1; s.K[1][0] = e.K2; s.F[0] = e.F1; s.F[1] = e.F2; s.w = e.w; s.tag = e.tag;
-  }
   return s;
 }
 
-template <int FAM> __device__ inline typename EntOf<FAM>::T store_lin(const LinS& s) {
-  typename EntOf<FAM>::T e;
-  if constexpr (FAM == FAM_LINE2D) {
-    e.K = s.K[0][0]; e.F = s.F[0]; e.w = s.w; e._ = 0;
-  } else if constexpr (FAM == FAM_PLANE3D) {
-    e.K1 = s.K[0][0]; e.K2 = s.K[0][1]; e.F = s.F[0]; e.w = s.w;
-  } else {
-    e.K1 = s.K[0][0]; e.K2 = s.K[1][0]; e.F1 = s.F[0]; e.F2 = s.F[1]; e.w = s.w; e.tag = s.tag;
-  }
+// entry -> register state
+template <int FAM> __device__ inline LinS load_ent(const EntL2& e) {
+  LinS s = lin_zero<FAM>();
+  s.K[0][0] = e.K; s.F[0] = e.F; s.w = e.w;
+  return s;
+}
+template <int FAM> __device__ inline LinS load_ent(const EntP3& e) {
+  LinS s = lin_zero<FAM>();
+  s.K[0][0] = e.K1; s.K[0][1] = e.K2; s.F[0] = e.F; s.w = e.w;
+  return s;
+}
+template <int FAM> __device__ inline LinS load_ent(const EntR3& e) {
+  LinS s = lin_zero<FAM>();
+  s.K[0][0] = e.K1; s.K[1][0] = e.K2; s.F[0] = e.F1; s.F[1] = e.F2; s.w = e.w; s.tag = e.tag;
+  return s;
+}
+template <int FAM> __device__ inline LinS load_ent(const EntL2p& e) {
+  LinS s = lin_zero<FAM>();
+  s.K[0][0] = e.K; s.F[0] = e.F; s.w = (int32_t)e.w;
+  return s;
+}
+template <int FAM> __device__ inline LinS load_ent(const EntP3p& e) {
+  LinS s = lin_zero<FAM>();
+  s.K[0][0] = sext_field(e.lo, 0, 13);
+  s.K[0][1] = sext_field(e.lo, 13, 13);
+  s.F[0] = sext_field(e.hi, 0, 16);
+  s.w = (int32_t)(((e.hi >> 16) << 6) | (e.lo >> 26));
+  return s;
+}
+
+// register state -> entry; a packed store clears ok when a value does not fit
+template <int FAM, typename E> __device__ inline E store_ent(const LinS& s, bool& ok);
+template <> __device__ inline EntL2 store_ent<FAM_LINE2D, EntL2>(const LinS& s, bool&) {
+  EntL2 e;
+  e.K = s.K[0][0]; e.F = s.F[0]; e.w = s.w; e._ = 0;
   return e;
+}
+template <> __device__ inline EntP3 store_ent<FAM_PLANE3D, EntP3>(const LinS& s, bool&) {
+  EntP3 e;
+  e.K1 = s.K[0][0]; e.K2 = s.K[0][1]; e.F = s.F[0]; e.w = s.w;
+  return e;
+}
+template <> __device__ inline EntR3 store_ent<FAM_RAY3D, EntR3>(const LinS& s, bool&) {
+  EntR3 e;
+  e.K1 = s.K[0][0]; e.K2 = s.K[1][0]; e.F1 = s.F[0]; e.F2 = s.F[1]; e.w = s.w; e.tag = s.tag;
+  return e;
+}
+template <> __device__ inline EntL2p store_ent<FAM_LINE2D, EntL2p>(const LinS& s, bool& ok) {
+  ok = ok && abs(s.K[0][0]) <= GV_L2_MAX && abs(s.F[0]) <= GV_L2_MAX;
+  EntL2p e;
+  e.K = (int16_t)s.K[0][0]; e.F = (int16_t)s.F[0]; e.w = (uint32_t)s.w;
+  return e;
+}
+template <> __device__ inline EntP3p store_ent<FAM_PLANE3D, EntP3p>(const LinS& s, bool& ok) {
+  ok = ok && abs(s.K[0][0]) <= GV_P3_KMAX && abs(s.K[0][1]) <= GV_P3_KMAX && abs(s.F[0]) <= GV_P3_FMAX &&
+       (uint32_t)s.w <= GV_P3_WMAX;
+  return pack_p3(s.K[0][0], s.K[0][1], s.F[0], (uint32_t)s.w);
+}
+
+template <int FAM> __device__ inline LinS load_lin(const typename EntOf<FAM>::T& e) { return load_ent<FAM>(e); }
+template <int FAM> __device__ inline typename EntOf<FAM>::T store_lin(const LinS& s) {
+  bool ok = true;
+  return store_ent<FAM, typename EntOf<FAM>::T>(s, ok);
 }
 
 // per-lane selection from a small uniform array (avoids scratch indexing)

@@ -23,6 +23,11 @@ __device__ inline uint64_t wave_max_u64(uint64_t v) {
 }
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
 __device__ inline uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+// lane L of the result takes the wave-uniform value v (v_writelane; no memory access)
+template <int L> __device__ inline uint32_t write_lane(uint32_t old, uint32_t v) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(v), "n"(L));
+  return old;
+}
 __device__ inline uint32_t mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -39,114 +44,127 @@ __global__ void k_item_fill(const Cell* __restrict__ cells, uint32_t ncell, cons
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   uint32_t o = ioff[c], k = nitem[c];
-  for (uint32_t j = 0; j < k; j++) items[o + j] = Item{c, j * (uint32_t)GV_ITEM};
+  const uint64_t off = cells[c].off;
+  const uint32_t len = cells[c].len;
+  for (uint32_t j = 0; j < k; j++)
+    items[o + j] = Item{off + (uint64_t)j * GV_ITEM, c, min((uint32_t)GV_ITEM, len - j * (uint32_t)GV_ITEM)};
   if (c == ncell - 1) *total = o + k;
 }
 
 // ---------------------------------------------------------------------------
 // Linear families: incidence test of every (canonical surface, child) pair,
-// pass masks, weighted and unweighted per-child counts.
+// per-child counts, and the pass masks in transposed form: for every group
+// of 64 consecutive entries of an item and every child, the 64-bit wave
+// ballot of the entries that meet the child.  A cell at batch offset off
+// with index c stores its g-th group at off/64 + c + g (injective over a
+// batch; at most nent/64 + ncell + 1 groups).
 // ---------------------------------------------------------------------------
-// PLANE3D with all three axes splitting: the per-axis ranges K*{b, b+1} of
-// the two slopes are shared by the 8 children (digit = b_a1 b_a2 b_a0).
-__device__ inline uint32_t plane_mask_all(const LinS& s, const LevelC& lv) {
-  const int32_t K1 = s.K[0][0], K2 = s.K[0][1], F2 = 2 * s.F[0];
-  const int32_t a1 = imin32(K1, 0), c1 = imax32(K1, 0);
-  const int32_t a2 = imin32(K2, 0), c2 = imax32(K2, 0);
-  const int32_t H = lv.H[2], pad = lv.padu[2];
-  const int32_t lo0 = -pad, hi0 = H + pad, lo1 = H - pad, hi1 = 2 * H + pad;
-  uint32_t mask = 0;
-#pragma unroll
-  for (int b1 = 0; b1 < 2; b1++) {
-#pragma unroll
-    for (int b2 = 0; b2 < 2; b2++) {
-      const int32_t gmin = F2 + (b1 ? K1 + a1 : a1) + (b2 ? K2 + a2 : a2);
-      const int32_t gmax = F2 + (b1 ? K1 + c1 : c1) + (b2 ? K2 + c2 : c2);
-      const int d = (b1 << 2) | (b2 << 1);
-      mask |= (uint32_t)(gmax >= lo0 && gmin <= hi0) << d;
-      mask |= (uint32_t)(gmax >= lo1 && gmin <= hi1) << (d | 1);
-    }
-  }
-  return mask;
+__device__ inline uint64_t lin_group0(const Item& I) { return I.off / 64 + (uint64_t)I.cell; }
+
+__device__ inline uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
-template <int FAM> __device__ inline uint32_t lin_mask(const LinS& s, const LevelC& lv, uint32_t nch) {
-  if constexpr (FAM == FAM_PLANE3D) {
-    if (lv.abits == 3) return plane_mask_all(s, lv);
-  }
-  uint32_t mask = 0;
+// Pass predicates of one surface for the NCH children of its cell.
+// PLANE3D with all three axes splitting (digit = b_a1 b_a2 b_a0): with
+// c = max(K, 0), child (b1, b2, b0) is met iff
+//   0 <= u - b0 H <= H + 2 pad + |K1| + |K2|,  u = 2F + pad + c1 + c2 + b1 K1 + b2 K2,
+// which is the general test (the surface's range over the child reaches the
+// child's widened interval) with both bounds in one unsigned comparison.
+template <int FAM, int NCH>
+__device__ inline void lin_pass(const LinS& s, const LevelC& lv, bool (&p)[NCH]) {
+  if constexpr (FAM == FAM_PLANE3D && NCH == 8) {
+    const int32_t K1 = s.K[0][0], K2 = s.K[0][1], K12 = K1 + K2;
+    const int32_t H = lv.H[2], pad = lv.padu[2];
+    const int32_t S = imax32(K1, 0) + imax32(K2, 0);  // |K1| + |K2| = 2 S - K12
+    const int32_t u = 2 * s.F[0] + pad + S;
+    const uint32_t R = (uint32_t)(2 * S + (H + 2 * pad) - K12);
+    const int32_t uu[4] = {u, u + K2, u + K1, u + K12};  // (b1, b2) = 00, 01, 10, 11
 #pragma unroll
-  for (int ch = 0; ch < 8; ch++)
-    if ((uint32_t)ch < nch && lin_meets<FAM>(s, lv, lv.cbits[ch])) mask |= 1u << ch;
-  return mask;
+    for (int q = 0; q < 4; q++) {
+      p[2 * q] = (uint32_t)uu[q] <= R;
+      p[2 * q + 1] = (uint32_t)(uu[q] - H) <= R;
+    }
+  } else {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ch++) p[ch] = lin_meets<FAM>(s, lv, lv.cbits[ch]);
+  }
+}
+
+template <int N, int L = 0> __device__ inline void put_lanes(const uint64_t (&b)[N], uint32_t& lo, uint32_t& hi) {
+  if constexpr (L < N) {
+    lo = write_lane<L>(lo, (uint32_t)b[L]);
+    hi = write_lane<L>(hi, (uint32_t)(b[L] >> 32));
+    put_lanes<N, L + 1>(b, lo, hi);
+  }
 }
 
 // UNIT: every multiplicity is 1 (no merged surfaces), so a child's count is
-// the popcount of the wave's ballot, accumulated in scalar registers.
-template <int FAM, bool UNIT>
+// the popcount of its ballot, accumulated in scalar registers.
+template <int FAM, bool UNIT, typename E, int NCH>
 __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Cell* __restrict__ cells,
                                                    const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
-                                                   const typename EntOf<FAM>::T* __restrict__ ents,
-                                                   uint8_t* __restrict__ masks, uint32_t* __restrict__ ccnt,
-                                                   uint32_t* __restrict__ cnent, uint32_t* __restrict__ itemcnt,
-                                                   uint32_t istride) {
-  const uint32_t nch = 1u << lv.abits;
+                                                   const E* __restrict__ ents, uint64_t* __restrict__ lm,
+                                                   uint32_t* __restrict__ ccnt, uint32_t* __restrict__ cnent,
+                                                   uint32_t* __restrict__ itemcnt, uint32_t istride) {
+  // entries per lane in flight: a whole item for 8-byte entries
+  constexpr int NB = sizeof(E) <= 8 ? 16 : (sizeof(E) <= 16 ? 8 : 4);
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t nitems = *nitems_p;
+  Item I = wave < nitems ? items[wave] : Item{};
   for (uint32_t it = wave; it < nitems; it += nwaves) {
-    const Item I = items[it];
-    const Cell C = cells[I.cell];
-    const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
-    uint32_t aw[8], an[8];
+    const Item In = it + nwaves < nitems ? items[it + nwaves] : Item{};  // next item, fetched early
+    const uint32_t cnt = I.cnt;
+    const uint64_t g0 = lin_group0(I);
+    uint32_t aw[NCH], an[NCH];
 #pragma unroll
-    for (int ch = 0; ch < 8; ch++) { aw[ch] = 0; an[ch] = 0; }
-    // four entries per lane in flight
-    for (uint32_t k0 = 0; k0 < cnt; k0 += 256) {
-      typename EntOf<FAM>::T ev[4];
+    for (int ch = 0; ch < NCH; ch++) { aw[ch] = 0; an[ch] = 0; }
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * NB) {
+      E ev[NB];
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
+      for (int j = 0; j < NB; j++) {
         const uint32_t k = k0 + 64 * j + lane;
-        if (k < cnt) ev[j] = ents[C.off + I.start + k];
+        ev[j] = E{};
+        if (k < cnt) ev[j] = ents[I.off + k];
       }
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const uint32_t k = k0 + 64 * j + lane;
-        const bool valid = k < cnt;
-        const LinS s = load_lin<FAM>(ev[j]);
-        const uint32_t mask = valid ? lin_mask<FAM>(s, lv, nch) : 0u;
-        if (valid) masks[C.off + I.start + k] = (uint8_t)mask;
+      for (int j = 0; j < NB; j++) {
+        if (k0 + 64 * j >= cnt) break;
+        const uint32_t rem = cnt - (k0 + 64 * j);
+        const uint64_t vm = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);  // lanes holding an entry
+        const LinS s = load_ent<FAM>(ev[j]);
+        bool p[NCH];
+        lin_pass<FAM, NCH>(s, lv, p);
+        uint64_t b[NCH];
 #pragma unroll
-        for (int ch = 0; ch < 8; ch++) {
-          if ((uint32_t)ch >= nch) break;
-          if constexpr (UNIT) {
-            an[ch] += (uint32_t)__popcll(__ballot((mask >> ch) & 1u));
-          } else {
-            const uint32_t p = (mask >> ch) & 1u;
-            aw[ch] += p ? (uint32_t)s.w : 0u;
-            an[ch] += p;
-          }
+        for (int ch = 0; ch < NCH; ch++) {
+          b[ch] = __builtin_amdgcn_ballot_w64(p[ch]) & vm;
+          an[ch] += (uint32_t)__popcll(b[ch]);
+          if constexpr (!UNIT) aw[ch] += p[ch] ? (uint32_t)s.w : 0u;  // an empty lane's weight is 0
+        }
+        if (lm) {
+          // lane ch of (wlo, whi) receives child ch's ballot
+          uint32_t wlo = 0, whi = 0;
+          put_lanes<NCH>(b, wlo, whi);
+          if (lane < (uint32_t)NCH) lm[(g0 + (k0 + 64 * j) / 64) * NCH + lane] = (uint64_t)wlo | ((uint64_t)whi << 32);
         }
       }
     }
 #pragma unroll
-    for (int ch = 0; ch < 8; ch++) {
-      if ((uint32_t)ch >= nch) break;
-      uint32_t w, n;
-      if constexpr (UNIT) {
-        n = an[ch];
-        w = n;
-      } else {
-        w = wave_sum_u32(aw[ch]);
-        n = wave_sum_u32(an[ch]);
-      }
+    for (int ch = 0; ch < NCH; ch++) {
+      const uint32_t n = an[ch];
+      const uint32_t w = UNIT ? n : wave_sum_u32(aw[ch]);
       if (lane == 0 && n) {
-        atomicAdd(&ccnt[I.cell * nch + ch], w);
-        atomicAdd(&cnent[I.cell * nch + ch], n);
+        atomicAdd(&ccnt[I.cell * NCH + ch], w);
+        atomicAdd(&cnent[I.cell * NCH + ch], n);
         if (istride) itemcnt[(uint64_t)ch * istride + it] = n;
       }
     }
+    I = In;
   }
 }
 
@@ -297,7 +315,7 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pt
     const Item I = items[it];
     const Cell C = cells[I.cell];
     const ProbC& P = Ptab[C.prob];
-    const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
+    const uint32_t cnt = I.cnt;
     const int sector = (int)C.sector;
     PoseLevel B;
     pose_level_boxes(P, lv, C, m, B);
@@ -312,7 +330,7 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pt
 #pragma unroll
     for (int ch = 0; ch < 16; ch++) { aw[ch] = 0; an[ch] = 0; }
     for (uint32_t k = lane; k < cnt; k += 64) {
-      const uint64_t ei = C.off + I.start + k;
+      const uint64_t ei = I.off + k;
       const E e = ents[ei];
       uint32_t mask;
       if constexpr (sizeof(E) == sizeof(EntQ64)) {
@@ -482,7 +500,8 @@ __global__ void k_chunk_totals(const uint32_t* keepc, const uint32_t* cidx, cons
 // compaction pass must read
 __global__ void k_chunk_reads(const Cell* __restrict__ cells, uint32_t ncell, uint32_t nch,
                               const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
-                              const uint32_t* __restrict__ keepc, unsigned long long* __restrict__ acc) {
+                              const uint32_t* __restrict__ keepc, uint32_t bits_per_entry,
+                              unsigned long long* __restrict__ acc) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t v = 0;
   if (c < ncell) {
@@ -491,7 +510,7 @@ __global__ void k_chunk_reads(const Cell* __restrict__ cells, uint32_t ncell, ui
       const uint32_t r = rank_of[(uint64_t)c * nch + ch];
       hit = hit || (r >= r0 && r < r1 && keepc[r - r0]);
     }
-    v = hit ? cells[c].len : 0;
+    v = hit ? (uint64_t)cells[c].len * bits_per_entry : 0;
   }
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   if ((threadIdx.x & 63u) == 0 && v) atomicAdd(acc, (unsigned long long)v);
@@ -527,14 +546,86 @@ __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const u
 // their exclusive scan (itemoff, child-major) gives each item's offset inside
 // the child's list; within an item, a wavefront ballot ranks the lanes.
 // ---------------------------------------------------------------------------
-template <int FAM, typename E, typename M, bool POSE>
+// Linear-family compaction reads the transposed pass masks of the count
+// pass: per 64-entry group, one uniform word per child gives the lanes to
+// write and, by its bit count below the lane, their order.
+template <int FAM, typename E, typename EO, int NCH>
+__global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const Cell* __restrict__ cells,
+                                                     const Item* __restrict__ items,
+                                                     const uint32_t* __restrict__ nitems_p,
+                                                     const uint32_t* __restrict__ ioff,
+                                                     const uint64_t* __restrict__ itemoff, uint32_t istride,
+                                                     const E* __restrict__ ents, const uint64_t* __restrict__ lm,
+                                                     const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
+                                                     const uint32_t* __restrict__ keepc,
+                                                     const uint64_t* __restrict__ coff, EO* __restrict__ out,
+                                                     int* __restrict__ ovf) {
+  constexpr int GJ = 4;  // 64-entry groups per round trip: their words (one lane each) and entries load together
+  static_assert(GJ * NCH <= 64, "one lane per (group, child) word");
+  bool fits = true;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t nitems = *nitems_p;
+  for (uint32_t it = wave; it < nitems; it += nwaves) {
+    const Item I = items[it];
+    uint32_t kmask = 0;
+    uint64_t wpos[NCH];
+    const uint32_t first = ioff[I.cell];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ch++) {
+      wpos[ch] = 0;
+      const uint32_t r = rank_of[(uint64_t)I.cell * NCH + ch];
+      if (r >= r0 && r < r1 && keepc[r - r0]) {
+        kmask |= 1u << ch;
+        wpos[ch] = coff[r - r0] + (itemoff[(uint64_t)ch * istride + it] - itemoff[(uint64_t)ch * istride + first]);
+      }
+    }
+    kmask = uniform_u32(kmask);
+    if (!kmask) continue;
+    const uint32_t cnt = I.cnt;
+    const uint64_t g0 = lin_group0(I);
+    const uint32_t lj = lane / NCH, lch = lane % NCH;
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * GJ) {
+      uint64_t mw = 0;  // lane j*NCH + ch: the word of group j, child ch
+      if (lj < (uint32_t)GJ && k0 + 64 * lj < cnt && ((kmask >> lch) & 1u)) mw = lm[(g0 + k0 / 64 + lj) * NCH + lch];
+      E ev[GJ];
+#pragma unroll
+      for (int j = 0; j < GJ; j++) {
+        const uint32_t k = k0 + 64 * j + lane;
+        ev[j] = E{};
+        if (k < cnt) ev[j] = ents[I.off + k];
+      }
+#pragma unroll
+      for (int j = 0; j < GJ; j++) {
+        if (k0 + 64 * j >= cnt) break;
+        const LinS s = load_ent<FAM>(ev[j]);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ch++) {
+          if (!((kmask >> ch) & 1u)) continue;
+          const uint64_t b = readlane64(mw, j * NCH + ch);
+          if ((b >> lane) & 1ull)
+            out[wpos[ch] + mbcnt64(b)] = store_ent<FAM, EO>(lin_canon_child<FAM>(s, lv, lv.cbits[ch]), fits);
+          wpos[ch] += (uint64_t)__popcll(b);
+        }
+      }
+    }
+  }
+  if (!fits) atomicOr(ovf, 1);
+}
+
+// Linear families re-encode on the way (the child list may use the packed
+// entry); a value that does not fit its encoding sets *ovf.
+template <int FAM, typename E, typename EO, typename M, bool POSE>
 __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restrict__ cells,
                                                  const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
                                                  const uint32_t* __restrict__ ioff, const uint64_t* __restrict__ itemoff,
                                                  uint32_t istride, const E* __restrict__ ents,
                                                  const M* __restrict__ masks, const uint32_t* __restrict__ rank_of,
                                                  uint32_t r0, uint32_t r1, const uint32_t* __restrict__ keepc,
-                                                 const uint64_t* __restrict__ coff, E* __restrict__ out) {
+                                                 const uint64_t* __restrict__ coff, EO* __restrict__ out,
+                                                 int* __restrict__ ovf) {
+  bool fits = true;
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -557,12 +648,11 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
     }
     kmask = uniform_u32(kmask);
     if (!kmask) continue;
-    const Cell C = cells[I.cell];
-    const uint32_t cnt = min((uint32_t)GV_ITEM, C.len - I.start);
+    const uint32_t cnt = I.cnt;
     for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
       const uint32_t k = k0 + lane;
       const bool valid = k < cnt;
-      const uint64_t ei = C.off + I.start + k;
+      const uint64_t ei = I.off + k;
       uint32_t mask = 0;
       E e;
       if (valid) {
@@ -579,13 +669,14 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
           if constexpr (POSE) {
             out[pos] = e;
           } else {
-            out[pos] = store_lin<FAM>(lin_canon_child<FAM>(load_lin<FAM>(e), lv, lv.cbits[ch]));
+            out[pos] = store_ent<FAM, EO>(lin_canon_child<FAM>(load_ent<FAM>(e), lv, lv.cbits[ch]), fits);
           }
         }
         wpos[ch] += (uint64_t)__popcll(bal);
       }
     }
   }
+  if (!fits) atomicOr(ovf, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -619,6 +710,27 @@ template <> struct Tuple<EntP3> {
   __device__ static bool same(const EntP3& a, const EntP3& b) { return a.K1 == b.K1 && a.K2 == b.K2 && a.F == b.F; }
   __device__ static void setw(EntP3& e, uint32_t w) { e.w = (int32_t)w; }
   __device__ static uint32_t w(const EntP3& e) { return (uint32_t)e.w; }
+};
+template <> struct Tuple<EntL2p> {
+  __device__ static uint64_t hash(const EntL2p& e) {
+    return hcomb(hcomb(6, (uint32_t)(int32_t)e.K), (uint32_t)(int32_t)e.F);
+  }
+  __device__ static bool same(const EntL2p& a, const EntL2p& b) { return a.K == b.K && a.F == b.F; }
+  __device__ static void setw(EntL2p& e, uint32_t w) { e.w = w; }
+  __device__ static uint32_t w(const EntL2p& e) { return e.w; }
+};
+// a merged PLANE3D weight never exceeds the problem size, below the 22-bit
+// limit whenever packed entries are used
+template <> struct Tuple<EntP3p> {
+  __device__ static uint64_t hash(const EntP3p& e) { return hcomb(hcomb(7, e.lo & 0x3ffffffu), e.hi & 0xffffu); }
+  __device__ static bool same(const EntP3p& a, const EntP3p& b) {
+    return (a.lo & 0x3ffffffu) == (b.lo & 0x3ffffffu) && (a.hi & 0xffffu) == (b.hi & 0xffffu);
+  }
+  __device__ static void setw(EntP3p& e, uint32_t w) {
+    e.lo = (e.lo & 0x3ffffffu) | ((w & 0x3fu) << 26);
+    e.hi = (e.hi & 0xffffu) | ((w >> 6) << 16);
+  }
+  __device__ static uint32_t w(const EntP3p& e) { return ((e.hi >> 16) << 6) | (e.lo >> 26); }
 };
 template <> struct Tuple<EntR3> {
   __device__ static uint64_t hash(const EntR3& e) {

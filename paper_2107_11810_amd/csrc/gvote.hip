@@ -126,6 +126,8 @@ struct gv_ctx {
   // round-robin (each problem needs its own first-descent beam), so by
   // default every epoch holds one problem.
   uint64_t batch_n = 0;
+  // packed 8-byte list entries where the lattice bounds allow (GV_PACK=0 off)
+  bool pack = true;
 };
 
 namespace gvi {
@@ -398,7 +400,9 @@ struct Run {
   unsigned long long* drecheck = nullptr;
   uint64_t* dtot = nullptr;
   uint32_t* dummy = nullptr;              // sink for outputs a leaf-level pass does not need
-  unsigned long long* dreads = nullptr;   // parent entries read by compaction passes
+  unsigned long long* dreads = nullptr;   // parent bytes read by compaction passes
+  int* dovf = nullptr;                    // set when a packed entry could not hold a value
+  int pack_from = 1 << 30;                // lists of this level and deeper use the packed entry
   size_t ent_bytes = 0;
   uint64_t budget_entries = 0;            // max entries of one materialized chunk
   uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
@@ -593,7 +597,12 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   uint32_t* itemcnt = leaf ? nullptr : dalloc<uint32_t>(X, (uint64_t)nch * pa->istride);
   if (itemcnt) HIPCHK(hipMemsetAsync(itemcnt, 0, (uint64_t)nch * pa->istride * sizeof(uint32_t), X.st));
 
-  pa->masks = dalloc<M>(X, b.nent);
+  // linear families: transposed 64-bit pass words per (64-entry group, child)
+  const bool linear = FAM != FAM_POSE4DOF;
+  if (linear)
+    pa->masks = leaf ? nullptr : dalloc<uint64_t>(X, (b.nent / 64 + b.ncell + 1) * nch);  // no compaction after a leaf pass
+  else
+    pa->masks = dalloc<M>(X, b.nent);
   uint32_t* ccnt = dalloc<uint32_t>(X, nk);
   pa->cnent = dalloc<uint32_t>(X, nk);
   HIPCHK(hipMemsetAsync(ccnt, 0, nk * sizeof(uint32_t), X.st));
@@ -601,20 +610,28 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
   auto evp = ev_begin(X, 0);
   X.stats.test_launches++;
-  X.stats.test_bytes += b.nent * (sizeof(E) + sizeof(M));
+  X.stats.test_bytes += linear ? b.nent * sizeof(E) + (leaf ? 0 : b.nent * nch / 8) : b.nent * (sizeof(E) + sizeof(M));
   if constexpr (FAM == FAM_POSE4DOF) {
     k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, X.m64,
                                              X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck,
                                              itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
   } else {
-    if (b.unit)
-      k_count_lin<FAM, true><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
-                                                      (uint8_t*)pa->masks, ccnt, pa->cnent,
-                                                      itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
-    else
-      k_count_lin<FAM, false><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
-                                                       (uint8_t*)pa->masks, ccnt, pa->cnent,
-                                                       itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
+    uint32_t* ic = itemcnt ? itemcnt : X.dummy;
+    const uint32_t is = itemcnt ? pa->istride : 0u;
+    uint64_t* lm = (uint64_t*)pa->masks;
+#define GV_COUNT_LIN(U, N) \
+  k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, lm, ccnt, \
+                                                    pa->cnent, ic, is)
+    switch ((b.unit ? 16 : 0) | nch) {
+      case 16 | 2: GV_COUNT_LIN(true, 2); break;
+      case 16 | 4: GV_COUNT_LIN(true, 4); break;
+      case 16 | 8: GV_COUNT_LIN(true, 8); break;
+      case 2: GV_COUNT_LIN(false, 2); break;
+      case 4: GV_COUNT_LIN(false, 4); break;
+      case 8: GV_COUNT_LIN(false, 8); break;
+      default: throw DevErr{GV_EINVAL};
+    }
+#undef GV_COUNT_LIN
   }
   ev_end(X, evp);
   HIPCHK(hipGetLastError());
@@ -645,9 +662,9 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   X.stats.cells_pruned += nk - nkept;
   if (X.trace) {
     const uint64_t bst = d2h1(X, X.dbest);
-    std::fprintf(stderr, "gv: level %d cells %u entries %llu kept %llu best %llu%s\n", m, b.ncell,
+    std::fprintf(stderr, "gv: level %d cells %u entries %llu kept %llu best %llu%s%s\n", m, b.ncell,
                  (unsigned long long)b.nent, (unsigned long long)nkept, (unsigned long long)(bst >> P.B),
-                 dive ? " (dive)" : "");
+                 dive ? " (dive)" : "", m >= X.pack_from ? " packed" : "");
   }
   if (nkept == 0) {
     dfree(X, keepf);
@@ -740,7 +757,7 @@ void plan_chunks(Run& X, Parent* pa, std::vector<std::pair<uint32_t, uint32_t>>&
 
 // Materialize one chunk [r0, r1) of a parent as a new batch (after cutting it
 // against the current best).  Returns false when nothing remains.
-template <int FAM, typename E, typename M>
+template <int FAM, typename E, typename EO, typename M>
 bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   const ProbC& P = X.P0;
   const LevelC lv = P.lev[pa->level];
@@ -766,19 +783,35 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     nb.ncell = (uint32_t)tot[0];
     nb.nent = tot[1];
     nb.cells = dalloc<Cell>(X, nb.ncell);
-    nb.ents = dalloc<E>(X, nb.nent);
+    nb.ents = dalloc<EO>(X, nb.nent);
     k_emit_ranked<<<nblk(nr), 256, 0, X.st>>>(lv, pa->cells, pa->order, r0, r1, keepc, cidx, coff, pa->cnent,
                                               nb.cells);
     const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
     auto evp = ev_begin(X, 1);
     X.stats.compact_launches++;
-    X.stats.compact_bytes += nb.nent * sizeof(E);
+    X.stats.compact_bytes += nb.nent * sizeof(EO);
+    const bool linear = FAM != FAM_POSE4DOF;
     if (X.ctx->kernel_timing)
-      k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(pa->cells, pa->ncell, nch, pa->rank_of, r0, r1, keepc,
-                                                       X.dreads);
-    k_compact<FAM, E, M, FAM == FAM_POSE4DOF><<<grid, 256, 0, X.st>>>(
-        lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, (const E*)pa->ents,
-        (const M*)pa->masks, pa->rank_of, r0, r1, keepc, coff, (E*)nb.ents);
+      k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(
+          pa->cells, pa->ncell, nch, pa->rank_of, r0, r1, keepc,
+          (uint32_t)(linear ? 8 * sizeof(E) + nch : 8 * (sizeof(E) + sizeof(M))), X.dreads);
+    if constexpr (FAM == FAM_POSE4DOF) {
+      k_compact<FAM, E, EO, M, true><<<grid, 256, 0, X.st>>>(
+          lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, (const E*)pa->ents,
+          (const M*)pa->masks, pa->rank_of, r0, r1, keepc, coff, (EO*)nb.ents, X.dovf);
+    } else {
+#define GV_COMPACT_LIN(N)                                                                                        \
+  k_compact_lin<FAM, E, EO, N><<<grid, 256, 0, X.st>>>(lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, \
+                                                       pa->istride, (const E*)pa->ents, (const uint64_t*)pa->masks, \
+                                                       pa->rank_of, r0, r1, keepc, coff, (EO*)nb.ents, X.dovf)
+      switch (nch) {
+        case 2: GV_COMPACT_LIN(2); break;
+        case 4: GV_COMPACT_LIN(4); break;
+        case 8: GV_COMPACT_LIN(8); break;
+        default: throw DevErr{GV_EINVAL};
+      }
+#undef GV_COMPACT_LIN
+    }
     ev_end(X, evp);
     HIPCHK(hipGetLastError());
     nb.unit = pa->unit;
@@ -789,8 +822,27 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   dfree(X, csize);
   dfree(X, coff);
   if (--pa->pending == 0) free_parent(X, pa);
-  if (made && want_group(X, nb)) group_batch<E>(X, nb, true);
+  if (made && want_group(X, nb)) group_batch<EO>(X, nb, true);
   return made;
+}
+
+// Entry type of a level's lists: the packed entry from pack_from on.
+template <int FAM, typename E>
+using PackedT = std::conditional_t<FAM == FAM_POSE4DOF || std::is_void_v<typename PackOf<FAM>::T>, E,
+                                   typename PackOf<FAM>::T>;
+
+template <int FAM, typename E, typename M>
+Parent* expand_at(Run& X, Batch& b, bool own_ents, bool dive) {
+  if (b.level >= X.pack_from) return expand<FAM, PackedT<FAM, E>, M>(X, b, own_ents, dive);
+  return expand<FAM, E, M>(X, b, own_ents, dive);
+}
+
+template <int FAM, typename E, typename M>
+bool materialize_at(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
+  using EP = PackedT<FAM, E>;
+  if (pa->level >= X.pack_from) return materialize<FAM, EP, EP, M>(X, pa, r0, r1, nb);
+  if (pa->level + 1 >= X.pack_from) return materialize<FAM, E, EP, M>(X, pa, r0, r1, nb);
+  return materialize<FAM, E, E, M>(X, pa, r0, r1, nb);
 }
 
 template <int FAM, typename E, typename M>
@@ -892,10 +944,13 @@ void epoch_begin(Run& X) {
   X.dtot = dalloc<uint64_t>(X, 2);
   X.dummy = dalloc<uint32_t>(X, 64);
   X.dreads = dalloc<unsigned long long>(X, 1);
+  X.dovf = dalloc<int>(X, 1);
+  X.pack_from = 1 << 30;
   X.dooff = dalloc<uint64_t>(X, np + 1);
   HIPCHK(hipMemsetAsync(X.dbest, 0, np * 8, X.st));
   HIPCHK(hipMemsetAsync(X.drecheck, 0, 8, X.st));
   HIPCHK(hipMemsetAsync(X.dreads, 0, 8, X.st));
+  HIPCHK(hipMemsetAsync(X.dovf, 0, sizeof(int), X.st));
   HIPCHK(hipMemcpyAsync(X.dooff, X.ooff.data(), (np + 1) * 8, hipMemcpyHostToDevice, X.st));
   std::vector<ProbC> tab(np);
   for (uint32_t p = 0; p < np; p++) tab[p] = X.probs[p]->S.P;
@@ -990,10 +1045,10 @@ void start_search(Run& X) {
     b.ents = ents;
     bool own = false;
     while (true) {
-      Parent* pa = expand<FAM, E, M>(X, b, own, true);
+      Parent* pa = expand_at<FAM, E, M>(X, b, own, true);
       if (!pa) break;
       pa->pending = 1;
-      if (!materialize<FAM, E, M>(X, pa, 0, pa->nkept, b)) break;
+      if (!materialize_at<FAM, E, M>(X, pa, 0, pa->nkept, b)) break;
       own = true;
     }
   }
@@ -1017,11 +1072,11 @@ bool epoch_step(Run& X) {
   X.stack.pop_back();
   Batch b;
   if (t.chunk) {
-    if (!materialize<FAM, E, M>(X, t.par, t.r0, t.r1, b)) return !X.stack.empty();
+    if (!materialize_at<FAM, E, M>(X, t.par, t.r0, t.r1, b)) return !X.stack.empty();
   } else {
     b = t.b;
   }
-  Parent* pa = expand<FAM, E, M>(X, b, true, false);
+  Parent* pa = expand_at<FAM, E, M>(X, b, true, false);
   if (pa) push_children<FAM, E, M>(X, pa, X.stack);
   return !X.stack.empty();
 }
@@ -1093,6 +1148,27 @@ void build_linear(Run& X) {
       D *= (Hm + (double)P.lev[m - 1].padu[q] + 4.0 * ks + 2.0) * kprod;
     }
     X.lat_bound[m] = D;
+  }
+  // first level from which every list value fits the packed entry: slopes
+  // as above, heights within the cell plus its pads plus the slope spans
+  uint64_t nmax = 0;
+  for (ProbRec* pr : X.probs) nmax = std::max<uint64_t>(nmax, (uint64_t)pr->n);
+  X.pack_from = 1 << 30;
+  if (X.ctx->pack && (FAM == FAM_LINE2D || (FAM == FAM_PLANE3D && nmax <= GV_P3_WMAX))) {
+    const int q = (FAM == FAM_LINE2D) ? 1 : 2;
+    const double kmax = (FAM == FAM_LINE2D) ? GV_L2_MAX : GV_P3_KMAX;
+    const double fmax = (FAM == FAM_LINE2D) ? GV_L2_MAX : GV_P3_FMAX;
+    for (int m = P.Lstar - 1; m >= 1; m--) {
+      double kb = 0.0, ks = 0.0;
+      for (int pi = 0; pi < ((FAM == FAM_PLANE3D) ? 2 : 1); pi++) {
+        const double km = std::ceil((double)mk_all / std::ldexp(1.0, std::min(m, P.L[pi]))) + 1.0;
+        kb = std::max(kb, km);
+        ks += km;
+      }
+      const double fb = (double)P.lev[m].H[q] + (double)P.lev[m - 1].padu[q] + 2.0 * ks + 4.0;
+      if (kb > kmax || fb > fmax) break;
+      X.pack_from = m;
+    }
   }
   X.root = root;
   start_search<FAM, E, uint8_t>(X);
@@ -1172,9 +1248,17 @@ void epoch_finish(Run& X) {
   const ProbC& P = X.P0;
   std::vector<unsigned long long> best(np);
   unsigned long long rech = 0;
+  int ovf = 0;
   HIPCHK(hipMemcpyAsync(best.data(), X.dbest, np * 8, hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipMemcpyAsync(&rech, X.drecheck, 8, hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipMemcpyAsync(&ovf, X.dovf, sizeof(int), hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipStreamSynchronize(X.st));
+  if (ovf)
+    for (ProbRec* pr : X.probs)
+      if (pr->st == GV_OK) {
+        pr->st = GV_ERANGE;
+        pr->err = "internal: a lattice value outgrew its packed list entry";
+      }
   std::vector<PathC> paths(np);
   std::vector<Cols> ctab(np);
   for (uint32_t p = 0; p < np; p++) {
@@ -1235,7 +1319,7 @@ void epoch_finish(Run& X) {
     HIPCHK(hipEventElapsedTime(&ms, e.first.first, e.first.second));
     (e.second == 0 ? X.stats.test_ms : X.stats.compact_ms) += (double)ms;
   }
-  if (X.ctx->kernel_timing) X.stats.compact_bytes += d2h1(X, X.dreads) * X.ent_bytes;
+  if (X.ctx->kernel_timing) X.stats.compact_bytes += d2h1(X, X.dreads) / 8;
   X.stats.fp64_rechecks = rech;
   X.stats.levels = (uint32_t)P.Lstar;
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - X.t0).count();
@@ -1285,6 +1369,7 @@ void epoch_release(Run& X) {
   dfree(X, X.dtot);
   dfree(X, X.dummy);
   dfree(X, X.dreads);
+  dfree(X, X.dovf);
   dfree(X, X.dooff);
   X.dP = nullptr;
   X.dbest = nullptr;
@@ -1292,6 +1377,7 @@ void epoch_release(Run& X) {
   X.dtot = nullptr;
   X.dummy = nullptr;
   X.dreads = nullptr;
+  X.dovf = nullptr;
   X.dooff = nullptr;
 }
 
@@ -1522,6 +1608,7 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
   if (const char* e = std::getenv("GV_MAX_EPOCHS")) c->max_epochs = std::max(1, atoi(e));
   if (const char* e = std::getenv("GV_MAX_BATCH")) c->max_batch = (size_t)std::max(1, atoi(e));
   if (const char* e = std::getenv("GV_BATCH_N")) c->batch_n = std::strtoull(e, nullptr, 10);
+  if (const char* e = std::getenv("GV_PACK")) c->pack = atoi(e) != 0;
   *out = c;
   return GV_OK;
 }
