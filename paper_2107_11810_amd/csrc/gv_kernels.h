@@ -23,11 +23,6 @@ __device__ inline uint64_t wave_max_u64(uint64_t v) {
 }
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
 __device__ inline uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-// lane L of the result takes the wave-uniform value v (v_writelane; no memory access)
-template <int L> __device__ inline uint32_t write_lane(uint32_t old, uint32_t v) {
-  asm("v_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(v), "n"(L));
-  return old;
-}
 __device__ inline uint32_t mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -52,20 +47,12 @@ __global__ void k_item_fill(const Cell* __restrict__ cells, uint32_t ncell, cons
 }
 
 // ---------------------------------------------------------------------------
-// Linear families: incidence test of every (canonical surface, child) pair,
-// per-child counts, and the pass masks in transposed form: for every group
-// of 64 consecutive entries of an item and every child, the 64-bit wave
-// ballot of the entries that meet the child.  A cell at batch offset off
-// with index c stores its g-th group at off/64 + c + g (injective over a
-// batch; at most nent/64 + ncell + 1 groups).
+// Linear families: incidence test of every (canonical surface, child) pair
+// and per-child counts.  No pass masks are stored: the compaction pass reads
+// every entry anyway and repeats the (cheap, integer) test.
 // ---------------------------------------------------------------------------
-__device__ inline uint64_t lin_group0(const Item& I) { return I.off / 64 + (uint64_t)I.cell; }
-
-__device__ inline uint64_t readlane64(uint64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-  return (uint64_t)lo | ((uint64_t)hi << 32);
-}
+// a height no child interval reaches: lanes without an entry fail every test
+#define GV_F_NONE (1 << 27)
 
 // Pass predicates of one surface for the NCH children of its cell.
 // PLANE3D with all three axes splitting (digit = b_a1 b_a2 b_a0): with
@@ -93,20 +80,11 @@ __device__ inline void lin_pass(const LinS& s, const LevelC& lv, bool (&p)[NCH])
   }
 }
 
-template <int N, int L = 0> __device__ inline void put_lanes(const uint64_t (&b)[N], uint32_t& lo, uint32_t& hi) {
-  if constexpr (L < N) {
-    lo = write_lane<L>(lo, (uint32_t)b[L]);
-    hi = write_lane<L>(hi, (uint32_t)(b[L] >> 32));
-    put_lanes<N, L + 1>(b, lo, hi);
-  }
-}
-
 // UNIT: every multiplicity is 1 (no merged surfaces), so a child's count is
 // the popcount of its ballot, accumulated in scalar registers.
 template <int FAM, bool UNIT, typename E, int NCH>
-__global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Cell* __restrict__ cells,
-                                                   const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
-                                                   const E* __restrict__ ents, uint64_t* __restrict__ lm,
+__global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Item* __restrict__ items,
+                                                   const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
                                                    uint32_t* __restrict__ ccnt, uint32_t* __restrict__ cnent,
                                                    uint32_t* __restrict__ itemcnt, uint32_t istride) {
   // entries per lane in flight: a whole item for 8-byte entries
@@ -119,7 +97,6 @@ __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Cell* __rest
   for (uint32_t it = wave; it < nitems; it += nwaves) {
     const Item In = it + nwaves < nitems ? items[it + nwaves] : Item{};  // next item, fetched early
     const uint32_t cnt = I.cnt;
-    const uint64_t g0 = lin_group0(I);
     uint32_t aw[NCH], an[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ch++) { aw[ch] = 0; an[ch] = 0; }
@@ -134,23 +111,14 @@ __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Cell* __rest
 #pragma unroll
       for (int j = 0; j < NB; j++) {
         if (k0 + 64 * j >= cnt) break;
-        const uint32_t rem = cnt - (k0 + 64 * j);
-        const uint64_t vm = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);  // lanes holding an entry
-        const LinS s = load_ent<FAM>(ev[j]);
+        LinS s = load_ent<FAM>(ev[j]);
+        if (k0 + 64 * j + lane >= cnt) s.F[0] = s.F[1] = GV_F_NONE;
         bool p[NCH];
         lin_pass<FAM, NCH>(s, lv, p);
-        uint64_t b[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ch++) {
-          b[ch] = __builtin_amdgcn_ballot_w64(p[ch]) & vm;
-          an[ch] += (uint32_t)__popcll(b[ch]);
-          if constexpr (!UNIT) aw[ch] += p[ch] ? (uint32_t)s.w : 0u;  // an empty lane's weight is 0
-        }
-        if (lm) {
-          // lane ch of (wlo, whi) receives child ch's ballot
-          uint32_t wlo = 0, whi = 0;
-          put_lanes<NCH>(b, wlo, whi);
-          if (lane < (uint32_t)NCH) lm[(g0 + (k0 + 64 * j) / 64) * NCH + lane] = (uint64_t)wlo | ((uint64_t)whi << 32);
+          an[ch] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p[ch]));
+          if constexpr (!UNIT) aw[ch] += p[ch] ? (uint32_t)s.w : 0u;
         }
       }
     }
@@ -546,22 +514,21 @@ __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const u
 // their exclusive scan (itemoff, child-major) gives each item's offset inside
 // the child's list; within an item, a wavefront ballot ranks the lanes.
 // ---------------------------------------------------------------------------
-// Linear-family compaction reads the transposed pass masks of the count
-// pass: per 64-entry group, one uniform word per child gives the lanes to
-// write and, by its bit count below the lane, their order.
+// Linear-family compaction: every entry of an item with a child in the
+// chunk is re-tested; a child's ballot gives the lanes to write and, by its
+// bit count below the lane, their order.  The child list may use the packed
+// entry; a value that does not fit sets *ovf.
 template <int FAM, typename E, typename EO, int NCH>
-__global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const Cell* __restrict__ cells,
-                                                     const Item* __restrict__ items,
+__global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const Item* __restrict__ items,
                                                      const uint32_t* __restrict__ nitems_p,
                                                      const uint32_t* __restrict__ ioff,
                                                      const uint64_t* __restrict__ itemoff, uint32_t istride,
-                                                     const E* __restrict__ ents, const uint64_t* __restrict__ lm,
+                                                     const E* __restrict__ ents,
                                                      const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
                                                      const uint32_t* __restrict__ keepc,
                                                      const uint64_t* __restrict__ coff, EO* __restrict__ out,
                                                      int* __restrict__ ovf) {
-  constexpr int GJ = 4;  // 64-entry groups per round trip: their words (one lane each) and entries load together
-  static_assert(GJ * NCH <= 64, "one lane per (group, child) word");
+  constexpr int GJ = sizeof(E) <= 8 ? 8 : 4;  // entries per lane in flight
   bool fits = true;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -584,11 +551,7 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const Cell* __re
     kmask = uniform_u32(kmask);
     if (!kmask) continue;
     const uint32_t cnt = I.cnt;
-    const uint64_t g0 = lin_group0(I);
-    const uint32_t lj = lane / NCH, lch = lane % NCH;
     for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * GJ) {
-      uint64_t mw = 0;  // lane j*NCH + ch: the word of group j, child ch
-      if (lj < (uint32_t)GJ && k0 + 64 * lj < cnt && ((kmask >> lch) & 1u)) mw = lm[(g0 + k0 / 64 + lj) * NCH + lch];
       E ev[GJ];
 #pragma unroll
       for (int j = 0; j < GJ; j++) {
@@ -599,13 +562,15 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const Cell* __re
 #pragma unroll
       for (int j = 0; j < GJ; j++) {
         if (k0 + 64 * j >= cnt) break;
-        const LinS s = load_ent<FAM>(ev[j]);
+        LinS s = load_ent<FAM>(ev[j]);
+        if (k0 + 64 * j + lane >= cnt) s.F[0] = s.F[1] = GV_F_NONE;
+        bool p[NCH];
+        lin_pass<FAM, NCH>(s, lv, p);
 #pragma unroll
         for (int ch = 0; ch < NCH; ch++) {
           if (!((kmask >> ch) & 1u)) continue;
-          const uint64_t b = readlane64(mw, j * NCH + ch);
-          if ((b >> lane) & 1ull)
-            out[wpos[ch] + mbcnt64(b)] = store_ent<FAM, EO>(lin_canon_child<FAM>(s, lv, lv.cbits[ch]), fits);
+          const uint64_t b = __builtin_amdgcn_ballot_w64(p[ch]);
+          if (p[ch]) out[wpos[ch] + mbcnt64(b)] = store_ent<FAM, EO>(lin_canon_child<FAM>(s, lv, lv.cbits[ch]), fits);
           wpos[ch] += (uint64_t)__popcll(b);
         }
       }

@@ -404,7 +404,7 @@ struct Run {
   int* dovf = nullptr;                    // set when a packed entry could not hold a value
   int pack_from = 1 << 30;                // lists of this level and deeper use the packed entry
   size_t ent_bytes = 0;
-  uint64_t budget_entries = 0;            // max entries of one materialized chunk
+  uint64_t chunk_bytes = 0;               // device bytes one materialized chunk may need
   uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
   bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
   bool beam = true;                       // progressive chunks until the first leaf level
@@ -597,12 +597,9 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   uint32_t* itemcnt = leaf ? nullptr : dalloc<uint32_t>(X, (uint64_t)nch * pa->istride);
   if (itemcnt) HIPCHK(hipMemsetAsync(itemcnt, 0, (uint64_t)nch * pa->istride * sizeof(uint32_t), X.st));
 
-  // linear families: transposed 64-bit pass words per (64-entry group, child)
+  // POSE4DOF keeps per-entry pass masks; linear compaction repeats the test
   const bool linear = FAM != FAM_POSE4DOF;
-  if (linear)
-    pa->masks = leaf ? nullptr : dalloc<uint64_t>(X, (b.nent / 64 + b.ncell + 1) * nch);  // no compaction after a leaf pass
-  else
-    pa->masks = dalloc<M>(X, b.nent);
+  if (!linear) pa->masks = dalloc<M>(X, b.nent);
   uint32_t* ccnt = dalloc<uint32_t>(X, nk);
   pa->cnent = dalloc<uint32_t>(X, nk);
   HIPCHK(hipMemsetAsync(ccnt, 0, nk * sizeof(uint32_t), X.st));
@@ -610,7 +607,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
   auto evp = ev_begin(X, 0);
   X.stats.test_launches++;
-  X.stats.test_bytes += linear ? b.nent * sizeof(E) + (leaf ? 0 : b.nent * nch / 8) : b.nent * (sizeof(E) + sizeof(M));
+  X.stats.test_bytes += linear ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
   if constexpr (FAM == FAM_POSE4DOF) {
     k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, X.m64,
                                              X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck,
@@ -618,10 +615,8 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   } else {
     uint32_t* ic = itemcnt ? itemcnt : X.dummy;
     const uint32_t is = itemcnt ? pa->istride : 0u;
-    uint64_t* lm = (uint64_t*)pa->masks;
 #define GV_COUNT_LIN(U, N) \
-  k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, lm, ccnt, \
-                                                    pa->cnent, ic, is)
+  k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, (const E*)b.ents, ccnt, pa->cnent, ic, is)
     switch ((b.unit ? 16 : 0) | nch) {
       case 16 | 2: GV_COUNT_LIN(true, 2); break;
       case 16 | 4: GV_COUNT_LIN(true, 4); break;
@@ -731,8 +726,9 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
 }
 
 // Chunk schedule over the sorted children: chunk j holds at most
-// first_cells * 4^j cells and at most budget entries, so the first descent
-// follows a narrow beam of the highest-count cells.
+// first_cells * 4^j cells (so the first descent follows a narrow beam of
+// the highest-count cells) and at most chunk_bytes of estimated device
+// memory once expanded: its lists plus the per-cell and per-child arrays.
 void plan_chunks(Run& X, Parent* pa, std::vector<std::pair<uint32_t, uint32_t>>& chunks) {
   const uint32_t nk = pa->nkept;
   const uint64_t stride = std::max<uint64_t>(1, (nk + (1u << 20) - 1) >> 20);
@@ -745,10 +741,16 @@ void plan_chunks(Run& X, Parent* pa, std::vector<std::pair<uint32_t, uint32_t>>&
   dfree(X, d);
   auto at = [&](uint64_t i) { return i >= ns ? s[ns] : s[i]; };  // sample i -> soff[min(i*stride, nk)]
   auto rk = [&](uint64_t i) { return (uint32_t)std::min<uint64_t>(i * stride, nk); };
+  const int lc = std::min(pa->level + 1, X.P0.Lstar - 1);
+  const double per_cell = 64.0 + 40.0 * (double)(1u << X.P0.lev[lc].abits);
+  const double per_ent = (double)X.ent_bytes + 8.0;
+  auto fits = [&](uint64_t a, uint64_t b) {
+    return (double)(at(b) - at(a)) * per_ent + (double)(rk(b) - rk(a)) * per_cell <= (double)X.chunk_bytes;
+  };
   uint64_t i0 = 0, cap = X.beam ? X.first_cells : (1ull << 30);
   while (rk(i0) < nk) {
     uint64_t i1 = i0 + 1;
-    while (i1 < ns && (rk(i1 + 1) - rk(i0)) <= cap && at(i1 + 1) - at(i0) <= X.budget_entries) i1++;
+    while (i1 < ns && (rk(i1 + 1) - rk(i0)) <= cap && fits(i0, i1 + 1)) i1++;
     chunks.push_back({rk(i0), rk(i1)});
     i0 = i1;
     cap = X.beam ? std::min<uint64_t>(cap * 4, 1ull << 30) : (1ull << 30);
@@ -794,16 +796,16 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     if (X.ctx->kernel_timing)
       k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(
           pa->cells, pa->ncell, nch, pa->rank_of, r0, r1, keepc,
-          (uint32_t)(linear ? 8 * sizeof(E) + nch : 8 * (sizeof(E) + sizeof(M))), X.dreads);
+          (uint32_t)(linear ? 8 * sizeof(E) : 8 * (sizeof(E) + sizeof(M))), X.dreads);
     if constexpr (FAM == FAM_POSE4DOF) {
       k_compact<FAM, E, EO, M, true><<<grid, 256, 0, X.st>>>(
           lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, (const E*)pa->ents,
           (const M*)pa->masks, pa->rank_of, r0, r1, keepc, coff, (EO*)nb.ents, X.dovf);
     } else {
 #define GV_COMPACT_LIN(N)                                                                                        \
-  k_compact_lin<FAM, E, EO, N><<<grid, 256, 0, X.st>>>(lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, \
-                                                       pa->istride, (const E*)pa->ents, (const uint64_t*)pa->masks, \
-                                                       pa->rank_of, r0, r1, keepc, coff, (EO*)nb.ents, X.dovf)
+  k_compact_lin<FAM, E, EO, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, \
+                                                       (const E*)pa->ents, pa->rank_of, r0, r1, keepc, coff,          \
+                                                       (EO*)nb.ents, X.dovf)
       switch (nch) {
         case 2: GV_COMPACT_LIN(2); break;
         case 4: GV_COMPACT_LIN(4); break;
@@ -927,7 +929,9 @@ void epoch_begin(Run& X) {
   X.P0 = p0->S.P;
   X.fam = p0->S.fam;
   X.group_mode = p0->p.group;
-  X.budget_entries = std::max<uint64_t>(1ull << 22, X.ctx->budget / (uint64_t)(X.P0.Lstar + 2) / 64);
+  // one parent batch per level stays alive under the one being built, and
+  // grouping a new batch briefly needs about twice its size again
+  X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.ctx->budget / (uint64_t)(X.P0.Lstar + 4));
   const uint32_t np = (uint32_t)X.probs.size();
   X.ooff.assign(np + 1, 0);
   for (uint32_t p = 0; p < np; p++) X.ooff[p + 1] = X.ooff[p] + (uint64_t)X.probs[p]->n;
