@@ -29,13 +29,14 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 WORKLOADS = {
     "plane3d_1m": dict(desc="3D plane fitting by point-plane duality: n=1e6 points in the unit cube, 1% inliers "
                             "on a random plane with vertical noise 0.001, eps 0.003 on (a1, a2, a0)",
-                       kernel="k_count_lin<PLANE3D>", bound="hbm"),
+                       kernel="k_count_lin<PLANE3D>", compact="k_compact_lin<PLANE3D>", bound="hbm"),
     "pose4dof_1m": dict(desc="gravity-aligned 4-DoF pose: 1e6 matches in a 200 m box, 0.5% inliers with 0.5 deg "
-                             "bearing noise, eps 0.5 m / 0.5 deg", kernel="k_count_pose<EntQ32>", bound="alu"),
+                             "bearing noise, eps 0.5 m / 0.5 deg", kernel="k_count_pose<EntQ32>",
+                        compact="k_compact<POSE4DOF>", bound="alu"),
     "ray3d_100k": dict(desc="ray intersection: 1e5 rays, 1% through a common centre", kernel="k_count_lin<RAY3D>",
-                       bound="hbm"),
+                       compact="k_compact_lin<RAY3D>", bound="hbm"),
     "line2d_10k": dict(desc="2D line fitting by duality: 1e4 points, 5% inliers", kernel="k_count_lin<LINE2D>",
-                       bound="hbm"),
+                       compact="k_compact_lin<LINE2D>", bound="hbm"),
     "pose4dof_serve256": dict(desc="256 independent 4-DoF pose problems, matches log-uniform in [1e3, 2e5], inlier "
                                    "ratio log-uniform in [0.2%, 10%], served through gv_submit/gv_poll",
                               kernel="k_count_pose<EntQ32>", bound="alu"),
@@ -157,6 +158,22 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
 
 
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of the kernel from the committed memory-counter
+    record (profiles/traffic.json), or None when there is none or the kernel
+    sources changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_2107_11810_amd", "csrc", f), "rb").read()
+                   for f in ("gv_device.h", "gv_kernels.h"))
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
+
+
 def cpu_baseline(g, budget_tests):
     """The oracle as it stands, single thread, stopped after a fixed number
     of incidence tests of the same solve."""
@@ -228,14 +245,14 @@ def main():
     if t_ms >= c_ms:
         kname, kms, kb, kn = W["kernel"], t_ms, t_b, t_n
     else:
-        kname, kms, kb, kn = "k_compact", c_ms, c_b, c_n
+        kname, kms, kb, kn = W["compact"], c_ms, c_b, c_n
     achieved = (kb / kn) / (kms / kn * 1e-3) / 1e9 if kn and kms > 0 else 0.0
     roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, kname),
             "launches": kn, "avg_launch_us": round(kms / kn * 1e3, 2) if kn else None,
             "bytes_per_launch": int(kb / kn) if kn else None,
             "kernel_ms_per_step": round(kms / len(results), 2),
-            "other_kernel_ms_per_step": round((c_ms if kname != "k_compact" else t_ms) / len(results), 2)}
+            "other_kernel_ms_per_step": round((c_ms if kname == W["kernel"] else t_ms) / len(results), 2)}
     out = {
         "metric": "incidence tests/s",
         "value": tests / sec,

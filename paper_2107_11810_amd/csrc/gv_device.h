@@ -190,7 +190,7 @@ template <int FAM> __device__ inline int Qax(const LinS& s, int qi) {
   return qi == 0 ? (t == 0 ? 1 : 0) : (t == 2 ? 1 : 2);
 }
 
-template <int FAM> __device__ inline LinS lin_zero() {
+template <int FAM> __device__ __host__ inline LinS lin_zero() {
   LinS s;
   s.K[0][0] = s.K[0][1] = s.K[1][0] = s.K[1][1] = 0;
   s.F[0] = s.F[1] = 0;
@@ -200,27 +200,27 @@ template <int FAM> __device__ inline LinS lin_zero() {
 }
 
 // entry -> register state
-template <int FAM> __device__ inline LinS load_ent(const EntL2& e) {
+template <int FAM> __device__ __host__ inline LinS load_ent(const EntL2& e) {
   LinS s = lin_zero<FAM>();
   s.K[0][0] = e.K; s.F[0] = e.F; s.w = e.w;
   return s;
 }
-template <int FAM> __device__ inline LinS load_ent(const EntP3& e) {
+template <int FAM> __device__ __host__ inline LinS load_ent(const EntP3& e) {
   LinS s = lin_zero<FAM>();
   s.K[0][0] = e.K1; s.K[0][1] = e.K2; s.F[0] = e.F; s.w = e.w;
   return s;
 }
-template <int FAM> __device__ inline LinS load_ent(const EntR3& e) {
+template <int FAM> __device__ __host__ inline LinS load_ent(const EntR3& e) {
   LinS s = lin_zero<FAM>();
   s.K[0][0] = e.K1; s.K[1][0] = e.K2; s.F[0] = e.F1; s.F[1] = e.F2; s.w = e.w; s.tag = e.tag;
   return s;
 }
-template <int FAM> __device__ inline LinS load_ent(const EntL2p& e) {
+template <int FAM> __device__ __host__ inline LinS load_ent(const EntL2p& e) {
   LinS s = lin_zero<FAM>();
   s.K[0][0] = e.K; s.F[0] = e.F; s.w = (int32_t)e.w;
   return s;
 }
-template <int FAM> __device__ inline LinS load_ent(const EntP3p& e) {
+template <int FAM> __device__ __host__ inline LinS load_ent(const EntP3p& e) {
   LinS s = lin_zero<FAM>();
   s.K[0][0] = sext_field(e.lo, 0, 13);
   s.K[0][1] = sext_field(e.lo, 13, 13);
@@ -230,29 +230,29 @@ template <int FAM> __device__ inline LinS load_ent(const EntP3p& e) {
 }
 
 // register state -> entry; a packed store clears ok when a value does not fit
-template <int FAM, typename E> __device__ inline E store_ent(const LinS& s, bool& ok);
-template <> __device__ inline EntL2 store_ent<FAM_LINE2D, EntL2>(const LinS& s, bool&) {
+template <int FAM, typename E> __device__ __host__ inline E store_ent(const LinS& s, bool& ok);
+template <> __device__ __host__ inline EntL2 store_ent<FAM_LINE2D, EntL2>(const LinS& s, bool&) {
   EntL2 e;
   e.K = s.K[0][0]; e.F = s.F[0]; e.w = s.w; e._ = 0;
   return e;
 }
-template <> __device__ inline EntP3 store_ent<FAM_PLANE3D, EntP3>(const LinS& s, bool&) {
+template <> __device__ __host__ inline EntP3 store_ent<FAM_PLANE3D, EntP3>(const LinS& s, bool&) {
   EntP3 e;
   e.K1 = s.K[0][0]; e.K2 = s.K[0][1]; e.F = s.F[0]; e.w = s.w;
   return e;
 }
-template <> __device__ inline EntR3 store_ent<FAM_RAY3D, EntR3>(const LinS& s, bool&) {
+template <> __device__ __host__ inline EntR3 store_ent<FAM_RAY3D, EntR3>(const LinS& s, bool&) {
   EntR3 e;
   e.K1 = s.K[0][0]; e.K2 = s.K[1][0]; e.F1 = s.F[0]; e.F2 = s.F[1]; e.w = s.w; e.tag = s.tag;
   return e;
 }
-template <> __device__ inline EntL2p store_ent<FAM_LINE2D, EntL2p>(const LinS& s, bool& ok) {
+template <> __device__ __host__ inline EntL2p store_ent<FAM_LINE2D, EntL2p>(const LinS& s, bool& ok) {
   ok = ok && abs(s.K[0][0]) <= GV_L2_MAX && abs(s.F[0]) <= GV_L2_MAX;
   EntL2p e;
   e.K = (int16_t)s.K[0][0]; e.F = (int16_t)s.F[0]; e.w = (uint32_t)s.w;
   return e;
 }
-template <> __device__ inline EntP3p store_ent<FAM_PLANE3D, EntP3p>(const LinS& s, bool& ok) {
+template <> __device__ __host__ inline EntP3p store_ent<FAM_PLANE3D, EntP3p>(const LinS& s, bool& ok) {
   ok = ok && abs(s.K[0][0]) <= GV_P3_KMAX && abs(s.K[0][1]) <= GV_P3_KMAX && abs(s.F[0]) <= GV_P3_FMAX &&
        (uint32_t)s.w <= GV_P3_WMAX;
   return pack_p3(s.K[0][0], s.K[0][1], s.F[0], (uint32_t)s.w);

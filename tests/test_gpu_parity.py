@@ -188,3 +188,31 @@ def test_grouping_duplicates_at_root(ctx):
     assert rg["stats"]["groups_merged"] >= 1000
     assert rg["count"] == ro["count"] and rg["leaf_index"] == ro["leaf_index"]
     assert np.array_equal(rg["inliers"], ro["inliers"])
+
+
+@pytest.mark.parametrize("name,seed", [("line2d_10k", None), ("line2d_small", 41), ("plane3d_small", 42),
+                                       ("plane3d_small", 43)])
+def test_packed_entries_change_nothing(ctx, name, seed):
+    """Lists in the packed 8-byte entry (the default wherever the lattice
+    bounds allow) and in the full entry (GV_PACK=0) give the same result,
+    equal to the oracle's."""
+    import os
+    from paper_2107_11810_amd import gvote
+    g = synth.config(name) if seed is None else synth.config(name, seed=seed)
+    _say("pack", name, seed)
+    old = os.environ.get("GV_PACK")
+    os.environ["GV_PACK"] = "0"
+    try:
+        full = gvote.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("GV_PACK", None)
+        else:
+            os.environ["GV_PACK"] = old
+    try:
+        r_full = full.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    finally:
+        full.close()
+    r_pack = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    check_same(g, r_pack, r_full)
+    check_same(g, r_pack, oracle.solve(OP(g)))
