@@ -406,6 +406,7 @@ struct Run {
   size_t ent_bytes = 0;
   uint64_t chunk_bytes = 0;               // device bytes one materialized chunk may need
   uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
+  uint64_t dive_cells = 16384;            // cells from which the diversified dive goes greedy
   bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
   bool beam = true;                       // progressive chunks until the first leaf level
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
@@ -932,6 +933,7 @@ void epoch_begin(Run& X) {
   // one parent batch per level stays alive under the one being built, and
   // grouping a new batch briefly needs about twice its size again
   X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.ctx->budget / (uint64_t)(X.P0.Lstar + 4));
+  if (const char* cb = std::getenv("GV_CHUNK_BYTES")) X.chunk_bytes = std::max<uint64_t>(1ull << 20, std::strtoull(cb, nullptr, 10));
   const uint32_t np = (uint32_t)X.probs.size();
   X.ooff.assign(np + 1, 0);
   for (uint32_t p = 0; p < np; p++) X.ooff[p + 1] = X.ooff[p] + (uint64_t)X.probs[p]->n;
@@ -941,6 +943,8 @@ void epoch_begin(Run& X) {
   // quality on small ones; problems sharing an epoch each keep that width
   X.first_cells = 65536ull * (uint64_t)np;
   if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
+  X.dive_cells = 16384ull * (uint64_t)np;
+  if (const char* dc = std::getenv("GV_DIVE_CELLS")) X.dive_cells = std::strtoull(dc, nullptr, 10);
   HIPCHK(hipSetDevice(X.ctx->device));
   X.dP = dalloc<ProbC>(X, np);
   X.dbest = dalloc<unsigned long long>(X, np);
@@ -1055,6 +1059,38 @@ void start_search(Run& X) {
       if (!materialize_at<FAM, E, M>(X, pa, 0, pa->nkept, b)) break;
       own = true;
     }
+  }
+  // diversified dive: every kept child (up to one chunk of the count order)
+  // while the batch holds fewer than dive_cells cells, then the best child of
+  // each cell down to a leaf.  Thousands of greedy paths from different
+  // coarse cells find a strong bound early where the top-count coarse cells
+  // are clutter; like the dive above it only changes bounds, never a result.
+  if (X.dive_cells > 0) {
+    const bool beam = X.beam;
+    Batch b;
+    b.level = 0;
+    b.ncell = (uint32_t)cells.size();
+    b.nent = tot;
+    b.unit = unit;
+    b.cells = dalloc<Cell>(X, cells.size());
+    HIPCHK(hipMemcpyAsync(b.cells, dcells, cells.size() * sizeof(Cell), hipMemcpyDeviceToDevice, X.st));
+    b.ents = ents;
+    bool own = false;
+    while (true) {
+      const bool dv = b.ncell >= X.dive_cells;
+      Parent* pa = expand_at<FAM, E, M>(X, b, own, dv);
+      if (!pa) break;
+      uint32_t r1 = pa->nkept;
+      if (!dv) {
+        std::vector<std::pair<uint32_t, uint32_t>> ch;
+        plan_chunks(X, pa, ch);
+        r1 = ch.front().second;
+      }
+      pa->pending = 1;
+      if (!materialize_at<FAM, E, M>(X, pa, 0, r1, b)) break;
+      own = true;
+    }
+    X.beam = beam;
   }
   Task t{};
   t.chunk = false;
