@@ -75,7 +75,7 @@ def serve_bench(args):
                     time.sleep(dt)
             # the arrival time is recorded before the ticket becomes visible
             arrivals.append(time.perf_counter())
-            tickets.append(gvote.submit(ctx, g["family"], c, g["lo"], g["hi"], g["eps"]))
+            tickets.append(gvote.submit(ctx, g["family"], c, g["lo"], g["hi"], g["eps"], precision=args.precision))
         return tickets, arrivals
 
     def collect(tickets, box, n_total):

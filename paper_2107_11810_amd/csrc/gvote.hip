@@ -95,6 +95,7 @@ struct DevCache {
 
 namespace gvi {
 struct ProbRec;
+struct Lane;
 }
 
 struct gv_ctx {
@@ -117,9 +118,10 @@ struct gv_ctx {
   std::map<uint64_t, gvi::ProbRec*> tickets;
   uint64_t next_ticket = 1;
   uint64_t inflight = 0;   // estimated bytes of admitted problems
-  std::thread worker;
+  std::vector<gvi::Lane*> lanes;  // serving lanes, started by the first gv_submit
+  int nlanes = 4;          // one host thread, stream and allocator each
+  int running = 0;         // epochs running in the lanes
   bool stop = false;
-  int max_epochs = 4;      // epochs stepped round-robin
   size_t max_batch = 1024; // problems per epoch
   // observations an epoch may take beyond its first problem.  Sharing batches
   // between problems measured slower than stepping one-problem epochs
@@ -142,7 +144,7 @@ struct DevErr {
   do {                                                                                 \
     hipError_t e_ = (x);                                                               \
     if (e_ != hipSuccess) {                                                            \
-      X.ctx->err = std::string(#x) + ": " + hipGetErrorString(e_);                     \
+      *X.err = std::string(#x) + ": " + hipGetErrorString(e_);                         \
       throw DevErr{GV_EDEVICE};                                                        \
     }                                                                                  \
   } while (0)
@@ -389,7 +391,11 @@ struct Task {
 // in device tables indexed by the cell's problem id.
 struct Run {
   gv_ctx* ctx = nullptr;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;                 // every device operation of the epoch is ordered on it
+  DevCache* cache = nullptr;                // allocator of that stream
+  std::vector<hipEvent_t>* ev_pool = nullptr;
+  std::string* err = nullptr;               // text of the failing HIP call
+  uint64_t budget = 0;                      // device bytes the epoch may plan with
   std::vector<ProbRec*> probs;
   int fam = 0;
   ProbC P0{};  // level structure shared by the epoch (first problem's constants)
@@ -424,15 +430,25 @@ struct Run {
   std::chrono::steady_clock::time_point t0;
 };
 
+// epochs of gv_solve / gv_parametrize use the context's stream and allocator
+void bind_ctx(Run& X, gv_ctx* c) {
+  X.ctx = c;
+  X.st = c->stream;
+  X.cache = &c->cache;
+  X.ev_pool = &c->ev_pool;
+  X.err = &c->err;
+  X.budget = c->budget;
+}
+
 template <typename T>
 T* dalloc(Run& X, size_t count) {
   if (count == 0) count = 1;
-  void* p = X.ctx->cache.get(count * sizeof(T), X.st, X.ctx->err);
+  void* p = X.cache->get(count * sizeof(T), X.st, *X.err);
   if (!p) throw DevErr{GV_ENOMEM};
   return (T*)p;
 }
 void dfree(Run& X, void* p) {
-  if (p) X.ctx->cache.put(p);
+  if (p) X.cache->put(p);
 }
 
 template <typename In, typename Out>
@@ -478,13 +494,14 @@ std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind) {
   gv_ctx* c = X.ctx;
   std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
   if (!c->kernel_timing) return p;
-  while (c->ev_pool.size() < 2 * (X.ev_used + 1)) {
+  std::vector<hipEvent_t>& pool = *X.ev_pool;
+  while (pool.size() < 2 * (X.ev_used + 1)) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
-    c->ev_pool.push_back(e);
+    pool.push_back(e);
   }
-  p.first = c->ev_pool[2 * X.ev_used];
-  p.second = c->ev_pool[2 * X.ev_used + 1];
+  p.first = pool[2 * X.ev_used];
+  p.second = pool[2 * X.ev_used + 1];
   X.ev_used++;
   HIPCHK(hipEventRecord(p.first, X.st));
   X.ev.push_back({p, kind});
@@ -918,7 +935,7 @@ void fail_all(Run& X, gv_status st) {
   for (ProbRec* pr : X.probs)
     if (pr->st == GV_OK) {
       pr->st = st;
-      pr->err = X.ctx->err;
+      pr->err = *X.err;
     }
 }
 
@@ -932,7 +949,7 @@ void epoch_begin(Run& X) {
   X.group_mode = p0->p.group;
   // one parent batch per level stays alive under the one being built, and
   // grouping a new batch briefly needs about twice its size again
-  X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.ctx->budget / (uint64_t)(X.P0.Lstar + 4));
+  X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.budget / (uint64_t)(X.P0.Lstar + 4));
   if (const char* cb = std::getenv("GV_CHUNK_BYTES")) X.chunk_bytes = std::max<uint64_t>(1ull << 20, std::strtoull(cb, nullptr, 10));
   const uint32_t np = (uint32_t)X.probs.size();
   X.ooff.assign(np + 1, 0);
@@ -1476,8 +1493,7 @@ gv_status deliver(const ProbRec* pr, gv_result* r) {
 // run an epoch to completion on the calling thread (ctx->mu held)
 void run_epoch(gv_ctx* ctx, std::vector<ProbRec*>& probs) {
   Run X;
-  X.ctx = ctx;
-  X.st = ctx->stream;
+  bind_ctx(X, ctx);
   X.probs = probs;
   try {
     auto step = epoch_build(X);
@@ -1491,101 +1507,127 @@ void run_epoch(gv_ctx* ctx, std::vector<ProbRec*>& probs) {
 }
 
 // ===========================================================================
-// Continuous batching: a worker thread admits queued problems into epochs
-// (compatible problems, within the memory budget, up to max_epochs live at
-// once) and steps the live epochs round-robin, one expansion at a time, so a
-// request that arrives while others run starts at the next step.
+// Continuous batching: lanes (host thread + HIP stream + allocator each) take
+// queued problems as memory allows and run them as epochs, so requests that
+// arrive while others are on the device start as soon as a lane frees up and
+// their work overlaps the others' on the GPU.
 // ===========================================================================
+struct Lane {
+  gv_ctx* ctx = nullptr;
+  hipStream_t st = nullptr;
+  DevCache cache;
+  std::vector<hipEvent_t> ev_pool;
+  std::string err;
+  std::thread th;
+};
+
 void publish(gv_ctx* ctx, std::vector<ProbRec*>& probs) {
   std::lock_guard<std::mutex> g(ctx->qmu);
   for (ProbRec* pr : probs) {
     pr->done = true;
     ctx->inflight -= std::min(ctx->inflight, pr->est_bytes);
   }
+  ctx->running--;
   ctx->cv_done.notify_all();
+  ctx->cv_work.notify_all();  // memory was released: a waiting lane may admit now
 }
 
-void worker_main(gv_ctx* ctx) {
-  struct Live {
-    std::unique_ptr<Run> X;
-    std::function<bool(Run&)> step;
-  };
-  std::vector<Live> live;
-  size_t rr = 0;
+void lane_main(Lane* L) {
+  gv_ctx* ctx = L->ctx;
+  (void)hipSetDevice(ctx->device);
   while (true) {
     std::vector<ProbRec*> admit;
     {
       std::unique_lock<std::mutex> lk(ctx->qmu);
-      if (live.empty()) ctx->cv_work.wait(lk, [&] { return ctx->stop || !ctx->queue.empty(); });
-      if (ctx->stop && ctx->queue.empty() && live.empty()) break;
-      if (!ctx->queue.empty() && (int)live.size() < ctx->max_epochs) {
-        ProbRec* first = ctx->queue.front();
-        uint64_t nsum = 0;
-        for (auto it = ctx->queue.begin(); it != ctx->queue.end() && admit.size() < ctx->max_batch;) {
-          ProbRec* pr = *it;
-          if (pr->canceled) {
-            it = ctx->queue.erase(it);
-            pr->done = true;
-            continue;
+      while (true) {
+        if (ctx->stop && ctx->queue.empty()) return;
+        if (!ctx->queue.empty()) {
+          ProbRec* first = nullptr;
+          uint64_t nsum = 0;
+          for (auto it = ctx->queue.begin(); it != ctx->queue.end() && admit.size() < ctx->max_batch;) {
+            ProbRec* pr = *it;
+            if (pr->canceled) {
+              it = ctx->queue.erase(it);
+              pr->done = true;
+              continue;
+            }
+            if (!first) first = pr;
+            // a problem is admitted when its estimate fits in half the budget
+            // next to the running ones (or nothing else runs); small ones may
+            // share an epoch up to batch_n observations
+            const bool fits =
+                ctx->inflight + pr->est_bytes <= ctx->budget / 2 || (ctx->running == 0 && admit.empty());
+            const bool small = admit.empty() || nsum + (uint64_t)pr->n <= ctx->batch_n;
+            if (!small || !fits) break;
+            if (same_structure(first, pr)) {
+              admit.push_back(pr);
+              nsum += (uint64_t)pr->n;
+              ctx->inflight += pr->est_bytes;
+              it = ctx->queue.erase(it);
+            } else {
+              ++it;
+            }
           }
-          const bool fits = ctx->inflight + pr->est_bytes <= ctx->budget / 2 || (live.empty() && admit.empty());
-          // small problems share an epoch (their per-step overheads amortize);
-          // a large one gets an epoch of its own, stepped alongside the others
-          const bool small = admit.empty() || nsum + (uint64_t)pr->n <= ctx->batch_n;
-          if (!small) break;
-          if (same_structure(first, pr) && fits) {
-            admit.push_back(pr);
-            nsum += (uint64_t)pr->n;
-            ctx->inflight += pr->est_bytes;
-            it = ctx->queue.erase(it);
-          } else {
-            ++it;
-          }
+          ctx->cv_done.notify_all();
         }
-        ctx->cv_done.notify_all();
+        if (!admit.empty()) {
+          ctx->running++;
+          break;
+        }
+        if (ctx->stop && ctx->queue.empty()) return;
+        ctx->cv_work.wait(lk);
       }
     }
-    if (!admit.empty()) {
-      Live L;
-      L.X.reset(new Run());
-      L.X->ctx = ctx;
-      L.X->st = ctx->stream;
-      L.X->probs = admit;
-      bool ok = true;
-      {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        try {
-          L.step = epoch_build(*L.X);
-        } catch (DevErr& e) {
-          fail_all(*L.X, e.st);
-          epoch_release(*L.X);
-          ok = false;
-        }
+    Run X;
+    X.ctx = ctx;
+    X.st = L->st;
+    X.cache = &L->cache;
+    X.ev_pool = &L->ev_pool;
+    X.err = &L->err;
+    X.budget = ctx->budget / (uint64_t)std::max(1, ctx->nlanes);
+    X.probs = admit;
+    L->err.clear();
+    try {
+      auto step = epoch_build(X);
+      while (step(X)) {
       }
-      if (ok) live.push_back(std::move(L));
-      else publish(ctx, admit);
+      epoch_finish(X);
+    } catch (DevErr& e) {
+      fail_all(X, e.st);
     }
-    if (!live.empty()) {
-      const size_t i = rr++ % live.size();
-      Live& L = live[i];
-      bool more = false;
-      {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        try {
-          more = L.step(*L.X);
-          if (!more) epoch_finish(*L.X);
-        } catch (DevErr& e) {
-          fail_all(*L.X, e.st);
-          more = false;
-        }
-        if (!more) epoch_release(*L.X);
-      }
-      if (!more) {
-        publish(ctx, L.X->probs);
-        live.erase(live.begin() + (long)i);
-      }
-    }
+    epoch_release(X);
+    // keep this lane's share of cached blocks bounded
+    if (L->cache.cached > ctx->budget / (uint64_t)(2 * std::max(1, ctx->nlanes))) L->cache.trim(L->st);
+    publish(ctx, admit);
   }
+}
+
+void start_lanes(gv_ctx* ctx) {
+  for (int i = 0; i < ctx->nlanes; i++) {
+    Lane* L = new Lane();
+    L->ctx = ctx;
+    (void)hipSetDevice(ctx->device);
+    if (hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking) != hipSuccess) {
+      delete L;
+      break;
+    }
+    L->th = std::thread(lane_main, L);
+    ctx->lanes.push_back(L);
+  }
+}
+
+void stop_lanes(gv_ctx* ctx) {
+  for (Lane* L : ctx->lanes)
+    if (L->th.joinable()) L->th.join();
+  for (Lane* L : ctx->lanes) {
+    (void)hipStreamSynchronize(L->st);
+    L->cache.trim(L->st);
+    for (auto& kv : L->cache.live) (void)hipFree(kv.first);
+    for (hipEvent_t e : L->ev_pool) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(L->st);
+    delete L;
+  }
+  ctx->lanes.clear();
 }
 
 }  // namespace gvi
@@ -1645,7 +1687,7 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
   size_t fr = 0, tot = 0;
   (void)hipMemGetInfo(&fr, &tot);
   c->budget = (cfg && cfg->mem_budget_bytes) ? cfg->mem_budget_bytes : (uint64_t)(0.6 * (double)fr);
-  if (const char* e = std::getenv("GV_MAX_EPOCHS")) c->max_epochs = std::max(1, atoi(e));
+  if (const char* e = std::getenv("GV_LANES")) c->nlanes = std::max(1, std::min(16, atoi(e)));
   if (const char* e = std::getenv("GV_MAX_BATCH")) c->max_batch = (size_t)std::max(1, atoi(e));
   if (const char* e = std::getenv("GV_BATCH_N")) c->batch_n = std::strtoull(e, nullptr, 10);
   if (const char* e = std::getenv("GV_PACK")) c->pack = atoi(e) != 0;
@@ -1661,7 +1703,7 @@ gv_status gv_destroy(gv_ctx* ctx) {
     for (ProbRec* pr : ctx->queue) pr->canceled = true;
   }
   ctx->cv_work.notify_all();
-  if (ctx->worker.joinable()) ctx->worker.join();
+  stop_lanes(ctx);
   for (auto& kv : ctx->tickets) delete kv.second;
   ctx->tickets.clear();
   (void)hipSetDevice(ctx->device);
@@ -1732,7 +1774,14 @@ gv_status gv_submit(gv_ctx* ctx, const gv_problem* p, uint64_t* ticket) {
   pr->ticket = ctx->next_ticket++;
   ctx->tickets[pr->ticket] = pr;
   ctx->queue.push_back(pr);
-  if (!ctx->worker.joinable()) ctx->worker = std::thread(worker_main, ctx);
+  if (ctx->lanes.empty()) start_lanes(ctx);
+  if (ctx->lanes.empty()) {
+    ctx->tickets.erase(pr->ticket);
+    ctx->queue.pop_back();
+    delete pr;
+    set_err(ctx, "could not create a serving stream");
+    return GV_EDEVICE;
+  }
   ctx->cv_work.notify_one();
   *ticket = pr->ticket;
   return GV_OK;
@@ -1800,8 +1849,7 @@ gv_status gv_parametrize(gv_ctx* ctx, const gv_problem* p, double* t_out, double
   }
   std::lock_guard<std::mutex> g(ctx->mu);
   Run X;
-  X.ctx = ctx;
-  X.st = ctx->stream;
+  bind_ctx(X, ctx);
   st = GV_OK;
   std::vector<void*> owned;
   try {
