@@ -413,6 +413,7 @@ struct Run {
   uint64_t chunk_bytes = 0;               // device bytes one materialized chunk may need
   uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
   uint64_t dive_cells = 16384;            // cells from which the diversified dive goes greedy
+  bool root_dive = false;                 // greedy dive from the root cells first (the diversified dive subsumes it)
   bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
   bool beam = true;                       // progressive chunks until the first leaf level
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
@@ -962,6 +963,7 @@ void epoch_begin(Run& X) {
   if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
   X.dive_cells = 16384ull * (uint64_t)np;
   if (const char* dc = std::getenv("GV_DIVE_CELLS")) X.dive_cells = std::strtoull(dc, nullptr, 10);
+  if (const char* rd = std::getenv("GV_ROOT_DIVE")) X.root_dive = atoi(rd) != 0;
   HIPCHK(hipSetDevice(X.ctx->device));
   X.dP = dalloc<ProbC>(X, np);
   X.dbest = dalloc<unsigned long long>(X, np);
@@ -1059,7 +1061,7 @@ void start_search(Run& X) {
   HIPCHK(hipMemcpyAsync(dcells, cells.data(), cells.size() * sizeof(Cell), hipMemcpyHostToDevice, X.st));
   HIPCHK(hipStreamSynchronize(X.st));
   // greedy dive in every cell: achieved leaf keys are valid starting bounds
-  {
+  if (X.root_dive) {
     Batch b;
     b.level = 0;
     b.ncell = (uint32_t)cells.size();
