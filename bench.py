@@ -45,8 +45,9 @@ WORKLOADS = {
 
 def serve_bench(args):
     """Plain binary64, one problem at a time (gv_solve) against the binary32
-    filter with continuous batching (gv_submit/gv_poll), same 256 problems,
-    inputs resident in HBM; then Poisson arrivals for p50/p99 latency."""
+    filter with continuous batching (gv_submit/gv_poll, four lanes), same 256
+    problems, inputs resident in HBM; then Poisson arrivals for p50/p99
+    latency, beside the plain form's FIFO latency on the same arrivals."""
     import threading
     import numpy as np
     from paper_2107_11810_amd import gvote, synth
@@ -58,9 +59,12 @@ def serve_bench(args):
     g0 = probs[0]
     ctx.solve(g0["family"], cols[0], g0["lo"], g0["hi"], g0["eps"])  # warm-up
     hip.hipDeviceSynchronize()
+    plain, dur = [], []
     t0 = time.perf_counter()
-    plain = [ctx.solve(g["family"], c, g["lo"], g["hi"], g["eps"], precision=gvote.FP64_PLAIN)
-             for g, c in zip(probs, cols)]
+    for g, c in zip(probs, cols):
+        t1 = time.perf_counter()
+        plain.append(ctx.solve(g["family"], c, g["lo"], g["hi"], g["eps"], precision=gvote.FP64_PLAIN))
+        dur.append(time.perf_counter() - t1)
     t_plain = time.perf_counter() - t0
     print(f"plain binary64 one at a time: {t_plain:.2f} s", file=sys.stderr, flush=True)
 
@@ -108,7 +112,7 @@ def serve_bench(args):
     same = all(r["count"] == p["count"] and r["leaf_index"] == p["leaf_index"] for r, p in zip(box[1], plain))
     mu = len(probs) / t_batch
     print(f"filter + continuous batching: {t_batch:.2f} s, identical={same}", file=sys.stderr, flush=True)
-    lat = {}
+    lat, fifo = {}, {}
     for frac in (0.8, 0.5):
         arr = synth.poisson_arrivals(len(probs), frac * mu, seed=199)
         tickets, arrivals = [], []
@@ -122,7 +126,15 @@ def serve_bench(args):
         th.join()
         L = np.array(box2[0]) - np.array(arrivals)
         lat[frac] = (float(np.percentile(L, 50)), float(np.percentile(L, 99)))
-        print(f"arrivals at {frac:.1f} x saturated rate: p50 {lat[frac][0]*1e3:.1f} ms, p99 {lat[frac][1]*1e3:.1f} ms",
+        # the plain form on the same arrival times: one solve at a time in
+        # arrival order, each taking its measured binary64 duration
+        fin, done_t = [], 0.0
+        for a, d in zip(arr, dur):
+            done_t = max(done_t, a) + d
+            fin.append(done_t - a)
+        fifo[frac] = (float(np.percentile(fin, 50)), float(np.percentile(fin, 99)))
+        print(f"arrivals at {frac:.1f} x saturated rate: p50 {lat[frac][0]*1e3:.1f} ms, p99 {lat[frac][1]*1e3:.1f} ms"
+              f" (plain FIFO on the same arrivals: p50 {fifo[frac][0]*1e3:.1f} ms, p99 {fifo[frac][1]*1e3:.1f} ms)",
               file=sys.stderr, flush=True)
     ctx.close()
     out = {
@@ -135,6 +147,7 @@ def serve_bench(args):
         "batched_over_plain": (len(probs) / t_plain and mu / (len(probs) / t_plain)),
         "identical_to_plain": same,
         "latency_ms": {f"{f}x_saturated": {"p50": lat[f][0] * 1e3, "p99": lat[f][1] * 1e3} for f in lat},
+        "plain_fifo_latency_ms": {f"{f}x_saturated": {"p50": fifo[f][0] * 1e3, "p99": fifo[f][1] * 1e3} for f in fifo},
     }
     print(json.dumps(out), flush=True)
 
