@@ -514,50 +514,76 @@ __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const u
 // their exclusive scan (itemoff, child-major) gives each item's offset inside
 // the child's list; within an item, a wavefront ballot ranks the lanes.
 // ---------------------------------------------------------------------------
-// Linear-family compaction: every entry of an item with a child in the
-// chunk is re-tested; a child's ballot gives the lanes to write and, by its
-// bit count below the lane, their order.  The child list may use the packed
+// Work list of one linear-family compaction pass: the items whose cell has a
+// child in the chunk, each with its kept children and, per kept child, where
+// its survivors go (the child's list offset plus the item's offset inside
+// that list).  One thread per item; a wave appends its records with one
+// atomic.
+template <int NCH> struct CWork {
+  uint64_t off;
+  uint32_t cnt, kmask;
+  uint64_t wpos[NCH];
+};
+
+template <int NCH>
+__global__ void k_chunk_work(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
+                             const uint32_t* __restrict__ ioff, const uint64_t* __restrict__ itemoff,
+                             uint32_t istride, const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
+                             const uint32_t* __restrict__ keepc, const uint64_t* __restrict__ coff,
+                             CWork<NCH>* __restrict__ work, uint32_t* __restrict__ nwork) {
+  const uint32_t it = blockIdx.x * blockDim.x + threadIdx.x;
+  CWork<NCH> w{};
+  if (it < *nitems_p) {
+    const Item I = items[it];
+    const uint32_t first = ioff[I.cell];
+    w.off = I.off;
+    w.cnt = I.cnt;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ch++) {
+      const uint32_t r = rank_of[(uint64_t)I.cell * NCH + ch];
+      if (r >= r0 && r < r1 && keepc[r - r0]) {
+        w.kmask |= 1u << ch;
+        w.wpos[ch] = coff[r - r0] + (itemoff[(uint64_t)ch * istride + it] - itemoff[(uint64_t)ch * istride + first]);
+      }
+    }
+  }
+  const uint64_t b = __ballot(w.kmask != 0u);
+  if (!b) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(nwork, (uint32_t)__popcll(b));
+  base = __shfl(base, 0, 64);
+  if (w.kmask) work[base + mbcnt64(b)] = w;
+}
+
+// Linear-family compaction over the work list: every entry of a work item is
+// re-tested; a kept child's ballot gives the lanes to write and, by its bit
+// count below the lane, their order.  The child list may use the packed
 // entry; a value that does not fit sets *ovf.
 template <int FAM, typename E, typename EO, int NCH>
-__global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const Item* __restrict__ items,
-                                                     const uint32_t* __restrict__ nitems_p,
-                                                     const uint32_t* __restrict__ ioff,
-                                                     const uint64_t* __restrict__ itemoff, uint32_t istride,
-                                                     const E* __restrict__ ents,
-                                                     const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
-                                                     const uint32_t* __restrict__ keepc,
-                                                     const uint64_t* __restrict__ coff, EO* __restrict__ out,
-                                                     int* __restrict__ ovf) {
+__global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>* __restrict__ work,
+                                                     const uint32_t* __restrict__ nwork_p, const E* __restrict__ ents,
+                                                     EO* __restrict__ out, int* __restrict__ ovf) {
   constexpr int GJ = sizeof(E) <= 8 ? 8 : 4;  // entries per lane in flight
   bool fits = true;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-  const uint32_t nitems = *nitems_p;
-  for (uint32_t it = wave; it < nitems; it += nwaves) {
-    const Item I = items[it];
-    uint32_t kmask = 0;
+  const uint32_t nwork = *nwork_p;
+  for (uint32_t wi = wave; wi < nwork; wi += nwaves) {
+    const CWork<NCH> W = work[wi];
+    const uint32_t kmask = W.kmask;
+    const uint32_t cnt = W.cnt;
     uint64_t wpos[NCH];
-    const uint32_t first = ioff[I.cell];
 #pragma unroll
-    for (int ch = 0; ch < NCH; ch++) {
-      wpos[ch] = 0;
-      const uint32_t r = rank_of[(uint64_t)I.cell * NCH + ch];
-      if (r >= r0 && r < r1 && keepc[r - r0]) {
-        kmask |= 1u << ch;
-        wpos[ch] = coff[r - r0] + (itemoff[(uint64_t)ch * istride + it] - itemoff[(uint64_t)ch * istride + first]);
-      }
-    }
-    kmask = uniform_u32(kmask);
-    if (!kmask) continue;
-    const uint32_t cnt = I.cnt;
+    for (int ch = 0; ch < NCH; ch++) wpos[ch] = W.wpos[ch];
     for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * GJ) {
       E ev[GJ];
 #pragma unroll
       for (int j = 0; j < GJ; j++) {
         const uint32_t k = k0 + 64 * j + lane;
         ev[j] = E{};
-        if (k < cnt) ev[j] = ents[I.off + k];
+        if (k < cnt) ev[j] = ents[W.off + k];
       }
 #pragma unroll
       for (int j = 0; j < GJ; j++) {

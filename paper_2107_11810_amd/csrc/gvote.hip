@@ -808,22 +808,40 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     k_emit_ranked<<<nblk(nr), 256, 0, X.st>>>(lv, pa->cells, pa->order, r0, r1, keepc, cidx, coff, pa->cnent,
                                               nb.cells);
     const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
-    auto evp = ev_begin(X, 1);
-    X.stats.compact_launches++;
-    X.stats.compact_bytes += nb.nent * sizeof(EO);
     const bool linear = FAM != FAM_POSE4DOF;
+    // linear families: the items with a child in this chunk become a work
+    // list (offsets resolved), then one wave per work item
+    void* work = nullptr;
+    uint32_t* nwork = nullptr;
+    if (linear) {
+      nwork = dalloc<uint32_t>(X, 1);
+      HIPCHK(hipMemsetAsync(nwork, 0, sizeof(uint32_t), X.st));
+#define GV_WORK(N)                                                                                               \
+  work = dalloc<CWork<N>>(X, pa->max_items);                                                                     \
+  k_chunk_work<N><<<nblk(pa->max_items), 256, 0, X.st>>>(pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, \
+                                                        pa->rank_of, r0, r1, keepc, coff, (CWork<N>*)work, nwork)
+      switch (nch) {
+        case 2: GV_WORK(2); break;
+        case 4: GV_WORK(4); break;
+        case 8: GV_WORK(8); break;
+        default: throw DevErr{GV_EINVAL};
+      }
+#undef GV_WORK
+    }
     if (X.ctx->kernel_timing)
       k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(
           pa->cells, pa->ncell, nch, pa->rank_of, r0, r1, keepc,
           (uint32_t)(linear ? 8 * sizeof(E) : 8 * (sizeof(E) + sizeof(M))), X.dreads);
+    auto evp = ev_begin(X, 1);
+    X.stats.compact_launches++;
+    X.stats.compact_bytes += nb.nent * sizeof(EO);
     if constexpr (FAM == FAM_POSE4DOF) {
       k_compact<FAM, E, EO, M, true><<<grid, 256, 0, X.st>>>(
           lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, (const E*)pa->ents,
           (const M*)pa->masks, pa->rank_of, r0, r1, keepc, coff, (EO*)nb.ents, X.dovf);
     } else {
-#define GV_COMPACT_LIN(N)                                                                                        \
-  k_compact_lin<FAM, E, EO, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, \
-                                                       (const E*)pa->ents, pa->rank_of, r0, r1, keepc, coff,          \
+#define GV_COMPACT_LIN(N)                                                                                         \
+  k_compact_lin<FAM, E, EO, N><<<grid, 256, 0, X.st>>>(lv, (const CWork<N>*)work, nwork, (const E*)pa->ents,      \
                                                        (EO*)nb.ents, X.dovf)
       switch (nch) {
         case 2: GV_COMPACT_LIN(2); break;
@@ -835,6 +853,8 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     }
     ev_end(X, evp);
     HIPCHK(hipGetLastError());
+    dfree(X, work);
+    dfree(X, nwork);
     nb.unit = pa->unit;
     made = true;
   }
