@@ -81,12 +81,14 @@ __device__ inline void lin_pass(const LinS& s, const LevelC& lv, bool (&p)[NCH])
 }
 
 // UNIT: every multiplicity is 1 (no merged surfaces), so a child's count is
-// the popcount of its ballot, accumulated in scalar registers.
+// the popcount of its ballot, accumulated in scalar registers.  Each item
+// writes its per-child entry counts (and, unless UNIT, weights) as one row
+// icnt[it * NCH + ch]; k_cell_scan turns the rows into per-cell counts and
+// per-item list offsets, so no atomics are needed.
 template <int FAM, bool UNIT, typename E, int NCH>
 __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Item* __restrict__ items,
                                                    const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
-                                                   uint32_t* __restrict__ ccnt, uint32_t* __restrict__ cnent,
-                                                   uint32_t* __restrict__ itemcnt, uint32_t istride) {
+                                                   uint32_t* __restrict__ icnt, uint32_t* __restrict__ iw) {
   // entries per lane in flight: a whole item for 8-byte entries
   constexpr int NB = sizeof(E) <= 8 ? 16 : (sizeof(E) <= 16 ? 8 : 4);
   const uint32_t lane = lane_id();
@@ -122,18 +124,42 @@ __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Item* __rest
         }
       }
     }
+    // lane ch < NCH writes child ch's column of the item's row
+    uint32_t vn = 0, vw = 0;
 #pragma unroll
     for (int ch = 0; ch < NCH; ch++) {
-      const uint32_t n = an[ch];
-      const uint32_t w = UNIT ? n : wave_sum_u32(aw[ch]);
-      if (lane == 0 && n) {
-        atomicAdd(&ccnt[I.cell * NCH + ch], w);
-        atomicAdd(&cnent[I.cell * NCH + ch], n);
-        if (istride) itemcnt[(uint64_t)ch * istride + it] = n;
-      }
+      const uint32_t w = UNIT ? an[ch] : wave_sum_u32(aw[ch]);
+      vn = lane == (uint32_t)ch ? an[ch] : vn;
+      vw = lane == (uint32_t)ch ? w : vw;
+    }
+    if (lane < (uint32_t)NCH) {
+      icnt[(uint64_t)it * NCH + lane] = vn;
+      if constexpr (!UNIT) iw[(uint64_t)it * NCH + lane] = vw;
     }
     I = In;
   }
+}
+
+// Per (cell, child): the cell's count and entries from its items' rows, and
+// each item's offset inside the child's list (exclusive, within the cell).
+// A cell of length len owns ceil(len / GV_ITEM) items from ioff[cell].
+template <int NCH, bool UNIT>
+__global__ void k_cell_scan(const Cell* __restrict__ cells, uint32_t ncell, const uint32_t* __restrict__ ioff,
+                            const uint32_t* __restrict__ icnt, const uint32_t* __restrict__ iw,
+                            uint64_t* __restrict__ itemoff, uint32_t* __restrict__ ccnt, uint32_t* __restrict__ cnent) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (uint64_t)ncell * NCH) return;
+  const uint32_t c = (uint32_t)(t / NCH), ch = (uint32_t)(t % NCH);
+  const uint32_t i0 = ioff[c], ni = (cells[c].len + GV_ITEM - 1) / GV_ITEM;
+  uint64_t n = 0, w = 0;
+  for (uint32_t i = i0; i < i0 + ni; i++) {
+    const uint64_t k = (uint64_t)i * NCH + ch;
+    if (itemoff) itemoff[k] = n;
+    n += icnt[k];
+    if constexpr (!UNIT) w += iw[k];
+  }
+  cnent[t] = (uint32_t)n;
+  ccnt[t] = (uint32_t)(UNIT ? n : w);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,15 +553,13 @@ template <int NCH> struct CWork {
 
 template <int NCH>
 __global__ void k_chunk_work(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
-                             const uint32_t* __restrict__ ioff, const uint64_t* __restrict__ itemoff,
-                             uint32_t istride, const uint32_t* __restrict__ rank_of, uint32_t r0, uint32_t r1,
-                             const uint32_t* __restrict__ keepc, const uint64_t* __restrict__ coff,
+                             const uint64_t* __restrict__ itemoff, const uint32_t* __restrict__ rank_of, uint32_t r0,
+                             uint32_t r1, const uint32_t* __restrict__ keepc, const uint64_t* __restrict__ coff,
                              CWork<NCH>* __restrict__ work, uint32_t* __restrict__ nwork) {
   const uint32_t it = blockIdx.x * blockDim.x + threadIdx.x;
   CWork<NCH> w{};
   if (it < *nitems_p) {
     const Item I = items[it];
-    const uint32_t first = ioff[I.cell];
     w.off = I.off;
     w.cnt = I.cnt;
 #pragma unroll
@@ -543,7 +567,7 @@ __global__ void k_chunk_work(const Item* __restrict__ items, const uint32_t* __r
       const uint32_t r = rank_of[(uint64_t)I.cell * NCH + ch];
       if (r >= r0 && r < r1 && keepc[r - r0]) {
         w.kmask |= 1u << ch;
-        w.wpos[ch] = coff[r - r0] + (itemoff[(uint64_t)ch * istride + it] - itemoff[(uint64_t)ch * istride + first]);
+        w.wpos[ch] = coff[r - r0] + itemoff[(uint64_t)it * NCH + ch];
       }
     }
   }

@@ -613,16 +613,26 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, pa->ioff, pa->items, pa->nitems);
   dfree(X, nitem);
   pa->istride = (uint32_t)pa->max_items;
-  uint32_t* itemcnt = leaf ? nullptr : dalloc<uint32_t>(X, (uint64_t)nch * pa->istride);
-  if (itemcnt) HIPCHK(hipMemsetAsync(itemcnt, 0, (uint64_t)nch * pa->istride * sizeof(uint32_t), X.st));
-
-  // POSE4DOF keeps per-entry pass masks; linear compaction repeats the test
+  // POSE4DOF keeps per-entry pass masks and counts with atomics, per-item
+  // survivors child-major; linear families write one row of per-child
+  // counts per item (item-major) and repeat the test in the compaction
   const bool linear = FAM != FAM_POSE4DOF;
+  uint32_t* itemcnt = nullptr;
+  uint32_t* itemw = nullptr;
+  if (linear) {
+    itemcnt = dalloc<uint32_t>(X, (uint64_t)nch * pa->max_items);
+    if (!b.unit) itemw = dalloc<uint32_t>(X, (uint64_t)nch * pa->max_items);
+  } else if (!leaf) {
+    itemcnt = dalloc<uint32_t>(X, (uint64_t)nch * pa->istride);
+    HIPCHK(hipMemsetAsync(itemcnt, 0, (uint64_t)nch * pa->istride * sizeof(uint32_t), X.st));
+  }
   if (!linear) pa->masks = dalloc<M>(X, b.nent);
   uint32_t* ccnt = dalloc<uint32_t>(X, nk);
   pa->cnent = dalloc<uint32_t>(X, nk);
-  HIPCHK(hipMemsetAsync(ccnt, 0, nk * sizeof(uint32_t), X.st));
-  HIPCHK(hipMemsetAsync(pa->cnent, 0, nk * sizeof(uint32_t), X.st));
+  if (!linear) {
+    HIPCHK(hipMemsetAsync(ccnt, 0, nk * sizeof(uint32_t), X.st));
+    HIPCHK(hipMemsetAsync(pa->cnent, 0, nk * sizeof(uint32_t), X.st));
+  }
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
   auto evp = ev_begin(X, 0);
   X.stats.test_launches++;
@@ -632,10 +642,8 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
                                              X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck,
                                              itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
   } else {
-    uint32_t* ic = itemcnt ? itemcnt : X.dummy;
-    const uint32_t is = itemcnt ? pa->istride : 0u;
 #define GV_COUNT_LIN(U, N) \
-  k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, (const E*)b.ents, ccnt, pa->cnent, ic, is)
+  k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, (const E*)b.ents, itemcnt, itemw)
     switch ((b.unit ? 16 : 0) | nch) {
       case 16 | 2: GV_COUNT_LIN(true, 2); break;
       case 16 | 4: GV_COUNT_LIN(true, 4); break;
@@ -649,6 +657,27 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   }
   ev_end(X, evp);
   HIPCHK(hipGetLastError());
+  if constexpr (FAM != FAM_POSE4DOF) {
+    // per-cell counts and per-item offsets from the items' rows
+    if (!leaf) pa->itemoff = dalloc<uint64_t>(X, (uint64_t)nch * pa->max_items);
+#define GV_CELL_SCAN(U, N)                                                                                      \
+  k_cell_scan<N, U><<<nblk((uint64_t)b.ncell * N), 256, 0, X.st>>>(b.cells, b.ncell, pa->ioff, itemcnt, itemw,  \
+                                                                   pa->itemoff, ccnt, pa->cnent)
+    switch ((b.unit ? 16 : 0) | nch) {
+      case 16 | 2: GV_CELL_SCAN(true, 2); break;
+      case 16 | 4: GV_CELL_SCAN(true, 4); break;
+      case 16 | 8: GV_CELL_SCAN(true, 8); break;
+      case 2: GV_CELL_SCAN(false, 2); break;
+      case 4: GV_CELL_SCAN(false, 4); break;
+      case 8: GV_CELL_SCAN(false, 8); break;
+      default: throw DevErr{GV_EINVAL};
+    }
+#undef GV_CELL_SCAN
+    HIPCHK(hipGetLastError());
+    dfree(X, itemcnt);
+    dfree(X, itemw);
+    itemcnt = itemw = nullptr;
+  }
 
   uint32_t* keepf = dalloc<uint32_t>(X, nk);
   uint64_t* keptn = dalloc<uint64_t>(X, nk);
@@ -688,9 +717,11 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     free_parent(X, pa);
     return nullptr;
   }
-  pa->itemoff = dalloc<uint64_t>(X, (uint64_t)nch * pa->istride);
-  excl_scan(X, itemcnt, pa->itemoff, (uint64_t)nch * pa->istride);
-  dfree(X, itemcnt);
+  if (itemcnt) {  // POSE4DOF: child-major offsets for k_compact
+    pa->itemoff = dalloc<uint64_t>(X, (uint64_t)nch * pa->istride);
+    excl_scan(X, itemcnt, pa->itemoff, (uint64_t)nch * pa->istride);
+    dfree(X, itemcnt);
+  }
   pa->nkept = (uint32_t)nkept;
   uint32_t* kcnt = dalloc<uint32_t>(X, nkept);
   uint32_t* kid = dalloc<uint32_t>(X, nkept);
@@ -818,8 +849,8 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
       HIPCHK(hipMemsetAsync(nwork, 0, sizeof(uint32_t), X.st));
 #define GV_WORK(N)                                                                                               \
   work = dalloc<CWork<N>>(X, pa->max_items);                                                                     \
-  k_chunk_work<N><<<nblk(pa->max_items), 256, 0, X.st>>>(pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, \
-                                                        pa->rank_of, r0, r1, keepc, coff, (CWork<N>*)work, nwork)
+  k_chunk_work<N><<<nblk(pa->max_items), 256, 0, X.st>>>(pa->items, pa->nitems, pa->itemoff, pa->rank_of, r0, r1, \
+                                                        keepc, coff, (CWork<N>*)work, nwork)
       switch (nch) {
         case 2: GV_WORK(2); break;
         case 4: GV_WORK(4); break;
