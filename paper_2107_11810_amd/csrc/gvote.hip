@@ -999,9 +999,11 @@ void epoch_begin(Run& X) {
   X.P0 = p0->S.P;
   X.fam = p0->S.fam;
   X.group_mode = p0->p.group;
-  // one parent batch per level stays alive under the one being built, and
-  // grouping a new batch briefly needs about twice its size again
-  X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.budget / (uint64_t)(X.P0.Lstar + 4));
+  // the parent batches of the levels above stay alive under the one being
+  // built, but only the deepest few are large (the lists grow with depth
+  // until pruning bites): measured peaks are about twice one chunk, and a
+  // fifth of the budget per chunk leaves room for four large levels
+  X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.budget / 5);
   if (const char* cb = std::getenv("GV_CHUNK_BYTES")) X.chunk_bytes = std::max<uint64_t>(1ull << 20, std::strtoull(cb, nullptr, 10));
   const uint32_t np = (uint32_t)X.probs.size();
   X.ooff.assign(np + 1, 0);
@@ -1436,8 +1438,8 @@ void epoch_finish(Run& X) {
   X.stats.ms_total = ms;
   X.stats.ms_kernels = ms;
   if (X.trace)
-    std::fprintf(stderr, "gv: epoch of %u problems: %.3g tests, %llu cells expanded, %.1f ms\n", np,
-                 (double)X.stats.tests, (unsigned long long)X.stats.cells_expanded, ms);
+    std::fprintf(stderr, "gv: epoch of %u problems: %.3g tests, %llu cells expanded, %.1f ms, peak %.2f GB\n", np,
+                 (double)X.stats.tests, (unsigned long long)X.stats.cells_expanded, ms, (double)X.cache->peak * 1e-9);
   for (uint32_t p = 0; p < np; p++) {
     ProbRec* pr = X.probs[p];
     pr->stats = X.stats;
@@ -1637,7 +1639,10 @@ void lane_main(Lane* L) {
     X.cache = &L->cache;
     X.ev_pool = &L->ev_pool;
     X.err = &L->err;
-    X.budget = ctx->budget / (uint64_t)std::max(1, ctx->nlanes);
+    // lanes share the device: smaller chunks keep their allocations small
+    // and their latency steady (measured: 8 GB chunks per lane raised the
+    // p50 latency under Poisson arrivals from 31 ms to 1.5 s)
+    X.budget = ctx->budget / (uint64_t)(3 * std::max(1, ctx->nlanes));
     X.probs = admit;
     L->err.clear();
     try {
