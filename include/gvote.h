@@ -75,7 +75,9 @@ typedef struct {
   int device;                 /* HIP device ordinal */
   uint64_t mem_budget_bytes;  /* 0: 60% of the device's free memory */
   void *hip_stream;           /* optional hipStream_t to run on; NULL: own stream */
-  const char *autotune_cache; /* optional path of the tile autotuner cache */
+  const char *autotune_cache; /* reserved, ignored: kernel launch shapes are
+                                 fixed (one wave per list item of <= 1024
+                                 entries, 8 blocks of 4 waves per CU) */
   int kernel_timing;          /* 1: time the incidence and compaction kernels
                                  with HIP events on the solve stream (adds
                                  one event pair per launch) */
@@ -106,8 +108,9 @@ typedef struct {
   uint32_t levels;            /* L*: depth of the leaves */
   double ms_total, ms_kernels;
   /* with kernel_timing: summed event time, launches and algorithmic bytes
-   * (entries read + masks written) of the incidence-test kernel, and the
-   * same for the compaction kernel (entries + masks read, children written) */
+   * of the incidence-test kernel (entries read; POSE4DOF also writes a pass
+   * mask per entry) and of the compaction kernel (entries of the parents
+   * with a child in the chunk read, POSE4DOF masks read, children written) */
   double test_ms, compact_ms;
   uint64_t test_launches, compact_launches;
   uint64_t test_bytes, compact_bytes;
@@ -134,9 +137,10 @@ gv_status gv_create(gv_ctx **out, const gv_ctx_config *cfg);
 gv_status gv_destroy(gv_ctx *ctx);
 
 /* Solve one problem, blocking (Alg. 2 end to end: front end, root
- * canonization and grouping, greedy dive, depth-first frontier expansion with
- * pruning, best-key reduction, path-replay inlier extraction).  Calls on one
- * context are serialized. */
+ * canonization and grouping, a dive that seeds the best key, depth-first
+ * frontier expansion with pruning, best-key reduction, path-replay inlier
+ * extraction) on the context's stream.  gv_solve calls on one context are
+ * serialized; they may run while submitted problems are served. */
 gv_status gv_solve(gv_ctx *ctx, const gv_problem *p, gv_result *r);
 
 /* Front end only (Eq. 1-3 and the posing surface): writes the normalized
@@ -148,8 +152,10 @@ gv_status gv_parametrize(gv_ctx *ctx, const gv_problem *p, double *t_out, double
                          int32_t *tag_out);
 
 /* Continuous batching: enqueue a problem (columns copied or borrowed as in
- * gv_problem) and return a ticket.  Problems run concurrently on the device,
- * admitted as memory frees up; results equal gv_solve's. */
+ * gv_problem) and return a ticket.  The first call starts the context's
+ * serving lanes (four by default: a host thread, HIP stream and allocator
+ * each); a free lane takes queued problems as the memory budget allows, so
+ * problems run concurrently on the device.  Results equal gv_solve's. */
 gv_status gv_submit(gv_ctx *ctx, const gv_problem *p, uint64_t *ticket);
 
 /* Wait up to timeout_ms (0: do not wait, <0: forever) for a ticket; on

@@ -130,3 +130,28 @@ def test_serving_error_paths(ctx):
         assert st == 0
     st, _ = gvote.poll(ctx, ts[-1], len(big["cols"][0]))
     assert st in (0, -7)
+
+
+def test_solve_while_serving(ctx):
+    """gv_solve on the context's stream while the serving lanes run submitted
+    problems: both give the results of solving each problem alone."""
+    import threading
+    from paper_2107_11810_amd import gvote
+    probs = pose_batch(10, seed0=900)
+    lin = [synth.config("plane3d_small", seed=s) for s in (51, 52, 53)]
+    ref = [ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"]) for g in probs]
+    ref_lin = [ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"]) for g in lin]
+    _say("serving while solving")
+    tickets = [gvote.submit(ctx, g["family"], g["cols"], g["lo"], g["hi"], g["eps"]) for g in probs]
+    out = {}
+
+    def solver():
+        out["lin"] = [ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"]) for g in lin]
+    th = threading.Thread(target=solver)
+    th.start()
+    for g, t, a in zip(probs, tickets, ref):
+        st, r = gvote.poll(ctx, t, len(g["cols"][0]))
+        assert st == 0 and same(r, a)
+    th.join()
+    for r, a in zip(out["lin"], ref_lin):
+        assert same(r, a)
