@@ -290,7 +290,9 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const P
   return mask;
 }
 
-template <typename E>
+// UNIT: every multiplicity is 1, so a child's count is the popcount of its
+// ballot (scalar), else per-lane sums reduced across the wave.
+template <typename E, bool UNIT>
 __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Ptab, int m, LevelC lv,
                                                     const Cell* __restrict__ cells, const Item* __restrict__ items,
                                                     const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
@@ -323,25 +325,36 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pt
     uint32_t aw[16], an[16];
 #pragma unroll
     for (int ch = 0; ch < 16; ch++) { aw[ch] = 0; an[ch] = 0; }
-    for (uint32_t k = lane; k < cnt; k += 64) {
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
+      const uint32_t k = k0 + lane;
       const uint64_t ei = I.off + k;
-      const E e = ents[ei];
-      uint32_t mask;
-      if constexpr (sizeof(E) == sizeof(EntQ64)) {
-        mask = pose_mask64(P, lv, B, sector, e.W1, e.W2, e.W3, e.xi, e.eta);
-      } else {
-        mask = pose_mask32(P, lv, B, Bf, sector, e, m64, n_root, nre);
+      uint32_t mask = 0, w = 0;
+      if (k < cnt) {
+        const E e = ents[ei];
+        w = e.w;
+        if constexpr (sizeof(E) == sizeof(EntQ64)) {
+          mask = pose_mask64(P, lv, B, sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+        } else {
+          mask = pose_mask32(P, lv, B, Bf, sector, e, m64, n_root, nre);
+        }
+        masks[ei] = (uint16_t)mask;
       }
 #pragma unroll
       for (int ch = 0; ch < 16; ch++) {
-        if ((mask >> ch) & 1u) { aw[ch] += e.w; an[ch] += 1u; }
+        const bool p = (mask >> ch) & 1u;
+        if constexpr (UNIT) {
+          an[ch] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
+        } else {
+          aw[ch] += p ? w : 0u;
+          an[ch] += p ? 1u : 0u;
+        }
       }
-      masks[ei] = (uint16_t)mask;
     }
 #pragma unroll
     for (int ch = 0; ch < 16; ch++) {
       if ((uint32_t)ch < nch) {
-        uint32_t w = wave_sum_u32(aw[ch]), n = wave_sum_u32(an[ch]);
+        const uint32_t n = UNIT ? an[ch] : wave_sum_u32(an[ch]);
+        const uint32_t w = UNIT ? n : wave_sum_u32(aw[ch]);
         if (lane == 0 && n) {
           atomicAdd(&ccnt[I.cell * nch + ch], w);
           atomicAdd(&cnent[I.cell * nch + ch], n);

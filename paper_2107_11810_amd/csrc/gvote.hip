@@ -638,9 +638,16 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   X.stats.test_launches++;
   X.stats.test_bytes += linear ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
   if constexpr (FAM == FAM_POSE4DOF) {
-    k_count_pose<E><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, X.m64,
-                                             X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck,
-                                             itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
+    if (b.unit)
+      k_count_pose<E, true><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
+                                                     X.m64, X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent,
+                                                     X.drecheck, itemcnt ? itemcnt : X.dummy,
+                                                     itemcnt ? pa->istride : 0u);
+    else
+      k_count_pose<E, false><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
+                                                      X.m64, X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent,
+                                                      X.drecheck, itemcnt ? itemcnt : X.dummy,
+                                                      itemcnt ? pa->istride : 0u);
   } else {
 #define GV_COUNT_LIN(U, N) \
   k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, (const E*)b.ents, itemcnt, itemw)
