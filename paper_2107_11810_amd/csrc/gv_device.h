@@ -351,24 +351,33 @@ template <typename R> __device__ inline R rmax2_of(const VBox<R>& v) {
 }
 
 // silhouette corners: V's angular span runs from (ax,ay) counter-clockwise to
-// (bx,by); returns false when V holds the apex
+// (bx,by); returns false when V holds the apex.  The corner of each case
+// (V right of, left of or across the vertical axis, and above, below or
+// across the horizontal one) is picked by selects, without branches.
 template <typename R>
 __device__ inline bool silhouette(const VBox<R>& v, R& ax, R& ay, R& bx, R& by) {
-  R z = (R)0;
-  if (v.x0 > z) {
-    if (v.y0 > z) { ax = v.x1; ay = v.y0; bx = v.x0; by = v.y1; }
-    else if (v.y1 < z) { ax = v.x0; ay = v.y0; bx = v.x1; by = v.y1; }
-    else { ax = v.x0; ay = v.y0; bx = v.x0; by = v.y1; }
-  } else if (v.x1 < z) {
-    if (v.y0 > z) { ax = v.x1; ay = v.y1; bx = v.x0; by = v.y0; }
-    else if (v.y1 < z) { ax = v.x0; ay = v.y1; bx = v.x1; by = v.y0; }
-    else { ax = v.x1; ay = v.y1; bx = v.x1; by = v.y0; }
-  } else {
-    if (v.y0 > z) { ax = v.x1; ay = v.y0; bx = v.x0; by = v.y0; }
-    else if (v.y1 < z) { ax = v.x0; ay = v.y1; bx = v.x1; by = v.y1; }
-    else return false;
-  }
-  return true;
+  const R z = (R)0;
+  const bool right = v.x0 > z, left = v.x1 < z, up = v.y0 > z, down = v.y1 < z;
+  ax = (up || (left && !down)) ? v.x1 : v.x0;
+  ay = (left || (!right && down)) ? v.y1 : v.y0;
+  bx = (down || (left && !up)) ? v.x1 : v.x0;
+  by = (right || (!left && down)) ? v.y1 : v.y0;
+  return right || left || up || down;
+}
+
+// kappa-half edge directions of one kappa interval [Llo, Lhi] for one
+// surface: e_lo = (1 - Llo xi, Llo + xi), e_hi likewise, and (binary32) the
+// magnitudes that scale their certified cross-product bounds
+template <typename R> struct KEdge { R pl, ph, elx, ely, ehx, ehy; };
+template <typename R> __device__ inline KEdge<R> kedge(R xi, R Llo, R Lhi) {
+  KEdge<R> e;
+  e.pl = Llo * xi;
+  e.ph = Lhi * xi;
+  e.elx = (R)1 - e.pl;
+  e.ely = Llo + xi;
+  e.ehx = (R)1 - e.ph;
+  e.ehy = Lhi + xi;
+  return e;
 }
 
 // z-half in binary64: z = W3 - eta r over r in [r_min, r_max] must reach
@@ -384,21 +393,43 @@ __device__ inline bool zhalf64(double W3, double eta, double rmin2, double rmax2
   return lo_ok && hi_ok;
 }
 
+// z-half terms that do not depend on the (x, y) part of the child: the
+// signed reach of the surface's height range against the child's padded z
+// interval, oriented so that the slope a = |eta| is non-negative
+template <typename R> struct ZPre { R Tlo, Thi, a2, Ylo, Yhi; };
+template <typename R> __device__ inline ZPre<R> zpre(R W3, R eta, R ZH, R ZL) {
+  ZPre<R> z;
+  const R Glo = W3 - ZH, Ghi = W3 - ZL;
+  R a;
+  if (eta >= (R)0) { z.Tlo = Glo; z.Thi = Ghi; a = eta; }
+  else { z.Tlo = -Ghi; z.Thi = -Glo; a = -eta; }
+  z.a2 = a * a;
+  z.Ylo = z.Tlo * z.Tlo;
+  z.Yhi = z.Thi * z.Thi;
+  return z;
+}
+__device__ inline bool zhalf64p(const ZPre<double>& z, double rmin2, double rmax2) {
+  const bool lo_ok = (z.Tlo <= 0.0) || (z.a2 * rmax2 >= z.Ylo);
+  const bool hi_ok = (z.Thi >= 0.0) && (z.a2 * rmin2 <= z.Yhi);
+  return lo_ok && hi_ok;
+}
+
 // kappa-half in binary64: the cone of directions with kappa in [Llo, Lhi]
 // (kappa = (v2 - xi v1)/(v1 + xi v2), v1 + xi v2 > 0) meets V.
-__device__ inline bool khalf64(const VBox<double>& v, double rmin2, double Rg2, double xi, double Llo,
-                               double Lhi) {
+__device__ inline bool khalf64e(const VBox<double>& v, double rmin2, double Rg2, const KEdge<double>& e) {
   if (rmin2 < Rg2) return true;  // apex guard
   double ax, ay, bx, by;
   if (!silhouette(v, ax, ay, bx, by)) return true;
-  double elx = 1.0 - Llo * xi, ely = Llo + xi;
-  double ehx = 1.0 - Lhi * xi, ehy = Lhi + xi;
-  double c1 = elx * ay - ely * ax;  // cross(e_lo, a)
-  double c2 = ax * ehy - ay * ehx;  // cross(a, e_hi)
-  double c3 = elx * by - ely * bx;  // cross(e_lo, b)
-  double c4 = bx * ehy - by * ehx;  // cross(b, e_hi)
+  double c1 = e.elx * ay - e.ely * ax;  // cross(e_lo, a)
+  double c2 = ax * e.ehy - ay * e.ehx;  // cross(a, e_hi)
+  double c3 = e.elx * by - e.ely * bx;  // cross(e_lo, b)
+  double c4 = bx * e.ehy - by * e.ehx;  // cross(b, e_hi)
   return (c1 >= 0.0 && c2 >= 0.0) || (c3 >= 0.0 && c4 >= 0.0) || (c1 <= 0.0 && c3 >= 0.0) ||
          (c2 >= 0.0 && c4 <= 0.0);
+}
+__device__ inline bool khalf64(const VBox<double>& v, double rmin2, double Rg2, double xi, double Llo,
+                               double Lhi) {
+  return khalf64e(v, rmin2, Rg2, kedge<double>(xi, Llo, Lhi));
 }
 
 // binary32 filters: return 1 (meets), 0 (misses) or -1 (undecided: the
@@ -408,48 +439,41 @@ __device__ inline bool khalf64(const VBox<double>& v, double rmin2, double Rg2, 
 
 __device__ inline int sgn_cert(float v, float bound) { return v > bound ? 1 : (v < -bound ? -1 : 0); }
 
-__device__ inline int zhalf32(float W3, float eta, float rmin2, float rmax2, float ZH, float ZL) {
-  float Glo = W3 - ZH, Ghi = W3 - ZL;  // exact
-  float Tlo, Thi, a;
-  if (eta >= 0.0f) { Tlo = Glo; Thi = Ghi; a = eta; }
-  else { Tlo = -Ghi; Thi = -Glo; a = -eta; }
-  float a2 = a * a;
-  int lo_ok, hi_ok;
-  if (Tlo <= 0.0f) lo_ok = 1;
+
+__device__ inline int zhalf32p(const ZPre<float>& z, float rmin2, float rmax2) {
+  int lo_ok;
+  if (z.Tlo <= 0.0f) lo_ok = 1;
   else {
-    float X = a2 * rmax2, Y = Tlo * Tlo;
-    int s = sgn_cert(X - Y, 8.0f * GV_U32 * (X + Y));
+    float X = z.a2 * rmax2;
+    int s = sgn_cert(X - z.Ylo, 8.0f * GV_U32 * (X + z.Ylo));
     lo_ok = s > 0 ? 1 : (s < 0 ? 0 : -1);
   }
   if (lo_ok == 0) return 0;
-  if (Thi < 0.0f) return 0;
-  {
-    float X = a2 * rmin2, Y = Thi * Thi;
-    int s = sgn_cert(Y - X, 8.0f * GV_U32 * (X + Y));
-    hi_ok = s > 0 ? 1 : (s < 0 ? 0 : -1);
-  }
+  if (z.Thi < 0.0f) return 0;
+  float X = z.a2 * rmin2;
+  int s = sgn_cert(z.Yhi - X, 8.0f * GV_U32 * (X + z.Yhi));
+  const int hi_ok = s > 0 ? 1 : (s < 0 ? 0 : -1);
   if (hi_ok == 0) return 0;
   return (lo_ok == 1 && hi_ok == 1) ? 1 : -1;
 }
 
-__device__ inline int khalf32(const VBox<float>& v, float rmin2, float Rg2, float xi, float Llo, float Lhi) {
+__device__ inline int khalf32e(const VBox<float>& v, float rmin2, float Rg2, const KEdge<float>& e, float Sl,
+                               float Sh) {
   int g = sgn_cert(Rg2 - rmin2, 4.0f * GV_U32 * (Rg2 + rmin2));
   if (g > 0) return 1;  // apex guard certified
   if (g == 0) return -1;
   float ax, ay, bx, by;
   if (!silhouette(v, ax, ay, bx, by)) return 1;
-  float pl = Llo * xi, ph = Lhi * xi;
-  float elx = 1.0f - pl, ely = Llo + xi;
-  float ehx = 1.0f - ph, ehy = Lhi + xi;
-  float Sl = fabsf(pl) + fabsf(elx) + fabsf(ely);
-  float Sh = fabsf(ph) + fabsf(ehx) + fabsf(ehy);
   float Na = fabsf(ax) + fabsf(ay), Nb = fabsf(bx) + fabsf(by);
   const float k = 8.0f * GV_U32;
-  int s1 = sgn_cert(elx * ay - ely * ax, k * Sl * Na);
-  int s2 = sgn_cert(ax * ehy - ay * ehx, k * Sh * Na);
-  int s3 = sgn_cert(elx * by - ely * bx, k * Sl * Nb);
-  int s4 = sgn_cert(bx * ehy - by * ehx, k * Sh * Nb);
+  int s1 = sgn_cert(e.elx * ay - e.ely * ax, k * Sl * Na);
+  int s2 = sgn_cert(ax * e.ehy - ay * e.ehx, k * Sh * Na);
+  int s3 = sgn_cert(e.elx * by - e.ely * bx, k * Sl * Nb);
+  int s4 = sgn_cert(bx * e.ehy - by * e.ehx, k * Sh * Nb);
   if (s1 == 0 || s2 == 0 || s3 == 0 || s4 == 0) return -1;
   bool r = (s1 > 0 && s2 > 0) || (s3 > 0 && s4 > 0) || (s1 < 0 && s3 > 0) || (s2 > 0 && s4 < 0);
   return r ? 1 : 0;
 }
+// magnitudes bounding the rounding of the cross products with e_lo, e_hi
+__device__ inline float kedge_sl(const KEdge<float>& e) { return fabsf(e.pl) + fabsf(e.elx) + fabsf(e.ely); }
+__device__ inline float kedge_sh(const KEdge<float>& e) { return fabsf(e.ph) + fabsf(e.ehx) + fabsf(e.ehy); }

@@ -198,6 +198,9 @@ __device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const P
                                        double W1, double W2, double W3, double xi, double eta) {
   const uint32_t nch = 1u << lv.abits;
   uint32_t zbits = 0, kbits = 0;  // bit (bx | by<<1 | b<<2)
+  // terms shared by the four (x, y) parts
+  const ZPre<double> zp[2] = {zpre<double>(W3, eta, B.ZH[0], B.ZL[0]), zpre<double>(W3, eta, B.ZH[1], B.ZL[1])};
+  const KEdge<double> ke[2] = {kedge<double>(xi, B.Llo[0], B.Lhi[0]), kedge<double>(xi, B.Llo[1], B.Lhi[1])};
 #pragma unroll
   for (int xy = 0; xy < 4; xy++) {
     int bx = xy & 1, by = xy >> 1;
@@ -207,12 +210,12 @@ __device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const P
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       if (b && !lv.split[2]) continue;
-      if (zhalf64(W3, eta, rmin2, rmax2, B.ZH[b], B.ZL[b])) zbits |= 1u << (xy | (b << 2));
+      if (zhalf64p(zp[b], rmin2, rmax2)) zbits |= 1u << (xy | (b << 2));
     }
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       if (b && !lv.split[3]) continue;
-      if (khalf64(v, rmin2, P.Rg2, xi, B.Llo[b], B.Lhi[b])) kbits |= 1u << (xy | (b << 2));
+      if (khalf64e(v, rmin2, P.Rg2, ke[b])) kbits |= 1u << (xy | (b << 2));
     }
   }
   uint32_t mask = 0;
@@ -236,6 +239,10 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const P
   // Bf layout: Xlo[2] Xhi[2] Ylo[2] Yhi[2] ZH[2] ZL[2] Llo[2] Lhi[2]
   bool have64 = false;
   double W1 = 0, W2 = 0, W3 = 0, xi = 0, eta = 0;
+  // terms shared by the four (x, y) parts
+  const ZPre<float> zp[2] = {zpre<float>(e.W3, e.eta, Bf[8], Bf[10]), zpre<float>(e.W3, e.eta, Bf[9], Bf[11])};
+  const KEdge<float> ke[2] = {kedge<float>(e.xi, Bf[12], Bf[14]), kedge<float>(e.xi, Bf[13], Bf[15])};
+  const float Sl[2] = {kedge_sl(ke[0]), kedge_sl(ke[1])}, Sh[2] = {kedge_sh(ke[0]), kedge_sh(ke[1])};
 #pragma unroll
   for (int xy = 0; xy < 4; xy++) {
     int bx = xy & 1, by = xy >> 1;
@@ -246,12 +253,12 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const P
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       if (b && !lv.split[2]) continue;
-      zr[b] = zhalf32(e.W3, e.eta, rmin2, rmax2, Bf[8 + b], Bf[10 + b]);
+      zr[b] = zhalf32p(zp[b], rmin2, rmax2);
     }
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       if (b && !lv.split[3]) continue;
-      kr[b] = khalf32(v, rmin2, P.Rg2f, e.xi, Bf[12 + b], Bf[14 + b]);
+      kr[b] = khalf32e(v, rmin2, P.Rg2f, ke[b], Sl[b], Sh[b]);
     }
     bool need = (zr[0] < 0) || (zr[1] < 0) || (kr[0] < 0) || (kr[1] < 0);
     if (need) {
