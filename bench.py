@@ -171,6 +171,14 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
 
 
+def per_kernel(name, ms, nbytes, launches, steps):
+    """Achieved algorithmic HBM rate of one kernel over the timed solves."""
+    gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"kernel": name, "launches": launches, "ms_per_step": round(ms / steps, 2),
+            "bytes_per_launch": int(nbytes / launches) if launches else None,
+            "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of the kernel from the committed memory-counter
     record (profiles/traffic.json), or None when there is none or the kernel
@@ -265,7 +273,10 @@ def main():
             "launches": kn, "avg_launch_us": round(kms / kn * 1e3, 2) if kn else None,
             "bytes_per_launch": int(kb / kn) if kn else None,
             "kernel_ms_per_step": round(kms / len(results), 2),
-            "other_kernel_ms_per_step": round((c_ms if kname == W["kernel"] else t_ms) / len(results), 2)}
+            "other_kernel_ms_per_step": round((c_ms if kname == W["kernel"] else t_ms) / len(results), 2),
+            # both big kernels: the incidence test (count pass) and compaction
+            "kernels": [per_kernel(W["kernel"], t_ms, t_b, t_n, len(results)),
+                        per_kernel(W["compact"], c_ms, c_b, c_n, len(results))]}
     out = {
         "metric": "incidence tests/s",
         "value": tests / sec,
