@@ -258,7 +258,6 @@ template <> __device__ __host__ inline EntP3p store_ent<FAM_PLANE3D, EntP3p>(con
   return pack_p3(s.K[0][0], s.K[0][1], s.F[0], (uint32_t)s.w);
 }
 
-template <int FAM> __device__ inline LinS load_lin(const typename EntOf<FAM>::T& e) { return load_ent<FAM>(e); }
 template <int FAM> __device__ inline typename EntOf<FAM>::T store_lin(const LinS& s) {
   bool ok = true;
   return store_ent<FAM, typename EntOf<FAM>::T>(s, ok);

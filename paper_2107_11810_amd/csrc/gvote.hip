@@ -376,6 +376,7 @@ struct Parent {
   uint32_t istride = 0;
   int pending = 0;
   bool sorted = true;  // children in descending count order
+  uint64_t kept_entries = 0;  // entries of all kept children
   bool unit = true;    // every multiplicity is 1
 };
 
@@ -696,8 +697,8 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
                                         X.dbest, keepf, keptn);
   }
   HIPCHK(hipGetLastError());
-  dfree(X, keptn);
   if (leaf) {
+    dfree(X, keptn);
     if (!dive) X.beam = false;
     dfree(X, keepf);
     dfree(X, ccnt);
@@ -708,7 +709,19 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   uint32_t* keepscan = dalloc<uint32_t>(X, nk);
   excl_scan(X, keepf, keepscan, nk);
   k_kept_total<<<1, 64, 0, X.st>>>(keepf, keepscan, nk, X.dtot);
-  const uint64_t nkept = d2h1(X, X.dtot);
+  {
+    size_t tb = 0;
+    HIPCHK(hipcub::DeviceReduce::Sum(nullptr, tb, keptn, X.dtot + 1, (int)nk, X.st));
+    void* tmp = dalloc<char>(X, tb);
+    HIPCHK(hipcub::DeviceReduce::Sum(tmp, tb, keptn, X.dtot + 1, (int)nk, X.st));
+    dfree(X, tmp);
+  }
+  dfree(X, keptn);
+  uint64_t kt[2];
+  HIPCHK(hipMemcpyAsync(kt, X.dtot, sizeof(kt), hipMemcpyDeviceToHost, X.st));
+  HIPCHK(hipStreamSynchronize(X.st));
+  const uint64_t nkept = kt[0];
+  pa->kept_entries = kt[1];
   X.stats.cells_pruned += nk - nkept;
   if (X.trace) {
     const uint64_t bst = d2h1(X, X.dbest);
@@ -927,7 +940,17 @@ bool materialize_at(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
 template <int FAM, typename E, typename M>
 void push_children(Run& X, Parent* pa, std::vector<Task>& stack) {
   std::vector<std::pair<uint32_t, uint32_t>> chunks;
-  plan_chunks(X, pa, chunks);
+  // all kept children in one chunk when they fit (no need to sample the
+  // list offsets), else the chunk schedule
+  const int lc = std::min(pa->level + 1, X.P0.Lstar - 1);
+  const double per_cell = 64.0 + 40.0 * (double)(1u << X.P0.lev[lc].abits);
+  const double per_ent = (double)X.ent_bytes + 8.0;
+  const uint64_t cap = X.beam ? X.first_cells : (1ull << 30);
+  if ((uint64_t)pa->nkept <= cap &&
+      (double)pa->kept_entries * per_ent + (double)pa->nkept * per_cell <= (double)X.chunk_bytes)
+    chunks.push_back({0u, pa->nkept});
+  else
+    plan_chunks(X, pa, chunks);
   pa->pending = (int)chunks.size();
   for (auto it = chunks.rbegin(); it != chunks.rend(); ++it) {
     Task t{};
