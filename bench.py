@@ -67,6 +67,10 @@ def serve_bench(args):
         dur.append(time.perf_counter() - t1)
     t_plain = time.perf_counter() - t0
     print(f"plain binary64 one at a time: {t_plain:.2f} s", file=sys.stderr, flush=True)
+    slow = sorted(range(len(dur)), key=lambda i: -dur[i])[:5]
+    print("slowest plain solves: " + ", ".join(
+        f"#{i} n={len(probs[i]['cols'][0])} {dur[i]*1e3:.0f} ms (library {plain[i]['stats']['ms_total']:.0f} ms, "
+        f"{plain[i]['stats']['tests']:.3g} tests)" for i in slow), file=sys.stderr, flush=True)
 
     def submit_all(order_times=None, tickets=None, arrivals=None):
         tickets = [] if tickets is None else tickets

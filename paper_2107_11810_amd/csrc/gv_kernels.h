@@ -185,10 +185,12 @@ __device__ inline void pose_level_boxes(const ProbC& P, const LevelC& lv, const 
   }
 }
 
-// binary64 mask over the children of one cell for one surface
+// binary64 mask over the children of one cell for one surface.  ALL: every
+// axis splits at this level (16 children), so no per-axis checks.
+template <bool ALL>
 __device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const PoseLevel& B, int sector,
                                        double W1, double W2, double W3, double xi, double eta) {
-  const uint32_t nch = 1u << lv.abits;
+  const uint32_t nch = ALL ? 16u : 1u << lv.abits;
   uint32_t zbits = 0, kbits = 0;  // bit (bx | by<<1 | b<<2)
   // terms shared by the four (x, y) parts
   const ZPre<double> zp[2] = {zpre<double>(W3, eta, B.ZH[0], B.ZL[0]), zpre<double>(W3, eta, B.ZH[1], B.ZL[1])};
@@ -196,17 +198,17 @@ __device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const P
 #pragma unroll
   for (int xy = 0; xy < 4; xy++) {
     int bx = xy & 1, by = xy >> 1;
-    if ((bx && !lv.split[0]) || (by && !lv.split[1])) continue;
+    if (!ALL && ((bx && !lv.split[0]) || (by && !lv.split[1]))) continue;
     VBox<double> v = pose_vbox<double>(W1, W2, B.Xlo[bx], B.Xhi[bx], B.Ylo[by], B.Yhi[by], sector);
     double rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
 #pragma unroll
     for (int b = 0; b < 2; b++) {
-      if (b && !lv.split[2]) continue;
+      if (!ALL && b && !lv.split[2]) continue;
       if (zhalf64p(zp[b], rmin2, rmax2)) zbits |= 1u << (xy | (b << 2));
     }
 #pragma unroll
     for (int b = 0; b < 2; b++) {
-      if (b && !lv.split[3]) continue;
+      if (!ALL && b && !lv.split[3]) continue;
       if (khalf64e(v, rmin2, P.Rg2, ke[b])) kbits |= 1u << (xy | (b << 2));
     }
   }
@@ -222,11 +224,14 @@ __device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const P
   return mask;
 }
 
-// binary32 mask with binary64 recheck of undecided halves
-__device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const PoseLevel& B, const float* Bf,
+// binary32 mask with binary64 recheck of undecided halves (the binary64
+// child boxes are built only when a recheck needs them)
+template <bool ALL>
+__device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const Cell& C, int m, const float* Bf,
                                        int sector, const EntQ32& e, const double* __restrict__ m64,
                                        uint64_t n_root, uint32_t& nrecheck) {
-  const uint32_t nch = 1u << lv.abits;
+  const uint32_t nch = ALL ? 16u : 1u << lv.abits;
+  PoseLevel B;
   uint32_t zbits = 0, kbits = 0;
   // Bf layout: Xlo[2] Xhi[2] Ylo[2] Yhi[2] ZH[2] ZL[2] Llo[2] Lhi[2]
   bool have64 = false;
@@ -238,18 +243,18 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const P
 #pragma unroll
   for (int xy = 0; xy < 4; xy++) {
     int bx = xy & 1, by = xy >> 1;
-    if ((bx && !lv.split[0]) || (by && !lv.split[1])) continue;
+    if (!ALL && ((bx && !lv.split[0]) || (by && !lv.split[1]))) continue;
     VBox<float> v = pose_vbox<float>(e.W1, e.W2, Bf[0 + bx], Bf[2 + bx], Bf[4 + by], Bf[6 + by], sector);
     float rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
     int zr[2] = {0, 0}, kr[2] = {0, 0};
 #pragma unroll
     for (int b = 0; b < 2; b++) {
-      if (b && !lv.split[2]) continue;
+      if (!ALL && b && !lv.split[2]) continue;
       zr[b] = zhalf32p(zp[b], rmin2, rmax2);
     }
 #pragma unroll
     for (int b = 0; b < 2; b++) {
-      if (b && !lv.split[3]) continue;
+      if (!ALL && b && !lv.split[3]) continue;
       kr[b] = khalf32e(v, rmin2, P.Rg2f, ke[b], Sl[b], Sh[b]);
     }
     bool need = (zr[0] < 0) || (zr[1] < 0) || (kr[0] < 0) || (kr[1] < 0);
@@ -261,6 +266,7 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const P
         W3 = m64[2 * n_root + r];
         xi = m64[3 * n_root + r];
         eta = m64[4 * n_root + r];
+        pose_level_boxes(P, lv, C, m, B);
         have64 = true;
       }
       VBox<double> vd = pose_vbox<double>(W1, W2, B.Xlo[bx], B.Xhi[bx], B.Ylo[by], B.Yhi[by], sector);
@@ -291,7 +297,7 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const P
 
 // UNIT: every multiplicity is 1, so a child's count is the popcount of its
 // ballot (scalar), else per-lane sums reduced across the wave.
-template <typename E, bool UNIT>
+template <typename E, bool UNIT, bool ALL>
 __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Ptab, int m, LevelC lv,
                                                     const Cell* __restrict__ cells, const Item* __restrict__ items,
                                                     const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
@@ -300,7 +306,7 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pt
                                                     uint32_t* __restrict__ cnent,
                                                     unsigned long long* __restrict__ rechecks,
                                                     uint32_t* __restrict__ itemcnt, uint32_t istride) {
-  const uint32_t nch = 1u << lv.abits;
+  const uint32_t nch = ALL ? 16u : 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -332,9 +338,9 @@ __global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Pt
         const E e = ents[ei];
         w = e.w;
         if constexpr (sizeof(E) == sizeof(EntQ64)) {
-          mask = pose_mask64(P, lv, B, sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+          mask = pose_mask64<ALL>(P, lv, B, sector, e.W1, e.W2, e.W3, e.xi, e.eta);
         } else {
-          mask = pose_mask32(P, lv, B, Bf, sector, e, m64, n_root, nre);
+          mask = pose_mask32<ALL>(P, lv, C, m, Bf, sector, e, m64, n_root, nre);
         }
         masks[ei] = (uint16_t)mask;
       }

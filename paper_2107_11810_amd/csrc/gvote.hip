@@ -48,22 +48,28 @@ struct DevCache {
     size_t step = (size_t)1 << (e >= 3 ? e - 3 : 0);
     return (b + step - 1) / step * step;
   }
+  // a cached block serves a request up to 1.25x its size (1.5x from 64 MB
+  // on, where sizes vary most and each new block costs the most)
+  static size_t slack(size_t r) { return r >= (64ull << 20) ? r / 2 : r / 4; }
+  void* take(std::multimap<size_t, void*>::iterator it) {
+    void* p = it->second;
+    live[p] = it->first;
+    in_use += it->first;
+    cached -= it->first;
+    free_blocks.erase(it);
+    peak = std::max(peak, in_use);
+    return p;
+  }
   void* get(size_t bytes, hipStream_t st, std::string& err) {
     const size_t r = round(bytes);
     auto it = free_blocks.lower_bound(r);
-    if (it != free_blocks.end() && it->first <= r + r / 4) {
-      void* p = it->second;
-      live[p] = it->first;
-      in_use += it->first;
-      cached -= it->first;
-      free_blocks.erase(it);
-      peak = std::max(peak, in_use);
-      return p;
-    }
+    if (it != free_blocks.end() && it->first <= r + slack(r)) return take(it);
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, r);
     if (e != hipSuccess) {
       (void)hipGetLastError();
+      // out of device memory: any cached block large enough, else free them all
+      if (it != free_blocks.end()) return take(it);
       trim(st);
       e = hipMalloc(&p, r);
       if (e != hipSuccess) {
@@ -76,6 +82,17 @@ struct DevCache {
     in_use += r;
     peak = std::max(peak, in_use);
     return p;
+  }
+  // free the largest cached blocks until at most target bytes stay cached
+  void release_to(uint64_t target, hipStream_t st) {
+    if (cached <= target) return;
+    (void)hipStreamSynchronize(st);
+    while (cached > target && !free_blocks.empty()) {
+      auto it = std::prev(free_blocks.end());
+      (void)hipFree(it->second);
+      cached -= it->first;
+      free_blocks.erase(it);
+    }
   }
   void put(void* p) {
     auto it = live.find(p);
@@ -639,16 +656,20 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   X.stats.test_launches++;
   X.stats.test_bytes += linear ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
   if constexpr (FAM == FAM_POSE4DOF) {
-    if (b.unit)
-      k_count_pose<E, true><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
-                                                     X.m64, X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent,
-                                                     X.drecheck, itemcnt ? itemcnt : X.dummy,
-                                                     itemcnt ? pa->istride : 0u);
-    else
-      k_count_pose<E, false><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,
-                                                      X.m64, X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent,
-                                                      X.drecheck, itemcnt ? itemcnt : X.dummy,
-                                                      itemcnt ? pa->istride : 0u);
+#define GV_COUNT_POSE(U, A)                                                                                 \
+  k_count_pose<E, U, A><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, \
+                                                X.m64, X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck, \
+                                                itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u)
+    // every axis splits at most levels: that variant has no per-axis checks
+    const bool all = lv.abits == 4;
+    if (b.unit) {
+      if (all) GV_COUNT_POSE(true, true);
+      else GV_COUNT_POSE(true, false);
+    } else {
+      if (all) GV_COUNT_POSE(false, true);
+      else GV_COUNT_POSE(false, false);
+    }
+#undef GV_COUNT_POSE
   } else {
 #define GV_COUNT_LIN(U, N) \
   k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, (const E*)b.ents, itemcnt, itemw)
@@ -1685,7 +1706,8 @@ void lane_main(Lane* L) {
     }
     epoch_release(X);
     // keep this lane's share of cached blocks bounded
-    if (L->cache.cached > ctx->budget / (uint64_t)(2 * std::max(1, ctx->nlanes))) L->cache.trim(L->st);
+    if (L->cache.cached > ctx->budget / (uint64_t)(2 * std::max(1, ctx->nlanes)))
+      L->cache.release_to(ctx->budget / (uint64_t)(4 * std::max(1, ctx->nlanes)), L->st);
     publish(ctx, admit);
   }
 }
@@ -1825,6 +1847,9 @@ gv_status gv_solve(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
     ctx->err.clear();
     std::vector<ProbRec*> v{&pr};
     run_epoch(ctx, v);
+    // bounded cache: many problems of different sizes would otherwise fill
+    // the device with idle blocks, and then free them all at once
+    if (ctx->cache.cached > ctx->budget / 2) ctx->cache.release_to(ctx->budget / 4, ctx->stream);
   }
   if (pr.st != GV_OK) {
     set_err(ctx, pr.err.empty() ? ctx->err : pr.err);
