@@ -298,7 +298,7 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const C
 // UNIT: every multiplicity is 1, so a child's count is the popcount of its
 // ballot (scalar), else per-lane sums reduced across the wave.
 template <typename E, bool UNIT, bool ALL>
-__global__ void __launch_bounds__(256) k_count_pose(const ProbC* __restrict__ Ptab, int m, LevelC lv,
+__global__ void __launch_bounds__(256, 4) k_count_pose(const ProbC* __restrict__ Ptab, int m, LevelC lv,
                                                     const Cell* __restrict__ cells, const Item* __restrict__ items,
                                                     const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
                                                     const double* __restrict__ m64, uint64_t n_root,
