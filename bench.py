@@ -199,6 +199,22 @@ def measured_traffic(workload, kernel):
     return int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
 
 
+def measured_valu(workload, kernel):
+    """VALU lane-operations per incidence test of the kernel from the
+    committed counter record (profiles/valu.json), or None when there is
+    none or the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "valu.json")))[workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_2107_11810_amd", "csrc", f), "rb").read()
+                   for f in ("gv_device.h", "gv_kernels.h"))
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(rec["lane_ops_per_test"])
+
+
 def cpu_baseline(g, budget_tests):
     """The oracle as it stands, single thread, stopped after a fixed number
     of incidence tests of the same solve."""
@@ -281,6 +297,16 @@ def main():
             # both big kernels: the incidence test (count pass) and compaction
             "kernels": [per_kernel(W["kernel"], t_ms, t_b, t_n, len(results)),
                         per_kernel(W["compact"], c_ms, c_b, c_n, len(results))]}
+    if W["bound"] == "alu" and kname == W["kernel"]:
+        # the incidence kernel of this family is bound by vector ALU work:
+        # lane-operations per test (counted once with rocprofv3, see
+        # profiles/valu.json) times the tests, over its event time
+        opt = measured_valu(args.workload, kname)
+        if opt is not None and kms > 0:
+            ach = opt * tests / (kms * 1e-3) / 1e12
+            roof.update({"bound": "alu", "achieved": round(ach, 2), "peak": VALU_LANE_OPS / 1e12,
+                         "unit": "T lane-ops/s", "frac": round(ach / (VALU_LANE_OPS / 1e12), 4),
+                         "lane_ops_per_test": round(opt, 2)})
     out = {
         "metric": "incidence tests/s",
         "value": tests / sec,
