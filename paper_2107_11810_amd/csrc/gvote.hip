@@ -432,6 +432,8 @@ struct Run {
   uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
   uint64_t dive_cells = 16384;            // cells from which the diversified dive goes greedy
   bool root_dive = false;                 // greedy dive from the root cells first (the diversified dive subsumes it)
+  uint64_t waits = 0;                     // host waits for the stream, and their time
+  double wait_ms = 0.0;
   bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
   bool beam = true;                       // progressive chunks until the first leaf level
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
@@ -448,6 +450,14 @@ struct Run {
   bool own_first = true;
   std::chrono::steady_clock::time_point t0;
 };
+
+// the host waits for the epoch's stream (counted for the trace line)
+void host_wait(Run& X) {
+  const auto t = std::chrono::steady_clock::now();
+  HIPCHK(hipStreamSynchronize(X.st));
+  X.waits++;
+  X.wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+}
 
 // epochs of gv_solve / gv_parametrize use the context's stream and allocator
 void bind_ctx(Run& X, gv_ctx* c) {
@@ -505,7 +515,7 @@ template <typename T>
 uint64_t d2h1(Run& X, const T* p) {
   T v{};
   HIPCHK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   return (uint64_t)v;
 }
 
@@ -560,7 +570,7 @@ void group_batch(Run& X, Batch& b, bool own_ents) {
   uint32_t last[2];
   HIPCHK(hipMemcpyAsync(&last[0], hscan + n - 1, 4, hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipMemcpyAsync(&last[1], head + n - 1, 4, hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   const uint64_t U = (uint64_t)last[0] + last[1];
   if (U < n) {
     E* out = dalloc<E>(X, U);
@@ -740,7 +750,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   dfree(X, keptn);
   uint64_t kt[2];
   HIPCHK(hipMemcpyAsync(kt, X.dtot, sizeof(kt), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   const uint64_t nkept = kt[0];
   pa->kept_entries = kt[1];
   X.stats.cells_pruned += nk - nkept;
@@ -828,7 +838,7 @@ void plan_chunks(Run& X, Parent* pa, std::vector<std::pair<uint32_t, uint32_t>>&
   k_gather_u64<<<nblk(ns + 1), 256, 0, X.st>>>(pa->soff, nk, stride, d);
   std::vector<uint64_t> s(ns + 1);
   HIPCHK(hipMemcpyAsync(s.data(), d, (ns + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   dfree(X, d);
   auto at = [&](uint64_t i) { return i >= ns ? s[ns] : s[i]; };  // sample i -> soff[min(i*stride, nk)]
   auto rk = [&](uint64_t i) { return (uint32_t)std::min<uint64_t>(i * stride, nk); };
@@ -868,7 +878,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   k_chunk_totals<<<1, 64, 0, X.st>>>(keepc, cidx, csize, coff, nr, X.dtot);
   uint64_t tot[2];
   HIPCHK(hipMemcpyAsync(tot, X.dtot, sizeof(tot), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   bool made = false;
   X.stats.cells_pruned += nr - tot[0];
   if (tot[0] > 0) {
@@ -1099,7 +1109,7 @@ void epoch_begin(Run& X) {
       }
     }
   }
-  HIPCHK(hipStreamSynchronize(X.st));  // tables and copied columns are read below
+  host_wait(X);  // tables and copied columns are read below
 }
 
 // Root cells of every valid problem, grouping of equal root surfaces, one
@@ -1128,13 +1138,13 @@ void start_search(Run& X) {
     rb.nent = X.Ntot;
     rb.cells = dalloc<Cell>(X, rc.size());
     HIPCHK(hipMemcpyAsync(rb.cells, rc.data(), rc.size() * sizeof(Cell), hipMemcpyHostToDevice, X.st));
-    HIPCHK(hipStreamSynchronize(X.st));
+    host_wait(X);
     rb.ents = X.root;
     if (X.group_mode >= 0) group_batch<E>(X, rb, true);
     X.root = rb.ents;
     unit = rb.unit;
     HIPCHK(hipMemcpyAsync(rc.data(), rb.cells, rc.size() * sizeof(Cell), hipMemcpyDeviceToHost, X.st));
-    HIPCHK(hipStreamSynchronize(X.st));
+    host_wait(X);
     dfree(X, rb.cells);
   }
   // one list per (problem, sector): the pass masks are written per entry
@@ -1163,7 +1173,7 @@ void start_search(Run& X) {
   X.root = nullptr;
   Cell* dcells = dalloc<Cell>(X, cells.size());
   HIPCHK(hipMemcpyAsync(dcells, cells.data(), cells.size() * sizeof(Cell), hipMemcpyHostToDevice, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   // greedy dive in every cell: achieved leaf keys are valid starting bounds
   if (X.root_dive) {
     Batch b;
@@ -1263,7 +1273,7 @@ void build_linear(Run& X) {
   std::vector<int> bad(np);
   HIPCHK(hipMemcpyAsync(mx.data(), dmax, 2 * np * sizeof(unsigned), hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipMemcpyAsync(bad.data(), dbad, np * sizeof(int), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   dfree(X, dmax);
   dfree(X, dbad);
   const ProbC& P = X.P0;
@@ -1356,7 +1366,7 @@ bool build_pose(Run& X) {
   std::vector<int> bad(np);
   HIPCHK(hipMemcpyAsync(mxb.data(), dmx, mxb.size() * 8, hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipMemcpyAsync(bad.data(), dbad, np * sizeof(int), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   std::vector<ProbC> tab(np);
   for (uint32_t p = 0; p < np; p++) {
     ProbRec* pr = X.probs[p];
@@ -1382,7 +1392,7 @@ bool build_pose(Run& X) {
                                                        dmx + 8 * p);
   }
   HIPCHK(hipMemcpyAsync(mxb.data(), dmx, mxb.size() * 8, hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   dfree(X, dmx);
   dfree(X, dbad);
   bool all32 = true;
@@ -1415,7 +1425,7 @@ void epoch_finish(Run& X) {
   HIPCHK(hipMemcpyAsync(best.data(), X.dbest, np * 8, hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipMemcpyAsync(&rech, X.drecheck, 8, hipMemcpyDeviceToHost, X.st));
   HIPCHK(hipMemcpyAsync(&ovf, X.dovf, sizeof(int), hipMemcpyDeviceToHost, X.st));
-  HIPCHK(hipStreamSynchronize(X.st));
+  host_wait(X);
   if (ovf)
     for (ProbRec* pr : X.probs)
       if (pr->st == GV_OK) {
@@ -1458,7 +1468,7 @@ void epoch_finish(Run& X) {
     for (uint32_t p = 0; p < np; p++)
       HIPCHK(hipMemcpyAsync(&pb[p], pos + std::min<uint64_t>(X.ooff[p], X.Ntot - 1), 4, hipMemcpyDeviceToHost, X.st));
     HIPCHK(hipMemcpyAsync(&pb[np], pos + X.Ntot - 1, 4, hipMemcpyDeviceToHost, X.st));
-    HIPCHK(hipStreamSynchronize(X.st));
+    host_wait(X);
     pb[np] += lastf;
     for (uint32_t p = 0; p < np; p++)
       if (X.ooff[p] >= X.Ntot) pb[p] = pb[np];
@@ -1469,7 +1479,7 @@ void epoch_finish(Run& X) {
       k_write_inliers<<<gg, 256, 0, X.st>>>(flag, pos, X.dooff, np, X.Ntot, dout);
       all.resize(tot);
       HIPCHK(hipMemcpyAsync(all.data(), dout, tot * sizeof(int64_t), hipMemcpyDeviceToHost, X.st));
-      HIPCHK(hipStreamSynchronize(X.st));
+      host_wait(X);
       dfree(X, dout);
     }
     dfree(X, flag);
@@ -1489,8 +1499,11 @@ void epoch_finish(Run& X) {
   X.stats.ms_total = ms;
   X.stats.ms_kernels = ms;
   if (X.trace)
-    std::fprintf(stderr, "gv: epoch of %u problems: %.3g tests, %llu cells expanded, %.1f ms, peak %.2f GB\n", np,
-                 (double)X.stats.tests, (unsigned long long)X.stats.cells_expanded, ms, (double)X.cache->peak * 1e-9);
+    std::fprintf(stderr,
+                 "gv: epoch of %u problems: %.3g tests, %llu cells expanded, %.1f ms, peak %.2f GB, %llu host waits "
+                 "(%.1f ms)\n",
+                 np, (double)X.stats.tests, (unsigned long long)X.stats.cells_expanded, ms,
+                 (double)X.cache->peak * 1e-9, (unsigned long long)X.waits, X.wait_ms);
   for (uint32_t p = 0; p < np; p++) {
     ProbRec* pr = X.probs[p];
     pr->stats = X.stats;
@@ -1993,7 +2006,7 @@ gv_status gv_parametrize(gv_ctx* ctx, const gv_problem* p, double* t_out, double
       if (tag_out) HIPCHK(hipMemcpyAsync(tag_out, tg, p->n * sizeof(int32_t), hipMemcpyDeviceToHost, X.st));
       int hb = 0;
       HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, X.st));
-      HIPCHK(hipStreamSynchronize(X.st));
+      host_wait(X);
       dfree(X, t);
       dfree(X, f);
       dfree(X, tg);
