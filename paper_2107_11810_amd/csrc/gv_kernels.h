@@ -8,6 +8,8 @@
 #pragma once
 #include "gv_device.h"
 
+#include <type_traits>
+
 __device__ inline uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -15,6 +17,10 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
 }
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
 __device__ inline uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint64_t uniform_u64(uint64_t v) {
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
 __device__ inline uint32_t mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -612,6 +618,77 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t nwork = *nwork_p;
+  if constexpr (FAM == FAM_PLANE3D && NCH == 8 && std::is_same<EO, EntP3p>::value) {
+    // Every axis splits; child digit = 4 b1 + 2 b2 + b0 (split axes in axis
+    // order, most significant first).  The pass test compares
+    // t = 2F + pad + S + b1 K1 + b2 K2 - b0 H against [0, R] (unsigned), and
+    // the child's canonical height is rne((2F + b1 K1 + b2 K2 - b0 H) / 2) =
+    // rne((t - pad - S) / 2), so a child costs a subtraction and a rounding.
+    // K1', K2' and the weight (the low word and the top of the high word) are
+    // the same in every child.  The written heights' range is checked once
+    // at the end; a packed input's K and weight always fit.
+    const int32_t H = lv.H[2], pad = lv.padu[2];
+    int32_t flo = 0, fhi = 0;
+    for (uint32_t wi = wave; wi < nwork; wi += nwaves) {
+      const CWork<8>* Wp = work + wi;
+      const uint64_t off = uniform_u64(Wp->off);
+      const uint32_t cnt = uniform_u32(Wp->cnt);
+      const uint32_t kmask = uniform_u32(Wp->kmask);
+      uint64_t wpos[8], keptm[8];
+      bool kept[8];
+#pragma unroll
+      for (int ch = 0; ch < 8; ch++) {
+        kept[ch] = (kmask >> ch) & 1u;
+        keptm[ch] = kept[ch] ? ~0ull : 0ull;
+        wpos[ch] = kept[ch] ? uniform_u64(Wp->wpos[ch]) : 0ull;
+      }
+      for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * GJ) {
+        E ev[GJ];
+#pragma unroll
+        for (int j = 0; j < GJ; j++) {
+          const uint32_t k = k0 + 64 * j + lane;
+          ev[j] = E{};
+          if (k < cnt) ev[j] = ents[off + k];
+        }
+#pragma unroll
+        for (int j = 0; j < GJ; j++) {
+          if (k0 + 64 * j >= cnt) break;
+          const LinS s = load_ent<FAM>(ev[j]);
+          const int32_t K1 = s.K[0][0], K2 = s.K[0][1], K12 = K1 + K2;
+          const int32_t S = imax32(K1, 0) + imax32(K2, 0);
+          const int32_t F = k0 + 64 * j + lane < cnt ? s.F[0] : GV_F_NONE;
+          const int32_t u = 2 * F + pad + S, base = pad + S;
+          const uint32_t R = (uint32_t)(2 * S + (H + 2 * pad) - K12);
+          const int32_t K1c = rne_half(K1), K2c = rne_half(K2);
+          const uint32_t w = (uint32_t)s.w;
+          if constexpr (!std::is_same<E, EntP3p>::value)
+            fits = fits && abs(K1c) <= GV_P3_KMAX && abs(K2c) <= GV_P3_KMAX && w <= GV_P3_WMAX;
+          const uint32_t lo = ((uint32_t)K1c & 0x1fffu) | (((uint32_t)K2c & 0x1fffu) << 13) | ((w & 0x3fu) << 26);
+          const uint32_t whi = (w >> 6) << 16;
+          const int32_t uu[4] = {u, u + K2, u + K1, u + K12};  // (b1, b2) = 00, 01, 10, 11
+#pragma unroll
+          for (int ch = 0; ch < 8; ch++) {
+            const int32_t t = (ch & 1) ? uu[ch >> 1] - H : uu[ch >> 1];
+            const bool c = (uint32_t)t <= R;
+            const uint64_t b = __builtin_amdgcn_ballot_w64(c) & keptm[ch];
+            if (c && kept[ch]) {
+              const int32_t Fc = rne_half(t - base);
+              flo = imin32(flo, Fc);
+              fhi = imax32(fhi, Fc);
+              EntP3p e;
+              e.lo = lo;
+              e.hi = ((uint32_t)Fc & 0xffffu) | whi;
+              (out + wpos[ch])[mbcnt64(b)] = e;
+            }
+            wpos[ch] += (uint64_t)__popcll(b);
+          }
+        }
+      }
+    }
+    fits = fits && flo >= -GV_P3_FMAX && fhi <= GV_P3_FMAX;
+    if (!fits) atomicOr(ovf, 1);
+    return;
+  }
   for (uint32_t wi = wave; wi < nwork; wi += nwaves) {
     const CWork<NCH> W = work[wi];
     const uint32_t kmask = W.kmask;
