@@ -45,6 +45,170 @@ __global__ void k_item_fill(const Cell* __restrict__ cells, uint32_t ncell, cons
 }
 
 // ---------------------------------------------------------------------------
+// Single-workgroup forms of the frontier bookkeeping for small batches: one
+// launch where the general form takes a device-wide scan (two launches) and
+// the small kernels around it.  1024 threads; thread t owns the contiguous
+// run [t * GV_SMALL_PER, (t + 1) * GV_SMALL_PER) of the array.  Totals that
+// the host reads go to host-coherent memory, fenced at system scope.
+// ---------------------------------------------------------------------------
+#define GV_SMALL_PER 16
+#define GV_SMALL_N (1024u * GV_SMALL_PER)
+
+// Exclusive prefix of the per-thread values s over the workgroup (wsum: 16
+// slots of LDS); every thread also gets the total.
+template <typename T>
+__device__ inline T block_excl(T s, T* wsum, T& tot) {
+  const uint32_t t = threadIdx.x, l = t & 63u, w = t >> 6;
+  T x = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(x, o, 64);
+    if (l >= (uint32_t)o) x += y;
+  }
+  if (l == 63u) wsum[w] = x;
+  __syncthreads();
+  T pre = 0, all = 0;
+  for (uint32_t k = 0; k < (blockDim.x >> 6); k++) {
+    const T v = wsum[k];
+    if (k < w) pre += v;
+    all += v;
+  }
+  __syncthreads();
+  tot = all;
+  return pre + x - s;
+}
+
+// out = exclusive prefix sums of in[0, n), n <= GV_SMALL_N; *total = the sum
+// (when given)
+template <typename In, typename Out>
+__global__ void __launch_bounds__(1024) k_scan_small(const In* __restrict__ in, Out* __restrict__ out, uint32_t n,
+                                                     Out* __restrict__ total) {
+  __shared__ Out wsum[16];
+  const uint32_t b = threadIdx.x * GV_SMALL_PER;
+  Out v[GV_SMALL_PER];
+  Out s = 0;
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++) {
+    v[j] = b + j < n ? (Out)in[b + j] : (Out)0;
+    s += v[j];
+  }
+  Out tot;
+  Out run = block_excl<Out>(s, wsum, tot);
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++) {
+    if (b + j < n) out[b + j] = run;
+    run += v[j];
+  }
+  if (total && threadIdx.x == 0) *total = tot;
+}
+
+// Work items of a batch of at most GV_SMALL_N cells: per-cell item counts,
+// their offsets and the items themselves, in one launch.
+__global__ void __launch_bounds__(1024) k_items_small(const Cell* __restrict__ cells, uint32_t ncell,
+                                                      uint32_t* __restrict__ ioff, Item* __restrict__ items,
+                                                      uint32_t* __restrict__ total) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t b = threadIdx.x * GV_SMALL_PER;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++)
+    if (b + j < ncell) s += (cells[b + j].len + GV_ITEM - 1) / GV_ITEM;
+  uint32_t tot;
+  uint32_t o = block_excl<uint32_t>(s, wsum, tot);
+  for (uint32_t c = b; c < min(b + GV_SMALL_PER, ncell); c++) {
+    const uint64_t off = cells[c].off;
+    const uint32_t len = cells[c].len, k = (len + GV_ITEM - 1) / GV_ITEM;
+    ioff[c] = o;
+    for (uint32_t j = 0; j < k; j++)
+      items[o + j] = Item{off + (uint64_t)j * GV_ITEM, c, min((uint32_t)GV_ITEM, len - j * (uint32_t)GV_ITEM)};
+    o += k;
+  }
+  if (threadIdx.x == 0) *total = tot;
+}
+
+// Prune tail of a small expansion: keepscan = exclusive prefix of keepf,
+// tot[0] = kept children, tot[1] = their entries (host-coherent memory).
+__global__ void __launch_bounds__(1024) k_keep_small(const uint32_t* __restrict__ keepf,
+                                                     const uint64_t* __restrict__ keptn, uint32_t nk,
+                                                     uint32_t* __restrict__ keepscan, uint64_t* tot) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint64_t wsum64[16];
+  const uint32_t b = threadIdx.x * GV_SMALL_PER;
+  uint32_t v[GV_SMALL_PER];
+  uint32_t s = 0;
+  uint64_t e = 0;
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++) {
+    v[j] = b + j < nk ? keepf[b + j] : 0u;
+    e += b + j < nk ? keptn[b + j] : 0ull;
+    s += v[j];
+  }
+  uint32_t kt;
+  uint64_t et;
+  uint32_t run = block_excl<uint32_t>(s, wsum, kt);
+  (void)block_excl<uint64_t>(e, wsum64, et);
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++) {
+    if (b + j < nk) keepscan[b + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) {
+    tot[0] = kt;
+    tot[1] = et;
+    __threadfence_system();
+  }
+}
+
+// Chunk totals of a small chunk: cidx / coff = exclusive prefixes of keepc /
+// csize, tot[0] = kept cells, tot[1] = their entries (host-coherent memory).
+__global__ void __launch_bounds__(1024) k_chunk_small(const uint32_t* __restrict__ keepc,
+                                                      const uint64_t* __restrict__ csize, uint32_t nr,
+                                                      uint32_t* __restrict__ cidx, uint64_t* __restrict__ coff,
+                                                      uint64_t* tot) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint64_t wsum64[16];
+  const uint32_t b = threadIdx.x * GV_SMALL_PER;
+  uint32_t v[GV_SMALL_PER];
+  uint64_t z[GV_SMALL_PER];
+  uint32_t s = 0;
+  uint64_t e = 0;
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++) {
+    v[j] = b + j < nr ? keepc[b + j] : 0u;
+    z[j] = b + j < nr ? csize[b + j] : 0ull;
+    s += v[j];
+    e += z[j];
+  }
+  uint32_t kt;
+  uint64_t et;
+  uint32_t run = block_excl<uint32_t>(s, wsum, kt);
+  uint64_t run64 = block_excl<uint64_t>(e, wsum64, et);
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++) {
+    if (b + j < nr) {
+      cidx[b + j] = run;
+      coff[b + j] = run64;
+    }
+    run += v[j];
+    run64 += z[j];
+  }
+  if (threadIdx.x == 0) {
+    tot[0] = kt;
+    tot[1] = et;
+    __threadfence_system();
+  }
+}
+
+// zero up to three u32 arrays in one launch
+__global__ void k_zero3(uint32_t* __restrict__ a, uint64_t na, uint32_t* __restrict__ b, uint64_t nb,
+                        uint32_t* __restrict__ c, uint64_t nc) {
+  const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, st = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = i0; i < na; i += st) a[i] = 0;
+  for (uint64_t i = i0; i < nb; i += st) b[i] = 0;
+  for (uint64_t i = i0; i < nc; i += st) c[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Linear families: incidence test of every (canonical surface, child) pair
 // and per-child counts.  No pass masks are stored: the compaction pass reads
 // every entry anyway and repeats the (cheap, integer) test.
@@ -438,16 +602,22 @@ __global__ void k_pick_best(LevelC lv, int B, uint64_t idxmask, int leaf, const 
 // ---------------------------------------------------------------------------
 __global__ void k_select_kept(const uint32_t* __restrict__ keepf, const uint32_t* __restrict__ keepscan,
                               const uint32_t* __restrict__ ccnt, uint64_t nk, uint32_t* __restrict__ kcnt,
-                              uint32_t* __restrict__ kid) {
+                              uint32_t* __restrict__ kid, uint32_t* __restrict__ rank_of) {
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nk) rank_of[k] = 0xffffffffu;  // k_rank fills in the kept children
   if (k < nk && keepf[k]) {
     kcnt[keepscan[k]] = ccnt[k];
     kid[keepscan[k]] = (uint32_t)k;
   }
 }
 
-__global__ void k_kept_total(const uint32_t* keepf, const uint32_t* keepscan, uint64_t nk, uint64_t* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = nk ? (uint64_t)keepscan[nk - 1] + keepf[nk - 1] : 0;
+__global__ void k_kept_total(const uint32_t* keepf, const uint32_t* keepscan, uint64_t nk, const uint64_t* esum,
+                             uint64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = nk ? (uint64_t)keepscan[nk - 1] + keepf[nk - 1] : 0;
+    out[1] = *esum;
+    __threadfence_system();
+  }
 }
 
 // rank_of[k] = position of child k in the sorted order; sn[r] = its entries
@@ -511,6 +681,7 @@ __global__ void k_chunk_totals(const uint32_t* keepc, const uint32_t* cidx, cons
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     out[0] = n ? (uint64_t)cidx[n - 1] + keepc[n - 1] : 0;
     out[1] = n ? coff[n - 1] + csize[n - 1] : 0;
+    __threadfence_system();
   }
 }
 

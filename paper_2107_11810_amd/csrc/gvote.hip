@@ -126,6 +126,8 @@ struct gv_ctx {
   std::string last_err;    // what gv_last_error reports
   int n_cu = 256;
   DevCache cache;
+  uint64_t* hpin = nullptr;      // host-coherent pinned words the kernels write totals to
+  uint64_t* hpin_dev = nullptr;  // (device address of the same)
   bool kernel_timing = false;
   std::vector<hipEvent_t> ev_pool;
   // continuous batching
@@ -412,6 +414,8 @@ struct Run {
   hipStream_t st = nullptr;                 // every device operation of the epoch is ordered on it
   DevCache* cache = nullptr;                // allocator of that stream
   std::vector<hipEvent_t>* ev_pool = nullptr;
+  uint64_t* hpin = nullptr;      // host-coherent totals (host and device address), else dtot is device memory
+  uint64_t* hpin_dev = nullptr;
   std::string* err = nullptr;               // text of the failing HIP call
   uint64_t budget = 0;                      // device bytes the epoch may plan with
   std::vector<ProbRec*> probs;
@@ -451,6 +455,26 @@ struct Run {
   std::chrono::steady_clock::time_point t0;
 };
 
+// Two host-coherent pinned words that kernels write totals to, so the host
+// reads them after a stream wait without a copy.  Null pointers (and device
+// memory plus a copy) when the allocation fails.
+void alloc_hpin(uint64_t*& h, uint64_t*& d) {
+  h = d = nullptr;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return;
+  void* q = nullptr;
+  if (hipHostGetDevicePointer(&q, p, 0) != hipSuccess) {
+    (void)hipHostFree(p);
+    return;
+  }
+  h = (uint64_t*)p;
+  d = (uint64_t*)q;
+}
+void free_hpin(uint64_t*& h, uint64_t*& d) {
+  if (h) (void)hipHostFree(h);
+  h = d = nullptr;
+}
+
 // the host waits for the epoch's stream (counted for the trace line)
 void host_wait(Run& X) {
   const auto t = std::chrono::steady_clock::now();
@@ -465,6 +489,8 @@ void bind_ctx(Run& X, gv_ctx* c) {
   X.st = c->stream;
   X.cache = &c->cache;
   X.ev_pool = &c->ev_pool;
+  X.hpin = c->hpin;
+  X.hpin_dev = c->hpin_dev;
   X.err = &c->err;
   X.budget = c->budget;
 }
@@ -483,6 +509,10 @@ void dfree(Run& X, void* p) {
 template <typename In, typename Out>
 void excl_scan(Run& X, const In* in, Out* out, uint64_t n) {
   if (n == 0) return;
+  if (n <= GV_SMALL_N) {
+    k_scan_small<In, Out><<<1, 1024, 0, X.st>>>(in, out, (uint32_t)n, nullptr);
+    return;
+  }
   size_t tb = 0;
   HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, X.st));
   void* tmp = dalloc<char>(X, tb);
@@ -509,6 +539,19 @@ void free_parent(Run& X, Parent* pa) {
   dfree(X, pa->ioff);
   dfree(X, pa->itemoff);
   delete pa;
+}
+
+// the two totals the last kernels wrote to X.dtot
+void read_tot(Run& X, uint64_t* v) {
+  if (X.hpin && X.dtot == X.hpin_dev) {
+    host_wait(X);
+    const volatile uint64_t* h = X.hpin;
+    v[0] = h[0];
+    v[1] = h[1];
+  } else {
+    HIPCHK(hipMemcpyAsync(v, X.dtot, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
+    host_wait(X);
+  }
 }
 
 template <typename T>
@@ -630,15 +673,19 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   pa->unit = b.unit;
 
   // work items: at most GV_ITEM entries of one cell each
-  uint32_t* nitem = dalloc<uint32_t>(X, b.ncell);
+  uint32_t* nitem = b.ncell <= GV_SMALL_N ? nullptr : dalloc<uint32_t>(X, b.ncell);
   pa->ioff = dalloc<uint32_t>(X, b.ncell);
   pa->max_items = b.ncell + b.nent / GV_ITEM + 1;
   pa->items = dalloc<Item>(X, pa->max_items);
   pa->nitems = dalloc<uint32_t>(X, 1);
-  HIPCHK(hipMemsetAsync(pa->nitems, 0, sizeof(uint32_t), X.st));
-  k_item_counts<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem);
-  excl_scan(X, nitem, pa->ioff, b.ncell);
-  k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, pa->ioff, pa->items, pa->nitems);
+  if (b.ncell <= GV_SMALL_N) {
+    k_items_small<<<1, 1024, 0, X.st>>>(b.cells, b.ncell, pa->ioff, pa->items, pa->nitems);
+  } else {
+    HIPCHK(hipMemsetAsync(pa->nitems, 0, sizeof(uint32_t), X.st));
+    k_item_counts<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem);
+    excl_scan(X, nitem, pa->ioff, b.ncell);
+    k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, pa->ioff, pa->items, pa->nitems);
+  }
   dfree(X, nitem);
   pa->istride = (uint32_t)pa->max_items;
   // POSE4DOF keeps per-entry pass masks and counts with atomics, per-item
@@ -652,14 +699,13 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     if (!b.unit) itemw = dalloc<uint32_t>(X, (uint64_t)nch * pa->max_items);
   } else if (!leaf) {
     itemcnt = dalloc<uint32_t>(X, (uint64_t)nch * pa->istride);
-    HIPCHK(hipMemsetAsync(itemcnt, 0, (uint64_t)nch * pa->istride * sizeof(uint32_t), X.st));
   }
   if (!linear) pa->masks = dalloc<M>(X, b.nent);
   uint32_t* ccnt = dalloc<uint32_t>(X, nk);
   pa->cnent = dalloc<uint32_t>(X, nk);
   if (!linear) {
-    HIPCHK(hipMemsetAsync(ccnt, 0, nk * sizeof(uint32_t), X.st));
-    HIPCHK(hipMemsetAsync(pa->cnent, 0, nk * sizeof(uint32_t), X.st));
+    const uint64_t ni = itemcnt ? (uint64_t)nch * pa->istride : 0;
+    k_zero3<<<gs_grid(X, std::max(nk, ni)), 256, 0, X.st>>>(ccnt, nk, pa->cnent, nk, itemcnt, ni);
   }
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
   auto evp = ev_begin(X, 0);
@@ -738,19 +784,22 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     return nullptr;
   }
   uint32_t* keepscan = dalloc<uint32_t>(X, nk);
-  excl_scan(X, keepf, keepscan, nk);
-  k_kept_total<<<1, 64, 0, X.st>>>(keepf, keepscan, nk, X.dtot);
-  {
+  if (nk <= GV_SMALL_N) {
+    k_keep_small<<<1, 1024, 0, X.st>>>(keepf, keptn, (uint32_t)nk, keepscan, X.dtot);
+  } else {
+    excl_scan(X, keepf, keepscan, nk);
+    uint64_t* esum = dalloc<uint64_t>(X, 1);
     size_t tb = 0;
-    HIPCHK(hipcub::DeviceReduce::Sum(nullptr, tb, keptn, X.dtot + 1, (int)nk, X.st));
+    HIPCHK(hipcub::DeviceReduce::Sum(nullptr, tb, keptn, esum, (int)nk, X.st));
     void* tmp = dalloc<char>(X, tb);
-    HIPCHK(hipcub::DeviceReduce::Sum(tmp, tb, keptn, X.dtot + 1, (int)nk, X.st));
+    HIPCHK(hipcub::DeviceReduce::Sum(tmp, tb, keptn, esum, (int)nk, X.st));
     dfree(X, tmp);
+    k_kept_total<<<1, 64, 0, X.st>>>(keepf, keepscan, nk, esum, X.dtot);
+    dfree(X, esum);
   }
   dfree(X, keptn);
   uint64_t kt[2];
-  HIPCHK(hipMemcpyAsync(kt, X.dtot, sizeof(kt), hipMemcpyDeviceToHost, X.st));
-  host_wait(X);
+  read_tot(X, kt);
   const uint64_t nkept = kt[0];
   pa->kept_entries = kt[1];
   X.stats.cells_pruned += nk - nkept;
@@ -776,7 +825,8 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   pa->nkept = (uint32_t)nkept;
   uint32_t* kcnt = dalloc<uint32_t>(X, nkept);
   uint32_t* kid = dalloc<uint32_t>(X, nkept);
-  k_select_kept<<<nblk(nk), 256, 0, X.st>>>(keepf, keepscan, ccnt, nk, kcnt, kid);
+  pa->rank_of = dalloc<uint32_t>(X, nk);
+  k_select_kept<<<nblk(nk), 256, 0, X.st>>>(keepf, keepscan, ccnt, nk, kcnt, kid, pa->rank_of);
   dfree(X, keepf);
   dfree(X, keepscan);
   // POSE4DOF keeps count order throughout: its bound keeps improving after
@@ -814,14 +864,16 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   }
   dfree(X, kcnt);
   dfree(X, kid);
-  pa->rank_of = dalloc<uint32_t>(X, nk);
-  HIPCHK(hipMemsetAsync(pa->rank_of, 0xff, nk * sizeof(uint32_t), X.st));
   uint32_t* sn = dalloc<uint32_t>(X, nkept);
   k_rank<<<nblk(nkept), 256, 0, X.st>>>(pa->order, (uint32_t)nkept, pa->cnent, ccnt, pa->rank_of, sn, pa->scount);
   dfree(X, ccnt);
   pa->soff = dalloc<uint64_t>(X, nkept + 1);
-  excl_scan(X, sn, pa->soff, nkept);
-  k_soff_last<<<1, 64, 0, X.st>>>(pa->soff, sn, (uint32_t)nkept);
+  if (nkept <= GV_SMALL_N) {
+    k_scan_small<uint32_t, uint64_t><<<1, 1024, 0, X.st>>>(sn, pa->soff, (uint32_t)nkept, pa->soff + nkept);
+  } else {
+    excl_scan(X, sn, pa->soff, nkept);
+    k_soff_last<<<1, 64, 0, X.st>>>(pa->soff, sn, (uint32_t)nkept);
+  }
   dfree(X, sn);
   return pa;
 }
@@ -873,12 +925,15 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   uint64_t* coff = dalloc<uint64_t>(X, nr);
   k_chunk_keep<<<nblk(nr), 256, 0, X.st>>>(pa->order, pa->scount, pa->cells, nch, X.dbest, P.B, r0, r1, pa->cnent,
                                             keepc, csize);
-  excl_scan(X, keepc, cidx, nr);
-  excl_scan(X, csize, coff, nr);
-  k_chunk_totals<<<1, 64, 0, X.st>>>(keepc, cidx, csize, coff, nr, X.dtot);
+  if (nr <= GV_SMALL_N) {
+    k_chunk_small<<<1, 1024, 0, X.st>>>(keepc, csize, nr, cidx, coff, X.dtot);
+  } else {
+    excl_scan(X, keepc, cidx, nr);
+    excl_scan(X, csize, coff, nr);
+    k_chunk_totals<<<1, 64, 0, X.st>>>(keepc, cidx, csize, coff, nr, X.dtot);
+  }
   uint64_t tot[2];
-  HIPCHK(hipMemcpyAsync(tot, X.dtot, sizeof(tot), hipMemcpyDeviceToHost, X.st));
-  host_wait(X);
+  read_tot(X, tot);
   bool made = false;
   X.stats.cells_pruned += nr - tot[0];
   if (tot[0] > 0) {
@@ -1082,7 +1137,7 @@ void epoch_begin(Run& X) {
   X.dP = dalloc<ProbC>(X, np);
   X.dbest = dalloc<unsigned long long>(X, np);
   X.drecheck = dalloc<unsigned long long>(X, 1);
-  X.dtot = dalloc<uint64_t>(X, 2);
+  X.dtot = X.hpin_dev ? X.hpin_dev : dalloc<uint64_t>(X, 2);
   X.dummy = dalloc<uint32_t>(X, 64);
   X.dreads = dalloc<unsigned long long>(X, 1);
   X.dovf = dalloc<int>(X, 1);
@@ -1542,7 +1597,7 @@ void epoch_release(Run& X) {
   dfree(X, X.dP);
   dfree(X, X.dbest);
   dfree(X, X.drecheck);
-  dfree(X, X.dtot);
+  if (X.dtot != X.hpin_dev) dfree(X, X.dtot);
   dfree(X, X.dummy);
   dfree(X, X.dreads);
   dfree(X, X.dovf);
@@ -1635,6 +1690,8 @@ struct Lane {
   gv_ctx* ctx = nullptr;
   hipStream_t st = nullptr;
   DevCache cache;
+  uint64_t* hpin = nullptr;
+  uint64_t* hpin_dev = nullptr;
   std::vector<hipEvent_t> ev_pool;
   std::string err;
   std::thread th;
@@ -1702,6 +1759,8 @@ void lane_main(Lane* L) {
     X.st = L->st;
     X.cache = &L->cache;
     X.ev_pool = &L->ev_pool;
+    X.hpin = L->hpin;
+    X.hpin_dev = L->hpin_dev;
     X.err = &L->err;
     // lanes share the device: smaller chunks keep their allocations small
     // and their latency steady (measured: 8 GB chunks per lane raised the
@@ -1734,6 +1793,7 @@ void start_lanes(gv_ctx* ctx) {
       delete L;
       break;
     }
+    alloc_hpin(L->hpin, L->hpin_dev);
     L->th = std::thread(lane_main, L);
     ctx->lanes.push_back(L);
   }
@@ -1748,6 +1808,7 @@ void stop_lanes(gv_ctx* ctx) {
     for (auto& kv : L->cache.live) (void)hipFree(kv.first);
     for (hipEvent_t e : L->ev_pool) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(L->st);
+    free_hpin(L->hpin, L->hpin_dev);
     delete L;
   }
   ctx->lanes.clear();
@@ -1807,6 +1868,7 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
     }
     c->own_stream = true;
   }
+  alloc_hpin(c->hpin, c->hpin_dev);
   size_t fr = 0, tot = 0;
   (void)hipMemGetInfo(&fr, &tot);
   c->budget = (cfg && cfg->mem_budget_bytes) ? cfg->mem_budget_bytes : (uint64_t)(0.6 * (double)fr);
@@ -1836,6 +1898,7 @@ gv_status gv_destroy(gv_ctx* ctx) {
   for (auto& kv : ctx->cache.live) (void)hipFree(kv.first);
   ctx->cache.live.clear();
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  free_hpin(ctx->hpin, ctx->hpin_dev);
   delete ctx;
   return GV_OK;
 }
