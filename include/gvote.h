@@ -75,9 +75,22 @@ typedef struct {
   int device;                 /* HIP device ordinal */
   uint64_t mem_budget_bytes;  /* 0: 60% of the device's free memory */
   void *hip_stream;           /* optional hipStream_t to run on; NULL: own stream */
-  const char *autotune_cache; /* reserved, ignored: kernel launch shapes are
-                                 fixed (one wave per list item of <= 1024
-                                 entries, 8 blocks of 4 waves per CU) */
+  const char *autotune_cache; /* path of a text file for the launch-shape
+                                 autotuner, or NULL to keep its choices in
+                                 this context only.  The count and compaction
+                                 kernels loop over list items (one wave per
+                                 item of <= 1024 entries), so their grid
+                                 changes nothing but speed.  Per family and
+                                 kernel the library times each candidate grid
+                                 (2, 4, 8, 16 or 32 blocks of 4 waves per CU)
+                                 on its large launches with HIP events and
+                                 keeps the one with the least time per entry;
+                                 launches before that use 8.  The choices are
+                                 read from the file at creation (lines
+                                 "arch CUs family kernel blocks" of this
+                                 device) and written to it when made; an
+                                 unreadable or unwritable file only means
+                                 tuning again.  Results never depend on it. */
   int kernel_timing;          /* 1: time the incidence and compaction kernels
                                  with HIP events on the solve stream (adds
                                  one event pair per launch) */

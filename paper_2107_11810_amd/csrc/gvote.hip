@@ -115,6 +115,21 @@ struct ProbRec;
 struct Lane;
 }
 
+// Candidate grids of the item-looping kernels, in blocks of four waves per
+// CU.  A slot tries them in turn on its large launches and keeps the one with
+// the lowest event time per entry once each has kTuneSamples samples.
+constexpr int kTuneCand[] = {2, 4, 8, 16, 32};
+constexpr int kNCand = 5;
+constexpr int kTuneSamples = 3;
+constexpr uint64_t kTuneMinEntries = 8ull << 20;  // smaller launches use the default shape
+constexpr int kGridDefault = 8;
+struct gvi_tune_slot {
+  int chosen = 0;  // blocks per CU once chosen
+  int next = 0;    // next candidate to try
+  double ms[kNCand] = {}, units[kNCand] = {};
+  int n[kNCand] = {};
+};
+
 struct gv_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -149,6 +164,14 @@ struct gv_ctx {
   uint64_t batch_n = 0;
   // packed 8-byte list entries where the lattice bounds allow (GV_PACK=0 off)
   bool pack = true;
+  // launch-shape autotuner: per family (index 1..4) and kernel (0 count,
+  // 1 compaction)
+  std::mutex tmu;
+  gvi_tune_slot tune[5][2];
+  bool autotune = true;
+  uint64_t tune_min = kTuneMinEntries;  // launches with fewer entries are not tuning samples
+  std::string tune_path;   // autotune cache file ("" = keep choices in memory)
+  std::string arch;        // device architecture name, the cache file's key
 };
 
 namespace gvi {
@@ -436,11 +459,18 @@ struct Run {
   uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
   uint64_t dive_cells = 16384;            // cells from which the diversified dive goes greedy
   bool root_dive = false;                 // greedy dive from the root cells first (the diversified dive subsumes it)
+  int grid_env[2] = {0, 0};               // GV_GRID_COUNT / GV_GRID_COMPACT: fixed blocks per CU (experiments)
   uint64_t waits = 0;                     // host waits for the stream, and their time
   double wait_ms = 0.0;
   bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
   bool beam = true;                       // progressive chunks until the first leaf level
-  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
+  struct EvRec {
+    std::pair<hipEvent_t, hipEvent_t> e;
+    int kind;        // 0 count, 1 compaction
+    int cand;        // autotuner candidate index, -1 when not a tuning sample
+    uint64_t units;  // entries the launch processed
+  };
+  std::vector<EvRec> ev;
   size_t ev_used = 0;
   gv_stats stats{};
   // originals and roots
@@ -562,10 +592,95 @@ uint64_t d2h1(Run& X, const T* p) {
   return (uint64_t)v;
 }
 
-std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind) {
+// Autotune cache file: one line per choice,
+//   <arch> <compute units> <family 1..4> <kernel 0 count | 1 compaction> <blocks per CU>
+void tune_load(gv_ctx* c) {
+  if (c->tune_path.empty()) return;
+  FILE* f = std::fopen(c->tune_path.c_str(), "r");
+  if (!f) return;
+  char arch[128];
+  int ncu, fam, kind, gpc;
+  while (std::fscanf(f, "%127s %d %d %d %d", arch, &ncu, &fam, &kind, &gpc) == 5) {
+    if (c->arch != arch || ncu != c->n_cu || fam < 1 || fam > 4 || kind < 0 || kind > 1) continue;
+    for (int k = 0; k < kNCand; k++)
+      if (kTuneCand[k] == gpc) c->tune[fam][kind].chosen = gpc;
+  }
+  std::fclose(f);
+}
+
+// Rewrites the cache file with this context's choices, keeping the lines of
+// other devices (called with c->tmu held).
+void tune_save(gv_ctx* c) {
+  if (c->tune_path.empty()) return;
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(c->tune_path.c_str(), "r")) {
+    char arch[128];
+    int ncu, fam, kind, gpc;
+    while (std::fscanf(f, "%127s %d %d %d %d", arch, &ncu, &fam, &kind, &gpc) == 5) {
+      const bool mine = c->arch == arch && ncu == c->n_cu && fam >= 1 && fam <= 4 && kind >= 0 && kind <= 1 &&
+                        c->tune[fam][kind].chosen;
+      if (!mine) keep.push_back(std::string(arch) + " " + std::to_string(ncu) + " " + std::to_string(fam) + " " +
+                                std::to_string(kind) + " " + std::to_string(gpc));
+    }
+    std::fclose(f);
+  }
+  const std::string tmp = c->tune_path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const std::string& l : keep) std::fprintf(f, "%s\n", l.c_str());
+  for (int fam = 1; fam <= 4; fam++)
+    for (int kind = 0; kind < 2; kind++)
+      if (c->tune[fam][kind].chosen)
+        std::fprintf(f, "%s %d %d %d %d\n", c->arch.c_str(), c->n_cu, fam, kind, c->tune[fam][kind].chosen);
+  std::fclose(f);
+  std::rename(tmp.c_str(), c->tune_path.c_str());
+}
+
+// One timed tuning launch; once every candidate has its samples the slot
+// keeps the lowest time per entry.
+void tune_sample(Run& X, int kind, int cand, double ms, uint64_t units) {
+  gv_ctx* c = X.ctx;
+  std::lock_guard<std::mutex> g(c->tmu);
+  gvi_tune_slot& t = c->tune[X.P0.fam][kind];
+  if (t.chosen) return;
+  t.ms[cand] += ms;
+  t.units[cand] += (double)units;
+  t.n[cand]++;
+  for (int k = 0; k < kNCand; k++)
+    if (t.n[k] < kTuneSamples) return;
+  int best = 0;
+  for (int k = 1; k < kNCand; k++)
+    if (t.ms[k] / t.units[k] < t.ms[best] / t.units[best]) best = k;
+  t.chosen = kTuneCand[best];
+  if (X.trace) {
+    std::fprintf(stderr, "gv: autotune family %d %s:", X.P0.fam, kind ? "compaction" : "count");
+    for (int k = 0; k < kNCand; k++) std::fprintf(stderr, " %d:%.3g", kTuneCand[k], t.ms[k] / t.units[k] * 1e9);
+    std::fprintf(stderr, " ps/entry -> %d blocks per CU\n", t.chosen);
+  }
+  tune_save(c);
+}
+
+// Blocks per CU of the next count (kind 0) or compaction (kind 1) launch of
+// X.units entries; *cand = the candidate index when the launch is a tuning
+// sample, else -1.
+int grid_pick(Run& X, int kind, uint64_t units, int* cand) {
+  *cand = -1;
+  if (X.grid_env[kind]) return X.grid_env[kind];
+  gv_ctx* c = X.ctx;
+  if (!c->autotune) return kGridDefault;
+  std::lock_guard<std::mutex> g(c->tmu);
+  gvi_tune_slot& t = c->tune[X.P0.fam][kind];
+  if (t.chosen) return t.chosen;
+  if (units < c->tune_min) return kGridDefault;
+  *cand = t.next;
+  t.next = (t.next + 1) % kNCand;
+  return kTuneCand[*cand];
+}
+
+std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind, int cand = -1, uint64_t units = 0) {
   gv_ctx* c = X.ctx;
   std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
-  if (!c->kernel_timing) return p;
+  if (!c->kernel_timing && cand < 0) return p;
   std::vector<hipEvent_t>& pool = *X.ev_pool;
   while (pool.size() < 2 * (X.ev_used + 1)) {
     hipEvent_t e;
@@ -576,7 +691,7 @@ std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind) {
   p.second = pool[2 * X.ev_used + 1];
   X.ev_used++;
   HIPCHK(hipEventRecord(p.first, X.st));
-  X.ev.push_back({p, kind});
+  X.ev.push_back({p, kind, cand, units});
   return p;
 }
 void ev_end(Run& X, std::pair<hipEvent_t, hipEvent_t> p) {
@@ -707,8 +822,10 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     const uint64_t ni = itemcnt ? (uint64_t)nch * pa->istride : 0;
     k_zero3<<<gs_grid(X, std::max(nk, ni)), 256, 0, X.st>>>(ccnt, nk, pa->cnent, nk, itemcnt, ni);
   }
-  const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
-  auto evp = ev_begin(X, 0);
+  int cand;
+  const int gpc = grid_pick(X, 0, b.nent, &cand);
+  const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * gpc);
+  auto evp = ev_begin(X, 0, cand, b.nent);
   X.stats.test_launches++;
   X.stats.test_bytes += linear ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
   if constexpr (FAM == FAM_POSE4DOF) {
@@ -944,7 +1061,9 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     nb.ents = dalloc<EO>(X, nb.nent);
     k_emit_ranked<<<nblk(nr), 256, 0, X.st>>>(lv, pa->cells, pa->order, r0, r1, keepc, cidx, coff, pa->cnent,
                                               nb.cells);
-    const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * 8);
+    int cand;
+    const int gpc = grid_pick(X, 1, nb.nent, &cand);
+    const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * gpc);
     const bool linear = FAM != FAM_POSE4DOF;
     // linear families: the items with a child in this chunk become a work
     // list (offsets resolved), then one wave per work item
@@ -969,7 +1088,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
       k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(
           pa->cells, pa->ncell, nch, pa->rank_of, r0, r1, keepc,
           (uint32_t)(linear ? 8 * sizeof(E) : 8 * (sizeof(E) + sizeof(M))), X.dreads);
-    auto evp = ev_begin(X, 1);
+    auto evp = ev_begin(X, 1, cand, nb.nent);
     X.stats.compact_launches++;
     X.stats.compact_bytes += nb.nent * sizeof(EO);
     if constexpr (FAM == FAM_POSE4DOF) {
@@ -1121,6 +1240,8 @@ void epoch_begin(Run& X) {
   // fifth of the budget per chunk leaves room for four large levels
   X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.budget / 5);
   if (const char* cb = std::getenv("GV_CHUNK_BYTES")) X.chunk_bytes = std::max<uint64_t>(1ull << 20, std::strtoull(cb, nullptr, 10));
+  if (const char* e = std::getenv("GV_GRID_COUNT")) X.grid_env[0] = std::max(1, std::min(64, atoi(e)));
+  if (const char* e = std::getenv("GV_GRID_COMPACT")) X.grid_env[1] = std::max(1, std::min(64, atoi(e)));
   const uint32_t np = (uint32_t)X.probs.size();
   X.ooff.assign(np + 1, 0);
   for (uint32_t p = 0; p < np; p++) X.ooff[p + 1] = X.ooff[p] + (uint64_t)X.probs[p]->n;
@@ -1544,8 +1665,9 @@ void epoch_finish(Run& X) {
   // kernel timing
   for (auto& e : X.ev) {
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e.first.first, e.first.second));
-    (e.second == 0 ? X.stats.test_ms : X.stats.compact_ms) += (double)ms;
+    HIPCHK(hipEventElapsedTime(&ms, e.e.first, e.e.second));
+    if (X.ctx->kernel_timing) (e.kind == 0 ? X.stats.test_ms : X.stats.compact_ms) += (double)ms;
+    if (e.cand >= 0) tune_sample(X, e.kind, e.cand, (double)ms, e.units);
   }
   if (X.ctx->kernel_timing) X.stats.compact_bytes += d2h1(X, X.dreads) / 8;
   X.stats.fp64_rechecks = rech;
@@ -1858,7 +1980,17 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
     return GV_EDEVICE;
   }
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    c->n_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    for (char& ch : c->arch)
+      if (ch == ' ') ch = '_';
+  }
+  if (c->arch.empty()) c->arch = "unknown";
+  if (cfg && cfg->autotune_cache) c->tune_path = cfg->autotune_cache;
+  if (const char* e = std::getenv("GV_AUTOTUNE")) c->autotune = atoi(e) != 0;
+  if (const char* e = std::getenv("GV_TUNE_MIN_ENTRIES")) c->tune_min = std::strtoull(e, nullptr, 10);
+  tune_load(c);
   if (cfg && cfg->hip_stream) {
     c->stream = (hipStream_t)cfg->hip_stream;
   } else {

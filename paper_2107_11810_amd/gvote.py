@@ -129,13 +129,14 @@ def make_problem(family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, 
 
 
 class Context:
-    def __init__(self, device=0, mem_budget_bytes=0, hip_stream=None, kernel_timing=False):
+    def __init__(self, device=0, mem_budget_bytes=0, hip_stream=None, kernel_timing=False, autotune_cache=None):
         self._h = ctypes.c_void_p()
         cfg = CtxConfig()
         cfg.device = device
         cfg.mem_budget_bytes = mem_budget_bytes
         cfg.hip_stream = hip_stream
-        cfg.autotune_cache = None
+        self._tune_path = None if autotune_cache is None else os.fsencode(autotune_cache)
+        cfg.autotune_cache = self._tune_path
         cfg.kernel_timing = 1 if kernel_timing else 0
         st = lib().gv_create(ctypes.byref(self._h), ctypes.byref(cfg))
         if st != 0:
