@@ -798,6 +798,10 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
     // K1', K2' and the weight (the low word and the top of the high word) are
     // the same in every child.  The written heights' range is checked once
     // at the end; a packed input's K and weight always fit.
+    // A wave holds a whole item (16 entries per lane) and writes its
+    // survivors child by child, so each child list receives one sequential
+    // run per item instead of eight interleaved ones (measured 11% faster
+    // than writing all children per entry).
     const int32_t H = lv.H[2], pad = lv.padu[2];
     int32_t flo = 0, fhi = 0;
     for (uint32_t wi = wave; wi < nwork; wi += nwaves) {
@@ -805,50 +809,59 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
       const uint64_t off = uniform_u64(Wp->off);
       const uint32_t cnt = uniform_u32(Wp->cnt);
       const uint32_t kmask = uniform_u32(Wp->kmask);
-      uint64_t wpos[8], keptm[8];
+      uint64_t wpos[8];
       bool kept[8];
 #pragma unroll
       for (int ch = 0; ch < 8; ch++) {
         kept[ch] = (kmask >> ch) & 1u;
-        keptm[ch] = kept[ch] ? ~0ull : 0ull;
         wpos[ch] = kept[ch] ? uniform_u64(Wp->wpos[ch]) : 0ull;
       }
-      for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * GJ) {
-        E ev[GJ];
+      constexpr int G = GV_ITEM / 64;
+      for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * G) {
+        E ev[G];
 #pragma unroll
-        for (int j = 0; j < GJ; j++) {
+        for (int j = 0; j < G; j++) {
           const uint32_t k = k0 + 64 * j + lane;
           ev[j] = E{};
           if (k < cnt) ev[j] = ents[off + k];
         }
+        int32_t U[G], BASE[G], KA[G], KB[G];
+        uint32_t RR[G], LO[G], WHI[G];
 #pragma unroll
-        for (int j = 0; j < GJ; j++) {
-          if (k0 + 64 * j >= cnt) break;
+        for (int j = 0; j < G; j++) {
           const LinS s = load_ent<FAM>(ev[j]);
           const int32_t K1 = s.K[0][0], K2 = s.K[0][1], K12 = K1 + K2;
           const int32_t S = imax32(K1, 0) + imax32(K2, 0);
           const int32_t F = k0 + 64 * j + lane < cnt ? s.F[0] : GV_F_NONE;
-          const int32_t u = 2 * F + pad + S, base = pad + S;
-          const uint32_t R = (uint32_t)(2 * S + (H + 2 * pad) - K12);
+          U[j] = 2 * F + pad + S;
+          BASE[j] = pad + S;
+          KA[j] = K1;
+          KB[j] = K2;
+          RR[j] = (uint32_t)(2 * S + (H + 2 * pad) - K12);
           const int32_t K1c = rne_half(K1), K2c = rne_half(K2);
           const uint32_t w = (uint32_t)s.w;
           if constexpr (!std::is_same<E, EntP3p>::value)
             fits = fits && abs(K1c) <= GV_P3_KMAX && abs(K2c) <= GV_P3_KMAX && w <= GV_P3_WMAX;
-          const uint32_t lo = ((uint32_t)K1c & 0x1fffu) | (((uint32_t)K2c & 0x1fffu) << 13) | ((w & 0x3fu) << 26);
-          const uint32_t whi = (w >> 6) << 16;
-          const int32_t uu[4] = {u, u + K2, u + K1, u + K12};  // (b1, b2) = 00, 01, 10, 11
+          LO[j] = ((uint32_t)K1c & 0x1fffu) | (((uint32_t)K2c & 0x1fffu) << 13) | ((w & 0x3fu) << 26);
+          WHI[j] = (w >> 6) << 16;
+        }
 #pragma unroll
-          for (int ch = 0; ch < 8; ch++) {
-            const int32_t t = (ch & 1) ? uu[ch >> 1] - H : uu[ch >> 1];
-            const bool c = (uint32_t)t <= R;
-            const uint64_t b = __builtin_amdgcn_ballot_w64(c) & keptm[ch];
-            if (c && kept[ch]) {
-              const int32_t Fc = rne_half(t - base);
+        for (int ch = 0; ch < 8; ch++) {
+          if (!kept[ch]) continue;
+#pragma unroll
+          for (int j = 0; j < G; j++) {
+            if (k0 + 64 * j >= cnt) break;
+            const int32_t uu = U[j] + ((ch & 4) ? KA[j] : 0) + ((ch & 2) ? KB[j] : 0);
+            const int32_t t = (ch & 1) ? uu - H : uu;
+            const bool c = (uint32_t)t <= RR[j];
+            const uint64_t b = __builtin_amdgcn_ballot_w64(c);
+            if (c) {
+              const int32_t Fc = rne_half(t - BASE[j]);
               flo = imin32(flo, Fc);
               fhi = imax32(fhi, Fc);
               EntP3p e;
-              e.lo = lo;
-              e.hi = ((uint32_t)Fc & 0xffffu) | whi;
+              e.lo = LO[j];
+              e.hi = ((uint32_t)Fc & 0xffffu) | WHI[j];
               (out + wpos[ch])[mbcnt64(b)] = e;
             }
             wpos[ch] += (uint64_t)__popcll(b);
