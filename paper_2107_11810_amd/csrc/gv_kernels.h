@@ -943,6 +943,52 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
     kmask = uniform_u32(kmask);
     if (!kmask) continue;
     const uint32_t cnt = I.cnt;
+    if constexpr (POSE) {
+      // G entries per lane in registers, survivors written child by child:
+      // one sequential run per child list instead of sixteen interleaved ones
+      // (entries move as 16-byte words: the copy never looks inside them)
+      static_assert(sizeof(E) % 16 == 0 && std::is_same<E, EO>::value, "pose entries are copied whole");
+      constexpr int NV = sizeof(E) / 16;
+      constexpr int G = sizeof(E) <= 32 ? 16 : 8;
+#pragma unroll
+      for (int ch = 0; ch < 16; ch++) wpos[ch] = uniform_u64(wpos[ch]);
+      const uint4* src = reinterpret_cast<const uint4*>(ents + I.off);
+      uint4* dst = reinterpret_cast<uint4*>(out);
+      for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * G) {
+        uint32_t mk[G];
+        uint4 ev[G][NV];
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+          const uint32_t k = k0 + 64 * j + lane;
+          mk[j] = k < cnt ? (uint32_t)masks[I.off + k] & kmask : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+#pragma unroll
+          for (int q = 0; q < NV; q++) {
+            ev[j][q] = make_uint4(0u, 0u, 0u, 0u);
+            if (mk[j]) ev[j][q] = src[(uint64_t)(k0 + 64 * j + lane) * NV + q];
+          }
+        }
+#pragma unroll
+        for (int ch = 0; ch < 16; ch++) {
+          if (!((kmask >> ch) & 1u)) continue;
+#pragma unroll
+          for (int j = 0; j < G; j++) {
+            if (k0 + 64 * j >= cnt) break;
+            const bool p = (mk[j] >> ch) & 1u;
+            const uint64_t bal = __ballot(p);
+            if (p) {
+              const uint64_t pos = wpos[ch] + mbcnt64(bal);
+#pragma unroll
+              for (int q = 0; q < NV; q++) dst[pos * NV + q] = ev[j][q];
+            }
+            wpos[ch] += (uint64_t)__popcll(bal);
+          }
+        }
+      }
+      continue;
+    }
     for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
       const uint32_t k = k0 + lane;
       const bool valid = k < cnt;
