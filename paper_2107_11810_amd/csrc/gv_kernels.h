@@ -51,7 +51,7 @@ __global__ void k_item_fill(const Cell* __restrict__ cells, uint32_t ncell, cons
 // run [t * GV_SMALL_PER, (t + 1) * GV_SMALL_PER) of the array.  Totals that
 // the host reads go to host-coherent memory, fenced at system scope.
 // ---------------------------------------------------------------------------
-#define GV_SMALL_PER 16
+#define GV_SMALL_PER 4
 #define GV_SMALL_N (1024u * GV_SMALL_PER)
 
 // Exclusive prefix of the per-thread values s over the workgroup (wsum: 16
@@ -109,18 +109,26 @@ __global__ void __launch_bounds__(1024) k_items_small(const Cell* __restrict__ c
                                                       uint32_t* __restrict__ total) {
   __shared__ uint32_t wsum[16];
   const uint32_t b = threadIdx.x * GV_SMALL_PER;
+  uint64_t off[GV_SMALL_PER];
+  uint32_t len[GV_SMALL_PER];
   uint32_t s = 0;
 #pragma unroll
-  for (int j = 0; j < GV_SMALL_PER; j++)
-    if (b + j < ncell) s += (cells[b + j].len + GV_ITEM - 1) / GV_ITEM;
+  for (int j = 0; j < GV_SMALL_PER; j++) {  // every load issued before any is used
+    const bool in = b + j < ncell;
+    off[j] = in ? cells[b + j].off : 0ull;
+    len[j] = in ? cells[b + j].len : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++) s += (len[j] + GV_ITEM - 1) / GV_ITEM;
   uint32_t tot;
   uint32_t o = block_excl<uint32_t>(s, wsum, tot);
-  for (uint32_t c = b; c < min(b + GV_SMALL_PER, ncell); c++) {
-    const uint64_t off = cells[c].off;
-    const uint32_t len = cells[c].len, k = (len + GV_ITEM - 1) / GV_ITEM;
-    ioff[c] = o;
-    for (uint32_t j = 0; j < k; j++)
-      items[o + j] = Item{off + (uint64_t)j * GV_ITEM, c, min((uint32_t)GV_ITEM, len - j * (uint32_t)GV_ITEM)};
+#pragma unroll
+  for (int j = 0; j < GV_SMALL_PER; j++) {
+    if (b + j >= ncell) break;
+    const uint32_t k = (len[j] + GV_ITEM - 1) / GV_ITEM;
+    ioff[b + j] = o;
+    for (uint32_t i = 0; i < k; i++)
+      items[o + i] = Item{off[j] + (uint64_t)i * GV_ITEM, b + j, min((uint32_t)GV_ITEM, len[j] - i * (uint32_t)GV_ITEM)};
     o += k;
   }
   if (threadIdx.x == 0) *total = tot;
