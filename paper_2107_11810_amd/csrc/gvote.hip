@@ -966,12 +966,20 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
       k_prob_max<<<nblk(nkept), 256, 0, X.st>>>(kcnt, kid, (uint32_t)nkept, b.cells, nch, pmax);
       k_prob_norm<<<nblk(nkept), 256, 0, X.st>>>(kcnt, kid, (uint32_t)nkept, b.cells, nch, pmax, key);
     }
+    // one problem: the key is a count, at most n, so only its low bits are
+    // sorted (fewer radix passes on small problems)
+    int end_bit = 32;
+    if (!pmax) {
+      end_bit = 1;
+      while (end_bit < 32 && (uint64_t)X.probs[0]->n >> end_bit) end_bit++;
+    }
     uint32_t* skey = dalloc<uint32_t>(X, nkept);
     size_t tb = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, key, skey, kid, pa->order, (int)nkept, 0, 32,
-                                                         X.st));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, key, skey, kid, pa->order, (int)nkept, 0,
+                                                         end_bit, X.st));
     void* tmp = dalloc<char>(X, tb);
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, key, skey, kid, pa->order, (int)nkept, 0, 32, X.st));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, key, skey, kid, pa->order, (int)nkept, 0, end_bit,
+                                                         X.st));
     dfree(X, tmp);
     dfree(X, skey);
     if (pmax) {
