@@ -89,6 +89,11 @@ template <> struct EntOf<FAM_RAY3D> { using T = EntR3; };
 #define GV_L2_MAX 32767    // |K|, |F| limit of a packed LINE2D entry
 struct __attribute__((aligned(8))) EntL2p { int16_t K, F; uint32_t w; };
 struct __attribute__((aligned(8))) EntP3p { uint32_t lo, hi; };
+// PLANE3D unit-weight lists at the deep levels, where the slopes fit 8 bits:
+// one word, K1 (8, signed) | K2 (8, signed) << 8 | F (16, signed) << 16, and
+// every multiplicity is 1.
+#define GV_P3U_KMAX 127
+struct __attribute__((aligned(4))) EntP3u { uint32_t v; };
 template <int FAM> struct PackOf { using T = void; };  // no packed entry
 template <> struct PackOf<FAM_LINE2D> { using T = EntL2p; };
 template <> struct PackOf<FAM_PLANE3D> { using T = EntP3p; };
@@ -229,6 +234,15 @@ template <int FAM> __device__ __host__ inline LinS load_ent(const EntP3p& e) {
   return s;
 }
 
+template <int FAM> __device__ __host__ inline LinS load_ent(const EntP3u& e) {
+  LinS s = lin_zero<FAM>();
+  s.K[0][0] = sext_field(e.v, 0, 8);
+  s.K[0][1] = sext_field(e.v, 8, 8);
+  s.F[0] = sext_field(e.v, 16, 16);
+  s.w = 1;
+  return s;
+}
+
 // register state -> entry; a packed store clears ok when a value does not fit
 template <int FAM, typename E> __device__ __host__ inline E store_ent(const LinS& s, bool& ok);
 template <> __device__ __host__ inline EntL2 store_ent<FAM_LINE2D, EntL2>(const LinS& s, bool&) {
@@ -256,6 +270,14 @@ template <> __device__ __host__ inline EntP3p store_ent<FAM_PLANE3D, EntP3p>(con
   ok = ok && abs(s.K[0][0]) <= GV_P3_KMAX && abs(s.K[0][1]) <= GV_P3_KMAX && abs(s.F[0]) <= GV_P3_FMAX &&
        (uint32_t)s.w <= GV_P3_WMAX;
   return pack_p3(s.K[0][0], s.K[0][1], s.F[0], (uint32_t)s.w);
+}
+
+template <> __device__ __host__ inline EntP3u store_ent<FAM_PLANE3D, EntP3u>(const LinS& s, bool& ok) {
+  ok = ok && abs(s.K[0][0]) <= GV_P3U_KMAX && abs(s.K[0][1]) <= GV_P3U_KMAX && abs(s.F[0]) <= GV_P3_FMAX &&
+       s.w == 1;
+  EntP3u e;
+  e.v = ((uint32_t)s.K[0][0] & 0xffu) | (((uint32_t)s.K[0][1] & 0xffu) << 8) | ((uint32_t)s.F[0] << 16);
+  return e;
 }
 
 template <int FAM> __device__ inline typename EntOf<FAM>::T store_lin(const LinS& s) {

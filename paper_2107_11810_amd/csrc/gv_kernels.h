@@ -207,6 +207,15 @@ __global__ void __launch_bounds__(1024) k_chunk_small(const uint32_t* __restrict
   }
 }
 
+// one-word unit-weight PLANE3D entries -> 8-byte entries (before grouping)
+__global__ void k_unit_to_p3(const EntP3u* __restrict__ in, uint64_t n, EntP3p* __restrict__ out) {
+  const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st) {
+    const LinS s = load_ent<FAM_PLANE3D>(in[i]);
+    out[i] = pack_p3(s.K[0][0], s.K[0][1], s.F[0], 1u);
+  }
+}
+
 // zero up to three u32 arrays in one launch
 __global__ void k_zero3(uint32_t* __restrict__ a, uint64_t na, uint32_t* __restrict__ b, uint64_t nb,
                         uint32_t* __restrict__ c, uint64_t nc) {
@@ -797,7 +806,9 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t nwork = *nwork_p;
-  if constexpr (FAM == FAM_PLANE3D && NCH == 8 && std::is_same<EO, EntP3p>::value) {
+  if constexpr (FAM == FAM_PLANE3D && NCH == 8 &&
+                (std::is_same<EO, EntP3p>::value || std::is_same<EO, EntP3u>::value)) {
+    constexpr bool UW = std::is_same<EO, EntP3u>::value;  // one-word unit-weight child entries
     // Every axis splits; child digit = 4 b1 + 2 b2 + b0 (split axes in axis
     // order, most significant first).  The pass test compares
     // t = 2F + pad + S + b1 K1 + b2 K2 - b0 H against [0, R] (unsigned), and
@@ -848,10 +859,18 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
           RR[j] = (uint32_t)(2 * S + (H + 2 * pad) - K12);
           const int32_t K1c = rne_half(K1), K2c = rne_half(K2);
           const uint32_t w = (uint32_t)s.w;
-          if constexpr (!std::is_same<E, EntP3p>::value)
-            fits = fits && abs(K1c) <= GV_P3_KMAX && abs(K2c) <= GV_P3_KMAX && w <= GV_P3_WMAX;
-          LO[j] = ((uint32_t)K1c & 0x1fffu) | (((uint32_t)K2c & 0x1fffu) << 13) | ((w & 0x3fu) << 26);
-          WHI[j] = (w >> 6) << 16;
+          if constexpr (UW) {
+            // a one-word input's K and weight always fit
+            if constexpr (!std::is_same<E, EntP3u>::value)
+              fits = fits && abs(K1c) <= GV_P3U_KMAX && abs(K2c) <= GV_P3U_KMAX && (w == 1u || F == GV_F_NONE);
+            LO[j] = ((uint32_t)K1c & 0xffu) | (((uint32_t)K2c & 0xffu) << 8);
+            WHI[j] = 0u;
+          } else {
+            if constexpr (!std::is_same<E, EntP3p>::value)
+              fits = fits && abs(K1c) <= GV_P3_KMAX && abs(K2c) <= GV_P3_KMAX && w <= GV_P3_WMAX;
+            LO[j] = ((uint32_t)K1c & 0x1fffu) | (((uint32_t)K2c & 0x1fffu) << 13) | ((w & 0x3fu) << 26);
+            WHI[j] = (w >> 6) << 16;
+          }
         }
 #pragma unroll
         for (int ch = 0; ch < 8; ch++) {
@@ -867,9 +886,13 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
               const int32_t Fc = rne_half(t - BASE[j]);
               flo = imin32(flo, Fc);
               fhi = imax32(fhi, Fc);
-              EntP3p e;
-              e.lo = LO[j];
-              e.hi = ((uint32_t)Fc & 0xffffu) | WHI[j];
+              EO e;
+              if constexpr (UW) {
+                e.v = LO[j] | ((uint32_t)Fc << 16);
+              } else {
+                e.lo = LO[j];
+                e.hi = ((uint32_t)Fc & 0xffffu) | WHI[j];
+              }
               (out + wpos[ch])[mbcnt64(b)] = e;
             }
             wpos[ch] += (uint64_t)__popcll(b);

@@ -454,6 +454,7 @@ struct Run {
   unsigned long long* dreads = nullptr;   // parent bytes read by compaction passes
   int* dovf = nullptr;                    // set when a packed entry could not hold a value
   int pack_from = 1 << 30;                // lists of this level and deeper use the packed entry
+  int unit_from = 1 << 30;                // PLANE3D unit-weight lists of this level and deeper: one word
   size_t ent_bytes = 0;
   uint64_t chunk_bytes = 0;               // device bytes one materialized chunk may need
   uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
@@ -924,7 +925,8 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     const uint64_t bst = d2h1(X, X.dbest);
     std::fprintf(stderr, "gv: level %d cells %u entries %llu kept %llu best %llu%s%s\n", m, b.ncell,
                  (unsigned long long)b.nent, (unsigned long long)nkept, (unsigned long long)(bst >> P.B),
-                 dive ? " (dive)" : "", m >= X.pack_from ? " packed" : "");
+                 dive ? " (dive)" : "",
+                 (b.unit && m >= X.unit_from) ? " one-word" : (m >= X.pack_from ? " packed" : ""));
   }
   if (nkept == 0) {
     dfree(X, keepf);
@@ -1127,7 +1129,20 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   dfree(X, csize);
   dfree(X, coff);
   if (--pa->pending == 0) free_parent(X, pa);
-  if (made && want_group(X, nb)) group_batch<EO>(X, nb, true);
+  if constexpr (std::is_same<EO, EntP3u>::value) {
+    // merged entries carry weights: widen to the 8-byte entry, then group
+    if (made && want_group(X, nb)) {
+      if (X.trace) std::fprintf(stderr, "gv: level %d one-word lists widened for grouping\n", nb.level);
+      EntP3p* w = dalloc<EntP3p>(X, nb.nent);
+      k_unit_to_p3<<<gs_grid(X, nb.nent), 256, 0, X.st>>>((const EntP3u*)nb.ents, nb.nent, w);
+      dfree(X, nb.ents);
+      nb.ents = w;
+      nb.unit = false;
+      group_batch<EntP3p>(X, nb, true);
+    }
+  } else {
+    if (made && want_group(X, nb)) group_batch<EO>(X, nb, true);
+  }
   return made;
 }
 
@@ -1138,6 +1153,8 @@ using PackedT = std::conditional_t<FAM == FAM_POSE4DOF || std::is_void_v<typenam
 
 template <int FAM, typename E, typename M>
 Parent* expand_at(Run& X, Batch& b, bool own_ents, bool dive) {
+  if constexpr (FAM == FAM_PLANE3D)
+    if (b.unit && b.level >= X.unit_from) return expand<FAM, EntP3u, M>(X, b, own_ents, dive);
   if (b.level >= X.pack_from) return expand<FAM, PackedT<FAM, E>, M>(X, b, own_ents, dive);
   return expand<FAM, E, M>(X, b, own_ents, dive);
 }
@@ -1145,6 +1162,13 @@ Parent* expand_at(Run& X, Batch& b, bool own_ents, bool dive) {
 template <int FAM, typename E, typename M>
 bool materialize_at(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   using EP = PackedT<FAM, E>;
+  if constexpr (FAM == FAM_PLANE3D) {
+    if (pa->unit && pa->level + 1 >= X.unit_from) {
+      if (pa->level >= X.unit_from) return materialize<FAM, EntP3u, EntP3u, M>(X, pa, r0, r1, nb);
+      if (pa->level >= X.pack_from) return materialize<FAM, EP, EntP3u, M>(X, pa, r0, r1, nb);
+      return materialize<FAM, E, EntP3u, M>(X, pa, r0, r1, nb);
+    }
+  }
   if (pa->level >= X.pack_from) return materialize<FAM, EP, EP, M>(X, pa, r0, r1, nb);
   if (pa->level + 1 >= X.pack_from) return materialize<FAM, E, EP, M>(X, pa, r0, r1, nb);
   return materialize<FAM, E, E, M>(X, pa, r0, r1, nb);
@@ -1525,6 +1549,23 @@ void build_linear(Run& X) {
       const double fb = (double)P.lev[m].H[q] + (double)P.lev[m - 1].padu[q] + 2.0 * ks + 4.0;
       if (kb > kmax || fb > fmax) break;
       X.pack_from = m;
+    }
+  }
+  // PLANE3D: first level from which unit-weight lists fit one word (slopes
+  // 8 bits, heights 16).  A one-word list that is to be grouped is widened to
+  // the 8-byte entry first, so these levels lie within the packed ones.
+  X.unit_from = 1 << 30;
+  if (FAM == FAM_PLANE3D && X.ctx->pack) {
+    for (int m = P.Lstar - 1; m >= std::max(1, X.pack_from); m--) {
+      double kb = 0.0, ks = 0.0;
+      for (int pi = 0; pi < 2; pi++) {
+        const double km = std::ceil((double)mk_all / std::ldexp(1.0, std::min(m, P.L[pi]))) + 1.0;
+        kb = std::max(kb, km);
+        ks += km;
+      }
+      const double fb = (double)P.lev[m].H[2] + (double)P.lev[m - 1].padu[2] + 2.0 * ks + 4.0;
+      if (kb > GV_P3U_KMAX || fb > GV_P3_FMAX) break;
+      X.unit_from = m;
     }
   }
   X.root = root;

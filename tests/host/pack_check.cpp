@@ -1,4 +1,5 @@
-// Host-side check of the packed list entries: every value inside the
+// Host-side check of the packed list entries (8-byte LINE2D and PLANE3D,
+// one-word PLANE3D unit-weight): every value inside the
 // limits round-trips exactly, every value outside is flagged.  Built with
 // hipcc as host code (the entry functions are host-callable).
 #include "../../paper_2107_11810_amd/csrc/gv_device.h"
@@ -52,6 +53,26 @@ int main() {
   {
     bool ok = false;
     (void)store_ent<FAM_PLANE3D, EntP3p>(plane(0, 0, 0, 1), ok);
+    CHECK(!ok);
+  }
+  // PLANE3D one-word unit-weight entry: 8-bit K1, K2, 16-bit F, weight 1
+  static_assert(sizeof(EntP3u) == 4, "the one-word entry is 4 bytes");
+  const int32_t ku[] = {0, 1, -1, 2, -2, 64, -64, 100, -100, GV_P3U_KMAX, -GV_P3U_KMAX, GV_P3U_KMAX - 1};
+  for (int32_t K1 : ku)
+    for (int32_t K2 : ku)
+      for (int32_t F : fs) {
+        bool ok = true;
+        const EntP3u e = store_ent<FAM_PLANE3D, EntP3u>(plane(K1, K2, F, 1), ok);
+        const LinS r = load_ent<FAM_PLANE3D>(e);
+        CHECK(ok);
+        CHECK(r.K[0][0] == K1 && r.K[0][1] == K2 && r.F[0] == F && r.w == 1);
+      }
+  const LinS badu[] = {plane(GV_P3U_KMAX + 1, 0, 0, 1), plane(0, -GV_P3U_KMAX - 1, 0, 1),
+                       plane(0, 0, GV_P3_FMAX + 1, 1), plane(0, 0, -GV_P3_FMAX - 1, 1), plane(0, 0, 0, 2),
+                       plane(0, 0, 0, 0)};
+  for (const LinS& s : badu) {
+    bool ok = true;
+    (void)store_ent<FAM_PLANE3D, EntP3u>(s, ok);
     CHECK(!ok);
   }
   // LINE2D: 16-bit K and F, full 32-bit weight

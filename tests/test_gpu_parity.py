@@ -216,3 +216,30 @@ def test_packed_entries_change_nothing(ctx, name, seed):
     r_pack = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
     check_same(g, r_pack, r_full)
     check_same(g, r_pack, oracle.solve(OP(g)))
+
+
+@pytest.mark.parametrize("n,eps", [(100000, 0.1), (20000, 0.05)])
+def test_dense_plane_grouping_parity(ctx, n, eps):
+    """Every point on one plane: the winning cells' lists hold every surface
+    down to the leaves, so lists at the deep levels (one-word unit-weight
+    entries) outgrow their lattice and are grouped (widened first).  Same
+    result as the oracle and as full entries (GV_PACK=0)."""
+    import os
+    from paper_2107_11810_amd import gvote
+    g = synth.plane3d(seed=7, n=n, n_in=n, sigma=0.0, eps=(eps,) * 3)
+    _say("dense plane", n, eps)
+    r = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    check_same(g, r, oracle.solve(OP(g)))
+    old = os.environ.get("GV_PACK")
+    os.environ["GV_PACK"] = "0"
+    try:
+        full = gvote.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("GV_PACK", None)
+        else:
+            os.environ["GV_PACK"] = old
+    try:
+        check_same(g, r, full.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"]))
+    finally:
+        full.close()
