@@ -230,7 +230,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=3, help="untimed solves first (they include the autotuning)")
     ap.add_argument("--workload", default="plane3d_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-tests", type=float, default=2.5e8, help="oracle sample size (incidence tests)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -84,7 +84,8 @@ typedef struct {
                                  kernel the library times each candidate grid
                                  (2, 4, 8, 16 or 32 blocks of 4 waves per CU)
                                  on its large launches with HIP events and
-                                 keeps the one with the least time per entry;
+                                 keeps the one with the least time per byte
+                                 of list entries moved;
                                  launches before that use 8.  The choices are
                                  read from the file at creation (lines
                                  "arch CUs family kernel blocks" of this

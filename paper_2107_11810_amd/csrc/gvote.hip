@@ -117,11 +117,13 @@ struct Lane;
 
 // Candidate grids of the item-looping kernels, in blocks of four waves per
 // CU.  A slot tries them in turn on its large launches and keeps the one with
-// the lowest event time per entry once each has kTuneSamples samples.
+// the lowest event time per byte (the entry bytes the launch reads or
+// writes, so levels with different entry sizes compare) once each has
+// kTuneSamples samples.
 constexpr int kTuneCand[] = {2, 4, 8, 16, 32};
 constexpr int kNCand = 5;
-constexpr int kTuneSamples = 3;
-constexpr uint64_t kTuneMinEntries = 8ull << 20;  // smaller launches use the default shape
+constexpr int kTuneSamples = 4;
+constexpr uint64_t kTuneMinBytes = 256ull << 20;  // smaller launches use the default shape
 constexpr int kGridDefault = 8;
 struct gvi_tune_slot {
   int chosen = 0;  // blocks per CU once chosen
@@ -169,7 +171,7 @@ struct gv_ctx {
   std::mutex tmu;
   gvi_tune_slot tune[5][2];
   bool autotune = true;
-  uint64_t tune_min = kTuneMinEntries;  // launches with fewer entries are not tuning samples
+  uint64_t tune_min = kTuneMinBytes;  // launches of fewer entry bytes are not tuning samples
   std::string tune_path;   // autotune cache file ("" = keep choices in memory)
   std::string arch;        // device architecture name, the cache file's key
 };
@@ -469,7 +471,7 @@ struct Run {
     std::pair<hipEvent_t, hipEvent_t> e;
     int kind;        // 0 count, 1 compaction
     int cand;        // autotuner candidate index, -1 when not a tuning sample
-    uint64_t units;  // entries the launch processed
+    uint64_t units;  // entry bytes the launch read (count) or wrote (compaction)
   };
   std::vector<EvRec> ev;
   size_t ev_used = 0;
@@ -638,7 +640,7 @@ void tune_save(gv_ctx* c) {
 }
 
 // One timed tuning launch; once every candidate has its samples the slot
-// keeps the lowest time per entry.
+// keeps the lowest time per byte.
 void tune_sample(Run& X, int kind, int cand, double ms, uint64_t units) {
   gv_ctx* c = X.ctx;
   std::lock_guard<std::mutex> g(c->tmu);
@@ -656,13 +658,13 @@ void tune_sample(Run& X, int kind, int cand, double ms, uint64_t units) {
   if (X.trace) {
     std::fprintf(stderr, "gv: autotune family %d %s:", X.P0.fam, kind ? "compaction" : "count");
     for (int k = 0; k < kNCand; k++) std::fprintf(stderr, " %d:%.3g", kTuneCand[k], t.ms[k] / t.units[k] * 1e9);
-    std::fprintf(stderr, " ps/entry -> %d blocks per CU\n", t.chosen);
+    std::fprintf(stderr, " ps/byte -> %d blocks per CU\n", t.chosen);
   }
   tune_save(c);
 }
 
-// Blocks per CU of the next count (kind 0) or compaction (kind 1) launch of
-// X.units entries; *cand = the candidate index when the launch is a tuning
+// Blocks per CU of the next count (kind 0) or compaction (kind 1) launch
+// moving `units` entry bytes; *cand = the candidate index when the launch is a tuning
 // sample, else -1.
 int grid_pick(Run& X, int kind, uint64_t units, int* cand) {
   *cand = -1;
@@ -824,11 +826,12 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     k_zero3<<<gs_grid(X, std::max(nk, ni)), 256, 0, X.st>>>(ccnt, nk, pa->cnent, nk, itemcnt, ni);
   }
   int cand;
-  const int gpc = grid_pick(X, 0, b.nent, &cand);
+  const uint64_t tbytes = FAM != FAM_POSE4DOF ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
+  const int gpc = grid_pick(X, 0, tbytes, &cand);
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * gpc);
-  auto evp = ev_begin(X, 0, cand, b.nent);
+  auto evp = ev_begin(X, 0, cand, tbytes);
   X.stats.test_launches++;
-  X.stats.test_bytes += linear ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
+  X.stats.test_bytes += tbytes;
   if constexpr (FAM == FAM_POSE4DOF) {
 #define GV_COUNT_POSE(U, A)                                                                                 \
   k_count_pose<E, U, A><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, \
@@ -1072,7 +1075,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     k_emit_ranked<<<nblk(nr), 256, 0, X.st>>>(lv, pa->cells, pa->order, r0, r1, keepc, cidx, coff, pa->cnent,
                                               nb.cells);
     int cand;
-    const int gpc = grid_pick(X, 1, nb.nent, &cand);
+    const int gpc = grid_pick(X, 1, nb.nent * sizeof(EO), &cand);
     const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * gpc);
     const bool linear = FAM != FAM_POSE4DOF;
     // linear families: the items with a child in this chunk become a work
@@ -1098,7 +1101,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
       k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(
           pa->cells, pa->ncell, nch, pa->rank_of, r0, r1, keepc,
           (uint32_t)(linear ? 8 * sizeof(E) : 8 * (sizeof(E) + sizeof(M))), X.dreads);
-    auto evp = ev_begin(X, 1, cand, nb.nent);
+    auto evp = ev_begin(X, 1, cand, nb.nent * sizeof(EO));
     X.stats.compact_launches++;
     X.stats.compact_bytes += nb.nent * sizeof(EO);
     if constexpr (FAM == FAM_POSE4DOF) {
@@ -2038,7 +2041,7 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
   if (c->arch.empty()) c->arch = "unknown";
   if (cfg && cfg->autotune_cache) c->tune_path = cfg->autotune_cache;
   if (const char* e = std::getenv("GV_AUTOTUNE")) c->autotune = atoi(e) != 0;
-  if (const char* e = std::getenv("GV_TUNE_MIN_ENTRIES")) c->tune_min = std::strtoull(e, nullptr, 10);
+  if (const char* e = std::getenv("GV_TUNE_MIN_BYTES")) c->tune_min = std::strtoull(e, nullptr, 10);
   tune_load(c);
   if (cfg && cfg->hip_stream) {
     c->stream = (hipStream_t)cfg->hip_stream;

@@ -81,7 +81,7 @@ def test_autotune_cache_and_results(tmp_path, name):
         base.close()
     assert r0["count"] == ro["count"] and r0["leaf_index"] == ro["leaf_index"]
     assert np.array_equal(r0["inliers"], ro["inliers"])
-    with Env(GV_TUNE_MIN_ENTRIES=0):
+    with Env(GV_TUNE_MIN_BYTES=0):
         c = gvote.Context(0, autotune_cache=path)
         try:
             for i in range(12):
@@ -99,7 +99,7 @@ def test_autotune_cache_and_results(tmp_path, name):
         assert ncu > 0 and f in (1, 2, 3, 4) and k in (0, 1) and blocks in CANDIDATES
     before = open(path).read()
     # choices read back: no more tuning samples, same results, file unchanged
-    with Env(GV_TUNE_MIN_ENTRIES=0):
+    with Env(GV_TUNE_MIN_BYTES=0):
         c2 = gvote.Context(0, autotune_cache=path)
         try:
             assert same(solve(c2, g), r0)
