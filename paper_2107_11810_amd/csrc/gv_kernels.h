@@ -565,6 +565,29 @@ __global__ void __launch_bounds__(256, 4) k_count_pose(const ProbC* __restrict__
 // and, at the last level, the best-key reduction (u64 atomic max).
 // key = count * 2^B + (2^B - 1 - leaf index): largest count, lowest index.
 // ---------------------------------------------------------------------------
+// Best-key update of a wave's leaf keys: when every active lane belongs to
+// one problem (the usual case) the wave reduces its maximum first and one
+// lane issues the atomic; otherwise every lane does.  Every lane of the wave
+// must call it (inactive ones with active = false).
+__device__ inline void wave_best_max(unsigned long long* __restrict__ best, uint32_t prob, uint64_t key,
+                                     bool active) {
+  const uint64_t act = __builtin_amdgcn_ballot_w64(active);
+  if (!act) return;
+  const uint32_t lead = (uint32_t)__builtin_ctzll(act);
+  const uint32_t p0 = __shfl(prob, (int)lead, 64);
+  if (__builtin_amdgcn_ballot_w64(active && prob != p0) == 0ull) {
+    uint64_t k = active ? key : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint64_t y = __shfl_xor(k, o, 64);
+      k = y > k ? y : k;
+    }
+    if (lane_id() == lead && k > best[p0]) atomicMax(&best[p0], (unsigned long long)k);
+  } else if (active && key > best[prob]) {
+    atomicMax(&best[prob], (unsigned long long)key);
+  }
+}
+
 __global__ void k_prune(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell* __restrict__ cells, uint32_t ncell,
                         const uint32_t* __restrict__ ccnt, const uint32_t* __restrict__ cnent,
                         unsigned long long* __restrict__ best, uint32_t* __restrict__ keepf,
@@ -572,6 +595,19 @@ __global__ void k_prune(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell
   const uint32_t nch = 1u << lv.abits;
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nk = (uint64_t)ncell * nch;
+  if (leaf) {  // (uniform: the whole wave stays for the reduction)
+    const bool act = k < nk;
+    uint64_t key = 0;
+    uint32_t prob = 0;
+    if (act) {
+      const uint32_t c = (uint32_t)(k / nch), ch = (uint32_t)(k % nch);
+      const uint64_t pre = (cells[c].prefix << lv.abits) | ch;
+      key = ((uint64_t)ccnt[k] << B) | (idxmask - (pre << lv.rem_next));
+      prob = cells[c].prob;
+    }
+    wave_best_max(best, prob, key, act);
+    return;
+  }
   if (k >= nk) return;
   const uint32_t c = (uint32_t)(k / nch), ch = (uint32_t)(k % nch);
   const Cell& C = cells[c];
@@ -579,9 +615,7 @@ __global__ void k_prune(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell
   const uint64_t idxmin = pre << lv.rem_next;
   const uint64_t key = ((uint64_t)ccnt[k] << B) | (idxmask - idxmin);
   unsigned long long* bp = &best[C.prob];
-  if (leaf) {
-    if (key > *bp) atomicMax(bp, (unsigned long long)key);
-  } else {
+  {
     const uint32_t keep = key > *bp ? 1u : 0u;
     keepf[k] = keep;
     keptn[k] = keep ? (uint64_t)cnent[k] : 0ull;
@@ -595,20 +629,27 @@ __global__ void k_pick_best(LevelC lv, int B, uint64_t idxmask, int leaf, const 
                             unsigned long long* __restrict__ best, uint32_t* __restrict__ keepf,
                             uint64_t* __restrict__ keptn) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
+  const bool act = c < ncell;
   const uint32_t nch = 1u << lv.abits;
   const uint64_t o = (uint64_t)c * nch;
   uint32_t bc = 0, bd = 0;
-  for (uint32_t ch = 0; ch < nch; ch++)
-    if (ch == 0 || ccnt[o + ch] > bc) { bc = ccnt[o + ch]; bd = ch; }
-  for (uint32_t ch = 0; ch < nch; ch++) {
-    keepf[o + ch] = (ch == bd) ? 1u : 0u;
-    keptn[o + ch] = (ch == bd) ? (uint64_t)cnent[o + ch] : 0ull;
+  if (act) {
+    for (uint32_t ch = 0; ch < nch; ch++)
+      if (ch == 0 || ccnt[o + ch] > bc) { bc = ccnt[o + ch]; bd = ch; }
+    for (uint32_t ch = 0; ch < nch; ch++) {
+      keepf[o + ch] = (ch == bd) ? 1u : 0u;
+      keptn[o + ch] = (ch == bd) ? (uint64_t)cnent[o + ch] : 0ull;
+    }
   }
-  if (leaf) {
-    const uint64_t pre = (cells[c].prefix << lv.abits) | bd;
-    const uint64_t key = ((uint64_t)bc << B) | (idxmask - (pre << lv.rem_next));
-    atomicMax(&best[cells[c].prob], (unsigned long long)key);
+  if (leaf) {  // (uniform: the whole wave stays for the reduction)
+    uint64_t key = 0;
+    uint32_t prob = 0;
+    if (act) {
+      const uint64_t pre = (cells[c].prefix << lv.abits) | bd;
+      key = ((uint64_t)bc << B) | (idxmask - (pre << lv.rem_next));
+      prob = cells[c].prob;
+    }
+    wave_best_max(best, prob, key, act);
   }
 }
 

@@ -553,6 +553,31 @@ void excl_scan(Run& X, const In* in, Out* out, uint64_t n) {
   dfree(X, tmp);
 }
 
+// Stable descending sort of at most GV_SMALL_N (key, value) pairs in one
+// workgroup (a block radix sort over the key's low end_bit bits): one launch
+// where the device-wide sort takes several.  Padding keys are 0 and sort
+// after every real key of 0, because the sort is stable.
+__global__ void __launch_bounds__(1024) k_sort_desc_small(const uint32_t* __restrict__ key,
+                                                          const uint32_t* __restrict__ val, uint32_t n, int end_bit,
+                                                          uint32_t* __restrict__ out) {
+  constexpr int PER = GV_SMALL_N / 1024;
+  using BRS = hipcub::BlockRadixSort<uint32_t, 1024, PER, uint32_t>;
+  __shared__ typename BRS::TempStorage tmp;
+  uint32_t k[PER], v[PER];
+#pragma unroll
+  for (int j = 0; j < PER; j++) {
+    const uint32_t i = threadIdx.x * PER + j;
+    k[j] = i < n ? key[i] : 0u;
+    v[j] = i < n ? val[i] : 0xffffffffu;
+  }
+  BRS(tmp).SortDescending(k, v, 0, end_bit);
+#pragma unroll
+  for (int j = 0; j < PER; j++) {
+    const uint32_t i = threadIdx.x * PER + j;
+    if (i < n) out[i] = v[j];
+  }
+}
+
 inline unsigned nblk(uint64_t n, unsigned b = 256) { return (unsigned)std::max<uint64_t>(1, (n + b - 1) / b); }
 inline unsigned gs_grid(Run& X, uint64_t n) {
   return (unsigned)std::min<uint64_t>(nblk(n), (uint64_t)X.ctx->n_cu * 16);
@@ -978,15 +1003,19 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
       end_bit = 1;
       while (end_bit < 32 && (uint64_t)X.probs[0]->n >> end_bit) end_bit++;
     }
-    uint32_t* skey = dalloc<uint32_t>(X, nkept);
-    size_t tb = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, key, skey, kid, pa->order, (int)nkept, 0,
-                                                         end_bit, X.st));
-    void* tmp = dalloc<char>(X, tb);
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, key, skey, kid, pa->order, (int)nkept, 0, end_bit,
-                                                         X.st));
-    dfree(X, tmp);
-    dfree(X, skey);
+    if (nkept <= GV_SMALL_N) {
+      k_sort_desc_small<<<1, 1024, 0, X.st>>>(key, kid, (uint32_t)nkept, end_bit, pa->order);
+    } else {
+      uint32_t* skey = dalloc<uint32_t>(X, nkept);
+      size_t tb = 0;
+      HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, key, skey, kid, pa->order, (int)nkept, 0,
+                                                           end_bit, X.st));
+      void* tmp = dalloc<char>(X, tb);
+      HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, key, skey, kid, pa->order, (int)nkept, 0, end_bit,
+                                                           X.st));
+      dfree(X, tmp);
+      dfree(X, skey);
+    }
     if (pmax) {
       dfree(X, pmax);
       dfree(X, key);
