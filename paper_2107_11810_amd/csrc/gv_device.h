@@ -453,47 +453,48 @@ __device__ inline bool khalf64(const VBox<double>& v, double rmin2, double Rg2, 
   return khalf64e(v, rmin2, Rg2, kedge<double>(xi, Llo, Lhi));
 }
 
-// binary32 filters: return 1 (meets), 0 (misses) or -1 (undecided: the
-// binary32 value lies within its certified error bound of the threshold).
-// Inputs are exact in binary32 (checked per problem on the host).
+// binary32 filters: each decides meets / misses, or reports the half as
+// undecided when a binary32 value lies within its certified error bound of
+// the threshold.  Inputs are exact in binary32 (checked per problem on the
+// host).  Each certified sign is a pair of comparisons (v > bound: positive,
+// v < -bound: negative, neither: undecided), kept as lane masks so that the
+// logic combining them runs on the scalar unit.
 #define GV_U32 5.9604644775390625e-08f  // 2^-24
 
-__device__ inline int sgn_cert(float v, float bound) { return v > bound ? 1 : (v < -bound ? -1 : 0); }
-
-
-__device__ inline int zhalf32p(const ZPre<float>& z, float rmin2, float rmax2) {
-  int lo_ok;
-  if (z.Tlo <= 0.0f) lo_ok = 1;
-  else {
-    float X = z.a2 * rmax2;
-    int s = sgn_cert(X - z.Ylo, 8.0f * GV_U32 * (X + z.Ylo));
-    lo_ok = s > 0 ? 1 : (s < 0 ? 0 : -1);
-  }
-  if (lo_ok == 0) return 0;
-  if (z.Thi < 0.0f) return 0;
-  float X = z.a2 * rmin2;
-  int s = sgn_cert(z.Yhi - X, 8.0f * GV_U32 * (X + z.Yhi));
-  const int hi_ok = s > 0 ? 1 : (s < 0 ? 0 : -1);
-  if (hi_ok == 0) return 0;
-  return (lo_ok == 1 && hi_ok == 1) ? 1 : -1;
+// z-half: returns whether it passes; *und = undecided (recheck in binary64).
+__device__ inline bool zhalf32m(const ZPre<float>& z, float rmin2, float rmax2, bool& und) {
+  const float X = z.a2 * rmax2;
+  const float dl = X - z.Ylo, bl = 8.0f * GV_U32 * (X + z.Ylo);
+  const bool lo_t = z.Tlo <= 0.0f;
+  const bool lp = lo_t || dl > bl, ln = !lo_t && dl < -bl;
+  const float X2 = z.a2 * rmin2;
+  const float dh = z.Yhi - X2, bh = 8.0f * GV_U32 * (X2 + z.Yhi);
+  const bool hneg = z.Thi < 0.0f;
+  const bool hp = !hneg && dh > bh, hn = hneg || dh < -bh;
+  const bool pass = lp && hp;
+  und = !(ln || hn) && !pass;
+  return pass;
 }
 
-__device__ inline int khalf32e(const VBox<float>& v, float rmin2, float Rg2, const KEdge<float>& e, float Sl,
-                               float Sh) {
-  int g = sgn_cert(Rg2 - rmin2, 4.0f * GV_U32 * (Rg2 + rmin2));
-  if (g > 0) return 1;  // apex guard certified
-  if (g == 0) return -1;
+// kappa-half: returns whether it passes; *und = undecided.  kSl, kSh: the
+// cross products' bound factors 8u (|p| + |e_x| + |e_y|) of e_lo and e_hi.
+__device__ inline bool khalf32m(const VBox<float>& v, float rmin2, float Rg2, const KEdge<float>& e, float kSl,
+                                float kSh, bool& und) {
+  const float gv = Rg2 - rmin2, gb = 4.0f * GV_U32 * (Rg2 + rmin2);
+  const bool gpos = gv > gb, gneg = gv < -gb;  // apex guard certified either way
   float ax, ay, bx, by;
-  if (!silhouette(v, ax, ay, bx, by)) return 1;
-  float Na = fabsf(ax) + fabsf(ay), Nb = fabsf(bx) + fabsf(by);
-  const float k = 8.0f * GV_U32;
-  int s1 = sgn_cert(e.elx * ay - e.ely * ax, k * Sl * Na);
-  int s2 = sgn_cert(ax * e.ehy - ay * e.ehx, k * Sh * Na);
-  int s3 = sgn_cert(e.elx * by - e.ely * bx, k * Sl * Nb);
-  int s4 = sgn_cert(bx * e.ehy - by * e.ehx, k * Sh * Nb);
-  if (s1 == 0 || s2 == 0 || s3 == 0 || s4 == 0) return -1;
-  bool r = (s1 > 0 && s2 > 0) || (s3 > 0 && s4 > 0) || (s1 < 0 && s3 > 0) || (s2 > 0 && s4 < 0);
-  return r ? 1 : 0;
+  const bool sil = silhouette(v, ax, ay, bx, by);
+  const float Na = fabsf(ax) + fabsf(ay), Nb = fabsf(bx) + fabsf(by);
+  const float v1 = e.elx * ay - e.ely * ax, b1 = kSl * Na;  // cross(e_lo, a)
+  const float v2 = ax * e.ehy - ay * e.ehx, b2 = kSh * Na;  // cross(a, e_hi)
+  const float v3 = e.elx * by - e.ely * bx, b3 = kSl * Nb;  // cross(e_lo, b)
+  const float v4 = bx * e.ehy - by * e.ehx, b4 = kSh * Nb;  // cross(b, e_hi)
+  const bool p1 = v1 > b1, n1 = v1 < -b1, p2 = v2 > b2, n2 = v2 < -b2;
+  const bool p3 = v3 > b3, n3 = v3 < -b3, p4 = v4 > b4, n4 = v4 < -b4;
+  const bool und_c = !(p1 || n1) || !(p2 || n2) || !(p3 || n3) || !(p4 || n4);
+  const bool r = (p1 && p2) || (p3 && p4) || (n1 && p3) || (p2 && n4);
+  und = !gpos && (!gneg || (sil && und_c));
+  return gpos || (gneg && (!sil || r));
 }
 // magnitudes bounding the rounding of the cross products with e_lo, e_hi
 __device__ inline float kedge_sl(const KEdge<float>& e) { return fabsf(e.pl) + fabsf(e.elx) + fabsf(e.ely); }

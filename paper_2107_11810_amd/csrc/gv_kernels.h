@@ -426,25 +426,26 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const C
   // terms shared by the four (x, y) parts
   const ZPre<float> zp[2] = {zpre<float>(e.W3, e.eta, Bf[8], Bf[10]), zpre<float>(e.W3, e.eta, Bf[9], Bf[11])};
   const KEdge<float> ke[2] = {kedge<float>(e.xi, Bf[12], Bf[14]), kedge<float>(e.xi, Bf[13], Bf[15])};
-  const float Sl[2] = {kedge_sl(ke[0]), kedge_sl(ke[1])}, Sh[2] = {kedge_sh(ke[0]), kedge_sh(ke[1])};
+  const float kSl[2] = {8.0f * GV_U32 * kedge_sl(ke[0]), 8.0f * GV_U32 * kedge_sl(ke[1])};
+  const float kSh[2] = {8.0f * GV_U32 * kedge_sh(ke[0]), 8.0f * GV_U32 * kedge_sh(ke[1])};
 #pragma unroll
   for (int xy = 0; xy < 4; xy++) {
     int bx = xy & 1, by = xy >> 1;
     if (!ALL && ((bx && !lv.split[0]) || (by && !lv.split[1]))) continue;
     VBox<float> v = pose_vbox<float>(e.W1, e.W2, Bf[0 + bx], Bf[2 + bx], Bf[4 + by], Bf[6 + by], sector);
     float rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
-    int zr[2] = {0, 0}, kr[2] = {0, 0};
+    bool zp_[2] = {false, false}, zu[2] = {false, false}, kp[2] = {false, false}, ku[2] = {false, false};
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       if (!ALL && b && !lv.split[2]) continue;
-      zr[b] = zhalf32p(zp[b], rmin2, rmax2);
+      zp_[b] = zhalf32m(zp[b], rmin2, rmax2, zu[b]);
     }
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       if (!ALL && b && !lv.split[3]) continue;
-      kr[b] = khalf32e(v, rmin2, P.Rg2f, ke[b], Sl[b], Sh[b]);
+      kp[b] = khalf32m(v, rmin2, P.Rg2f, ke[b], kSl[b], kSh[b], ku[b]);
     }
-    bool need = (zr[0] < 0) || (zr[1] < 0) || (kr[0] < 0) || (kr[1] < 0);
+    bool need = zu[0] || zu[1] || ku[0] || ku[1];
     if (need) {
       if (!have64) {
         const uint64_t r = e.ridx;
@@ -460,14 +461,14 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const C
       double rmin2d = rmin2_of(vd), rmax2d = rmax2_of(vd);
 #pragma unroll
       for (int b = 0; b < 2; b++) {
-        if (zr[b] < 0) { zr[b] = zhalf64(W3, eta, rmin2d, rmax2d, B.ZH[b], B.ZL[b]) ? 1 : 0; nrecheck++; }
-        if (kr[b] < 0) { kr[b] = khalf64(vd, rmin2d, P.Rg2, xi, B.Llo[b], B.Lhi[b]) ? 1 : 0; nrecheck++; }
+        if (zu[b]) { zp_[b] = zhalf64(W3, eta, rmin2d, rmax2d, B.ZH[b], B.ZL[b]); nrecheck++; }
+        if (ku[b]) { kp[b] = khalf64(vd, rmin2d, P.Rg2, xi, B.Llo[b], B.Lhi[b]); nrecheck++; }
       }
     }
 #pragma unroll
     for (int b = 0; b < 2; b++) {
-      if (zr[b] > 0) zbits |= 1u << (xy | (b << 2));
-      if (kr[b] > 0) kbits |= 1u << (xy | (b << 2));
+      if (zp_[b]) zbits |= 1u << (xy | (b << 2));
+      if (kp[b]) kbits |= 1u << (xy | (b << 2));
     }
   }
   uint32_t mask = 0;
