@@ -13,6 +13,7 @@
 // root and evaluated in binary64 (or binary32 with a certified bound).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #define GV_MAXL 40
@@ -70,6 +71,14 @@ struct __attribute__((aligned(8))) EntR3 { int32_t K1, K2, F1, F2, w, tag; };   
 
 // POSE4DOF entries: quantized parameters, weight, index of the root record.
 struct __attribute__((aligned(16))) EntQ32 { float W1, W2, W3, xi, eta; uint32_t w, ridx, _; };
+// unit-weight POSE4DOF lists below the root: the binary32 values and the
+// root index only (24 bytes; every multiplicity is 1)
+struct __attribute__((aligned(8))) EntQ24 { float W1, W2, W3, xi, eta; uint32_t ridx; };
+static_assert(sizeof(EntQ24) == 24 && offsetof(EntQ24, ridx) == 20 && offsetof(EntQ32, eta) == 16 &&
+                  offsetof(EntQ32, ridx) == 24,
+              "the compaction copies these entries as words");
+template <typename E> __device__ inline uint32_t pose_w(const E& e) { return e.w; }
+template <> __device__ inline uint32_t pose_w<EntQ24>(const EntQ24&) { return 1u; }
 struct __attribute__((aligned(16))) EntQ64 { double W1, W2, W3, xi, eta; uint32_t w, ridx; };
 
 template <int FAM> struct EntOf;

@@ -413,9 +413,9 @@ __device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const P
 
 // binary32 mask with binary64 recheck of undecided halves (the binary64
 // child boxes are built only when a recheck needs them)
-template <bool ALL>
+template <bool ALL, typename EQ>
 __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const Cell& C, int m, const float* Bf,
-                                       int sector, const EntQ32& e, const double* __restrict__ m64,
+                                       int sector, const EQ& e, const double* __restrict__ m64,
                                        uint64_t n_root, uint32_t& nrecheck) {
   const uint32_t nch = ALL ? 16u : 1u << lv.abits;
   PoseLevel B;
@@ -524,7 +524,7 @@ __global__ void __launch_bounds__(256, 4) k_count_pose(const ProbC* __restrict__
       uint32_t mask = 0, w = 0;
       if (k < cnt) {
         const E e = ents[ei];
-        w = e.w;
+        w = pose_w(e);
         if constexpr (sizeof(E) == sizeof(EntQ64)) {
           mask = pose_mask64<ALL>(P, lv, B, sector, e.W1, e.W2, e.W3, e.xi, e.eta);
         } else {
@@ -1019,17 +1019,20 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
     if constexpr (POSE) {
       // G entries per lane in registers, survivors written child by child:
       // one sequential run per child list instead of sixteen interleaved ones
-      // (entries move as 16-byte words: the copy never looks inside them)
-      static_assert(sizeof(E) % 16 == 0 && std::is_same<E, EO>::value, "pose entries are copied whole");
-      constexpr int NV = sizeof(E) / 16;
-      constexpr int G = sizeof(E) <= 32 ? 16 : 8;
+      // Entries move as words the copy never looks inside (16-byte words,
+      // or 8-byte ones for the 24-byte unit entry).  EntQ32 -> EntQ24 drops
+      // the weight (1 in a unit list) and the padding on the way.
+      constexpr bool CONV = std::is_same<E, EntQ32>::value && std::is_same<EO, EntQ24>::value;
+      static_assert(CONV || std::is_same<E, EO>::value, "pose entries are copied whole");
+      using Wd = std::conditional_t<sizeof(EO) % 16 == 0, uint4, uint2>;
+      constexpr int NV = sizeof(EO) / sizeof(Wd);
+      constexpr int G = sizeof(EO) <= 32 ? 16 : 8;
 #pragma unroll
       for (int ch = 0; ch < 16; ch++) wpos[ch] = uniform_u64(wpos[ch]);
-      const uint4* src = reinterpret_cast<const uint4*>(ents + I.off);
-      uint4* dst = reinterpret_cast<uint4*>(out);
+      Wd* dst = reinterpret_cast<Wd*>(out);
       for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * G) {
         uint32_t mk[G];
-        uint4 ev[G][NV];
+        Wd ev[G][NV];
 #pragma unroll
         for (int j = 0; j < G; j++) {
           const uint32_t k = k0 + 64 * j + lane;
@@ -1037,10 +1040,22 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
         }
 #pragma unroll
         for (int j = 0; j < G; j++) {
+          const uint64_t ei = I.off + k0 + 64 * j + lane;
+          if constexpr (CONV) {
+            uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = lo;
+            if (mk[j]) {
+              lo = reinterpret_cast<const uint4*>(ents + ei)[0];  // W1 W2 W3 xi
+              hi = reinterpret_cast<const uint4*>(ents + ei)[1];  // eta w ridx pad
+            }
+            ev[j][0] = make_uint2(lo.x, lo.y);
+            ev[j][1] = make_uint2(lo.z, lo.w);
+            ev[j][2] = make_uint2(hi.x, hi.z);
+          } else {
 #pragma unroll
-          for (int q = 0; q < NV; q++) {
-            ev[j][q] = make_uint4(0u, 0u, 0u, 0u);
-            if (mk[j]) ev[j][q] = src[(uint64_t)(k0 + 64 * j + lane) * NV + q];
+            for (int q = 0; q < NV; q++) {
+              ev[j][q] = Wd{};
+              if (mk[j]) ev[j][q] = reinterpret_cast<const Wd*>(ents + ei)[q];
+            }
           }
         }
 #pragma unroll
@@ -1079,11 +1094,8 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
         const uint64_t bal = __ballot(p);
         if (p) {
           const uint64_t pos = wpos[ch] + mbcnt64(bal);
-          if constexpr (POSE) {
-            out[pos] = e;
-          } else {
+          if constexpr (!POSE)  // (POSE4DOF lists take the path above)
             out[pos] = store_ent<FAM, EO>(lin_canon_child<FAM>(load_ent<FAM>(e), lv, lv.cbits[ch]), fits);
-          }
         }
         wpos[ch] += (uint64_t)__popcll(bal);
       }

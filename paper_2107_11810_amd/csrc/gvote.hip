@@ -457,6 +457,7 @@ struct Run {
   int* dovf = nullptr;                    // set when a packed entry could not hold a value
   int pack_from = 1 << 30;                // lists of this level and deeper use the packed entry
   int unit_from = 1 << 30;                // PLANE3D unit-weight lists of this level and deeper: one word
+  bool q24 = false;                       // POSE4DOF unit-weight lists below the root: 24-byte entries
   size_t ent_bytes = 0;
   uint64_t chunk_bytes = 0;               // device bytes one materialized chunk may need
   uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
@@ -1161,7 +1162,10 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   dfree(X, csize);
   dfree(X, coff);
   if (--pa->pending == 0) free_parent(X, pa);
-  if constexpr (std::is_same<EO, EntP3u>::value) {
+  if constexpr (std::is_same<EO, EntQ24>::value) {
+    // used only where no list is grouped
+    if (made && want_group(X, nb)) throw DevErr{GV_EINVAL};
+  } else if constexpr (std::is_same<EO, EntP3u>::value) {
     // merged entries carry weights: widen to the 8-byte entry, then group
     if (made && want_group(X, nb)) {
       if (X.trace) std::fprintf(stderr, "gv: level %d one-word lists widened for grouping\n", nb.level);
@@ -1187,6 +1191,8 @@ template <int FAM, typename E, typename M>
 Parent* expand_at(Run& X, Batch& b, bool own_ents, bool dive) {
   if constexpr (FAM == FAM_PLANE3D)
     if (b.unit && b.level >= X.unit_from) return expand<FAM, EntP3u, M>(X, b, own_ents, dive);
+  if constexpr (FAM == FAM_POSE4DOF && std::is_same<E, EntQ32>::value)
+    if (b.unit && b.level >= 1 && X.q24) return expand<FAM, EntQ24, M>(X, b, own_ents, dive);
   if (b.level >= X.pack_from) return expand<FAM, PackedT<FAM, E>, M>(X, b, own_ents, dive);
   return expand<FAM, E, M>(X, b, own_ents, dive);
 }
@@ -1194,6 +1200,12 @@ Parent* expand_at(Run& X, Batch& b, bool own_ents, bool dive) {
 template <int FAM, typename E, typename M>
 bool materialize_at(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   using EP = PackedT<FAM, E>;
+  if constexpr (FAM == FAM_POSE4DOF && std::is_same<E, EntQ32>::value) {
+    if (pa->unit && X.q24) {
+      if (pa->level >= 1) return materialize<FAM, EntQ24, EntQ24, M>(X, pa, r0, r1, nb);
+      return materialize<FAM, EntQ32, EntQ24, M>(X, pa, r0, r1, nb);
+    }
+  }
   if constexpr (FAM == FAM_PLANE3D) {
     if (pa->unit && pa->level + 1 >= X.unit_from) {
       if (pa->level >= X.unit_from) return materialize<FAM, EntP3u, EntP3u, M>(X, pa, r0, r1, nb);
@@ -1660,6 +1672,8 @@ bool build_pose(Run& X) {
     pr->filter_ok = pr->p.precision == GV_FP32_FILTER && pose_filter_exact(pr->S, mx);
     if (pr->st == GV_OK && !pr->filter_ok) all32 = false;
   }
+  // (grouping below the root is off for this family unless forced)
+  X.q24 = X.ctx->pack && X.group_mode <= 0;
   if (all32) {
     dfree(X, e64);
     X.root = e32;
