@@ -31,7 +31,7 @@ WORKLOADS = {
                             "on a random plane with vertical noise 0.001, eps 0.003 on (a1, a2, a0)",
                        kernel="k_count_lin<PLANE3D>", compact="k_compact_lin<PLANE3D>", bound="hbm"),
     "pose4dof_1m": dict(desc="gravity-aligned 4-DoF pose: 1e6 matches in a 200 m box, 0.5% inliers with 0.5 deg "
-                             "bearing noise, eps 0.5 m / 0.5 deg", kernel="k_count_pose<EntQ32>",
+                             "bearing noise, eps 0.5 m / 0.5 deg", kernel="k_count_pose<POSE4DOF>",
                         compact="k_compact<POSE4DOF>", bound="alu"),
     "ray3d_100k": dict(desc="ray intersection: 1e5 rays, 1% through a common centre", kernel="k_count_lin<RAY3D>",
                        compact="k_compact_lin<RAY3D>", bound="hbm"),
@@ -39,7 +39,7 @@ WORKLOADS = {
                        compact="k_compact_lin<LINE2D>", bound="hbm"),
     "pose4dof_serve256": dict(desc="256 independent 4-DoF pose problems, matches log-uniform in [1e3, 2e5], inlier "
                                    "ratio log-uniform in [0.2%, 10%], served through gv_submit/gv_poll",
-                              kernel="k_count_pose<EntQ32>", bound="alu"),
+                              kernel="k_count_pose<POSE4DOF>", bound="alu"),
 }
 
 
