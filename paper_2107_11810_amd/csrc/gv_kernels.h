@@ -805,14 +805,39 @@ template <int NCH> struct CWork {
   uint64_t wpos[NCH];
 };
 
+// Items a chunk [r0, r1) of a parent's kept children can draw from, written
+// to out[0], out[1] (host-coherent memory): in parent order (sorted == 0)
+// the chunk's children belong to a contiguous range of parent cells, so
+// only those cells' items; in count order every item.  Also clears the work
+// list's counter.
+__global__ void k_chunk_range(const uint32_t* __restrict__ order, uint32_t r0, uint32_t r1, uint32_t nch,
+                              const uint32_t* __restrict__ ioff, uint32_t ncell, const uint32_t* __restrict__ nitems_p,
+                              int sorted, uint32_t* __restrict__ nwork, uint64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *nwork = 0;
+    if (sorted || r1 <= r0) {
+      out[0] = 0;
+      out[1] = *nitems_p;
+    } else {
+      const uint32_t c0 = order[r0] / nch, c1 = order[r1 - 1] / nch;
+      out[0] = ioff[c0];
+      out[1] = c1 + 1 < ncell ? ioff[c1 + 1] : *nitems_p;
+    }
+    __threadfence_system();
+  }
+}
+
+// One thread per item of [i0, i1); with acc, also the bits of the entries
+// the compaction reads (items with a kept child in the chunk).
 template <int NCH>
-__global__ void k_chunk_work(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p,
+__global__ void k_chunk_work(const Item* __restrict__ items, uint32_t i0, uint32_t i1,
                              const uint64_t* __restrict__ itemoff, const uint32_t* __restrict__ rank_of, uint32_t r0,
                              uint32_t r1, const uint32_t* __restrict__ keepc, const uint64_t* __restrict__ coff,
-                             CWork<NCH>* __restrict__ work, uint32_t* __restrict__ nwork) {
-  const uint32_t it = blockIdx.x * blockDim.x + threadIdx.x;
+                             CWork<NCH>* __restrict__ work, uint32_t* __restrict__ nwork, uint32_t bits_per_entry,
+                             unsigned long long* __restrict__ acc) {
+  const uint32_t it = i0 + blockIdx.x * blockDim.x + threadIdx.x;
   CWork<NCH> w{};
-  if (it < *nitems_p) {
+  if (it < i1) {
     const Item I = items[it];
     w.off = I.off;
     w.cnt = I.cnt;
@@ -824,6 +849,11 @@ __global__ void k_chunk_work(const Item* __restrict__ items, const uint32_t* __r
         w.wpos[ch] = coff[r - r0] + itemoff[(uint64_t)it * NCH + ch];
       }
     }
+  }
+  if (acc) {
+    uint64_t v = w.kmask ? (uint64_t)w.cnt * bits_per_entry : 0ull;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63u) == 0 && v) atomicAdd(acc, (unsigned long long)v);
   }
   const uint64_t b = __ballot(w.kmask != 0u);
   if (!b) return;

@@ -600,15 +600,14 @@ void free_parent(Run& X, Parent* pa) {
   delete pa;
 }
 
-// the two totals the last kernels wrote to X.dtot
-void read_tot(Run& X, uint64_t* v) {
+// the first n (<= 4) totals the last kernels wrote to X.dtot
+void read_tot(Run& X, uint64_t* v, int n = 2) {
   if (X.hpin && X.dtot == X.hpin_dev) {
     host_wait(X);
     const volatile uint64_t* h = X.hpin;
-    v[0] = h[0];
-    v[1] = h[1];
+    for (int i = 0; i < n; i++) v[i] = h[i];
   } else {
-    HIPCHK(hipMemcpyAsync(v, X.dtot, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
+    HIPCHK(hipMemcpyAsync(v, X.dtot, n * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
     host_wait(X);
   }
 }
@@ -1092,8 +1091,16 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     excl_scan(X, csize, coff, nr);
     k_chunk_totals<<<1, 64, 0, X.st>>>(keepc, cidx, csize, coff, nr, X.dtot);
   }
-  uint64_t tot[2];
-  read_tot(X, tot);
+  // linear families: the item range the chunk draws from (read with the totals)
+  const bool linear = FAM != FAM_POSE4DOF;
+  uint32_t* nwork = nullptr;
+  if (linear) {
+    nwork = dalloc<uint32_t>(X, 1);
+    k_chunk_range<<<1, 64, 0, X.st>>>(pa->order, r0, r1, nch, pa->ioff, pa->ncell, pa->nitems, pa->sorted ? 1 : 0,
+                                      nwork, X.dtot + 2);
+  }
+  uint64_t tot[4];
+  read_tot(X, tot, linear ? 4 : 2);
   bool made = false;
   X.stats.cells_pruned += nr - tot[0];
   if (tot[0] > 0) {
@@ -1107,18 +1114,16 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     int cand;
     const int gpc = grid_pick(X, 1, nb.nent * sizeof(EO), &cand);
     const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * gpc);
-    const bool linear = FAM != FAM_POSE4DOF;
     // linear families: the items with a child in this chunk become a work
     // list (offsets resolved), then one wave per work item
     void* work = nullptr;
-    uint32_t* nwork = nullptr;
     if (linear) {
-      nwork = dalloc<uint32_t>(X, 1);
-      HIPCHK(hipMemsetAsync(nwork, 0, sizeof(uint32_t), X.st));
-#define GV_WORK(N)                                                                                               \
-  work = dalloc<CWork<N>>(X, pa->max_items);                                                                     \
-  k_chunk_work<N><<<nblk(pa->max_items), 256, 0, X.st>>>(pa->items, pa->nitems, pa->itemoff, pa->rank_of, r0, r1, \
-                                                        keepc, coff, (CWork<N>*)work, nwork)
+      const uint32_t i0 = (uint32_t)tot[2], i1 = (uint32_t)std::max(tot[2], tot[3]);
+#define GV_WORK(N)                                                                                                \
+  work = dalloc<CWork<N>>(X, std::max<uint64_t>(1, i1 - i0));                                                     \
+  k_chunk_work<N><<<nblk(i1 - i0), 256, 0, X.st>>>(pa->items, i0, i1, pa->itemoff, pa->rank_of, r0, r1, keepc, coff, \
+                                                  (CWork<N>*)work, nwork, (uint32_t)(8 * sizeof(E)),             \
+                                                  X.ctx->kernel_timing ? X.dreads : nullptr)
       switch (nch) {
         case 2: GV_WORK(2); break;
         case 4: GV_WORK(4); break;
@@ -1127,7 +1132,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
       }
 #undef GV_WORK
     }
-    if (X.ctx->kernel_timing)
+    if (X.ctx->kernel_timing && !linear)
       k_chunk_reads<<<nblk(pa->ncell), 256, 0, X.st>>>(
           pa->cells, pa->ncell, nch, pa->rank_of, r0, r1, keepc,
           (uint32_t)(linear ? 8 * sizeof(E) : 8 * (sizeof(E) + sizeof(M))), X.dreads);
@@ -1153,10 +1158,10 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     ev_end(X, evp);
     HIPCHK(hipGetLastError());
     dfree(X, work);
-    dfree(X, nwork);
     nb.unit = pa->unit;
     made = true;
   }
+  dfree(X, nwork);
   dfree(X, keepc);
   dfree(X, cidx);
   dfree(X, csize);
@@ -1334,7 +1339,7 @@ void epoch_begin(Run& X) {
   X.dP = dalloc<ProbC>(X, np);
   X.dbest = dalloc<unsigned long long>(X, np);
   X.drecheck = dalloc<unsigned long long>(X, 1);
-  X.dtot = X.hpin_dev ? X.hpin_dev : dalloc<uint64_t>(X, 2);
+  X.dtot = X.hpin_dev ? X.hpin_dev : dalloc<uint64_t>(X, 4);
   X.dummy = dalloc<uint32_t>(X, 64);
   X.dreads = dalloc<unsigned long long>(X, 1);
   X.dovf = dalloc<int>(X, 1);
