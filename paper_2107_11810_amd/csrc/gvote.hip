@@ -460,7 +460,7 @@ struct Run {
   bool q24 = false;                       // POSE4DOF unit-weight lists below the root: 24-byte entries
   size_t ent_bytes = 0;
   uint64_t chunk_bytes = 0;               // device bytes one materialized chunk may need
-  uint64_t first_cells = 65536;           // cells in the first chunk of every expansion
+  uint64_t first_cells = 262144;          // cells in the first chunk of every expansion
   uint64_t dive_cells = 16384;            // cells from which the diversified dive goes greedy
   bool root_dive = false;                 // greedy dive from the root cells first (the diversified dive subsumes it)
   int grid_env[2] = {0, 0};               // GV_GRID_COUNT / GV_GRID_COMPACT: fixed blocks per CU (experiments)
@@ -1330,7 +1330,9 @@ void epoch_begin(Run& X) {
   // first-descent beam: 65536 cells per problem keeps the planted cells of a
   // large problem in it at the coarse levels and pays for itself in bound
   // quality on small ones; problems sharing an epoch each keep that width
-  X.first_cells = 65536ull * (uint64_t)np;
+  // (262144: the hardest problems of the 256-problem pose set find their
+  // bound in the first chunk; 65536 left one solving 8x longer)
+  X.first_cells = 262144ull * (uint64_t)np;
   if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
   X.dive_cells = 16384ull * (uint64_t)np;
   if (const char* dc = std::getenv("GV_DIVE_CELLS")) X.dive_cells = std::strtoull(dc, nullptr, 10);
