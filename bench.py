@@ -45,7 +45,7 @@ WORKLOADS = {
 
 def serve_bench(args):
     """Plain binary64, one problem at a time (gv_solve) against the binary32
-    filter with continuous batching (gv_submit/gv_poll, four lanes), same 256
+    filter with continuous batching (gv_submit/gv_poll, three lanes), same 256
     problems, inputs resident in HBM; then Poisson arrivals for p50/p99
     latency, beside the plain form's FIFO latency on the same arrivals."""
     import threading

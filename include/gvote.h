@@ -167,7 +167,7 @@ gv_status gv_parametrize(gv_ctx *ctx, const gv_problem *p, double *t_out, double
 
 /* Continuous batching: enqueue a problem (columns copied or borrowed as in
  * gv_problem) and return a ticket.  The first call starts the context's
- * serving lanes (four by default: a host thread, HIP stream and allocator
+ * serving lanes (three by default: a host thread, HIP stream and allocator
  * each); a free lane takes queued problems as the memory budget allows, so
  * problems run concurrently on the device.  Results equal gv_solve's. */
 gv_status gv_submit(gv_ctx *ctx, const gv_problem *p, uint64_t *ticket);
