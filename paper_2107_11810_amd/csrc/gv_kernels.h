@@ -712,11 +712,13 @@ __global__ void k_prob_norm(const uint32_t* __restrict__ kcnt, const uint32_t* _
 __global__ void k_soff_last(uint64_t* soff, const uint32_t* sn, uint32_t nkept) {
   if (threadIdx.x == 0 && blockIdx.x == 0) soff[nkept] = nkept ? soff[nkept - 1] + sn[nkept - 1] : 0;
 }
+// out may be host-coherent memory the host reads after the stream wait
 __global__ void k_gather_u64(const uint64_t* __restrict__ a, uint64_t n, uint64_t stride, uint64_t* __restrict__ out) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t m = (n + stride - 1) / stride;
   if (i < m) out[i] = a[i * stride];
   if (i == 0) out[m] = a[n];
+  __threadfence_system();
 }
 
 // Re-cut a pending chunk [r0, r1) against the current bounds: a child is

@@ -495,10 +495,15 @@ struct Run {
 // Two host-coherent pinned words that kernels write totals to, so the host
 // reads them after a stream wait without a copy.  Null pointers (and device
 // memory plus a copy) when the allocation fails.
+// Layout: 8 words of totals, then kStageN + 1 words that the chunk planner's
+// samples are gathered into.
+constexpr uint64_t kStageN = 65536;
 void alloc_hpin(uint64_t*& h, uint64_t*& d) {
   h = d = nullptr;
   void* p = nullptr;
-  if (hipHostMalloc(&p, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return;
+  if (hipHostMalloc(&p, (8 + kStageN + 1) * sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess)
+    return;
   void* q = nullptr;
   if (hipHostGetDevicePointer(&q, p, 0) != hipSuccess) {
     (void)hipHostFree(p);
@@ -1046,14 +1051,21 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
 // memory once expanded: its lists plus the per-cell and per-child arrays.
 void plan_chunks(Run& X, Parent* pa, std::vector<std::pair<uint32_t, uint32_t>>& chunks) {
   const uint32_t nk = pa->nkept;
-  const uint64_t stride = std::max<uint64_t>(1, (nk + (1u << 20) - 1) >> 20);
+  const uint64_t stride = std::max<uint64_t>(1, ((uint64_t)nk + kStageN - 1) / kStageN);
   const uint64_t ns = (nk + stride - 1) / stride;  // samples soff[i*stride], plus soff[nk]
-  uint64_t* d = dalloc<uint64_t>(X, ns + 1);
-  k_gather_u64<<<nblk(ns + 1), 256, 0, X.st>>>(pa->soff, nk, stride, d);
   std::vector<uint64_t> s(ns + 1);
-  HIPCHK(hipMemcpyAsync(s.data(), d, (ns + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
-  host_wait(X);
-  dfree(X, d);
+  if (X.hpin) {
+    // gathered straight into host-coherent memory: no copy
+    k_gather_u64<<<nblk(ns + 1), 256, 0, X.st>>>(pa->soff, nk, stride, X.hpin_dev + 8);
+    host_wait(X);
+    std::memcpy(s.data(), X.hpin + 8, (ns + 1) * sizeof(uint64_t));
+  } else {
+    uint64_t* d = dalloc<uint64_t>(X, ns + 1);
+    k_gather_u64<<<nblk(ns + 1), 256, 0, X.st>>>(pa->soff, nk, stride, d);
+    HIPCHK(hipMemcpyAsync(s.data(), d, (ns + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, X.st));
+    host_wait(X);
+    dfree(X, d);
+  }
   auto at = [&](uint64_t i) { return i >= ns ? s[ns] : s[i]; };  // sample i -> soff[min(i*stride, nk)]
   auto rk = [&](uint64_t i) { return (uint32_t)std::min<uint64_t>(i * stride, nk); };
   const int lc = std::min(pa->level + 1, X.P0.Lstar - 1);
