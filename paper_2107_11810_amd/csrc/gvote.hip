@@ -1238,17 +1238,23 @@ bool materialize_at(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   return materialize<FAM, E, E, M>(X, pa, r0, r1, nb);
 }
 
+// Whether every kept child fits the first chunk the schedule would cut (the
+// same rule as plan_chunks, decided from the totals already on the host).
+bool one_chunk(const Run& X, const Parent* pa) {
+  const int lc = std::min(pa->level + 1, X.P0.Lstar - 1);
+  const double per_cell = 64.0 + 40.0 * (double)(1u << X.P0.lev[lc].abits);
+  const double per_ent = (double)X.ent_bytes + 8.0;
+  const uint64_t cap = X.beam ? X.first_cells : (1ull << 30);
+  return (uint64_t)pa->nkept <= cap &&
+         (double)pa->kept_entries * per_ent + (double)pa->nkept * per_cell <= (double)X.chunk_bytes;
+}
+
 template <int FAM, typename E, typename M>
 void push_children(Run& X, Parent* pa, std::vector<Task>& stack) {
   std::vector<std::pair<uint32_t, uint32_t>> chunks;
   // all kept children in one chunk when they fit (no need to sample the
   // list offsets), else the chunk schedule
-  const int lc = std::min(pa->level + 1, X.P0.Lstar - 1);
-  const double per_cell = 64.0 + 40.0 * (double)(1u << X.P0.lev[lc].abits);
-  const double per_ent = (double)X.ent_bytes + 8.0;
-  const uint64_t cap = X.beam ? X.first_cells : (1ull << 30);
-  if ((uint64_t)pa->nkept <= cap &&
-      (double)pa->kept_entries * per_ent + (double)pa->nkept * per_cell <= (double)X.chunk_bytes)
+  if (one_chunk(X, pa))
     chunks.push_back({0u, pa->nkept});
   else
     plan_chunks(X, pa, chunks);
@@ -1488,7 +1494,7 @@ void start_search(Run& X) {
       Parent* pa = expand_at<FAM, E, M>(X, b, own, dv);
       if (!pa) break;
       uint32_t r1 = pa->nkept;
-      if (!dv) {
+      if (!dv && !one_chunk(X, pa)) {
         std::vector<std::pair<uint32_t, uint32_t>> ch;
         plan_chunks(X, pa, ch);
         r1 = ch.front().second;
