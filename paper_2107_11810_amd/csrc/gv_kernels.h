@@ -724,15 +724,17 @@ __global__ void k_gather_u64(const uint64_t* __restrict__ a, uint64_t n, uint64_
 // Re-cut a pending chunk [r0, r1) against the current bounds: a child is
 // kept only if its count can still reach the best leaf of its own problem.
 // keepc / csize are chunk-local (index r - r0).
+// keep_all: no re-cut (a chunk materialized right after its parent's
+// pruning, whose bounds cannot have moved; its sizes are then known).
 __global__ void k_chunk_keep(const uint32_t* __restrict__ order, const uint32_t* __restrict__ scount,
                              const Cell* __restrict__ cells, uint32_t nch, const unsigned long long* __restrict__ best,
                              int B, uint32_t r0, uint32_t r1, const uint32_t* __restrict__ cnent,
-                             uint32_t* __restrict__ keepc, uint64_t* __restrict__ csize) {
+                             uint32_t* __restrict__ keepc, uint64_t* __restrict__ csize, int keep_all) {
   const uint32_t r = r0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= r1) return;
   const uint32_t k = order[r];
   const uint64_t bc = (uint64_t)(best[cells[k / nch].prob] >> B);
-  const uint32_t keep = (uint64_t)scount[r] >= bc ? 1u : 0u;
+  const uint32_t keep = (keep_all || (uint64_t)scount[r] >= bc) ? 1u : 0u;
   keepc[r - r0] = keep;
   csize[r - r0] = keep ? (uint64_t)cnent[k] : 0ull;
 }
@@ -832,14 +834,15 @@ __global__ void k_chunk_range(const uint32_t* __restrict__ order, uint32_t r0, u
 // One thread per item of [i0, i1); with acc, also the bits of the entries
 // the compaction reads (items with a kept child in the chunk).
 template <int NCH>
-__global__ void k_chunk_work(const Item* __restrict__ items, uint32_t i0, uint32_t i1,
+__global__ void k_chunk_work(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_p, uint32_t i0,
+                             uint32_t i1,
                              const uint64_t* __restrict__ itemoff, const uint32_t* __restrict__ rank_of, uint32_t r0,
                              uint32_t r1, const uint32_t* __restrict__ keepc, const uint64_t* __restrict__ coff,
                              CWork<NCH>* __restrict__ work, uint32_t* __restrict__ nwork, uint32_t bits_per_entry,
                              unsigned long long* __restrict__ acc) {
   const uint32_t it = i0 + blockIdx.x * blockDim.x + threadIdx.x;
   CWork<NCH> w{};
-  if (it < i1) {
+  if (it < i1 && it < *nitems_p) {
     const Item I = items[it];
     w.off = I.off;
     w.cnt = I.cnt;

@@ -425,6 +425,7 @@ struct Parent {
   bool sorted = true;  // children in descending count order
   uint64_t kept_entries = 0;  // entries of all kept children
   bool unit = true;    // every multiplicity is 1
+  bool fresh = false;  // its one chunk comes next, right after its pruning
 };
 
 struct Task {
@@ -1097,8 +1098,13 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   uint32_t* cidx = dalloc<uint32_t>(X, nr);
   uint64_t* csize = dalloc<uint64_t>(X, nr);
   uint64_t* coff = dalloc<uint64_t>(X, nr);
+  // A chunk of every kept child materialized right after its parent's
+  // pruning: no bound has moved since, so nothing is re-cut and its sizes
+  // are the parent's totals (no wait for the device).
+  const bool fresh = pa->fresh && r0 == 0 && r1 == pa->nkept;
+  pa->fresh = false;
   k_chunk_keep<<<nblk(nr), 256, 0, X.st>>>(pa->order, pa->scount, pa->cells, nch, X.dbest, P.B, r0, r1, pa->cnent,
-                                            keepc, csize);
+                                            keepc, csize, fresh ? 1 : 0);
   if (nr <= GV_SMALL_N) {
     k_chunk_small<<<1, 1024, 0, X.st>>>(keepc, csize, nr, cidx, coff, X.dtot);
   } else {
@@ -1115,7 +1121,14 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
                                       nwork, X.dtot + 2);
   }
   uint64_t tot[4];
-  read_tot(X, tot, linear ? 4 : 2);
+  if (fresh) {
+    tot[0] = pa->nkept;
+    tot[1] = pa->kept_entries;
+    tot[2] = 0;
+    tot[3] = pa->max_items;  // every item (clamped to the count on the device)
+  } else {
+    read_tot(X, tot, linear ? 4 : 2);
+  }
   bool made = false;
   X.stats.cells_pruned += nr - tot[0];
   if (tot[0] > 0) {
@@ -1136,7 +1149,8 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
       const uint32_t i0 = (uint32_t)tot[2], i1 = (uint32_t)std::max(tot[2], tot[3]);
 #define GV_WORK(N)                                                                                                \
   work = dalloc<CWork<N>>(X, std::max<uint64_t>(1, i1 - i0));                                                     \
-  k_chunk_work<N><<<nblk(i1 - i0), 256, 0, X.st>>>(pa->items, i0, i1, pa->itemoff, pa->rank_of, r0, r1, keepc, coff, \
+  k_chunk_work<N><<<nblk(i1 - i0), 256, 0, X.st>>>(pa->items, pa->nitems, i0, i1, pa->itemoff, pa->rank_of, r0, r1, \
+                                                  keepc, coff,                                                    \
                                                   (CWork<N>*)work, nwork, (uint32_t)(8 * sizeof(E)),             \
                                                   X.ctx->kernel_timing ? X.dreads : nullptr)
       switch (nch) {
@@ -1254,10 +1268,12 @@ void push_children(Run& X, Parent* pa, std::vector<Task>& stack) {
   std::vector<std::pair<uint32_t, uint32_t>> chunks;
   // all kept children in one chunk when they fit (no need to sample the
   // list offsets), else the chunk schedule
-  if (one_chunk(X, pa))
+  if (one_chunk(X, pa)) {
     chunks.push_back({0u, pa->nkept});
-  else
+    pa->fresh = true;  // (the next step materializes it)
+  } else {
     plan_chunks(X, pa, chunks);
+  }
   pa->pending = (int)chunks.size();
   for (auto it = chunks.rbegin(); it != chunks.rend(); ++it) {
     Task t{};
@@ -1417,8 +1433,8 @@ void start_search(Run& X) {
     rb.ncell = (uint32_t)rc.size();
     rb.nent = X.Ntot;
     rb.cells = dalloc<Cell>(X, rc.size());
+    // (rc stays alive and is next written by a copy later on the same stream)
     HIPCHK(hipMemcpyAsync(rb.cells, rc.data(), rc.size() * sizeof(Cell), hipMemcpyHostToDevice, X.st));
-    host_wait(X);
     rb.ents = X.root;
     if (X.group_mode >= 0) group_batch<E>(X, rb, true);
     X.root = rb.ents;
@@ -1494,10 +1510,14 @@ void start_search(Run& X) {
       Parent* pa = expand_at<FAM, E, M>(X, b, own, dv);
       if (!pa) break;
       uint32_t r1 = pa->nkept;
-      if (!dv && !one_chunk(X, pa)) {
-        std::vector<std::pair<uint32_t, uint32_t>> ch;
-        plan_chunks(X, pa, ch);
-        r1 = ch.front().second;
+      if (!dv) {
+        if (one_chunk(X, pa)) {
+          pa->fresh = true;
+        } else {
+          std::vector<std::pair<uint32_t, uint32_t>> ch;
+          plan_chunks(X, pa, ch);
+          r1 = ch.front().second;
+        }
       }
       pa->pending = 1;
       if (!materialize_at<FAM, E, M>(X, pa, 0, r1, b)) break;
