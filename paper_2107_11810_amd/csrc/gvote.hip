@@ -1357,7 +1357,7 @@ void epoch_begin(Run& X) {
   // until pruning bites): measured peaks are about twice one chunk, and a
   // fifth of the budget per chunk leaves room for four large levels
   X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.budget / 5);
-  if (const char* cb = std::getenv("GV_CHUNK_BYTES")) X.chunk_bytes = std::max<uint64_t>(1ull << 20, std::strtoull(cb, nullptr, 10));
+  if (const char* cb = std::getenv("GV_CHUNK_BYTES")) X.chunk_bytes = std::max<uint64_t>(4096, std::strtoull(cb, nullptr, 10));
   if (const char* e = std::getenv("GV_GRID_COUNT")) X.grid_env[0] = std::max(1, std::min(64, atoi(e)));
   if (const char* e = std::getenv("GV_GRID_COMPACT")) X.grid_env[1] = std::max(1, std::min(64, atoi(e)));
   const uint32_t np = (uint32_t)X.probs.size();

@@ -243,3 +243,27 @@ def test_dense_plane_grouping_parity(ctx, n, eps):
         check_same(g, r, full.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"]))
     finally:
         full.close()
+
+
+@pytest.mark.parametrize("fam", FAMS)
+def test_many_small_chunks_parity(ctx, fam):
+    """Tiny chunks (GV_CHUNK_BYTES, GV_FIRST_CELLS) split every expansion into
+    many chunks, in count order during the first descent and in parent order
+    after it: sampled chunk plans, re-cuts against the moving bound and the
+    item ranges of parent-ordered chunks all run.  Same result as the
+    oracle."""
+    import os
+    g = synth.config(fam + "_small")
+    _say("small chunks", fam)
+    old = {k: os.environ.get(k) for k in ("GV_CHUNK_BYTES", "GV_FIRST_CELLS")}
+    os.environ["GV_CHUNK_BYTES"] = "65536"
+    os.environ["GV_FIRST_CELLS"] = "64"
+    try:
+        r = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    check_same(g, r, oracle.solve(OP(g)))
