@@ -986,8 +986,10 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   dfree(X, keepf);
   dfree(X, keepscan);
   // POSE4DOF keeps count order throughout: its bound keeps improving after
-  // the first descent, and its incidence test (not the list traffic) dominates
-  pa->sorted = X.beam || dive || FAM == FAM_POSE4DOF;
+  // the first descent, and its incidence test (not the list traffic) dominates.
+  // The greedy dive keeps one child per cell and takes them all at once, so
+  // their order changes nothing there: parent order, no sort.
+  pa->sorted = !dive && (X.beam || FAM == FAM_POSE4DOF);
   pa->scount = dalloc<uint32_t>(X, nkept);
   if (!pa->sorted) {
     // after the first descent the bounds are strong: keep parent order so
