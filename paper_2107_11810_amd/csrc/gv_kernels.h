@@ -654,6 +654,35 @@ __global__ void k_pick_best(LevelC lv, int B, uint64_t idxmask, int leaf, const 
   }
 }
 
+// Greedy dive above the leaves: every cell keeps its best child, in parent
+// order, so rank r is cell r.  Writes the kept list directly: order (child
+// index), count, entries, and each child's rank (~0 for the dropped ones).
+__global__ void k_pick_kept(LevelC lv, uint32_t ncell, const uint32_t* __restrict__ ccnt,
+                            const uint32_t* __restrict__ cnent, uint32_t* __restrict__ order,
+                            uint32_t* __restrict__ scount, uint32_t* __restrict__ sn, uint32_t* __restrict__ rank_of) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const uint32_t nch = 1u << lv.abits;
+  const uint64_t o = (uint64_t)c * nch;
+  uint32_t bc = 0, bd = 0;
+  for (uint32_t ch = 0; ch < nch; ch++)
+    if (ch == 0 || ccnt[o + ch] > bc) { bc = ccnt[o + ch]; bd = ch; }
+  for (uint32_t ch = 0; ch < nch; ch++) rank_of[o + ch] = ch == bd ? c : 0xffffffffu;
+  order[c] = (uint32_t)(o + bd);
+  scount[c] = bc;
+  sn[c] = cnent[o + bd];
+}
+
+// the host's totals from a scan's last value: out[0] = n, out[1] = *sum
+// (host-coherent memory)
+__global__ void k_tot_from(uint64_t n, const uint64_t* __restrict__ sum, uint64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = n;
+    out[1] = *sum;
+    __threadfence_system();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Ordering of kept children: highest count first (radix sort on the host
 // side), so the first descent of the depth-first search follows the most

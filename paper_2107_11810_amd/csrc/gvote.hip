@@ -919,6 +919,46 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     itemcnt = itemw = nullptr;
   }
 
+  if (dive && !leaf) {
+    // greedy dive: one child per cell in parent order; the kept list is
+    // written directly (no selection scan, no sort), its entries summed by
+    // the offsets' scan
+    const uint32_t nkept = b.ncell;
+    pa->nkept = nkept;
+    pa->sorted = false;
+    pa->order = dalloc<uint32_t>(X, nkept);
+    pa->scount = dalloc<uint32_t>(X, nkept);
+    pa->rank_of = dalloc<uint32_t>(X, nk);
+    uint32_t* sn = dalloc<uint32_t>(X, nkept);
+    k_pick_kept<<<nblk(nkept), 256, 0, X.st>>>(lv, nkept, ccnt, pa->cnent, pa->order, pa->scount, sn, pa->rank_of);
+    dfree(X, ccnt);
+    pa->soff = dalloc<uint64_t>(X, nkept + 1);
+    if (nkept <= GV_SMALL_N) {
+      k_scan_small<uint32_t, uint64_t><<<1, 1024, 0, X.st>>>(sn, pa->soff, nkept, pa->soff + nkept);
+    } else {
+      excl_scan(X, sn, pa->soff, nkept);
+      k_soff_last<<<1, 64, 0, X.st>>>(pa->soff, sn, nkept);
+    }
+    k_tot_from<<<1, 64, 0, X.st>>>(nkept, pa->soff + nkept, X.dtot);
+    dfree(X, sn);
+    if (itemcnt) {  // POSE4DOF: child-major offsets for k_compact
+      pa->itemoff = dalloc<uint64_t>(X, (uint64_t)nch * pa->istride);
+      excl_scan(X, itemcnt, pa->itemoff, (uint64_t)nch * pa->istride);
+      dfree(X, itemcnt);
+    }
+    HIPCHK(hipGetLastError());
+    uint64_t kt[2];
+    read_tot(X, kt);
+    pa->kept_entries = kt[1];
+    X.stats.cells_pruned += nk - nkept;
+    if (X.trace) {
+      const uint64_t bst = d2h1(X, X.dbest);
+      std::fprintf(stderr, "gv: level %d cells %u entries %llu kept %llu best %llu (dive)%s\n", m, b.ncell,
+                   (unsigned long long)b.nent, (unsigned long long)nkept, (unsigned long long)(bst >> P.B),
+                   (b.unit && m >= X.unit_from) ? " one-word" : (m >= X.pack_from ? " packed" : ""));
+    }
+    return pa;
+  }
   uint32_t* keepf = dalloc<uint32_t>(X, nk);
   uint64_t* keptn = dalloc<uint64_t>(X, nk);
   if (dive) {
