@@ -283,6 +283,23 @@ __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Item* __rest
     for (int ch = 0; ch < NCH; ch++) { aw[ch] = 0; an[ch] = 0; }
     for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * NB) {
       E ev[NB];
+      if (k0 + 64 * NB <= cnt) {
+        // a full block (the common case): no per-entry bounds
+#pragma unroll
+        for (int j = 0; j < NB; j++) ev[j] = ents[I.off + k0 + 64 * j + lane];
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+          const LinS s = load_ent<FAM>(ev[j]);
+          bool p[NCH];
+          lin_pass<FAM, NCH>(s, lv, p);
+#pragma unroll
+          for (int ch = 0; ch < NCH; ch++) {
+            an[ch] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p[ch]));
+            if constexpr (!UNIT) aw[ch] += p[ch] ? (uint32_t)s.w : 0u;
+          }
+        }
+        continue;
+      }
 #pragma unroll
       for (int j = 0; j < NB; j++) {
         const uint32_t k = k0 + 64 * j + lane;
@@ -934,12 +951,17 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
       const uint64_t off = uniform_u64(Wp->off);
       const uint32_t cnt = uniform_u32(Wp->cnt);
       const uint32_t kmask = uniform_u32(Wp->kmask);
-      uint64_t wpos[8];
+      // each kept child's run starts at a wave-uniform address; the
+      // position inside the run (< cnt) is a scalar 32-bit count, so a
+      // store is a scalar base plus one per-lane offset
+      EO* cbase[8];
+      uint32_t cpos[8];
       bool kept[8];
 #pragma unroll
       for (int ch = 0; ch < 8; ch++) {
         kept[ch] = (kmask >> ch) & 1u;
-        wpos[ch] = kept[ch] ? uniform_u64(Wp->wpos[ch]) : 0ull;
+        cbase[ch] = out + (kept[ch] ? uniform_u64(Wp->wpos[ch]) : 0ull);
+        cpos[ch] = 0u;
       }
       constexpr int G = GV_ITEM / 64;
       for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * G) {
@@ -999,9 +1021,11 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
                 e.lo = LO[j];
                 e.hi = ((uint32_t)Fc & 0xffffu) | WHI[j];
               }
-              (out + wpos[ch])[mbcnt64(b)] = e;
+              // 32-bit byte offset (< GV_ITEM entries) from the scalar base
+              const uint32_t boff = (cpos[ch] + mbcnt64(b)) * (uint32_t)sizeof(EO);
+              *reinterpret_cast<EO*>(reinterpret_cast<char*>(cbase[ch]) + boff) = e;
             }
-            wpos[ch] += (uint64_t)__popcll(b);
+            cpos[ch] = uniform_u32(cpos[ch] + (uint32_t)__popcll(b));
           }
         }
       }
@@ -1044,6 +1068,17 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
   }
   if (!fits) atomicOr(ovf, 1);
 }
+
+// a copied word as a clang vector, for stores through a global-memory pointer
+template <typename W> struct WordVec;
+template <> struct WordVec<uint4> {
+  using T = uint32_t __attribute__((ext_vector_type(4)));
+  __device__ static T of(const uint4& v) { return T{v.x, v.y, v.z, v.w}; }
+};
+template <> struct WordVec<uint2> {
+  using T = uint32_t __attribute__((ext_vector_type(2)));
+  __device__ static T of(const uint2& v) { return T{v.x, v.y}; }
+};
 
 // Linear families re-encode on the way (the child list may use the packed
 // entry); a value that does not fit its encoding sets *ovf.
@@ -1091,9 +1126,14 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
       using Wd = std::conditional_t<sizeof(EO) % 16 == 0, uint4, uint2>;
       constexpr int NV = sizeof(EO) / sizeof(Wd);
       constexpr int G = sizeof(EO) <= 32 ? 16 : 8;
+      // each child's run continues at a wave-uniform byte address; a lane
+      // adds its 32-bit rank offset, so a store is a scalar base plus one
+      // per-lane offset
+      using gchar = __attribute__((address_space(1))) char;  // global memory
+      gchar* cb[16];
 #pragma unroll
-      for (int ch = 0; ch < 16; ch++) wpos[ch] = uniform_u64(wpos[ch]);
-      Wd* dst = reinterpret_cast<Wd*>(out);
+      for (int ch = 0; ch < 16; ch++)
+        cb[ch] = (gchar*)out + uniform_u64(wpos[ch]) * sizeof(EO);  // address-space cast
       for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * G) {
         uint32_t mk[G];
         Wd ev[G][NV];
@@ -1122,6 +1162,12 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
             }
           }
         }
+        // Every entry load of the block completes here, once.  Without this
+        // wait the loads' lane-dependent branches leave the compiler unsure
+        // which of them are outstanding, and it waits for the whole memory
+        // counter (stores included) before every store.  Encoding:
+        // vmcnt(0), expcnt and lgkmcnt left at their maxima.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
         for (int ch = 0; ch < 16; ch++) {
           if (!((kmask >> ch) & 1u)) continue;
@@ -1131,11 +1177,12 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
             const bool p = (mk[j] >> ch) & 1u;
             const uint64_t bal = __ballot(p);
             if (p) {
-              const uint64_t pos = wpos[ch] + mbcnt64(bal);
+              using gV = __attribute__((address_space(1))) typename WordVec<Wd>::T;
+              gV* d = (gV*)(cb[ch] + mbcnt64(bal) * (uint32_t)sizeof(EO));
 #pragma unroll
-              for (int q = 0; q < NV; q++) dst[pos * NV + q] = ev[j][q];
+              for (int q = 0; q < NV; q++) d[q] = WordVec<Wd>::of(ev[j][q]);
             }
-            wpos[ch] += (uint64_t)__popcll(bal);
+            cb[ch] += (uint32_t)__popcll(bal) * (uint32_t)sizeof(EO);
           }
         }
       }
