@@ -210,9 +210,17 @@ def measured_valu(workload, kernel):
         return None
     src = b"".join(open(os.path.join(ROOT, "paper_2107_11810_amd", "csrc", f), "rb").read()
                    for f in ("gv_device.h", "gv_kernels.h"))
-    if rec.get("kernel") != kernel or rec.get("sources_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("sources_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    return float(rec["lane_ops_per_test"])
+    per_kernel_ops = rec.get("kernels", {rec.get("kernel"): rec.get("lane_ops_per_test")})
+    v = per_kernel_ops.get(kernel)
+    return float(v) if v is not None else None
+
+
+def valu_frac(opt, tests, ms):
+    """Fraction of the non-packed VALU peak that opt lane-operations per test
+    over the given tests take in ms of kernel time."""
+    return round(opt * tests / (ms * 1e-3) / VALU_LANE_OPS, 4) if ms > 0 else None
 
 
 def cpu_baseline(g, budget_tests):
@@ -297,6 +305,11 @@ def main():
             # both big kernels: the incidence test (count pass) and compaction
             "kernels": [per_kernel(W["kernel"], t_ms, t_b, t_n, len(results)),
                         per_kernel(W["compact"], c_ms, c_b, c_n, len(results))]}
+    # measured vector-ALU issue of each kernel beside its HBM figure
+    for k, ms in zip(roof["kernels"], (t_ms, c_ms)):
+        opt_k = measured_valu(args.workload, k["kernel"])
+        if opt_k is not None:
+            k["valu_frac"] = valu_frac(opt_k, tests, ms)
     if W["bound"] == "alu" and kname == W["kernel"]:
         # the incidence kernel of this family is bound by vector ALU work:
         # lane-operations per test (counted once with rocprofv3, see

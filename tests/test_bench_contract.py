@@ -31,3 +31,10 @@ def test_counter_records_are_tied_to_the_kernel_sources():
     assert bench.measured_traffic("plane3d_1m", "no_such_kernel") is None
     assert bench.measured_valu("pose4dof_1m", "no_such_kernel") is None
     assert bench.measured_traffic("no_such_workload", "k_compact_lin<PLANE3D>") is None
+
+
+def test_valu_fraction():
+    import bench
+    # 39.3216e12 lane-ops/s peak: 10 lane-ops per test over 3.93216e12 tests in 1 s is the peak
+    assert abs(bench.valu_frac(10.0, 3.93216e12, 1000.0) - 1.0) < 1e-9
+    assert bench.valu_frac(10.0, 1e9, 0.0) is None
