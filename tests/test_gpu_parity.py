@@ -267,3 +267,23 @@ def test_many_small_chunks_parity(ctx, fam):
             else:
                 os.environ[k] = v
     check_same(g, r, oracle.solve(OP(g)))
+
+
+@pytest.mark.parametrize("fam,n", [("plane3d", 511), ("plane3d", 512), ("plane3d", 513), ("plane3d", 1023),
+                                   ("plane3d", 1024), ("plane3d", 1025), ("line2d", 1024), ("line2d", 2049),
+                                   ("ray3d", 256), ("ray3d", 257)])
+def test_block_boundary_parity(ctx, fam, n):
+    """Root lists just under, at and just over a multiple of the count pass's
+    block (1024 entries of 4 or 8 bytes, 512 of 16, 256 of 24): full blocks
+    take the branch without per-entry bounds, the rest the ragged one."""
+    k = max(8, n // 20)
+    if fam == "plane3d":
+        g = synth.plane3d(seed=n, n=n, n_in=k, eps=(0.02, 0.02, 0.02))
+    elif fam == "line2d":
+        g = synth.line2d(seed=n, n=n, n_in=k, eps=(0.01, 0.01))
+    else:
+        g = synth.ray3d(seed=n, n=n, n_in=k, eps=2.0)
+    _say("block boundary", fam, n)
+    ro = oracle.solve(OP(g))
+    rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    check_same(g, rg, ro)
