@@ -27,8 +27,8 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (binary64, no contraction, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-pthread", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm", "-lpthread"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -47,6 +47,7 @@ class _Problem(ctypes.Structure):
         ("no_group", ctypes.c_int),
         ("no_dive", ctypes.c_int),
         ("test_budget", ctypes.c_uint64),
+        ("threads", ctypes.c_int),
     ]
 
 
@@ -86,6 +87,9 @@ def lib():
         L.or_leaf_count.argtypes = [P(_Problem), ctypes.c_uint64, P(ctypes.c_uint64), P(ctypes.c_int64),
                                     ctypes.c_int64]
         L.or_all_leaf_counts.argtypes = [P(_Problem), P(ctypes.c_uint32), ctypes.c_uint64]
+        L.or_level_counts.argtypes = [P(_Problem), ctypes.c_int, P(ctypes.c_uint32), ctypes.c_uint64]
+        L.or_leaf_indicator.argtypes = [P(_Problem), ctypes.c_int64, P(ctypes.c_uint8), ctypes.c_uint64]
+        L.or_cell_masks.argtypes = [P(_Problem), ctypes.c_int, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_uint32)]
         L.or_meets.argtypes = [P(_Problem), P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int32,
                                ctypes.c_int, ctypes.c_int32, P(ctypes.c_int32)]
         L.or_canon_at.argtypes = [P(_Problem), P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int32,
@@ -109,7 +113,7 @@ class Problem:
     """A voting problem: observation columns (SoA), domain box, per-axis eps."""
 
     def __init__(self, family, cols, lo, hi, eps, canon_c=0.0, no_prune=False, no_group=False,
-                 no_dive=False, test_budget=0):
+                 no_dive=False, test_budget=0, threads=1):
         self.family = FAMILIES[family] if isinstance(family, str) else int(family)
         self.cols = [np.ascontiguousarray(np.asarray(c, dtype=np.float64)) for c in cols]
         if len(self.cols) != NCOLS[self.family]:
@@ -121,6 +125,7 @@ class Problem:
         self.canon_c = float(canon_c)
         self.no_prune, self.no_group, self.no_dive = no_prune, no_group, no_dive
         self.test_budget = int(test_budget)
+        self.threads = int(threads)
 
     def _c(self):
         p = _Problem()
@@ -133,6 +138,7 @@ class Problem:
         p.canon_c = self.canon_c
         p.no_prune, p.no_group, p.no_dive = int(self.no_prune), int(self.no_group), int(self.no_dive)
         p.test_budget = self.test_budget
+        p.threads = self.threads
         return p
 
 
@@ -194,6 +200,45 @@ def all_leaf_counts(prob: Problem) -> np.ndarray:
     if st != 0:
         raise OracleError(st, "all_leaf_counts")
     return out
+
+
+def level_counts(prob: Problem, level: int) -> np.ndarray:
+    """Chain counts of every cell of one level (index = [sector] || digits)."""
+    k = constants(prob)
+    bits = (2 if prob.family == 4 else 0) + sum(
+        sum(1 for j in range(4) if m < k["L"][j]) for m in range(level))
+    out = np.zeros(1 << bits, dtype=np.uint32)
+    p = prob._c()
+    st = lib().or_level_counts(ctypes.byref(p), int(level), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                               out.size)
+    if st != 0:
+        raise OracleError(st, "level_counts")
+    return out
+
+
+def leaf_indicator(prob: Problem, i: int) -> np.ndarray:
+    """1 at every leaf where surface i is counted (its chain passes)."""
+    k = constants(prob)
+    out = np.zeros(1 << int(k["B"]), dtype=np.uint8)
+    p = prob._c()
+    st = lib().or_leaf_indicator(ctypes.byref(p), int(i), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                 out.size)
+    if st != 0:
+        raise OracleError(st, "leaf_indicator")
+    return out
+
+
+def cell_masks(prob: Problem, level: int, sector: int, coords) -> np.ndarray:
+    """Pass masks (bit = child digit) of every surface, canonized along the
+    path to the cell, against the children of that cell."""
+    cc = np.ascontiguousarray(np.asarray(list(coords) + [0] * (4 - len(coords)), dtype=np.int32))
+    out = np.zeros(max(1, prob.n), dtype=np.uint32)
+    p = prob._c()
+    st = lib().or_cell_masks(ctypes.byref(p), int(level), int(sector), cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    if st != 0:
+        raise OracleError(st, "cell_masks")
+    return out[: prob.n]
 
 
 def meets(prob: Problem, t, f, tag, level, sector, coords) -> bool:

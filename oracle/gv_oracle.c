@@ -29,6 +29,7 @@
 #include "gv_oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
@@ -57,9 +58,27 @@ typedef struct {
   double sW, sW3, sXi, sEta, Rg2, padz, padk, epsk, ce;
   /* search state */
   uint64_t best;
+  uint64_t *shared_best; /* thread pool: one best key for every worker */
   uint64_t tests, expanded, pruned, merged, budget;
-  int over;
 } ctx;
+
+/* Best key so far.  With a thread pool every worker reads and raises one
+ * shared value; it only tightens pruning, never changes the result, because
+ * a leaf's key is unique (count, then lowest index). */
+static uint64_t best_get(const ctx *C) {
+  return C->shared_best ? __atomic_load_n(C->shared_best, __ATOMIC_RELAXED) : C->best;
+}
+
+static void best_offer(ctx *C, uint64_t key) {
+  if (!C->shared_best) {
+    if (key > C->best) C->best = key;
+    return;
+  }
+  uint64_t cur = __atomic_load_n(C->shared_best, __ATOMIC_RELAXED);
+  while (key > cur &&
+         !__atomic_compare_exchange_n(C->shared_best, &cur, key, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+  }
+}
 
 const char *or_status_str(int st) {
   switch (st) {
@@ -489,9 +508,9 @@ static int expand(ctx *C, int m, int sector, const int32_t *cc, uint64_t prefix,
     uint64_t cnt = filter(C, S, n, m, sector, ch, buf, &nc);
     uint64_t cpre = (prefix << a) | (uint64_t)digit;
     uint64_t key = key_of(C, cnt, cpre << C->rem[m + 1]);
-    if (!C->prob->no_prune && key <= C->best) { C->pruned++; continue; }
+    if (!C->prob->no_prune && key <= best_get(C)) { C->pruned++; continue; }
     if (m + 1 == C->Lstar) {
-      if (key > C->best) C->best = key;
+      best_offer(C, key);
       continue;
     }
     for (int64_t i = 0; i < nc; i++) canon(C, &buf[i], m + 1, ch);
@@ -535,8 +554,7 @@ static int dive(ctx *C, int sector, const rec *S0, int64_t n0) {
     rec *t = cur; cur = nxt; nxt = t;
     n = nc;
     if (m + 1 == C->Lstar) {
-      uint64_t key = key_of(C, bestc, prefix);
-      if (key > C->best) C->best = key;
+      best_offer(C, key_of(C, bestc, prefix));
     }
   }
   free(cur);
@@ -555,6 +573,22 @@ static int leaf_path(const ctx *C, uint64_t idx, int *sector, int32_t path[][MAX
     child_coords(C, m, path[m], digit, path[m + 1]);
   }
   return OR_OK;
+}
+
+/* Path of cell coordinates from the root to the level-`level` cell whose
+ * index is [sector] || the child digits of levels 0..level-1. */
+static void cell_path(const ctx *C, uint64_t idx, int level, int *sector, int32_t path[][MAXD]) {
+  int bits = 0;
+  for (int m = 0; m < level; m++) bits += C->abits[m];
+  *sector = C->fam == OR_POSE4DOF ? (int)(idx >> bits) : 0;
+  for (int j = 0; j < MAXD; j++) path[0][j] = 0;
+  int rem = bits;
+  for (int m = 0; m < level; m++) {
+    int a = C->abits[m];
+    rem -= a;
+    int digit = (int)((idx >> rem) & ((1ULL << a) - 1ULL));
+    child_coords(C, m, path[m], digit, path[m + 1]);
+  }
 }
 
 /* per-surface chain along a fixed path (member tracking by replay) */
@@ -644,6 +678,116 @@ static int replay_inliers(const ctx *C, uint64_t idx, uint64_t *count, int64_t *
   return OR_OK;
 }
 
+/* ------------------------------------------------------------------ */
+/* Optional thread pool: disjoint subtrees of one level, handed out in   */
+/* index order; each worker derives its subtree's list from the root by  */
+/* the same filter / canonize / group steps and searches it depth-first. */
+/* Workers share only the best key, so the result equals the serial one. */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  ctx *base;
+  const rec *S;
+  int64_t n;
+  int level;          /* subtrees are the cells of this level */
+  uint64_t ntask;     /* nsec * 2^(digit bits of levels 0..level-1) */
+  uint64_t *next;     /* shared task counter */
+  int *status;        /* first error of any worker */
+  ctx local;          /* this worker's counters */
+} worker;
+
+static int subtree(ctx *C, const rec *S, int64_t n, int level, uint64_t task) {
+  int sector;
+  int32_t path[MAXL + 1][MAXD];
+  cell_path(C, task, level, &sector, path);
+  rec *cur = (rec *)malloc(sizeof(rec) * (size_t)(n > 0 ? n : 1));
+  rec *nxt = (rec *)malloc(sizeof(rec) * (size_t)(n > 0 ? n : 1));
+  if (!cur || !nxt) { free(cur); free(nxt); return OR_ENOMEM; }
+  memcpy(cur, S, sizeof(rec) * (size_t)n);
+  int64_t nc = n;
+  uint64_t prefix = (uint64_t)sector;
+  int st = OR_OK;
+  for (int m = 0; m < level; m++) {
+    int a = C->abits[m];
+    int digit = (int)((task >> (C->rem[m + 1] - C->rem[level])) & ((1ULL << a) - 1ULL));
+    int64_t k;
+    uint64_t cnt = filter(C, cur, nc, m, sector, path[m + 1], nxt, &k);
+    prefix = (prefix << a) | (uint64_t)digit;
+    uint64_t key = key_of(C, cnt, prefix << C->rem[m + 1]);
+    if (!C->prob->no_prune && key <= best_get(C)) { C->pruned++; goto out; }
+    for (int64_t i = 0; i < k; i++) canon(C, &nxt[i], m + 1, path[m + 1]);
+    k = group(C, nxt, k);
+    rec *t = cur; cur = nxt; nxt = t;
+    nc = k;
+  }
+  st = expand(C, level, sector, path[level], prefix, cur, nc);
+out:
+  free(cur);
+  free(nxt);
+  return st;
+}
+
+static void *worker_main(void *arg) {
+  worker *W = (worker *)arg;
+  for (;;) {
+    if (__atomic_load_n(W->status, __ATOMIC_RELAXED)) break;
+    uint64_t t = __atomic_fetch_add(W->next, 1, __ATOMIC_RELAXED);
+    if (t >= W->ntask) break;
+    int st = subtree(&W->local, W->S, W->n, W->level, t);
+    if (st) {
+      int zero = 0;
+      __atomic_compare_exchange_n(W->status, &zero, st, 0, __ATOMIC_RELAXED, __ATOMIC_RELAXED);
+      break;
+    }
+  }
+  return NULL;
+}
+
+static int search_parallel(ctx *C, const rec *S, int64_t n, int nthreads) {
+  int nsec = C->fam == OR_POSE4DOF ? 4 : 1;
+  /* subtrees: the first level with at least 64 cells per worker (or the
+   * last level above the leaves) */
+  int level = 0;
+  uint64_t cells = (uint64_t)nsec;
+  while (level < C->Lstar - 1 && cells < 64ULL * (uint64_t)nthreads) cells <<= C->abits[level++];
+  if (level == 0) {
+    for (int s = 0; s < nsec; s++) {
+      int32_t zero[MAXD] = {0, 0, 0, 0};
+      int st = expand(C, 0, s, zero, (uint64_t)s, S, n);
+      if (st) return st;
+    }
+    return OR_OK;
+  }
+  uint64_t shared = C->best, next = 0;
+  int status = OR_OK;
+  worker *W = (worker *)calloc((size_t)nthreads, sizeof(worker));
+  pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+  if (!W || !th) { free(W); free(th); return OR_ENOMEM; }
+  uint64_t budget = C->budget ? (C->budget + (uint64_t)nthreads - 1) / (uint64_t)nthreads : 0;
+  int started = 0;
+  for (int i = 0; i < nthreads; i++) {
+    W[i].base = C; W[i].S = S; W[i].n = n; W[i].level = level; W[i].ntask = cells;
+    W[i].next = &next; W[i].status = &status;
+    W[i].local = *C;
+    W[i].local.shared_best = &shared;
+    W[i].local.tests = W[i].local.expanded = W[i].local.pruned = W[i].local.merged = 0;
+    W[i].local.budget = budget;
+    if (pthread_create(&th[i], NULL, worker_main, &W[i]) != 0) break;
+    started++;
+  }
+  if (started == 0) worker_main(&W[0]);
+  for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
+  for (int i = 0; i < (started ? started : 1); i++) {
+    C->tests += W[i].local.tests;
+    C->expanded += W[i].local.expanded;
+    C->pruned += W[i].local.pruned;
+    C->merged += W[i].local.merged;
+  }
+  C->best = shared;
+  free(W);
+  free(th);
+  return status;
+}
+
 int or_solve(const or_problem *p, or_result *res, int64_t *inliers, int64_t cap) {
   ctx C;
   memset(res, 0, sizeof(*res));
@@ -660,8 +804,12 @@ int or_solve(const or_problem *p, or_result *res, int64_t *inliers, int64_t cap)
   C.best = 0;
   if (!p->no_dive)
     for (int s = 0; s < nsec && !st; s++) st = dive(&C, s, S, n);
-  int32_t zero[MAXD] = {0, 0, 0, 0};
-  for (int s = 0; s < nsec && !st; s++) st = expand(&C, 0, s, zero, (uint64_t)s, S, n);
+  if (!st && p->threads > 1) {
+    st = search_parallel(&C, S, n, p->threads);
+  } else {
+    int32_t zero[MAXD] = {0, 0, 0, 0};
+    for (int s = 0; s < nsec && !st; s++) st = expand(&C, 0, s, zero, (uint64_t)s, S, n);
+  }
   free(S);
   res->tests = C.tests;
   res->cells_expanded = C.expanded;
@@ -783,6 +931,99 @@ int or_all_leaf_counts(const or_problem *p, uint32_t *out, uint64_t out_len) {
     out[idx] = k;
   }
   free(S);
+  return OR_OK;
+}
+
+/* chain of one surface down a path, levels 0..level-1 */
+static int chain_upto(const ctx *C, rec r, int sector, int32_t path[][MAXD], int level) {
+  canon(C, &r, 0, path[0]);
+  for (int m = 0; m < level; m++) {
+    if (!meets(C, &r, m, sector, path[m + 1])) return 0;
+    if (m + 1 < C->Lstar) canon(C, &r, m + 1, path[m + 1]);
+  }
+  return 1;
+}
+
+static int small_tree(ctx *C, const or_problem *p) {
+  int st = ctx_init(C, p);
+  if (st) return st;
+  if (C->B > 24) return OR_EINVAL;
+  if (C->fam == OR_POSE4DOF) return pose_lattice(C);
+  return OR_OK;
+}
+
+int or_level_counts(const or_problem *p, int level, uint32_t *out, uint64_t out_len) {
+  ctx C;
+  int st = small_tree(&C, p);
+  if (st) return st;
+  if (level < 0 || level > C.Lstar) return OR_EINVAL;
+  int bits = C.fam == OR_POSE4DOF ? 2 : 0;
+  for (int m = 0; m < level; m++) bits += C.abits[m];
+  if (out_len < (1ULL << bits)) return OR_EINVAL;
+  rec *S = (rec *)malloc(sizeof(rec) * (size_t)(p->n > 0 ? p->n : 1));
+  if (!S) return OR_ENOMEM;
+  for (int64_t i = 0; i < p->n; i++) {
+    st = front(&C, i, &S[i]);
+    if (st) { free(S); return st; }
+  }
+  for (uint64_t idx = 0; idx < (1ULL << bits); idx++) {
+    int sector;
+    int32_t path[MAXL + 1][MAXD];
+    cell_path(&C, idx, level, &sector, path);
+    uint32_t k = 0;
+    for (int64_t i = 0; i < p->n; i++) k += (uint32_t)chain_upto(&C, S[i], sector, path, level);
+    out[idx] = k;
+  }
+  free(S);
+  return OR_OK;
+}
+
+int or_leaf_indicator(const or_problem *p, int64_t i, uint8_t *out, uint64_t out_len) {
+  ctx C;
+  int st = small_tree(&C, p);
+  if (st) return st;
+  if (i < 0 || i >= p->n || out_len < (1ULL << C.B)) return OR_EINVAL;
+  rec r;
+  st = front(&C, i, &r);
+  if (st) return st;
+  for (uint64_t idx = 0; idx < (1ULL << C.B); idx++) {
+    int sector;
+    int32_t path[MAXL + 1][MAXD];
+    leaf_path(&C, idx, &sector, path);
+    out[idx] = (uint8_t)chain_passes(&C, r, sector, path);
+  }
+  return OR_OK;
+}
+
+int or_cell_masks(const or_problem *p, int level, int32_t sector, const int32_t *coords, uint32_t *masks) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (level < 0 || level >= C.Lstar) return OR_EINVAL;
+  if (C.fam == OR_POSE4DOF) {
+    st = pose_lattice(&C);
+    if (st) return st;
+  }
+  /* the path of cells from the root to the given one */
+  int32_t path[MAXL + 1][MAXD];
+  for (int m = 0; m <= level; m++)
+    for (int j = 0; j < MAXD; j++) {
+      int bits = j < C.d ? imin(level, C.L[j]) : 0, mb = j < C.d ? imin(m, C.L[j]) : 0;
+      path[m][j] = j < C.d ? (coords[j] >> (bits - mb)) : 0;
+    }
+  for (int64_t i = 0; i < p->n; i++) {
+    rec r;
+    st = front(&C, i, &r);
+    if (st) return st;
+    for (int m = 0; m <= level; m++) canon(&C, &r, m, path[m]);
+    uint32_t mask = 0;
+    for (int digit = 0; digit < (1 << C.abits[level]); digit++) {
+      int32_t ch[MAXD];
+      child_coords(&C, level, path[level], digit, ch);
+      if (meets(&C, &r, level, sector, ch)) mask |= 1u << digit;
+    }
+    masks[i] = mask;
+  }
   return OR_OK;
 }
 

@@ -42,6 +42,8 @@ typedef struct {
   int no_group;          /* 1: never merge equal canonical surfaces */
   int no_dive;           /* 1: no greedy dive for the starting lower bound */
   uint64_t test_budget;  /* 0: unlimited; else stop with OR_EBUDGET */
+  int threads;           /* > 1: search disjoint subtrees on that many
+                            threads sharing the best key (same result) */
 } or_problem;
 
 typedef struct {
@@ -76,6 +78,20 @@ int or_leaf_count(const or_problem *p, uint64_t leaf_index, uint64_t *count,
 
 /* Chain counts of every leaf (tiny problems only): out has 2^B entries. */
 int or_all_leaf_counts(const or_problem *p, uint32_t *out, uint64_t out_len);
+
+/* Chain counts of every cell of one level (tiny problems only): out has
+ * 2^(bits) entries, a cell's index being [sector] || its child digits of
+ * levels 0..level-1; level L* gives the leaf counts. */
+int or_level_counts(const or_problem *p, int level, uint32_t *out, uint64_t out_len);
+
+/* Whether surface i's chain reaches each leaf (tiny problems only): out has
+ * 2^B bytes, 1 where the surface is counted. */
+int or_leaf_indicator(const or_problem *p, int64_t i, uint8_t *out, uint64_t out_len);
+
+/* Every surface's canonical form at one cell (root canonization, then the
+ * canonization at each cell of the path to it) tested against each child of
+ * that cell: masks[i] bit d = passes child digit d. */
+int or_cell_masks(const or_problem *p, int level, int32_t sector, const int32_t *coords, uint32_t *masks);
 
 /* One canonized-surface/cell test, for unit pins.  level: cell level of the
  * surface's canonization (the tested cell is at level+1); coords: tested cell

@@ -159,7 +159,7 @@ def bearing_to_xi_eta(d, yaw):
 
 
 def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=0.5,
-             eps_deg=0.5, rho_max=None):
+             eps_deg=0.5, rho_max=None, height=None):
     """2D-3D matches (w, xi, eta) for a camera at c* with yaw theta*: inliers
     are points seen at lateral tangent xi0 and elevation tangent eta0 in
     [-1, 1], horizontal range U(1, rho_max), bearing perturbed by noise_deg;
@@ -167,7 +167,9 @@ def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=
     Axes (x, y, z, yaw)."""
     rng = _rng(seed)
     rho_max = size if rho_max is None else rho_max
-    c = rng.uniform(0.0, size, size=3)
+    height = size if height is None else height
+    top = np.array([size, size, height])
+    c = rng.uniform(0.0, top, size=3)
     yaw = rng.uniform(0.0, 2 * math.pi)
     ws, xis, etas = [], [], []
     got = 0
@@ -176,7 +178,7 @@ def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=
         if tried > 40 * n_in + 4000 and got < 0.01 * tried:
             # the camera sees (almost) none of the box from this pose, e.g. on
             # a wall facing out: draw another pose
-            c = rng.uniform(0.0, size, size=3)
+            c = rng.uniform(0.0, top, size=3)
             yaw = rng.uniform(0.0, 2 * math.pi)
             ws, xis, etas = [], [], []
             got = tried = 0
@@ -190,7 +192,7 @@ def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=
         nrm = np.sqrt(1.0 + xi0 * xi0)
         d = np.stack([rho * hx / nrm, rho * hy / nrm, rho * eta0], axis=1)
         w = c[None, :] + d
-        ok = np.all((w >= 0.0) & (w <= size), axis=1)
+        ok = np.all((w >= 0.0) & (w <= top[None, :]), axis=1)
         w, d = w[ok], d[ok]
         if w.shape[0] == 0:
             continue
@@ -204,7 +206,7 @@ def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=
     w_in = np.concatenate(ws)[:n_in]
     xi_in = np.concatenate(xis)[:n_in]
     eta_in = np.concatenate(etas)[:n_in]
-    w_out = rng.uniform(0.0, size, size=(n - n_in, 3))
+    w_out = rng.uniform(0.0, top, size=(n - n_in, 3))
     xi_out = rng.uniform(-1.0, 1.0, size=n - n_in)
     eta_out = rng.uniform(-1.0, 1.0, size=n - n_in)
     W = np.concatenate([w_in, w_out])
@@ -213,7 +215,7 @@ def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=
     is_in[:n_in] = True
     cols, planted = _shuffle(rng, cols, is_in)
     eps_k = math.radians(eps_deg)
-    return _problem("pose4dof", cols, (0.0, 0.0, 0.0, 0.0), (size, size, size, 2 * math.pi),
+    return _problem("pose4dof", cols, (0.0, 0.0, 0.0, 0.0), (size, size, height, 2 * math.pi),
                     (eps_m, eps_m, eps_m, eps_k), truth=(c[0], c[1], c[2], yaw), planted=planted)
 
 
@@ -242,6 +244,12 @@ def config(name: str, **kw):
     if name == "pose4dof_tiny":
         return pose4dof(seed=kw.get("seed", 4), n=kw.get("n", 48), n_in=kw.get("n_in", 12), noise_deg=0.2,
                         eps_m=25.0, eps_deg=11.5, rho_max=60.0)
+    if name == "pose4dof_tiny_flat":  # z extent smaller than the xy extent
+        return pose4dof(seed=kw.get("seed", 5), n=kw.get("n", 48), n_in=kw.get("n_in", 12), noise_deg=0.2,
+                        eps_m=25.0, eps_deg=11.5, rho_max=60.0, height=100.0)
+    if name == "pose4dof_small_flat":
+        return pose4dof(seed=kw.get("seed", 18), n=kw.get("n", 3000), n_in=kw.get("n_in", 300), noise_deg=0.2,
+                        eps_m=4.0, eps_deg=2.0, rho_max=80.0, height=60.0)
     if name == "line2d_small":
         return line2d(seed=kw.get("seed", 11), n=kw.get("n", 2000), n_in=kw.get("n_in", 200), sigma=0.003,
                       eps=(0.01, 0.01))

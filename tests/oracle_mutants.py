@@ -1,0 +1,94 @@
+"""Mutation check of the oracle pins (run by hand, not collected by pytest).
+
+Each entry plants one plausible mistake in a scratch copy of the oracle's C
+source (a dropped or wrong term, a wrong sign, index or constant) and runs
+the CPU pins against it; every mutant must make at least one pin fail.
+
+    python tests/oracle_mutants.py            # all mutants
+    python tests/oracle_mutants.py sf_x4      # one
+"""
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_bounds.py"]
+
+# (name, text in gv_oracle.c, replacement)
+MUTANTS = [
+    ("kappa_always_true", "if (rmin2 < C->Rg2) return 1; /* apex guard", "return 1; /* apex guard"),
+    ("leaf_point_L2", "ldexp(1.0, -(C->L[j] + 1));\n    pt[j]", "ldexp(1.0, -(C->L[j] + 2));\n    pt[j]"),
+    ("yaw_minus", "(M_PI / 2.0) + atan(pt[3])", "(M_PI / 2.0) - atan(pt[3])"),
+    ("sf_x4", "C->sf[q] = p2floor(ep / (double)(C->ell + 1));",
+     "C->sf[q] = 4.0 * p2floor(ep / (double)(C->ell + 1));"),
+    ("pad_m3", "(double)((m + 1) * (C->ell + 1))", "(double)((m + 3) * (C->ell + 1))"),
+    ("extra_level", "while (ldexp(C->E[j], -L) > ej) {", "while (ldexp(C->E[j], -L) >= 0.5 * ej) {"),
+    ("sXi_x64", "C->sXi = p2floor(ek / (l1 * Bk));", "C->sXi = 64.0 * p2floor(ek / (l1 * Bk));"),
+    ("padz_3eps", "C->padz = ceil((C->epsn[2] + ez * 0.5)", "C->padz = ceil((3.0 * C->epsn[2] + ez * 0.5)"),
+    ("zhi_rmax", "int zhi_ok = (Thi >= 0.0) && (a2 * rmin2 <= Thi * Thi);",
+     "int zhi_ok = (Thi >= 0.0) && (a2 * rmax2 <= Thi * Thi);"),
+    ("zlo_rmin", "int zlo_ok = (Tlo <= 0.0) || (a2 * rmax2 >= Tlo * Tlo);",
+     "int zlo_ok = (Tlo <= 0.0) || (a2 * rmin2 >= Tlo * Tlo);"),
+    ("arc_swap", "if (cross2(elx, ely, bx, by) >= 0.0 && cross2(bx, by, ehx, ehy) >= 0.0) return 1;",
+     "if (cross2(elx, ely, bx, by) >= 0.0 && cross2(ehx, ehy, bx, by) >= 0.0) return 1;"),
+    ("sector3", "default: x0 = -Bhi; x1 = -Blo; y0 = Alo; y1 = Ahi; break;",
+     "default: x0 = -Bhi; x1 = -Blo; y0 = -Ahi; y1 = -Alo; break;"),
+    ("canon_step4", "for (int k = 0; k < nP; k++) fn = fn - tn[k] * u[P[k]];",
+     "for (int k = 0; k < nP; k++) fn = fn + tn[k] * u[P[k]];"),
+    ("canon_floor", "double fl = nearbyint(floc / sf) * sf;", "double fl = floor(floc / sf) * sf;"),
+    ("digit_lsb", "int b = (digit >> (a - 1 - k)) & 1;", "int b = (digit >> k) & 1;"),
+    ("tie_high", "return (count << C->B) | (mask - idx);", "return (count << C->B) | idx;"),
+    ("group_noweight", "S[k].w += S[i].w;", "S[k].w += 0;"),
+    ("pad_next", "if (gmax < clo - C->pad[m][q]) return 0;",
+     "if (gmax < clo - C->pad[m + 1 < C->Lstar ? m + 1 : m][q]) return 0;"),
+    ("plane_sign", "r->p[1] = -((y * C->E[1]) * C->inv[2]);", "r->p[1] = ((y * C->E[1]) * C->inv[2]);"),
+    ("line_front", "r->p[4] = ((y - x * C->lo[0]) - C->lo[1]) * C->inv[1];",
+     "r->p[4] = ((y + x * C->lo[0]) - C->lo[1]) * C->inv[1];"),
+    ("ray_minaxis", "if (fabs(u[k]) > fabs(u[pi])) pi = k;", "if (fabs(u[k]) < fabs(u[pi])) pi = k;"),
+    ("ray_front", "r->p[4 + qi] = ((w[q] - C->lo[q]) + s * (C->lo[pi] - w[pi])) * C->inv[q];",
+     "r->p[4 + qi] = ((w[q] - C->lo[q]) + s * (C->lo[pi] + w[pi])) * C->inv[q];"),
+    ("pose_eta", "r->p[4] = p->col[4][i] * C->ce;", "r->p[4] = p->col[4][i];"),
+    ("sEta_x64", "C->sEta = p2floor(ez / (l1 * Rb));", "C->sEta = 64.0 * p2floor(ez / (l1 * Rb));"),
+    ("sW_x64", "C->sW = p2floor(wz < wk ? wz : wk);", "C->sW = 64.0 * p2floor(wz < wk ? wz : wk);"),
+    ("Rg_x4", "double Rg = ldexp(1.0, -Lxy); /* apex guard", "double Rg = ldexp(4.0, -Lxy); /* apex guard"),
+    ("guard_rmax", "if (rmin2 < C->Rg2) return 1;", "if (rmax2 < C->Rg2) return 1;"),
+    ("padk_3eps", "C->padk = ceil((C->epsk + ek * 0.5)", "C->padk = ceil((3.0 * C->epsk + ek * 0.5)"),
+    ("inl_last", "if (inl && k < cap) inl[k] = i;", "if (inl && k < cap) inl[k] = i + (i == C->prob->n - 1);"),
+]
+
+
+def run(name, old, new):
+    with tempfile.TemporaryDirectory(prefix=f"mut_{name}_") as d:
+        for sub in ("oracle", "tests", "paper_2107_11810_amd"):
+            shutil.copytree(os.path.join(ROOT, sub), os.path.join(d, sub),
+                            ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+        shutil.copy(os.path.join(ROOT, "pytest.ini"), d)
+        src_path = os.path.join(d, "oracle", "gv_oracle.c")
+        src = open(src_path).read()
+        if src.count(old) != 1:
+            return None, f"pattern found {src.count(old)} times"
+        open(src_path, "w").write(src.replace(old, new))
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"]
+                           + PINS, cwd=d, capture_output=True, text=True)
+        tail = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else r.stderr[-200:]
+        return r.returncode != 0, tail
+
+
+def main():
+    only = set(sys.argv[1:])
+    survived = []
+    for name, old, new in MUTANTS:
+        if only and name not in only:
+            continue
+        killed, tail = run(name, old, new)
+        print(f"{name:20s} {'killed' if killed else 'SURVIVED' if killed is False else 'NOT APPLIED'}  {tail}",
+              flush=True)
+        if not killed:
+            survived.append(name)
+    sys.exit(1 if survived else 0)
+
+
+if __name__ == "__main__":
+    main()

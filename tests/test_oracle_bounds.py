@@ -1,0 +1,597 @@
+"""Pins of the oracle's lattice, pads, leaves, returned point and certified
+bounds against what the paper and its readings fix, computed here from the
+problem's eps, canon constant c and number of parameters l alone (never from
+the oracle's own constants):
+
+  * leaf levels: the smallest L with E 2^-L <= eps (Alg. 2 stops when the
+    cell diameter is at most eps, read per axis), and the levels of the five
+    benchmark workloads;
+  * steps: s_f = largest power of two <= eps'/(l+1), eps' = eps/(c (L*+1))
+    (the canonization steps of Sec. 3.2.1 with eps' = eps/(c log 1/eps), the
+    logarithm read as the number of levels); the deviation a canonization
+    may cause inside its cell is at most (l+1) s_f / 2 <= eps'/2;
+  * pads: a canonical surface of level m is tested against a child with
+    pad(m) = eps + E(m) rounded up to the lattice, E(m) = (m+1)(l+1)s_f/2;
+    the predicate switches exactly there;
+  * (LOW) every original surface within eps of a leaf, evaluated directly in
+    binary64 from its observation, is counted at that leaf;
+  * (UP) every surface counted at a leaf is within eps + 2E(L*-1) + s_f of
+    it (linear families), within the pose pads plus the root quantization
+    (4-DoF pose; the kappa axis waived within the apex guard);
+  * 4-DoF pose: the predicate is tight (a passing cell holds a point within
+    the pads plus the sampling resolution) and the root lattice moves z and
+    kappa by at most eps'/2;
+  * the returned point is the centre of the returned leaf, and on planted
+    problems lies near the truth.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_11810_amd import synth
+
+ELL = {"line2d": 1, "plane3d": 2, "ray3d": 2, "pose4dof": 4}
+
+
+def P(g, **kw):
+    return oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], **kw)
+
+
+def p2floor(x):
+    return 2.0 ** math.floor(math.log2(x))
+
+
+def levels_of(E, eps):
+    """Smallest L >= 0 with E 2^-L <= eps (the leaf side is at most eps)."""
+    L = 0
+    while E * 2.0 ** -L > eps:
+        L += 1
+    return L
+
+
+def geometry(g):
+    """Per-axis extent, normalized eps, levels, L*, index bits, from the
+    problem's box and eps only."""
+    fam = g["family"]
+    if fam == "pose4dof":
+        E = [g["hi"][j] - g["lo"][j] for j in range(3)] + [2.0]
+        epsn = [g["eps"][j] / E[j] for j in range(3)] + [g["eps"][3] / 2.0]
+        L = [levels_of(E[j], g["eps"][j]) for j in range(3)] + [levels_of(2.0, g["eps"][3])]
+        B = sum(L) + 2
+    else:
+        d = len(g["lo"])
+        E = [g["hi"][j] - g["lo"][j] for j in range(d)]
+        epsn = [g["eps"][j] / E[j] for j in range(d)]
+        L = [levels_of(E[j], g["eps"][j]) for j in range(d)]
+        B = sum(L)
+    return E, epsn, L, max(L), B
+
+
+def lin_steps(g, c=1.0):
+    """Free step s_f per axis, and the accumulated allowance E(m)."""
+    E, epsn, L, Ls, _ = geometry(g)
+    ell = ELL[g["family"]]
+    sf = [p2floor(epsn[q] / (c * (Ls + 1)) / (ell + 1)) for q in range(len(E))]
+
+    def Em(q, m):
+        return (m + 1) * (ell + 1) * sf[q] / 2.0
+
+    def pad(q, m):
+        return math.ceil((epsn[q] + Em(q, m)) / sf[q]) * sf[q]
+    return sf, Em, pad
+
+
+def pose_bounds(g, c=1.0):
+    """eps' of z and kappa, and upper bounds of the pads (the pad is eps plus
+    half of eps', rounded up to a lattice step of at most eps'/(l+1))."""
+    E, epsn, L, Ls, _ = geometry(g)
+    ell = ELL["pose4dof"]
+    ez = epsn[2] / (c * (Ls + 1))
+    ek = g["eps"][3] / (c * (Ls + 1))
+    padz_max = epsn[2] + ez / 2 + ez / (ell + 1)
+    padk_max = g["eps"][3] + ek / 2 + ek / (ell + 1)
+    Rg = 2.0 ** -max(L[0], L[1])
+    return ez, ek, padz_max, padk_max, Rg
+
+
+def decode_leaf(L, idx, pose):
+    """Leaf index -> (sector, per-axis coordinates): digits of levels
+    0..L*-1, each the split axes' bits in axis order, most significant first,
+    the pose sector on top."""
+    Ls = max(L)
+    nb = sum(L)
+    coords = [0] * len(L)
+    pos = nb
+    for m in range(Ls):
+        for j in range(len(L)):
+            if m < L[j]:
+                pos -= 1
+                coords[j] = 2 * coords[j] + ((idx >> pos) & 1)
+    sector = (idx >> nb) if pose else 0
+    return sector, coords
+
+
+def leaf_grid(L, pose):
+    """Coordinates of every leaf in index order, shape (2^B, d) (+ sectors)."""
+    nb = sum(L)
+    n = 1 << (nb + (2 if pose else 0))
+    idx = np.arange(n, dtype=np.int64)
+    coords = np.zeros((n, len(L)), dtype=np.int64)
+    pos = nb
+    for m in range(max(L)):
+        for j in range(len(L)):
+            if m < L[j]:
+                pos -= 1
+                coords[:, j] = 2 * coords[:, j] + ((idx >> pos) & 1)
+    sec = (idx >> nb) if pose else np.zeros(n, dtype=np.int64)
+    return coords, sec
+
+
+# ----------------------------------------------------------------------------
+# Leaf levels
+# ----------------------------------------------------------------------------
+BENCH = [  # workload, leaf levels and index bits of the benchmark configurations
+    (dict(family="line2d", lo=[-1, -1], hi=[1, 2], eps=[0.005, 0.005]), [9, 10], 19),
+    (dict(family="plane3d", lo=[-1, -1, -2], hi=[1, 1, 3], eps=[0.003] * 3), [10, 10, 11], 31),
+    (dict(family="ray3d", lo=[0, 0, 0], hi=[100, 100, 100], eps=[0.25] * 3), [9, 9, 9], 27),
+    (dict(family="pose4dof", lo=[0, 0, 0, 0], hi=[200, 200, 200, 2 * math.pi],
+          eps=[0.5, 0.5, 0.5, math.radians(0.5)]), [9, 9, 9, 8], 37),
+]
+
+
+@pytest.mark.parametrize("cfg,levels,bits", BENCH)
+def test_leaf_levels_of_the_benchmark_workloads(cfg, levels, bits):
+    nc = {"line2d": 2, "plane3d": 3, "ray3d": 6, "pose4dof": 5}[cfg["family"]]
+    pr = oracle.Problem(cfg["family"], [np.zeros(0)] * nc, cfg["lo"], cfg["hi"], cfg["eps"])
+    k = oracle.constants(pr)
+    d = len(levels)
+    assert k["L"][:d] == levels
+    assert k["Lstar"] == max(levels)
+    assert k["B"] == bits
+
+
+def test_leaf_levels_are_the_smallest_with_side_at_most_eps():
+    rng = np.random.default_rng(21)
+    for _ in range(300):
+        E = float(rng.uniform(0.1, 500.0))
+        eps = float(E * 2.0 ** -rng.uniform(0.2, 14.0))
+        pr = oracle.Problem("line2d", [np.zeros(0)] * 2, [0.0, 0.0], [E, 1.0], [eps, 0.3])
+        L = oracle.constants(pr)["L"][0]
+        assert E * 2.0 ** -L <= eps
+        assert L == 0 or E * 2.0 ** -(L - 1) > eps
+
+
+# ----------------------------------------------------------------------------
+# Canonization deviation against the paper's bound with steps from eps and c
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["line2d_10k", "plane3d_small", "ray3d_small"])
+@pytest.mark.parametrize("c", [1.0, 0.5])
+def test_canonization_deviation_within_paper_bound(name, c):
+    g = synth.config(name)
+    pr = P(g, canon_c=c)
+    E, epsn, L, Ls, _ = geometry(g)
+    ell = ELL[g["family"]]
+    sf, _, _ = lin_steps(g, c)
+    t, f, tag = oracle.parametrize(pr)
+    rng = np.random.default_rng(9)
+    d = len(L)
+    worst = 0.0
+    for trial in range(300):
+        i = int(rng.integers(0, t.shape[0]))
+        m = int(rng.integers(0, Ls))
+        cc = [int(rng.integers(0, 2 ** min(m, L[j]))) for j in range(d)] + [0] * (4 - d)
+        t2, f2 = oracle.canon_at(pr, t[i], f[i], tag[i], m, cc)
+        h = [2.0 ** -min(m, L[j]) for j in range(d)]
+        if g["family"] == "line2d":
+            groups = [([0], 1)]
+        elif g["family"] == "plane3d":
+            groups = [([0, 1], 2)]
+        else:
+            pi = int(tag[i])
+            qs = [q for q in range(3) if q != pi]
+            groups = [([pi], qs[0]), ([pi], qs[1])]
+        for qi, (pax, q) in enumerate(groups):
+            pts = np.concatenate([rng.uniform(0, 1, (64, len(pax))),
+                                  np.array([[(cb >> kk) & 1 for kk in range(len(pax))]
+                                            for cb in range(2 ** len(pax))], float)])
+            x = np.stack([(cc[j] + pts[:, kk]) * h[j] for kk, j in enumerate(pax)], 1)
+            G0 = f[i, qi] + sum(t[i, 2 * qi + kk] * x[:, kk] for kk in range(len(pax)))
+            G1 = f2[qi] + sum(t2[2 * qi + kk] * x[:, kk] for kk in range(len(pax)))
+            dev = float(np.max(np.abs(G1 - G0)))
+            bound = (ell + 1) * sf[q] / 2
+            eps_prime = epsn[q] / (c * (Ls + 1))
+            assert bound <= eps_prime / 2
+            assert dev <= bound * (1 + 1e-12) + 1e-15, (trial, m, dev, bound)
+            worst = max(worst, dev / bound)
+            # canonical parameters sit on the lattice of their level
+            for kk, j in enumerate(pax):
+                st = sf[q] * 2.0 ** min(m, L[j])
+                assert t2[2 * qi + kk] / st == round(t2[2 * qi + kk] / st)
+    assert worst > 0.2
+
+
+# ----------------------------------------------------------------------------
+# Pads: the predicate switches exactly at pad(m) (linear families)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["line2d_10k", "plane3d_small", "ray3d_small"])
+def test_linear_predicate_switches_at_the_pad(name):
+    g = synth.config(name)
+    pr = P(g)
+    E, epsn, L, Ls, _ = geometry(g)
+    sf, _, pad = lin_steps(g)
+    rng = np.random.default_rng(31)
+    d = len(L)
+    fam = g["family"]
+    for trial in range(400):
+        m = int(rng.integers(0, Ls))
+        m1 = m + 1
+        cc = [int(rng.integers(0, 2 ** min(m1, L[j]))) for j in range(d)]
+        h = [2.0 ** -min(m1, L[j]) for j in range(d)]
+        if fam == "line2d":
+            pax, qs, tag = [0], [1], 0
+        elif fam == "plane3d":
+            pax, qs, tag = [0, 1], [2], 0
+        else:
+            tag = int(rng.integers(0, 3))
+            pax, qs = [tag], [q for q in range(3) if q != tag]
+        t = np.zeros(4)
+        f = np.zeros(2)
+        # slopes on the level-m lattice, small integers of it
+        for qi, q in enumerate(qs):
+            for kk, j in enumerate(pax):
+                st = sf[q] * 2.0 ** min(m, L[j])
+                t[2 * qi + kk] = st * int(rng.integers(-40, 41))
+        # place dependent axis qsel at the edge of the padded interval, the
+        # others in the middle of theirs
+        qsel = int(rng.integers(0, len(qs)))
+        side = int(rng.integers(0, 2))
+        res = {}
+        for delta in (0, 1):
+            for qi, q in enumerate(qs):
+                lo_q, hi_q = cc[q] * h[q], (cc[q] + 1) * h[q]
+                terms = [t[2 * qi + kk] * np.array([cc[j] * h[j], (cc[j] + 1) * h[j]]) for kk, j in enumerate(pax)]
+                smin = sum(float(x.min()) for x in terms)
+                smax = sum(float(x.max()) for x in terms)
+                if qi != qsel:
+                    f[qi] = (lo_q + hi_q) / 2 - (smin + smax) / 2
+                    f[qi] = round(f[qi] / sf[q]) * sf[q]
+                elif side == 0:   # range top at lo - pad (passes) or one step below
+                    f[qi] = lo_q - pad(q, m) - delta * sf[q] - smax
+                else:             # range bottom at hi + pad, or one step above
+                    f[qi] = hi_q + pad(q, m) + delta * sf[q] - smin
+            res[delta] = oracle.meets(pr, t, f, tag, m, 0, cc + [0] * (4 - d))
+        assert res[0] and not res[1], (trial, m, cc, qsel, side)
+
+
+# ----------------------------------------------------------------------------
+# Exhaustive LOW and UP over every leaf of tiny problems
+# ----------------------------------------------------------------------------
+def _leaf_boxes(g, L, pose):
+    coords, sec = leaf_grid(L, pose)
+    E, *_ = geometry(g)
+    lo = np.array(g["lo"][:len(L)], float)
+    if pose:
+        lo[3] = -1.0
+    h = np.array([E[j] * 2.0 ** -L[j] for j in range(len(L))])
+    return lo + coords * h, lo + (coords + 1) * h, sec
+
+
+def _lin_distances(g, i, blo, bhi):
+    """Per dependent axis: distance (user units) between the surface's range
+    over each leaf's parameter box and the leaf's interval on that axis,
+    evaluated from the observation itself."""
+    c = [col[i] for col in g["cols"]]
+    fam = g["family"]
+    out = []
+    if fam == "line2d":          # b = y - x a
+        x, y = c
+        v0, v1 = y - x * blo[:, 0], y - x * bhi[:, 0]
+        out.append((1, np.minimum(v0, v1), np.maximum(v0, v1)))
+    elif fam == "plane3d":       # a0 = z - x a1 - y a2
+        x, y, z = c
+        p = [-x * blo[:, 0], -x * bhi[:, 0]]
+        q = [-y * blo[:, 1], -y * bhi[:, 1]]
+        out.append((2, z + np.minimum(*p) + np.minimum(*q), z + np.maximum(*p) + np.maximum(*q)))
+    else:                        # x_q = w_q + (u_q/u_pi)(x_pi - w_pi), pi = dominant axis
+        w, u = np.array(c[:3]), np.array(c[3:])
+        pi = int(np.argmax(np.abs(u)))
+        for q in range(3):
+            if q == pi:
+                continue
+            s = u[q] / u[pi]
+            v0 = w[q] + s * (blo[:, pi] - w[pi])
+            v1 = w[q] + s * (bhi[:, pi] - w[pi])
+            out.append((q, np.minimum(v0, v1), np.maximum(v0, v1)))
+    dist = []
+    for q, gmin, gmax in out:
+        dist.append((q, np.maximum(0.0, np.maximum(blo[:, q] - gmax, gmin - bhi[:, q]))))
+    return dist
+
+
+def _angle_span(wx, wy, blo, bhi):
+    """Arguments of (w - p) over each box p in [blo, bhi] (boxes not holding
+    w): [a0, a1] with a1 - a0 < pi, from the corners around the centre's."""
+    cx = (blo[:, 0] + bhi[:, 0]) / 2
+    cy = (blo[:, 1] + bhi[:, 1]) / 2
+    ac = np.arctan2(wy - cy, wx - cx)
+    ds = []
+    for X in (blo[:, 0], bhi[:, 0]):
+        for Y in (blo[:, 1], bhi[:, 1]):
+            a = np.arctan2(wy - Y, wx - X)
+            ds.append(np.mod(a - ac + np.pi, 2 * np.pi) - np.pi)
+    ds = np.stack(ds)
+    return ac + ds.min(0), ac + ds.max(0)
+
+
+def _overlap_mod(a0, a1, b0, b1):
+    """Do [a0, a1] and [b0, b1] (angles, each shorter than pi) meet modulo 2 pi?"""
+    hit = np.zeros(np.broadcast(a0, b0).shape, bool)
+    for k in (-2, -1, 0, 1, 2):
+        s = 2 * np.pi * k
+        hit |= (a0 + s <= b1) & (b0 <= a1 + s)
+    return hit
+
+
+def _pose_parts(g, i, blo, bhi, sec):
+    """Direct evaluation from the match (w, xi, eta): per leaf, the z range
+    W3 - eta [r_min, r_max] (metres) and the argument span of the direction
+    from the camera to w, turned into the sector's frame and offset by
+    atan(xi), so that kappa = tan of it."""
+    w1, w2, w3, xi, eta = (col[i] for col in g["cols"])
+    dx = np.maximum(0.0, np.maximum(blo[:, 0] - w1, w1 - bhi[:, 0]))
+    dy = np.maximum(0.0, np.maximum(blo[:, 1] - w2, w2 - bhi[:, 1]))
+    rmin = np.hypot(dx, dy)
+    rmax = np.hypot(np.maximum(np.abs(w1 - blo[:, 0]), np.abs(w1 - bhi[:, 0])),
+                    np.maximum(np.abs(w2 - blo[:, 1]), np.abs(w2 - bhi[:, 1])))
+    z0, z1 = w3 - eta * rmax, w3 - eta * rmin
+    zmin, zmax = np.minimum(z0, z1), np.maximum(z0, z1)
+    zdist = np.maximum(0.0, np.maximum(blo[:, 2] - zmax, zmin - bhi[:, 2]))
+    a0, a1 = _angle_span(w1, w2, blo, bhi)
+    off = sec * (np.pi / 2) + math.atan(xi)
+    return zdist, rmin, a0 - off, a1 - off
+
+
+TINY = [("line2d_tiny", s) for s in (1, 2, 3)] + [("plane3d_tiny", s) for s in (1, 2)] + \
+       [("ray3d_tiny", s) for s in (1, 2)] + [("pose4dof_tiny", s) for s in (1, 2, 3)] + \
+       [("pose4dof_tiny_flat", s) for s in (5, 6)]
+
+
+@pytest.mark.parametrize("name,seed", TINY)
+def test_every_leaf_low_and_up(name, seed):
+    g = synth.config(name, seed=seed)
+    pr = P(g)
+    E, epsn, L, Ls, B = geometry(g)
+    pose = g["family"] == "pose4dof"
+    blo, bhi, sec = _leaf_boxes(g, L, pose)
+    n = len(g["cols"][0])
+    total = np.zeros(blo.shape[0], np.int64)
+    n_low = n_up = 0
+    if pose:
+        ez, ek, pzm, pkm, Rg = pose_bounds(g)
+        Ez = E[2]
+    else:
+        sf, Em, _ = lin_steps(g)
+    for i in range(n):
+        ind = oracle.leaf_indicator(pr, i).astype(bool)
+        total += ind
+        if not pose:
+            # LOW: within eps (directly) on every dependent axis -> counted
+            low = np.ones(ind.shape, bool)
+            for q, dist in _lin_distances(g, i, blo, bhi):
+                low &= dist <= g["eps"][q] * (1 - 1e-9)
+            assert np.all(ind[low]), i
+            n_low += int(low.sum())
+            for q, dist in _lin_distances(g, i, blo, bhi):
+                # UP: counted -> within eps + 2E(L*-1) + s_f on each axis
+                up = (epsn[q] + 2 * Em(q, Ls - 1) + sf[q]) * E[q]
+                assert np.all(dist[ind] <= up * (1 + 1e-9)), (i, q, float(dist[ind].max()), up)
+                n_up += int(ind.sum())
+        else:
+            zdist, rmin, p0, p1 = _pose_parts(g, i, blo, bhi, sec)
+            klo, khi = blo[:, 3], bhi[:, 3]
+            e3 = g["eps"][3]
+            # LOW, per axis (the predicate tests z and kappa separately)
+            zlow = zdist <= g["eps"][2] * (1 - 1e-9)
+            klow = _overlap_mod(p0, p1, np.arctan(klo - e3 * (1 - 1e-9)), np.arctan(khi + e3 * (1 - 1e-9)))
+            # the apex guard is decided on the quantized surface, whose apex
+            # moves by at most one xy step (< ek Rg / (l+1)): count on it only
+            # clear of that band on either side
+            band = ek * Rg / (ELL["pose4dof"] + 1) * E[0]
+            guard = rmin < Rg * E[0] - band
+            low = zlow & (guard | ((rmin > Rg * E[0] + band) & klow))
+            assert np.all(ind[low]), i
+            n_low += int(low.sum())
+            # UP: z within the pad bound plus the root quantization; kappa
+            # likewise where the leaf is outside the apex guard
+            assert np.all(zdist[ind] <= (pzm + ez / 2) * Ez * (1 + 1e-9)), i
+            kb = (pkm + ek / 2) * 1.02  # kappa moves by ek/2 to first order
+            far = ind & (rmin >= Rg * E[0] * (1 + 1e-9))
+            kup = _overlap_mod(p0, p1, np.arctan(klo - kb) - 1e-9, np.arctan(khi + kb) + 1e-9)
+            assert np.all(kup[far]), i
+            n_up += int(ind.sum())
+    # the per-surface indicators add up to the leaf counts of the search tree
+    assert np.array_equal(total, oracle.all_leaf_counts(pr).astype(np.int64))
+    assert n_low > 0 and n_up > 0
+
+
+@pytest.mark.parametrize("name,seed", [("line2d_tiny", 1), ("plane3d_tiny", 2), ("ray3d_tiny", 1),
+                                       ("pose4dof_tiny", 1)])
+def test_counts_shrink_down_the_tree(name, seed):
+    """count(child) <= count(parent) for every cell of every level, the root
+    holds every surface, and the leaf level equals the leaf counts."""
+    g = synth.config(name, seed=seed)
+    pr = P(g)
+    E, epsn, L, Ls, B = geometry(g)
+    pose = g["family"] == "pose4dof"
+    n = len(g["cols"][0])
+    prev = oracle.level_counts(pr, 0)
+    assert np.all(prev == n) and prev.size == (4 if pose else 1)
+    for m in range(Ls):
+        cur = oracle.level_counts(pr, m + 1)
+        a = sum(1 for j in range(len(L)) if m < L[j])
+        parent = np.repeat(prev, 1 << a)  # child index = parent index << a | digit
+        assert cur.size == parent.size
+        assert np.all(cur <= parent), m
+        assert np.any(cur < parent)
+        prev = cur
+    assert np.array_equal(prev, oracle.all_leaf_counts(pr))
+
+
+# ----------------------------------------------------------------------------
+# 4-DoF pose: predicate tightness and the root lattice
+# ----------------------------------------------------------------------------
+def _pose_cell(L, m1, cc):
+    h = [2.0 ** -min(m1, L[j]) for j in range(4)]
+    box = [(cc[j] * h[j], (cc[j] + 1) * h[j]) for j in range(3)]
+    kb = (2 * cc[3] * h[3] - 1, 2 * (cc[3] + 1) * h[3] - 1)
+    return box, kb, h
+
+
+def _rot(sec, a, b):
+    return [(a, b), (b, -a), (-a, -b), (-b, a)][sec]
+
+
+@pytest.mark.parametrize("name,seed", [("pose4dof_small", 14), ("pose4dof_small", 15), ("pose4dof_small_flat", 18)])
+def test_pose_predicate_is_tight(name, seed):
+    """Where the predicate passes, the cell holds a point whose z is within
+    the z pad (exactly, from the range of horizontal distances) and, away
+    from the apex guard, a point whose kappa is within the kappa pad, up to
+    the sampling resolution (kappa compared as an angle, whose gradient is
+    1/r)."""
+    g = synth.config(name, seed=seed)
+    pr = P(g)
+    E, epsn, L, Ls, B = geometry(g)
+    ez, ek, pzm, pkm, Rg = pose_bounds(g)
+    t, f, _ = oracle.parametrize(pr, root_canon=True)
+    rng = np.random.default_rng(seed)
+    G = 48
+    s = np.linspace(0.0, 1.0, G)
+    SX, SY = np.meshgrid(s, s, indexing="ij")
+    SX, SY = SX.ravel(), SY.ravel()
+    n_pass = n_k = 0
+    for trial in range(5000):
+        i = int(rng.integers(0, t.shape[0]))
+        m = int(rng.integers(0, Ls))
+        m1 = m + 1
+        sec = int(rng.integers(0, 4))
+        W1, W2, xi, eta, W3 = t[i, 0], t[i, 1], t[i, 2], t[i, 3], f[i, 0]
+        # a cell near the surface: take a point of it, jitter the coordinates
+        X0, Y0 = rng.uniform(0, 1, 2)
+        v1, v2 = _rot(sec, W1 - X0, W2 - Y0)
+        D = v1 + xi * v2
+        if D <= 0:
+            continue
+        kap = (v2 - xi * v1) / D
+        Z = W3 - eta * math.hypot(v1, v2)
+        n1 = [2 ** min(m1, L[j]) for j in range(4)]
+        base = [X0, Y0, min(max(Z, 0.0), 1 - 1e-12), min(max((kap + 1) / 2, 0.0), 1 - 1e-12)]
+        cc = [int(min(n1[j] - 1, max(0, math.floor(base[j] * n1[j]) + int(rng.integers(-2, 3)))))
+              for j in range(4)]
+        if not oracle.meets(pr, t[i], f[i], 0, m, sec, cc):
+            continue
+        n_pass += 1
+        box, (Klo, Khi), h = _pose_cell(L, m1, cc)
+        # z: exact range over the cell from the apex distances
+        ax0, ax1 = W1 - box[0][1], W1 - box[0][0]
+        ay0, ay1 = W2 - box[1][1], W2 - box[1][0]
+        dx = max(0.0, ax0, -ax1)
+        dy = max(0.0, ay0, -ay1)
+        rmin = math.hypot(dx, dy)
+        rmax = math.hypot(max(abs(ax0), abs(ax1)), max(abs(ay0), abs(ay1)))
+        z0, z1 = sorted([W3 - eta * rmin, W3 - eta * rmax])
+        zd = max(0.0, box[2][0] - z1, z0 - box[2][1])
+        assert zd <= pzm * (1 + 1e-9), (trial, zd, pzm)
+        if rmin < Rg:
+            continue
+        X = box[0][0] + SX * h[0]
+        Y = box[1][0] + SY * h[1]
+        v1, v2 = _rot(sec, W1 - X, W2 - Y)
+        D = v1 + xi * v2
+        psi = np.arctan2(v2 - xi * v1, D)  # = atan(kappa) where D > 0
+        res = h[0] / (G - 1) / math.sqrt(2) / rmin + 1e-12
+        ok = (D > 0) & (psi >= math.atan(Klo - pkm) - res) & (psi <= math.atan(Khi + pkm) + res)
+        assert ok.any(), (trial, i, m, sec, cc)
+        n_k += 1
+    assert n_pass > 200 and n_k > 100
+
+
+@pytest.mark.parametrize("name", ["pose4dof_small", "pose4dof_tiny", "pose4dof_small_flat"])
+def test_pose_root_lattice_moves_z_and_kappa_by_at_most_half_eps_prime(name):
+    g = synth.config(name)
+    pr = P(g)
+    E, epsn, L, Ls, B = geometry(g)
+    ez, ek, pzm, pkm, Rg = pose_bounds(g)
+    t0, f0, _ = oracle.parametrize(pr)
+    t1, f1, _ = oracle.parametrize(pr, root_canon=True)
+    rng = np.random.default_rng(3)
+    X, Y = rng.uniform(0, 1, (2, 4000))
+    worst_z = worst_k = 0.0
+    kmax = 1.0 + g["eps"][3] + ek / 2
+    for i in range(0, t0.shape[0], max(1, t0.shape[0] // 400)):
+        for sec in range(4):
+            va = _rot(sec, t0[i, 0] - X, t0[i, 1] - Y)
+            vb = _rot(sec, t1[i, 0] - X, t1[i, 1] - Y)
+            za = f0[i, 0] - t0[i, 3] * np.hypot(*va)
+            zb = f1[i, 0] - t1[i, 3] * np.hypot(*vb)
+            dz = float(np.max(np.abs(za - zb)))
+            assert dz <= ez / 2 * (1 + 1e-6), (i, dz, ez / 2)
+            worst_z = max(worst_z, dz / (ez / 2))
+            Da = va[0] + t0[i, 2] * va[1]
+            Db = vb[0] + t1[i, 2] * vb[1]
+            ka = (va[1] - t0[i, 2] * va[0]) / np.where(Da > 0, Da, 1.0)
+            kb = (vb[1] - t1[i, 2] * vb[0]) / np.where(Db > 0, Db, 1.0)
+            sel = (Da > 0) & (Db > 0) & (np.hypot(*va) >= Rg) & (np.abs(ka) <= kmax)
+            if sel.any():
+                dk = float(np.max(np.abs(ka - kb)[sel]))
+                assert dk <= ek / 2 * 1.02, (i, sec, dk, ek / 2)
+                worst_k = max(worst_k, dk / (ek / 2))
+    assert worst_z > 0.05 and worst_k > 0.02
+
+
+# ----------------------------------------------------------------------------
+# Returned point
+# ----------------------------------------------------------------------------
+SMALL = ["line2d_small", "plane3d_small", "ray3d_small", "pose4dof_small", "line2d_tiny", "pose4dof_tiny",
+         "pose4dof_small_flat"]
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_point_is_the_centre_of_the_returned_leaf(name):
+    g = synth.config(name)
+    pr = P(g)
+    E, epsn, L, Ls, B = geometry(g)
+    pose = g["family"] == "pose4dof"
+    r = oracle.solve(pr)
+    sec, coords = decode_leaf(L, r["leaf_index"], pose)
+    assert list(r["leaf_coords"][:len(L)]) == coords
+    assert r["sector"] == sec
+    for j in range(3 if pose else len(L)):
+        lo = g["lo"][j] + E[j] * coords[j] * 2.0 ** -L[j]
+        hi = g["lo"][j] + E[j] * (coords[j] + 1) * 2.0 ** -L[j]
+        assert abs(r["point"][j] - (lo + hi) / 2) <= 1e-12 * max(1.0, abs(hi))
+    if pose:
+        klo = -1.0 + 2.0 * coords[3] * 2.0 ** -L[3]
+        khi = -1.0 + 2.0 * (coords[3] + 1) * 2.0 ** -L[3]
+        yaw = r["point"][3]
+        assert 0.0 <= yaw < 2 * math.pi
+        kap = math.tan(yaw - sec * math.pi / 2)
+        assert abs(kap - (klo + khi) / 2) <= 1e-12
+
+
+@pytest.mark.parametrize("name,seed", [("line2d_small", None), ("ray3d_small", None), ("pose4dof_small", None),
+                                       ("pose4dof_small", 16), ("pose4dof_small", 17), ("pose4dof_small_flat", None),
+                                       ("line2d_10k", None)])
+def test_point_near_the_planted_truth(name, seed):
+    g = synth.config(name, seed=seed) if seed else synth.config(name)
+    pr = P(g)
+    E, epsn, L, Ls, B = geometry(g)
+    r = oracle.solve(pr)
+    tr = list(map(float, g["truth"]))
+    for j in range(len(L)):
+        side = E[j] * 2.0 ** -L[j] if j < 3 or g["family"] != "pose4dof" else 2 * g["eps"][3]
+        diff = abs(r["point"][j] - tr[j])
+        if g["family"] == "pose4dof" and j == 3:
+            diff = min(diff, 2 * math.pi - diff)
+        assert diff <= 2 * g["eps"][j] + side, (j, r["point"][j], tr[j])

@@ -88,8 +88,9 @@ def _pose_obs(c, yaw, w):
     return xi, eta, F
 
 
+@pytest.mark.parametrize("height", [200.0, 90.0])
 @pytest.mark.parametrize("yaw", [0.3, 1.2, 2.0, 2.9, 3.6, 4.4, 5.2, 6.1, math.pi / 4 - 1e-3])
-def test_pose4dof_surface_and_sector_identity(yaw):
+def test_pose4dof_surface_and_sector_identity(yaw, height):
     """z = w3 - eta r and kappa = ((w2-y) - xi (w1-x)) / ((w1-x) + xi (w2-y))
     (the 5DoF surface with unit focal length) evaluated at the true camera
     returns its height and tan of its yaw offset inside sector
@@ -97,15 +98,15 @@ def test_pose4dof_surface_and_sector_identity(yaw):
     with |kappa| <= 1."""
     rng = np.random.default_rng(8)
     c = np.array([80.0, 120.0, 60.0])
-    w = rng.uniform(0, 200, (500, 3))
+    w = rng.uniform(0, [200, 200, height], (500, 3))
     xi, eta, F = _pose_obs(c, yaw, w)
     keep = (F > 1.0) & (np.abs(xi) < 50)
     w, xi, eta = w[keep], xi[keep], eta[keep]
     g = {"family": "pose4dof", "cols": [w[:, 0], w[:, 1], w[:, 2], xi, eta], "lo": [0, 0, 0, 0],
-         "hi": [200, 200, 200, 2 * math.pi], "eps": [1, 1, 1, 0.01]}
+         "hi": [200, 200, height, 2 * math.pi], "eps": [1, 1, 1, 0.01]}
     t, f, _ = oracle.parametrize(P(g))
     W1, W2, xiq, etaq, W3 = t[:, 0], t[:, 1], t[:, 2], t[:, 3], f[:, 0]
-    X, Y, Z = c / 200.0
+    X, Y, Z = c / np.array([200.0, 200.0, height])
     s = int(math.floor((yaw + math.pi / 4) / (math.pi / 2))) % 4
     kstar = math.tan(yaw - s * math.pi / 2)
     a, b = W1 - X, W2 - Y
@@ -492,3 +493,21 @@ def test_inliers_within_approximation_bound(name):
             E = lstar * (ell + 1) * sf / 2
             assert dist <= k["epsn"][q] + 2 * E + sf + 1e-12
     assert r["n_inliers"] == r["count"]
+
+
+# ----------------------------------------------------------------------------
+# Thread pool: disjoint subtrees sharing only the best key give the serial
+# result (the key of a leaf is unique, so the search order cannot matter)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny", "line2d_small",
+                                  "plane3d_small", "ray3d_small", "pose4dof_small", "pose4dof_small_flat"])
+@pytest.mark.parametrize("threads", [2, 5])
+def test_thread_pool_equals_serial(name, threads):
+    g = synth.config(name)
+    a = oracle.solve(P(g))
+    b = oracle.solve(P(g, threads=threads))
+    assert (a["count"], a["leaf_index"], a["sector"]) == (b["count"], b["leaf_index"], b["sector"])
+    assert np.array_equal(a["inliers"], b["inliers"])
+    assert a["point"] == b["point"]
+    c = oracle.solve(P(g, threads=threads, no_dive=True))
+    assert (c["count"], c["leaf_index"]) == (a["count"], a["leaf_index"])
