@@ -105,9 +105,17 @@ typedef struct {
                                  the call returns / the ticket is polled);
                                  0: host pointers (copied during the call) */
   double lo[4], hi[4];        /* domain box, user units, family axis order */
-  double eps[4];              /* per-axis eps, user units; POSE4DOF eps[3] is
-                                 the yaw tolerance in radians */
-  double canon_c;             /* eps' = eps / (c (L*+1)); 0 -> 1.0 */
+  double eps[4];              /* per-axis eps, user units.  POSE4DOF eps[3] is
+                                 the yaw tolerance in radians, applied to
+                                 kappa = tan(yaw offset inside the sector), so
+                                 the tolerance on the yaw angle itself is
+                                 eps / (1 + kappa^2), between eps/2 and eps */
+  double canon_c;             /* eps' = eps / (c (L*+1)); 0 -> 1.0.  +INFINITY:
+                                 exact mode, the plain definition (Sec. 3.1,
+                                 Alg. 1 on the leaf grid): every surface is
+                                 quantized once to a fixed 2^-36 lattice and
+                                 never re-canonized, pads are eps rounded up
+                                 to that lattice, tests run in binary64 */
   gv_precision precision;
   int group;                  /* merging of equal canonical surfaces (never
                                  changes a result): 0 at the root and in cells
@@ -128,6 +136,9 @@ typedef struct {
   double test_ms, compact_ms;
   uint64_t test_launches, compact_launches;
   uint64_t test_bytes, compact_bytes;
+  double ms_queued;           /* gv_submit: time from submission until a
+                                 serving lane admitted the problem (memory
+                                 admission); 0 for gv_solve */
 } gv_stats;
 
 typedef struct {
@@ -139,7 +150,22 @@ typedef struct {
   int64_t *inliers;           /* caller buffer (host), sorted ascending */
   uint64_t inliers_cap;
   uint64_t n_inliers;         /* on GV_EBUFSZ: required capacity */
-  double bound[4];            /* per-axis allowance: eps + rounding allowance, user units */
+  double bound[4];            /* certified approximation bound per axis, user
+                                 units (Sec. 3.2): on an axis that surfaces
+                                 depend on (LINE2D b, PLANE3D a0, every RAY3D
+                                 axis, POSE4DOF z and yaw), every reported
+                                 inlier's range over the leaf's parameter box
+                                 comes within bound[j] of the leaf's interval
+                                 on that axis: the last pad plus the
+                                 accumulated canonization allowance.  POSE4DOF
+                                 bound[3] is in kappa units, which also bounds
+                                 the yaw angle in radians (|d yaw/d kappa| <=
+                                 1), and holds where the leaf is farther from
+                                 the match than the apex guard (one leaf xy
+                                 side).  On a pure parameter axis (LINE2D a,
+                                 PLANE3D a1 a2, POSE4DOF x y): half the leaf
+                                 side, the distance from point[] to any point
+                                 of the leaf. */
   gv_stats stats;
 } gv_result;
 
@@ -176,8 +202,25 @@ gv_status gv_submit(gv_ctx *ctx, const gv_problem *p, uint64_t *ticket);
  * success fills *r (inliers into r->inliers) and retires the ticket. */
 gv_status gv_poll(gv_ctx *ctx, uint64_t ticket, gv_result *r, int timeout_ms);
 
-/* Cancel a pending ticket; a later poll returns GV_ECANCELED. */
+/* Cancel a ticket: a queued problem is dropped, a running one stops at its
+ * next frontier expansion; a later poll returns GV_ECANCELED. */
 gv_status gv_cancel(gv_ctx *ctx, uint64_t ticket);
+
+/* Incidence test only (the sub-box step of Alg. 2: which surfaces pass
+ * within eps of each child, Sec. 3.2.1 and the Surface-Box paragraph of Sec.
+ * 3.3), for parity checks of that step.  Every observation of p becomes its
+ * canonical surface at the cell of `level` with integer coordinates
+ * coords[0..3] (each in [0, 2^min(level, L_j))) and, for POSE4DOF, yaw
+ * sector `sector` (0..3, else 0): the root canonization followed by the
+ * child canonization of every level on the path to that cell (POSE4DOF and
+ * exact mode: the root quantization only).  It is then tested against each
+ * child of the cell exactly as the search tests it, in p->precision.
+ * masks_out[i] (host buffer of n words) gets bit d set when surface i passes
+ * child digit d (the split axes' bits in axis order, most significant
+ * first).  stats_out (may be NULL): tests = n * children, fp64_rechecks =
+ * decisions the binary32 filter left to binary64.  0 <= level < L*. */
+gv_status gv_incidence(gv_ctx *ctx, const gv_problem *p, int32_t level, int32_t sector, const int32_t coords[4],
+                       uint32_t *masks_out, gv_stats *stats_out);
 
 /* Static text for a status code. */
 const char *gv_status_str(gv_status s);

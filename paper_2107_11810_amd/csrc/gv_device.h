@@ -21,6 +21,16 @@
 #define GV_ITEM 1024  // entries per work item (one wave)
 
 enum { FAM_LINE2D = 1, FAM_PLANE3D = 2, FAM_RAY3D = 3, FAM_POSE4DOF = 4 };
+// Exact mode of a linear family (quantized once at the root to a fixed
+// 2^-36 lattice, never re-canonized, tested in binary64): kernel-side family
+// code = family + 4.
+enum { FAM_XLINE2D = 5, FAM_XPLANE3D = 6, FAM_XRAY3D = 7 };
+constexpr bool fam_exact(int f) { return f >= FAM_XLINE2D; }
+constexpr int fam_base(int f) { return f >= FAM_XLINE2D ? f - 4 : f; }
+// families whose count pass stores per-entry pass masks and whose
+// compaction copies entries unchanged (the surfaces do not change below the
+// root)
+constexpr bool fam_masked(int f) { return f == FAM_POSE4DOF || fam_exact(f); }
 
 // Per-level constants for the test from level m to level m+1.
 struct LevelC {
@@ -44,6 +54,10 @@ struct ProbC {
   double sW, sW3, sXi, sEta, Rg2, padz, padk;
   double inv_sW, inv_sW3, inv_sXi, inv_sEta;
   float Rg2f, padzf, padkf, _pf;
+  // exact mode: 1 when every surface is quantized once to the 2^-36
+  // lattice and never re-canonized; xpad = eps rounded up to that lattice
+  int32_t exact, _pe;
+  double xpad[4];
   LevelC lev[GV_MAXL];
 };
 
@@ -80,6 +94,14 @@ static_assert(sizeof(EntQ24) == 24 && offsetof(EntQ24, ridx) == 20 && offsetof(E
 template <typename E> __device__ inline uint32_t pose_w(const E& e) { return e.w; }
 template <> __device__ inline uint32_t pose_w<EntQ24>(const EntQ24&) { return 1u; }
 struct __attribute__((aligned(16))) EntQ64 { double W1, W2, W3, xi, eta; uint32_t w, ridx; };
+
+// Exact-mode linear entry: the root-quantized binary64 parameters.
+//   LINE2D  a = t,   f0 = f
+//   PLANE3D a = t1,  b = t2, f0 = f
+//   RAY3D   a = t of the first dependent axis, b = t of the second, f0, f1;
+//           tag = parameter axis
+struct __attribute__((aligned(8))) EntX { double a, b, f0, f1; uint32_t w; int32_t tag; };
+static_assert(sizeof(EntX) == 40, "copied as 8-byte words");
 
 template <int FAM> struct EntOf;
 template <> struct EntOf<FAM_LINE2D> { using T = EntL2; };
@@ -351,6 +373,54 @@ template <int FAM> __device__ inline LinS lin_canon_child(const LinS& s, const L
     o.F[qi] = rne_half(v);
   }
   return o;
+}
+
+// ---------------------------------------------------------------------------
+// Exact mode (linear families): the surface/box test in binary64 with the
+// operation order of the plain definition (per dependent axis q, the range
+// of f + sum t_i u_i over the child's parameter box, each term's min and max
+// at the two ends, against the child's q-interval widened by the pad).
+// lo/hi: the child box per axis.
+// ---------------------------------------------------------------------------
+__device__ inline bool x_axis(double f, double t0, int j0, double t1, int j1, int q, const double* lo,
+                              const double* hi, double pad) {
+  double gmin = f, gmax = f;
+  {
+    const double a = t0 * lo[j0], b = t0 * hi[j0];
+    gmin = gmin + (a < b ? a : b);
+    gmax = gmax + (a < b ? b : a);
+  }
+  if (j1 >= 0) {
+    const double a = t1 * lo[j1], b = t1 * hi[j1];
+    gmin = gmin + (a < b ? a : b);
+    gmax = gmax + (a < b ? b : a);
+  }
+  return !(gmax < lo[q] - pad) && !(gmin > hi[q] + pad);
+}
+
+template <int BF>
+__device__ inline bool x_meets(const EntX& e, const double* lo, const double* hi, const double* xpad) {
+  if constexpr (BF == FAM_LINE2D) {
+    return x_axis(e.f0, e.a, 0, 0.0, -1, 1, lo, hi, xpad[1]);
+  } else if constexpr (BF == FAM_PLANE3D) {
+    return x_axis(e.f0, e.a, 0, e.b, 1, 2, lo, hi, xpad[2]);
+  } else {
+    const int t = e.tag;
+    const int q0 = t == 0 ? 1 : 0, q1 = t == 2 ? 1 : 2;
+    return x_axis(e.f0, e.a, t, 0.0, -1, q0, lo, hi, xpad[q0]) && x_axis(e.f1, e.b, t, 0.0, -1, q1, lo, hi, xpad[q1]);
+  }
+}
+
+// the child box (per axis, in the unit cube) of digit cb of a level-m cell
+__device__ inline void x_child_box(const ProbC& P, const LevelC& lv, const int32_t* c, int m, uint32_t cb,
+                                   double* lo, double* hi) {
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int32_t cj = lv.split[j] ? 2 * c[j] + (int32_t)((cb >> j) & 1u) : c[j];
+    const double h = ldexp(1.0, -min(m + 1, P.L[j]));
+    lo[j] = (double)cj * h;
+    hi[j] = (double)(cj + 1) * h;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -230,9 +230,6 @@ __global__ void k_zero3(uint32_t* __restrict__ a, uint64_t na, uint32_t* __restr
 // and per-child counts.  No pass masks are stored: the compaction pass reads
 // every entry anyway and repeats the (cheap, integer) test.
 // ---------------------------------------------------------------------------
-// a height no child interval reaches: lanes without an entry fail every test
-#define GV_F_NONE (1 << 27)
-
 // Pass predicates of one surface for the NCH children of its cell.
 // PLANE3D with all three axes splitting (digit = b_a1 b_a2 b_a0): with
 // c = max(K, 0), child (b1, b2, b0) is met iff
@@ -309,12 +306,13 @@ __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Item* __rest
 #pragma unroll
       for (int j = 0; j < NB; j++) {
         if (k0 + 64 * j >= cnt) break;
-        LinS s = load_ent<FAM>(ev[j]);
-        if (k0 + 64 * j + lane >= cnt) s.F[0] = s.F[1] = GV_F_NONE;
+        const LinS s = load_ent<FAM>(ev[j]);
+        const bool valid = k0 + 64 * j + lane < cnt;  // lanes past the item's end pass nothing
         bool p[NCH];
         lin_pass<FAM, NCH>(s, lv, p);
 #pragma unroll
         for (int ch = 0; ch < NCH; ch++) {
+          p[ch] = p[ch] && valid;
           an[ch] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p[ch]));
           if constexpr (!UNIT) aw[ch] += p[ch] ? (uint32_t)s.w : 0u;
         }
@@ -974,12 +972,14 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
         }
         int32_t U[G], BASE[G], KA[G], KB[G];
         uint32_t RR[G], LO[G], WHI[G];
+        bool V[G];  // lanes past the item's end pass nothing
 #pragma unroll
         for (int j = 0; j < G; j++) {
           const LinS s = load_ent<FAM>(ev[j]);
           const int32_t K1 = s.K[0][0], K2 = s.K[0][1], K12 = K1 + K2;
           const int32_t S = imax32(K1, 0) + imax32(K2, 0);
-          const int32_t F = k0 + 64 * j + lane < cnt ? s.F[0] : GV_F_NONE;
+          V[j] = k0 + 64 * j + lane < cnt;
+          const int32_t F = s.F[0];
           U[j] = 2 * F + pad + S;
           BASE[j] = pad + S;
           KA[j] = K1;
@@ -990,7 +990,7 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
           if constexpr (UW) {
             // a one-word input's K and weight always fit
             if constexpr (!std::is_same<E, EntP3u>::value)
-              fits = fits && abs(K1c) <= GV_P3U_KMAX && abs(K2c) <= GV_P3U_KMAX && (w == 1u || F == GV_F_NONE);
+              fits = fits && abs(K1c) <= GV_P3U_KMAX && abs(K2c) <= GV_P3U_KMAX && (w == 1u || !V[j]);
             LO[j] = ((uint32_t)K1c & 0xffu) | (((uint32_t)K2c & 0xffu) << 8);
             WHI[j] = 0u;
           } else {
@@ -1008,7 +1008,7 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
             if (k0 + 64 * j >= cnt) break;
             const int32_t uu = U[j] + ((ch & 4) ? KA[j] : 0) + ((ch & 2) ? KB[j] : 0);
             const int32_t t = (ch & 1) ? uu - H : uu;
-            const bool c = (uint32_t)t <= RR[j];
+            const bool c = V[j] && (uint32_t)t <= RR[j];
             const uint64_t b = __builtin_amdgcn_ballot_w64(c);
             if (c) {
               const int32_t Fc = rne_half(t - BASE[j]);
@@ -1052,13 +1052,14 @@ __global__ void __launch_bounds__(256) k_compact_lin(LevelC lv, const CWork<NCH>
 #pragma unroll
       for (int j = 0; j < GJ; j++) {
         if (k0 + 64 * j >= cnt) break;
-        LinS s = load_ent<FAM>(ev[j]);
-        if (k0 + 64 * j + lane >= cnt) s.F[0] = s.F[1] = GV_F_NONE;
+        const LinS s = load_ent<FAM>(ev[j]);
+        const bool valid = k0 + 64 * j + lane < cnt;  // lanes past the item's end pass nothing
         bool p[NCH];
         lin_pass<FAM, NCH>(s, lv, p);
 #pragma unroll
         for (int ch = 0; ch < NCH; ch++) {
           if (!((kmask >> ch) & 1u)) continue;
+          p[ch] = p[ch] && valid;
           const uint64_t b = __builtin_amdgcn_ballot_w64(p[ch]);
           if (p[ch]) out[wpos[ch] + mbcnt64(b)] = store_ent<FAM, EO>(lin_canon_child<FAM>(s, lv, lv.cbits[ch]), fits);
           wpos[ch] += (uint64_t)__popcll(b);

@@ -32,6 +32,7 @@
 #include "gv_device.h"
 #include "gv_kernels.h"
 #include "gv_root.h"
+#include "gv_exact.h"
 
 // Caching device allocator owned by a context.  All library work on a
 // context is ordered on its stream, so a block released after its last use
@@ -202,6 +203,8 @@ struct Setup {
   double epsn[4];
   double ez, ek;  // pose eps'
   bool filter;    // binary32 filter usable
+  bool exact;     // canon_c = +inf: quantize once to 2^-36, no re-canonization
+  double Hmax, R2;  // POSE4DOF data bounds: max |eta'|, max squared horizontal reach
   int64_t n;
 };
 
@@ -230,7 +233,8 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
   P.nsec = S.fam == GV_POSE4DOF ? 4 : 1;
   double c = p->canon_c == 0.0 ? 1.0 : p->canon_c;
   if (!(c > 0.0) || std::isnan(c)) { why = "canon_c must be > 0"; return GV_EINVAL; }
-  if (std::isinf(c)) { why = "exact mode (canon_c = inf) is not available on the device path"; return GV_EINVAL; }
+  S.exact = std::isinf(c);
+  P.exact = S.exact ? 1 : 0;
   int nuser = S.fam == GV_POSE4DOF ? 3 : S.d;
   for (int j = 0; j < nuser; j++) {
     if (!std::isfinite(p->lo[j]) || !std::isfinite(p->hi[j]) || !(p->hi[j] > p->lo[j])) { why = "bad box"; return GV_EINVAL; }
@@ -298,7 +302,14 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
       lv.cbits[dg] = cb;
     }
   }
-  if (S.fam != GV_POSE4DOF) {
+  if (S.fam != GV_POSE4DOF && S.exact) {
+    // exact mode: one 2^-36 lattice, pads = eps rounded up to it
+    for (int q = 0; q < S.d; q++) {
+      P.sf[q] = 0x1p-36;
+      P.inv_sf[q] = 0x1p36;
+      P.xpad[q] = std::ceil((S.epsn[q] + 0.0) / P.sf[q]) * P.sf[q];
+    }
+  } else if (S.fam != GV_POSE4DOF) {
     for (int q = 0; q < S.d; q++) {
       double ep = S.epsn[q] / (c * (double)(Lstar + 1));
       P.sf[q] = p2floor(ep / (double)(S.ell + 1));
@@ -313,7 +324,7 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
         P.lev[m].H[q] = (int32_t)H;
       }
     }
-  } else {
+  } else if (!S.exact) {
     S.ez = S.epsn[2] / (c * (double)(Lstar + 1));
     S.ek = epsk / (c * (double)(Lstar + 1));
   }
@@ -326,6 +337,14 @@ void pose_lattice(Setup& S, double Hmax, double R2, double epsk) {
   int Lxy = std::max(P.L[0], P.L[1]);
   double Rg = std::ldexp(1.0, -Lxy);
   P.Rg2 = Rg * Rg;
+  S.Hmax = Hmax;
+  S.R2 = R2;
+  if (S.exact) {
+    // exact mode: every parameter on the 2^-36 lattice, pads = eps rounded up
+    P.sW = P.sW3 = P.sXi = P.sEta = 0x1p-36;
+    P.padz = std::ceil(S.epsn[2] / P.sW3) * P.sW3;
+    P.padk = std::ceil(epsk / P.sXi) * P.sXi;
+  } else {
   double l1 = (double)(S.ell + 1);
   double Hb = (Hmax > 0x1p-10 ? Hmax : 0x1p-10) * (1.0 + 0x1p-20);
   double Rb = (std::sqrt(R2) + 0x1p-20) * (1.0 + 0x1p-20);
@@ -338,6 +357,7 @@ void pose_lattice(Setup& S, double Hmax, double R2, double epsk) {
   P.sXi = p2floor(S.ek / (l1 * Bk));
   P.padz = std::ceil((S.epsn[2] + S.ez * 0.5) / P.sW3) * P.sW3;
   P.padk = std::ceil((epsk + S.ek * 0.5) / P.sXi) * P.sXi;
+  }
   P.inv_sW = 1.0 / P.sW;
   P.inv_sW3 = 1.0 / P.sW3;
   P.inv_sXi = 1.0 / P.sXi;
@@ -388,6 +408,8 @@ struct ProbRec {
   // serving
   uint64_t ticket = 0;
   bool done = false, canceled = false;
+  std::chrono::steady_clock::time_point t_submit{};
+  double ms_queued = 0.0;  // submission to admission
 };
 
 struct Batch {
@@ -472,6 +494,7 @@ struct Run {
   double wait_ms = 0.0;
   bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
   bool beam = true;                       // progressive chunks until the first leaf level
+  bool root_only = false;                 // build the root entries only (gv_incidence)
   struct EvRec {
     std::pair<hipEvent_t, hipEvent_t> e;
     int kind;        // 0 count, 1 compaction
@@ -794,7 +817,7 @@ void group_batch(Run& X, Batch& b, bool own_ents) {
 bool want_group(const Run& X, const Batch& b) {
   if (X.group_mode < 0 || b.nent < 2) return false;
   if (X.group_mode > 0) return true;
-  if (X.fam == GV_POSE4DOF) return false;
+  if (X.fam == GV_POSE4DOF || X.P0.exact) return false;
   const double avg = (double)b.nent / (double)std::max<uint32_t>(1, b.ncell);
   return avg >= 0.5 * X.lat_bound[b.level];
 }
@@ -843,7 +866,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   // POSE4DOF keeps per-entry pass masks and counts with atomics, per-item
   // survivors child-major; linear families write one row of per-child
   // counts per item (item-major) and repeat the test in the compaction
-  const bool linear = FAM != FAM_POSE4DOF;
+  const bool linear = !fam_masked(FAM);
   uint32_t* itemcnt = nullptr;
   uint32_t* itemw = nullptr;
   if (linear) {
@@ -860,7 +883,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     k_zero3<<<gs_grid(X, std::max(nk, ni)), 256, 0, X.st>>>(ccnt, nk, pa->cnent, nk, itemcnt, ni);
   }
   int cand;
-  const uint64_t tbytes = FAM != FAM_POSE4DOF ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
+  const uint64_t tbytes = linear ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
   const int gpc = grid_pick(X, 0, tbytes, &cand);
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * gpc);
   auto evp = ev_begin(X, 0, cand, tbytes);
@@ -881,6 +904,16 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
       else GV_COUNT_POSE(false, false);
     }
 #undef GV_COUNT_POSE
+  } else if constexpr (fam_exact(FAM)) {
+    if (b.unit)
+      k_count_x<fam_base(FAM), true><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems,
+                                                            (const EntX*)b.ents, (uint8_t*)pa->masks, ccnt, pa->cnent,
+                                                            itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
+    else
+      k_count_x<fam_base(FAM), false><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems,
+                                                             (const EntX*)b.ents, (uint8_t*)pa->masks, ccnt,
+                                                             pa->cnent, itemcnt ? itemcnt : X.dummy,
+                                                             itemcnt ? pa->istride : 0u);
   } else {
 #define GV_COUNT_LIN(U, N) \
   k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, (const E*)b.ents, itemcnt, itemw)
@@ -897,7 +930,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   }
   ev_end(X, evp);
   HIPCHK(hipGetLastError());
-  if constexpr (FAM != FAM_POSE4DOF) {
+  if constexpr (!fam_masked(FAM)) {
     // per-cell counts and per-item offsets from the items' rows
     if (!leaf) pa->itemoff = dalloc<uint64_t>(X, (uint64_t)nch * pa->max_items);
 #define GV_CELL_SCAN(U, N)                                                                                      \
@@ -1029,7 +1062,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   // the first descent, and its incidence test (not the list traffic) dominates.
   // The greedy dive keeps one child per cell and takes them all at once, so
   // their order changes nothing there: parent order, no sort.
-  pa->sorted = !dive && (X.beam || FAM == FAM_POSE4DOF);
+  pa->sorted = !dive && (X.beam || fam_masked(FAM));
   pa->scount = dalloc<uint32_t>(X, nkept);
   if (!pa->sorted) {
     // after the first descent the bounds are strong: keep parent order so
@@ -1155,7 +1188,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     k_chunk_totals<<<1, 64, 0, X.st>>>(keepc, cidx, csize, coff, nr, X.dtot);
   }
   // linear families: the item range the chunk draws from (read with the totals)
-  const bool linear = FAM != FAM_POSE4DOF;
+  const bool linear = !fam_masked(FAM);
   uint32_t* nwork = nullptr;
   if (linear) {
     nwork = dalloc<uint32_t>(X, 1);
@@ -1210,7 +1243,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     auto evp = ev_begin(X, 1, cand, nb.nent * sizeof(EO));
     X.stats.compact_launches++;
     X.stats.compact_bytes += nb.nent * sizeof(EO);
-    if constexpr (FAM == FAM_POSE4DOF) {
+    if constexpr (fam_masked(FAM)) {
       k_compact<FAM, E, EO, M, true><<<grid, 256, 0, X.st>>>(
           lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, (const E*)pa->ents,
           (const M*)pa->masks, pa->rank_of, r0, r1, keepc, coff, (EO*)nb.ents, X.dovf);
@@ -1371,7 +1404,7 @@ gv_status prepare_problem(ProbRec* pr) {
 // problems can share an epoch when their level structure is identical
 bool same_structure(const ProbRec* a, const ProbRec* b) {
   const ProbC &A = a->S.P, &B = b->S.P;
-  if (a->S.fam != b->S.fam || A.Lstar != B.Lstar || A.B != B.B) return false;
+  if (a->S.fam != b->S.fam || A.Lstar != B.Lstar || A.B != B.B || A.exact != B.exact) return false;
   if (a->p.precision != b->p.precision || a->p.group != b->p.group) return false;
   for (int j = 0; j < 4; j++)
     if (A.L[j] != B.L[j]) return false;
@@ -1703,7 +1736,38 @@ void build_linear(Run& X) {
     }
   }
   X.root = root;
-  start_search<FAM, E, uint8_t>(X);
+  if (!X.root_only) start_search<FAM, E, uint8_t>(X);
+}
+
+// exact mode of a linear family: root quantization, then the search over
+// unchanged surfaces (pass masks, copying compaction)
+template <int BF>
+void build_exact(Run& X) {
+  const uint32_t np = (uint32_t)X.probs.size();
+  EntX* root = dalloc<EntX>(X, X.Ntot);
+  int* dbad = dalloc<int>(X, np);
+  HIPCHK(hipMemsetAsync(dbad, 0, np * sizeof(int), X.st));
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    if (pr->n > 0)
+      k_root_x<BF><<<gs_grid(X, pr->n), 256, 0, X.st>>>(X.dP + p, pr->cols, pr->n, root + X.ooff[p], dbad + p);
+  }
+  std::vector<int> bad(np);
+  HIPCHK(hipMemcpyAsync(bad.data(), dbad, np * sizeof(int), hipMemcpyDeviceToHost, X.st));
+  host_wait(X);
+  dfree(X, dbad);
+  for (uint32_t p = 0; p < np; p++) {
+    ProbRec* pr = X.probs[p];
+    if (bad[p] & 1) {
+      pr->st = GV_EINVAL;
+      pr->err = "non-finite observation or zero ray direction";
+    } else if (bad[p] & 2) {
+      pr->st = GV_ERANGE;
+      pr->err = "surface parameters beyond the exact-mode range";
+    }
+  }
+  X.root = root;
+  if (!X.root_only) start_search<BF + 4, EntX, uint8_t>(X);
 }
 
 template <typename E>
@@ -1767,11 +1831,11 @@ bool build_pose(Run& X) {
   if (all32) {
     dfree(X, e64);
     X.root = e32;
-    start_search<FAM_POSE4DOF, EntQ32, uint16_t>(X);
+    if (!X.root_only) start_search<FAM_POSE4DOF, EntQ32, uint16_t>(X);
   } else {
     dfree(X, e32);
     X.root = e64;
-    start_search<FAM_POSE4DOF, EntQ64, uint16_t>(X);
+    if (!X.root_only) start_search<FAM_POSE4DOF, EntQ64, uint16_t>(X);
   }
   return all32;
 }
@@ -1815,7 +1879,13 @@ void epoch_finish(Run& X) {
     int* dbad = dalloc<int>(X, 1);
     HIPCHK(hipMemsetAsync(dbad, 0, sizeof(int), X.st));
     const unsigned gg = gs_grid(X, X.Ntot);
-    switch (X.fam) {
+    if (X.P0.exact && X.fam != GV_POSE4DOF) {
+      switch (X.fam) {
+        case GV_LINE2D: k_replay_x<FAM_LINE2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+        case GV_PLANE3D: k_replay_x<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+        default: k_replay_x<FAM_RAY3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+      }
+    } else switch (X.fam) {
       case GV_LINE2D: k_replay_lin<FAM_LINE2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
       case GV_PLANE3D: k_replay_lin<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
       case GV_RAY3D: k_replay_lin<FAM_RAY3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
@@ -1922,6 +1992,13 @@ void epoch_release(Run& X) {
 // build an epoch and return its step function
 std::function<bool(Run&)> epoch_build(Run& X) {
   epoch_begin(X);
+  if (X.P0.exact && X.fam != GV_POSE4DOF) {
+    switch (X.fam) {
+      case GV_LINE2D: build_exact<FAM_LINE2D>(X); return epoch_step<FAM_XLINE2D, EntX, uint8_t>;
+      case GV_PLANE3D: build_exact<FAM_PLANE3D>(X); return epoch_step<FAM_XPLANE3D, EntX, uint8_t>;
+      default: build_exact<FAM_RAY3D>(X); return epoch_step<FAM_XRAY3D, EntX, uint8_t>;
+    }
+  }
   switch (X.fam) {
     case GV_LINE2D: build_linear<FAM_LINE2D>(X); return epoch_step<FAM_LINE2D, EntL2, uint8_t>;
     case GV_PLANE3D: build_linear<FAM_PLANE3D>(X); return epoch_step<FAM_PLANE3D, EntP3, uint8_t>;
@@ -1949,17 +2026,47 @@ void fill_result(const ProbRec* pr, gv_result* r) {
     if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
     r->point[3] = yaw;
   }
+  // Certified bound per axis (the approximation guarantee of Sec. 3.2):
+  // on an axis a surface depends on, every reported inlier's range over the
+  // leaf's parameter box comes within bound[q] of the leaf's q-interval (the
+  // canonical surface of the last level passes within its pad, and differs
+  // from the original by at most the canonization allowance); on a pure
+  // parameter axis, half the leaf side (the distance from the returned point
+  // to any point of the leaf).
+  const double h37 = 0x1p-37;
   for (int j = 0; j < 4; j++) r->bound[j] = 0.0;
-  for (int j = 0; j < pr->S.d; j++) {
-    if (pr->S.fam == GV_POSE4DOF) {
-      r->bound[j] = j == 2 ? (P.padz + pr->S.ez * 0.5) * P.E[2]
-                           : (j == 3 ? P.padk + pr->S.ek * 0.5 : 0.5 * std::ldexp(P.E[j], -P.L[j]));
+  for (int j = 0; j < pr->S.d; j++) r->bound[j] = 0.5 * std::ldexp(P.E[j], -P.L[j]);
+  if (pr->S.fam == GV_POSE4DOF) {
+    if (pr->S.exact) {
+      // 2^-37 per parameter: z moves by at most (1 + R + 2 H) 2^-37, kappa
+      // by (1 + k^2)(1 + 2/R_g) 2^-37 with |k| <= 1 + pad
+      const double R = std::sqrt(pr->S.R2), kk = 1.0 + P.padk;
+      r->bound[2] = (P.padz + (1.0 + R + 2.0 * pr->S.Hmax) * h37) * P.E[2];
+      r->bound[3] = P.padk + (1.0 + kk * kk) * (1.0 + 2.0 / std::sqrt(P.Rg2)) * h37;
     } else {
-      const double Em = (double)(P.Lstar * (pr->S.ell + 1)) * P.sf[j] * 0.5;
-      r->bound[j] = (pr->S.epsn[j] + 2.0 * Em + P.sf[j]) * P.E[j];
+      r->bound[2] = (P.padz + pr->S.ez * 0.5) * P.E[2];
+      // kappa units; also a yaw bound in radians, as |d yaw / d kappa| <= 1.
+      // Holds where the leaf is farther than the apex guard from the match.
+      r->bound[3] = P.padk + pr->S.ek * 0.5;
+    }
+  } else {
+    const int npar = pr->S.fam == GV_PLANE3D ? 2 : 1;
+    for (int q = 0; q < pr->S.d; q++) {
+      const bool dep = pr->S.fam == GV_RAY3D || q == pr->S.d - 1;
+      if (!dep) continue;
+      double b;
+      if (pr->S.exact) {
+        b = P.xpad[q] + (double)(npar + 1) * h37;
+      } else {
+        const int m = P.Lstar - 1;
+        const double Em = (double)((m + 1) * (pr->S.ell + 1)) * P.sf[q] * 0.5;
+        b = 0.5 * (double)P.lev[m].padu[q] * P.sf[q] + Em;
+      }
+      r->bound[q] = b * P.E[q];
     }
   }
   r->stats = pr->stats;
+  r->stats.ms_queued = pr->ms_queued;
   r->n_inliers = pr->inliers.size();
 }
 
@@ -2043,6 +2150,8 @@ void lane_main(Lane* L) {
             const bool small = admit.empty() || nsum + (uint64_t)pr->n <= ctx->batch_n;
             if (!small || !fits) break;
             if (same_structure(first, pr)) {
+              pr->ms_queued =
+                  std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - pr->t_submit).count();
               admit.push_back(pr);
               nsum += (uint64_t)pr->n;
               ctx->inflight += pr->est_bytes;
@@ -2077,9 +2186,16 @@ void lane_main(Lane* L) {
     L->err.clear();
     try {
       auto step = epoch_build(X);
+      bool dropped = false;
       while (step(X)) {
+        // a running epoch stops at its next expansion once every problem in
+        // it has been cancelled
+        std::lock_guard<std::mutex> g(ctx->qmu);
+        dropped = std::all_of(admit.begin(), admit.end(), [](const ProbRec* pr) { return pr->canceled; });
+        if (dropped) break;
       }
-      epoch_finish(X);
+      if (dropped) fail_all(X, GV_ECANCELED);
+      else epoch_finish(X);
     } catch (DevErr& e) {
       fail_all(X, e.st);
     }
@@ -2277,6 +2393,7 @@ gv_status gv_submit(gv_ctx* ctx, const gv_problem* p, uint64_t* ticket) {
     }
   }
   std::lock_guard<std::mutex> g(ctx->qmu);
+  pr->t_submit = std::chrono::steady_clock::now();
   pr->ticket = ctx->next_ticket++;
   ctx->tickets[pr->ticket] = pr;
   ctx->queue.push_back(pr);
@@ -2340,6 +2457,123 @@ gv_status gv_cancel(gv_ctx* ctx, uint64_t ticket) {
     pr->done = true;
     ctx->cv_done.notify_all();
   }
+  return GV_OK;
+}
+
+gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t sector, const int32_t* coords,
+                       uint32_t* masks_out, gv_stats* stats_out) {
+  if (!ctx || !p || !coords || (!masks_out && p->n > 0)) return GV_EINVAL;
+  ProbRec pr;
+  pr.p = *p;
+  gv_status st = prepare_problem(&pr);
+  if (st != GV_OK) {
+    set_err(ctx, pr.err);
+    return st;
+  }
+  const ProbC& P = pr.S.P;
+  if (level < 0 || level >= P.Lstar || sector < 0 || sector >= P.nsec) {
+    set_err(ctx, "level or sector out of range");
+    return GV_EINVAL;
+  }
+  for (int j = 0; j < 4; j++) {
+    const int bits = j < P.d ? std::min(level, P.L[j]) : 0;
+    if (coords[j] < 0 || (int64_t)coords[j] >= (1ll << bits)) {
+      set_err(ctx, "cell coordinates out of range");
+      return GV_EINVAL;
+    }
+  }
+  // the path's child digits: split axes' bits in axis order, MSB first
+  PathC path{};
+  path.sector = sector;
+  for (int k = 0; k < level; k++) {
+    uint32_t dg = 0;
+    for (int j = 0; j < P.d; j++)
+      if (k < P.L[j]) dg = (dg << 1) | (uint32_t)((coords[j] >> (std::min(level, P.L[j]) - 1 - k)) & 1);
+    path.digit[k] = (uint8_t)dg;
+  }
+  Cell C{};
+  for (int j = 0; j < 4; j++) C.c[j] = coords[j];
+  C.sector = (uint32_t)sector;
+  const uint32_t nch = 1u << P.lev[level].abits;
+  gv_stats stats{};
+  stats.levels = (uint32_t)P.Lstar;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->err.clear();
+    Run X;
+    bind_ctx(X, ctx);
+    X.probs = {&pr};
+    X.root_only = true;
+    try {
+      epoch_begin(X);
+      bool f32 = false;
+      if (pr.S.fam == GV_POSE4DOF) {
+        f32 = build_pose(X);
+      } else if (pr.S.exact) {
+        switch (pr.S.fam) {
+          case GV_LINE2D: build_exact<FAM_LINE2D>(X); break;
+          case GV_PLANE3D: build_exact<FAM_PLANE3D>(X); break;
+          default: build_exact<FAM_RAY3D>(X); break;
+        }
+      } else {
+        switch (pr.S.fam) {
+          case GV_LINE2D: build_linear<FAM_LINE2D>(X); break;
+          case GV_PLANE3D: build_linear<FAM_PLANE3D>(X); break;
+          default: build_linear<FAM_RAY3D>(X); break;
+        }
+      }
+      if (pr.st == GV_OK && pr.n > 0) {
+        uint32_t* dm = dalloc<uint32_t>(X, (uint64_t)pr.n);
+        const unsigned gg = gs_grid(X, (uint64_t)pr.n);
+        if (pr.S.fam == GV_POSE4DOF) {
+          if (f32)
+            k_incidence_pose<EntQ32><<<gg, 256, 0, X.st>>>(X.dP, (const EntQ32*)X.root, pr.n, X.m64, X.Ntot, C, level,
+                                                          dm, X.drecheck);
+          else
+            k_incidence_pose<EntQ64><<<gg, 256, 0, X.st>>>(X.dP, (const EntQ64*)X.root, pr.n, X.m64, X.Ntot, C, level,
+                                                          dm, X.drecheck);
+        } else if (pr.S.exact) {
+          switch (pr.S.fam) {
+            case GV_LINE2D: k_incidence_x<FAM_LINE2D><<<gg, 256, 0, X.st>>>(X.dP, (const EntX*)X.root, pr.n, C, level, dm); break;
+            case GV_PLANE3D: k_incidence_x<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, (const EntX*)X.root, pr.n, C, level, dm); break;
+            default: k_incidence_x<FAM_RAY3D><<<gg, 256, 0, X.st>>>(X.dP, (const EntX*)X.root, pr.n, C, level, dm); break;
+          }
+        } else {
+#define GV_INC(F, N) \
+  k_incidence_lin<F, typename EntOf<F>::T, N><<<gg, 256, 0, X.st>>>(X.dP, (const typename EntOf<F>::T*)X.root, pr.n, path, level, dm)
+          switch (pr.S.fam * 16 + (int)nch) {
+            case GV_LINE2D * 16 + 2: GV_INC(FAM_LINE2D, 2); break;
+            case GV_LINE2D * 16 + 4: GV_INC(FAM_LINE2D, 4); break;
+            case GV_PLANE3D * 16 + 2: GV_INC(FAM_PLANE3D, 2); break;
+            case GV_PLANE3D * 16 + 4: GV_INC(FAM_PLANE3D, 4); break;
+            case GV_PLANE3D * 16 + 8: GV_INC(FAM_PLANE3D, 8); break;
+            case GV_RAY3D * 16 + 2: GV_INC(FAM_RAY3D, 2); break;
+            case GV_RAY3D * 16 + 4: GV_INC(FAM_RAY3D, 4); break;
+            case GV_RAY3D * 16 + 8: GV_INC(FAM_RAY3D, 8); break;
+            default: throw DevErr{GV_EINVAL};
+          }
+#undef GV_INC
+        }
+        HIPCHK(hipGetLastError());
+        unsigned long long rech = 0;
+        HIPCHK(hipMemcpyAsync(masks_out, dm, (size_t)pr.n * sizeof(uint32_t), hipMemcpyDeviceToHost, X.st));
+        HIPCHK(hipMemcpyAsync(&rech, X.drecheck, 8, hipMemcpyDeviceToHost, X.st));
+        host_wait(X);
+        dfree(X, dm);
+        stats.tests = (uint64_t)pr.n * nch;
+        stats.fp64_rechecks = rech;
+      }
+    } catch (DevErr& e) {
+      fail_all(X, e.st);
+    }
+    epoch_release(X);
+  }
+  if (stats_out) *stats_out = stats;
+  if (pr.st != GV_OK) {
+    set_err(ctx, pr.err.empty() ? ctx->err : pr.err);
+    return pr.st;
+  }
+  set_err(ctx, "");
   return GV_OK;
 }
 

@@ -23,7 +23,7 @@ FP64_PLAIN, FP32_FILTER = 0, 1
 STATUS = {0: "GV_OK", -1: "GV_EINVAL", -2: "GV_ENOMEM", -3: "GV_ETOOBIG", -4: "GV_EBUFSZ",
           -5: "GV_EAGAIN", -6: "GV_ETIMEDOUT", -7: "GV_ECANCELED", -8: "GV_EDEVICE", -9: "GV_ERANGE"}
 
-EXPORTS = ["gv_create", "gv_destroy", "gv_solve", "gv_parametrize", "gv_submit", "gv_poll", "gv_cancel",
+EXPORTS = ["gv_create", "gv_destroy", "gv_solve", "gv_parametrize", "gv_incidence", "gv_submit", "gv_poll", "gv_cancel",
            "gv_status_str", "gv_last_error"]
 
 
@@ -47,7 +47,8 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_kernels", ctypes.c_double),
                 ("test_ms", ctypes.c_double), ("compact_ms", ctypes.c_double),
                 ("test_launches", ctypes.c_uint64), ("compact_launches", ctypes.c_uint64),
-                ("test_bytes", ctypes.c_uint64), ("compact_bytes", ctypes.c_uint64)]
+                ("test_bytes", ctypes.c_uint64), ("compact_bytes", ctypes.c_uint64),
+                ("ms_queued", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -79,6 +80,8 @@ def lib():
         L.gv_solve.argtypes = [ctypes.c_void_p, P(Problem), P(Result)]
         L.gv_parametrize.argtypes = [ctypes.c_void_p, P(Problem), P(ctypes.c_double), P(ctypes.c_double),
                                      P(ctypes.c_int32)]
+        L.gv_incidence.argtypes = [ctypes.c_void_p, P(Problem), ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32),
+                                   P(ctypes.c_uint32), P(Stats)]
         L.gv_submit.argtypes = [ctypes.c_void_p, P(Problem), P(ctypes.c_uint64)]
         L.gv_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(Result), ctypes.c_int]
         L.gv_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
@@ -86,7 +89,8 @@ def lib():
         L.gv_status_str.restype = ctypes.c_char_p
         L.gv_last_error.argtypes = [ctypes.c_void_p]
         L.gv_last_error.restype = ctypes.c_char_p
-        for name in ("gv_create", "gv_destroy", "gv_solve", "gv_parametrize", "gv_submit", "gv_poll", "gv_cancel"):
+        for name in ("gv_create", "gv_destroy", "gv_solve", "gv_parametrize", "gv_incidence", "gv_submit", "gv_poll",
+                     "gv_cancel"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -179,6 +183,19 @@ class Context:
                       "compact_bytes": s.compact_bytes},
         }
 
+    def incidence(self, family, cols, lo, hi, eps, level, sector, coords, canon_c=0.0, precision=FP32_FILTER):
+        """Pass masks of every surface against the children of one cell
+        (gv_incidence); returns (masks, tests, fp64 rechecks)."""
+        p, keep = make_problem(family, cols, lo, hi, eps, canon_c, precision)
+        cc = (ctypes.c_int32 * 4)(*[int(c) for c in list(coords) + [0] * (4 - len(coords))])
+        masks = np.zeros(max(1, p.n), dtype=np.uint32)
+        st_out = Stats()
+        st = lib().gv_incidence(self._h, ctypes.byref(p), int(level), int(sector), cc,
+                                masks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(st_out))
+        if st != 0:
+            raise GvError(st, self.last_error())
+        return masks[: p.n], int(st_out.tests), int(st_out.fp64_rechecks)
+
     def parametrize(self, family, cols, lo, hi, eps):
         p, keep = make_problem(family, cols, lo, hi, eps)
         n = p.n
@@ -261,7 +278,8 @@ def _result_dict(r, buf):
     return {"count": int(r.count), "leaf_index": int(r.leaf_index), "sector": int(r.sector),
             "leaf_coords": list(r.leaf_coords), "point": list(r.point), "n_inliers": int(r.n_inliers),
             "inliers": buf[: r.n_inliers].copy(), "bound": list(r.bound),
-            "stats": {"tests": s.tests, "fp64_rechecks": s.fp64_rechecks, "ms_total": s.ms_total}}
+            "stats": {"tests": s.tests, "fp64_rechecks": s.fp64_rechecks, "ms_total": s.ms_total,
+                      "ms_queued": s.ms_queued}}
 
 
 def submit(ctx, family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, group=0):
