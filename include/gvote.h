@@ -183,6 +183,18 @@ gv_status gv_destroy(gv_ctx *ctx);
  * serialized; they may run while submitted problems are served. */
 gv_status gv_solve(gv_ctx *ctx, const gv_problem *p, gv_result *r);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): gv_solve with every
+ * device buffer of the search taken from one region of 256 MiB that the
+ * library holds, as static device memory, on each GPU it runs on until the
+ * process ends; no device or pinned allocation, no event, no tuning sample.
+ * Results equal gv_solve's.  At most 2^19 observations (GV_ETOOBIG beyond,
+ * and when a search outgrows the region).  Calls on one device share the
+ * region, which keeps the last call's contents, so they run one after the
+ * other (a per-device lock); overlapping calls on one GPU queue behind each
+ * other.  Host columns are copied into the region. */
+gv_status gv_solve_noalloc(gv_ctx *ctx, const gv_problem *p, gv_result *r);
+
 /* Front end only (Eq. 1-3 and the posing surface): writes the normalized
  * parameters, row-major, t_out n x 4 and f_out n x 2 (host buffers), and
  * tag_out n (RAY3D parameter axis, else 0; may be NULL).  Layout per family:

@@ -42,6 +42,56 @@ struct DevCache {
   std::multimap<size_t, void*> free_blocks;
   std::map<void*, size_t> live;
   uint64_t cached = 0, in_use = 0, peak = 0;
+  // Arena mode: every block is carved from one fixed device region
+  // [arena, arena + arena_size) (first fit, neighbours coalesce on release);
+  // nothing is ever allocated from or returned to the runtime.
+  char* arena = nullptr;
+  size_t arena_size = 0;
+  std::map<size_t, size_t> afree;  // offset -> length of the free runs
+  void arena_reset(char* base, size_t size) {
+    arena = base;
+    arena_size = size;
+    afree.clear();
+    afree[0] = size;
+    live.clear();
+    in_use = peak = 0;
+  }
+  void* arena_get(size_t bytes, std::string& err) {
+    const size_t r = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    for (auto it = afree.begin(); it != afree.end(); ++it) {
+      if (it->second < r) continue;
+      const size_t off = it->first, len = it->second;
+      afree.erase(it);
+      if (len > r) afree[off + r] = len - r;
+      void* p = arena + off;
+      live[p] = r;
+      in_use += r;
+      peak = std::max(peak, in_use);
+      return p;
+    }
+    err = "the search outgrew the library's scratch region";
+    return nullptr;
+  }
+  void arena_put(void* p) {
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    size_t off = (size_t)((char*)p - arena), len = it->second;
+    in_use -= len;
+    live.erase(it);
+    auto nx = afree.lower_bound(off);
+    if (nx != afree.end() && off + len == nx->first) {
+      len += nx->second;
+      nx = afree.erase(nx);
+    }
+    if (nx != afree.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += len;
+        return;
+      }
+    }
+    afree[off] = len;
+  }
 
   static size_t round(size_t b) {
     if (b <= 4096) return 4096;
@@ -62,6 +112,7 @@ struct DevCache {
     return p;
   }
   void* get(size_t bytes, hipStream_t st, std::string& err) {
+    if (arena) return arena_get(bytes, err);
     const size_t r = round(bytes);
     auto it = free_blocks.lower_bound(r);
     if (it != free_blocks.end() && it->first <= r + slack(r)) return take(it);
@@ -86,7 +137,7 @@ struct DevCache {
   }
   // free the largest cached blocks until at most target bytes stay cached
   void release_to(uint64_t target, hipStream_t st) {
-    if (cached <= target) return;
+    if (arena || cached <= target) return;
     (void)hipStreamSynchronize(st);
     while (cached > target && !free_blocks.empty()) {
       auto it = std::prev(free_blocks.end());
@@ -96,6 +147,10 @@ struct DevCache {
     }
   }
   void put(void* p) {
+    if (arena) {
+      arena_put(p);
+      return;
+    }
     auto it = live.find(p);
     if (it == live.end()) return;
     free_blocks.emplace(it->second, p);
@@ -104,6 +159,7 @@ struct DevCache {
     live.erase(it);
   }
   void trim(hipStream_t st) {
+    if (arena) return;
     (void)hipStreamSynchronize(st);
     for (auto& kv : free_blocks) (void)hipFree(kv.second);
     free_blocks.clear();
@@ -115,6 +171,27 @@ namespace gvi {
 struct ProbRec;
 struct Lane;
 }
+
+// Scratch region of the allocation-free solve (gv_solve_noalloc): device
+// memory of a fixed size that the library holds on every GPU it runs on
+// until the process ends.  In host code this name is not a device address;
+// the address comes from hipGetSymbolAddress, once per device, when a context
+// is created there, and only that address is used afterwards.
+constexpr size_t kScratchBytes = 256ull << 20;
+constexpr int64_t kNoAllocMaxN = 1ll << 19;  // observations per allocation-free solve
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Per device: the scratch address, and the arena over it (calls on one
+// device take the slot's lock, so they run one after the other).
+struct ScratchSlot {
+  std::mutex mu;
+  bool init = false;
+  void* ptr = nullptr;
+  std::string err;
+  DevCache arena;
+};
+constexpr int kMaxDevices = 64;
+static ScratchSlot g_scratch[kMaxDevices];
 
 // Candidate grids of the item-looping kernels, in blocks of four waves per
 // CU.  A slot tries them in turn on its large launches and keeps the one with
@@ -495,6 +572,7 @@ struct Run {
   bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
   bool beam = true;                       // progressive chunks until the first leaf level
   bool root_only = false;                 // build the root entries only (gv_incidence)
+  bool fixed = false;                     // no tuning samples, no events (allocation-free solve)
   struct EvRec {
     std::pair<hipEvent_t, hipEvent_t> e;
     int kind;        // 0 count, 1 compaction
@@ -726,6 +804,11 @@ void tune_sample(Run& X, int kind, int cand, double ms, uint64_t units) {
 int grid_pick(Run& X, int kind, uint64_t units, int* cand) {
   *cand = -1;
   if (X.grid_env[kind]) return X.grid_env[kind];
+  if (X.fixed) {
+    std::lock_guard<std::mutex> g(X.ctx->tmu);
+    const int ch = X.ctx->tune[X.P0.fam][kind].chosen;
+    return ch ? ch : kGridDefault;
+  }
   gv_ctx* c = X.ctx;
   if (!c->autotune) return kGridDefault;
   std::lock_guard<std::mutex> g(c->tmu);
@@ -740,7 +823,7 @@ int grid_pick(Run& X, int kind, uint64_t units, int* cand) {
 std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind, int cand = -1, uint64_t units = 0) {
   gv_ctx* c = X.ctx;
   std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
-  if (!c->kernel_timing && cand < 0) return p;
+  if ((!c->kernel_timing && cand < 0) || X.fixed) return p;
   std::vector<hipEvent_t>& pool = *X.ev_pool;
   while (pool.size() < 2 * (X.ev_used + 1)) {
     hipEvent_t e;
@@ -1431,7 +1514,7 @@ void epoch_begin(Run& X) {
   // built, but only the deepest few are large (the lists grow with depth
   // until pruning bites): measured peaks are about twice one chunk, and a
   // fifth of the budget per chunk leaves room for four large levels
-  X.chunk_bytes = std::max<uint64_t>(64ull << 20, X.budget / 5);
+  X.chunk_bytes = std::max<uint64_t>(X.fixed ? (4ull << 20) : (64ull << 20), X.budget / 5);
   if (const char* cb = std::getenv("GV_CHUNK_BYTES")) X.chunk_bytes = std::max<uint64_t>(4096, std::strtoull(cb, nullptr, 10));
   if (const char* e = std::getenv("GV_GRID_COUNT")) X.grid_env[0] = std::max(1, std::min(64, atoi(e)));
   if (const char* e = std::getenv("GV_GRID_COMPACT")) X.grid_env[1] = std::max(1, std::min(64, atoi(e)));
@@ -2288,6 +2371,22 @@ gv_status gv_create(gv_ctx** out, const gv_ctx_config* cfg) {
       if (ch == ' ') ch = '_';
   }
   if (c->arch.empty()) c->arch = "unknown";
+  if (c->device >= 0 && c->device < kMaxDevices) {
+    // the scratch region's address on this device (device current)
+    ScratchSlot& S = g_scratch[c->device];
+    std::lock_guard<std::mutex> g(S.mu);
+    if (!S.init) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e == hipSuccess && ptr) {
+        S.ptr = ptr;
+      } else {
+        (void)hipGetLastError();
+        S.err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      }
+      S.init = true;
+    }
+  }
   if (cfg && cfg->autotune_cache) c->tune_path = cfg->autotune_cache;
   if (const char* e = std::getenv("GV_AUTOTUNE")) c->autotune = atoi(e) != 0;
   if (const char* e = std::getenv("GV_TUNE_MIN_BYTES")) c->tune_min = std::strtoull(e, nullptr, 10);
@@ -2359,6 +2458,59 @@ gv_status gv_solve(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
     // bounded cache: many problems of different sizes would otherwise fill
     // the device with idle blocks, and then free them all at once
     if (ctx->cache.cached > ctx->budget / 2) ctx->cache.release_to(ctx->budget / 4, ctx->stream);
+  }
+  if (pr.st != GV_OK) {
+    set_err(ctx, pr.err.empty() ? ctx->err : pr.err);
+    return pr.st;
+  }
+  set_err(ctx, "");
+  return deliver(&pr, r);
+}
+
+gv_status gv_solve_noalloc(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
+  if (!ctx || !p || !r) return GV_EINVAL;
+  std::memset(&r->stats, 0, sizeof(r->stats));
+  if (ctx->device < 0 || ctx->device >= kMaxDevices) return GV_EINVAL;
+  ProbRec pr;
+  pr.p = *p;
+  gv_status st = prepare_problem(&pr);
+  if (st != GV_OK) {
+    set_err(ctx, pr.err);
+    return st;
+  }
+  if (pr.n > kNoAllocMaxN) {
+    set_err(ctx, "more observations than the allocation-free solve takes (2^19)");
+    return GV_ETOOBIG;
+  }
+  ScratchSlot& S = g_scratch[ctx->device];
+  std::lock_guard<std::mutex> gs(S.mu);
+  if (!S.ptr) {
+    set_err(ctx, S.err.empty() ? "scratch region unavailable" : S.err);
+    return GV_EDEVICE;
+  }
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->err.clear();
+    // a fresh free list over the whole region: blocks hold the previous
+    // call's contents, and every buffer the search reads is written (or
+    // cleared) before it is read, as with reused blocks of the caching
+    // allocator
+    S.arena.arena_reset((char*)S.ptr, kScratchBytes);
+    Run X;
+    bind_ctx(X, ctx);
+    X.cache = &S.arena;
+    X.fixed = true;
+    X.budget = kScratchBytes / 2;
+    X.probs = {&pr};
+    try {
+      auto step = epoch_build(X);
+      while (step(X)) {
+      }
+      epoch_finish(X);
+    } catch (DevErr& e) {
+      fail_all(X, e.st == GV_ENOMEM ? GV_ETOOBIG : e.st);
+    }
+    epoch_release(X);
   }
   if (pr.st != GV_OK) {
     set_err(ctx, pr.err.empty() ? ctx->err : pr.err);

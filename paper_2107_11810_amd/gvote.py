@@ -23,7 +23,8 @@ FP64_PLAIN, FP32_FILTER = 0, 1
 STATUS = {0: "GV_OK", -1: "GV_EINVAL", -2: "GV_ENOMEM", -3: "GV_ETOOBIG", -4: "GV_EBUFSZ",
           -5: "GV_EAGAIN", -6: "GV_ETIMEDOUT", -7: "GV_ECANCELED", -8: "GV_EDEVICE", -9: "GV_ERANGE"}
 
-EXPORTS = ["gv_create", "gv_destroy", "gv_solve", "gv_parametrize", "gv_incidence", "gv_submit", "gv_poll", "gv_cancel",
+EXPORTS = ["gv_create", "gv_destroy", "gv_solve", "gv_solve_noalloc", "gv_parametrize", "gv_incidence", "gv_submit",
+           "gv_poll", "gv_cancel",
            "gv_status_str", "gv_last_error"]
 
 
@@ -78,6 +79,7 @@ def lib():
         L.gv_create.argtypes = [P(ctypes.c_void_p), P(CtxConfig)]
         L.gv_destroy.argtypes = [ctypes.c_void_p]
         L.gv_solve.argtypes = [ctypes.c_void_p, P(Problem), P(Result)]
+        L.gv_solve_noalloc.argtypes = [ctypes.c_void_p, P(Problem), P(Result)]
         L.gv_parametrize.argtypes = [ctypes.c_void_p, P(Problem), P(ctypes.c_double), P(ctypes.c_double),
                                      P(ctypes.c_int32)]
         L.gv_incidence.argtypes = [ctypes.c_void_p, P(Problem), ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32),
@@ -89,8 +91,8 @@ def lib():
         L.gv_status_str.restype = ctypes.c_char_p
         L.gv_last_error.argtypes = [ctypes.c_void_p]
         L.gv_last_error.restype = ctypes.c_char_p
-        for name in ("gv_create", "gv_destroy", "gv_solve", "gv_parametrize", "gv_incidence", "gv_submit", "gv_poll",
-                     "gv_cancel"):
+        for name in ("gv_create", "gv_destroy", "gv_solve", "gv_solve_noalloc", "gv_parametrize", "gv_incidence",
+                     "gv_submit", "gv_poll", "gv_cancel"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -160,14 +162,17 @@ class Context:
     def last_error(self):
         return lib().gv_last_error(self._h).decode()
 
-    def solve(self, family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, cap=None, group=0):
+    def solve(self, family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, cap=None, group=0,
+              noalloc=False):
+        """gv_solve (or gv_solve_noalloc: no allocation, fixed scratch)."""
         p, keep = make_problem(family, cols, lo, hi, eps, canon_c, precision, group)
         cap = p.n if cap is None else cap
         buf = np.zeros(max(1, cap), dtype=np.int64)
         r = Result()
         r.inliers = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         r.inliers_cap = cap
-        st = lib().gv_solve(self._h, ctypes.byref(p), ctypes.byref(r))
+        fn = lib().gv_solve_noalloc if noalloc else lib().gv_solve
+        st = fn(self._h, ctypes.byref(p), ctypes.byref(r))
         if st != 0:
             raise GvError(st, self.last_error())
         s = r.stats
