@@ -48,6 +48,8 @@ class _Problem(ctypes.Structure):
         ("no_dive", ctypes.c_int),
         ("test_budget", ctypes.c_uint64),
         ("threads", ctypes.c_int),
+        ("has_seed", ctypes.c_int),
+        ("seed_leaf", ctypes.c_uint64),
     ]
 
 
@@ -113,7 +115,7 @@ class Problem:
     """A voting problem: observation columns (SoA), domain box, per-axis eps."""
 
     def __init__(self, family, cols, lo, hi, eps, canon_c=0.0, no_prune=False, no_group=False,
-                 no_dive=False, test_budget=0, threads=1):
+                 no_dive=False, test_budget=0, threads=1, seed_leaf=None):
         self.family = FAMILIES[family] if isinstance(family, str) else int(family)
         self.cols = [np.ascontiguousarray(np.asarray(c, dtype=np.float64)) for c in cols]
         if len(self.cols) != NCOLS[self.family]:
@@ -126,6 +128,7 @@ class Problem:
         self.no_prune, self.no_group, self.no_dive = no_prune, no_group, no_dive
         self.test_budget = int(test_budget)
         self.threads = int(threads)
+        self.seed_leaf = seed_leaf
 
     def _c(self):
         p = _Problem()
@@ -139,6 +142,8 @@ class Problem:
         p.no_prune, p.no_group, p.no_dive = int(self.no_prune), int(self.no_group), int(self.no_dive)
         p.test_budget = self.test_budget
         p.threads = self.threads
+        p.has_seed = 0 if self.seed_leaf is None else 1
+        p.seed_leaf = 0 if self.seed_leaf is None else int(self.seed_leaf)
         return p
 
 

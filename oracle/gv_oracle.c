@@ -802,6 +802,13 @@ int or_solve(const or_problem *p, or_result *res, int64_t *inliers, int64_t cap)
   n = group(&C, S, n);
   int nsec = C.fam == OR_POSE4DOF ? 4 : 1;
   C.best = 0;
+  if (p->has_seed) {
+    /* a leaf named by the caller: its count by replay is achieved */
+    uint64_t cnt;
+    int64_t ninl;
+    st = replay_inliers(&C, p->seed_leaf, &cnt, NULL, 0, &ninl);
+    if (!st) C.best = key_of(&C, cnt, p->seed_leaf);
+  }
   if (!p->no_dive)
     for (int s = 0; s < nsec && !st; s++) st = dive(&C, s, S, n);
   if (!st && p->threads > 1) {

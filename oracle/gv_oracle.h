@@ -44,6 +44,10 @@ typedef struct {
   uint64_t test_budget;  /* 0: unlimited; else stop with OR_EBUDGET */
   int threads;           /* > 1: search disjoint subtrees on that many
                             threads sharing the best key (same result) */
+  int has_seed;          /* 1: seed_leaf's achieved key (its count by
+                            replay) starts the best key; any achieved leaf
+                            key is a valid bound, so the result is the same */
+  uint64_t seed_leaf;
 } or_problem;
 
 typedef struct {

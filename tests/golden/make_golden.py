@@ -14,6 +14,7 @@ that a change of the generator is detected.
 import argparse
 import hashlib
 import json
+import math
 import os
 import platform
 import sys
@@ -40,8 +41,29 @@ def inliers_sha(inl):
     return hashlib.sha256(np.ascontiguousarray(np.sort(inl), dtype="<i8").tobytes()).hexdigest()
 
 
+def truth_leaf(g):
+    """Leaf holding the generator's planted truth (input metadata, not a
+    result): its count by the oracle's replay is an achieved key, a valid
+    starting bound that cannot change the result."""
+    k = oracle.constants(oracle.Problem(g["family"], [np.zeros(0)] * len(g["cols"]), g["lo"], g["hi"], g["eps"]))
+    tr = [float(x) for x in g["truth"]]
+    if g["family"] == "pose4dof":
+        yaw = tr[3]
+        s = int(math.floor((yaw + math.pi / 4) / (math.pi / 2))) % 4
+        kap = math.tan(yaw - s * math.pi / 2)
+        u = [(tr[j] - g["lo"][j]) / (g["hi"][j] - g["lo"][j]) for j in range(3)] + [(kap + 1) / 2]
+        d = 4
+    else:
+        s = None
+        d = len(g["lo"])
+        u = [(tr[j] - g["lo"][j]) / (g["hi"][j] - g["lo"][j]) for j in range(d)]
+    L = k["L"][:d]
+    coords = [min(2 ** L[j] - 1, max(0, int(math.floor(u[j] * 2 ** L[j])))) for j in range(d)]
+    return oracle.leaf_index_of(L, coords, s)
+
+
 def solve_one(g, threads):
-    pr = oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], threads=threads)
+    pr = oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], threads=threads, seed_leaf=truth_leaf(g))
     t0 = time.perf_counter()
     r = oracle.solve(pr)
     wall = time.perf_counter() - t0
@@ -51,6 +73,7 @@ def solve_one(g, threads):
         "leaf_coords": [int(x) for x in r["leaf_coords"]], "n_inliers": int(r["n_inliers"]),
         "inliers_sha256": inliers_sha(r["inliers"]), "point": [float(x) for x in r["point"]],
         "oracle_tests": int(r["tests"]), "oracle_search_s": float(r["seconds"]), "oracle_wall_s": wall,
+        "seed_leaf": int(pr.seed_leaf),
     }
 
 

@@ -511,3 +511,18 @@ def test_thread_pool_equals_serial(name, threads):
     assert a["point"] == b["point"]
     c = oracle.solve(P(g, threads=threads, no_dive=True))
     assert (c["count"], c["leaf_index"]) == (a["count"], a["leaf_index"])
+
+
+@pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_small", "ray3d_small", "pose4dof_small", "pose4dof_tiny"])
+def test_seed_leaf_changes_nothing(name):
+    """Any leaf's achieved key is a valid starting bound: seeding the search
+    with it (alone or with the thread pool) gives the unseeded result."""
+    g = synth.config(name)
+    a = oracle.solve(P(g))
+    B = oracle.constants(P(g))["B"]
+    rng = np.random.default_rng(12)
+    for leaf in [a["leaf_index"], 0, (1 << B) - 1] + [int(x) for x in rng.integers(0, 1 << B, 3)]:
+        for threads in (1, 3):
+            b = oracle.solve(P(g, seed_leaf=leaf, threads=threads))
+            assert (b["count"], b["leaf_index"]) == (a["count"], a["leaf_index"])
+            assert np.array_equal(b["inliers"], a["inliers"])
