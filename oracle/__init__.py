@@ -91,6 +91,8 @@ def lib():
         L.or_all_leaf_counts.argtypes = [P(_Problem), P(ctypes.c_uint32), ctypes.c_uint64]
         L.or_level_counts.argtypes = [P(_Problem), ctypes.c_int, P(ctypes.c_uint32), ctypes.c_uint64]
         L.or_leaf_indicator.argtypes = [P(_Problem), ctypes.c_int64, P(ctypes.c_uint8), ctypes.c_uint64]
+        L.or_report.argtypes = [P(_Problem), ctypes.c_uint64, P(ctypes.c_uint64), P(ctypes.c_uint32), ctypes.c_int64,
+                                P(ctypes.c_int64), P(ctypes.c_uint64)]
         L.or_cell_masks.argtypes = [P(_Problem), ctypes.c_int, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_uint32)]
         L.or_meets.argtypes = [P(_Problem), P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int32,
                                ctypes.c_int, ctypes.c_int32, P(ctypes.c_int32)]
@@ -231,6 +233,21 @@ def leaf_indicator(prob: Problem, i: int) -> np.ndarray:
     if st != 0:
         raise OracleError(st, "leaf_indicator")
     return out
+
+
+def report(prob: Problem, tau: int, cap: int = 1 << 20):
+    """Every leaf whose count reaches tau: (leaf indices, counts), index order."""
+    idx = np.zeros(max(1, cap), dtype=np.uint64)
+    cnt = np.zeros(max(1, cap), dtype=np.uint32)
+    n = ctypes.c_int64(0)
+    tests = ctypes.c_uint64(0)
+    p = prob._c()
+    st = lib().or_report(ctypes.byref(p), int(tau), idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                         cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), cap, ctypes.byref(n),
+                         ctypes.byref(tests))
+    if st != 0:
+        raise OracleError(st, "report")
+    return idx[: n.value].copy(), cnt[: n.value].copy()
 
 
 def cell_masks(prob: Problem, level: int, sector: int, coords) -> np.ndarray:

@@ -60,6 +60,13 @@ typedef struct {
   uint64_t best;
   uint64_t *shared_best; /* thread pool: one best key for every worker */
   uint64_t tests, expanded, pruned, merged, budget;
+  /* threshold reporting: the best key stays at tau 2^B - 1, so a cell is
+   * pruned exactly when its count is below tau; every leaf that reaches
+   * tau is recorded instead of raising the best key */
+  int report;
+  uint64_t *rep_idx;
+  uint32_t *rep_cnt;
+  int64_t rep_cap, rep_n;
 } ctx;
 
 /* Best key so far.  With a thread pool every worker reads and raises one
@@ -510,7 +517,15 @@ static int expand(ctx *C, int m, int sector, const int32_t *cc, uint64_t prefix,
     uint64_t key = key_of(C, cnt, cpre << C->rem[m + 1]);
     if (!C->prob->no_prune && key <= best_get(C)) { C->pruned++; continue; }
     if (m + 1 == C->Lstar) {
-      best_offer(C, key);
+      if (C->report) {
+        if (C->rep_n < C->rep_cap) {
+          C->rep_idx[C->rep_n] = cpre;
+          C->rep_cnt[C->rep_n] = (uint32_t)cnt;
+        }
+        C->rep_n++;
+      } else {
+        best_offer(C, key);
+      }
       continue;
     }
     for (int64_t i = 0; i < nc; i++) canon(C, &buf[i], m + 1, ch);
@@ -844,6 +859,38 @@ int or_solve(const or_problem *p, or_result *res, int64_t *inliers, int64_t cap)
   res->n_inliers = ninl;
   if (cnt != res->count) return OR_EINVAL; /* internal consistency: never expected */
   if (ninl > cap) return OR_EBUFSZ;
+  return OR_OK;
+}
+
+/* Threshold reporting (the ray-intersection setting of Sec. 4.3: every
+ * cell of the leaf grid met by at least tau surfaces): the search of Alg. 2
+ * with the cut "count < tau" in place of the best key.  Leaves come out in
+ * index order (children are visited in digit order). */
+int or_report(const or_problem *p, uint64_t tau, uint64_t *leaves, uint32_t *counts, int64_t cap,
+              int64_t *n_out, uint64_t *tests) {
+  ctx C;
+  *n_out = 0;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (tau < 1 || tau >= (1ULL << (63 - C.B))) return OR_EINVAL;
+  rec *S;
+  int64_t n;
+  st = build_root(&C, &S, &n);
+  if (st) return st;
+  n = group(&C, S, n);
+  C.report = 1;
+  C.rep_idx = leaves;
+  C.rep_cnt = counts;
+  C.rep_cap = cap;
+  C.best = (tau << C.B) - 1ULL;
+  int nsec = C.fam == OR_POSE4DOF ? 4 : 1;
+  int32_t zero[MAXD] = {0, 0, 0, 0};
+  for (int s = 0; s < nsec && !st; s++) st = expand(&C, 0, s, zero, (uint64_t)s, S, n);
+  free(S);
+  *n_out = C.rep_n;
+  if (tests) *tests = C.tests;
+  if (st) return st;
+  if (C.rep_n > cap) return OR_EBUFSZ;
   return OR_OK;
 }
 

@@ -68,6 +68,12 @@ typedef struct {
  * receives the sorted original indices counted at the chosen leaf. */
 int or_solve(const or_problem *p, or_result *r, int64_t *inliers, int64_t cap);
 
+/* Threshold reporting: every leaf whose count reaches tau (>= 1), in index
+ * order, with its count; cap entries at most (OR_EBUFSZ beyond, n_out then
+ * holds the number found). */
+int or_report(const or_problem *p, uint64_t tau, uint64_t *leaves, uint32_t *counts, int64_t cap,
+              int64_t *n_out, uint64_t *tests);
+
 /* Front end only: normalized surface parameters.  t: n x 4 (row-major, unused
  * slots 0), f: n x 2, tag: n (RAY3D parameter axis, else 0). */
 int or_parametrize(const or_problem *p, double *t, double *f, int32_t *tag);

@@ -526,3 +526,25 @@ def test_seed_leaf_changes_nothing(name):
             b = oracle.solve(P(g, seed_leaf=leaf, threads=threads))
             assert (b["count"], b["leaf_index"]) == (a["count"], a["leaf_index"])
             assert np.array_equal(b["inliers"], a["inliers"])
+
+
+# ----------------------------------------------------------------------------
+# Threshold reporting (ray intersection, Sec. 4.3): every leaf with at least
+# tau surfaces, equal to the per-leaf chain counts of every leaf
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny"])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_report_equals_every_leaf_at_or_above_tau(name, seed):
+    g = synth.config(name, seed=seed)
+    pr = P(g)
+    counts = oracle.all_leaf_counts(pr)
+    best = int(counts.max())
+    for tau in sorted({1, 2, max(1, best // 2), max(1, best - 1), best, best + 1}):
+        idx, cnt = oracle.report(pr, tau)
+        want = np.nonzero(counts >= tau)[0]
+        assert np.array_equal(idx.astype(np.int64), want), tau
+        assert np.array_equal(cnt, counts[want])
+    # the top of the report is the maximum-depth result
+    r = oracle.solve(pr)
+    idx, cnt = oracle.report(pr, best)
+    assert idx[0] == r["leaf_index"] and cnt[0] == r["count"]
