@@ -183,6 +183,16 @@ gv_status gv_destroy(gv_ctx *ctx);
  * serialized; they may run while submitted problems are served. */
 gv_status gv_solve(gv_ctx *ctx, const gv_problem *p, gv_result *r);
 
+/* Threshold reporting (the ray-intersection setting of Sec. 4.3: every cell
+ * of the leaf grid that more than a threshold of surfaces meet): the same
+ * search with the cut "count < tau" in place of the best key.  Writes every
+ * leaf whose count is at least tau (>= 1) with its count, in ascending leaf
+ * index order, to leaves[] / counts[] (host buffers of cap entries).
+ * *n_out = the number of such leaves; GV_EBUFSZ when it exceeds cap.  Exact
+ * mode, precision and grouping as in gv_problem.  stats_out may be NULL. */
+gv_status gv_report(gv_ctx *ctx, const gv_problem *p, uint64_t tau, uint64_t *leaves, uint32_t *counts,
+                    uint64_t cap, uint64_t *n_out, gv_stats *stats_out);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): gv_solve with every
  * device buffer of the search taken from one region of 256 MiB that the

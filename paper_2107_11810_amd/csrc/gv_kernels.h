@@ -638,6 +638,29 @@ __global__ void k_prune(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell
   }
 }
 
+// Threshold reporting at the last level: every leaf whose key exceeds its
+// problem's fixed bound tau 2^B - 1 (count >= tau) is appended to the output
+// (up to cap; *n counts them all).  At this level a child's digit completes
+// its leaf index.
+__global__ void k_report_leaves(LevelC lv, int B, uint64_t idxmask, const Cell* __restrict__ cells, uint32_t ncell,
+                                const uint32_t* __restrict__ ccnt, const unsigned long long* __restrict__ best,
+                                uint64_t* __restrict__ out_idx, uint32_t* __restrict__ out_cnt,
+                                unsigned long long* __restrict__ n, uint64_t cap) {
+  const uint32_t nch = 1u << lv.abits;
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (uint64_t)ncell * nch) return;
+  const uint32_t c = (uint32_t)(k / nch), ch = (uint32_t)(k % nch);
+  const uint64_t idx = ((cells[c].prefix << lv.abits) | ch) << lv.rem_next;
+  const uint64_t key = ((uint64_t)ccnt[k] << B) | (idxmask - idx);
+  if (key > best[cells[c].prob]) {
+    const unsigned long long slot = atomicAdd(n, 1ull);
+    if (slot < cap) {
+      out_idx[slot] = idx;
+      out_cnt[slot] = ccnt[k];
+    }
+  }
+}
+
 // Greedy dive: in every cell keep only the best child (count, then lowest
 // digit); at the last level record its key.
 __global__ void k_pick_best(LevelC lv, int B, uint64_t idxmask, int leaf, const Cell* __restrict__ cells,

@@ -573,6 +573,13 @@ struct Run {
   bool beam = true;                       // progressive chunks until the first leaf level
   bool root_only = false;                 // build the root entries only (gv_incidence)
   bool fixed = false;                     // no tuning samples, no events (allocation-free solve)
+  // threshold reporting: the best key stays at tau 2^B - 1 (cells below tau
+  // are cut) and every leaf reaching tau is appended to rep_idx / rep_cnt
+  bool report = false;
+  uint64_t tau = 0, rep_cap = 0;
+  uint64_t* rep_idx = nullptr;
+  uint32_t* rep_cnt = nullptr;
+  unsigned long long* rep_n = nullptr;
   struct EvRec {
     std::pair<hipEvent_t, hipEvent_t> e;
     int kind;        // 0 count, 1 compaction
@@ -1080,11 +1087,18 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   if (dive) {
     k_pick_best<<<nblk(b.ncell), 256, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, b.ncell, ccnt,
                                                  pa->cnent, X.dbest, keepf, keptn);
+  } else if (leaf && X.report) {
+    // (the leaves are reported below; the bound stays fixed)
   } else {
     k_prune<<<nblk(nk), 256, 0, X.st>>>(lv, P.B, P.idxmask, leaf ? 1 : 0, b.cells, b.ncell, ccnt, pa->cnent,
                                         X.dbest, keepf, keptn);
   }
   HIPCHK(hipGetLastError());
+  if (leaf && X.report) {
+    k_report_leaves<<<nblk(nk), 256, 0, X.st>>>(lv, P.B, P.idxmask, b.cells, b.ncell, ccnt, X.dbest, X.rep_idx,
+                                                 X.rep_cnt, X.rep_n, X.rep_cap);
+    HIPCHK(hipGetLastError());
+  }
   if (leaf) {
     dfree(X, keptn);
     if (!dive) X.beam = false;
@@ -1542,7 +1556,14 @@ void epoch_begin(Run& X) {
   X.dovf = dalloc<int>(X, 1);
   X.pack_from = 1 << 30;
   X.dooff = dalloc<uint64_t>(X, np + 1);
-  HIPCHK(hipMemsetAsync(X.dbest, 0, np * 8, X.st));
+  if (X.report) {
+    std::vector<unsigned long long> b0(np);
+    for (uint32_t p = 0; p < np; p++) b0[p] = (unsigned long long)((X.tau << X.probs[p]->S.P.B) - 1ull);
+    HIPCHK(hipMemcpyAsync(X.dbest, b0.data(), np * 8, hipMemcpyHostToDevice, X.st));
+    host_wait(X);
+  } else {
+    HIPCHK(hipMemsetAsync(X.dbest, 0, np * 8, X.st));
+  }
   HIPCHK(hipMemsetAsync(X.drecheck, 0, 8, X.st));
   HIPCHK(hipMemsetAsync(X.dreads, 0, 8, X.st));
   HIPCHK(hipMemsetAsync(X.dovf, 0, sizeof(int), X.st));
@@ -1629,7 +1650,7 @@ void start_search(Run& X) {
   HIPCHK(hipMemcpyAsync(dcells, cells.data(), cells.size() * sizeof(Cell), hipMemcpyHostToDevice, X.st));
   host_wait(X);
   // greedy dive in every cell: achieved leaf keys are valid starting bounds
-  if (X.root_dive) {
+  if (X.root_dive && !X.report) {
     Batch b;
     b.level = 0;
     b.ncell = (uint32_t)cells.size();
@@ -1652,7 +1673,7 @@ void start_search(Run& X) {
   // each cell down to a leaf.  Thousands of greedy paths from different
   // coarse cells find a strong bound early where the top-count coarse cells
   // are clutter; like the dive above it only changes bounds, never a result.
-  if (X.dive_cells > 0) {
+  if (X.dive_cells > 0 && !X.report) {
     const bool beam = X.beam;
     Batch b;
     b.level = 0;
@@ -2465,6 +2486,85 @@ gv_status gv_solve(gv_ctx* ctx, const gv_problem* p, gv_result* r) {
   }
   set_err(ctx, "");
   return deliver(&pr, r);
+}
+
+gv_status gv_report(gv_ctx* ctx, const gv_problem* p, uint64_t tau, uint64_t* leaves, uint32_t* counts,
+                    uint64_t cap, uint64_t* n_out, gv_stats* stats_out) {
+  if (!ctx || !p || !n_out || (cap > 0 && (!leaves || !counts))) return GV_EINVAL;
+  *n_out = 0;
+  ProbRec pr;
+  pr.p = *p;
+  gv_status st = prepare_problem(&pr);
+  if (st != GV_OK) {
+    set_err(ctx, pr.err);
+    return st;
+  }
+  if (tau < 1 || pr.S.P.B >= 63 || tau >= (1ull << (63 - pr.S.P.B))) {
+    set_err(ctx, "tau must be at least 1 and fit the key");
+    return GV_EINVAL;
+  }
+  uint64_t total = 0;
+  std::vector<std::pair<uint64_t, uint32_t>> found;
+  gv_stats stats{};
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->err.clear();
+    Run X;
+    bind_ctx(X, ctx);
+    X.probs = {&pr};
+    X.report = true;
+    X.tau = tau;
+    X.rep_cap = cap;
+    try {
+      X.rep_idx = dalloc<uint64_t>(X, std::max<uint64_t>(1, cap));
+      X.rep_cnt = dalloc<uint32_t>(X, std::max<uint64_t>(1, cap));
+      X.rep_n = dalloc<unsigned long long>(X, 1);
+      HIPCHK(hipMemsetAsync(X.rep_n, 0, 8, X.st));
+      auto step = epoch_build(X);
+      while (step(X)) {
+      }
+      unsigned long long nn = 0;
+      HIPCHK(hipMemcpyAsync(&nn, X.rep_n, 8, hipMemcpyDeviceToHost, X.st));
+      host_wait(X);
+      total = nn;
+      const uint64_t k = std::min<uint64_t>(nn, cap);
+      if (k > 0) {
+        std::vector<uint64_t> hi(k);
+        std::vector<uint32_t> hc(k);
+        HIPCHK(hipMemcpyAsync(hi.data(), X.rep_idx, k * 8, hipMemcpyDeviceToHost, X.st));
+        HIPCHK(hipMemcpyAsync(hc.data(), X.rep_cnt, k * 4, hipMemcpyDeviceToHost, X.st));
+        host_wait(X);
+        found.resize(k);
+        for (uint64_t i = 0; i < k; i++) found[i] = {hi[i], hc[i]};
+        std::sort(found.begin(), found.end());
+      }
+      X.stats.levels = (uint32_t)X.P0.Lstar;
+      X.stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - X.t0).count();
+      stats = X.stats;
+    } catch (DevErr& e) {
+      fail_all(X, e.st);
+    }
+    dfree(X, X.rep_idx);
+    dfree(X, X.rep_cnt);
+    dfree(X, X.rep_n);
+    epoch_release(X);
+  }
+  if (stats_out) *stats_out = stats;
+  if (pr.st != GV_OK) {
+    set_err(ctx, pr.err.empty() ? ctx->err : pr.err);
+    return pr.st;
+  }
+  *n_out = total;
+  if (total > cap) {
+    set_err(ctx, "more leaves reach tau than the output holds");
+    return GV_EBUFSZ;
+  }
+  for (size_t i = 0; i < found.size(); i++) {
+    leaves[i] = found[i].first;
+    counts[i] = found[i].second;
+  }
+  set_err(ctx, "");
+  return GV_OK;
 }
 
 gv_status gv_solve_noalloc(gv_ctx* ctx, const gv_problem* p, gv_result* r) {

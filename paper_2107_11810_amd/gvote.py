@@ -23,7 +23,8 @@ FP64_PLAIN, FP32_FILTER = 0, 1
 STATUS = {0: "GV_OK", -1: "GV_EINVAL", -2: "GV_ENOMEM", -3: "GV_ETOOBIG", -4: "GV_EBUFSZ",
           -5: "GV_EAGAIN", -6: "GV_ETIMEDOUT", -7: "GV_ECANCELED", -8: "GV_EDEVICE", -9: "GV_ERANGE"}
 
-EXPORTS = ["gv_create", "gv_destroy", "gv_solve", "gv_solve_noalloc", "gv_parametrize", "gv_incidence", "gv_submit",
+EXPORTS = ["gv_create", "gv_destroy", "gv_solve", "gv_solve_noalloc", "gv_report", "gv_parametrize", "gv_incidence",
+           "gv_submit",
            "gv_poll", "gv_cancel",
            "gv_status_str", "gv_last_error"]
 
@@ -80,6 +81,8 @@ def lib():
         L.gv_destroy.argtypes = [ctypes.c_void_p]
         L.gv_solve.argtypes = [ctypes.c_void_p, P(Problem), P(Result)]
         L.gv_solve_noalloc.argtypes = [ctypes.c_void_p, P(Problem), P(Result)]
+        L.gv_report.argtypes = [ctypes.c_void_p, P(Problem), ctypes.c_uint64, P(ctypes.c_uint64), P(ctypes.c_uint32),
+                                ctypes.c_uint64, P(ctypes.c_uint64), P(Stats)]
         L.gv_parametrize.argtypes = [ctypes.c_void_p, P(Problem), P(ctypes.c_double), P(ctypes.c_double),
                                      P(ctypes.c_int32)]
         L.gv_incidence.argtypes = [ctypes.c_void_p, P(Problem), ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32),
@@ -91,7 +94,8 @@ def lib():
         L.gv_status_str.restype = ctypes.c_char_p
         L.gv_last_error.argtypes = [ctypes.c_void_p]
         L.gv_last_error.restype = ctypes.c_char_p
-        for name in ("gv_create", "gv_destroy", "gv_solve", "gv_solve_noalloc", "gv_parametrize", "gv_incidence",
+        for name in ("gv_create", "gv_destroy", "gv_solve", "gv_solve_noalloc", "gv_report", "gv_parametrize",
+                     "gv_incidence",
                      "gv_submit", "gv_poll", "gv_cancel"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -187,6 +191,21 @@ class Context:
                       "compact_launches": s.compact_launches, "test_bytes": s.test_bytes,
                       "compact_bytes": s.compact_bytes},
         }
+
+    def report(self, family, cols, lo, hi, eps, tau, cap=1 << 20, canon_c=0.0, precision=FP32_FILTER, group=0):
+        """Every leaf whose count reaches tau (gv_report): (leaf indices,
+        counts, stats), ascending leaf index."""
+        p, keep = make_problem(family, cols, lo, hi, eps, canon_c, precision, group)
+        idx = np.zeros(max(1, cap), dtype=np.uint64)
+        cnt = np.zeros(max(1, cap), dtype=np.uint32)
+        n = ctypes.c_uint64(0)
+        st_out = Stats()
+        st = lib().gv_report(self._h, ctypes.byref(p), int(tau), idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                             cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(cap), ctypes.byref(n),
+                             ctypes.byref(st_out))
+        if st != 0:
+            raise GvError(st, self.last_error())
+        return idx[: n.value].copy(), cnt[: n.value].copy(), {"tests": st_out.tests, "ms_total": st_out.ms_total}
 
     def incidence(self, family, cols, lo, hi, eps, level, sector, coords, canon_c=0.0, precision=FP32_FILTER):
         """Pass masks of every surface against the children of one cell

@@ -2,12 +2,17 @@
 times (default context, binary32 filter, inputs resident in device memory).
 
 ray3d_100k and line2d_10k: the oracle's full search finishes in seconds, so
-the comparison is complete.  plane3d_1m and pose4dof_1m: the oracle's full
-search takes hours, so it checks what it can compute one by one: the chain
-count and inlier set of the device's chosen leaf (must be identical), and
-that no sampled other leaf (the planted truth's leaf, its neighbours, random
-leaves) has a larger key; plus the planted-inlier lower bound.
+the comparison is run here.  plane3d_1m, pose4dof_1m and the 256 problems
+of pose4dof_serve256: complete comparison with golden files that a
+committed script wrote from the oracle alone (tests/golden/make_golden.py):
+count, leaf, sector, leaf coordinates, point and the SHA-256 of the sorted
+inlier set, per problem; the served problems go through gv_submit/gv_poll.
+Also, for the two large single problems, the oracle's replay of the chosen
+leaf and the planted-inlier lower bound.
 """
+import hashlib
+import json
+import os
 import math
 import sys
 
@@ -130,3 +135,70 @@ def test_fullsize_sampled_parity(ctx, name):
     _say(f"  count {r['count']} truth-leaf {ct} planted found {planted_in}/{len(g['planted'])}")
     assert r["count"] >= ct
     assert planted_in >= 0.8 * len(g["planted"])
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"no golden file for {name}")
+    return json.load(open(path))
+
+
+def _cols_sha(g):
+    h = hashlib.sha256()
+    for c in g["cols"]:
+        h.update(np.ascontiguousarray(c, dtype="<f8").tobytes())
+    return h.hexdigest()
+
+
+def _inl_sha(inl):
+    return hashlib.sha256(np.ascontiguousarray(np.sort(inl), dtype="<i8").tobytes()).hexdigest()
+
+
+def check_golden(r, gold):
+    assert r["count"] == gold["count"], (r["count"], gold["count"])
+    assert r["leaf_index"] == gold["leaf_index"]
+    assert r["sector"] == gold["sector"]
+    assert list(r["leaf_coords"]) == gold["leaf_coords"]
+    assert r["n_inliers"] == gold["n_inliers"]
+    assert _inl_sha(r["inliers"]) == gold["inliers_sha256"]
+    assert [float(x) for x in r["point"]] == gold["point"]
+
+
+@pytest.mark.parametrize("name", ["plane3d_1m", "pose4dof_1m"])
+def test_fullsize_golden_parity(ctx, name):
+    gold = _golden(name)["problems"][0]
+    g = synth.config(name)
+    assert _cols_sha(g) == gold["cols_sha256"]  # the generator has not changed
+    _say("golden", name)
+    for prec in (1, 0):
+        from paper_2107_11810_amd import gvote
+        cols = gvote.to_device(g["cols"])
+        r = ctx.solve(g["family"], cols, g["lo"], g["hi"], g["eps"], precision=prec)
+        _say(f"  precision {prec}: count {r['count']} tests {r['stats']['tests']:.3g} "
+             f"(oracle {gold['oracle_tests']:.3g})")
+        check_golden(r, gold)
+
+
+def test_serve256_golden_parity(ctx):
+    """All 256 problems of the serving workload through continuous batching
+    (and the binary64 plain form for every eighth) against their goldens."""
+    from paper_2107_11810_amd import gvote
+    gold = _golden("pose4dof_serve256")["problems"]
+    probs = synth.batch_pose4dof(n_problems=256)
+    assert len(gold) == len(probs)
+    _say("serve256 golden")
+    cols = [gvote.to_device(g["cols"]) for g in probs]
+    tickets = [gvote.submit(ctx, g["family"], c, g["lo"], g["hi"], g["eps"]) for g, c in zip(probs, cols)]
+    for i, (g, t) in enumerate(zip(probs, tickets)):
+        st, r = gvote.poll(ctx, t, len(g["cols"][0]))
+        assert st == 0, (i, st)
+        assert _cols_sha(g) == gold[i]["cols_sha256"], i
+        check_golden(r, gold[i])
+    for i in range(0, len(probs), 8):
+        g = probs[i]
+        r = ctx.solve(g["family"], cols[i], g["lo"], g["hi"], g["eps"], precision=gvote.FP64_PLAIN)
+        check_golden(r, gold[i])

@@ -1,0 +1,67 @@
+"""Threshold reporting on the device (gv_report) against the oracle's: the
+set of leaves met by at least tau surfaces, with their counts, in index
+order (the ray-intersection setting of Sec. 4.3)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_11810_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2107_11810_amd import gvote
+    c = gvote.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def OP(g, **kw):
+    return oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], **kw)
+
+
+@pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny", "line2d_small",
+                                  "ray3d_small", "pose4dof_small", "plane3d_small"])
+def test_report_equals_oracle(ctx, name):
+    g = synth.config(name)
+    best = oracle.solve(OP(g))["count"]
+    for tau in sorted({max(1, best // 4), max(1, best // 2), best, best + 1}):
+        _say("report", name, tau)
+        io, co = oracle.report(OP(g), tau)
+        for prec in (0, 1):
+            ig, cg, _ = ctx.report(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], tau, precision=prec)
+            assert np.array_equal(ig, io), (tau, prec, len(ig), len(io))
+            assert np.array_equal(cg, co)
+    # exact mode
+    tau = max(1, best // 2)
+    io, co = oracle.report(OP(g, canon_c=math.inf), tau)
+    ig, cg, _ = ctx.report(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], tau, canon_c=math.inf)
+    assert np.array_equal(ig, io) and np.array_equal(cg, co)
+
+
+def test_report_rays_full_size(ctx):
+    """The 100k-ray workload: every leaf met by at least half the best count."""
+    g = synth.config("ray3d_100k")
+    r = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+    tau = max(1, r["count"] // 2)
+    _say("rays", r["count"], tau)
+    io, co = oracle.report(OP(g), tau)
+    ig, cg, st = ctx.report(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], tau)
+    assert np.array_equal(ig, io) and np.array_equal(cg, co)
+    assert ig[np.argmax(cg)] == r["leaf_index"] and cg.max() == r["count"]
+    # a buffer too small reports the size it needs
+    from paper_2107_11810_amd import gvote
+    if len(io) > 1:
+        with pytest.raises(gvote.GvError) as e:
+            ctx.report(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], tau, cap=1)
+        assert e.value.status == -4
