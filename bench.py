@@ -7,9 +7,13 @@ plane-fitting workload: n = 1,000,000 points in the unit cube, 1% planted
 inliers on a random plane with vertical noise sigma = 0.001, eps = 0.003 on
 every dual axis, inputs resident in HBM before the timed region.
 
-Prints one JSON line with the incidence-test throughput of the whole job,
-the roofline figure of the dominant kernel (HIP events on the solve stream,
-inside the library) and the CPU oracle timed on a bounded sample.
+Prints one JSON line: the incidence-test throughput of the whole job, the
+roofline figure of the dominant kernel (HIP events on the solve stream,
+inside the library), the CPU oracle timed on a bounded sample (one thread
+and all cores), and, as extra keys, the 4-DoF pose workload (1e6 matches)
+and the 256-problem serving workload (solves/s batched against plain,
+p50/p99 latency).  Every result is compared with the oracle's golden file
+for its workload (tests/golden/); a mismatch exits non-zero.
 """
 import argparse
 import json
@@ -43,17 +47,40 @@ WORKLOADS = {
 }
 
 
-def serve_bench(args):
+def _inl_sha(inl):
+    import hashlib
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(np.sort(inl), dtype="<i8").tobytes()).hexdigest()
+
+
+def load_golden(workload):
+    """The oracle's results for a workload (tests/golden/, written by a
+    script that calls only the oracle), or None."""
+    try:
+        return json.load(open(os.path.join(ROOT, "tests", "golden", workload + ".json")))
+    except (OSError, ValueError):
+        return None
+
+
+def golden_match(r, gold):
+    return (r["count"] == gold["count"] and r["leaf_index"] == gold["leaf_index"] and r["sector"] == gold["sector"]
+            and r["n_inliers"] == gold["n_inliers"] and _inl_sha(r["inliers"]) == gold["inliers_sha256"]
+            and [float(x) for x in r["point"]] == gold["point"])
+
+
+def serve_bench(args, ctx=None):
     """Plain binary64, one problem at a time (gv_solve) against the binary32
     filter with continuous batching (gv_submit/gv_poll, three lanes), same 256
     problems, inputs resident in HBM; then Poisson arrivals for p50/p99
-    latency, beside the plain form's FIFO latency on the same arrivals."""
+    latency, beside the plain form's FIFO latency on the same arrivals.
+    Returns the figures and whether every result equals the oracle's."""
     import threading
     import numpy as np
     from paper_2107_11810_amd import gvote, synth
     probs = synth.batch_pose4dof(n_problems=256)
     print(f"{len(probs)} problems, {sum(len(g['cols'][0]) for g in probs)} matches", file=sys.stderr, flush=True)
-    ctx = gvote.Context(0)
+    own = ctx is None
+    ctx = gvote.Context(0) if own else ctx
     cols = [gvote.to_device(g["cols"]) for g in probs]
     hip = gvote.hip()
     g0 = probs[0]
@@ -113,10 +140,12 @@ def serve_bench(args):
     box = []
     collect(tk, box, len(probs))
     t_batch = time.perf_counter() - t0
-    same = all(r["count"] == p["count"] and r["leaf_index"] == p["leaf_index"] for r, p in zip(box[1], plain))
+    batched = box[1]
+    same = all(r["count"] == p["count"] and r["leaf_index"] == p["leaf_index"] and r["sector"] == p["sector"]
+               and np.array_equal(r["inliers"], p["inliers"]) for r, p in zip(batched, plain))
     mu = len(probs) / t_batch
     print(f"filter + continuous batching: {t_batch:.2f} s, identical={same}", file=sys.stderr, flush=True)
-    lat, fifo = {}, {}
+    lat, fifo, served = {}, {}, []
     for frac in (0.8, 0.5):
         arr = synth.poisson_arrivals(len(probs), frac * mu, seed=199)
         tickets, arrivals = [], []
@@ -128,6 +157,7 @@ def serve_bench(args):
         box2 = []
         collect(tickets, box2, len(probs))
         th.join()
+        served.append(box2[1])
         L = np.array(box2[0]) - np.array(arrivals)
         lat[frac] = (float(np.percentile(L, 50)), float(np.percentile(L, 99)))
         # the plain form on the same arrival times: one solve at a time in
@@ -140,21 +170,29 @@ def serve_bench(args):
         print(f"arrivals at {frac:.1f} x saturated rate: p50 {lat[frac][0]*1e3:.1f} ms, p99 {lat[frac][1]*1e3:.1f} ms"
               f" (plain FIFO on the same arrivals: p50 {fifo[frac][0]*1e3:.1f} ms, p99 {fifo[frac][1]*1e3:.1f} ms)",
               file=sys.stderr, flush=True)
-    ctx.close()
-    out = {
-        "metric": "solves/s", "value": mu, "unit": "solves/s", "n_gpus": 1, "steps": len(probs), "warmup": 1,
-        "ms_per_step": 1e3 * t_batch / len(probs), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "pose4dof_serve256", "description": WORKLOADS["pose4dof_serve256"]["desc"],
-                   "n_problems": len(probs), "total_matches": int(sum(len(g["cols"][0]) for g in probs))},
-        "plain_fp64_solves_per_s": len(probs) / t_plain,
-        "batched_over_plain": (len(probs) / t_plain and mu / (len(probs) / t_plain)),
+    if own:
+        ctx.close()
+    gold = load_golden("pose4dof_serve256")
+    golden = None
+    if gold is not None and len(gold["problems"]) == len(probs):
+        ok = all(golden_match(r, gg) for r, gg in zip(batched, gold["problems"]))
+        ok = ok and all(golden_match(r, gg) for r, gg in zip(plain, gold["problems"]))
+        ok = ok and all(golden_match(r, gg) for rs in served for r, gg in zip(rs, gold["problems"]))
+        golden = {"problems": len(probs), "matches": ok,
+                  "oracle_tests": int(sum(gg["oracle_tests"] for gg in gold["problems"])),
+                  "gpu_tests_plain": int(sum(r["stats"]["tests"] for r in plain)),
+                  "oracle_wall_s": round(sum(gg["oracle_wall_s"] for gg in gold["problems"]), 1),
+                  "oracle_threads": gold.get("threads")}
+    return {
+        "solves_per_s": mu, "plain_fp64_solves_per_s": len(probs) / t_plain,
+        "batched_over_plain": mu / (len(probs) / t_plain), "ms_batched": 1e3 * t_batch, "ms_plain": 1e3 * t_plain,
         "identical_to_plain": same,
         "latency_ms": {f"{f}x_saturated": {"p50": lat[f][0] * 1e3, "p99": lat[f][1] * 1e3} for f in lat},
-        "plain_fifo_latency_ms": {f"{f}x_saturated": {"p50": fifo[f][0] * 1e3, "p99": fifo[f][1] * 1e3} for f in fifo},
+        "plain_fifo_latency_ms": {f"{f}x_saturated": {"p50": fifo[f][0] * 1e3, "p99": fifo[f][1] * 1e3}
+                                  for f in fifo},
+        "n_problems": len(probs), "total_matches": int(sum(len(g["cols"][0]) for g in probs)),
+        "golden": golden,
     }
-    print(json.dumps(out), flush=True)
-
 
 
 def calibrate_copy(nbytes=1 << 30, reps=3):
@@ -223,66 +261,84 @@ def valu_frac(opt, tests, ms):
     return round(opt * tests / (ms * 1e-3) / VALU_LANE_OPS, 4) if ms > 0 else None
 
 
-def cpu_baseline(g, budget_tests):
-    """The oracle as it stands, single thread, stopped after a fixed number
-    of incidence tests of the same solve."""
+# Operations per incidence test of the 4-DoF predicate, counted from its
+# definition (the binary64 surface/box test: the z half and the kappa cone
+# half of the Sec. 4.2.1 surface), amortized over the 16 children of a cell
+# that share an (x, y) part, a z bit or a kappa bit.  Per surface and cell:
+#   z bits (2): 2 differences, the orientation by the sign of eta (1
+#     compare, 2 negations, 3 selects), the squares a^2, T_lo^2, T_hi^2
+#     (a^2 once): 21
+#   kappa bits (2): the padded ends (2) and the two edge directions
+#     (2 products, 4 sums): 16
+#   (x, y) parts (4), 111 each: the rectangle (4), r_min^2 (4 compares,
+#     4 selects, 2 products, 1 sum), r_max^2 (4 products, 2 max, 1 sum),
+#     silhouette corners (4 compares, 12 selects), apex guard (1); per z
+#     bit 2 products, 4 compares, 3 and/or (2 x 9); per kappa bit 4 cross
+#     products (3 each), 8 sign compares, 7 and/or (2 x 27): 444
+#   child masks: 16
+# = 497 operations for 16 tests.  The binary32 filter's error bounds are not
+# counted: they are the implementation's cost, not the method's.
+POSE_DAG_OPS_PER_TEST = 497.0 / 16.0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def cpu_baseline(g, budget_tests, threads):
+    """The oracle as it stands, stopped after a fixed number of incidence
+    tests of the same solve: on one host thread, and on `threads` threads
+    (its thread pool over disjoint subtrees, same result)."""
     import oracle
-    pr = oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], test_budget=int(budget_tests))
-    r = oracle.solve(pr)
-    return {"value": r["tests"] / r["seconds"], "unit": "tests/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {r['tests']:.3g} incidence tests of the same solve (greedy dive then depth-first "
-                      f"search), one host thread, {r['seconds']:.1f} s"}
+    out = {}
+    for nt in (threads, 1):
+        pr = oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], test_budget=int(budget_tests * nt),
+                            threads=nt)
+        r = oracle.solve(pr)
+        out[nt] = (r["tests"] / r["seconds"], r["tests"], r["seconds"])
+    v, n, sec = out[threads]
+    v1, n1, sec1 = out[1]
+    return {"value": v, "unit": "tests/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n:.3g} incidence tests of the same solve (greedy dive then depth-first search over "
+                      f"disjoint subtrees), {threads} host threads, {sec:.1f} s",
+            "single_thread": {"value": v1, "cores": 1,
+                              "sample": f"first {n1:.3g} incidence tests, one host thread, {sec1:.1f} s"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=3, help="untimed solves first (they include the autotuning)")
-    ap.add_argument("--workload", default="plane3d_1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-tests", type=float, default=2.5e8, help="oracle sample size (incidence tests)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", type=int, default=1, help="0 binary64, 1 binary32 filter")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run 1 GiB device copies (scale for the memory counters)")
-    args = ap.parse_args()
-    if args.calibrate_copy:
-        calibrate_copy()
-        return
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
-        sys.exit(2)
-
-    if args.workload == "pose4dof_serve256":
-        serve_bench(args)
-        return
+def single_leg(name, args, ctx, warmup, steps):
+    """Timed solves of one workload with inputs resident in HBM: throughput,
+    the roofline of the dominant kernel, and the comparison with the
+    oracle's golden result."""
     from paper_2107_11810_amd import gvote, synth
-    W = WORKLOADS[args.workload]
-    g = synth.config(args.workload)
-    n = len(g["cols"][0])
-    ctx = gvote.Context(0, kernel_timing=True)
+    W = WORKLOADS[name]
+    g = synth.config(name)
     cols = gvote.to_device(g["cols"])  # inputs resident in HBM
     hip = gvote.hip()
 
     def solve():
         return ctx.solve(g["family"], cols, g["lo"], g["hi"], g["eps"], precision=args.precision)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         r = solve()
-        print(f"warmup {i}: count={r['count']} tests={r['stats']['tests']:.3g} "
+        print(f"{name} warmup {i}: count={r['count']} tests={r['stats']['tests']:.3g} "
               f"{r['stats']['ms_total']:.0f} ms", file=sys.stderr, flush=True)
     hip.hipDeviceSynchronize()
     results = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         results.append(solve())
     hip.hipDeviceSynchronize()
-    t1 = time.perf_counter()
-    sec = t1 - t0
+    sec = time.perf_counter() - t0
     for i, r in enumerate(results):
-        print(f"step {i}: count={r['count']} inliers={r['n_inliers']} tests={r['stats']['tests']:.3g} "
-              f"{r['stats']['ms_total']:.0f} ms", file=sys.stderr, flush=True)
-    counts = {(r["count"], r["leaf_index"]) for r in results}
+        print(f"{name} step {i}: count={r['count']} inliers={r['n_inliers']} tests={r['stats']['tests']:.3g} "
+              f"{r['stats']['ms_total']:.1f} ms", file=sys.stderr, flush=True)
     tests = sum(r["stats"]["tests"] for r in results)
     st = [r["stats"] for r in results]
     t_ms = sum(s["test_ms"] for s in st)
@@ -297,7 +353,7 @@ def main():
         kname, kms, kb, kn = W["compact"], c_ms, c_b, c_n
     achieved = (kb / kn) / (kms / kn * 1e-3) / 1e9 if kn and kms > 0 else 0.0
     roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, kname),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, kname),
             "launches": kn, "avg_launch_us": round(kms / kn * 1e3, 2) if kn else None,
             "bytes_per_launch": int(kb / kn) if kn else None,
             "kernel_ms_per_step": round(kms / len(results), 2),
@@ -305,29 +361,90 @@ def main():
             # both big kernels: the incidence test (count pass) and compaction
             "kernels": [per_kernel(W["kernel"], t_ms, t_b, t_n, len(results)),
                         per_kernel(W["compact"], c_ms, c_b, c_n, len(results))]}
-    # measured vector-ALU issue of each kernel beside its HBM figure
     for k, ms in zip(roof["kernels"], (t_ms, c_ms)):
-        opt_k = measured_valu(args.workload, k["kernel"])
+        opt_k = measured_valu(name, k["kernel"])
         if opt_k is not None:
             k["valu_frac"] = valu_frac(opt_k, tests, ms)
-    if W["bound"] == "alu" and kname == W["kernel"]:
+    if W["bound"] == "alu" and kname == W["kernel"] and kms > 0:
         # the incidence kernel of this family is bound by vector ALU work:
-        # lane-operations per test (counted once with rocprofv3, see
-        # profiles/valu.json) times the tests, over its event time
-        opt = measured_valu(args.workload, kname)
-        if opt is not None and kms > 0:
-            ach = opt * tests / (kms * 1e-3) / 1e12
-            roof.update({"bound": "alu", "achieved": round(ach, 2), "peak": VALU_LANE_OPS / 1e12,
-                         "unit": "T lane-ops/s", "frac": round(ach / (VALU_LANE_OPS / 1e12), 4),
-                         "lane_ops_per_test": round(opt, 2)})
+        # operations per test of the predicate's definition, times the tests,
+        # over its event time; beside it the measured issue rate (VALU
+        # instructions x 64 lanes per test, from the counter record)
+        ach = POSE_DAG_OPS_PER_TEST * tests / (kms * 1e-3) / 1e12
+        roof.update({"bound": "alu", "achieved": round(ach, 2), "peak": VALU_LANE_OPS / 1e12,
+                     "unit": "T ops/s", "frac": round(ach / (VALU_LANE_OPS / 1e12), 4),
+                     "ops_per_test": round(POSE_DAG_OPS_PER_TEST, 2), "traffic": None})
+        issued = measured_valu(name, kname)
+        if issued is not None:
+            roof["issued_lane_ops_per_test"] = round(issued, 2)
+            roof["issue_frac"] = valu_frac(issued, tests, kms)
+    gold = load_golden(name)
+    golden = None
+    if gold is not None:
+        gg = gold["problems"][0]
+        golden = {"matches": all(golden_match(r, gg) for r in results), "oracle_tests_per_solve": gg["oracle_tests"],
+                  "oracle_wall_s": round(gg["oracle_wall_s"], 1), "oracle_threads": gold.get("threads"),
+                  "oracle_solves_per_s": round(1.0 / gg["oracle_wall_s"], 6)}
+    for c in cols:
+        c.free()
+    return {
+        "g": g, "sec": sec, "steps": steps, "tests": tests, "results": results, "roofline": roof,
+        "tests_per_s": tests / sec, "solves_per_s": steps / sec, "ms_per_solve": 1e3 * sec / steps,
+        "tests_per_solve": tests / steps, "count": results[0]["count"],
+        "deterministic": len({(r["count"], r["leaf_index"]) for r in results}) == 1, "golden": golden,
+        "rechecks_per_solve": sum(r["stats"]["fp64_rechecks"] for r in results) / steps,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=3, help="untimed solves first (they include the autotuning)")
+    ap.add_argument("--workload", default="plane3d_1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-tests", type=float, default=2.5e8, help="oracle sample size per thread (incidence tests)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--precision", type=int, default=1, help="0 binary64, 1 binary32 filter")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 1 GiB device copies (scale for the memory counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    from paper_2107_11810_amd import gvote
+    ok = True
+    if args.workload == "pose4dof_serve256":
+        sv = serve_bench(args)
+        ok = sv["identical_to_plain"] and (sv["golden"] is None or sv["golden"]["matches"])
+        out = {
+            "metric": "solves/s", "value": sv["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "steps": sv["n_problems"], "warmup": 1, "ms_per_step": sv["ms_batched"] / sv["n_problems"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": "pose4dof_serve256", "description": WORKLOADS["pose4dof_serve256"]["desc"],
+                       "n_problems": sv["n_problems"], "total_matches": sv["total_matches"]},
+        }
+        out.update({k: v for k, v in sv.items() if k not in ("solves_per_s", "n_problems", "total_matches")})
+        print(json.dumps(out), flush=True)
+        sys.exit(0 if ok else 1)
+
+    W = WORKLOADS[args.workload]
+    ctx = gvote.Context(0, kernel_timing=True)
+    head = single_leg(args.workload, args, ctx, args.warmup, args.steps)
+    g = head["g"]
+    n = len(g["cols"][0])
     out = {
         "metric": "incidence tests/s",
-        "value": tests / sec,
+        "value": head["tests_per_s"],
         "unit": "tests/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * sec / args.steps,
+        "ms_per_step": head["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -335,16 +452,35 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": W["desc"], "n": n, "eps": g["eps"],
                    "canon_c": 1.0, "precision": "fp32_filter" if args.precision else "fp64_plain"},
-        "solves_per_s": args.steps / sec,
-        "tests_per_solve": tests / args.steps,
-        "count": results[0]["count"],
-        "deterministic": len(counts) == 1,
-        "roofline": roof,
+        "solves_per_s": head["solves_per_s"],
+        "tests_per_solve": head["tests_per_solve"],
+        "count": head["count"],
+        "deterministic": head["deterministic"],
+        "roofline": head["roofline"],
+        "golden": head["golden"],
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_tests)
+    if head["golden"] is not None:
+        ok = ok and head["golden"]["matches"]
+    if args.workload == "plane3d_1m" and not args.no_extras:
+        # the 4-DoF pose workload, timed the same way
+        pl = single_leg("pose4dof_1m", args, ctx, 3, 10)
+        out["pose4dof_1m"] = {
+            "description": WORKLOADS["pose4dof_1m"]["desc"], "tests_per_s": pl["tests_per_s"],
+            "ms_per_solve": pl["ms_per_solve"], "solves_per_s": pl["solves_per_s"],
+            "tests_per_solve": pl["tests_per_solve"], "count": pl["count"], "roofline": pl["roofline"],
+            "rechecks_per_solve": pl["rechecks_per_solve"], "golden": pl["golden"]}
+        if pl["golden"] is not None:
+            ok = ok and pl["golden"]["matches"]
+        # the serving workload: batched binary32 filter against plain binary64
+        sv = serve_bench(args)
+        out["pose4dof_serve256"] = dict({"description": WORKLOADS["pose4dof_serve256"]["desc"]}, **sv)
+        ok = ok and sv["identical_to_plain"] and (sv["golden"] is None or sv["golden"]["matches"])
     ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_tests, max(1, min(os.cpu_count() or 1, 16)))
+    out["matches_oracle"] = ok
     print(json.dumps(out), flush=True)
+    sys.exit(0 if ok else 1)
 
 
 if __name__ == "__main__":

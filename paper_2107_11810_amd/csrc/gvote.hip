@@ -33,6 +33,7 @@
 #include "gv_kernels.h"
 #include "gv_root.h"
 #include "gv_exact.h"
+#include "gv_subtree.h"
 
 // Caching device allocator owned by a context.  All library work on a
 // context is ordered on its stream, so a block released after its last use
@@ -492,10 +493,11 @@ struct ProbRec {
 struct Batch {
   int level;
   uint32_t ncell;
-  uint64_t nent;
+  uint64_t nent;     // entries of the list buffer
   Cell* cells;
   void* ents;
   bool unit = true;  // every multiplicity is 1
+  uint64_t nlive = ~0ull;  // entries the cells hold, when fewer than nent
 };
 
 // Expansion state of a batch whose kept children are materialized later,
@@ -573,6 +575,17 @@ struct Run {
   bool beam = true;                       // progressive chunks until the first leaf level
   bool root_only = false;                 // build the root entries only (gv_incidence)
   bool fixed = false;                     // no tuning samples, no events (allocation-free solve)
+  // POSE4DOF: cells of this level and deeper whose lists hold at most
+  // GV_SUB_T entries are searched to the leaves on the device
+  // (k_subtree_pose), one workgroup per cell (GV_SUBTREE=0: off).  Measured
+  // on the 256-problem set: from two levels above the leaves it matches the
+  // host-driven path (1.03 against 1.02 s batched) with one host wait for
+  // the last two levels; from four levels above the leaves a workgroup's
+  // depth-first walk of a large subtree becomes the critical path (1.51 s),
+  // from seven levels above 2.64 s.
+  bool subtree = true;
+  int subtree_from = -2;  // < 0: relative to the leaf level
+  unsigned long long* dtests = nullptr;   // tests counted on the device
   // threshold reporting: the best key stays at tau 2^B - 1 (cells below tau
   // are cut) and every leaf reaching tau is appended to rep_idx / rep_cnt
   bool report = false;
@@ -925,7 +938,8 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   const uint32_t nch = 1u << lv.abits;
   const bool leaf = (m + 1 == P.Lstar);
   const uint64_t nk = (uint64_t)b.ncell * nch;
-  X.stats.tests += b.nent * nch;
+  const uint64_t nlive = std::min(b.nent, b.nlive);
+  X.stats.tests += nlive * nch;
   X.stats.cells_expanded += b.ncell;
 
   Parent* pa = new Parent();
@@ -973,7 +987,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     k_zero3<<<gs_grid(X, std::max(nk, ni)), 256, 0, X.st>>>(ccnt, nk, pa->cnent, nk, itemcnt, ni);
   }
   int cand;
-  const uint64_t tbytes = linear ? b.nent * sizeof(E) : b.nent * (sizeof(E) + sizeof(M));
+  const uint64_t tbytes = linear ? nlive * sizeof(E) : nlive * (sizeof(E) + sizeof(M));
   const int gpc = grid_pick(X, 0, tbytes, &cand);
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * gpc);
   auto evp = ev_begin(X, 0, cand, tbytes);
@@ -1550,6 +1564,11 @@ void epoch_begin(Run& X) {
   X.dP = dalloc<ProbC>(X, np);
   X.dbest = dalloc<unsigned long long>(X, np);
   X.drecheck = dalloc<unsigned long long>(X, 1);
+  X.dtests = dalloc<unsigned long long>(X, 1);
+  HIPCHK(hipMemsetAsync(X.dtests, 0, 8, X.st));
+  if (const char* e = std::getenv("GV_SUBTREE")) X.subtree = atoi(e) != 0;
+  if (const char* e = std::getenv("GV_SUBTREE_FROM")) X.subtree_from = atoi(e);
+  if (X.subtree_from < 0) X.subtree_from = std::max(1, X.P0.Lstar + X.subtree_from);
   X.dtot = X.hpin_dev ? X.hpin_dev : dalloc<uint64_t>(X, 4);
   X.dummy = dalloc<uint32_t>(X, 64);
   X.dreads = dalloc<unsigned long long>(X, 1);
@@ -1716,6 +1735,68 @@ void start_search(Run& X) {
   X.own_first = true;
 }
 
+// Device search of a batch's small cells (k_subtree_pose); cells with longer
+// lists come back as a batch of the same list buffer for the host-driven
+// path.
+template <typename E>
+void run_subtree(Run& X, Batch& b) {
+  const int nframes = X.P0.Lstar - b.level;
+  // workgroups: up to four per CU, their frame buffers within an eighth of
+  // the epoch's memory budget
+  const uint64_t per_wg = (uint64_t)(nframes - 1) * GV_SUB_T * sizeof(E) + (uint64_t)nframes * GV_SUB_T * 2;
+  const uint64_t fit = std::max<uint64_t>(1, X.budget / 8 / per_wg);
+  const uint32_t G = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(b.ncell, (uint64_t)X.ctx->n_cu * 4u), fit);
+  E* fbuf = dalloc<E>(X, (uint64_t)G * (uint64_t)(nframes - 1) * GV_SUB_T);
+  uint16_t* mbuf = dalloc<uint16_t>(X, (uint64_t)G * (uint64_t)nframes * GV_SUB_T);
+  Cell* over = dalloc<Cell>(X, b.ncell);
+  uint32_t* ctr = dalloc<uint32_t>(X, 3);
+  HIPCHK(hipMemsetAsync(ctr, 0, 3 * sizeof(uint32_t), X.st));
+  k_subtree_pose<E><<<G, GV_SUB_WG, 0, X.st>>>(X.dP, b.level, b.cells, b.ncell, (const E*)b.ents, X.m64, X.Ntot,
+                                                X.dbest, X.drecheck, X.dtests, ctr, over, ctr + 1, fbuf, mbuf,
+                                                nframes);
+  HIPCHK(hipGetLastError());
+  uint32_t back[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(back, ctr + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, X.st));
+  host_wait(X);
+  dfree(X, fbuf);
+  dfree(X, mbuf);
+  dfree(X, ctr);
+  dfree(X, b.cells);
+  X.stats.cells_expanded += b.ncell - back[0];
+  if (X.trace)
+    std::fprintf(stderr, "gv: level %d cells %u entries %llu searched on the device, %u cells back\n", b.level,
+                 b.ncell, (unsigned long long)b.nent, back[0]);
+  if (back[0] == 0) {
+    dfree(X, over);
+    dfree(X, b.ents);
+    return;
+  }
+  Task t{};
+  t.chunk = false;
+  t.b = b;
+  t.b.cells = over;
+  t.b.ncell = back[0];
+  t.b.nlive = back[1];
+  X.stack.push_back(t);
+}
+
+template <int FAM, typename E>
+bool subtree_at(Run& X, Batch& b) {
+  if constexpr (FAM != FAM_POSE4DOF) {
+    return false;
+  } else {
+    if (!X.subtree || X.report || b.level < X.subtree_from || b.level + 1 >= X.P0.Lstar) return false;
+    if constexpr (std::is_same<E, EntQ32>::value) {
+      if (b.unit && b.level >= 1 && X.q24) {
+        run_subtree<EntQ24>(X, b);
+        return true;
+      }
+    }
+    run_subtree<E>(X, b);
+    return true;
+  }
+}
+
 // one expansion of the epoch's depth-first search; false when finished
 template <int FAM, typename E, typename M>
 bool epoch_step(Run& X) {
@@ -1728,6 +1809,8 @@ bool epoch_step(Run& X) {
   } else {
     b = t.b;
   }
+  // a batch that came back from the device search goes to the host path
+  if (b.nlive == ~0ull && subtree_at<FAM, E>(X, b)) return !X.stack.empty();
   Parent* pa = expand_at<FAM, E, M>(X, b, true, false);
   if (pa) push_children<FAM, E, M>(X, pa, X.stack);
   return !X.stack.empty();
@@ -2030,6 +2113,7 @@ void epoch_finish(Run& X) {
   }
   if (X.ctx->kernel_timing) X.stats.compact_bytes += d2h1(X, X.dreads) / 8;
   X.stats.fp64_rechecks = rech;
+  X.stats.tests += d2h1(X, X.dtests);
   X.stats.levels = (uint32_t)P.Lstar;
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - X.t0).count();
   X.stats.ms_total = ms;
@@ -2078,6 +2162,8 @@ void epoch_release(Run& X) {
   dfree(X, X.dP);
   dfree(X, X.dbest);
   dfree(X, X.drecheck);
+  dfree(X, X.dtests);
+  X.dtests = nullptr;
   if (X.dtot != X.hpin_dev) dfree(X, X.dtot);
   dfree(X, X.dummy);
   dfree(X, X.dreads);
