@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gv_oracle.c")
 _LIB = os.path.join(_HERE, "libgv_oracle.so")
 
-FAMILIES = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4}
-NCOLS = {1: 2, 2: 3, 3: 6, 4: 5}
+FAMILIES = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4, "sim2d": 5}
+NCOLS = {1: 2, 2: 3, 3: 6, 4: 5, 5: 4}
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EBUFSZ", -4: "ERANGE", -5: "EBUDGET"}
 

@@ -12,7 +12,8 @@
  *     hyperplanes in 3-space (Eq. 3), rays in 3-space (Sec. 4.3, the
  *     two-equation line form, generalized to the dominant axis), and the
  *     known-gravity calibrated pose (the 5DoF surface of Sec. 4.2.1 with
- *     focal length 1).
+ *     focal length 1), and similarity alignment of planar point sets (Sec.
+ *     4.4, the translation written in terms of scale-rotation).
  *   - Canonization (Sec. 3.2.1): translate to the cell's minimum corner,
  *     round essential parameters to eps'/((l+1) delta) and free parameters
  *     to eps'/(l+1), group equal results and keep their multiplicity.
@@ -116,6 +117,8 @@ static void lin_axes(const ctx *C, int tag, int *nP, int P[2], int *nQ, int Q[2]
     *nP = 1; P[0] = 0; *nQ = 1; Q[0] = 1;
   } else if (C->fam == OR_PLANE3D) {
     *nP = 2; P[0] = 0; P[1] = 1; *nQ = 1; Q[0] = 2;
+  } else if (C->fam == OR_SIM2D) {
+    *nP = 2; P[0] = 0; P[1] = 1; *nQ = 2; Q[0] = 2; Q[1] = 3;
   } else { /* RAY3D: parameter axis = tag, dependents ascending */
     int k = 0;
     *nP = 1; P[0] = tag; *nQ = 2;
@@ -138,6 +141,7 @@ static int ctx_init(ctx *C, const or_problem *p) {
     case OR_PLANE3D: C->d = 3; C->ell = 2; break;
     case OR_RAY3D: C->d = 3; C->ell = 2; break;
     case OR_POSE4DOF: C->d = 4; C->ell = 4; break;
+    case OR_SIM2D: C->d = 4; C->ell = 2; break;
     default: return OR_EINVAL;
   }
   C->c = p->canon_c == 0.0 ? 1.0 : p->canon_c;
@@ -233,6 +237,17 @@ static int front(const ctx *C, int64_t i, rec *r) {
     r->p[0] = -((x * C->E[0]) * C->inv[2]);
     r->p[1] = -((y * C->E[1]) * C->inv[2]);
     r->p[4] = (((z - x * C->lo[0]) - y * C->lo[1]) - C->lo[2]) * C->inv[2];
+  } else if (C->fam == OR_SIM2D) {
+    /* correspondence p -> q under q_x = a p_x + b p_y + c, q_y = -b p_x +
+     * a p_y + d: the translation as a function of (a, b),
+     * c = q_x - a p_x - b p_y,  d = q_y + b p_x - a p_y */
+    double px = p->col[0][i], py = p->col[1][i], qx = p->col[2][i], qy = p->col[3][i];
+    r->p[0] = -((px * C->E[0]) * C->inv[2]);
+    r->p[1] = -((py * C->E[1]) * C->inv[2]);
+    r->p[4] = (((qx - px * C->lo[0]) - py * C->lo[1]) - C->lo[2]) * C->inv[2];
+    r->p[2] = -((py * C->E[0]) * C->inv[3]);
+    r->p[3] = (px * C->E[1]) * C->inv[3];
+    r->p[5] = (((qy - py * C->lo[0]) + px * C->lo[1]) - C->lo[3]) * C->inv[3];
   } else if (C->fam == OR_RAY3D) {
     /* ray w + s u -> x_q = w_q + (u_q/u_pi)(x_pi - w_pi), pi the dominant axis */
     double w[3], u[3];

@@ -20,7 +20,7 @@
 extern "C" {
 #endif
 
-enum { OR_LINE2D = 1, OR_PLANE3D = 2, OR_RAY3D = 3, OR_POSE4DOF = 4 };
+enum { OR_LINE2D = 1, OR_PLANE3D = 2, OR_RAY3D = 3, OR_POSE4DOF = 4, OR_SIM2D = 5 };
 
 enum {
   OR_OK = 0,

@@ -13,6 +13,9 @@ Recipes (each stands in for a workload of the paper):
   * pose4dof: 2D-3D matches seen from a gravity-aligned camera at a random
     position and yaw, plus random matches (stands in for the SfM query
     matches of the posing evaluation, which are not available).
+  * sim2d: two planar point sets, part of one mapped into the other by a
+    similarity with noise; every pair is a hypothetical correspondence
+    (pointset alignment).
 """
 from __future__ import annotations
 
@@ -20,7 +23,7 @@ import math
 
 import numpy as np
 
-FAMILY_IDS = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4}
+FAMILY_IDS = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4, "sim2d": 5}
 
 
 def _rng(seed):
@@ -219,6 +222,40 @@ def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=
                     (eps_m, eps_m, eps_m, eps_k), truth=(c[0], c[1], c[2], yaw), planted=planted)
 
 
+def sim2d(seed=105, n_a=10_000, k=9, n_in=1000, sigma=0.002, eps=0.01, lo=(0.25, -1.25, -2.0, -2.0),
+          hi=(1.25, 1.25, 2.0, 2.0)):
+    """Point sets A, B in [0,1]^2 and k candidate correspondences per point
+    of A, as a descriptor matcher would propose them.  n_in points of A (in
+    [0.25, 0.75]^2) map into B by q = [[a, b], [-b, a]] p + (c, d), a =
+    s cos t, b = s sin t, scale s in [0.6, 1.2], rotation t in [-60, 60]
+    deg, plus isotropic Gaussian noise sigma, and their true image is one of
+    their candidates; every other candidate is a uniform point.
+    Observations: columns (px, py, qx, qy), n_a * k of them.  Axes
+    (a, b, c, d); the box keeps a >= 0.25, away from the degenerate
+    similarities of scale near 0 that map all of A to one point."""
+    rng = _rng(seed)
+    s = rng.uniform(0.6, 1.2)
+    t = rng.uniform(-math.pi / 3, math.pi / 3)
+    a, b = s * math.cos(t), s * math.sin(t)
+    M = np.array([[a, b], [-b, a]])
+    A = rng.uniform(0.0, 1.0, size=(n_a, 2))
+    A[:n_in] = rng.uniform(0.25, 0.75, size=(n_in, 2))
+    img = A[:n_in] @ M.T
+    lo_t = -img.min(axis=0)
+    hi_t = 1.0 - img.max(axis=0)
+    tr = rng.uniform(lo_t, np.maximum(lo_t, hi_t))
+    Q = rng.uniform(0.0, 1.0, size=(n_a, k, 2))
+    slot = rng.integers(0, k, size=n_in)
+    Q[np.arange(n_in), slot] = img + tr + rng.normal(0.0, sigma, size=(n_in, 2))
+    P = np.repeat(A[:, None, :], k, axis=1)
+    is_in = np.zeros((n_a, k), bool)
+    is_in[np.arange(n_in), slot] = True
+    cols = [P[..., 0].ravel(), P[..., 1].ravel(), Q[..., 0].ravel(), Q[..., 1].ravel()]
+    cols, planted = _shuffle(rng, cols, is_in.ravel())
+    return _problem("sim2d", cols, lo, hi, (eps, eps, eps, eps), truth=(a, b, float(tr[0]), float(tr[1])),
+                    planted=planted)
+
+
 # --------------------------------------------------------------------------
 # Named workloads.  Full sizes are the paper-scale planted-inlier configs; the
 # "tiny" ones have few surfaces and a coarse eps so every leaf can be checked.
@@ -232,6 +269,12 @@ def config(name: str, **kw):
         return ray3d(**kw)
     if name == "pose4dof_1m":
         return pose4dof(**kw)
+    if name == "sim2d_90k":
+        return sim2d(**kw)
+    if name == "sim2d_tiny":
+        return sim2d(seed=kw.get("seed", 6), n_a=12, k=4, n_in=6, sigma=0.01, eps=0.3)
+    if name == "sim2d_small":
+        return sim2d(seed=kw.get("seed", 16), n_a=500, k=6, n_in=80, sigma=0.003, eps=0.03)
     if name == "line2d_tiny":
         return line2d(seed=kw.get("seed", 1), n=kw.get("n", 48), n_in=kw.get("n_in", 12), sigma=0.01,
                       eps=(0.1, 0.1))

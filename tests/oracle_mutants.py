@@ -56,6 +56,9 @@ MUTANTS = [
     ("guard_rmax", "if (rmin2 < C->Rg2) return 1;", "if (rmax2 < C->Rg2) return 1;"),
     ("padk_3eps", "C->padk = ceil((C->epsk + ek * 0.5)", "C->padk = ceil((3.0 * C->epsk + ek * 0.5)"),
     ("inl_last", "if (inl && k < cap) inl[k] = i;", "if (inl && k < cap) inl[k] = i + (i == C->prob->n - 1);"),
+    ("sim_front_d", "r->p[3] = (px * C->E[1]) * C->inv[3];", "r->p[3] = -(px * C->E[1]) * C->inv[3];"),
+    ("sim_axes", "*nP = 2; P[0] = 0; P[1] = 1; *nQ = 2; Q[0] = 2; Q[1] = 3;",
+     "*nP = 2; P[0] = 0; P[1] = 1; *nQ = 2; Q[0] = 3; Q[1] = 2;"),
 ]
 
 

@@ -32,7 +32,7 @@ import pytest
 import oracle
 from paper_2107_11810_amd import synth
 
-ELL = {"line2d": 1, "plane3d": 2, "ray3d": 2, "pose4dof": 4}
+ELL = {"line2d": 1, "plane3d": 2, "ray3d": 2, "pose4dof": 4, "sim2d": 2}
 
 
 def P(g, **kw):
@@ -166,7 +166,7 @@ def test_leaf_levels_are_the_smallest_with_side_at_most_eps():
 # ----------------------------------------------------------------------------
 # Canonization deviation against the paper's bound with steps from eps and c
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["line2d_10k", "plane3d_small", "ray3d_small"])
+@pytest.mark.parametrize("name", ["line2d_10k", "plane3d_small", "ray3d_small", "sim2d_small"])
 @pytest.mark.parametrize("c", [1.0, 0.5])
 def test_canonization_deviation_within_paper_bound(name, c):
     g = synth.config(name)
@@ -188,6 +188,8 @@ def test_canonization_deviation_within_paper_bound(name, c):
             groups = [([0], 1)]
         elif g["family"] == "plane3d":
             groups = [([0, 1], 2)]
+        elif g["family"] == "sim2d":
+            groups = [([0, 1], 2), ([0, 1], 3)]
         else:
             pi = int(tag[i])
             qs = [q for q in range(3) if q != pi]
@@ -215,7 +217,7 @@ def test_canonization_deviation_within_paper_bound(name, c):
 # ----------------------------------------------------------------------------
 # Pads: the predicate switches exactly at pad(m) (linear families)
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["line2d_10k", "plane3d_small", "ray3d_small"])
+@pytest.mark.parametrize("name", ["line2d_10k", "plane3d_small", "ray3d_small", "sim2d_small"])
 def test_linear_predicate_switches_at_the_pad(name):
     g = synth.config(name)
     pr = P(g)
@@ -233,6 +235,8 @@ def test_linear_predicate_switches_at_the_pad(name):
             pax, qs, tag = [0], [1], 0
         elif fam == "plane3d":
             pax, qs, tag = [0, 1], [2], 0
+        elif fam == "sim2d":
+            pax, qs, tag = [0, 1], [2, 3], 0
         else:
             tag = int(rng.integers(0, 3))
             pax, qs = [tag], [q for q in range(3) if q != tag]
@@ -294,6 +298,12 @@ def _lin_distances(g, i, blo, bhi):
         p = [-x * blo[:, 0], -x * bhi[:, 0]]
         q = [-y * blo[:, 1], -y * bhi[:, 1]]
         out.append((2, z + np.minimum(*p) + np.minimum(*q), z + np.maximum(*p) + np.maximum(*q)))
+    elif fam == "sim2d":         # c = qx - a px - b py,  d = qy + b px - a py
+        px, py, qx, qy = c
+        for q, base, ta, tb in ((2, qx, -px, -py), (3, qy, -py, px)):
+            u = [ta * blo[:, 0], ta * bhi[:, 0]]
+            v = [tb * blo[:, 1], tb * bhi[:, 1]]
+            out.append((q, base + np.minimum(*u) + np.minimum(*v), base + np.maximum(*u) + np.maximum(*v)))
     else:                        # x_q = w_q + (u_q/u_pi)(x_pi - w_pi), pi = dominant axis
         w, u = np.array(c[:3]), np.array(c[3:])
         pi = int(np.argmax(np.abs(u)))
@@ -355,7 +365,7 @@ def _pose_parts(g, i, blo, bhi, sec):
 
 TINY = [("line2d_tiny", s) for s in (1, 2, 3)] + [("plane3d_tiny", s) for s in (1, 2)] + \
        [("ray3d_tiny", s) for s in (1, 2)] + [("pose4dof_tiny", s) for s in (1, 2, 3)] + \
-       [("pose4dof_tiny_flat", s) for s in (5, 6)]
+       [("pose4dof_tiny_flat", s) for s in (5, 6)] + [("sim2d_tiny", s) for s in (6, 7)]
 
 
 @pytest.mark.parametrize("name,seed", TINY)
@@ -417,7 +427,7 @@ def test_every_leaf_low_and_up(name, seed):
 
 
 @pytest.mark.parametrize("name,seed", [("line2d_tiny", 1), ("plane3d_tiny", 2), ("ray3d_tiny", 1),
-                                       ("pose4dof_tiny", 1)])
+                                       ("pose4dof_tiny", 1), ("sim2d_tiny", 6)])
 def test_counts_shrink_down_the_tree(name, seed):
     """count(child) <= count(parent) for every cell of every level, the root
     holds every surface, and the leaf level equals the leaf counts."""
@@ -554,7 +564,7 @@ def test_pose_root_lattice_moves_z_and_kappa_by_at_most_half_eps_prime(name):
 # Returned point
 # ----------------------------------------------------------------------------
 SMALL = ["line2d_small", "plane3d_small", "ray3d_small", "pose4dof_small", "line2d_tiny", "pose4dof_tiny",
-         "pose4dof_small_flat"]
+         "pose4dof_small_flat", "sim2d_small"]
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -582,7 +592,7 @@ def test_point_is_the_centre_of_the_returned_leaf(name):
 
 @pytest.mark.parametrize("name,seed", [("line2d_small", None), ("ray3d_small", None), ("pose4dof_small", None),
                                        ("pose4dof_small", 16), ("pose4dof_small", 17), ("pose4dof_small_flat", None),
-                                       ("line2d_10k", None)])
+                                       ("line2d_10k", None), ("sim2d_small", None)])
 def test_point_near_the_planted_truth(name, seed):
     g = synth.config(name, seed=seed) if seed else synth.config(name)
     pr = P(g)

@@ -82,6 +82,25 @@ def test_ray3d_lines_pass_through_centre():
             assert abs(G - uc[q]) <= 1e-13
 
 
+def test_sim2d_correspondence_surfaces_pass_through_the_similarity():
+    """q = [[a, b], [-b, a]] p + (c, d) (the linear parametrization of Sec.
+    4.4): a noise-free correspondence gives a surface through (a, b, c, d),
+    on both dependent axes."""
+    rng = np.random.default_rng(17)
+    a, b, c, d = 0.83, -0.41, 0.27, -0.35
+    P_ = rng.uniform(0, 1, (300, 2))
+    Q = np.stack([a * P_[:, 0] + b * P_[:, 1] + c, -b * P_[:, 0] + a * P_[:, 1] + d], 1)
+    g = {"family": "sim2d", "cols": [P_[:, 0], P_[:, 1], Q[:, 0], Q[:, 1]], "lo": [0.25, -1.25, -2, -2],
+         "hi": [1.25, 1.25, 2, 2], "eps": [0.01] * 4}
+    t, f, _ = oracle.parametrize(P(g))
+    ua, ub, uc, ud = norm(g, 0, a), norm(g, 1, b), norm(g, 2, c), norm(g, 3, d)
+    assert np.max(np.abs(f[:, 0] + t[:, 0] * ua + t[:, 1] * ub - uc)) <= 32 * ULP
+    assert np.max(np.abs(f[:, 1] + t[:, 2] * ua + t[:, 3] * ub - ud)) <= 32 * ULP
+    # slopes: -px E_a / E_c, -py E_b / E_c on c; -py E_a / E_d, px E_b / E_d on d
+    assert np.allclose(t, np.stack([-P_[:, 0] * 1.0 / 4, -P_[:, 1] * 2.5 / 4, -P_[:, 1] * 1.0 / 4,
+                                    P_[:, 0] * 2.5 / 4], 1), rtol=0, atol=4 * ULP)
+
+
 def _pose_obs(c, yaw, w):
     d = w - c[None]
     xi, eta, F = synth.bearing_to_xi_eta(d, yaw)
@@ -301,7 +320,7 @@ def test_exact_mode_hough_accumulator_line2d():
 # ----------------------------------------------------------------------------
 # Search = maximum over every leaf of the per-surface chain count
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny"])
+@pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny", "sim2d_tiny"])
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_search_equals_all_leaf_chain_counts(name, seed):
     g = synth.config(name, seed=seed)
@@ -500,7 +519,8 @@ def test_inliers_within_approximation_bound(name):
 # result (the key of a leaf is unique, so the search order cannot matter)
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny", "line2d_small",
-                                  "plane3d_small", "ray3d_small", "pose4dof_small", "pose4dof_small_flat"])
+                                  "plane3d_small", "ray3d_small", "pose4dof_small", "pose4dof_small_flat",
+                                  "sim2d_tiny"])
 @pytest.mark.parametrize("threads", [2, 5])
 def test_thread_pool_equals_serial(name, threads):
     g = synth.config(name)
@@ -532,7 +552,7 @@ def test_seed_leaf_changes_nothing(name):
 # Threshold reporting (ray intersection, Sec. 4.3): every leaf with at least
 # tau surfaces, equal to the per-leaf chain counts of every leaf
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny"])
+@pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny", "sim2d_tiny"])
 @pytest.mark.parametrize("seed", [1, 2])
 def test_report_equals_every_leaf_at_or_above_tau(name, seed):
     g = synth.config(name, seed=seed)
