@@ -28,6 +28,12 @@
  *                                        Requires hi[0]-lo[0] == hi[1]-lo[1];
  *                                        yaw always spans [0, 2 pi) in four
  *                                        sectors, lo[3]/hi[3] are ignored.
+ *   GV_SIM2D    cols (px, py, qx, qy)   axes (a, b, c, d): a candidate
+ *                                        correspondence p -> q of two planar
+ *                                        point sets under the similarity
+ *                                        q = [[a, b], [-b, a]] p + (c, d)
+ *                                        (Sec. 4.4): c = qx - a px - b py,
+ *                                        d = qy + b px - a py.
  *
  * Per-axis eps (Sec. 3.2, "different eps for each coordinate"): leaves are
  * the cells of the dyadic subdivision of the box whose side on axis j is at
@@ -60,7 +66,7 @@ enum {
   GV_ERANGE = -9     /* lattice too fine for the exact device arithmetic */
 };
 
-typedef enum { GV_LINE2D = 1, GV_PLANE3D = 2, GV_RAY3D = 3, GV_POSE4DOF = 4 } gv_family;
+typedef enum { GV_LINE2D = 1, GV_PLANE3D = 2, GV_RAY3D = 3, GV_POSE4DOF = 4, GV_SIM2D = 5 } gv_family;
 
 /* GV_FP64_PLAIN: every predicate decision in binary64.
  * GV_FP32_FILTER: binary32 evaluation with a certified forward-error bound;
@@ -209,7 +215,9 @@ gv_status gv_solve_noalloc(gv_ctx *ctx, const gv_problem *p, gv_result *r);
  * parameters, row-major, t_out n x 4 and f_out n x 2 (host buffers), and
  * tag_out n (RAY3D parameter axis, else 0; may be NULL).  Layout per family:
  * LINE2D t=(t,0,0,0) f=(f,0); PLANE3D t=(t1,t2,0,0) f=(f,0); RAY3D
- * t=(t_q1,0,t_q2,0) f=(f_q1,f_q2); POSE4DOF t=(W1,W2,xi,eta') f=(W3,0). */
+ * t=(t_q1,0,t_q2,0) f=(f_q1,f_q2); POSE4DOF t=(W1,W2,xi,eta') f=(W3,0); SIM2D
+ * t=(t_ca,t_cb,t_da,t_db) f=(f_c,f_d) (slopes of the dependent axes c, d over
+ * the parameter axes a, b). */
 gv_status gv_parametrize(gv_ctx *ctx, const gv_problem *p, double *t_out, double *f_out,
                          int32_t *tag_out);
 

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "gvote.hip")
 LIB = os.path.join(HERE, "libgvote.so")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("gvote.hip", "gv_device.h", "gv_kernels.h", "gv_root.h", "gv_exact.h")] + [
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("gvote.hip", "gv_device.h", "gv_kernels.h", "gv_root.h", "gv_exact.h",
+                                                          "gv_subtree.h")] + [
     os.path.join(ROOT, "include", "gvote.h")]
 
 HIPCC_FLAGS = [

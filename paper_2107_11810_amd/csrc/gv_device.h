@@ -20,13 +20,13 @@
 #define GV_MAXD 4
 #define GV_ITEM 1024  // entries per work item (one wave)
 
-enum { FAM_LINE2D = 1, FAM_PLANE3D = 2, FAM_RAY3D = 3, FAM_POSE4DOF = 4 };
+enum { FAM_LINE2D = 1, FAM_PLANE3D = 2, FAM_RAY3D = 3, FAM_POSE4DOF = 4, FAM_SIM2D = 5 };
 // Exact mode of a linear family (quantized once at the root to a fixed
 // 2^-36 lattice, never re-canonized, tested in binary64): kernel-side family
-// code = family + 4.
-enum { FAM_XLINE2D = 5, FAM_XPLANE3D = 6, FAM_XRAY3D = 7 };
-constexpr bool fam_exact(int f) { return f >= FAM_XLINE2D; }
-constexpr int fam_base(int f) { return f >= FAM_XLINE2D ? f - 4 : f; }
+// code = family + 8.
+enum { FAM_XLINE2D = 9, FAM_XPLANE3D = 10, FAM_XRAY3D = 11, FAM_XSIM2D = 13 };
+constexpr bool fam_exact(int f) { return f >= 8; }
+constexpr int fam_base(int f) { return f >= 8 ? f - 8 : f; }
 // families whose count pass stores per-entry pass masks and whose
 // compaction copies entries unchanged (the surfaces do not change below the
 // root)
@@ -82,6 +82,8 @@ struct Item {
 struct __attribute__((aligned(16))) EntL2 { int32_t K, F, w, _; };                 // LINE2D
 struct __attribute__((aligned(16))) EntP3 { int32_t K1, K2, F, w; };               // PLANE3D
 struct __attribute__((aligned(8))) EntR3 { int32_t K1, K2, F1, F2, w, tag; };     // RAY3D: K_q over axis tag
+// SIM2D: K[q][i] of dependent axes c, d over parameter axes a, b
+struct __attribute__((aligned(16))) EntS2 { int32_t K00, K01, K10, K11, F0, F1, w, _; };
 
 // POSE4DOF entries: quantized parameters, weight, index of the root record.
 struct __attribute__((aligned(16))) EntQ32 { float W1, W2, W3, xi, eta; uint32_t w, ridx, _; };
@@ -95,18 +97,21 @@ template <typename E> __device__ inline uint32_t pose_w(const E& e) { return e.w
 template <> __device__ inline uint32_t pose_w<EntQ24>(const EntQ24&) { return 1u; }
 struct __attribute__((aligned(16))) EntQ64 { double W1, W2, W3, xi, eta; uint32_t w, ridx; };
 
-// Exact-mode linear entry: the root-quantized binary64 parameters.
-//   LINE2D  a = t,   f0 = f
-//   PLANE3D a = t1,  b = t2, f0 = f
-//   RAY3D   a = t of the first dependent axis, b = t of the second, f0, f1;
-//           tag = parameter axis
-struct __attribute__((aligned(8))) EntX { double a, b, f0, f1; uint32_t w; int32_t tag; };
-static_assert(sizeof(EntX) == 40, "copied as 8-byte words");
+// Exact-mode linear entry: the root-quantized binary64 parameters t[q][i]
+// (slope of dependent axis q over parameter axis i) and f[q].
+//   LINE2D  t00 = t,  f0 = f
+//   PLANE3D t00 = t1, t01 = t2, f0 = f
+//   RAY3D   t00 = t of the first dependent axis, t10 = of the second; tag =
+//           parameter axis
+//   SIM2D   t00, t01 (axis c over a, b), t10, t11 (axis d), f0, f1
+struct __attribute__((aligned(16))) EntX { double t00, t01, t10, t11, f0, f1; uint32_t w; int32_t tag; };
+static_assert(sizeof(EntX) == 64, "copied as 16-byte words");
 
 template <int FAM> struct EntOf;
 template <> struct EntOf<FAM_LINE2D> { using T = EntL2; };
 template <> struct EntOf<FAM_PLANE3D> { using T = EntP3; };
 template <> struct EntOf<FAM_RAY3D> { using T = EntR3; };
+template <> struct EntOf<FAM_SIM2D> { using T = EntS2; };
 
 // Packed linear entries for the deeper levels, once the host has shown
 // that every lattice value of a level fits (8 bytes instead of 16):
@@ -169,6 +174,17 @@ __device__ inline bool front_eval(int fam, const double* const* col, int64_t i, 
     t[0] = -((x * P.E[0]) * P.inv[2]);
     t[1] = -((y * P.E[1]) * P.inv[2]);
     f[0] = (((z - x * P.lo[0]) - y * P.lo[1]) - P.lo[2]) * P.inv[2];
+  } else if (fam == FAM_SIM2D) {
+    // q_x = a p_x + b p_y + c, q_y = -b p_x + a p_y + d:
+    // c = q_x - a p_x - b p_y, d = q_y + b p_x - a p_y
+    double px = col[0][i], py = col[1][i], qx = col[2][i], qy = col[3][i];
+    if (!isfinite(px) || !isfinite(py) || !isfinite(qx) || !isfinite(qy)) return false;
+    t[0] = -((px * P.E[0]) * P.inv[2]);
+    t[1] = -((py * P.E[1]) * P.inv[2]);
+    f[0] = (((qx - px * P.lo[0]) - py * P.lo[1]) - P.lo[2]) * P.inv[2];
+    t[2] = -((py * P.E[0]) * P.inv[3]);
+    t[3] = (px * P.E[1]) * P.inv[3];
+    f[1] = (((qy - py * P.lo[0]) + px * P.lo[1]) - P.lo[3]) * P.inv[3];
   } else if (fam == FAM_RAY3D) {
     double w[3], u[3];
     for (int k = 0; k < 3; k++) {
@@ -210,17 +226,18 @@ struct LinS {
   int32_t w, tag;
 };
 
-template <int FAM> __device__ inline constexpr int nQ() { return FAM == FAM_RAY3D ? 2 : 1; }
-template <int FAM> __device__ inline constexpr int nP() { return FAM == FAM_PLANE3D ? 2 : 1; }
+template <int FAM> __device__ inline constexpr int nQ() { return FAM == FAM_RAY3D || FAM == FAM_SIM2D ? 2 : 1; }
+template <int FAM> __device__ inline constexpr int nP() { return FAM == FAM_PLANE3D || FAM == FAM_SIM2D ? 2 : 1; }
 
 template <int FAM> __device__ inline int Pax(const LinS& s, int pi) {
   if (FAM == FAM_LINE2D) return 0;
-  if (FAM == FAM_PLANE3D) return pi;
+  if (FAM == FAM_PLANE3D || FAM == FAM_SIM2D) return pi;
   return s.tag;
 }
 template <int FAM> __device__ inline int Qax(const LinS& s, int qi) {
   if (FAM == FAM_LINE2D) return 1;
   if (FAM == FAM_PLANE3D) return 2;
+  if (FAM == FAM_SIM2D) return 2 + qi;
   // RAY3D: the two non-parameter axes, ascending
   int t = s.tag;
   return qi == 0 ? (t == 0 ? 1 : 0) : (t == 2 ? 1 : 2);
@@ -249,6 +266,12 @@ template <int FAM> __device__ __host__ inline LinS load_ent(const EntP3& e) {
 template <int FAM> __device__ __host__ inline LinS load_ent(const EntR3& e) {
   LinS s = lin_zero<FAM>();
   s.K[0][0] = e.K1; s.K[1][0] = e.K2; s.F[0] = e.F1; s.F[1] = e.F2; s.w = e.w; s.tag = e.tag;
+  return s;
+}
+template <int FAM> __device__ __host__ inline LinS load_ent(const EntS2& e) {
+  LinS s = lin_zero<FAM>();
+  s.K[0][0] = e.K00; s.K[0][1] = e.K01; s.K[1][0] = e.K10; s.K[1][1] = e.K11;
+  s.F[0] = e.F0; s.F[1] = e.F1; s.w = e.w;
   return s;
 }
 template <int FAM> __device__ __host__ inline LinS load_ent(const EntL2p& e) {
@@ -289,6 +312,12 @@ template <> __device__ __host__ inline EntP3 store_ent<FAM_PLANE3D, EntP3>(const
 template <> __device__ __host__ inline EntR3 store_ent<FAM_RAY3D, EntR3>(const LinS& s, bool&) {
   EntR3 e;
   e.K1 = s.K[0][0]; e.K2 = s.K[1][0]; e.F1 = s.F[0]; e.F2 = s.F[1]; e.w = s.w; e.tag = s.tag;
+  return e;
+}
+template <> __device__ __host__ inline EntS2 store_ent<FAM_SIM2D, EntS2>(const LinS& s, bool&) {
+  EntS2 e;
+  e.K00 = s.K[0][0]; e.K01 = s.K[0][1]; e.K10 = s.K[1][0]; e.K11 = s.K[1][1];
+  e.F0 = s.F[0]; e.F1 = s.F[1]; e.w = s.w; e._ = 0;
   return e;
 }
 template <> __device__ __host__ inline EntL2p store_ent<FAM_LINE2D, EntL2p>(const LinS& s, bool& ok) {
@@ -401,13 +430,16 @@ __device__ inline bool x_axis(double f, double t0, int j0, double t1, int j1, in
 template <int BF>
 __device__ inline bool x_meets(const EntX& e, const double* lo, const double* hi, const double* xpad) {
   if constexpr (BF == FAM_LINE2D) {
-    return x_axis(e.f0, e.a, 0, 0.0, -1, 1, lo, hi, xpad[1]);
+    return x_axis(e.f0, e.t00, 0, 0.0, -1, 1, lo, hi, xpad[1]);
   } else if constexpr (BF == FAM_PLANE3D) {
-    return x_axis(e.f0, e.a, 0, e.b, 1, 2, lo, hi, xpad[2]);
+    return x_axis(e.f0, e.t00, 0, e.t01, 1, 2, lo, hi, xpad[2]);
+  } else if constexpr (BF == FAM_SIM2D) {
+    return x_axis(e.f0, e.t00, 0, e.t01, 1, 2, lo, hi, xpad[2]) && x_axis(e.f1, e.t10, 0, e.t11, 1, 3, lo, hi, xpad[3]);
   } else {
     const int t = e.tag;
     const int q0 = t == 0 ? 1 : 0, q1 = t == 2 ? 1 : 2;
-    return x_axis(e.f0, e.a, t, 0.0, -1, q0, lo, hi, xpad[q0]) && x_axis(e.f1, e.b, t, 0.0, -1, q1, lo, hi, xpad[q1]);
+    return x_axis(e.f0, e.t00, t, 0.0, -1, q0, lo, hi, xpad[q0]) &&
+           x_axis(e.f1, e.t10, t, 0.0, -1, q1, lo, hi, xpad[q1]);
   }
 }
 

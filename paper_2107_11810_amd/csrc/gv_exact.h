@@ -19,14 +19,14 @@ template <int BF>
 __device__ inline bool root_x(const ProbC& P, const double* const* col, int64_t i, EntX& e, int* bad) {
   double t[4], f[2];
   int32_t tag;
-  e = EntX{0.0, 0.0, 0.0, 0.0, 1u, 0};
+  e = EntX{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1u, 0};
   if (!front_eval(BF, col, i, P, t, f, &tag)) {
     atomicOr(bad, 1);
     return false;
   }
   const double s = 0x1p-36, inv = 0x1p36, u = 0.0;
   // parameters per dependent axis: (slopes, offset)
-  const int nq = BF == FAM_RAY3D ? 2 : 1, np = BF == FAM_PLANE3D ? 2 : 1;
+  const int nq = BF == FAM_RAY3D || BF == FAM_SIM2D ? 2 : 1, np = BF == FAM_PLANE3D || BF == FAM_SIM2D ? 2 : 1;
   double out_t[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, out_f[2] = {0.0, 0.0};
   double M = 0.0;
   for (int qi = 0; qi < nq; qi++) {
@@ -48,9 +48,7 @@ __device__ inline bool root_x(const ProbC& P, const double* const* col, int64_t 
     M = mq > M ? mq : M;
   }
   if (!(M < 0x1p12)) atomicOr(bad, 2);  // beyond the range the definition evaluates exactly
-  if (BF == FAM_LINE2D) e = EntX{out_t[0][0], 0.0, out_f[0], 0.0, 1u, 0};
-  else if (BF == FAM_PLANE3D) e = EntX{out_t[0][0], out_t[0][1], out_f[0], 0.0, 1u, 0};
-  else e = EntX{out_t[0][0], out_t[1][0], out_f[0], out_f[1], 1u, tag};
+  e = EntX{out_t[0][0], out_t[0][1], out_t[1][0], out_t[1][1], out_f[0], out_f[1], 1u, tag};
   return true;
 }
 
@@ -58,14 +56,18 @@ __device__ inline bool root_x(const ProbC& P, const double* const* col, int64_t 
 template <> struct Tuple<EntX> {
   __device__ static uint64_t hash(const EntX& e) {
     uint64_t h = hcomb(8, (uint32_t)e.tag);
-    h = hcomb(h, (uint64_t)__double_as_longlong(e.a));
-    h = hcomb(h, (uint64_t)__double_as_longlong(e.b));
+    h = hcomb(h, (uint64_t)__double_as_longlong(e.t00));
+    h = hcomb(h, (uint64_t)__double_as_longlong(e.t01));
+    h = hcomb(h, (uint64_t)__double_as_longlong(e.t10));
+    h = hcomb(h, (uint64_t)__double_as_longlong(e.t11));
     h = hcomb(h, (uint64_t)__double_as_longlong(e.f0));
     return hcomb(h, (uint64_t)__double_as_longlong(e.f1));
   }
   __device__ static bool same(const EntX& x, const EntX& y) {
-    return x.tag == y.tag && __double_as_longlong(x.a) == __double_as_longlong(y.a) &&
-           __double_as_longlong(x.b) == __double_as_longlong(y.b) &&
+    return x.tag == y.tag && __double_as_longlong(x.t00) == __double_as_longlong(y.t00) &&
+           __double_as_longlong(x.t01) == __double_as_longlong(y.t01) &&
+           __double_as_longlong(x.t10) == __double_as_longlong(y.t10) &&
+           __double_as_longlong(x.t11) == __double_as_longlong(y.t11) &&
            __double_as_longlong(x.f0) == __double_as_longlong(y.f0) &&
            __double_as_longlong(x.f1) == __double_as_longlong(y.f1);
   }
@@ -88,13 +90,14 @@ __global__ void k_root_x(const ProbC* __restrict__ Pp, Cols cols, int64_t n, Ent
 // children (stored for the compaction), per child the summed multiplicities
 // (one atomic per item and child) and the item's survivors (for the
 // compaction's write offsets).
-template <int BF, bool UNIT>
+template <int BF, bool UNIT, typename M>
 __global__ void __launch_bounds__(256) k_count_x(const ProbC* __restrict__ Ptab, int m, LevelC lv,
                                                  const Cell* __restrict__ cells, const Item* __restrict__ items,
                                                  const uint32_t* __restrict__ nitems_p, const EntX* __restrict__ ents,
-                                                 uint8_t* __restrict__ masks, uint32_t* __restrict__ ccnt,
+                                                 M* __restrict__ masks, uint32_t* __restrict__ ccnt,
                                                  uint32_t* __restrict__ cnent, uint32_t* __restrict__ itemcnt,
                                                  uint32_t istride) {
+  constexpr int NC = 8 * (int)sizeof(M);  // children a mask holds (8, or 16 for four split axes)
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -104,9 +107,9 @@ __global__ void __launch_bounds__(256) k_count_x(const ProbC* __restrict__ Ptab,
     const Item I = items[it];
     const Cell C = cells[I.cell];
     const ProbC& P = Ptab[C.prob];
-    uint32_t aw[8], an[8];
+    uint32_t aw[NC], an[NC];
 #pragma unroll
-    for (int ch = 0; ch < 8; ch++) { aw[ch] = 0; an[ch] = 0; }
+    for (int ch = 0; ch < NC; ch++) { aw[ch] = 0; an[ch] = 0; }
     for (uint32_t k0 = 0; k0 < I.cnt; k0 += 64) {
       const uint32_t k = k0 + lane;
       uint32_t mask = 0, w = 0;
@@ -118,10 +121,10 @@ __global__ void __launch_bounds__(256) k_count_x(const ProbC* __restrict__ Ptab,
           x_child_box(P, lv, C.c, m, lv.cbits[ch], lo, hi);
           if (x_meets<BF>(e, lo, hi, P.xpad)) mask |= 1u << ch;
         }
-        masks[I.off + k] = (uint8_t)mask;
+        masks[I.off + k] = (M)mask;
       }
 #pragma unroll
-      for (int ch = 0; ch < 8; ch++) {
+      for (int ch = 0; ch < NC; ch++) {
         const bool p = (mask >> ch) & 1u;
         if constexpr (UNIT) {
           an[ch] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
@@ -132,7 +135,7 @@ __global__ void __launch_bounds__(256) k_count_x(const ProbC* __restrict__ Ptab,
       }
     }
 #pragma unroll
-    for (int ch = 0; ch < 8; ch++) {
+    for (int ch = 0; ch < NC; ch++) {
       if ((uint32_t)ch < nch) {
         const uint32_t n = UNIT ? an[ch] : wave_sum_u32(an[ch]);
         const uint32_t w = UNIT ? n : wave_sum_u32(aw[ch]);

@@ -1306,6 +1306,21 @@ template <> struct Tuple<EntR3> {
   __device__ static void setw(EntR3& e, uint32_t w) { e.w = (int32_t)w; }
   __device__ static uint32_t w(const EntR3& e) { return (uint32_t)e.w; }
 };
+template <> struct Tuple<EntS2> {
+  __device__ static uint64_t hash(const EntS2& e) {
+    uint64_t h = hcomb(9, (uint32_t)e.K00);
+    h = hcomb(h, (uint32_t)e.K01);
+    h = hcomb(h, (uint32_t)e.K10);
+    h = hcomb(h, (uint32_t)e.K11);
+    h = hcomb(h, (uint32_t)e.F0);
+    return hcomb(h, (uint32_t)e.F1);
+  }
+  __device__ static bool same(const EntS2& a, const EntS2& b) {
+    return a.K00 == b.K00 && a.K01 == b.K01 && a.K10 == b.K10 && a.K11 == b.K11 && a.F0 == b.F0 && a.F1 == b.F1;
+  }
+  __device__ static void setw(EntS2& e, uint32_t w) { e.w = (int32_t)w; }
+  __device__ static uint32_t w(const EntS2& e) { return (uint32_t)e.w; }
+};
 template <> struct Tuple<EntQ32> {
   __device__ static uint64_t hash(const EntQ32& e) {
     uint64_t h = hcomb(4, __float_as_uint(e.W1));

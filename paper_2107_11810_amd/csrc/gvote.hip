@@ -303,6 +303,7 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
     case GV_LINE2D: S.d = 2; S.ell = 1; break;
     case GV_PLANE3D: S.d = 3; S.ell = 2; break;
     case GV_RAY3D: S.d = 3; S.ell = 2; break;
+    case GV_SIM2D: S.d = 4; S.ell = 2; break;
     case GV_POSE4DOF: S.d = 4; S.ell = 4; break;
     default: why = "bad family"; return GV_EINVAL;
   }
@@ -1010,24 +1011,32 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
 #undef GV_COUNT_POSE
   } else if constexpr (fam_exact(FAM)) {
     if (b.unit)
-      k_count_x<fam_base(FAM), true><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems,
-                                                            (const EntX*)b.ents, (uint8_t*)pa->masks, ccnt, pa->cnent,
+      k_count_x<fam_base(FAM), true, M><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems,
+                                                            (const EntX*)b.ents, (M*)pa->masks, ccnt, pa->cnent,
                                                             itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u);
     else
-      k_count_x<fam_base(FAM), false><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems,
-                                                             (const EntX*)b.ents, (uint8_t*)pa->masks, ccnt,
+      k_count_x<fam_base(FAM), false, M><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems,
+                                                             (const EntX*)b.ents, (M*)pa->masks, ccnt,
                                                              pa->cnent, itemcnt ? itemcnt : X.dummy,
                                                              itemcnt ? pa->istride : 0u);
   } else {
 #define GV_COUNT_LIN(U, N) \
   k_count_lin<FAM, U, E, N><<<grid, 256, 0, X.st>>>(lv, pa->items, pa->nitems, (const E*)b.ents, itemcnt, itemw)
-    switch ((b.unit ? 16 : 0) | nch) {
-      case 16 | 2: GV_COUNT_LIN(true, 2); break;
-      case 16 | 4: GV_COUNT_LIN(true, 4); break;
-      case 16 | 8: GV_COUNT_LIN(true, 8); break;
+    switch ((b.unit ? 32 : 0) | nch) {
+      case 32 | 2: GV_COUNT_LIN(true, 2); break;
+      case 32 | 4: GV_COUNT_LIN(true, 4); break;
+      case 32 | 8: GV_COUNT_LIN(true, 8); break;
       case 2: GV_COUNT_LIN(false, 2); break;
       case 4: GV_COUNT_LIN(false, 4); break;
       case 8: GV_COUNT_LIN(false, 8); break;
+      case 32 | 16:
+        if constexpr (FAM == FAM_SIM2D) GV_COUNT_LIN(true, 16);
+        else throw DevErr{GV_EINVAL};
+        break;
+      case 16:
+        if constexpr (FAM == FAM_SIM2D) GV_COUNT_LIN(false, 16);
+        else throw DevErr{GV_EINVAL};
+        break;
       default: throw DevErr{GV_EINVAL};
     }
 #undef GV_COUNT_LIN
@@ -1040,13 +1049,15 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
 #define GV_CELL_SCAN(U, N)                                                                                      \
   k_cell_scan<N, U><<<nblk((uint64_t)b.ncell * N), 256, 0, X.st>>>(b.cells, b.ncell, pa->ioff, itemcnt, itemw,  \
                                                                    pa->itemoff, ccnt, pa->cnent)
-    switch ((b.unit ? 16 : 0) | nch) {
-      case 16 | 2: GV_CELL_SCAN(true, 2); break;
-      case 16 | 4: GV_CELL_SCAN(true, 4); break;
-      case 16 | 8: GV_CELL_SCAN(true, 8); break;
+    switch ((b.unit ? 32 : 0) | nch) {
+      case 32 | 2: GV_CELL_SCAN(true, 2); break;
+      case 32 | 4: GV_CELL_SCAN(true, 4); break;
+      case 32 | 8: GV_CELL_SCAN(true, 8); break;
+      case 32 | 16: GV_CELL_SCAN(true, 16); break;
       case 2: GV_CELL_SCAN(false, 2); break;
       case 4: GV_CELL_SCAN(false, 4); break;
       case 8: GV_CELL_SCAN(false, 8); break;
+      case 16: GV_CELL_SCAN(false, 16); break;
       default: throw DevErr{GV_EINVAL};
     }
 #undef GV_CELL_SCAN
@@ -1343,6 +1354,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
         case 2: GV_WORK(2); break;
         case 4: GV_WORK(4); break;
         case 8: GV_WORK(8); break;
+        case 16: GV_WORK(16); break;
         default: throw DevErr{GV_EINVAL};
       }
 #undef GV_WORK
@@ -1366,6 +1378,10 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
         case 2: GV_COMPACT_LIN(2); break;
         case 4: GV_COMPACT_LIN(4); break;
         case 8: GV_COMPACT_LIN(8); break;
+        case 16:
+          if constexpr (FAM == FAM_SIM2D) GV_COMPACT_LIN(16);
+          else throw DevErr{GV_EINVAL};
+          break;
         default: throw DevErr{GV_EINVAL};
       }
 #undef GV_COMPACT_LIN
@@ -1507,7 +1523,8 @@ gv_status prepare_problem(ProbRec* pr) {
       pr->err = "missing column";
       return GV_EINVAL;
     }
-  const uint64_t eb = pr->S.fam == GV_POSE4DOF ? 4 * (80 + 2 * 34) : (pr->S.fam == GV_RAY3D ? 4 * 26 : 4 * 18);
+  const uint64_t eb = pr->S.fam == GV_POSE4DOF ? 4 * (80 + 2 * 34)
+                      : (pr->S.fam == GV_SIM2D ? 4 * 34 : (pr->S.fam == GV_RAY3D ? 4 * 26 : 4 * 18));
   pr->est_bytes = (uint64_t)std::max<int64_t>(pr->n, 1) * eb + (64ull << 20);
   return GV_OK;
 }
@@ -1844,7 +1861,7 @@ void build_linear(Run& X) {
     Hmax = std::max(Hmax, (double)P.lev[0].H[j]);
     padmax = std::max(padmax, (double)P.lev[0].padu[j]);
   }
-  const double npar = (FAM == FAM_PLANE3D) ? 2.0 : 1.0;
+  const double npar = (FAM == FAM_PLANE3D || FAM == FAM_SIM2D) ? 2.0 : 1.0;
   unsigned mk_all = 0;
   for (uint32_t p = 0; p < np; p++) {
     ProbRec* pr = X.probs[p];
@@ -1869,12 +1886,13 @@ void build_linear(Run& X) {
   X.lat_bound[0] = 1e300;
   for (int m = 1; m <= P.Lstar; m++) {
     double D = (FAM == FAM_RAY3D) ? 3.0 : 1.0;
-    const int nq = (FAM == FAM_RAY3D) ? 2 : 1, npp = (FAM == FAM_PLANE3D) ? 2 : 1;
+    const int nq = (FAM == FAM_RAY3D || FAM == FAM_SIM2D) ? 2 : 1;
+    const int npp = (FAM == FAM_PLANE3D || FAM == FAM_SIM2D) ? 2 : 1;
     for (int qi = 0; qi < nq; qi++) {
-      const int q = (FAM == FAM_LINE2D) ? 1 : 2;
+      const int q = (FAM == FAM_LINE2D) ? 1 : (FAM == FAM_SIM2D ? 2 + qi : 2);
       double ks = 0.0, kprod = 1.0;
       for (int pi = 0; pi < npp; pi++) {
-        const int pax = (FAM == FAM_PLANE3D) ? pi : 0;
+        const int pax = (FAM == FAM_PLANE3D || FAM == FAM_SIM2D) ? pi : 0;
         const double km = std::ceil((double)mk_all / std::ldexp(1.0, std::min(m, P.L[pax]))) + 1.0;
         ks += km;
         kprod *= 2.0 * km + 1.0;
@@ -1954,7 +1972,9 @@ void build_exact(Run& X) {
     }
   }
   X.root = root;
-  if (!X.root_only) start_search<BF + 4, EntX, uint8_t>(X);
+  // sixteen children when all four axes of the similarity family split
+  using M = std::conditional_t<BF == FAM_SIM2D, uint16_t, uint8_t>;
+  if (!X.root_only) start_search<BF + 8, EntX, M>(X);
 }
 
 template <typename E>
@@ -2070,12 +2090,14 @@ void epoch_finish(Run& X) {
       switch (X.fam) {
         case GV_LINE2D: k_replay_x<FAM_LINE2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
         case GV_PLANE3D: k_replay_x<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+        case GV_SIM2D: k_replay_x<FAM_SIM2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
         default: k_replay_x<FAM_RAY3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
       }
     } else switch (X.fam) {
       case GV_LINE2D: k_replay_lin<FAM_LINE2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
       case GV_PLANE3D: k_replay_lin<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
       case GV_RAY3D: k_replay_lin<FAM_RAY3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+      case GV_SIM2D: k_replay_lin<FAM_SIM2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
       default: k_replay_pose<<<gg, 256, 0, X.st>>>(X.dP, X.m64, X.Ntot, X.dooff, np, dpaths, flag); break;
     }
     HIPCHK(hipGetLastError());
@@ -2186,6 +2208,7 @@ std::function<bool(Run&)> epoch_build(Run& X) {
     switch (X.fam) {
       case GV_LINE2D: build_exact<FAM_LINE2D>(X); return epoch_step<FAM_XLINE2D, EntX, uint8_t>;
       case GV_PLANE3D: build_exact<FAM_PLANE3D>(X); return epoch_step<FAM_XPLANE3D, EntX, uint8_t>;
+      case GV_SIM2D: build_exact<FAM_SIM2D>(X); return epoch_step<FAM_XSIM2D, EntX, uint16_t>;
       default: build_exact<FAM_RAY3D>(X); return epoch_step<FAM_XRAY3D, EntX, uint8_t>;
     }
   }
@@ -2193,6 +2216,7 @@ std::function<bool(Run&)> epoch_build(Run& X) {
     case GV_LINE2D: build_linear<FAM_LINE2D>(X); return epoch_step<FAM_LINE2D, EntL2, uint8_t>;
     case GV_PLANE3D: build_linear<FAM_PLANE3D>(X); return epoch_step<FAM_PLANE3D, EntP3, uint8_t>;
     case GV_RAY3D: build_linear<FAM_RAY3D>(X); return epoch_step<FAM_RAY3D, EntR3, uint8_t>;
+    case GV_SIM2D: build_linear<FAM_SIM2D>(X); return epoch_step<FAM_SIM2D, EntS2, uint8_t>;
     default:
       if (build_pose(X)) return step_pose<EntQ32>;
       return step_pose<EntQ64>;
@@ -2242,7 +2266,7 @@ void fill_result(const ProbRec* pr, gv_result* r) {
   } else {
     const int npar = pr->S.fam == GV_PLANE3D ? 2 : 1;
     for (int q = 0; q < pr->S.d; q++) {
-      const bool dep = pr->S.fam == GV_RAY3D || q == pr->S.d - 1;
+      const bool dep = pr->S.fam == GV_RAY3D || (pr->S.fam == GV_SIM2D ? q >= 2 : q == pr->S.d - 1);
       if (!dep) continue;
       double b;
       if (pr->S.exact) {
@@ -2851,12 +2875,14 @@ gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t 
         switch (pr.S.fam) {
           case GV_LINE2D: build_exact<FAM_LINE2D>(X); break;
           case GV_PLANE3D: build_exact<FAM_PLANE3D>(X); break;
+          case GV_SIM2D: build_exact<FAM_SIM2D>(X); break;
           default: build_exact<FAM_RAY3D>(X); break;
         }
       } else {
         switch (pr.S.fam) {
           case GV_LINE2D: build_linear<FAM_LINE2D>(X); break;
           case GV_PLANE3D: build_linear<FAM_PLANE3D>(X); break;
+          case GV_SIM2D: build_linear<FAM_SIM2D>(X); break;
           default: build_linear<FAM_RAY3D>(X); break;
         }
       }
@@ -2874,12 +2900,13 @@ gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t 
           switch (pr.S.fam) {
             case GV_LINE2D: k_incidence_x<FAM_LINE2D><<<gg, 256, 0, X.st>>>(X.dP, (const EntX*)X.root, pr.n, C, level, dm); break;
             case GV_PLANE3D: k_incidence_x<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, (const EntX*)X.root, pr.n, C, level, dm); break;
+            case GV_SIM2D: k_incidence_x<FAM_SIM2D><<<gg, 256, 0, X.st>>>(X.dP, (const EntX*)X.root, pr.n, C, level, dm); break;
             default: k_incidence_x<FAM_RAY3D><<<gg, 256, 0, X.st>>>(X.dP, (const EntX*)X.root, pr.n, C, level, dm); break;
           }
         } else {
 #define GV_INC(F, N) \
   k_incidence_lin<F, typename EntOf<F>::T, N><<<gg, 256, 0, X.st>>>(X.dP, (const typename EntOf<F>::T*)X.root, pr.n, path, level, dm)
-          switch (pr.S.fam * 16 + (int)nch) {
+          switch (pr.S.fam == GV_SIM2D ? pr.S.fam * 32 + (int)nch : pr.S.fam * 16 + (int)nch) {
             case GV_LINE2D * 16 + 2: GV_INC(FAM_LINE2D, 2); break;
             case GV_LINE2D * 16 + 4: GV_INC(FAM_LINE2D, 4); break;
             case GV_PLANE3D * 16 + 2: GV_INC(FAM_PLANE3D, 2); break;
@@ -2888,6 +2915,10 @@ gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t 
             case GV_RAY3D * 16 + 2: GV_INC(FAM_RAY3D, 2); break;
             case GV_RAY3D * 16 + 4: GV_INC(FAM_RAY3D, 4); break;
             case GV_RAY3D * 16 + 8: GV_INC(FAM_RAY3D, 8); break;
+            case GV_SIM2D * 32 + 2: GV_INC(FAM_SIM2D, 2); break;
+            case GV_SIM2D * 32 + 4: GV_INC(FAM_SIM2D, 4); break;
+            case GV_SIM2D * 32 + 8: GV_INC(FAM_SIM2D, 8); break;
+            case GV_SIM2D * 32 + 16: GV_INC(FAM_SIM2D, 16); break;
             default: throw DevErr{GV_EINVAL};
           }
 #undef GV_INC

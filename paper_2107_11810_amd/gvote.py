@@ -15,9 +15,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgvote.so")
 
-LINE2D, PLANE3D, RAY3D, POSE4DOF = 1, 2, 3, 4
-FAMILIES = {"line2d": LINE2D, "plane3d": PLANE3D, "ray3d": RAY3D, "pose4dof": POSE4DOF}
-NCOLS = {LINE2D: 2, PLANE3D: 3, RAY3D: 6, POSE4DOF: 5}
+LINE2D, PLANE3D, RAY3D, POSE4DOF, SIM2D = 1, 2, 3, 4, 5
+FAMILIES = {"line2d": LINE2D, "plane3d": PLANE3D, "ray3d": RAY3D, "pose4dof": POSE4DOF, "sim2d": SIM2D}
+NCOLS = {LINE2D: 2, PLANE3D: 3, RAY3D: 6, POSE4DOF: 5, SIM2D: 4}
 FP64_PLAIN, FP32_FILTER = 0, 1
 
 STATUS = {0: "GV_OK", -1: "GV_EINVAL", -2: "GV_ENOMEM", -3: "GV_ETOOBIG", -4: "GV_EBUFSZ",

@@ -75,7 +75,7 @@ def _random_cells(g, rng, k):
 
 
 @pytest.mark.parametrize("name", ["line2d_small", "plane3d_small", "ray3d_small", "pose4dof_small", "line2d_tiny",
-                                  "ray3d_tiny", "pose4dof_small_flat"])
+                                  "ray3d_tiny", "pose4dof_small_flat", "sim2d_tiny", "sim2d_small"])
 @pytest.mark.parametrize("exact", [False, True])
 def test_incidence_masks_equal_the_oracle(ctx, name, exact):
     g = synth.config(name)
@@ -265,7 +265,7 @@ def test_binary32_filter_at_the_thresholds(ctx, kind):
 # ----------------------------------------------------------------------------
 # Exact mode
 # ----------------------------------------------------------------------------
-FAMS = ["line2d", "plane3d", "ray3d", "pose4dof"]
+FAMS = ["line2d", "plane3d", "ray3d", "pose4dof", "sim2d"]
 
 
 @pytest.mark.parametrize("fam", FAMS)
@@ -306,7 +306,7 @@ def test_exact_mode_equals_plain_definition(ctx):
 # Certified bound
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("name", ["line2d_small", "plane3d_small", "ray3d_small", "pose4dof_small", "line2d_10k",
-                                  "pose4dof_small_flat", "pose4dof_tiny"])
+                                  "pose4dof_small_flat", "pose4dof_tiny", "sim2d_small"])
 @pytest.mark.parametrize("exact", [False, True])
 def test_every_inlier_within_the_reported_bound(ctx, name, exact):
     g = synth.config(name)
@@ -334,7 +334,7 @@ def test_every_inlier_within_the_reported_bound(ctx, name, exact):
             for q, dist in TB._lin_distances(g, int(i), blo, bhi):
                 assert dist[0] <= bound[q] * (1 + 1e-9), (i, q, float(dist[0]), bound[q])
         for q in range(d):
-            if g["family"] == "ray3d" or q == d - 1:
+            if g["family"] == "ray3d" or (q >= 2 if g["family"] == "sim2d" else q == d - 1):
                 assert g["eps"][q] <= bound[q] <= (2.0 * g["eps"][q] + 1e-9) * (1.0 if not exact else 1.0)
         return
     ez, ek, pzm, pkm, Rg = TB.pose_bounds(g)

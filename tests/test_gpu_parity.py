@@ -44,7 +44,7 @@ def check_same(g, r_gpu, r_or):
         assert r_gpu["point"][j] == r_or["point"][j]  # bit-equal binary64
 
 
-FAMS = ["line2d", "plane3d", "ray3d", "pose4dof"]
+FAMS = ["line2d", "plane3d", "ray3d", "pose4dof", "sim2d"]
 
 
 @pytest.mark.parametrize("name", [f + "_small" for f in FAMS] + ["line2d_10k"])

@@ -31,11 +31,15 @@ def OP(g, **kw):
 
 
 @pytest.mark.parametrize("name", ["line2d_tiny", "plane3d_tiny", "ray3d_tiny", "pose4dof_tiny", "line2d_small",
-                                  "ray3d_small", "pose4dof_small", "plane3d_small"])
+                                  "ray3d_small", "pose4dof_small", "plane3d_small", "sim2d_tiny", "sim2d_small"])
 def test_report_equals_oracle(ctx, name):
     g = synth.config(name)
     best = oracle.solve(OP(g))["count"]
-    for tau in sorted({max(1, best // 4), max(1, best // 2), best, best + 1}):
+    taus = {max(1, best // 4), max(1, best // 2), best, best + 1}
+    if name == "sim2d_small":
+        # four free parameters: tens of thousands of leaves already at half the best count
+        taus = {3 * best // 4, best, best + 1}
+    for tau in sorted(taus):
         _say("report", name, tau)
         io, co = oracle.report(OP(g), tau)
         for prec in (0, 1):
@@ -43,7 +47,7 @@ def test_report_equals_oracle(ctx, name):
             assert np.array_equal(ig, io), (tau, prec, len(ig), len(io))
             assert np.array_equal(cg, co)
     # exact mode
-    tau = max(1, best // 2)
+    tau = 3 * best // 4 if name == "sim2d_small" else max(1, best // 2)
     io, co = oracle.report(OP(g, canon_c=math.inf), tau)
     ig, cg, _ = ctx.report(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], tau, canon_c=math.inf)
     assert np.array_equal(ig, io) and np.array_equal(cg, co)
