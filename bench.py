@@ -41,6 +41,9 @@ WORKLOADS = {
                        compact="k_compact_lin<RAY3D>", bound="hbm"),
     "line2d_10k": dict(desc="2D line fitting by duality: 1e4 points, 5% inliers", kernel="k_count_lin<LINE2D>",
                        compact="k_compact_lin<LINE2D>", bound="hbm"),
+    "sim2d_90k": dict(desc="similarity pointset alignment: 10,000 points, 9 candidate correspondences each (90,000 "
+                           "surfaces), 1,000 true pairs under a planted similarity with noise 0.002, eps 0.01 on "
+                           "(a, b, c, d)", kernel="k_count_lin<SIM2D>", compact="k_compact_lin<SIM2D>", bound="hbm"),
     "pose4dof_serve256": dict(desc="256 independent 4-DoF pose problems, matches log-uniform in [1e3, 2e5], inlier "
                                    "ratio log-uniform in [0.2%, 10%], served through gv_submit/gv_poll",
                               kernel="k_count_pose<POSE4DOF>", bound="alu"),

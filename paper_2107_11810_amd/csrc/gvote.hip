@@ -203,6 +203,7 @@ constexpr int kTuneCand[] = {2, 4, 8, 16, 32};
 constexpr int kNCand = 5;
 constexpr int kTuneSamples = 4;
 constexpr uint64_t kTuneMinBytes = 256ull << 20;  // smaller launches use the default shape
+constexpr int kLastFam = GV_SIM2D;                 // family codes run 1..kLastFam
 constexpr int kGridDefault = 8;
 struct gvi_tune_slot {
   int chosen = 0;  // blocks per CU once chosen
@@ -248,10 +249,10 @@ struct gv_ctx {
   uint64_t batch_n = 0;
   // packed 8-byte list entries where the lattice bounds allow (GV_PACK=0 off)
   bool pack = true;
-  // launch-shape autotuner: per family (index 1..4) and kernel (0 count,
-  // 1 compaction)
+  // launch-shape autotuner: per family (index 1..kLastFam) and kernel
+  // (0 count, 1 compaction)
   std::mutex tmu;
-  gvi_tune_slot tune[5][2];
+  gvi_tune_slot tune[kLastFam + 1][2];
   bool autotune = true;
   uint64_t tune_min = kTuneMinBytes;  // launches of fewer entry bytes are not tuning samples
   std::string tune_path;   // autotune cache file ("" = keep choices in memory)
@@ -752,7 +753,7 @@ uint64_t d2h1(Run& X, const T* p) {
 }
 
 // Autotune cache file: one line per choice,
-//   <arch> <compute units> <family 1..4> <kernel 0 count | 1 compaction> <blocks per CU>
+//   <arch> <compute units> <family 1..kLastFam> <kernel 0 count | 1 compaction> <blocks per CU>
 void tune_load(gv_ctx* c) {
   if (c->tune_path.empty()) return;
   FILE* f = std::fopen(c->tune_path.c_str(), "r");
@@ -760,7 +761,7 @@ void tune_load(gv_ctx* c) {
   char arch[128];
   int ncu, fam, kind, gpc;
   while (std::fscanf(f, "%127s %d %d %d %d", arch, &ncu, &fam, &kind, &gpc) == 5) {
-    if (c->arch != arch || ncu != c->n_cu || fam < 1 || fam > 4 || kind < 0 || kind > 1) continue;
+    if (c->arch != arch || ncu != c->n_cu || fam < 1 || fam > kLastFam || kind < 0 || kind > 1) continue;
     for (int k = 0; k < kNCand; k++)
       if (kTuneCand[k] == gpc) c->tune[fam][kind].chosen = gpc;
   }
@@ -776,7 +777,7 @@ void tune_save(gv_ctx* c) {
     char arch[128];
     int ncu, fam, kind, gpc;
     while (std::fscanf(f, "%127s %d %d %d %d", arch, &ncu, &fam, &kind, &gpc) == 5) {
-      const bool mine = c->arch == arch && ncu == c->n_cu && fam >= 1 && fam <= 4 && kind >= 0 && kind <= 1 &&
+      const bool mine = c->arch == arch && ncu == c->n_cu && fam >= 1 && fam <= kLastFam && kind >= 0 && kind <= 1 &&
                         c->tune[fam][kind].chosen;
       if (!mine) keep.push_back(std::string(arch) + " " + std::to_string(ncu) + " " + std::to_string(fam) + " " +
                                 std::to_string(kind) + " " + std::to_string(gpc));
@@ -787,7 +788,7 @@ void tune_save(gv_ctx* c) {
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return;
   for (const std::string& l : keep) std::fprintf(f, "%s\n", l.c_str());
-  for (int fam = 1; fam <= 4; fam++)
+  for (int fam = 1; fam <= kLastFam; fam++)
     for (int kind = 0; kind < 2; kind++)
       if (c->tune[fam][kind].chosen)
         std::fprintf(f, "%s %d %d %d %d\n", c->arch.c_str(), c->n_cu, fam, kind, c->tune[fam][kind].chosen);

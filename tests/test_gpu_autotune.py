@@ -65,10 +65,11 @@ def read_lines(path):
     return out
 
 
-FAMILY = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4}
+FAMILY = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4, "sim2d": 5}
 
 
-@pytest.mark.parametrize("name", ["plane3d_small", "pose4dof_small"])
+# every family code indexes the tuner's table, the last one included
+@pytest.mark.parametrize("name", ["plane3d_small", "pose4dof_small", "sim2d_small"])
 def test_autotune_cache_and_results(tmp_path, name):
     from paper_2107_11810_amd import gvote
     g = synth.config(name)
@@ -96,7 +97,7 @@ def test_autotune_cache_and_results(tmp_path, name):
     mine = [l for l in lines if l[2] == fam]
     assert {l[3] for l in mine} == {0, 1}, lines
     for arch, ncu, f, k, blocks in lines:
-        assert ncu > 0 and f in (1, 2, 3, 4) and k in (0, 1) and blocks in CANDIDATES
+        assert ncu > 0 and f in FAMILY.values() and k in (0, 1) and blocks in CANDIDATES
     before = open(path).read()
     # choices read back: no more tuning samples, same results, file unchanged
     with Env(GV_TUNE_MIN_BYTES=0):
@@ -109,7 +110,7 @@ def test_autotune_cache_and_results(tmp_path, name):
 
 
 @pytest.mark.parametrize("grid", [1, 2, 32, 64])
-@pytest.mark.parametrize("name", ["line2d_small", "plane3d_small", "ray3d_small", "pose4dof_small"])
+@pytest.mark.parametrize("name", ["line2d_small", "plane3d_small", "ray3d_small", "pose4dof_small", "sim2d_small"])
 def test_fixed_grids_same_result(name, grid):
     from paper_2107_11810_amd import gvote
     g = synth.config(name)
