@@ -17,8 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gv_oracle.c")
 _LIB = os.path.join(_HERE, "libgv_oracle.so")
 
-FAMILIES = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4, "sim2d": 5}
-NCOLS = {1: 2, 2: 3, 3: 6, 4: 5, 5: 4}
+FAMILIES = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4, "sim2d": 5, "pose5dof": 6}
+NCOLS = {1: 2, 2: 3, 3: 6, 4: 5, 5: 4, 6: 5}
+POSE = (4, 6)  # the camera-posing families: four yaw sectors on top of the leaf index
+MAXD = 5
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EBUFSZ", -4: "ERANGE", -5: "EBUDGET"}
 
@@ -39,9 +41,9 @@ class _Problem(ctypes.Structure):
         ("family", ctypes.c_int),
         ("n", ctypes.c_int64),
         ("col", ctypes.POINTER(ctypes.c_double) * 6),
-        ("lo", ctypes.c_double * 4),
-        ("hi", ctypes.c_double * 4),
-        ("eps", ctypes.c_double * 4),
+        ("lo", ctypes.c_double * MAXD),
+        ("hi", ctypes.c_double * MAXD),
+        ("eps", ctypes.c_double * MAXD),
         ("canon_c", ctypes.c_double),
         ("no_prune", ctypes.c_int),
         ("no_group", ctypes.c_int),
@@ -59,11 +61,11 @@ class _Result(ctypes.Structure):
         ("leaf_index", ctypes.c_uint64),
         ("key", ctypes.c_uint64),
         ("sector", ctypes.c_int32),
-        ("leaf_coords", ctypes.c_int32 * 4),
-        ("levels", ctypes.c_int32 * 4),
+        ("leaf_coords", ctypes.c_int32 * MAXD),
+        ("levels", ctypes.c_int32 * MAXD),
         ("lstar", ctypes.c_int32),
         ("index_bits", ctypes.c_int32),
-        ("point", ctypes.c_double * 4),
+        ("point", ctypes.c_double * MAXD),
         ("n_inliers", ctypes.c_int64),
         ("tests", ctypes.c_uint64),
         ("cells_expanded", ctypes.c_uint64),
@@ -123,9 +125,9 @@ class Problem:
         if len(self.cols) != NCOLS[self.family]:
             raise ValueError("wrong number of columns")
         self.n = int(self.cols[0].shape[0]) if self.cols else 0
-        self.lo = list(lo) + [0.0] * (4 - len(lo))
-        self.hi = list(hi) + [0.0] * (4 - len(hi))
-        self.eps = list(eps) + [0.0] * (4 - len(eps))
+        self.lo = list(lo) + [0.0] * (MAXD - len(lo))
+        self.hi = list(hi) + [0.0] * (MAXD - len(hi))
+        self.eps = list(eps) + [0.0] * (MAXD - len(eps))
         self.canon_c = float(canon_c)
         self.no_prune, self.no_group, self.no_dive = no_prune, no_group, no_dive
         self.test_budget = int(test_budget)
@@ -138,7 +140,7 @@ class Problem:
         p.n = self.n
         for k, c in enumerate(self.cols):
             p.col[k] = _dptr(c)
-        for j in range(4):
+        for j in range(MAXD):
             p.lo[j], p.hi[j], p.eps[j] = self.lo[j], self.hi[j], self.eps[j]
         p.canon_c = self.canon_c
         p.no_prune, p.no_group, p.no_dive = int(self.no_prune), int(self.no_group), int(self.no_dive)
@@ -212,8 +214,8 @@ def all_leaf_counts(prob: Problem) -> np.ndarray:
 def level_counts(prob: Problem, level: int) -> np.ndarray:
     """Chain counts of every cell of one level (index = [sector] || digits)."""
     k = constants(prob)
-    bits = (2 if prob.family == 4 else 0) + sum(
-        sum(1 for j in range(4) if m < k["L"][j]) for m in range(level))
+    bits = (2 if prob.family in POSE else 0) + sum(
+        sum(1 for j in range(MAXD) if m < k["L"][j]) for m in range(level))
     out = np.zeros(1 << bits, dtype=np.uint32)
     p = prob._c()
     st = lib().or_level_counts(ctypes.byref(p), int(level), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
@@ -253,7 +255,7 @@ def report(prob: Problem, tau: int, cap: int = 1 << 20):
 def cell_masks(prob: Problem, level: int, sector: int, coords) -> np.ndarray:
     """Pass masks (bit = child digit) of every surface, canonized along the
     path to the cell, against the children of that cell."""
-    cc = np.ascontiguousarray(np.asarray(list(coords) + [0] * (4 - len(coords)), dtype=np.int32))
+    cc = np.ascontiguousarray(np.asarray(list(coords) + [0] * (MAXD - len(coords)), dtype=np.int32))
     out = np.zeros(max(1, prob.n), dtype=np.uint32)
     p = prob._c()
     st = lib().or_cell_masks(ctypes.byref(p), int(level), int(sector), cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -266,7 +268,7 @@ def cell_masks(prob: Problem, level: int, sector: int, coords) -> np.ndarray:
 def meets(prob: Problem, t, f, tag, level, sector, coords) -> bool:
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(4))
     f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(2))
-    cc = np.ascontiguousarray(np.asarray(coords, dtype=np.int32).reshape(4))
+    cc = np.ascontiguousarray(np.asarray(list(coords) + [0] * (MAXD - len(coords)), dtype=np.int32))
     p = prob._c()
     st = lib().or_meets(ctypes.byref(p), _dptr(t), _dptr(f), int(tag), int(level), int(sector),
                         cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
@@ -278,7 +280,7 @@ def meets(prob: Problem, t, f, tag, level, sector, coords) -> bool:
 def canon_at(prob: Problem, t, f, tag, level, coords):
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(4))
     f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(2))
-    cc = np.ascontiguousarray(np.asarray(coords, dtype=np.int32).reshape(4))
+    cc = np.ascontiguousarray(np.asarray(list(coords) + [0] * (MAXD - len(coords)), dtype=np.int32))
     to = np.zeros(4)
     fo = np.zeros(2)
     p = prob._c()
@@ -290,21 +292,21 @@ def canon_at(prob: Problem, t, f, tag, level, coords):
 
 
 def constants(prob: Problem) -> dict:
-    out = np.zeros(24)
+    out = np.zeros(27)
     p = prob._c()
-    st = lib().or_constants(ctypes.byref(p), _dptr(out), 24)
+    st = lib().or_constants(ctypes.byref(p), _dptr(out), 27)
     if st != 0:
         raise OracleError(st, "constants")
-    d = {"Lstar": int(out[0]), "B": int(out[1]), "L": [int(x) for x in out[2:6]],
+    d = {"Lstar": int(out[0]), "B": int(out[1]), "L": [int(x) for x in out[2:6]] + [int(out[24])],
          "steps": list(out[6:10]), "pad0": list(out[10:14]), "padlast": list(out[14:18]),
-         "Rg": out[18], "epsn": list(out[19:23]), "exact": bool(out[23])}
+         "Rg": out[18], "epsn": list(out[19:23]) + [out[25]], "exact": bool(out[23]), "Fb": out[26]}
     return d
 
 
 def leaf_index_of(levels, coords, sector=None) -> int:
     """Leaf index from per-axis leaf coordinates: digits of levels 0..L*-1,
-    each holding the split axes' bits in axis order, MSB first; the POSE4DOF
-    sector goes on top."""
+    each holding the split axes' bits in axis order, MSB first; the pose
+    families' sector goes on top."""
     d = len(levels)
     lstar = max(levels)
     idx = 0 if sector is None else int(sector)

@@ -12,8 +12,10 @@
  *     hyperplanes in 3-space (Eq. 3), rays in 3-space (Sec. 4.3, the
  *     two-equation line form, generalized to the dominant axis), and the
  *     known-gravity calibrated pose (the 5DoF surface of Sec. 4.2.1 with
- *     focal length 1), and similarity alignment of planar point sets (Sec.
- *     4.4, the translation written in terms of scale-rotation).
+ *     focal length 1), the known-gravity pose with unknown focal length
+ *     (the 5DoF surface of Sec. 4.2.1 itself, axes x, y, z, kappa, f), and
+ *     similarity alignment of planar point sets (Sec. 4.4, the translation
+ *     written in terms of scale-rotation).
  *   - Canonization (Sec. 3.2.1): translate to the cell's minimum corner,
  *     round essential parameters to eps'/((l+1) delta) and free parameters
  *     to eps'/(l+1), group equal results and keep their multiplicity.
@@ -35,7 +37,7 @@
 #include <string.h>
 #include <time.h>
 
-#define MAXD 4
+#define MAXD OR_MAXD
 #define MAXL 48
 
 typedef struct {
@@ -57,6 +59,8 @@ typedef struct {
   double pad[MAXL][MAXD];
   /* pose */
   double sW, sW3, sXi, sEta, Rg2, padz, padk, epsk, ce;
+  /* 5DoF: the f axis in user units (f > 0) and a bound on f over the box */
+  double flo, Ef, Fb;
   /* search state */
   uint64_t best;
   uint64_t *shared_best; /* thread pool: one best key for every worker */
@@ -109,6 +113,9 @@ static double p2floor(double x) {
 
 static int imin(int a, int b) { return a < b ? a : b; }
 
+/* the two camera-posing families share sectors, lattice and predicate */
+static int is_pose(const ctx *C) { return C->fam == OR_POSE4DOF || C->fam == OR_POSE5DOF; }
+
 /* side of axis j at level m in the unit cube: 2^-min(m, L_j) */
 static double side(const ctx *C, int j, int m) { return ldexp(1.0, -imin(m, C->L[j])); }
 
@@ -141,6 +148,7 @@ static int ctx_init(ctx *C, const or_problem *p) {
     case OR_PLANE3D: C->d = 3; C->ell = 2; break;
     case OR_RAY3D: C->d = 3; C->ell = 2; break;
     case OR_POSE4DOF: C->d = 4; C->ell = 4; break;
+    case OR_POSE5DOF: C->d = 5; C->ell = 4; break;
     case OR_SIM2D: C->d = 4; C->ell = 2; break;
     default: return OR_EINVAL;
   }
@@ -148,8 +156,9 @@ static int ctx_init(ctx *C, const or_problem *p) {
   if (!(C->c > 0.0) || isnan(C->c)) return OR_EINVAL;
   C->exact = isinf(C->c) ? 1 : 0;
 
-  int nuser = C->fam == OR_POSE4DOF ? 3 : C->d;
-  for (int j = 0; j < nuser; j++) {
+  /* axes given in user units: all but kappa for the pose families */
+  for (int j = 0; j < C->d; j++) {
+    if (is_pose(C) && j == 3) continue;
     if (!isfinite(p->lo[j]) || !isfinite(p->hi[j]) || !(p->hi[j] > p->lo[j])) return OR_EINVAL;
     if (!isfinite(p->eps[j]) || !(p->eps[j] > 0.0)) return OR_EINVAL;
     C->lo[j] = p->lo[j];
@@ -157,7 +166,7 @@ static int ctx_init(ctx *C, const or_problem *p) {
     C->inv[j] = 1.0 / C->E[j];
     C->epsn[j] = p->eps[j] * C->inv[j];
   }
-  if (C->fam == OR_POSE4DOF) {
+  if (is_pose(C)) {
     /* x and y share one scale so that horizontal distances stay Euclidean */
     if (C->E[0] != C->E[1]) return OR_EINVAL;
     if (!isfinite(p->eps[3]) || !(p->eps[3] > 0.0)) return OR_EINVAL;
@@ -165,11 +174,20 @@ static int ctx_init(ctx *C, const or_problem *p) {
     C->lo[3] = -1.0; C->E[3] = 2.0; C->inv[3] = 0.5;
     C->epsk = p->eps[3];
     C->epsn[3] = C->epsk * 0.5;
+    /* f: the factor of the image coordinates in the direction tangents,
+     * positive over the box; 4DoF is the case f = 1 */
+    C->flo = 1.0; C->Ef = 0.0; C->Fb = 1.0;
+    if (C->fam == OR_POSE5DOF) {
+      if (!(p->lo[4] > 0.0)) return OR_EINVAL;
+      C->flo = p->lo[4];
+      C->Ef = C->E[4];
+      C->Fb = p->hi[4] * (1.0 + 0x1p-20);
+    }
   }
   /* L_j: smallest L >= 0 with E_j 2^-L <= eps_j (leaf sides at most eps) */
   int Lstar = 0, Bcell = 0;
   for (int j = 0; j < C->d; j++) {
-    double ej = (C->fam == OR_POSE4DOF && j == 3) ? C->epsk : p->eps[j];
+    double ej = (is_pose(C) && j == 3) ? C->epsk : p->eps[j];
     int L = 0;
     while (ldexp(C->E[j], -L) > ej) {
       L++;
@@ -182,7 +200,7 @@ static int ctx_init(ctx *C, const or_problem *p) {
   if (Lstar < 1) return OR_EINVAL; /* the root alone would already be a leaf */
   C->Lstar = Lstar;
   C->Bcell = Bcell;
-  C->B = Bcell + (C->fam == OR_POSE4DOF ? 2 : 0);
+  C->B = Bcell + (is_pose(C) ? 2 : 0);
   if (C->B > 62) return OR_EINVAL;
   /* key = count * 2^B + low bits must fit 64 bits */
   if ((uint64_t)p->n >= (1ULL << (64 - C->B))) return OR_EINVAL;
@@ -195,7 +213,7 @@ static int ctx_init(ctx *C, const or_problem *p) {
   C->rem[Lstar] = 0;
   for (int m = Lstar - 1; m >= 0; m--) C->rem[m] = C->rem[m + 1] + C->abits[m];
 
-  if (C->fam != OR_POSE4DOF) {
+  if (!is_pose(C)) {
     /* free step: largest power of two <= eps'/(l+1), eps' = eps/(c(L*+1));
      * essential step at level m: free step * 2^min(m, L_P) = eps'/((l+1) delta) */
     for (int q = 0; q < C->d; q++) {
@@ -224,7 +242,7 @@ static int front(const ctx *C, int64_t i, rec *r) {
   const or_problem *p = C->prob;
   memset(r, 0, sizeof(*r));
   r->w = 1;
-  for (int k = 0; k < (C->fam == OR_RAY3D ? 6 : C->fam == OR_POSE4DOF ? 5 : C->d); k++)
+  for (int k = 0; k < (C->fam == OR_RAY3D ? 6 : is_pose(C) ? 5 : C->d); k++)
     if (!isfinite(p->col[k][i])) return OR_EINVAL;
   if (C->fam == OR_LINE2D) {
     /* point (x, y) -> dual line b = y - x a (vertical distance preserved) */
@@ -277,22 +295,32 @@ static int front(const ctx *C, int64_t i, rec *r) {
   return OR_OK;
 }
 
-/* POSE4DOF lattice: needs data bounds, so it runs after the front end. */
+/* Pose lattice: needs data bounds, so it runs after the front end.  The
+ * steps are chosen so that rounding one parameter by half a step moves z and
+ * kappa by at most eps'/(2(l+1)) anywhere on the box, from bounds on the
+ * derivatives of z = W3 - eta' f r and kappa = tan(phi - atan(xi f)):
+ * |dz/dW3| = 1, |dz/deta'| <= f R, |dz/dW| <= |eta'| f, |dkappa/dxi| <=
+ * (1 + kappa^2) f, |dkappa/dW| <= (1 + kappa^2) / r with r >= R_g. */
 static int pose_lattice(ctx *C) {
   const or_problem *p = C->prob;
   C->ce = C->E[0] * C->inv[2];
-  double Hmax = 0.0, R2 = 0.0;
+  double Hmax = 0.0, R2 = 0.0, Xmax = 0.0;
   for (int64_t i = 0; i < p->n; i++) {
     rec r;
     int st = front(C, i, &r);
     if (st) return st;
     double h = fabs(r.p[4]);
     if (h > Hmax) Hmax = h;
+    if (fabs(r.p[3]) > Xmax) Xmax = fabs(r.p[3]);
     double a0 = r.p[0] * r.p[0], a1 = (r.p[0] - 1.0) * (r.p[0] - 1.0);
     double b0 = r.p[1] * r.p[1], b1 = (r.p[1] - 1.0) * (r.p[1] - 1.0);
     double r2 = (a0 > a1 ? a0 : a1) + (b0 > b1 ? b0 : b1);
     if (r2 > R2) R2 = r2;
   }
+  /* 5DoF: the directions with kappa in a cell's widened interval, over the
+   * cell's f interval, form one arc of angle at most 2 atan(1 + padk) +
+   * atan(|xi| f_hi), padk <= 2 eps_kappa; the arc test needs it below pi */
+  if (C->fam == OR_POSE5DOF && !(2.0 * atan(1.0 + 2.0 * C->epsk) + atan(Xmax * p->hi[4]) < 3.1)) return OR_EINVAL;
   int Lxy = C->L[0] > C->L[1] ? C->L[0] : C->L[1];
   double Rg = ldexp(1.0, -Lxy); /* apex guard: one leaf xy side */
   C->Rg2 = Rg * Rg;
@@ -310,10 +338,10 @@ static int pose_lattice(ctx *C) {
   double pk0 = C->epsk + ek * 0.5;
   double Bk = 1.0 + (1.0 + pk0) * (1.0 + pk0); /* bound on 1 + kappa^2 */
   C->sW3 = p2floor(ez / l1);
-  C->sEta = p2floor(ez / (l1 * Rb));
-  double wz = ez / (l1 * Hb), wk = (ek * Rg) / (l1 * Bk);
+  C->sEta = p2floor(ez / (l1 * Rb * C->Fb));
+  double wz = ez / (l1 * Hb * C->Fb), wk = (ek * Rg) / (l1 * Bk);
   C->sW = p2floor(wz < wk ? wz : wk);
-  C->sXi = p2floor(ek / (l1 * Bk));
+  C->sXi = p2floor(ek / (l1 * Bk * C->Fb));
   C->padz = ceil((C->epsn[2] + ez * 0.5) / C->sW3) * C->sW3;
   C->padk = ceil((C->epsk + ek * 0.5) / C->sXi) * C->sXi;
   return OR_OK;
@@ -323,7 +351,7 @@ static int pose_lattice(ctx *C) {
 /* Canonization (Sec. 3.2.1).                                           */
 /* ------------------------------------------------------------------ */
 static void canon(const ctx *C, rec *r, int m, const int32_t *cc) {
-  if (C->fam == OR_POSE4DOF) {
+  if (is_pose(C)) {
     /* fixed global lattice, applied once at the root */
     if (m != 0) return;
     r->p[0] = nearbyint(r->p[0] / C->sW) * C->sW;
@@ -372,6 +400,13 @@ static double cross2(double ax, double ay, double bx, double by) { return ax * b
 
 static int meets_pose(const ctx *C, const rec *r, int m1, int sector, const int32_t *cc) {
   double hx = side(C, 0, m1), hy = side(C, 1, m1), hz = side(C, 2, m1), hk = side(C, 3, m1);
+  /* f interval of the cell in user units (4DoF: f = 1) */
+  double Fl = 1.0, Fh = 1.0;
+  if (C->fam == OR_POSE5DOF) {
+    double hf = side(C, 4, m1);
+    Fl = C->flo + C->Ef * ((double)cc[4] * hf);
+    Fh = C->flo + C->Ef * ((double)(cc[4] + 1) * hf);
+  }
   double Xlo = (double)cc[0] * hx, Xhi = (double)(cc[0] + 1) * hx;
   double Ylo = (double)cc[1] * hy, Yhi = (double)(cc[1] + 1) * hy;
   double Zlo = (double)cc[2] * hz, Zhi = (double)(cc[2] + 1) * hz;
@@ -385,7 +420,8 @@ static int meets_pose(const ctx *C, const rec *r, int m1, int sector, const int3
     case 2: x0 = -Ahi; x1 = -Alo; y0 = -Bhi; y1 = -Blo; break;
     default: x0 = -Bhi; x1 = -Blo; y0 = Alo; y1 = Ahi; break;
   }
-  /* z = W3 - eta * |v| over V: |v| spans [r_min, r_max] */
+  /* z = W3 - eta f |v| over V and the f interval: |v| spans [r_min, r_max],
+   * |eta| f spans [|eta| Fl, |eta| Fh] */
   double dx = x0 > 0.0 ? x0 : (x1 < 0.0 ? -x1 : 0.0);
   double dy = y0 > 0.0 ? y0 : (y1 < 0.0 ? -y1 : 0.0);
   double rmin2 = dx * dx + dy * dy;
@@ -395,15 +431,20 @@ static int meets_pose(const ctx *C, const rec *r, int m1, int sector, const int3
   double Tlo, Thi, a;
   if (eta >= 0.0) { Tlo = Glo; Thi = Ghi; a = eta; }
   else { Tlo = -Ghi; Thi = -Glo; a = -eta; }
-  double a2 = a * a;
-  int zlo_ok = (Tlo <= 0.0) || (a2 * rmax2 >= Tlo * Tlo); /* a r_max >= Tlo */
-  int zhi_ok = (Thi >= 0.0) && (a2 * rmin2 <= Thi * Thi); /* a r_min <= Thi */
+  double ah = a * Fh, al = a * Fl;
+  int zlo_ok = (Tlo <= 0.0) || ((ah * ah) * rmax2 >= Tlo * Tlo); /* a Fh r_max >= Tlo */
+  int zhi_ok = (Thi >= 0.0) && ((al * al) * rmin2 <= Thi * Thi); /* a Fl r_min <= Thi */
   if (!(zlo_ok && zhi_ok)) return 0;
-  /* kappa = (v2 - xi v1)/(v1 + xi v2) with v1 + xi v2 > 0, over V */
+  /* kappa = (v2 - t v1)/(v1 + t v2) with v1 + t v2 > 0 and t = xi f, over V
+   * and the f interval: the directions form the arc from the one with kappa
+   * = Llo at the smallest t counter-clockwise to the one with kappa = Lhi at
+   * the largest t */
   if (rmin2 < C->Rg2) return 1; /* apex guard: kappa unbounded near the apex */
   double Llo = Klo - C->padk, Lhi = Khi + C->padk;
-  double elx = 1.0 - Llo * xi, ely = Llo + xi; /* direction with kappa = Llo */
-  double ehx = 1.0 - Lhi * xi, ehy = Lhi + xi; /* direction with kappa = Lhi */
+  double t1 = xi * Fl, t2 = xi * Fh;
+  double tl = t1 < t2 ? t1 : t2, th = t1 < t2 ? t2 : t1;
+  double elx = 1.0 - Llo * tl, ely = Llo + tl; /* direction with kappa = Llo at t = tl */
+  double ehx = 1.0 - Lhi * th, ehy = Lhi + th; /* direction with kappa = Lhi at t = th */
   double ax, ay, bx, by; /* silhouette corners: V's angular span from a CCW to b */
   if (x0 > 0.0) {
     if (y0 > 0.0) { ax = x1; ay = y0; bx = x0; by = y1; }
@@ -428,7 +469,7 @@ static int meets_pose(const ctx *C, const rec *r, int m1, int sector, const int3
 
 static int meets(const ctx *C, const rec *r, int m, int sector, const int32_t *cc) {
   int m1 = m + 1;
-  if (C->fam == OR_POSE4DOF) return meets_pose(C, r, m1, sector, cc);
+  if (is_pose(C)) return meets_pose(C, r, m1, sector, cc);
   int nP, P[2], nQ, Q[2];
   lin_axes(C, r->tag, &nP, P, &nQ, Q);
   for (int qi = 0; qi < nQ; qi++) {
@@ -560,7 +601,7 @@ static int dive(ctx *C, int sector, const rec *S0, int64_t n0) {
   if (!cur || !nxt) { free(cur); free(nxt); return OR_ENOMEM; }
   memcpy(cur, S0, sizeof(rec) * (size_t)n0);
   int64_t n = n0;
-  int32_t cc[MAXD] = {0, 0, 0, 0};
+  int32_t cc[MAXD] = {0};
   uint64_t prefix = (uint64_t)sector;
   for (int m = 0; m < C->Lstar; m++) {
     int a = C->abits[m], bestd = 0;
@@ -595,7 +636,7 @@ static int dive(ctx *C, int sector, const rec *S0, int64_t n0) {
 /* decode a leaf index into the per-level path of cell coordinates */
 static int leaf_path(const ctx *C, uint64_t idx, int *sector, int32_t path[][MAXD]) {
   if (C->B < 64 && idx >= (1ULL << C->B)) return OR_EINVAL;
-  *sector = C->fam == OR_POSE4DOF ? (int)(idx >> C->Bcell) : 0;
+  *sector = is_pose(C) ? (int)(idx >> C->Bcell) : 0;
   for (int j = 0; j < MAXD; j++) path[0][j] = 0;
   for (int m = 0; m < C->Lstar; m++) {
     int a = C->abits[m];
@@ -610,7 +651,7 @@ static int leaf_path(const ctx *C, uint64_t idx, int *sector, int32_t path[][MAX
 static void cell_path(const ctx *C, uint64_t idx, int level, int *sector, int32_t path[][MAXD]) {
   int bits = 0;
   for (int m = 0; m < level; m++) bits += C->abits[m];
-  *sector = C->fam == OR_POSE4DOF ? (int)(idx >> bits) : 0;
+  *sector = is_pose(C) ? (int)(idx >> bits) : 0;
   for (int j = 0; j < MAXD; j++) path[0][j] = 0;
   int rem = bits;
   for (int m = 0; m < level; m++) {
@@ -632,7 +673,7 @@ static int chain_passes(const ctx *C, rec r, int sector, int32_t path[][MAXD]) {
 }
 
 static int check_range(ctx *C, const rec *S, int64_t n) {
-  if (C->fam == OR_POSE4DOF) return OR_OK;
+  if (is_pose(C)) return OR_OK;
   /* every value stays a multiple of sf/2 below 2^52 sf/2: exact in binary64 */
   for (int64_t i = 0; i < n; i++) {
     int nP, P[2], nQ, Q[2];
@@ -648,13 +689,13 @@ static int check_range(ctx *C, const rec *S, int64_t n) {
 
 static int build_root(ctx *C, rec **out, int64_t *nout) {
   const or_problem *p = C->prob;
-  if (C->fam == OR_POSE4DOF) {
+  if (is_pose(C)) {
     int st = pose_lattice(C);
     if (st) return st;
   }
   rec *S = (rec *)malloc(sizeof(rec) * (size_t)(p->n > 0 ? p->n : 1));
   if (!S) return OR_ENOMEM;
-  int32_t zero[MAXD] = {0, 0, 0, 0};
+  int32_t zero[MAXD] = {0};
   for (int64_t i = 0; i < p->n; i++) {
     int st = front(C, i, &S[i]);
     if (st) { free(S); return st; }
@@ -673,7 +714,7 @@ static void leaf_point(const ctx *C, int sector, const int32_t *lc, double *pt) 
     double u = (double)(2 * lc[j] + 1) * ldexp(1.0, -(C->L[j] + 1));
     pt[j] = C->lo[j] + C->E[j] * u;
   }
-  if (C->fam == OR_POSE4DOF) {
+  if (is_pose(C)) {
     double yaw = (double)sector * (M_PI / 2.0) + atan(pt[3]);
     if (yaw < 0.0) yaw += 2.0 * M_PI;
     if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
@@ -773,7 +814,7 @@ static void *worker_main(void *arg) {
 }
 
 static int search_parallel(ctx *C, const rec *S, int64_t n, int nthreads) {
-  int nsec = C->fam == OR_POSE4DOF ? 4 : 1;
+  int nsec = is_pose(C) ? 4 : 1;
   /* subtrees: the first level with at least 64 cells per worker (or the
    * last level above the leaves) */
   int level = 0;
@@ -781,7 +822,7 @@ static int search_parallel(ctx *C, const rec *S, int64_t n, int nthreads) {
   while (level < C->Lstar - 1 && cells < 64ULL * (uint64_t)nthreads) cells <<= C->abits[level++];
   if (level == 0) {
     for (int s = 0; s < nsec; s++) {
-      int32_t zero[MAXD] = {0, 0, 0, 0};
+      int32_t zero[MAXD] = {0};
       int st = expand(C, 0, s, zero, (uint64_t)s, S, n);
       if (st) return st;
     }
@@ -830,7 +871,7 @@ int or_solve(const or_problem *p, or_result *res, int64_t *inliers, int64_t cap)
   if (st) return st;
   double t0 = now_s();
   n = group(&C, S, n);
-  int nsec = C.fam == OR_POSE4DOF ? 4 : 1;
+  int nsec = is_pose(&C) ? 4 : 1;
   C.best = 0;
   if (p->has_seed) {
     /* a leaf named by the caller: its count by replay is achieved */
@@ -844,7 +885,7 @@ int or_solve(const or_problem *p, or_result *res, int64_t *inliers, int64_t cap)
   if (!st && p->threads > 1) {
     st = search_parallel(&C, S, n, p->threads);
   } else {
-    int32_t zero[MAXD] = {0, 0, 0, 0};
+    int32_t zero[MAXD] = {0};
     for (int s = 0; s < nsec && !st; s++) st = expand(&C, 0, s, zero, (uint64_t)s, S, n);
   }
   free(S);
@@ -860,12 +901,12 @@ int or_solve(const or_problem *p, or_result *res, int64_t *inliers, int64_t cap)
   res->leaf_index = mask - (C.best & mask);
   res->lstar = C.Lstar;
   res->index_bits = C.B;
-  for (int j = 0; j < 4; j++) res->levels[j] = j < C.d ? C.L[j] : 0;
+  for (int j = 0; j < MAXD; j++) res->levels[j] = j < C.d ? C.L[j] : 0;
   int sector;
   int32_t path[MAXL + 1][MAXD];
   leaf_path(&C, res->leaf_index, &sector, path);
   res->sector = sector;
-  for (int j = 0; j < 4; j++) res->leaf_coords[j] = j < C.d ? path[C.Lstar][j] : 0;
+  for (int j = 0; j < MAXD; j++) res->leaf_coords[j] = j < C.d ? path[C.Lstar][j] : 0;
   leaf_point(&C, sector, path[C.Lstar], res->point);
   uint64_t cnt;
   int64_t ninl;
@@ -898,8 +939,8 @@ int or_report(const or_problem *p, uint64_t tau, uint64_t *leaves, uint32_t *cou
   C.rep_cnt = counts;
   C.rep_cap = cap;
   C.best = (tau << C.B) - 1ULL;
-  int nsec = C.fam == OR_POSE4DOF ? 4 : 1;
-  int32_t zero[MAXD] = {0, 0, 0, 0};
+  int nsec = is_pose(&C) ? 4 : 1;
+  int32_t zero[MAXD] = {0};
   for (int s = 0; s < nsec && !st; s++) st = expand(&C, 0, s, zero, (uint64_t)s, S, n);
   free(S);
   *n_out = C.rep_n;
@@ -910,7 +951,7 @@ int or_report(const or_problem *p, uint64_t tau, uint64_t *leaves, uint32_t *cou
 }
 
 static void to_tf(const ctx *C, const rec *r, double *t, double *f, int32_t *tag) {
-  if (C->fam == OR_POSE4DOF) {
+  if (is_pose(C)) {
     t[0] = r->p[0]; t[1] = r->p[1]; t[2] = r->p[3]; t[3] = r->p[4];
     f[0] = r->p[2]; f[1] = r->p[5];
   } else {
@@ -924,7 +965,7 @@ static void from_tf(const ctx *C, const double *t, const double *f, int32_t tag,
   memset(r, 0, sizeof(*r));
   r->w = 1;
   r->tag = tag;
-  if (C->fam == OR_POSE4DOF) {
+  if (is_pose(C)) {
     r->p[0] = t[0]; r->p[1] = t[1]; r->p[3] = t[2]; r->p[4] = t[3];
     r->p[2] = f[0]; r->p[5] = f[1];
   } else {
@@ -937,7 +978,7 @@ int or_parametrize(const or_problem *p, double *t, double *f, int32_t *tag) {
   ctx C;
   int st = ctx_init(&C, p);
   if (st) return st;
-  if (C.fam == OR_POSE4DOF) C.ce = C.E[0] * C.inv[2];
+  if (is_pose(&C)) C.ce = C.E[0] * C.inv[2];
   for (int64_t i = 0; i < p->n; i++) {
     rec r;
     st = front(&C, i, &r);
@@ -965,7 +1006,7 @@ int or_leaf_count(const or_problem *p, uint64_t leaf_index, uint64_t *count, int
   ctx C;
   int st = ctx_init(&C, p);
   if (st) return st;
-  if (C.fam == OR_POSE4DOF) {
+  if (is_pose(&C)) {
     st = pose_lattice(&C);
     if (st) return st;
   }
@@ -981,7 +1022,7 @@ int or_all_leaf_counts(const or_problem *p, uint32_t *out, uint64_t out_len) {
   int st = ctx_init(&C, p);
   if (st) return st;
   if (C.B > 24 || out_len < (1ULL << C.B)) return OR_EINVAL;
-  if (C.fam == OR_POSE4DOF) {
+  if (is_pose(&C)) {
     st = pose_lattice(&C);
     if (st) return st;
   }
@@ -1017,7 +1058,7 @@ static int small_tree(ctx *C, const or_problem *p) {
   int st = ctx_init(C, p);
   if (st) return st;
   if (C->B > 24) return OR_EINVAL;
-  if (C->fam == OR_POSE4DOF) return pose_lattice(C);
+  if (is_pose(C)) return pose_lattice(C);
   return OR_OK;
 }
 
@@ -1026,7 +1067,7 @@ int or_level_counts(const or_problem *p, int level, uint32_t *out, uint64_t out_
   int st = small_tree(&C, p);
   if (st) return st;
   if (level < 0 || level > C.Lstar) return OR_EINVAL;
-  int bits = C.fam == OR_POSE4DOF ? 2 : 0;
+  int bits = is_pose(&C) ? 2 : 0;
   for (int m = 0; m < level; m++) bits += C.abits[m];
   if (out_len < (1ULL << bits)) return OR_EINVAL;
   rec *S = (rec *)malloc(sizeof(rec) * (size_t)(p->n > 0 ? p->n : 1));
@@ -1069,7 +1110,7 @@ int or_cell_masks(const or_problem *p, int level, int32_t sector, const int32_t 
   int st = ctx_init(&C, p);
   if (st) return st;
   if (level < 0 || level >= C.Lstar) return OR_EINVAL;
-  if (C.fam == OR_POSE4DOF) {
+  if (is_pose(&C)) {
     st = pose_lattice(&C);
     if (st) return st;
   }
@@ -1102,7 +1143,7 @@ int or_meets(const or_problem *p, const double *t, const double *f, int32_t tag,
   int st = ctx_init(&C, p);
   if (st) return st;
   if (level < 0 || level >= C.Lstar) return OR_EINVAL;
-  if (C.fam == OR_POSE4DOF) {
+  if (is_pose(&C)) {
     st = pose_lattice(&C);
     if (st) return st;
   }
@@ -1117,7 +1158,7 @@ int or_canon_at(const or_problem *p, const double *t, const double *f, int32_t t
   int st = ctx_init(&C, p);
   if (st) return st;
   if (level < 0 || level > C.Lstar) return OR_EINVAL;
-  if (C.fam == OR_POSE4DOF) {
+  if (is_pose(&C)) {
     st = pose_lattice(&C);
     if (st) return st;
   }
@@ -1133,8 +1174,8 @@ int or_constants(const or_problem *p, double *out, int out_len) {
   ctx C;
   int st = ctx_init(&C, p);
   if (st) return st;
-  if (out_len < 24) return OR_EINVAL;
-  if (C.fam == OR_POSE4DOF) {
+  if (out_len < 27) return OR_EINVAL;
+  if (is_pose(&C)) {
     st = pose_lattice(&C);
     if (st) return st;
   }
@@ -1142,7 +1183,7 @@ int or_constants(const or_problem *p, double *out, int out_len) {
   out[0] = C.Lstar;
   out[1] = C.B;
   for (int j = 0; j < 4; j++) out[2 + j] = j < C.d ? C.L[j] : 0;
-  if (C.fam == OR_POSE4DOF) {
+  if (is_pose(&C)) {
     out[6] = C.sW; out[7] = C.sW3; out[8] = C.sXi; out[9] = C.sEta;
     out[10] = C.padz; out[11] = C.padk;
     out[14] = C.padz; out[15] = C.padk;
@@ -1154,5 +1195,8 @@ int or_constants(const or_problem *p, double *out, int out_len) {
   out[18] = sqrt(C.Rg2);
   out[19] = C.epsn[0]; out[20] = C.epsn[1]; out[21] = C.epsn[2]; out[22] = C.epsn[3];
   out[23] = C.exact;
+  out[24] = C.d > 4 ? C.L[4] : 0;
+  out[25] = C.d > 4 ? C.epsn[4] : 0;
+  out[26] = is_pose(&C) ? C.Fb : 0;
   return OR_OK;
 }

@@ -20,7 +20,13 @@
 extern "C" {
 #endif
 
-enum { OR_LINE2D = 1, OR_PLANE3D = 2, OR_RAY3D = 3, OR_POSE4DOF = 4, OR_SIM2D = 5 };
+enum { OR_LINE2D = 1, OR_PLANE3D = 2, OR_RAY3D = 3, OR_POSE4DOF = 4, OR_SIM2D = 5, OR_POSE5DOF = 6 };
+
+/* Up to five axes: (x, y, z, kappa, f) for OR_POSE5DOF, the camera position,
+ * the tangent of the yaw offset inside a sector and the factor f that turns
+ * image coordinates into direction tangents (tangent = xi f); four or fewer
+ * for the other families. */
+#define OR_MAXD 5
 
 enum {
   OR_OK = 0,
@@ -35,8 +41,8 @@ typedef struct {
   int family;
   int64_t n;
   const double *col[6];  /* SoA observation columns, family order */
-  double lo[4], hi[4];   /* domain box, user units, family axis order */
-  double eps[4];         /* per-axis eps, user units */
+  double lo[OR_MAXD], hi[OR_MAXD]; /* domain box, user units, family axis order */
+  double eps[OR_MAXD];   /* per-axis eps, user units */
   double canon_c;        /* 0 -> 1.0; +INFINITY -> exact mode */
   int no_prune;          /* 1: never prune (pins only) */
   int no_group;          /* 1: never merge equal canonical surfaces */
@@ -54,11 +60,11 @@ typedef struct {
   uint64_t count;        /* max depth: number of original surfaces */
   uint64_t leaf_index;   /* [sector bits] || per-level child digits */
   uint64_t key;          /* count * 2^B + (2^B - 1 - leaf_index) */
-  int32_t sector;        /* POSE4DOF yaw sector 0..3, else 0 */
-  int32_t leaf_coords[4];
-  int32_t levels[4];     /* L_j per axis */
+  int32_t sector;        /* pose families: yaw sector 0..3, else 0 */
+  int32_t leaf_coords[OR_MAXD];
+  int32_t levels[OR_MAXD]; /* L_j per axis */
   int32_t lstar, index_bits;
-  double point[4];       /* leaf centre, user units; POSE4DOF: x,y,z,yaw */
+  double point[OR_MAXD];   /* leaf centre, user units; pose: x,y,z,yaw(,f) */
   int64_t n_inliers;
   uint64_t tests, cells_expanded, cells_pruned, groups_merged;
   double seconds;        /* wall time of the search (not the front end) */
@@ -118,7 +124,8 @@ int or_canon_at(const or_problem *p, const double *t, const double *f,
 
 /* Lattice and pad constants, for pins: out[0..]=
  * {Lstar, B, L0..L3, sf0..sf3 (linear) or sW,sW3,sXi,sEta (pose),
- *  pad0..pad3 at level 0, pad0..pad3 at level Lstar-1, Rg} */
+ *  pad0..pad3 at level 0, pad0..pad3 at level Lstar-1, Rg, epsn0..epsn3,
+ *  exact, L4, epsn4, Fb} (out_len >= 27) */
 int or_constants(const or_problem *p, double *out, int out_len);
 
 const char *or_status_str(int st);

@@ -13,6 +13,11 @@ Recipes (each stands in for a workload of the paper):
   * pose4dof: 2D-3D matches seen from a gravity-aligned camera at a random
     position and yaw, plus random matches (stands in for the SfM query
     matches of the posing evaluation, which are not available).
+  * pose5dof: the same with an unknown focal length: image coordinates are
+    direction tangents divided by the camera's factor f* (stands in for the
+    SfM query matches of the 5DoF evaluation: about 1e4-2e4 matches, camera
+    within 50 m horizontally and 5 m vertically of the truth, f within
+    [0.6, 1.3] of the truth).
   * sim2d: two planar point sets, part of one mapped into the other by a
     similarity with noise; every pair is a hypothetical correspondence
     (pointset alignment).
@@ -23,7 +28,7 @@ import math
 
 import numpy as np
 
-FAMILY_IDS = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4, "sim2d": 5}
+FAMILY_IDS = {"line2d": 1, "plane3d": 2, "ray3d": 3, "pose4dof": 4, "sim2d": 5, "pose5dof": 6}
 
 
 def _rng(seed):
@@ -222,6 +227,56 @@ def pose4dof(seed=104, n=1_000_000, n_in=5000, noise_deg=0.5, size=200.0, eps_m=
                     (eps_m, eps_m, eps_m, eps_k), truth=(c[0], c[1], c[2], yaw), planted=planted)
 
 
+def pose5dof(seed=106, n=20_000, n_in=300, noise_deg=0.5, half_xy=50.0, half_z=5.0, rho=(2.0, 100.0),
+             elev=0.5, eps_m=0.5, eps_deg=0.5, eps_f_rel=0.01, f_range=(0.6, 1.3), eps_z=None):
+    """2D-3D matches (w, xi, eta) for a gravity-aligned camera at c* with yaw
+    theta* and an unknown focal length: the camera's direction tangents are
+    f* times its image coordinates (f* = reference focal / true focal, drawn
+    in [0.7, 1.4]).  Inliers: points at horizontal range U(rho), lateral
+    tangent U(-1, 1), elevation tangent U(-elev, elev), bearing perturbed by
+    noise_deg, observed at (xi, eta) = tangents / f*.  Outliers: points
+    uniform over the region the inliers span, image coordinates uniform over
+    the same image.  Axes (x, y, z, yaw, f): a box of 2 half_xy by 2 half_xy
+    by 2 half_z around the camera, the truth uniform in its middle half, and
+    f in [f_range] times f*."""
+    rng = _rng(seed)
+    c = np.array([rng.uniform(-100.0, 100.0), rng.uniform(-100.0, 100.0), rng.uniform(0.0, 20.0)])
+    yaw = rng.uniform(0.0, 2 * math.pi)
+    fstar = rng.uniform(0.7, 1.4)
+    # box corner on a 2^-10 grid, so that hi - lo is exactly the box side
+    lo_xyz = np.round((c - np.array([half_xy, half_xy, half_z]) * rng.uniform(0.5, 1.5, size=3)) * 1024.0) / 1024.0
+    xi0 = rng.uniform(-1.0, 1.0, size=n_in)
+    eta0 = rng.uniform(-elev, elev, size=n_in)
+    r = rng.uniform(rho[0], rho[1], size=n_in)
+    hx = math.cos(yaw) - xi0 * math.sin(yaw)
+    hy = math.sin(yaw) + xi0 * math.cos(yaw)
+    nrm = np.sqrt(1.0 + xi0 * xi0)
+    d = np.stack([r * hx / nrm, r * hy / nrm, r * eta0], axis=1)
+    w_in = c[None, :] + d
+    dn = _perturb(rng, d / np.linalg.norm(d, axis=1, keepdims=True), noise_deg)
+    xi_in, eta_in, F = bearing_to_xi_eta(dn, yaw)
+    assert np.all(F > 0)
+    m = n - n_in
+    ang = rng.uniform(0.0, 2 * math.pi, size=m)
+    ro = rho[1] * np.sqrt(rng.uniform((rho[0] / rho[1]) ** 2, 1.0, size=m))
+    w_out = np.stack([c[0] + ro * np.cos(ang), c[1] + ro * np.sin(ang),
+                      c[2] + ro * rng.uniform(-elev, elev, size=m)], axis=1)
+    xi_out = rng.uniform(-1.0, 1.0, size=m)
+    eta_out = rng.uniform(-elev, elev, size=m)
+    W = np.concatenate([w_in, w_out])
+    cols = [W[:, 0], W[:, 1], W[:, 2], np.concatenate([xi_in, xi_out]) / fstar,
+            np.concatenate([eta_in, eta_out]) / fstar]
+    is_in = np.zeros(n, bool)
+    is_in[:n_in] = True
+    cols, planted = _shuffle(rng, cols, is_in)
+    hi_xyz = lo_xyz + np.array([2 * half_xy, 2 * half_xy, 2 * half_z])
+    flo, fhi = f_range[0] * fstar, f_range[1] * fstar
+    return _problem("pose5dof", cols, (lo_xyz[0], lo_xyz[1], lo_xyz[2], 0.0, flo),
+                    (hi_xyz[0], hi_xyz[1], hi_xyz[2], 2 * math.pi, fhi),
+                    (eps_m, eps_m, eps_m if eps_z is None else eps_z, math.radians(eps_deg), eps_f_rel * fstar),
+                    truth=(c[0], c[1], c[2], yaw, fstar), planted=planted)
+
+
 def sim2d(seed=105, n_a=10_000, k=9, n_in=1000, sigma=0.002, eps=0.01, lo=(0.25, -1.25, -2.0, -2.0),
           hi=(1.25, 1.25, 2.0, 2.0)):
     """Point sets A, B in [0,1]^2 and k candidate correspondences per point
@@ -269,6 +324,14 @@ def config(name: str, **kw):
         return ray3d(**kw)
     if name == "pose4dof_1m":
         return pose4dof(**kw)
+    if name == "pose5dof_20k":
+        return pose5dof(**kw)
+    if name == "pose5dof_tiny":
+        return pose5dof(seed=kw.get("seed", 7), n=kw.get("n", 48), n_in=kw.get("n_in", 12), noise_deg=0.2,
+                        half_z=25.0, rho=(2.0, 60.0), eps_m=25.0, eps_deg=11.5, eps_f_rel=0.25)
+    if name == "pose5dof_small":
+        return pose5dof(seed=kw.get("seed", 17), n=kw.get("n", 3000), n_in=kw.get("n_in", 300), noise_deg=0.2,
+                        half_z=10.0, rho=(2.0, 80.0), eps_m=4.0, eps_deg=2.0, eps_f_rel=0.05)
     if name == "sim2d_90k":
         return sim2d(**kw)
     if name == "sim2d_tiny":

@@ -14,7 +14,7 @@ import sys
 import tempfile
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_bounds.py"]
+PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_bounds.py", "tests/test_oracle_pose5.py"]
 
 # (name, text in gv_oracle.c, replacement)
 MUTANTS = [
@@ -25,12 +25,12 @@ MUTANTS = [
      "C->sf[q] = 4.0 * p2floor(ep / (double)(C->ell + 1));"),
     ("pad_m3", "(double)((m + 1) * (C->ell + 1))", "(double)((m + 3) * (C->ell + 1))"),
     ("extra_level", "while (ldexp(C->E[j], -L) > ej) {", "while (ldexp(C->E[j], -L) >= 0.5 * ej) {"),
-    ("sXi_x64", "C->sXi = p2floor(ek / (l1 * Bk));", "C->sXi = 64.0 * p2floor(ek / (l1 * Bk));"),
+    ("sXi_x64", "C->sXi = p2floor(ek / (l1 * Bk * C->Fb));", "C->sXi = 64.0 * p2floor(ek / (l1 * Bk * C->Fb));"),
     ("padz_3eps", "C->padz = ceil((C->epsn[2] + ez * 0.5)", "C->padz = ceil((3.0 * C->epsn[2] + ez * 0.5)"),
-    ("zhi_rmax", "int zhi_ok = (Thi >= 0.0) && (a2 * rmin2 <= Thi * Thi);",
-     "int zhi_ok = (Thi >= 0.0) && (a2 * rmax2 <= Thi * Thi);"),
-    ("zlo_rmin", "int zlo_ok = (Tlo <= 0.0) || (a2 * rmax2 >= Tlo * Tlo);",
-     "int zlo_ok = (Tlo <= 0.0) || (a2 * rmin2 >= Tlo * Tlo);"),
+    ("zhi_rmax", "int zhi_ok = (Thi >= 0.0) && ((al * al) * rmin2 <= Thi * Thi);",
+     "int zhi_ok = (Thi >= 0.0) && ((al * al) * rmax2 <= Thi * Thi);"),
+    ("zlo_rmin", "int zlo_ok = (Tlo <= 0.0) || ((ah * ah) * rmax2 >= Tlo * Tlo);",
+     "int zlo_ok = (Tlo <= 0.0) || ((ah * ah) * rmin2 >= Tlo * Tlo);"),
     ("arc_swap", "if (cross2(elx, ely, bx, by) >= 0.0 && cross2(bx, by, ehx, ehy) >= 0.0) return 1;",
      "if (cross2(elx, ely, bx, by) >= 0.0 && cross2(ehx, ehy, bx, by) >= 0.0) return 1;"),
     ("sector3", "default: x0 = -Bhi; x1 = -Blo; y0 = Alo; y1 = Ahi; break;",
@@ -50,13 +50,25 @@ MUTANTS = [
     ("ray_front", "r->p[4 + qi] = ((w[q] - C->lo[q]) + s * (C->lo[pi] - w[pi])) * C->inv[q];",
      "r->p[4 + qi] = ((w[q] - C->lo[q]) + s * (C->lo[pi] + w[pi])) * C->inv[q];"),
     ("pose_eta", "r->p[4] = p->col[4][i] * C->ce;", "r->p[4] = p->col[4][i];"),
-    ("sEta_x64", "C->sEta = p2floor(ez / (l1 * Rb));", "C->sEta = 64.0 * p2floor(ez / (l1 * Rb));"),
+    ("sEta_x64", "C->sEta = p2floor(ez / (l1 * Rb * C->Fb));", "C->sEta = 64.0 * p2floor(ez / (l1 * Rb * C->Fb));"),
     ("sW_x64", "C->sW = p2floor(wz < wk ? wz : wk);", "C->sW = 64.0 * p2floor(wz < wk ? wz : wk);"),
     ("Rg_x4", "double Rg = ldexp(1.0, -Lxy); /* apex guard", "double Rg = ldexp(4.0, -Lxy); /* apex guard"),
     ("guard_rmax", "if (rmin2 < C->Rg2) return 1;", "if (rmax2 < C->Rg2) return 1;"),
     ("padk_3eps", "C->padk = ceil((C->epsk + ek * 0.5)", "C->padk = ceil((3.0 * C->epsk + ek * 0.5)"),
     ("inl_last", "if (inl && k < cap) inl[k] = i;", "if (inl && k < cap) inl[k] = i + (i == C->prob->n - 1);"),
     ("sim_front_d", "r->p[3] = (px * C->E[1]) * C->inv[3];", "r->p[3] = -(px * C->E[1]) * C->inv[3];"),
+    # 5-DoF (unknown focal length)
+    ("f5_zhi_Fh", "double ah = a * Fh, al = a * Fl;", "double ah = a * Fh, al = a * Fh;"),
+    ("f5_zlo_Fl", "double ah = a * Fh, al = a * Fl;", "double ah = a * Fl, al = a * Fl;"),
+    ("f5_t_swap", "double tl = t1 < t2 ? t1 : t2, th = t1 < t2 ? t2 : t1;",
+     "double tl = t1 < t2 ? t2 : t1, th = t1 < t2 ? t1 : t2;"),
+    ("f5_cell_hi", "Fh = C->flo + C->Ef * ((double)(cc[4] + 1) * hf);",
+     "Fh = C->flo + C->Ef * ((double)(cc[4] + 2) * hf);"),
+    ("f5_cell_lo", "Fl = C->flo + C->Ef * ((double)cc[4] * hf);", "Fl = C->flo + C->Ef * ((double)(cc[4] + 1) * hf);"),
+    ("f5_no_f", "if (C->fam == OR_POSE5DOF) {\n    double hf", "if (0) {\n    double hf"),
+    ("f5_sEta_noF", "C->sEta = p2floor(ez / (l1 * Rb * C->Fb));", "C->sEta = p2floor(ez / (l1 * Rb));"),
+    ("f5_sXi_noF", "C->sXi = p2floor(ek / (l1 * Bk * C->Fb));", "C->sXi = p2floor(ek / (l1 * Bk));"),
+    ("f5_wz_noF", "double wz = ez / (l1 * Hb * C->Fb)", "double wz = ez / (l1 * Hb)"),
     ("sim_axes", "*nP = 2; P[0] = 0; P[1] = 1; *nQ = 2; Q[0] = 2; Q[1] = 3;",
      "*nP = 2; P[0] = 0; P[1] = 1; *nQ = 2; Q[0] = 3; Q[1] = 2;"),
 ]
