@@ -66,9 +66,10 @@ def load_golden(workload):
 
 
 def golden_match(r, gold):
+    k = len(gold["point"])  # axes of the family; the library reports 0 beyond them
     return (r["count"] == gold["count"] and r["leaf_index"] == gold["leaf_index"] and r["sector"] == gold["sector"]
             and r["n_inliers"] == gold["n_inliers"] and _inl_sha(r["inliers"]) == gold["inliers_sha256"]
-            and [float(x) for x in r["point"]] == gold["point"])
+            and [float(x) for x in r["point"][:k]] == gold["point"] and not any(r["point"][k:]))
 
 
 def serve_bench(args, ctx=None):

@@ -28,6 +28,21 @@
  *                                        Requires hi[0]-lo[0] == hi[1]-lo[1];
  *                                        yaw always spans [0, 2 pi) in four
  *                                        sectors, lo[3]/hi[3] are ignored.
+ *   GV_POSE5DOF cols (wx, wy, wz, xi, eta)  axes (x, y, z, yaw, f): a 2D-3D
+ *                                        match for a camera with known gravity
+ *                                        and unknown focal length (Sec. 4.2.1,
+ *                                        the (x, y, z, kappa, f) surface):
+ *                                        (xi, eta) are image coordinates whose
+ *                                        product with f gives the lateral and
+ *                                        elevation tangents, so f is the
+ *                                        reference focal length over the true
+ *                                        one.  Box as POSE4DOF plus lo[4] <
+ *                                        hi[4] with lo[4] > 0; eps[4] is the f
+ *                                        tolerance.  Tested in binary64 in both
+ *                                        precision modes.  GV_EINVAL unless
+ *                                        2 atan(1 + 2 eps[3]) + atan(max|xi|
+ *                                        hi[4]) < 3.1 (the directions one cell
+ *                                        admits then span less than pi).
  *   GV_SIM2D    cols (px, py, qx, qy)   axes (a, b, c, d): a candidate
  *                                        correspondence p -> q of two planar
  *                                        point sets under the similarity
@@ -41,8 +56,8 @@
  * descent, its canonized version passes within eps plus the accumulated
  * rounding allowance of the child cell, separately on each dependent axis.
  * The chosen leaf has the largest count; ties go to the lowest leaf index
- * (child digits in axis order, most significant first, POSE4DOF sector on
- * top).  Results are deterministic and do not depend on batching.
+ * (child digits in axis order, most significant first, the pose families'
+ * sector on top).  Results are deterministic and do not depend on batching.
  */
 #ifndef GVOTE_H
 #define GVOTE_H
@@ -66,7 +81,11 @@ enum {
   GV_ERANGE = -9     /* lattice too fine for the exact device arithmetic */
 };
 
-typedef enum { GV_LINE2D = 1, GV_PLANE3D = 2, GV_RAY3D = 3, GV_POSE4DOF = 4, GV_SIM2D = 5 } gv_family;
+typedef enum { GV_LINE2D = 1, GV_PLANE3D = 2, GV_RAY3D = 3, GV_POSE4DOF = 4, GV_SIM2D = 5, GV_POSE5DOF = 6 } gv_family;
+
+/* axes of the largest family (POSE5DOF); per-axis arrays below hold this
+ * many values, the unused ones ignored (inputs) or 0 (outputs) */
+#define GV_AXES 5
 
 /* GV_FP64_PLAIN: every predicate decision in binary64.
  * GV_FP32_FILTER: binary32 evaluation with a certified forward-error bound;
@@ -110,8 +129,8 @@ typedef struct {
   int cols_on_device;         /* 1: col[] are device pointers (borrowed until
                                  the call returns / the ticket is polled);
                                  0: host pointers (copied during the call) */
-  double lo[4], hi[4];        /* domain box, user units, family axis order */
-  double eps[4];              /* per-axis eps, user units.  POSE4DOF eps[3] is
+  double lo[GV_AXES], hi[GV_AXES]; /* domain box, user units, family axis order */
+  double eps[GV_AXES];        /* per-axis eps, user units.  Pose eps[3] is
                                  the yaw tolerance in radians, applied to
                                  kappa = tan(yaw offset inside the sector), so
                                  the tolerance on the yaw angle itself is
@@ -136,9 +155,9 @@ typedef struct {
   uint32_t levels;            /* L*: depth of the leaves */
   double ms_total, ms_kernels;
   /* with kernel_timing: summed event time, launches and algorithmic bytes
-   * of the incidence-test kernel (entries read; POSE4DOF also writes a pass
+   * of the incidence-test kernel (entries read; the pose families also write a pass
    * mask per entry) and of the compaction kernel (entries of the parents
-   * with a child in the chunk read, POSE4DOF masks read, children written) */
+   * with a child in the chunk read, pose masks read, children written) */
   double test_ms, compact_ms;
   uint64_t test_launches, compact_launches;
   uint64_t test_bytes, compact_bytes;
@@ -148,28 +167,28 @@ typedef struct {
 } gv_stats;
 
 typedef struct {
-  double point[4];            /* leaf centre, user units; POSE4DOF (x,y,z,yaw), yaw in [0,2pi) */
+  double point[GV_AXES];      /* leaf centre, user units; pose (x,y,z,yaw[,f]), yaw in [0,2pi) */
   uint64_t count;             /* maximum depth: number of original surfaces */
   uint64_t leaf_index;
-  int32_t sector;             /* POSE4DOF yaw sector (0..3), else 0 */
-  int32_t leaf_coords[4];
+  int32_t sector;             /* pose families: yaw sector (0..3), else 0 */
+  int32_t leaf_coords[GV_AXES];
   int64_t *inliers;           /* caller buffer (host), sorted ascending */
   uint64_t inliers_cap;
   uint64_t n_inliers;         /* on GV_EBUFSZ: required capacity */
-  double bound[4];            /* certified approximation bound per axis, user
+  double bound[GV_AXES];      /* certified approximation bound per axis, user
                                  units (Sec. 3.2): on an axis that surfaces
                                  depend on (LINE2D b, PLANE3D a0, every RAY3D
-                                 axis, POSE4DOF z and yaw), every reported
+                                 axis, pose z and yaw), every reported
                                  inlier's range over the leaf's parameter box
                                  comes within bound[j] of the leaf's interval
                                  on that axis: the last pad plus the
-                                 accumulated canonization allowance.  POSE4DOF
+                                 accumulated canonization allowance.  Pose
                                  bound[3] is in kappa units, which also bounds
                                  the yaw angle in radians (|d yaw/d kappa| <=
                                  1), and holds where the leaf is farther from
                                  the match than the apex guard (one leaf xy
                                  side).  On a pure parameter axis (LINE2D a,
-                                 PLANE3D a1 a2, POSE4DOF x y): half the leaf
+                                 PLANE3D a1 a2, pose x y and f): half the leaf
                                  side, the distance from point[] to any point
                                  of the leaf. */
   gv_stats stats;
@@ -215,7 +234,7 @@ gv_status gv_solve_noalloc(gv_ctx *ctx, const gv_problem *p, gv_result *r);
  * parameters, row-major, t_out n x 4 and f_out n x 2 (host buffers), and
  * tag_out n (RAY3D parameter axis, else 0; may be NULL).  Layout per family:
  * LINE2D t=(t,0,0,0) f=(f,0); PLANE3D t=(t1,t2,0,0) f=(f,0); RAY3D
- * t=(t_q1,0,t_q2,0) f=(f_q1,f_q2); POSE4DOF t=(W1,W2,xi,eta') f=(W3,0); SIM2D
+ * t=(t_q1,0,t_q2,0) f=(f_q1,f_q2); POSE4DOF and POSE5DOF t=(W1,W2,xi,eta') f=(W3,0); SIM2D
  * t=(t_ca,t_cb,t_da,t_db) f=(f_c,f_d) (slopes of the dependent axes c, d over
  * the parameter axes a, b). */
 gv_status gv_parametrize(gv_ctx *ctx, const gv_problem *p, double *t_out, double *f_out,
@@ -240,16 +259,17 @@ gv_status gv_cancel(gv_ctx *ctx, uint64_t ticket);
  * within eps of each child, Sec. 3.2.1 and the Surface-Box paragraph of Sec.
  * 3.3), for parity checks of that step.  Every observation of p becomes its
  * canonical surface at the cell of `level` with integer coordinates
- * coords[0..3] (each in [0, 2^min(level, L_j))) and, for POSE4DOF, yaw
+ * coords[0..4] (each in [0, 2^min(level, L_j)), 0 beyond the family's axes)
+ * and, for the pose families, yaw
  * sector `sector` (0..3, else 0): the root canonization followed by the
- * child canonization of every level on the path to that cell (POSE4DOF and
+ * child canonization of every level on the path to that cell (pose and
  * exact mode: the root quantization only).  It is then tested against each
  * child of the cell exactly as the search tests it, in p->precision.
  * masks_out[i] (host buffer of n words) gets bit d set when surface i passes
  * child digit d (the split axes' bits in axis order, most significant
  * first).  stats_out (may be NULL): tests = n * children, fp64_rechecks =
  * decisions the binary32 filter left to binary64.  0 <= level < L*. */
-gv_status gv_incidence(gv_ctx *ctx, const gv_problem *p, int32_t level, int32_t sector, const int32_t coords[4],
+gv_status gv_incidence(gv_ctx *ctx, const gv_problem *p, int32_t level, int32_t sector, const int32_t coords[GV_AXES],
                        uint32_t *masks_out, gv_stats *stats_out);
 
 /* Static text for a status code. */

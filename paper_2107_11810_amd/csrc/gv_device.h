@@ -9,18 +9,20 @@
 //   K_i = t_i / s_t,i(m)     (s_t,i(m) = s_f * 2^min(m, L_i), an integer)
 //   F_q = (G_q(u) - u_q) / s_f   (its height at the cell's min corner)
 // and both the child test and the next canonization are exact small-integer
-// arithmetic in units of s_f/2.  The POSE4DOF family is quantized once at the
-// root and evaluated in binary64 (or binary32 with a certified bound).
+// arithmetic in units of s_f/2.  The two camera-posing families (POSE4DOF,
+// and POSE5DOF with the focal-length factor f as a fifth axis) are quantized
+// once at the root and evaluated in binary64 (POSE4DOF also in binary32 with
+// a certified bound).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
 #define GV_MAXL 40
-#define GV_MAXD 4
+#define GV_MAXD 5
 #define GV_ITEM 1024  // entries per work item (one wave)
 
-enum { FAM_LINE2D = 1, FAM_PLANE3D = 2, FAM_RAY3D = 3, FAM_POSE4DOF = 4, FAM_SIM2D = 5 };
+enum { FAM_LINE2D = 1, FAM_PLANE3D = 2, FAM_RAY3D = 3, FAM_POSE4DOF = 4, FAM_SIM2D = 5, FAM_POSE5DOF = 6 };
 // Exact mode of a linear family (quantized once at the root to a fixed
 // 2^-36 lattice, never re-canonized, tested in binary64): kernel-side family
 // code = family + 8.
@@ -30,24 +32,27 @@ constexpr int fam_base(int f) { return f >= 8 ? f - 8 : f; }
 // families whose count pass stores per-entry pass masks and whose
 // compaction copies entries unchanged (the surfaces do not change below the
 // root)
-constexpr bool fam_masked(int f) { return f == FAM_POSE4DOF || fam_exact(f); }
+constexpr bool fam_pose(int f) { return f == FAM_POSE4DOF || f == FAM_POSE5DOF; }
+constexpr bool fam_masked(int f) { return fam_pose(f) || fam_exact(f); }
 
 // Per-level constants for the test from level m to level m+1.
 struct LevelC {
-  int32_t split[4];   // 1 if axis j splits at level m
-  int32_t H[4];       // h_j(m) / s_f,j  (linear families)
-  int32_t padu[4];    // 2 pad_j(m) / s_f,j (linear families)
-  int32_t abits;      // number of split axes
-  int32_t rem_next;   // index bits below level m+1
-  uint8_t cbits[16];  // child digit -> bit j set iff b_j = 1
+  int32_t split[GV_MAXD];  // 1 if axis j splits at level m
+  int32_t H[4];            // h_j(m) / s_f,j  (linear families)
+  int32_t padu[4];         // 2 pad_j(m) / s_f,j (linear families)
+  int32_t abits;           // number of split axes
+  int32_t rem_next;        // index bits below level m+1
+  uint8_t cbits[32];       // child digit -> bit j set iff b_j = 1
 };
 
 struct ProbC {
   int32_t fam, d, Lstar, B, Bcell, nsec;
-  int32_t L[4];
+  int32_t L[GV_MAXD];
   uint64_t idxmask;        // 2^B - 1
   // front end
-  double lo[4], E[4], inv[4], ce;
+  double lo[GV_MAXD], E[GV_MAXD], inv[GV_MAXD], ce;
+  // POSE5DOF: the f axis in user units, f = flo + Ef u (POSE4DOF: f = 1)
+  double flo, Ef;
   // linear lattice
   double sf[4], inv_sf[4];
   // pose lattice
@@ -62,7 +67,7 @@ struct ProbC {
 };
 
 struct Cell {
-  int32_t c[4];
+  int32_t c[GV_MAXD];
   uint64_t prefix;   // index bits of this cell (sector on top for POSE4DOF)
   uint64_t off;      // first entry of its list in the batch
   uint32_t len;      // number of entries

@@ -848,7 +848,7 @@ __global__ void k_emit_ranked(LevelC lv, const Cell* __restrict__ cells, const u
   const Cell P = cells[c];
   Cell o;
   const uint32_t cb = lv.cbits[ch];
-  for (int a = 0; a < 4; a++) o.c[a] = lv.split[a] ? 2 * P.c[a] + (int32_t)((cb >> a) & 1u) : P.c[a];
+  for (int a = 0; a < GV_MAXD; a++) o.c[a] = lv.split[a] ? 2 * P.c[a] + (int32_t)((cb >> a) & 1u) : P.c[a];
   o.prefix = (P.prefix << lv.abits) | ch;
   o.off = coff[r - r0];
   o.len = cnent[k];
@@ -1116,6 +1116,8 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
                                                  const uint64_t* __restrict__ coff, EO* __restrict__ out,
                                                  int* __restrict__ ovf) {
   bool fits = true;
+  // children a cell can have: one bit of the pass mask each
+  constexpr uint32_t NCP = POSE ? 8u * (uint32_t)sizeof(M) : 8u;
   const uint32_t nch = 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -1124,10 +1126,10 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
   for (uint32_t it = wave; it < nitems; it += nwaves) {
     const Item I = items[it];
     uint32_t kmask = 0;
-    uint64_t wpos[16];
+    uint64_t wpos[NCP];
     const uint32_t first = ioff[I.cell];
 #pragma unroll
-    for (uint32_t ch = 0; ch < (POSE ? 16u : 8u); ch++) {
+    for (uint32_t ch = 0; ch < NCP; ch++) {
       wpos[ch] = 0;
       if (ch >= nch) continue;
       const uint32_t r = rank_of[(uint64_t)I.cell * nch + ch];
@@ -1141,7 +1143,8 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
     const uint32_t cnt = I.cnt;
     if constexpr (POSE) {
       // G entries per lane in registers, survivors written child by child:
-      // one sequential run per child list instead of sixteen interleaved ones
+      // one sequential run per child list instead of one interleaved piece
+      // per child and row
       // Entries move as words the copy never looks inside (16-byte words,
       // or 8-byte ones for the 24-byte unit entry).  EntQ32 -> EntQ24 drops
       // the weight (1 in a unit list) and the padding on the way.
@@ -1154,9 +1157,9 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
       // adds its 32-bit rank offset, so a store is a scalar base plus one
       // per-lane offset
       using gchar = __attribute__((address_space(1))) char;  // global memory
-      gchar* cb[16];
+      gchar* cb[NCP];
 #pragma unroll
-      for (int ch = 0; ch < 16; ch++)
+      for (uint32_t ch = 0; ch < NCP; ch++)
         cb[ch] = (gchar*)out + uniform_u64(wpos[ch]) * sizeof(EO);  // address-space cast
       for (uint32_t k0 = 0; k0 < cnt; k0 += 64 * G) {
         uint32_t mk[G];
@@ -1193,7 +1196,7 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
         // vmcnt(0), expcnt and lgkmcnt left at their maxima.
         __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
-        for (int ch = 0; ch < 16; ch++) {
+        for (uint32_t ch = 0; ch < NCP; ch++) {
           if (!((kmask >> ch) & 1u)) continue;
 #pragma unroll
           for (int j = 0; j < G; j++) {
@@ -1223,7 +1226,7 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
         if (mask) e = ents[ei];
       }
 #pragma unroll
-      for (uint32_t ch = 0; ch < (POSE ? 16u : 8u); ch++) {
+      for (uint32_t ch = 0; ch < NCP; ch++) {
         if (!((kmask >> ch) & 1u)) continue;
         const bool p = (mask >> ch) & 1u;
         const uint64_t bal = __ballot(p);

@@ -1,0 +1,239 @@
+// gv_pose5.h -- the 5-DoF camera-posing family (Sec. 4.2.1: known gravity
+// direction, unknown focal length).  Axes (x, y, z, kappa, f): the camera
+// position, the tangent of the yaw offset inside one of four sectors, and
+// the factor f that turns image coordinates into direction tangents
+// (tangent = xi f).  A match (w, xi, eta) is the 3-surface
+//   kappa = ((w2 - y) - xi f (w1 - x)) / ((w1 - x) + xi f (w2 - y)),
+//   z     = w3 - eta f sqrt((w1 - x)^2 + (w2 - y)^2),
+// i.e. the 4-DoF surface with xi and eta scaled by f.  The surfaces are
+// quantized once at the root (the pose lattice, with the f bound in its
+// derivative bounds) and tested in binary64; a level has up to 32 children
+// (every axis split), so pass masks are 32-bit words.
+//
+// Over a cell, f runs through [Fl, Fh] (Fl > 0):
+//   z-half: |eta| f r spans [|eta| Fl r_min, |eta| Fh r_max], so the
+//     4-DoF conditions hold with the slope |eta| Fh on the r_max side and
+//     |eta| Fl on the r_min side;
+//   kappa-half: the cone of directions with kappa in [Llo, Lhi] at tangent
+//     t turns with atan t, so over t in [t_lo, t_hi] (t = xi f) the
+//     directions form one arc from (1 - Llo t_lo, Llo + t_lo)
+//     counter-clockwise to (1 - Lhi t_hi, Lhi + t_hi); every direction of it
+//     has a t at which kappa is in range and v1 + t v2 > 0.
+// Both conditions are tested separately, as for every family with two
+// dependent axes.
+#pragma once
+#include "gv_kernels.h"
+#include "gv_root.h"
+
+// child boxes of an item's cell per bit value (wave-uniform); f in user units
+struct Pose5Level {
+  double Xlo[2], Xhi[2], Ylo[2], Yhi[2], ZH[2], ZL[2], Llo[2], Lhi[2], Flo[2], Fhi[2];
+};
+
+__device__ inline void pose5_level_boxes(const ProbC& P, const LevelC& lv, const Cell& C, int m, Pose5Level& B) {
+  const int m1 = m + 1;
+  double h[5];
+  for (int j = 0; j < 5; j++) h[j] = ldexp(1.0, -min(m1, P.L[j]));
+  for (int b = 0; b < 2; b++) {
+    const int32_t cx = lv.split[0] ? 2 * C.c[0] + b : C.c[0];
+    const int32_t cy = lv.split[1] ? 2 * C.c[1] + b : C.c[1];
+    const int32_t cz = lv.split[2] ? 2 * C.c[2] + b : C.c[2];
+    const int32_t ck = lv.split[3] ? 2 * C.c[3] + b : C.c[3];
+    const int32_t cf = lv.split[4] ? 2 * C.c[4] + b : C.c[4];
+    B.Xlo[b] = (double)cx * h[0];
+    B.Xhi[b] = (double)(cx + 1) * h[0];
+    B.Ylo[b] = (double)cy * h[1];
+    B.Yhi[b] = (double)(cy + 1) * h[1];
+    const double Zlo = (double)cz * h[2], Zhi = (double)(cz + 1) * h[2];
+    B.ZH[b] = Zhi + P.padz;
+    B.ZL[b] = Zlo - P.padz;
+    const double Klo = 2.0 * ((double)ck * h[3]) - 1.0, Khi = 2.0 * ((double)(ck + 1) * h[3]) - 1.0;
+    B.Llo[b] = Klo - P.padk;
+    B.Lhi[b] = Khi + P.padk;
+    B.Flo[b] = P.flo + P.Ef * ((double)cf * h[4]);
+    B.Fhi[b] = P.flo + P.Ef * ((double)(cf + 1) * h[4]);
+  }
+}
+
+// z-half over the f interval: zp from zpre (the z bit), ah2 = (|eta| Fh)^2,
+// al2 = (|eta| Fl)^2 (the f bit)
+__device__ inline bool zhalf5(const ZPre<double>& z, double ah2, double al2, double rmin2, double rmax2) {
+  const bool lo_ok = (z.Tlo <= 0.0) || (ah2 * rmax2 >= z.Ylo);
+  const bool hi_ok = (z.Thi >= 0.0) && (al2 * rmin2 <= z.Yhi);
+  return lo_ok && hi_ok;
+}
+
+// kappa-half edge directions over the tangents t = xi f, f in [Fl, Fh]
+__device__ inline KEdge<double> kedge5(double xi, double Llo, double Lhi, double Fl, double Fh) {
+  const double t1 = xi * Fl, t2 = xi * Fh;
+  const double tl = t1 < t2 ? t1 : t2, th = t1 < t2 ? t2 : t1;
+  KEdge<double> e;
+  e.pl = Llo * tl;
+  e.ph = Lhi * th;
+  e.elx = 1.0 - e.pl;
+  e.ely = Llo + tl;
+  e.ehx = 1.0 - e.ph;
+  e.ehy = Lhi + th;
+  return e;
+}
+
+// Pass mask over the children of one cell for one surface.  ALL: every axis
+// splits at this level (32 children), so no per-axis checks.  Half-test bit
+// index: bx | by << 1 | (z or kappa bit) << 2 | bf << 3.
+template <bool ALL>
+__device__ inline uint32_t pose5_mask64(const ProbC& P, const LevelC& lv, const Pose5Level& B, int sector, double W1,
+                                        double W2, double W3, double xi, double eta) {
+  const uint32_t nch = ALL ? 32u : 1u << lv.abits;
+  uint32_t zbits = 0, kbits = 0;
+  const ZPre<double> zp[2] = {zpre<double>(W3, eta, B.ZH[0], B.ZL[0]), zpre<double>(W3, eta, B.ZH[1], B.ZL[1])};
+  const double a = eta >= 0.0 ? eta : -eta;
+#pragma unroll
+  for (int bf = 0; bf < 2; bf++) {
+    if (!ALL && bf && !lv.split[4]) continue;
+    const double ah = a * B.Fhi[bf], al = a * B.Flo[bf];
+    const double ah2 = ah * ah, al2 = al * al;
+    const KEdge<double> ke[2] = {kedge5(xi, B.Llo[0], B.Lhi[0], B.Flo[bf], B.Fhi[bf]),
+                                 kedge5(xi, B.Llo[1], B.Lhi[1], B.Flo[bf], B.Fhi[bf])};
+#pragma unroll
+    for (int xy = 0; xy < 4; xy++) {
+      const int bx = xy & 1, by = xy >> 1;
+      if (!ALL && ((bx && !lv.split[0]) || (by && !lv.split[1]))) continue;
+      const VBox<double> v = pose_vbox<double>(W1, W2, B.Xlo[bx], B.Xhi[bx], B.Ylo[by], B.Yhi[by], sector);
+      const double rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        if (!ALL && b && !lv.split[2]) continue;
+        if (zhalf5(zp[b], ah2, al2, rmin2, rmax2)) zbits |= 1u << (xy | (b << 2) | (bf << 3));
+      }
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        if (!ALL && b && !lv.split[3]) continue;
+        if (khalf64e(v, rmin2, P.Rg2, ke[b])) kbits |= 1u << (xy | (b << 2) | (bf << 3));
+      }
+    }
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int ch = 0; ch < 32; ch++) {
+    if ((uint32_t)ch >= nch) break;
+    const uint32_t cb = lv.cbits[ch];
+    const uint32_t xy = cb & 3u, zb = (cb >> 2) & 1u, kb = (cb >> 3) & 1u, fb = (cb >> 4) & 1u;
+    if (((zbits >> (xy | (zb << 2) | (fb << 3))) & 1u) && ((kbits >> (xy | (kb << 2) | (fb << 3))) & 1u))
+      mask |= 1u << ch;
+  }
+  return mask;
+}
+
+// Incidence test and per-child counts of a batch (one wave per item), with
+// a 32-bit pass mask stored per entry for the compaction.  UNIT: every
+// multiplicity is 1, so a child's count is the popcount of its ballot.
+template <bool UNIT, bool ALL>
+__global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ Ptab, int m, LevelC lv,
+                                                     const Cell* __restrict__ cells, const Item* __restrict__ items,
+                                                     const uint32_t* __restrict__ nitems_p,
+                                                     const EntQ64* __restrict__ ents, uint32_t* __restrict__ masks,
+                                                     uint32_t* __restrict__ ccnt, uint32_t* __restrict__ cnent,
+                                                     uint32_t* __restrict__ itemcnt, uint32_t istride) {
+  const uint32_t nch = ALL ? 32u : 1u << lv.abits;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t nitems = *nitems_p;
+  for (uint32_t it = wave; it < nitems; it += nwaves) {
+    const Item I = items[it];
+    const Cell C = cells[I.cell];
+    const ProbC& P = Ptab[C.prob];
+    const uint32_t cnt = I.cnt;
+    Pose5Level B;
+    pose5_level_boxes(P, lv, C, m, B);
+    uint32_t aw[32], an[32];
+#pragma unroll
+    for (int ch = 0; ch < 32; ch++) { aw[ch] = 0; an[ch] = 0; }
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      const uint64_t ei = I.off + k;
+      uint32_t mask = 0, w = 0;
+      if (k < cnt) {
+        const EntQ64 e = ents[ei];
+        w = e.w;
+        mask = pose5_mask64<ALL>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+        masks[ei] = mask;
+      }
+#pragma unroll
+      for (int ch = 0; ch < 32; ch++) {
+        const bool p = (mask >> ch) & 1u;
+        if constexpr (UNIT) {
+          an[ch] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
+        } else {
+          aw[ch] += p ? w : 0u;
+          an[ch] += p ? 1u : 0u;
+        }
+      }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 32; ch++) {
+      if ((uint32_t)ch < nch) {
+        const uint32_t n = UNIT ? an[ch] : wave_sum_u32(an[ch]);
+        const uint32_t w = UNIT ? n : wave_sum_u32(aw[ch]);
+        if (lane == 0 && n) {
+          atomicAdd(&ccnt[I.cell * nch + ch], w);
+          atomicAdd(&cnent[I.cell * nch + ch], n);
+          if (istride) itemcnt[(uint64_t)ch * istride + it] = n;
+        }
+      }
+    }
+  }
+}
+
+// Replay of every original match along its problem's chosen path: the
+// root-quantized surface passes every cell of the path (member tracking,
+// Sec. 3.2.1; the surfaces do not change below the root).
+__global__ void k_replay_pose5(const ProbC* __restrict__ Ptab, const double* __restrict__ m64, uint64_t Ntot,
+                               const uint64_t* __restrict__ ooff, uint32_t nprob, const PathC* __restrict__ paths,
+                               uint32_t* __restrict__ flag) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Ntot; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = prob_of(ooff, nprob, i);
+    const ProbC& P = Ptab[p];
+    const PathC& path = paths[p];
+    const double W1 = m64[i], W2 = m64[Ntot + i], W3 = m64[2 * Ntot + i], xi = m64[3 * Ntot + i],
+                 eta = m64[4 * Ntot + i];
+    const double a = eta >= 0.0 ? eta : -eta;
+    int32_t cc[5] = {0, 0, 0, 0, 0};
+    uint32_t ok = 1;
+    for (int m = 0; m < P.Lstar && ok; m++) {
+      const LevelC& lv = P.lev[m];
+      const uint32_t cb = lv.cbits[path.digit[m]];
+      int32_t ch[5];
+      for (int j = 0; j < 5; j++) ch[j] = lv.split[j] ? 2 * cc[j] + (int32_t)((cb >> j) & 1u) : cc[j];
+      const int m1 = m + 1;
+      double h[5];
+      for (int j = 0; j < 5; j++) h[j] = ldexp(1.0, -min(m1, P.L[j]));
+      const double Xlo = (double)ch[0] * h[0], Xhi = (double)(ch[0] + 1) * h[0];
+      const double Ylo = (double)ch[1] * h[1], Yhi = (double)(ch[1] + 1) * h[1];
+      const double Zlo = (double)ch[2] * h[2], Zhi = (double)(ch[2] + 1) * h[2];
+      const double Klo = 2.0 * ((double)ch[3] * h[3]) - 1.0, Khi = 2.0 * ((double)(ch[3] + 1) * h[3]) - 1.0;
+      const double Fl = P.flo + P.Ef * ((double)ch[4] * h[4]), Fh = P.flo + P.Ef * ((double)(ch[4] + 1) * h[4]);
+      const VBox<double> v = pose_vbox<double>(W1, W2, Xlo, Xhi, Ylo, Yhi, path.sector);
+      const double rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
+      const double ah = a * Fh, al = a * Fl;
+      ok = zhalf5(zpre<double>(W3, eta, Zhi + P.padz, Zlo - P.padz), ah * ah, al * al, rmin2, rmax2) &&
+           khalf64e(v, rmin2, P.Rg2, kedge5(xi, Klo - P.padk, Khi + P.padk, Fl, Fh));
+      for (int j = 0; j < 5; j++) cc[j] = ch[j];
+    }
+    flag[i] = ok;
+  }
+}
+
+// Incidence test only (gv_incidence): every root surface against the
+// children of cell C at level m, exactly as in the count pass.
+__global__ void k_incidence_pose5(const ProbC* __restrict__ Pp, const EntQ64* __restrict__ root, int64_t n, Cell C,
+                                  int m, uint32_t* __restrict__ masks) {
+  const ProbC& P = *Pp;
+  const LevelC& lv = P.lev[m];
+  Pose5Level B;
+  pose5_level_boxes(P, lv, C, m, B);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const EntQ64 e = root[i];
+    masks[i] = pose5_mask64<false>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+  }
+}

@@ -96,19 +96,23 @@ __global__ void k_root_lin(const ProbC* __restrict__ Pp, Cols cols, int64_t n, t
   atomicMax(&maxabs[1], mf);
 }
 
-__global__ void k_pose_bounds(const ProbC* __restrict__ Pp, Cols cols, int64_t n, unsigned long long* __restrict__ mx,
-                              int* __restrict__ bad) {
+// data bounds of a pose problem: mx[0] = max |eta'|, mx[1] = max squared
+// horizontal reach from the box, mx[7] = max |xi|
+__global__ void k_pose_bounds(const ProbC* __restrict__ Pp, int fam, Cols cols, int64_t n,
+                              unsigned long long* __restrict__ mx, int* __restrict__ bad) {
   const ProbC& P = *Pp;
-  double H = 0.0, R2 = 0.0;
+  double H = 0.0, R2 = 0.0, Xm = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double t[4], f[2];
     int32_t tag;
-    if (!front_eval(FAM_POSE4DOF, cols.c, i, P, t, f, &tag)) {
+    if (!front_eval(fam, cols.c, i, P, t, f, &tag)) {
       atomicOr(bad, 1);
       continue;
     }
     double h = fabs(t[3]);
     H = h > H ? h : H;
+    double x = fabs(t[2]);
+    Xm = x > Xm ? x : Xm;
     double a0 = t[0] * t[0], a1 = (t[0] - 1.0) * (t[0] - 1.0);
     double b0 = t[1] * t[1], b1 = (t[1] - 1.0) * (t[1] - 1.0);
     double r2 = (a0 > a1 ? a0 : a1) + (b0 > b1 ? b0 : b1);
@@ -116,11 +120,12 @@ __global__ void k_pose_bounds(const ProbC* __restrict__ Pp, Cols cols, int64_t n
   }
   atomic_max_f64_pos(&mx[0], H);
   atomic_max_f64_pos(&mx[1], R2);
+  atomic_max_f64_pos(&mx[7], Xm);
 }
 
 // quantize once at the root to the fixed pose lattice; the binary64 master
 // is SoA with stride Ntot, entries carry their global index
-__global__ void k_root_pose(const ProbC* __restrict__ Pp, Cols cols, int64_t n, uint64_t base, uint64_t Ntot,
+__global__ void k_root_pose(const ProbC* __restrict__ Pp, int fam, Cols cols, int64_t n, uint64_t base, uint64_t Ntot,
                             double* __restrict__ m64, EntQ32* __restrict__ e32, EntQ64* __restrict__ e64,
                             unsigned long long* __restrict__ mx) {
   const ProbC& P = *Pp;
@@ -128,7 +133,7 @@ __global__ void k_root_pose(const ProbC* __restrict__ Pp, Cols cols, int64_t n, 
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double t[4], f[2];
     int32_t tag;
-    front_eval(FAM_POSE4DOF, cols.c, i, P, t, f, &tag);
+    front_eval(fam, cols.c, i, P, t, f, &tag);
     const double W1 = rint(t[0] * P.inv_sW) * P.sW;
     const double W2 = rint(t[1] * P.inv_sW) * P.sW;
     const double W3 = rint(f[0] * P.inv_sW3) * P.sW3;

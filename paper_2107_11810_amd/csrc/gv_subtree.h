@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(GV_SUB_WG) k_subtree_pose(
           if (key <= *(volatile unsigned long long*)&best[C.prob]) continue;  // the bound moved
           Cell K = C;
           const uint32_t cb = lv.cbits[ch];
-          for (int a = 0; a < 4; a++) K.c[a] = lv.split[a] ? 2 * C.c[a] + (int32_t)((cb >> a) & 1u) : C.c[a];
+          for (int a = 0; a < GV_MAXD; a++) K.c[a] = lv.split[a] ? 2 * C.c[a] + (int32_t)((cb >> a) & 1u) : C.c[a];
           K.prefix = (C.prefix << lv.abits) | ch;
           K.off = 0;
           K.len = fr[d].nent[ch];

@@ -34,6 +34,7 @@
 #include "gv_root.h"
 #include "gv_exact.h"
 #include "gv_subtree.h"
+#include "gv_pose5.h"
 
 // Caching device allocator owned by a context.  All library work on a
 // context is ordered on its stream, so a block released after its last use
@@ -203,7 +204,7 @@ constexpr int kTuneCand[] = {2, 4, 8, 16, 32};
 constexpr int kNCand = 5;
 constexpr int kTuneSamples = 4;
 constexpr uint64_t kTuneMinBytes = 256ull << 20;  // smaller launches use the default shape
-constexpr int kLastFam = GV_SIM2D;                 // family codes run 1..kLastFam
+constexpr int kLastFam = GV_POSE5DOF;               // family codes run 1..kLastFam
 constexpr int kGridDefault = 8;
 struct gvi_tune_slot {
   int chosen = 0;  // blocks per CU once chosen
@@ -283,7 +284,7 @@ struct Setup {
   double ez, ek;  // pose eps'
   bool filter;    // binary32 filter usable
   bool exact;     // canon_c = +inf: quantize once to 2^-36, no re-canonization
-  double Hmax, R2;  // POSE4DOF data bounds: max |eta'|, max squared horizontal reach
+  double Hmax, R2;  // pose data bounds: max |eta'|, max squared horizontal reach
   int64_t n;
 };
 
@@ -306,17 +307,19 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
     case GV_RAY3D: S.d = 3; S.ell = 2; break;
     case GV_SIM2D: S.d = 4; S.ell = 2; break;
     case GV_POSE4DOF: S.d = 4; S.ell = 4; break;
+    case GV_POSE5DOF: S.d = 5; S.ell = 4; break;
     default: why = "bad family"; return GV_EINVAL;
   }
+  const bool pose = fam_pose(S.fam);
   P.fam = S.fam;
   P.d = S.d;
-  P.nsec = S.fam == GV_POSE4DOF ? 4 : 1;
+  P.nsec = pose ? 4 : 1;
   double c = p->canon_c == 0.0 ? 1.0 : p->canon_c;
   if (!(c > 0.0) || std::isnan(c)) { why = "canon_c must be > 0"; return GV_EINVAL; }
   S.exact = std::isinf(c);
   P.exact = S.exact ? 1 : 0;
-  int nuser = S.fam == GV_POSE4DOF ? 3 : S.d;
-  for (int j = 0; j < nuser; j++) {
+  for (int j = 0; j < S.d; j++) {
+    if (pose && j == 3) continue;  // kappa: fixed [-1, 1] per sector
     if (!std::isfinite(p->lo[j]) || !std::isfinite(p->hi[j]) || !(p->hi[j] > p->lo[j])) { why = "bad box"; return GV_EINVAL; }
     if (!std::isfinite(p->eps[j]) || !(p->eps[j] > 0.0)) { why = "bad eps"; return GV_EINVAL; }
     P.lo[j] = p->lo[j];
@@ -325,8 +328,8 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
     S.epsn[j] = p->eps[j] * P.inv[j];
   }
   double epsk = 0.0;
-  if (S.fam == GV_POSE4DOF) {
-    if (P.E[0] != P.E[1]) { why = "POSE4DOF needs hi[0]-lo[0] == hi[1]-lo[1]"; return GV_EINVAL; }
+  if (pose) {
+    if (P.E[0] != P.E[1]) { why = "pose families need hi[0]-lo[0] == hi[1]-lo[1]"; return GV_EINVAL; }
     if (!std::isfinite(p->eps[3]) || !(p->eps[3] > 0.0)) { why = "bad yaw eps"; return GV_EINVAL; }
     epsk = p->eps[3];
     P.lo[3] = -1.0;
@@ -334,10 +337,19 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
     P.inv[3] = 0.5;
     S.epsn[3] = epsk * 0.5;
     P.ce = P.E[0] * P.inv[2];
+    // f: the factor of the image coordinates in the direction tangents,
+    // positive over the box (POSE4DOF: f = 1)
+    P.flo = 1.0;
+    P.Ef = 0.0;
+    if (S.fam == GV_POSE5DOF) {
+      if (!(p->lo[4] > 0.0)) { why = "POSE5DOF needs lo[4] > 0 (f)"; return GV_EINVAL; }
+      P.flo = p->lo[4];
+      P.Ef = P.E[4];
+    }
   }
   int Lstar = 0, Bcell = 0;
   for (int j = 0; j < S.d; j++) {
-    double ej = (S.fam == GV_POSE4DOF && j == 3) ? epsk : p->eps[j];
+    double ej = (pose && j == 3) ? epsk : p->eps[j];
     int L = 0;
     while (std::ldexp(P.E[j], -L) > ej) {
       if (++L > 30) { why = "eps too small for the box"; return GV_EINVAL; }
@@ -350,7 +362,7 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
   if (Lstar > GV_MAXL) { why = "too many levels"; return GV_EINVAL; }
   P.Lstar = Lstar;
   P.Bcell = Bcell;
-  P.B = Bcell + (S.fam == GV_POSE4DOF ? 2 : 0);
+  P.B = Bcell + (pose ? 2 : 0);
   if (P.B > 62) { why = "leaf index does not fit 62 bits"; return GV_EINVAL; }
   if ((uint64_t)p->n >= (1ULL << (64 - P.B))) { why = "n too large for the key"; return GV_EINVAL; }
   P.idxmask = (1ULL << P.B) - 1ULL;
@@ -369,8 +381,8 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
     std::memset(&lv, 0, sizeof(lv));
     lv.abits = ab[m];
     lv.rem_next = rem[m + 1];
-    int splits[4], ns = 0;
-    for (int j = 0; j < 4; j++) {
+    int splits[GV_MAXD], ns = 0;
+    for (int j = 0; j < GV_MAXD; j++) {
       lv.split[j] = (j < S.d && m < P.L[j]) ? 1 : 0;
       if (lv.split[j]) splits[ns++] = j;
     }
@@ -382,14 +394,14 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
       lv.cbits[dg] = cb;
     }
   }
-  if (S.fam != GV_POSE4DOF && S.exact) {
+  if (!pose && S.exact) {
     // exact mode: one 2^-36 lattice, pads = eps rounded up to it
     for (int q = 0; q < S.d; q++) {
       P.sf[q] = 0x1p-36;
       P.inv_sf[q] = 0x1p36;
       P.xpad[q] = std::ceil((S.epsn[q] + 0.0) / P.sf[q]) * P.sf[q];
     }
-  } else if (S.fam != GV_POSE4DOF) {
+  } else if (!pose) {
     for (int q = 0; q < S.d; q++) {
       double ep = S.epsn[q] / (c * (double)(Lstar + 1));
       P.sf[q] = p2floor(ep / (double)(S.ell + 1));
@@ -411,9 +423,19 @@ gv_status setup_axes(const gv_problem* p, Setup& S, std::string& why) {
   return GV_OK;
 }
 
-// POSE4DOF lattice from the data bounds (same definition as the oracle)
-void pose_lattice(Setup& S, double Hmax, double R2, double epsk) {
+// Pose lattice from the data bounds (same definition as the oracle): rounding
+// one parameter by half a step moves z and kappa by at most eps'/(2(l+1))
+// anywhere on the box, from the derivative bounds of z = W3 - eta' f r and
+// kappa = tan(phi - atan(xi f)) (Fb bounds f; 1 for POSE4DOF).  POSE5DOF:
+// false when the directions of one cell could span an arc of pi or more
+// (max |xi| f_hi too large), which the arc test does not handle.
+bool pose_lattice(Setup& S, double Hmax, double R2, double epsk, double Xmax, const gv_problem* p) {
   ProbC& P = S.P;
+  double Fb = 1.0;
+  if (S.fam == GV_POSE5DOF) {
+    if (!(2.0 * std::atan(1.0 + 2.0 * epsk) + std::atan(Xmax * p->hi[4]) < 3.1)) return false;
+    Fb = p->hi[4] * (1.0 + 0x1p-20);
+  }
   int Lxy = std::max(P.L[0], P.L[1]);
   double Rg = std::ldexp(1.0, -Lxy);
   P.Rg2 = Rg * Rg;
@@ -431,10 +453,10 @@ void pose_lattice(Setup& S, double Hmax, double R2, double epsk) {
   double pk0 = epsk + S.ek * 0.5;
   double Bk = 1.0 + (1.0 + pk0) * (1.0 + pk0);
   P.sW3 = p2floor(S.ez / l1);
-  P.sEta = p2floor(S.ez / (l1 * Rb));
-  double wz = S.ez / (l1 * Hb), wk = (S.ek * Rg) / (l1 * Bk);
+  P.sEta = p2floor(S.ez / (l1 * Rb * Fb));
+  double wz = S.ez / (l1 * Hb * Fb), wk = (S.ek * Rg) / (l1 * Bk);
   P.sW = p2floor(wz < wk ? wz : wk);
-  P.sXi = p2floor(S.ek / (l1 * Bk));
+  P.sXi = p2floor(S.ek / (l1 * Bk * Fb));
   P.padz = std::ceil((S.epsn[2] + S.ez * 0.5) / P.sW3) * P.sW3;
   P.padk = std::ceil((epsk + S.ek * 0.5) / P.sXi) * P.sXi;
   }
@@ -445,6 +467,7 @@ void pose_lattice(Setup& S, double Hmax, double R2, double epsk) {
   P.Rg2f = (float)P.Rg2;
   P.padzf = (float)P.padz;
   P.padkf = (float)P.padk;
+  return true;
 }
 
 // binary32 evaluation is exact on the inputs iff every lattice value and
@@ -482,7 +505,7 @@ struct ProbRec {
   std::string err;
   uint64_t count = 0, leaf = 0;
   PathC path{};
-  int32_t coords[4] = {0, 0, 0, 0};
+  int32_t coords[GV_MAXD] = {0, 0, 0, 0, 0};
   std::vector<int64_t> inliers;
   gv_stats stats{};
   // serving
@@ -922,7 +945,7 @@ void group_batch(Run& X, Batch& b, bool own_ents) {
 bool want_group(const Run& X, const Batch& b) {
   if (X.group_mode < 0 || b.nent < 2) return false;
   if (X.group_mode > 0) return true;
-  if (X.fam == GV_POSE4DOF || X.P0.exact) return false;
+  if (fam_pose(X.fam) || X.P0.exact) return false;
   const double avg = (double)b.nent / (double)std::max<uint32_t>(1, b.ncell);
   return avg >= 0.5 * X.lat_bound[b.level];
 }
@@ -995,7 +1018,22 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   auto evp = ev_begin(X, 0, cand, tbytes);
   X.stats.test_launches++;
   X.stats.test_bytes += tbytes;
-  if constexpr (FAM == FAM_POSE4DOF) {
+  if constexpr (FAM == FAM_POSE5DOF) {
+#define GV_COUNT_POSE5(U, A)                                                                                   \
+  k_count_pose5<U, A><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const EntQ64*)b.ents, \
+                                             (uint32_t*)pa->masks, ccnt, pa->cnent, itemcnt ? itemcnt : X.dummy, \
+                                             itemcnt ? pa->istride : 0u)
+    static_assert(std::is_same<E, EntQ64>::value && std::is_same<M, uint32_t>::value, "5-DoF lists are binary64");
+    const bool all = lv.abits == 5;
+    if (b.unit) {
+      if (all) GV_COUNT_POSE5(true, true);
+      else GV_COUNT_POSE5(true, false);
+    } else {
+      if (all) GV_COUNT_POSE5(false, true);
+      else GV_COUNT_POSE5(false, false);
+    }
+#undef GV_COUNT_POSE5
+  } else if constexpr (FAM == FAM_POSE4DOF) {
 #define GV_COUNT_POSE(U, A)                                                                                 \
   k_count_pose<E, U, A><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents, \
                                                 X.m64, X.Ntot, (uint16_t*)pa->masks, ccnt, pa->cnent, X.drecheck, \
@@ -1493,20 +1531,20 @@ void push_children(Run& X, Parent* pa, std::vector<Task>& stack) {
 // Epochs
 // ===========================================================================
 void decode_leaf(const ProbC& P, uint64_t idx, PathC& path, int32_t* coords) {
-  path.sector = P.fam == GV_POSE4DOF ? (int32_t)(idx >> P.Bcell) : 0;
-  int32_t cc[4] = {0, 0, 0, 0};
+  path.sector = fam_pose(P.fam) ? (int32_t)(idx >> P.Bcell) : 0;
+  int32_t cc[GV_MAXD] = {0, 0, 0, 0, 0};
   for (int m = 0; m < P.Lstar; m++) {
     const LevelC& lv = P.lev[m];
     const uint32_t dg = (uint32_t)((idx >> lv.rem_next) & ((1ull << lv.abits) - 1ull));
     path.digit[m] = (uint8_t)dg;
     const uint32_t cb = lv.cbits[dg];
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < GV_MAXD; a++)
       if (lv.split[a]) cc[a] = 2 * cc[a] + (int32_t)((cb >> a) & 1u);
   }
-  for (int a = 0; a < 4; a++) coords[a] = cc[a];
+  for (int a = 0; a < GV_MAXD; a++) coords[a] = cc[a];
 }
 
-int ncols_of(int fam, int d) { return fam == GV_RAY3D ? 6 : (fam == GV_POSE4DOF ? 5 : d); }
+int ncols_of(int fam, int d) { return fam == GV_RAY3D ? 6 : (fam_pose(fam) ? 5 : d); }
 
 // host-side validation and constants of one problem
 gv_status prepare_problem(ProbRec* pr) {
@@ -1524,7 +1562,8 @@ gv_status prepare_problem(ProbRec* pr) {
       pr->err = "missing column";
       return GV_EINVAL;
     }
-  const uint64_t eb = pr->S.fam == GV_POSE4DOF ? 4 * (80 + 2 * 34)
+  const uint64_t eb = pr->S.fam == GV_POSE5DOF ? 4 * (96 + 2 * 52)
+                      : pr->S.fam == GV_POSE4DOF ? 4 * (80 + 2 * 34)
                       : (pr->S.fam == GV_SIM2D ? 4 * 34 : (pr->S.fam == GV_RAY3D ? 4 * 26 : 4 * 18));
   pr->est_bytes = (uint64_t)std::max<int64_t>(pr->n, 1) * eb + (64ull << 20);
   return GV_OK;
@@ -1535,7 +1574,7 @@ bool same_structure(const ProbRec* a, const ProbRec* b) {
   const ProbC &A = a->S.P, &B = b->S.P;
   if (a->S.fam != b->S.fam || A.Lstar != B.Lstar || A.B != B.B || A.exact != B.exact) return false;
   if (a->p.precision != b->p.precision || a->p.group != b->p.group) return false;
-  for (int j = 0; j < 4; j++)
+  for (int j = 0; j < GV_MAXD; j++)
     if (A.L[j] != B.L[j]) return false;
   return std::memcmp(A.lev, B.lev, sizeof(LevelC) * A.Lstar) == 0;
 }
@@ -1980,8 +2019,9 @@ void build_exact(Run& X) {
 
 template <typename E>
 bool step_pose(Run& X) { return epoch_step<FAM_POSE4DOF, E, uint16_t>(X); }
+bool step_pose5(Run& X) { return epoch_step<FAM_POSE5DOF, EntQ64, uint32_t>(X); }
 
-// returns true when the binary32 filter is used
+// returns true when the binary32 filter is used (POSE4DOF only)
 bool build_pose(Run& X) {
   const uint32_t np = (uint32_t)X.probs.size();
   unsigned long long* dmx = dalloc<unsigned long long>(X, 8 * np);
@@ -1991,7 +2031,7 @@ bool build_pose(Run& X) {
   for (uint32_t p = 0; p < np; p++) {
     ProbRec* pr = X.probs[p];
     if (pr->n > 0)
-      k_pose_bounds<<<gs_grid(X, pr->n), 256, 0, X.st>>>(X.dP + p, pr->cols, pr->n, dmx + 8 * p, dbad + p);
+      k_pose_bounds<<<gs_grid(X, pr->n), 256, 0, X.st>>>(X.dP + p, X.fam, pr->cols, pr->n, dmx + 8 * p, dbad + p);
   }
   std::vector<unsigned long long> mxb(8 * np);
   std::vector<int> bad(np);
@@ -2001,13 +2041,18 @@ bool build_pose(Run& X) {
   std::vector<ProbC> tab(np);
   for (uint32_t p = 0; p < np; p++) {
     ProbRec* pr = X.probs[p];
-    double H, R2;
+    double H, R2, Xm;
     std::memcpy(&H, &mxb[8 * p], 8);
     std::memcpy(&R2, &mxb[8 * p + 1], 8);
-    pose_lattice(pr->S, H, R2, pr->epsk);
+    std::memcpy(&Xm, &mxb[8 * p + 7], 8);
+    const bool arc_ok = pose_lattice(pr->S, H, R2, pr->epsk, Xm, &pr->p);
     if (bad[p] & 1) {
       pr->st = GV_EINVAL;
       pr->err = "non-finite observation";
+    } else if (!arc_ok) {
+      pr->st = GV_EINVAL;
+      pr->err = "POSE5DOF: image coordinates times the f range too wide (2 atan(1 + 2 eps[3]) + atan(max|xi| hi[4]) "
+                "must stay below 3.1)";
     }
     tab[p] = pr->S.P;
   }
@@ -2019,8 +2064,8 @@ bool build_pose(Run& X) {
   for (uint32_t p = 0; p < np; p++) {
     ProbRec* pr = X.probs[p];
     if (pr->n > 0 && pr->st == GV_OK)
-      k_root_pose<<<gs_grid(X, pr->n), 256, 0, X.st>>>(X.dP + p, pr->cols, pr->n, X.ooff[p], X.Ntot, X.m64, e32, e64,
-                                                       dmx + 8 * p);
+      k_root_pose<<<gs_grid(X, pr->n), 256, 0, X.st>>>(X.dP + p, X.fam, pr->cols, pr->n, X.ooff[p], X.Ntot, X.m64,
+                                                       e32, e64, dmx + 8 * p);
   }
   HIPCHK(hipMemcpyAsync(mxb.data(), dmx, mxb.size() * 8, hipMemcpyDeviceToHost, X.st));
   host_wait(X);
@@ -2031,11 +2076,18 @@ bool build_pose(Run& X) {
     ProbRec* pr = X.probs[p];
     double mx[8];
     std::memcpy(mx, &mxb[8 * p], 64);
-    pr->filter_ok = pr->p.precision == GV_FP32_FILTER && pose_filter_exact(pr->S, mx);
+    // (POSE5DOF: binary64 in both modes)
+    pr->filter_ok = pr->p.precision == GV_FP32_FILTER && pr->S.fam == GV_POSE4DOF && pose_filter_exact(pr->S, mx);
     if (pr->st == GV_OK && !pr->filter_ok) all32 = false;
   }
   // (grouping below the root is off for this family unless forced)
   X.q24 = X.ctx->pack && X.group_mode <= 0;
+  if (X.fam == GV_POSE5DOF) {
+    dfree(X, e32);
+    X.root = e64;
+    if (!X.root_only) start_search<FAM_POSE5DOF, EntQ64, uint32_t>(X);
+    return false;
+  }
   if (all32) {
     dfree(X, e64);
     X.root = e32;
@@ -2087,7 +2139,7 @@ void epoch_finish(Run& X) {
     int* dbad = dalloc<int>(X, 1);
     HIPCHK(hipMemsetAsync(dbad, 0, sizeof(int), X.st));
     const unsigned gg = gs_grid(X, X.Ntot);
-    if (X.P0.exact && X.fam != GV_POSE4DOF) {
+    if (X.P0.exact && !fam_pose(X.fam)) {
       switch (X.fam) {
         case GV_LINE2D: k_replay_x<FAM_LINE2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
         case GV_PLANE3D: k_replay_x<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
@@ -2099,6 +2151,7 @@ void epoch_finish(Run& X) {
       case GV_PLANE3D: k_replay_lin<FAM_PLANE3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
       case GV_RAY3D: k_replay_lin<FAM_RAY3D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
       case GV_SIM2D: k_replay_lin<FAM_SIM2D><<<gg, 256, 0, X.st>>>(X.dP, dctab, X.dooff, np, X.Ntot, dpaths, flag, dbad); break;
+      case GV_POSE5DOF: k_replay_pose5<<<gg, 256, 0, X.st>>>(X.dP, X.m64, X.Ntot, X.dooff, np, dpaths, flag); break;
       default: k_replay_pose<<<gg, 256, 0, X.st>>>(X.dP, X.m64, X.Ntot, X.dooff, np, dpaths, flag); break;
     }
     HIPCHK(hipGetLastError());
@@ -2205,7 +2258,7 @@ void epoch_release(Run& X) {
 // build an epoch and return its step function
 std::function<bool(Run&)> epoch_build(Run& X) {
   epoch_begin(X);
-  if (X.P0.exact && X.fam != GV_POSE4DOF) {
+  if (X.P0.exact && !fam_pose(X.fam)) {
     switch (X.fam) {
       case GV_LINE2D: build_exact<FAM_LINE2D>(X); return epoch_step<FAM_XLINE2D, EntX, uint8_t>;
       case GV_PLANE3D: build_exact<FAM_PLANE3D>(X); return epoch_step<FAM_XPLANE3D, EntX, uint8_t>;
@@ -2218,6 +2271,7 @@ std::function<bool(Run&)> epoch_build(Run& X) {
     case GV_PLANE3D: build_linear<FAM_PLANE3D>(X); return epoch_step<FAM_PLANE3D, EntP3, uint8_t>;
     case GV_RAY3D: build_linear<FAM_RAY3D>(X); return epoch_step<FAM_RAY3D, EntR3, uint8_t>;
     case GV_SIM2D: build_linear<FAM_SIM2D>(X); return epoch_step<FAM_SIM2D, EntS2, uint8_t>;
+    case GV_POSE5DOF: build_pose(X); return step_pose5;
     default:
       if (build_pose(X)) return step_pose<EntQ32>;
       return step_pose<EntQ64>;
@@ -2229,13 +2283,13 @@ void fill_result(const ProbRec* pr, gv_result* r) {
   r->count = pr->count;
   r->leaf_index = pr->leaf;
   r->sector = pr->path.sector;
-  for (int a = 0; a < 4; a++) r->leaf_coords[a] = a < pr->S.d ? pr->coords[a] : 0;
-  for (int j = 0; j < 4; j++) r->point[j] = 0.0;
+  for (int a = 0; a < GV_MAXD; a++) r->leaf_coords[a] = a < pr->S.d ? pr->coords[a] : 0;
+  for (int j = 0; j < GV_MAXD; j++) r->point[j] = 0.0;
   for (int j = 0; j < pr->S.d; j++) {
     double u = (double)(2 * pr->coords[j] + 1) * std::ldexp(1.0, -(P.L[j] + 1));
     r->point[j] = P.lo[j] + P.E[j] * u;
   }
-  if (pr->S.fam == GV_POSE4DOF) {
+  if (fam_pose(pr->S.fam)) {
     double yaw = (double)pr->path.sector * (M_PI / 2.0) + std::atan(r->point[3]);
     if (yaw < 0.0) yaw += 2.0 * M_PI;
     if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
@@ -2249,9 +2303,9 @@ void fill_result(const ProbRec* pr, gv_result* r) {
   // parameter axis, half the leaf side (the distance from the returned point
   // to any point of the leaf).
   const double h37 = 0x1p-37;
-  for (int j = 0; j < 4; j++) r->bound[j] = 0.0;
+  for (int j = 0; j < GV_MAXD; j++) r->bound[j] = 0.0;
   for (int j = 0; j < pr->S.d; j++) r->bound[j] = 0.5 * std::ldexp(P.E[j], -P.L[j]);
-  if (pr->S.fam == GV_POSE4DOF) {
+  if (fam_pose(pr->S.fam)) {
     if (pr->S.exact) {
       // 2^-37 per parameter: z moves by at most (1 + R + 2 H) 2^-37, kappa
       // by (1 + k^2)(1 + 2/R_g) 2^-37 with |k| <= 1 + pad
@@ -2838,7 +2892,7 @@ gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t 
     set_err(ctx, "level or sector out of range");
     return GV_EINVAL;
   }
-  for (int j = 0; j < 4; j++) {
+  for (int j = 0; j < GV_MAXD; j++) {
     const int bits = j < P.d ? std::min(level, P.L[j]) : 0;
     if (coords[j] < 0 || (int64_t)coords[j] >= (1ll << bits)) {
       set_err(ctx, "cell coordinates out of range");
@@ -2855,7 +2909,7 @@ gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t 
     path.digit[k] = (uint8_t)dg;
   }
   Cell C{};
-  for (int j = 0; j < 4; j++) C.c[j] = coords[j];
+  for (int j = 0; j < GV_MAXD; j++) C.c[j] = coords[j];
   C.sector = (uint32_t)sector;
   const uint32_t nch = 1u << P.lev[level].abits;
   gv_stats stats{};
@@ -2870,7 +2924,7 @@ gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t 
     try {
       epoch_begin(X);
       bool f32 = false;
-      if (pr.S.fam == GV_POSE4DOF) {
+      if (fam_pose(pr.S.fam)) {
         f32 = build_pose(X);
       } else if (pr.S.exact) {
         switch (pr.S.fam) {
@@ -2890,7 +2944,9 @@ gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t 
       if (pr.st == GV_OK && pr.n > 0) {
         uint32_t* dm = dalloc<uint32_t>(X, (uint64_t)pr.n);
         const unsigned gg = gs_grid(X, (uint64_t)pr.n);
-        if (pr.S.fam == GV_POSE4DOF) {
+        if (pr.S.fam == GV_POSE5DOF) {
+          k_incidence_pose5<<<gg, 256, 0, X.st>>>(X.dP, (const EntQ64*)X.root, pr.n, C, level, dm);
+        } else if (pr.S.fam == GV_POSE4DOF) {
           if (f32)
             k_incidence_pose<EntQ32><<<gg, 256, 0, X.st>>>(X.dP, (const EntQ32*)X.root, pr.n, X.m64, X.Ntot, C, level,
                                                           dm, X.drecheck);

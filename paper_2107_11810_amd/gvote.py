@@ -15,9 +15,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgvote.so")
 
-LINE2D, PLANE3D, RAY3D, POSE4DOF, SIM2D = 1, 2, 3, 4, 5
-FAMILIES = {"line2d": LINE2D, "plane3d": PLANE3D, "ray3d": RAY3D, "pose4dof": POSE4DOF, "sim2d": SIM2D}
-NCOLS = {LINE2D: 2, PLANE3D: 3, RAY3D: 6, POSE4DOF: 5, SIM2D: 4}
+LINE2D, PLANE3D, RAY3D, POSE4DOF, SIM2D, POSE5DOF = 1, 2, 3, 4, 5, 6
+FAMILIES = {"line2d": LINE2D, "plane3d": PLANE3D, "ray3d": RAY3D, "pose4dof": POSE4DOF, "sim2d": SIM2D,
+            "pose5dof": POSE5DOF}
+NCOLS = {LINE2D: 2, PLANE3D: 3, RAY3D: 6, POSE4DOF: 5, SIM2D: 4, POSE5DOF: 5}
+AXES = 5  # GV_AXES: per-axis arrays of the ABI
 FP64_PLAIN, FP32_FILTER = 0, 1
 
 STATUS = {0: "GV_OK", -1: "GV_EINVAL", -2: "GV_ENOMEM", -3: "GV_ETOOBIG", -4: "GV_EBUFSZ",
@@ -37,8 +39,8 @@ class CtxConfig(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [("family", ctypes.c_int), ("n", ctypes.c_int64), ("col", ctypes.c_void_p * 6),
-                ("cols_on_device", ctypes.c_int), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
-                ("eps", ctypes.c_double * 4), ("canon_c", ctypes.c_double), ("precision", ctypes.c_int),
+                ("cols_on_device", ctypes.c_int), ("lo", ctypes.c_double * AXES), ("hi", ctypes.c_double * AXES),
+                ("eps", ctypes.c_double * AXES), ("canon_c", ctypes.c_double), ("precision", ctypes.c_int),
                 ("group", ctypes.c_int)]
 
 
@@ -54,10 +56,10 @@ class Stats(ctypes.Structure):
 
 
 class Result(ctypes.Structure):
-    _fields_ = [("point", ctypes.c_double * 4), ("count", ctypes.c_uint64), ("leaf_index", ctypes.c_uint64),
-                ("sector", ctypes.c_int32), ("leaf_coords", ctypes.c_int32 * 4),
+    _fields_ = [("point", ctypes.c_double * AXES), ("count", ctypes.c_uint64), ("leaf_index", ctypes.c_uint64),
+                ("sector", ctypes.c_int32), ("leaf_coords", ctypes.c_int32 * AXES),
                 ("inliers", ctypes.POINTER(ctypes.c_int64)), ("inliers_cap", ctypes.c_uint64),
-                ("n_inliers", ctypes.c_uint64), ("bound", ctypes.c_double * 4), ("stats", Stats)]
+                ("n_inliers", ctypes.c_uint64), ("bound", ctypes.c_double * AXES), ("stats", Stats)]
 
 
 class GvError(RuntimeError):
@@ -128,7 +130,7 @@ def make_problem(family, cols, lo, hi, eps, canon_c=0.0, precision=FP32_FILTER, 
         p.col[k] = _col_ptr(c, on_dev)
         keep.append(c)
     p.cols_on_device = 1 if on_dev else 0
-    for j in range(4):
+    for j in range(AXES):
         p.lo[j] = float(lo[j]) if j < len(lo) else 0.0
         p.hi[j] = float(hi[j]) if j < len(hi) else 0.0
         p.eps[j] = float(eps[j]) if j < len(eps) else 0.0
@@ -211,7 +213,7 @@ class Context:
         """Pass masks of every surface against the children of one cell
         (gv_incidence); returns (masks, tests, fp64 rechecks)."""
         p, keep = make_problem(family, cols, lo, hi, eps, canon_c, precision)
-        cc = (ctypes.c_int32 * 4)(*[int(c) for c in list(coords) + [0] * (4 - len(coords))])
+        cc = (ctypes.c_int32 * AXES)(*[int(c) for c in list(coords) + [0] * (AXES - len(coords))])
         masks = np.zeros(max(1, p.n), dtype=np.uint32)
         st_out = Stats()
         st = lib().gv_incidence(self._h, ctypes.byref(p), int(level), int(sector), cc,

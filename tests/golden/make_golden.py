@@ -10,6 +10,7 @@ that a change of the generator is detected.
     python tests/golden/make_golden.py plane3d_1m [--threads 8]
     python tests/golden/make_golden.py pose4dof_1m
     python tests/golden/make_golden.py pose4dof_serve256
+    python tests/golden/make_golden.py pose5dof_20k
 """
 import argparse
 import hashlib
@@ -47,12 +48,14 @@ def truth_leaf(g):
     starting bound that cannot change the result."""
     k = oracle.constants(oracle.Problem(g["family"], [np.zeros(0)] * len(g["cols"]), g["lo"], g["hi"], g["eps"]))
     tr = [float(x) for x in g["truth"]]
-    if g["family"] == "pose4dof":
+    if g["family"] in ("pose4dof", "pose5dof"):
         yaw = tr[3]
         s = int(math.floor((yaw + math.pi / 4) / (math.pi / 2))) % 4
         kap = math.tan(yaw - s * math.pi / 2)
         u = [(tr[j] - g["lo"][j]) / (g["hi"][j] - g["lo"][j]) for j in range(3)] + [(kap + 1) / 2]
-        d = 4
+        if g["family"] == "pose5dof":
+            u.append((tr[4] - g["lo"][4]) / (g["hi"][4] - g["lo"][4]))
+        d = len(u)
     else:
         s = None
         d = len(g["lo"])
@@ -80,7 +83,7 @@ def solve_one(g, threads):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workload", choices=["line2d_10k", "ray3d_100k", "plane3d_1m", "pose4dof_1m",
-                                         "pose4dof_serve256"])
+                                         "pose4dof_serve256", "pose5dof_20k"])
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     args = ap.parse_args()
     out = {"workload": args.workload, "threads": args.threads, "host_cpus": os.cpu_count(),
