@@ -101,6 +101,9 @@ def lib():
         L.or_canon_at.argtypes = [P(_Problem), P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int32,
                                   ctypes.c_int, P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double)]
         L.or_constants.argtypes = [P(_Problem), P(ctypes.c_double), ctypes.c_int]
+        L.or_refine.argtypes = [P(_Problem), ctypes.c_uint64, P(ctypes.c_int64), ctypes.c_int64, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_int, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_int64),
+                                P(ctypes.c_double), P(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -301,6 +304,26 @@ def constants(prob: Problem) -> dict:
          "steps": list(out[6:10]), "pad0": list(out[10:14]), "padlast": list(out[14:18]),
          "Rg": out[18], "epsn": list(out[19:23]) + [out[25]], "exact": bool(out[23]), "Fb": out[26]}
     return d
+
+
+def refine(prob: Problem, leaf_index: int, idx, tau0: float, tau: float, rounds: int = 2, iters: int = 10) -> dict:
+    """Angular verification of the vote's inliers idx (tau0 at the centre of
+    leaf_index, tau after each round) and Gauss-Newton refinement of the pose
+    (pose families)."""
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    pose = np.zeros(MAXD)
+    ver = np.zeros(max(1, idx.size), dtype=np.int64)
+    nv = ctypes.c_int64(0)
+    rms = ctypes.c_double(0.0)
+    rms0 = ctypes.c_double(0.0)
+    p = prob._c()
+    st = lib().or_refine(ctypes.byref(p), int(leaf_index), idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                         idx.size, float(tau0), float(tau), int(rounds), int(iters), _dptr(pose),
+                         ver.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(nv), ctypes.byref(rms),
+                         ctypes.byref(rms0))
+    if st != 0:
+        raise OracleError(st, "refine")
+    return {"pose": list(pose), "verified": ver[: nv.value].copy(), "rms": rms.value, "rms0": rms0.value}
 
 
 def leaf_index_of(levels, coords, sector=None) -> int:

@@ -1200,3 +1200,215 @@ int or_constants(const or_problem *p, double *out, int out_len) {
   out[26] = is_pose(&C) ? C.Fb : 0;
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* After the vote (pose families): verification of the angular error of */
+/* the inlier set and refinement of the pose by a more accurate method   */
+/* that works on that nearly outlier-free set (Sec. 4.2, opening remark; */
+/* Sec. 5, angular verification of the final inlier set).                */
+/*                                                                       */
+/* Pose q = (x, y, z, kappa[, f]) in user units, within the sector s of  */
+/* the vote's leaf: the camera forward direction, turned into the        */
+/* sector's frame, is (1, kappa)/sqrt(1 + kappa^2).  In camera axes      */
+/* (forward, lateral, up) match i is observed along                      */
+/*   o = (1, a, b sqrt(1 + a^2)),  a = xi f, b = eta f  (f = 1 for 4DoF) */
+/* and its point w is seen along                                         */
+/*   d = ((u1 + kappa u2)/n, (u2 - kappa u1)/n, w3 - z),                 */
+/* u = Rot_s(w1 - x, w2 - y), n = sqrt(1 + kappa^2).  Only +, -, *, /    */
+/* and sqrt are used, so the verification decision (angle(o, d) <= tau:  */
+/* o.d > 0 and |o x d|^2 <= tan^2(tau) (o.d)^2) is exact IEEE binary64.  */
+/* The first verification is at the centre of the vote's leaf (the      */
+/* minimal cuboid) with a threshold tau0 that covers the leaf.           */
+/* Refinement: Gauss-Newton steps with a small fixed damping on the sum  */
+/* of squared differences of the unit directions, |d/|d| - o/|o||^2      */
+/* (= (2 sin(angle/2))^2), over the verified matches; a fixed number of  */
+/* steps per round, then verification again at the new pose.             */
+/* ------------------------------------------------------------------ */
+#define RF_DAMP 1e-6
+
+static void rf_rot(int s, double a, double b, double *u1, double *u2) {
+  switch (s & 3) {
+    case 0: *u1 = a; *u2 = b; break;
+    case 1: *u1 = b; *u2 = -a; break;
+    case 2: *u1 = -a; *u2 = -b; break;
+    default: *u1 = -b; *u2 = a; break;
+  }
+}
+
+/* directions o (observed) and d (predicted) of match i at pose q */
+static void rf_dirs(const or_problem *p, int five, int s, const double *q, int64_t i, double o[3], double d[3]) {
+  double f = five ? q[4] : 1.0;
+  double a = p->col[3][i] * f, b = p->col[4][i] * f;
+  o[0] = 1.0;
+  o[1] = a;
+  o[2] = b * sqrt(1.0 + a * a);
+  double u1, u2;
+  rf_rot(s, p->col[0][i] - q[0], p->col[1][i] - q[1], &u1, &u2);
+  double n = sqrt(1.0 + q[3] * q[3]);
+  d[0] = (u1 + q[3] * u2) / n;
+  d[1] = (u2 - q[3] * u1) / n;
+  d[2] = p->col[2][i] - q[2];
+}
+
+static int rf_verified(const double o[3], const double d[3], double T2) {
+  double dot = (o[0] * d[0] + o[1] * d[1]) + o[2] * d[2];
+  double c0 = o[1] * d[2] - o[2] * d[1], c1 = o[2] * d[0] - o[0] * d[2], c2 = o[0] * d[1] - o[1] * d[0];
+  double cr = (c0 * c0 + c1 * c1) + c2 * c2;
+  return dot > 0.0 && cr <= T2 * (dot * dot);
+}
+
+/* residual r = d/|d| - o/|o| and its Jacobian J (3 x P) w.r.t. q */
+static void rf_resid(const or_problem *p, int five, int s, const double *q, int64_t i, double r[3], double J[3][5]) {
+  double o[3], d[3];
+  rf_dirs(p, five, s, q, i, o, d);
+  double nd = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+  double no = sqrt((o[0] * o[0] + o[1] * o[1]) + o[2] * o[2]);
+  double dh[3] = {d[0] / nd, d[1] / nd, d[2] / nd}, oh[3] = {o[0] / no, o[1] / no, o[2] / no};
+  for (int k = 0; k < 3; k++) r[k] = dh[k] - oh[k];
+  /* derivatives of d: u depends on x, y through Rot_s; F, L on kappa */
+  double n2 = 1.0 + q[3] * q[3], n = sqrt(n2);
+  double ux1, ux2, uy1, uy2;
+  rf_rot(s, -1.0, 0.0, &ux1, &ux2);
+  rf_rot(s, 0.0, -1.0, &uy1, &uy2);
+  double dd[5][3];
+  dd[0][0] = (ux1 + q[3] * ux2) / n; dd[0][1] = (ux2 - q[3] * ux1) / n; dd[0][2] = 0.0;
+  dd[1][0] = (uy1 + q[3] * uy2) / n; dd[1][1] = (uy2 - q[3] * uy1) / n; dd[1][2] = 0.0;
+  dd[2][0] = 0.0; dd[2][1] = 0.0; dd[2][2] = -1.0;
+  dd[3][0] = d[1] / n2; dd[3][1] = -d[0] / n2; dd[3][2] = 0.0;
+  int P = five ? 5 : 4;
+  for (int k = 0; k < 4; k++) {
+    /* (I - dh dh^T) dd / |d| */
+    double pr = (dh[0] * dd[k][0] + dh[1] * dd[k][1]) + dh[2] * dd[k][2];
+    for (int c = 0; c < 3; c++) J[c][k] = (dd[k][c] - dh[c] * pr) / nd;
+  }
+  if (five) {
+    /* o depends on f: do/df = (0, xi, eta s + b a xi / s) */
+    double xi = p->col[3][i], eta = p->col[4][i];
+    double a = xi * q[4], b = eta * q[4];
+    double sa = sqrt(1.0 + a * a);
+    double dof[3] = {0.0, xi, eta * sa + (b * a) * xi / sa};
+    double pr = (oh[0] * dof[0] + oh[1] * dof[1]) + oh[2] * dof[2];
+    for (int c = 0; c < 3; c++) J[c][4] = -((dof[c] - oh[c] * pr) / no);
+  }
+  (void)P;
+}
+
+/* Cholesky solve of (A + damping diag(A)) x = -g; x = 0 when not positive
+ * definite */
+static void rf_solve(int P, double A[5][5], const double *g, double *x) {
+  double M[5][5], L[5][5] = {{0}};
+  for (int r = 0; r < P; r++)
+    for (int c = 0; c < P; c++) M[r][c] = A[r][c] + (r == c ? RF_DAMP * A[r][c] : 0.0);
+  for (int j = 0; j < P; j++) {
+    double sdiag = M[j][j];
+    for (int k = 0; k < j; k++) sdiag -= L[j][k] * L[j][k];
+    if (!(sdiag > 0.0) || !isfinite(sdiag)) {
+      for (int k = 0; k < P; k++) x[k] = 0.0;
+      return;
+    }
+    L[j][j] = sqrt(sdiag);
+    for (int r = j + 1; r < P; r++) {
+      double v = M[r][j];
+      for (int k = 0; k < j; k++) v -= L[r][k] * L[j][k];
+      L[r][j] = v / L[j][j];
+    }
+  }
+  double y[5];
+  for (int r = 0; r < P; r++) {
+    double v = -g[r];
+    for (int k = 0; k < r; k++) v -= L[r][k] * y[k];
+    y[r] = v / L[r][r];
+  }
+  for (int r = P - 1; r >= 0; r--) {
+    double v = y[r];
+    for (int k = r + 1; k < P; k++) v -= L[k][r] * x[k];
+    x[r] = v / L[r][r];
+  }
+}
+
+int or_refine(const or_problem *p, uint64_t leaf_index, const int64_t *idx, int64_t n_idx, double tau0, double tau,
+              int rounds, int iters, double *pose_out, int64_t *verified, int64_t *n_verified, double *rms_out,
+              double *rms0_out) {
+  ctx C;
+  int st = ctx_init(&C, p);
+  if (st) return st;
+  if (!is_pose(&C)) return OR_EINVAL;
+  if (!(tau > 0.0 && tau < 1.5) || !(tau0 > 0.0 && tau0 < 1.5) || rounds < 0 || iters < 0 || n_idx < 0)
+    return OR_EINVAL;
+  for (int64_t k = 0; k < n_idx; k++)
+    if (idx[k] < 0 || idx[k] >= p->n) return OR_EINVAL;
+  int five = C.fam == OR_POSE5DOF, P = five ? 5 : 4;
+  /* start: the centre of the vote's leaf, kappa at the centre of its
+   * interval, in user units */
+  int sector;
+  int32_t path[MAXL + 1][MAXD];
+  st = leaf_path(&C, leaf_index, &sector, path);
+  if (st) return st;
+  double q[5] = {0};
+  for (int j = 0; j < C.d; j++) {
+    double u = (double)(2 * path[C.Lstar][j] + 1) * ldexp(1.0, -(C.L[j] + 1));
+    q[j] = C.lo[j] + C.E[j] * u;
+  }
+  /* the first verification, at the leaf centre, takes tau0 (wide enough for
+   * the whole leaf); the later ones, at refined poses, take tau */
+  double T20 = tan(tau0) * tan(tau0), T2 = tan(tau) * tan(tau);
+  uint8_t *ok = (uint8_t *)calloc((size_t)(n_idx > 0 ? n_idx : 1), 1);
+  if (!ok) return OR_ENOMEM;
+  for (int round = 0; round <= rounds; round++) {
+    /* verification at the current pose */
+    for (int64_t k = 0; k < n_idx; k++) {
+      double o[3], d[3];
+      rf_dirs(p, five, sector, q, idx[k], o, d);
+      ok[k] = (uint8_t)rf_verified(o, d, round == 0 ? T20 : T2);
+    }
+    if (round == 0 && rms0_out) {
+      double e = 0.0;
+      int64_t m = 0;
+      for (int64_t k = 0; k < n_idx; k++) {
+        if (!ok[k]) continue;
+        double r[3], J[3][5];
+        rf_resid(p, five, sector, q, idx[k], r, J);
+        e += (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+        m++;
+      }
+      *rms0_out = m ? sqrt(e / (double)m) : 0.0;
+    }
+    if (round == rounds) break;
+    for (int it = 0; it < iters; it++) {
+      double A[5][5] = {{0}}, g[5] = {0};
+      for (int64_t k = 0; k < n_idx; k++) {
+        if (!ok[k]) continue;
+        double r[3], J[3][5];
+        rf_resid(p, five, sector, q, idx[k], r, J);
+        for (int a = 0; a < P; a++) {
+          g[a] += (J[0][a] * r[0] + J[1][a] * r[1]) + J[2][a] * r[2];
+          for (int b = 0; b <= a; b++) A[a][b] += (J[0][a] * J[0][b] + J[1][a] * J[1][b]) + J[2][a] * J[2][b];
+        }
+      }
+      for (int a = 0; a < P; a++)
+        for (int b = a + 1; b < P; b++) A[a][b] = A[b][a];
+      double dq[5];
+      rf_solve(P, A, g, dq);
+      for (int a = 0; a < P; a++) q[a] += dq[a];
+    }
+  }
+  int64_t m = 0;
+  double e = 0.0;
+  for (int64_t k = 0; k < n_idx; k++) {
+    if (!ok[k]) continue;
+    if (verified) verified[m] = idx[k];
+    m++;
+    double r[3], J[3][5];
+    rf_resid(p, five, sector, q, idx[k], r, J);
+    e += (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+  }
+  free(ok);
+  *n_verified = m;
+  *rms_out = m ? sqrt(e / (double)m) : 0.0;
+  double yaw = (double)sector * (M_PI / 2.0) + atan(q[3]);
+  if (yaw < 0.0) yaw += 2.0 * M_PI;
+  if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
+  for (int j = 0; j < MAXD; j++) pose_out[j] = j < C.d ? q[j] : 0.0;
+  pose_out[3] = yaw;
+  return OR_OK;
+}

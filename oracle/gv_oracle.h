@@ -128,6 +128,19 @@ int or_canon_at(const or_problem *p, const double *t, const double *f,
  *  exact, L4, epsn4, Fb} (out_len >= 27) */
 int or_constants(const or_problem *p, double *out, int out_len);
 
+/* After the vote (pose families): verification of the angular error of the
+ * vote's inliers idx[0..n_idx) at the centre of leaf `leaf_index` (angle at
+ * most tau0), then `rounds` rounds of `iters` Gauss-Newton steps on the
+ * verified ones, each followed by verification again at the new pose (angle
+ * at most tau) (Sec. 4.2 opening remark, Sec. 5 angular verification).  pose_out (OR_MAXD values): x, y, z, yaw in
+ * [0, 2 pi) (, f); verified (cap n_idx, may be NULL): the matches whose
+ * angle at the final pose is at most tau, in idx order; rms_out: root mean
+ * square of |d/|d| - o/|o|| over them at the final pose; rms0_out (may be
+ * NULL): the same over the first verification at the leaf centre. */
+int or_refine(const or_problem *p, uint64_t leaf_index, const int64_t *idx, int64_t n_idx, double tau0, double tau,
+              int rounds, int iters, double *pose_out, int64_t *verified, int64_t *n_verified, double *rms_out,
+              double *rms0_out);
+
 const char *or_status_str(int st);
 
 #ifdef __cplusplus

@@ -14,7 +14,8 @@ import sys
 import tempfile
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_bounds.py", "tests/test_oracle_pose5.py"]
+PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_bounds.py", "tests/test_oracle_pose5.py",
+        "tests/test_oracle_refine.py"]
 
 # (name, text in gv_oracle.c, replacement)
 MUTANTS = [
@@ -69,6 +70,14 @@ MUTANTS = [
     ("f5_sEta_noF", "C->sEta = p2floor(ez / (l1 * Rb * C->Fb));", "C->sEta = p2floor(ez / (l1 * Rb));"),
     ("f5_sXi_noF", "C->sXi = p2floor(ek / (l1 * Bk * C->Fb));", "C->sXi = p2floor(ek / (l1 * Bk));"),
     ("f5_wz_noF", "double wz = ez / (l1 * Hb * C->Fb)", "double wz = ez / (l1 * Hb)"),
+    # verification and refinement after the vote
+    ("rf_kappa_sign", "dd[3][0] = d[1] / n2; dd[3][1] = -d[0] / n2;", "dd[3][0] = -d[1] / n2; dd[3][1] = d[0] / n2;"),
+    ("rf_no_fder", "for (int c = 0; c < 3; c++) J[c][4] = -((dof[c] - oh[c] * pr) / no);",
+     "for (int c = 0; c < 3; c++) J[c][4] = 0.0 * pr;"),
+    ("rf_tau0", "round == 0 ? T20 : T2", "T2"),
+    ("rf_rot1", "case 1: *u1 = b; *u2 = -a; break;\n    case 2: *u1 = -a", "case 1: *u1 = -b; *u2 = a; break;\n    case 2: *u1 = -a"),
+    ("rf_obs_s", "o[2] = b * sqrt(1.0 + a * a);", "o[2] = b;"),
+    ("rf_dx_sign", "rf_rot(s, -1.0, 0.0, &ux1, &ux2);", "rf_rot(s, 1.0, 0.0, &ux1, &ux2);"),
     ("sim_axes", "*nP = 2; P[0] = 0; P[1] = 1; *nQ = 2; Q[0] = 2; Q[1] = 3;",
      "*nP = 2; P[0] = 0; P[1] = 1; *nQ = 2; Q[0] = 3; Q[1] = 2;"),
 ]
