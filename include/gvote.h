@@ -272,6 +272,38 @@ gv_status gv_cancel(gv_ctx *ctx, uint64_t ticket);
 gv_status gv_incidence(gv_ctx *ctx, const gv_problem *p, int32_t level, int32_t sector, const int32_t coords[GV_AXES],
                        uint32_t *masks_out, gv_stats *stats_out);
 
+/* Verification and refinement after the vote (pose families).  The vote's
+ * pose is handed to a more accurate method that works on its nearly
+ * outlier-free inlier set (Sec. 4.2, opening remark), and the angular error
+ * of the final inlier set is verified (Sec. 5).  Start: the centre of leaf
+ * `leaf_index` (as gv_solve returns it) with the kappa of its interval's
+ * centre.  Verification keeps the matches of idx[0..n_idx) (host buffer,
+ * indices into p's observations, e.g. the vote's inliers) whose angle
+ * between the observed bearing and the direction from the camera to their
+ * point is at most tau0 at the leaf centre (a tau0 that covers the leaf) and
+ * at most tau at later poses; the decision uses only +, -, *, / and sqrt
+ * in binary64, so it is exact IEEE arithmetic.  Then `rounds` times: `iters`
+ * damped Gauss-Newton steps on the kept matches minimizing the sum of
+ * |d/|d| - o/|o||^2 (the unit bearing differences; (2 sin(angle/2))^2 each)
+ * over (x, y, z, kappa[, f]) inside the leaf's yaw sector, then
+ * verification again.  Every step runs on the device without a host wait.
+ * Results: out->pose (x, y, z, yaw in [0, 2 pi)[, f]); out->verified (caller
+ * buffer of verified_cap entries) the kept matches in idx order, n_verified
+ * their number (GV_EBUFSZ when it exceeds the cap); out->rms the root mean
+ * square of |d/|d| - o/|o|| over them at the final pose, out->rms0 over the
+ * first verification's matches at the leaf centre.  GV_EINVAL for a family
+ * other than the pose ones, tau or tau0 outside (0, 1.5), rounds outside
+ * [0, 64], iters outside [0, 256], a leaf index or match index out of range. */
+typedef struct {
+  double pose[GV_AXES];
+  double rms0, rms;
+  int64_t *verified;
+  uint64_t verified_cap;
+  uint64_t n_verified;
+} gv_refined;
+gv_status gv_refine(gv_ctx *ctx, const gv_problem *p, uint64_t leaf_index, const int64_t *idx, uint64_t n_idx,
+                    double tau0, double tau, int32_t rounds, int32_t iters, gv_refined *out);
+
 /* Static text for a status code. */
 const char *gv_status_str(gv_status s);
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "gvote.hip")
 LIB = os.path.join(HERE, "libgvote.so")
 DEPS = [os.path.join(HERE, "csrc", f) for f in ("gvote.hip", "gv_device.h", "gv_kernels.h", "gv_root.h", "gv_exact.h",
-                                                          "gv_subtree.h", "gv_pose5.h")] + [
+                                                          "gv_subtree.h", "gv_pose5.h", "gv_refine.h")] + [
     os.path.join(ROOT, "include", "gvote.h")]
 
 HIPCC_FLAGS = [

@@ -35,6 +35,7 @@
 #include "gv_exact.h"
 #include "gv_subtree.h"
 #include "gv_pose5.h"
+#include "gv_refine.h"
 
 // Caching device allocator owned by a context.  All library work on a
 // context is ordered on its stream, so a block released after its last use
@@ -3063,6 +3064,139 @@ gv_status gv_parametrize(gv_ctx* ctx, const gv_problem* p, double* t_out, double
   dfree(X, X.dP);
   (void)hipStreamSynchronize(X.st);
   return st;
+}
+
+gv_status gv_refine(gv_ctx* ctx, const gv_problem* p, uint64_t leaf_index, const int64_t* idx, uint64_t n_idx,
+                    double tau0, double tau, int32_t rounds, int32_t iters, gv_refined* out) {
+  if (!ctx || !p || !out || (!idx && n_idx > 0)) return GV_EINVAL;
+  ProbRec pr;
+  pr.p = *p;
+  gv_status st = prepare_problem(&pr);
+  if (st != GV_OK) {
+    set_err(ctx, pr.err);
+    return st;
+  }
+  const ProbC& P = pr.S.P;
+  if (!fam_pose(pr.S.fam)) {
+    set_err(ctx, "gv_refine: pose families only");
+    return GV_EINVAL;
+  }
+  if (!(tau > 0.0 && tau < 1.5) || !(tau0 > 0.0 && tau0 < 1.5) || rounds < 0 || iters < 0 || rounds > 64 ||
+      iters > 256) {
+    set_err(ctx, "gv_refine: tau, tau0 in (0, 1.5), 0 <= rounds <= 64, 0 <= iters <= 256");
+    return GV_EINVAL;
+  }
+  if (leaf_index > P.idxmask) {
+    set_err(ctx, "gv_refine: leaf index out of range");
+    return GV_EINVAL;
+  }
+  for (uint64_t k = 0; k < n_idx; k++)
+    if (idx[k] < 0 || idx[k] >= pr.n) {
+      set_err(ctx, "gv_refine: match index out of range");
+      return GV_EINVAL;
+    }
+  // start: the centre of the vote's leaf, kappa at its interval's centre
+  RefState S0{};
+  PathC path{};
+  int32_t coords[GV_MAXD] = {0, 0, 0, 0, 0};
+  decode_leaf(P, leaf_index, path, coords);
+  for (int j = 0; j < pr.S.d; j++) {
+    const double u = (double)(2 * coords[j] + 1) * std::ldexp(1.0, -(P.L[j] + 1));
+    S0.q[j] = P.lo[j] + P.E[j] * u;
+  }
+  if (pr.S.fam != GV_POSE5DOF) S0.q[4] = 1.0;
+  S0.sector = path.sector;
+  S0.five = pr.S.fam == GV_POSE5DOF ? 1 : 0;
+  const double T20 = std::tan(tau0) * std::tan(tau0), T2 = std::tan(tau) * std::tan(tau);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->err.clear();
+  Run X;
+  bind_ctx(X, ctx);
+  std::vector<void*> owned;
+  std::vector<int64_t> ver;
+  RefState S{}, S0out{};
+  st = GV_OK;
+  try {
+    HIPCHK(hipSetDevice(ctx->device));
+    const int ncol = ncols_of(pr.S.fam, pr.S.d);
+    Cols cols{};
+    for (int k = 0; k < ncol; k++) {
+      if (p->cols_on_device || p->n == 0) {
+        cols.c[k] = p->col[k];
+      } else {
+        double* d = dalloc<double>(X, p->n);
+        HIPCHK(hipMemcpyAsync(d, p->col[k], p->n * sizeof(double), hipMemcpyHostToDevice, X.st));
+        owned.push_back(d);
+        cols.c[k] = d;
+      }
+    }
+    const uint64_t n = n_idx;
+    int64_t* didx = dalloc<int64_t>(X, std::max<uint64_t>(1, n));
+    uint32_t* ok = dalloc<uint32_t>(X, std::max<uint64_t>(1, n));
+    uint32_t* pos = dalloc<uint32_t>(X, std::max<uint64_t>(1, n));
+    RefState* dS = dalloc<RefState>(X, 2);  // [0]: the pose; [1]: the first sums, at the leaf centre
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(nblk(std::max<uint64_t>(1, n), GV_RF_WG), 1024);
+    double* part = dalloc<double>(X, (uint64_t)nb * GV_RF_NV);
+    owned.insert(owned.end(), {didx, ok, pos, dS, part});
+    if (n) HIPCHK(hipMemcpyAsync(didx, idx, n * sizeof(int64_t), hipMemcpyHostToDevice, X.st));
+    HIPCHK(hipMemcpyAsync(dS, &S0, sizeof(RefState), hipMemcpyHostToDevice, X.st));
+    const unsigned gv = gs_grid(X, std::max<uint64_t>(1, n));
+    // one round: verification at the current pose, then Gauss-Newton steps
+    // on the verified matches; after the last round, verification and sums
+    for (int round = 0; round <= rounds; round++) {
+      k_rf_verify<<<gv, 256, 0, X.st>>>(dS, cols, didx, n, round == 0 ? T20 : T2, ok);
+      if (round == 0) {
+        k_rf_accum<<<nb, GV_RF_WG, 0, X.st>>>(dS, cols, didx, n, ok, part);
+        k_rf_solve<<<1, 64, 0, X.st>>>(dS, part, nb, 0);
+        HIPCHK(hipMemcpyAsync(dS + 1, dS, sizeof(RefState), hipMemcpyDeviceToDevice, X.st));
+      }
+      if (round == rounds) break;
+      for (int it = 0; it < iters; it++) {
+        k_rf_accum<<<nb, GV_RF_WG, 0, X.st>>>(dS, cols, didx, n, ok, part);
+        k_rf_solve<<<1, 64, 0, X.st>>>(dS, part, nb, 1);
+      }
+    }
+    k_rf_accum<<<nb, GV_RF_WG, 0, X.st>>>(dS, cols, didx, n, ok, part);
+    k_rf_solve<<<1, 64, 0, X.st>>>(dS, part, nb, 0);
+    HIPCHK(hipGetLastError());
+    uint64_t nv = 0;
+    if (n) {
+      excl_scan(X, ok, pos, n);
+      uint32_t last[2] = {0, 0};
+      HIPCHK(hipMemcpyAsync(&last[0], pos + n - 1, 4, hipMemcpyDeviceToHost, X.st));
+      HIPCHK(hipMemcpyAsync(&last[1], ok + n - 1, 4, hipMemcpyDeviceToHost, X.st));
+      host_wait(X);
+      nv = (uint64_t)last[0] + last[1];
+      if (nv) {
+        int64_t* dv = dalloc<int64_t>(X, nv);
+        owned.push_back(dv);
+        k_rf_scatter<<<gv, 256, 0, X.st>>>(didx, n, ok, pos, dv);
+        ver.resize(nv);
+        HIPCHK(hipMemcpyAsync(ver.data(), dv, nv * sizeof(int64_t), hipMemcpyDeviceToHost, X.st));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(&S, dS, sizeof(RefState), hipMemcpyDeviceToHost, X.st));
+    HIPCHK(hipMemcpyAsync(&S0out, dS + 1, sizeof(RefState), hipMemcpyDeviceToHost, X.st));
+    host_wait(X);
+  } catch (DevErr& e) {
+    st = e.st;
+  }
+  for (void* q : owned) dfree(X, q);
+  (void)hipStreamSynchronize(X.st);
+  if (st != GV_OK) return st;
+  // pose in user units; yaw from kappa and the sector, in [0, 2 pi)
+  for (int j = 0; j < GV_MAXD; j++) out->pose[j] = j < pr.S.d ? S.q[j] : 0.0;
+  double yaw = (double)S.sector * (M_PI / 2.0) + std::atan(S.q[3]);
+  if (yaw < 0.0) yaw += 2.0 * M_PI;
+  if (yaw >= 2.0 * M_PI) yaw -= 2.0 * M_PI;
+  out->pose[3] = yaw;
+  out->rms = S.cnt > 0.0 ? std::sqrt(S.cost / S.cnt) : 0.0;
+  out->rms0 = S0out.cnt > 0.0 ? std::sqrt(S0out.cost / S0out.cnt) : 0.0;
+  out->n_verified = ver.size();
+  if (ver.size() > out->verified_cap || (!out->verified && !ver.empty())) return GV_EBUFSZ;
+  if (!ver.empty()) std::memcpy(out->verified, ver.data(), ver.size() * sizeof(int64_t));
+  set_err(ctx, "");
+  return GV_OK;
 }
 
 }  // extern "C"

@@ -26,7 +26,7 @@ STATUS = {0: "GV_OK", -1: "GV_EINVAL", -2: "GV_ENOMEM", -3: "GV_ETOOBIG", -4: "G
           -5: "GV_EAGAIN", -6: "GV_ETIMEDOUT", -7: "GV_ECANCELED", -8: "GV_EDEVICE", -9: "GV_ERANGE"}
 
 EXPORTS = ["gv_create", "gv_destroy", "gv_solve", "gv_solve_noalloc", "gv_report", "gv_parametrize", "gv_incidence",
-           "gv_submit",
+           "gv_refine", "gv_submit",
            "gv_poll", "gv_cancel",
            "gv_status_str", "gv_last_error"]
 
@@ -62,6 +62,12 @@ class Result(ctypes.Structure):
                 ("n_inliers", ctypes.c_uint64), ("bound", ctypes.c_double * AXES), ("stats", Stats)]
 
 
+class Refined(ctypes.Structure):
+    _fields_ = [("pose", ctypes.c_double * AXES), ("rms0", ctypes.c_double), ("rms", ctypes.c_double),
+                ("verified", ctypes.POINTER(ctypes.c_int64)), ("verified_cap", ctypes.c_uint64),
+                ("n_verified", ctypes.c_uint64)]
+
+
 class GvError(RuntimeError):
     def __init__(self, status, msg=""):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -89,6 +95,8 @@ def lib():
                                      P(ctypes.c_int32)]
         L.gv_incidence.argtypes = [ctypes.c_void_p, P(Problem), ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32),
                                    P(ctypes.c_uint32), P(Stats)]
+        L.gv_refine.argtypes = [ctypes.c_void_p, P(Problem), ctypes.c_uint64, P(ctypes.c_int64), ctypes.c_uint64,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P(Refined)]
         L.gv_submit.argtypes = [ctypes.c_void_p, P(Problem), P(ctypes.c_uint64)]
         L.gv_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(Result), ctypes.c_int]
         L.gv_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
@@ -97,7 +105,7 @@ def lib():
         L.gv_last_error.argtypes = [ctypes.c_void_p]
         L.gv_last_error.restype = ctypes.c_char_p
         for name in ("gv_create", "gv_destroy", "gv_solve", "gv_solve_noalloc", "gv_report", "gv_parametrize",
-                     "gv_incidence",
+                     "gv_incidence", "gv_refine",
                      "gv_submit", "gv_poll", "gv_cancel"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -221,6 +229,23 @@ class Context:
         if st != 0:
             raise GvError(st, self.last_error())
         return masks[: p.n], int(st_out.tests), int(st_out.fp64_rechecks)
+
+    def refine(self, family, cols, lo, hi, eps, leaf_index, idx, tau0, tau, rounds=2, iters=10):
+        """Angular verification and Gauss-Newton refinement after the vote
+        (gv_refine): returns {pose, verified, rms, rms0}."""
+        p, keep = make_problem(family, cols, lo, hi, eps)
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+        buf = np.zeros(max(1, idx.size), dtype=np.int64)
+        out = Refined()
+        out.verified = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        out.verified_cap = idx.size
+        st = lib().gv_refine(self._h, ctypes.byref(p), int(leaf_index),
+                             idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.size, float(tau0), float(tau),
+                             int(rounds), int(iters), ctypes.byref(out))
+        if st != 0:
+            raise GvError(st, self.last_error())
+        return {"pose": list(out.pose), "verified": buf[: out.n_verified].copy(), "rms": out.rms,
+                "rms0": out.rms0}
 
     def parametrize(self, family, cols, lo, hi, eps):
         p, keep = make_problem(family, cols, lo, hi, eps)

@@ -175,7 +175,7 @@ def check_golden(r, gold):
     assert [float(x) for x in _axes(r["point"], len(gold["point"]))] == gold["point"]
 
 
-@pytest.mark.parametrize("name", ["plane3d_1m", "pose4dof_1m"])
+@pytest.mark.parametrize("name", ["plane3d_1m", "pose4dof_1m", "pose5dof_20k"])
 def test_fullsize_golden_parity(ctx, name):
     gold = _golden(name)["problems"][0]
     g = synth.config(name)
