@@ -10,9 +10,11 @@ every dual axis, inputs resident in HBM before the timed region.
 Prints one JSON line: the incidence-test throughput of the whole job, the
 roofline figure of the dominant kernel (HIP events on the solve stream,
 inside the library), the CPU oracle timed on a bounded sample (one thread
-and all cores), and, as extra keys, the 4-DoF pose workload (1e6 matches)
-and the 256-problem serving workload (solves/s batched against plain,
-p50/p99 latency).  Every result is compared with the oracle's golden file
+and all cores), and, as extra keys, the 4-DoF pose workload (1e6 matches),
+the 5-DoF pose workload with unknown focal length (2e4 matches), the
+verification and refinement after the vote on both pose workloads, and the
+256-problem serving workload (solves/s batched against plain, p50/p99
+latency).  Every result is compared with the oracle's golden file
 for its workload (tests/golden/); a mismatch exits non-zero.
 """
 import argparse
@@ -37,6 +39,10 @@ WORKLOADS = {
     "pose4dof_1m": dict(desc="gravity-aligned 4-DoF pose: 1e6 matches in a 200 m box, 0.5% inliers with 0.5 deg "
                              "bearing noise, eps 0.5 m / 0.5 deg", kernel="k_count_pose<POSE4DOF>",
                         compact="k_compact<POSE4DOF>", bound="alu"),
+    "pose5dof_20k": dict(desc="gravity-aligned pose with unknown focal length (x, y, z, yaw, f): 2e4 matches, 1.5% "
+                              "inliers with 0.5 deg bearing noise, camera within 50 m / 5 m of the truth, f within "
+                              "[0.6, 1.3] of it, eps 0.5 m / 0.5 deg / 1% of f", kernel="k_count_pose5<POSE5DOF>",
+                         compact="k_compact<POSE5DOF>", bound="alu"),
     "ray3d_100k": dict(desc="ray intersection: 1e5 rays, 1% through a common centre", kernel="k_count_lin<RAY3D>",
                        compact="k_compact_lin<RAY3D>", bound="hbm"),
     "line2d_10k": dict(desc="2D line fitting by duality: 1e4 points, 5% inliers", kernel="k_count_lin<LINE2D>",
@@ -283,6 +289,14 @@ def valu_frac(opt, tests, ms):
 # = 497 operations for 16 tests.  The binary32 filter's error bounds are not
 # counted: they are the implementation's cost, not the method's.
 POSE_DAG_OPS_PER_TEST = 497.0 / 16.0
+# The same count for the 5-DoF predicate (32 children: the 4-DoF ones for
+# each half of the cell's f interval): z bits 21; per f bit the slopes
+# |eta| f_lo, |eta| f_hi and their squares (4, x2 = 8); kappa: padded ends
+# (2) and per (kappa bit, f bit) the tangents' ends (1 product, 1 select of
+# two shared per f bit) and edges (6): 34; (x, y) parts (4), 183 each: 39 as
+# above plus 9 per (z bit, f bit) and 27 per (kappa bit, f bit); child
+# masks 32.  827 operations for 32 tests.
+POSE5_DAG_OPS_PER_TEST = 827.0 / 32.0
 
 
 def cpu_model():
@@ -374,10 +388,11 @@ def single_leg(name, args, ctx, warmup, steps):
         # operations per test of the predicate's definition, times the tests,
         # over its event time; beside it the measured issue rate (VALU
         # instructions x 64 lanes per test, from the counter record)
-        ach = POSE_DAG_OPS_PER_TEST * tests / (kms * 1e-3) / 1e12
+        opt = POSE5_DAG_OPS_PER_TEST if g["family"] == "pose5dof" else POSE_DAG_OPS_PER_TEST
+        ach = opt * tests / (kms * 1e-3) / 1e12
         roof.update({"bound": "alu", "achieved": round(ach, 2), "peak": VALU_LANE_OPS / 1e12,
                      "unit": "T ops/s", "frac": round(ach / (VALU_LANE_OPS / 1e12), 4),
-                     "ops_per_test": round(POSE_DAG_OPS_PER_TEST, 2), "traffic": None})
+                     "ops_per_test": round(opt, 2), "traffic": None})
         issued = measured_valu(name, kname)
         if issued is not None:
             roof["issued_lane_ops_per_test"] = round(issued, 2)
@@ -389,15 +404,43 @@ def single_leg(name, args, ctx, warmup, steps):
         golden = {"matches": all(golden_match(r, gg) for r in results), "oracle_tests_per_solve": gg["oracle_tests"],
                   "oracle_wall_s": round(gg["oracle_wall_s"], 1), "oracle_threads": gold.get("threads"),
                   "oracle_solves_per_s": round(1.0 / gg["oracle_wall_s"], 6)}
+    refine = None
+    if g["family"] in ("pose4dof", "pose5dof"):
+        refine = refine_leg(ctx, g, cols, results[0])
     for c in cols:
         c.free()
     return {
+        "refine": refine,
         "g": g, "sec": sec, "steps": steps, "tests": tests, "results": results, "roofline": roof,
         "tests_per_s": tests / sec, "solves_per_s": steps / sec, "ms_per_solve": 1e3 * sec / steps,
         "tests_per_solve": tests / steps, "count": results[0]["count"],
         "deterministic": len({(r["count"], r["leaf_index"]) for r in results}) == 1, "golden": golden,
         "rechecks_per_solve": sum(r["stats"]["fp64_rechecks"] for r in results) / steps,
     }
+
+
+def refine_leg(ctx, g, cols, vote, reps=5):
+    """Verification and refinement after the vote (gv_refine) of a pose
+    workload: time per call, matches kept, pose error before and after."""
+    tau0, tau = math.radians(1.5), math.radians(0.75)
+    args = (g["family"], cols, g["lo"], g["hi"], g["eps"], vote["leaf_index"], vote["inliers"], tau0, tau)
+    r = ctx.refine(*args, rounds=3, iters=10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ctx.refine(*args, rounds=3, iters=10)
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    tr = list(map(float, g["truth"]))
+
+    def err(q):
+        dyaw = abs(q[3] - tr[3])
+        e = {"position_m": math.dist(q[:3], tr[:3]), "yaw_deg": math.degrees(min(dyaw, 2 * math.pi - dyaw))}
+        if g["family"] == "pose5dof":
+            e["f_rel"] = abs(q[4] - tr[4]) / tr[4]
+        return {k: round(v, 6) for k, v in e.items()}
+
+    return {"ms_per_refine": round(ms, 3), "rounds": 3, "iters": 10, "tau0_deg": 1.5, "tau_deg": 0.75,
+            "vote_inliers": int(vote["n_inliers"]), "kept": int(len(r["verified"])), "rms0": r["rms0"],
+            "rms": r["rms"], "error_leaf_centre": err(vote["point"]), "error_refined": err(r["pose"])}
 
 
 def main():
@@ -452,7 +495,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32" if g["family"] != "pose4dof" else ("f32+f64" if args.precision else "f64"),
+        "dtype": ("int32" if g["family"] not in ("pose4dof", "pose5dof")
+                  else ("f32+f64" if args.precision and g["family"] == "pose4dof" else "f64")),
         "data": "synthetic",
         "config": {"workload": args.workload, "description": W["desc"], "n": n, "eps": g["eps"],
                    "canon_c": 1.0, "precision": "fp32_filter" if args.precision else "fp64_plain"},
@@ -473,8 +517,18 @@ def main():
             "ms_per_solve": pl["ms_per_solve"], "solves_per_s": pl["solves_per_s"],
             "tests_per_solve": pl["tests_per_solve"], "count": pl["count"], "roofline": pl["roofline"],
             "rechecks_per_solve": pl["rechecks_per_solve"], "golden": pl["golden"]}
+        out["pose4dof_1m"]["refine"] = pl["refine"]
         if pl["golden"] is not None:
             ok = ok and pl["golden"]["matches"]
+        # the 5-DoF pose workload (unknown focal length)
+        p5 = single_leg("pose5dof_20k", args, ctx, 3, 10)
+        out["pose5dof_20k"] = {
+            "description": WORKLOADS["pose5dof_20k"]["desc"], "tests_per_s": p5["tests_per_s"],
+            "ms_per_solve": p5["ms_per_solve"], "solves_per_s": p5["solves_per_s"],
+            "tests_per_solve": p5["tests_per_solve"], "count": p5["count"], "roofline": p5["roofline"],
+            "golden": p5["golden"], "refine": p5["refine"]}
+        if p5["golden"] is not None:
+            ok = ok and p5["golden"]["matches"]
         # the serving workload: batched binary32 filter against plain binary64
         sv = serve_bench(args)
         out["pose4dof_serve256"] = dict({"description": WORKLOADS["pose4dof_serve256"]["desc"]}, **sv)
