@@ -529,11 +529,15 @@ def main():
             "golden": p5["golden"], "refine": p5["refine"]}
         if p5["golden"] is not None:
             ok = ok and p5["golden"]["matches"]
+    # (the serving leg gets a context of its own, after this one has released
+    # the device memory its caching allocator holds: a budget taken from the
+    # free memory left beside the 1e6-point solves' cache made it 15% slower)
+    ctx.close()
+    if args.workload == "plane3d_1m" and not args.no_extras:
         # the serving workload: batched binary32 filter against plain binary64
         sv = serve_bench(args)
         out["pose4dof_serve256"] = dict({"description": WORKLOADS["pose4dof_serve256"]["desc"]}, **sv)
         ok = ok and sv["identical_to_plain"] and (sv["golden"] is None or sv["golden"]["matches"])
-    ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_tests, max(1, min(os.cpu_count() or 1, 16)))
     out["matches_oracle"] = ok
