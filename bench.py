@@ -231,18 +231,27 @@ def per_kernel(name, ms, nbytes, launches, steps):
             "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def kernel_sources_sha256():
+    """SHA-256 of every HIP source of the library (sorted by name): a counter
+    record taken on other sources no longer describes the kernels."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2107_11810_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of the kernel from the committed memory-counter
     record (profiles/traffic.json), or None when there is none or the kernel
     sources changed since it was taken."""
-    import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[workload]
     except (OSError, KeyError, ValueError):
         return None
-    src = b"".join(open(os.path.join(ROOT, "paper_2107_11810_amd", "csrc", f), "rb").read()
-                   for f in ("gv_device.h", "gv_kernels.h"))
-    if rec.get("kernel") != kernel or rec.get("sources_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != kernel_sources_sha256():
         return None
     return int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
 
@@ -251,14 +260,11 @@ def measured_valu(workload, kernel):
     """VALU lane-operations per incidence test of the kernel from the
     committed counter record (profiles/valu.json), or None when there is
     none or the kernel sources changed since it was taken."""
-    import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "valu.json")))[workload]
     except (OSError, KeyError, ValueError):
         return None
-    src = b"".join(open(os.path.join(ROOT, "paper_2107_11810_amd", "csrc", f), "rb").read()
-                   for f in ("gv_device.h", "gv_kernels.h"))
-    if rec.get("sources_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("sources_sha256") != kernel_sources_sha256():
         return None
     per_kernel_ops = rec.get("kernels", {rec.get("kernel"): rec.get("lane_ops_per_test")})
     v = per_kernel_ops.get(kernel)

@@ -126,7 +126,12 @@ __device__ inline uint32_t pose5_mask64(const ProbC& P, const LevelC& lv, const 
 
 // Incidence test and per-child counts of a batch (one wave per item), with
 // a 32-bit pass mask stored per entry for the compaction.  UNIT: every
-// multiplicity is 1, so a child's count is the popcount of its ballot.
+// multiplicity is 1: each lane counts its own passes, four children to a
+// word (one byte each: a lane tests at most GV_ITEM/64 = 16 entries of an
+// item), the wave sums them once per item in 16-bit halves (at most 1024
+// per child).  Thirty-two scalar ballot accumulators, beside the cell's
+// binary64 child boxes, overflowed the scalar registers.
+static_assert(GV_ITEM / 64 <= 255 && 64 * (GV_ITEM / 64) <= 65535, "per-lane byte counters, 16-bit wave sums");
 template <bool UNIT, bool ALL>
 __global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ Ptab, int m, LevelC lv,
                                                      const Cell* __restrict__ cells, const Item* __restrict__ items,
@@ -146,39 +151,68 @@ __global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ P
     const uint32_t cnt = I.cnt;
     Pose5Level B;
     pose5_level_boxes(P, lv, C, m, B);
-    uint32_t aw[32], an[32];
+    if constexpr (UNIT) {
+      uint32_t pk[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // byte b of pk[g]: passes of child 4g + b
+      for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        const uint64_t ei = I.off + k;
+        uint32_t mask = 0;
+        if (k < cnt) {
+          const EntQ64 e = ents[ei];
+          mask = pose5_mask64<ALL>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+          masks[ei] = mask;
+        }
+        // spread each nibble of the mask to the low bits of four bytes
 #pragma unroll
-    for (int ch = 0; ch < 32; ch++) { aw[ch] = 0; an[ch] = 0; }
-    for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
-      const uint32_t k = k0 + lane;
-      const uint64_t ei = I.off + k;
-      uint32_t mask = 0, w = 0;
-      if (k < cnt) {
-        const EntQ64 e = ents[ei];
-        w = e.w;
-        mask = pose5_mask64<ALL>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
-        masks[ei] = mask;
+        for (int g = 0; g < 8; g++) pk[g] += (((mask >> (4 * g)) & 0xFu) * 0x204081u) & 0x01010101u;
       }
 #pragma unroll
-      for (int ch = 0; ch < 32; ch++) {
-        const bool p = (mask >> ch) & 1u;
-        if constexpr (UNIT) {
-          an[ch] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
-        } else {
+      for (int g = 0; g < 8; g++) {
+        if ((uint32_t)(4 * g) >= nch) break;
+        const uint32_t ev = wave_sum_u32(pk[g] & 0x00FF00FFu);         // children 4g, 4g + 2
+        const uint32_t od = wave_sum_u32((pk[g] >> 8) & 0x00FF00FFu);  // children 4g + 1, 4g + 3
+        const uint32_t n4[4] = {ev & 0xFFFFu, od & 0xFFFFu, ev >> 16, od >> 16};
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          const uint32_t ch = 4 * g + b, n = n4[b];
+          if (lane == 0 && ch < nch && n) {
+            atomicAdd(&ccnt[I.cell * nch + ch], n);
+            atomicAdd(&cnent[I.cell * nch + ch], n);
+            if (istride) itemcnt[(uint64_t)ch * istride + it] = n;
+          }
+        }
+      }
+    } else {
+      uint32_t aw[32], an[32];
+#pragma unroll
+      for (int ch = 0; ch < 32; ch++) { aw[ch] = 0; an[ch] = 0; }
+      for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        const uint64_t ei = I.off + k;
+        uint32_t mask = 0, w = 0;
+        if (k < cnt) {
+          const EntQ64 e = ents[ei];
+          w = e.w;
+          mask = pose5_mask64<ALL>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+          masks[ei] = mask;
+        }
+#pragma unroll
+        for (int ch = 0; ch < 32; ch++) {
+          const bool p = (mask >> ch) & 1u;
           aw[ch] += p ? w : 0u;
           an[ch] += p ? 1u : 0u;
         }
       }
-    }
 #pragma unroll
-    for (int ch = 0; ch < 32; ch++) {
-      if ((uint32_t)ch < nch) {
-        const uint32_t n = UNIT ? an[ch] : wave_sum_u32(an[ch]);
-        const uint32_t w = UNIT ? n : wave_sum_u32(aw[ch]);
-        if (lane == 0 && n) {
-          atomicAdd(&ccnt[I.cell * nch + ch], w);
-          atomicAdd(&cnent[I.cell * nch + ch], n);
-          if (istride) itemcnt[(uint64_t)ch * istride + it] = n;
+      for (int ch = 0; ch < 32; ch++) {
+        if ((uint32_t)ch < nch) {
+          const uint32_t n = wave_sum_u32(an[ch]);
+          const uint32_t w = wave_sum_u32(aw[ch]);
+          if (lane == 0 && n) {
+            atomicAdd(&ccnt[I.cell * nch + ch], w);
+            atomicAdd(&cnent[I.cell * nch + ch], n);
+            if (istride) itemcnt[(uint64_t)ch * istride + it] = n;
+          }
         }
       }
     }
