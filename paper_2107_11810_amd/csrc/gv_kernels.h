@@ -387,6 +387,37 @@ __device__ inline void pose_level_boxes(const ProbC& P, const LevelC& lv, const 
   }
 }
 
+// Pass mask of a cell's children from the half tests of one surface:
+// child ch passes iff its z half and its kappa half pass.  Half-test bit
+// index: bx | by << 1 | (z or kappa bit) << 2 [| bf << 3 for the f half,
+// NAX = 5].  ALL (every axis splits): the digit holds the axis bits in axis
+// order, most significant first, so each child's two bit indices are
+// compile-time constants; otherwise they come from the level's table.
+template <int NAX, bool ALL>
+__device__ inline uint32_t pose_children(const LevelC& lv, uint32_t nch, uint32_t zbits, uint32_t kbits) {
+  constexpr int NCH = 1 << NAX;
+  uint32_t mask = 0;
+  if constexpr (ALL) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ch++) {
+      const int bx = (ch >> (NAX - 1)) & 1, by = (ch >> (NAX - 2)) & 1, bz = (ch >> (NAX - 3)) & 1;
+      const int bk = (ch >> (NAX - 4)) & 1, bf = NAX == 5 ? (ch & 1) : 0;
+      const int zi = bx | (by << 1) | (bz << 2) | (bf << 3), ki = bx | (by << 1) | (bk << 2) | (bf << 3);
+      mask |= (((zbits >> zi) & (kbits >> ki)) & 1u) << ch;
+    }
+  } else {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ch++) {
+      if ((uint32_t)ch >= nch) break;
+      const uint32_t cb = lv.cbits[ch];
+      const uint32_t xy = cb & 3u, zb = (cb >> 2) & 1u, kb = (cb >> 3) & 1u, fb = NAX == 5 ? (cb >> 4) & 1u : 0u;
+      if (((zbits >> (xy | (zb << 2) | (fb << 3))) & 1u) && ((kbits >> (xy | (kb << 2) | (fb << 3))) & 1u))
+        mask |= 1u << ch;
+    }
+  }
+  return mask;
+}
+
 // binary64 mask over the children of one cell for one surface.  ALL: every
 // axis splits at this level (16 children), so no per-axis checks.
 template <bool ALL>
@@ -414,16 +445,7 @@ __device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const P
       if (khalf64e(v, rmin2, P.Rg2, ke[b])) kbits |= 1u << (xy | (b << 2));
     }
   }
-  uint32_t mask = 0;
-#pragma unroll
-  for (int ch = 0; ch < 16; ch++) {
-    if ((uint32_t)ch >= nch) break;
-    uint32_t cb = lv.cbits[ch];
-    uint32_t xy = (cb & 1u) | (((cb >> 1) & 1u) << 1);
-    uint32_t zb = (cb >> 2) & 1u, kb = (cb >> 3) & 1u;
-    if (((zbits >> (xy | (zb << 2))) & 1u) && ((kbits >> (xy | (kb << 2))) & 1u)) mask |= 1u << ch;
-  }
-  return mask;
+  return pose_children<4, ALL>(lv, nch, zbits, kbits);
 }
 
 // binary32 mask with binary64 recheck of undecided halves (the binary64
@@ -486,16 +508,7 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const C
       if (kp[b]) kbits |= 1u << (xy | (b << 2));
     }
   }
-  uint32_t mask = 0;
-#pragma unroll
-  for (int ch = 0; ch < 16; ch++) {
-    if ((uint32_t)ch >= nch) break;
-    uint32_t cb = lv.cbits[ch];
-    uint32_t xy = (cb & 1u) | (((cb >> 1) & 1u) << 1);
-    uint32_t zb = (cb >> 2) & 1u, kb = (cb >> 3) & 1u;
-    if (((zbits >> (xy | (zb << 2))) & 1u) && ((kbits >> (xy | (kb << 2))) & 1u)) mask |= 1u << ch;
-  }
-  return mask;
+  return pose_children<4, ALL>(lv, nch, zbits, kbits);
 }
 
 // UNIT: every multiplicity is 1, so a child's count is the popcount of its

@@ -112,16 +112,7 @@ __device__ inline uint32_t pose5_mask64(const ProbC& P, const LevelC& lv, const 
       }
     }
   }
-  uint32_t mask = 0;
-#pragma unroll
-  for (int ch = 0; ch < 32; ch++) {
-    if ((uint32_t)ch >= nch) break;
-    const uint32_t cb = lv.cbits[ch];
-    const uint32_t xy = cb & 3u, zb = (cb >> 2) & 1u, kb = (cb >> 3) & 1u, fb = (cb >> 4) & 1u;
-    if (((zbits >> (xy | (zb << 2) | (fb << 3))) & 1u) && ((kbits >> (xy | (kb << 2) | (fb << 3))) & 1u))
-      mask |= 1u << ch;
-  }
-  return mask;
+  return pose_children<5, ALL>(lv, nch, zbits, kbits);
 }
 
 // Incidence test and per-child counts of a batch (one wave per item), with
