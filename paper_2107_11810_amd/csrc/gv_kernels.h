@@ -1165,7 +1165,8 @@ __global__ void __launch_bounds__(256) k_compact(LevelC lv, const Cell* __restri
       static_assert(CONV || std::is_same<E, EO>::value, "pose entries are copied whole");
       using Wd = std::conditional_t<sizeof(EO) % 16 == 0, uint4, uint2>;
       constexpr int NV = sizeof(EO) / sizeof(Wd);
-      constexpr int G = sizeof(EO) <= 32 ? 16 : 8;
+      // (32-child masks: fewer entries per lane, the store loop runs per child)
+      constexpr int G = sizeof(EO) <= 32 && NCP <= 16 ? 16 : 8;
       // each child's run continues at a wave-uniform byte address; a lane
       // adds its 32-bit rank offset, so a store is a scalar base plus one
       // per-lane offset

@@ -64,15 +64,16 @@ __device__ inline bool zhalf5(const ZPre<double>& z, double ah2, double al2, dou
 }
 
 // kappa-half edge directions over the tangents t = xi f, f in [Fl, Fh]
-__device__ inline KEdge<double> kedge5(double xi, double Llo, double Lhi, double Fl, double Fh) {
-  const double t1 = xi * Fl, t2 = xi * Fh;
-  const double tl = t1 < t2 ? t1 : t2, th = t1 < t2 ? t2 : t1;
-  KEdge<double> e;
+template <typename R>
+__device__ inline KEdge<R> kedge5(R xi, R Llo, R Lhi, R Fl, R Fh) {
+  const R t1 = xi * Fl, t2 = xi * Fh;
+  const R tl = t1 < t2 ? t1 : t2, th = t1 < t2 ? t2 : t1;
+  KEdge<R> e;
   e.pl = Llo * tl;
   e.ph = Lhi * th;
-  e.elx = 1.0 - e.pl;
+  e.elx = (R)1 - e.pl;
   e.ely = Llo + tl;
-  e.ehx = 1.0 - e.ph;
+  e.ehx = (R)1 - e.ph;
   e.ehy = Lhi + th;
   return e;
 }
@@ -92,8 +93,8 @@ __device__ inline uint32_t pose5_mask64(const ProbC& P, const LevelC& lv, const 
     if (!ALL && bf && !lv.split[4]) continue;
     const double ah = a * B.Fhi[bf], al = a * B.Flo[bf];
     const double ah2 = ah * ah, al2 = al * al;
-    const KEdge<double> ke[2] = {kedge5(xi, B.Llo[0], B.Lhi[0], B.Flo[bf], B.Fhi[bf]),
-                                 kedge5(xi, B.Llo[1], B.Lhi[1], B.Flo[bf], B.Fhi[bf])};
+    const KEdge<double> ke[2] = {kedge5<double>(xi, B.Llo[0], B.Lhi[0], B.Flo[bf], B.Fhi[bf]),
+                                 kedge5<double>(xi, B.Llo[1], B.Lhi[1], B.Flo[bf], B.Fhi[bf])};
 #pragma unroll
     for (int xy = 0; xy < 4; xy++) {
       const int bx = xy & 1, by = xy >> 1;
@@ -115,6 +116,194 @@ __device__ inline uint32_t pose5_mask64(const ProbC& P, const LevelC& lv, const 
   return pose_children<5, ALL>(lv, nch, zbits, kbits);
 }
 
+// ---------------------------------------------------------------------------
+// binary32 filter.  W, xi, eta and the x, y, z, kappa child bounds are exact
+// in binary32 (lattice values, checked per problem on the host); the f
+// bounds are rounded to binary32.  Each half's deciding value is computed in
+// binary32 with a bound on its distance from the value the binary64 test
+// compares: where the value clears the bound the binary64 test decides the
+// same way, else the half is undecided and recomputed in binary64 with the
+// plain test's own operations.  Rounding: each operation adds a relative
+// error of at most u = 2^-24; the host keeps every nonzero intermediate of
+// the kappa half and of the z half's first products in the normal range.
+//   z-half, low end: X = (|eta| Fh)^2 rmax2 carries 8u (Fh rounded, the
+//     product, its square, the two roundings of rmax2, the last product),
+//     Tlo^2 one rounding and the difference one more: at most
+//     9u X + 2u Tlo^2 to first order.  The bound 16u (X + Tlo^2) covers the
+//     higher orders and the binary64 value's own rounding (below 2^-50
+//     relative); the absolute 2^-100 covers the last product's underflow
+//     (al^2 rmin2 can fall below the normal range).  The high end likewise
+//     with Fl and rmin2.
+//   kappa-half: t = xi F carries 2u (F rounded, the product), p = L t 3u,
+//     e_x = 1 - p at most 3u|p| + u|e_x|, e_y = L + t at most 2u|t| + u|e_y|;
+//     a cross product e_x a_y - e_y a_x with exact corners a then errs by at
+//     most 3u (|p| + |t| + |e_x| + |e_y|)(|a_x| + |a_y|); the bound takes 8u
+//     with |xi| Fh for |t|.  The apex guard is the 4-DoF one.
+// ---------------------------------------------------------------------------
+#define GV_TINY32 7.888609052210118e-31f  // 2^-100
+
+__device__ inline bool zhalf5_32m(const ZPre<float>& z, float ah2, float al2, float rmin2, float rmax2, bool& und) {
+  const float X = ah2 * rmax2;
+  const float dl = X - z.Ylo, bl = 16.0f * GV_U32 * (X + z.Ylo) + GV_TINY32;
+  const bool lo_t = z.Tlo <= 0.0f;
+  const bool lp = lo_t || dl > bl, ln = !lo_t && dl < -bl;
+  const float X2 = al2 * rmin2;
+  const float dh = z.Yhi - X2, bh = 16.0f * GV_U32 * (X2 + z.Yhi) + GV_TINY32;
+  const bool hneg = z.Thi < 0.0f;
+  const bool hp = !hneg && dh > bh, hn = hneg || dh < -bh;
+  const bool pass = lp && hp;
+  und = !(ln || hn) && !pass;
+  return pass;
+}
+
+// Bf layout: Xlo[2] Xhi[2] Ylo[2] Yhi[2] ZH[2] ZL[2] Llo[2] Lhi[2] Flo[2] Fhi[2]
+#define GV_P5_NBF 20
+__device__ inline void pose5_boxes32(const Pose5Level& B, float* Bf) {
+  for (int b = 0; b < 2; b++) {
+    Bf[0 + b] = (float)B.Xlo[b];
+    Bf[2 + b] = (float)B.Xhi[b];
+    Bf[4 + b] = (float)B.Ylo[b];
+    Bf[6 + b] = (float)B.Yhi[b];
+    Bf[8 + b] = (float)B.ZH[b];
+    Bf[10 + b] = (float)B.ZL[b];
+    Bf[12 + b] = (float)B.Llo[b];
+    Bf[14 + b] = (float)B.Lhi[b];
+    Bf[16 + b] = (float)B.Flo[b];
+    Bf[18 + b] = (float)B.Fhi[b];
+  }
+}
+
+// One child half's bounds in binary64, computed as pose5_level_boxes does
+// (bit-equal values): x, y by (bx, by), the z or kappa interval by bq, f by bf.
+__device__ inline void pose5_half_bounds(const ProbC& P, const LevelC& lv, const Cell& C, int m, int bx, int by,
+                                         int bq, int bf, bool kap, VBox<double>& xy, double& qlo, double& qhi,
+                                         double& Fl, double& Fh) {
+  const int m1 = m + 1;
+  const int32_t cx = lv.split[0] ? 2 * C.c[0] + bx : C.c[0];
+  const int32_t cy = lv.split[1] ? 2 * C.c[1] + by : C.c[1];
+  const int32_t cf = lv.split[4] ? 2 * C.c[4] + bf : C.c[4];
+  const double hx = ldexp(1.0, -min(m1, P.L[0])), hy = ldexp(1.0, -min(m1, P.L[1]));
+  const double hf = ldexp(1.0, -min(m1, P.L[4]));
+  xy.x0 = (double)cx * hx;
+  xy.x1 = (double)(cx + 1) * hx;
+  xy.y0 = (double)cy * hy;
+  xy.y1 = (double)(cy + 1) * hy;
+  Fl = P.flo + P.Ef * ((double)cf * hf);
+  Fh = P.flo + P.Ef * ((double)(cf + 1) * hf);
+  if (kap) {
+    const int32_t ck = lv.split[3] ? 2 * C.c[3] + bq : C.c[3];
+    const double hk = ldexp(1.0, -min(m1, P.L[3]));
+    const double Klo = 2.0 * ((double)ck * hk) - 1.0, Khi = 2.0 * ((double)(ck + 1) * hk) - 1.0;
+    qlo = Klo - P.padk;
+    qhi = Khi + P.padk;
+  } else {
+    const int32_t cz = lv.split[2] ? 2 * C.c[2] + bq : C.c[2];
+    const double hz = ldexp(1.0, -min(m1, P.L[2]));
+    const double Zlo = (double)cz * hz, Zhi = (double)(cz + 1) * hz;
+    qlo = Zlo - P.padz;  // ZL
+    qhi = Zhi + P.padz;  // ZH
+  }
+}
+
+// binary32 mask; the undecided halves (bit index xy | b << 2 | bf << 3 of
+// zund / kund) are then recomputed in binary64 one at a time, from the
+// entry's binary64 root values and the child's bounds, with the plain test's
+// operations
+template <bool ALL, typename EQ>
+__device__ inline uint32_t pose5_mask32(const ProbC& P, const LevelC& lv, const Cell& C, int m, const float* Bf,
+                                        int sector, const EQ& e, const double* __restrict__ m64, uint64_t n_root,
+                                        uint32_t& nrecheck) {
+  const uint32_t nch = ALL ? 32u : 1u << lv.abits;
+  uint32_t zbits = 0, kbits = 0, zund = 0, kund = 0;
+  const ZPre<float> zp[2] = {zpre<float>(e.W3, e.eta, Bf[8], Bf[10]), zpre<float>(e.W3, e.eta, Bf[9], Bf[11])};
+  const float a = fabsf(e.eta), axi = fabsf(e.xi);
+#pragma unroll
+  for (int bf = 0; bf < 2; bf++) {
+    if (!ALL && bf && !lv.split[4]) continue;
+    const float Fl = Bf[16 + bf], Fh = Bf[18 + bf];
+    const float ah = a * Fh, al = a * Fl;
+    const float ah2 = ah * ah, al2 = al * al;
+    const KEdge<float> ke[2] = {kedge5<float>(e.xi, Bf[12], Bf[14], Fl, Fh), kedge5<float>(e.xi, Bf[13], Bf[15], Fl, Fh)};
+    const float tm = axi * Fh;
+    float kSl[2], kSh[2];
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      kSl[b] = 8.0f * GV_U32 * (fabsf(ke[b].pl) + tm + fabsf(ke[b].elx) + fabsf(ke[b].ely));
+      kSh[b] = 8.0f * GV_U32 * (fabsf(ke[b].ph) + tm + fabsf(ke[b].ehx) + fabsf(ke[b].ehy));
+    }
+#pragma unroll
+    for (int xy = 0; xy < 4; xy++) {
+      const int bx = xy & 1, by = xy >> 1;
+      if (!ALL && ((bx && !lv.split[0]) || (by && !lv.split[1]))) continue;
+      const VBox<float> v = pose_vbox<float>(e.W1, e.W2, Bf[0 + bx], Bf[2 + bx], Bf[4 + by], Bf[6 + by], sector);
+      const float rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        if (!ALL && b && !lv.split[2]) continue;
+        bool u;
+        const uint32_t bit = 1u << (xy | (b << 2) | (bf << 3));
+        if (zhalf5_32m(zp[b], ah2, al2, rmin2, rmax2, u)) zbits |= bit;
+        if (u) zund |= bit;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        if (!ALL && b && !lv.split[3]) continue;
+        bool u;
+        const uint32_t bit = 1u << (xy | (b << 2) | (bf << 3));
+        if (khalf32m(v, rmin2, P.Rg2f, ke[b], kSl[b], kSh[b], u)) kbits |= bit;
+        if (u) kund |= bit;
+      }
+    }
+  }
+  if (zund | kund) {
+    const uint64_t r = e.ridx;
+    const double W1 = m64[r], W2 = m64[n_root + r], W3 = m64[2 * n_root + r], xi = m64[3 * n_root + r],
+                 eta = m64[4 * n_root + r];
+    uint32_t und = zund | (kund << 16);
+#pragma unroll 1
+    while (und) {
+      const uint32_t j = (uint32_t)__builtin_ctz(und);
+      und &= und - 1u;
+      const bool kap = j >= 16;
+      const uint32_t i = j & 15u;
+      const int bx = i & 1, by = (i >> 1) & 1, bq = (i >> 2) & 1, bf = (i >> 3) & 1;
+      VBox<double> box;
+      double qlo, qhi, Fl, Fh;
+      pose5_half_bounds(P, lv, C, m, bx, by, bq, bf, kap, box, qlo, qhi, Fl, Fh);
+      const VBox<double> vd = pose_vbox<double>(W1, W2, box.x0, box.x1, box.y0, box.y1, sector);
+      const double rmin2d = rmin2_of(vd);
+      bool pass;
+      if (kap) {
+        pass = khalf64e(vd, rmin2d, P.Rg2, kedge5<double>(xi, qlo, qhi, Fl, Fh));
+      } else {
+        const double rmax2d = rmax2_of(vd);
+        const ZPre<double> zq = zpre<double>(W3, eta, qhi, qlo);
+        const double aa = eta >= 0.0 ? eta : -eta;
+        const double ah = aa * Fh, al = aa * Fl;
+        pass = zhalf5(zq, ah * ah, al * al, rmin2d, rmax2d);
+      }
+      const uint32_t bm = 1u << i;
+      if (kap)
+        kbits = pass ? (kbits | bm) : (kbits & ~bm);
+      else
+        zbits = pass ? (zbits | bm) : (zbits & ~bm);
+      nrecheck++;
+    }
+  }
+  return pose_children<5, ALL>(lv, nch, zbits, kbits);
+}
+
+// mask of one entry: the binary64 test on binary64 lists, else the filter
+template <bool ALL, typename E>
+__device__ inline uint32_t pose5_mask_of(const ProbC& P, const LevelC& lv, const Cell& C, int m, const Pose5Level& B,
+                                         const float* Bf, const E& e, const double* __restrict__ m64,
+                                         uint64_t n_root, uint32_t& nre) {
+  if constexpr (std::is_same<E, EntQ64>::value)
+    return pose5_mask64<ALL>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+  else
+    return pose5_mask32<ALL>(P, lv, C, m, Bf, (int)C.sector, e, m64, n_root, nre);
+}
+
 // Incidence test and per-child counts of a batch (one wave per item), with
 // a 32-bit pass mask stored per entry for the compaction.  UNIT: every
 // multiplicity is 1: each lane counts its own passes, four children to a
@@ -123,18 +312,24 @@ __device__ inline uint32_t pose5_mask64(const ProbC& P, const LevelC& lv, const 
 // per child).  Thirty-two scalar ballot accumulators, beside the cell's
 // binary64 child boxes, overflowed the scalar registers.
 static_assert(GV_ITEM / 64 <= 255 && 64 * (GV_ITEM / 64) <= 65535, "per-lane byte counters, 16-bit wave sums");
-template <bool UNIT, bool ALL>
+// E: EntQ64 (binary64 lists) or EntQ32 / EntQ24 (binary32 filter; m64 holds
+// the binary64 root values for the recheck, n_root their column stride).
+template <typename E, bool UNIT, bool ALL>
 __global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ Ptab, int m, LevelC lv,
                                                      const Cell* __restrict__ cells, const Item* __restrict__ items,
-                                                     const uint32_t* __restrict__ nitems_p,
-                                                     const EntQ64* __restrict__ ents, uint32_t* __restrict__ masks,
-                                                     uint32_t* __restrict__ ccnt, uint32_t* __restrict__ cnent,
+                                                     const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
+                                                     const double* __restrict__ m64, uint64_t n_root,
+                                                     uint32_t* __restrict__ masks, uint32_t* __restrict__ ccnt,
+                                                     uint32_t* __restrict__ cnent,
+                                                     unsigned long long* __restrict__ rechecks,
                                                      uint32_t* __restrict__ itemcnt, uint32_t istride) {
+  constexpr bool F64 = std::is_same<E, EntQ64>::value;
   const uint32_t nch = ALL ? 32u : 1u << lv.abits;
   const uint32_t lane = lane_id();
   const uint32_t wave = uniform_u32((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t nitems = *nitems_p;
+  uint32_t nre = 0;
   for (uint32_t it = wave; it < nitems; it += nwaves) {
     const Item I = items[it];
     const Cell C = cells[I.cell];
@@ -142,6 +337,8 @@ __global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ P
     const uint32_t cnt = I.cnt;
     Pose5Level B;
     pose5_level_boxes(P, lv, C, m, B);
+    float Bf[F64 ? 1 : GV_P5_NBF];
+    if constexpr (!F64) pose5_boxes32(B, Bf);
     if constexpr (UNIT) {
       uint32_t pk[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // byte b of pk[g]: passes of child 4g + b
       for (uint32_t k0 = 0; k0 < cnt; k0 += 64) {
@@ -149,8 +346,8 @@ __global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ P
         const uint64_t ei = I.off + k;
         uint32_t mask = 0;
         if (k < cnt) {
-          const EntQ64 e = ents[ei];
-          mask = pose5_mask64<ALL>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+          const E e = ents[ei];
+          mask = pose5_mask_of<ALL>(P, lv, C, m, B, Bf, e, m64, n_root, nre);
           masks[ei] = mask;
         }
         // spread each nibble of the mask to the low bits of four bytes
@@ -182,9 +379,9 @@ __global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ P
         const uint64_t ei = I.off + k;
         uint32_t mask = 0, w = 0;
         if (k < cnt) {
-          const EntQ64 e = ents[ei];
-          w = e.w;
-          mask = pose5_mask64<ALL>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+          const E e = ents[ei];
+          w = pose_w(e);
+          mask = pose5_mask_of<ALL>(P, lv, C, m, B, Bf, e, m64, n_root, nre);
           masks[ei] = mask;
         }
 #pragma unroll
@@ -207,6 +404,10 @@ __global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ P
         }
       }
     }
+  }
+  if constexpr (!F64) {
+    const uint32_t tot = wave_sum_u32(nre);
+    if (lane == 0 && tot) atomicAdd(rechecks, (unsigned long long)tot);
   }
 }
 
@@ -242,7 +443,7 @@ __global__ void k_replay_pose5(const ProbC* __restrict__ Ptab, const double* __r
       const double rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
       const double ah = a * Fh, al = a * Fl;
       ok = zhalf5(zpre<double>(W3, eta, Zhi + P.padz, Zlo - P.padz), ah * ah, al * al, rmin2, rmax2) &&
-           khalf64e(v, rmin2, P.Rg2, kedge5(xi, Klo - P.padk, Khi + P.padk, Fl, Fh));
+           khalf64e(v, rmin2, P.Rg2, kedge5<double>(xi, Klo - P.padk, Khi + P.padk, Fl, Fh));
       for (int j = 0; j < 5; j++) cc[j] = ch[j];
     }
     flag[i] = ok;
@@ -251,14 +452,23 @@ __global__ void k_replay_pose5(const ProbC* __restrict__ Ptab, const double* __r
 
 // Incidence test only (gv_incidence): every root surface against the
 // children of cell C at level m, exactly as in the count pass.
-__global__ void k_incidence_pose5(const ProbC* __restrict__ Pp, const EntQ64* __restrict__ root, int64_t n, Cell C,
-                                  int m, uint32_t* __restrict__ masks) {
+template <typename E>
+__global__ void k_incidence_pose5(const ProbC* __restrict__ Pp, const E* __restrict__ root, int64_t n,
+                                  const double* __restrict__ m64, uint64_t n_root, Cell C, int m,
+                                  uint32_t* __restrict__ masks, unsigned long long* __restrict__ rechecks) {
   const ProbC& P = *Pp;
   const LevelC& lv = P.lev[m];
   Pose5Level B;
   pose5_level_boxes(P, lv, C, m, B);
+  float Bf[GV_P5_NBF];
+  pose5_boxes32(B, Bf);
+  uint32_t nre = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const EntQ64 e = root[i];
-    masks[i] = pose5_mask64<false>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+    const E e = root[i];
+    if constexpr (std::is_same<E, EntQ64>::value)
+      masks[i] = pose5_mask64<false>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+    else
+      masks[i] = pose5_mask32<false>(P, lv, C, m, Bf, (int)C.sector, e, m64, n_root, nre);
   }
+  if (nre) atomicAdd(rechecks, (unsigned long long)nre);
 }

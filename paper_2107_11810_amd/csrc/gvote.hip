@@ -487,6 +487,22 @@ bool pose_filter_exact(const Setup& S, const double* mx) {
   return true;
 }
 
+// POSE5DOF: the 4-DoF conditions on x, y, z, kappa and the lattice values,
+// every step at least 2^-30 and f within [2^-10, 2^10], so that the kappa
+// half's products and the z half's first products stay in binary32's normal
+// range, and the z half's products below 2^100 (the f bounds are rounded to
+// binary32; the filter's bounds include that rounding)
+bool pose5_filter_exact(const Setup& S, const double* mx) {
+  const ProbC& P = S.P;
+  if (!pose_filter_exact(S, mx)) return false;
+  if (std::min(std::min(P.sW, P.sW3), std::min(P.sXi, P.sEta)) < 0x1p-30) return false;
+  const double fmax = P.flo + P.Ef;
+  if (!(P.flo >= 0x1p-10 && fmax <= 0x1p10)) return false;
+  const double r = std::max(mx[2], mx[3]) + 1.0, a = mx[6] * fmax;
+  if (!(a * a * 2.0 * r * r < 0x1p100 && mx[5] * fmax < 0x1p20)) return false;
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // One problem inside an epoch (also the record behind a ticket).
 // ---------------------------------------------------------------------------
@@ -1020,11 +1036,11 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   X.stats.test_launches++;
   X.stats.test_bytes += tbytes;
   if constexpr (FAM == FAM_POSE5DOF) {
-#define GV_COUNT_POSE5(U, A)                                                                                   \
-  k_count_pose5<U, A><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const EntQ64*)b.ents, \
-                                             (uint32_t*)pa->masks, ccnt, pa->cnent, itemcnt ? itemcnt : X.dummy, \
-                                             itemcnt ? pa->istride : 0u)
-    static_assert(std::is_same<E, EntQ64>::value && std::is_same<M, uint32_t>::value, "5-DoF lists are binary64");
+#define GV_COUNT_POSE5(U, A)                                                                                     \
+  k_count_pose5<E, U, A><<<grid, 256, 0, X.st>>>(X.dP, m, lv, b.cells, pa->items, pa->nitems, (const E*)b.ents,   \
+                                                X.m64, X.Ntot, (uint32_t*)pa->masks, ccnt, pa->cnent, X.drecheck, \
+                                                itemcnt ? itemcnt : X.dummy, itemcnt ? pa->istride : 0u)
+    static_assert(std::is_same<M, uint32_t>::value, "5-DoF masks are 32-bit");
     const bool all = lv.abits == 5;
     if (b.unit) {
       if (all) GV_COUNT_POSE5(true, true);
@@ -1460,14 +1476,14 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
 
 // Entry type of a level's lists: the packed entry from pack_from on.
 template <int FAM, typename E>
-using PackedT = std::conditional_t<FAM == FAM_POSE4DOF || std::is_void_v<typename PackOf<FAM>::T>, E,
+using PackedT = std::conditional_t<fam_pose(FAM) || std::is_void_v<typename PackOf<FAM>::T>, E,
                                    typename PackOf<FAM>::T>;
 
 template <int FAM, typename E, typename M>
 Parent* expand_at(Run& X, Batch& b, bool own_ents, bool dive) {
   if constexpr (FAM == FAM_PLANE3D)
     if (b.unit && b.level >= X.unit_from) return expand<FAM, EntP3u, M>(X, b, own_ents, dive);
-  if constexpr (FAM == FAM_POSE4DOF && std::is_same<E, EntQ32>::value)
+  if constexpr ((FAM == FAM_POSE4DOF || FAM == FAM_POSE5DOF) && std::is_same<E, EntQ32>::value)
     if (b.unit && b.level >= 1 && X.q24) return expand<FAM, EntQ24, M>(X, b, own_ents, dive);
   if (b.level >= X.pack_from) return expand<FAM, PackedT<FAM, E>, M>(X, b, own_ents, dive);
   return expand<FAM, E, M>(X, b, own_ents, dive);
@@ -1476,7 +1492,7 @@ Parent* expand_at(Run& X, Batch& b, bool own_ents, bool dive) {
 template <int FAM, typename E, typename M>
 bool materialize_at(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
   using EP = PackedT<FAM, E>;
-  if constexpr (FAM == FAM_POSE4DOF && std::is_same<E, EntQ32>::value) {
+  if constexpr ((FAM == FAM_POSE4DOF || FAM == FAM_POSE5DOF) && std::is_same<E, EntQ32>::value) {
     if (pa->unit && X.q24) {
       if (pa->level >= 1) return materialize<FAM, EntQ24, EntQ24, M>(X, pa, r0, r1, nb);
       return materialize<FAM, EntQ32, EntQ24, M>(X, pa, r0, r1, nb);
@@ -2020,9 +2036,10 @@ void build_exact(Run& X) {
 
 template <typename E>
 bool step_pose(Run& X) { return epoch_step<FAM_POSE4DOF, E, uint16_t>(X); }
-bool step_pose5(Run& X) { return epoch_step<FAM_POSE5DOF, EntQ64, uint32_t>(X); }
+template <typename E>
+bool step_pose5(Run& X) { return epoch_step<FAM_POSE5DOF, E, uint32_t>(X); }
 
-// returns true when the binary32 filter is used (POSE4DOF only)
+// returns true when the binary32 filter is used
 bool build_pose(Run& X) {
   const uint32_t np = (uint32_t)X.probs.size();
   unsigned long long* dmx = dalloc<unsigned long long>(X, 8 * np);
@@ -2077,17 +2094,23 @@ bool build_pose(Run& X) {
     ProbRec* pr = X.probs[p];
     double mx[8];
     std::memcpy(mx, &mxb[8 * p], 64);
-    // (POSE5DOF: binary64 in both modes)
-    pr->filter_ok = pr->p.precision == GV_FP32_FILTER && pr->S.fam == GV_POSE4DOF && pose_filter_exact(pr->S, mx);
+    pr->filter_ok = pr->p.precision == GV_FP32_FILTER &&
+                    (pr->S.fam == GV_POSE4DOF ? pose_filter_exact(pr->S, mx) : pose5_filter_exact(pr->S, mx));
     if (pr->st == GV_OK && !pr->filter_ok) all32 = false;
   }
   // (grouping below the root is off for this family unless forced)
   X.q24 = X.ctx->pack && X.group_mode <= 0;
   if (X.fam == GV_POSE5DOF) {
-    dfree(X, e32);
-    X.root = e64;
-    if (!X.root_only) start_search<FAM_POSE5DOF, EntQ64, uint32_t>(X);
-    return false;
+    if (all32) {
+      dfree(X, e64);
+      X.root = e32;
+      if (!X.root_only) start_search<FAM_POSE5DOF, EntQ32, uint32_t>(X);
+    } else {
+      dfree(X, e32);
+      X.root = e64;
+      if (!X.root_only) start_search<FAM_POSE5DOF, EntQ64, uint32_t>(X);
+    }
+    return all32;
   }
   if (all32) {
     dfree(X, e64);
@@ -2272,7 +2295,9 @@ std::function<bool(Run&)> epoch_build(Run& X) {
     case GV_PLANE3D: build_linear<FAM_PLANE3D>(X); return epoch_step<FAM_PLANE3D, EntP3, uint8_t>;
     case GV_RAY3D: build_linear<FAM_RAY3D>(X); return epoch_step<FAM_RAY3D, EntR3, uint8_t>;
     case GV_SIM2D: build_linear<FAM_SIM2D>(X); return epoch_step<FAM_SIM2D, EntS2, uint8_t>;
-    case GV_POSE5DOF: build_pose(X); return step_pose5;
+    case GV_POSE5DOF:
+      if (build_pose(X)) return step_pose5<EntQ32>;
+      return step_pose5<EntQ64>;
     default:
       if (build_pose(X)) return step_pose<EntQ32>;
       return step_pose<EntQ64>;
@@ -2946,7 +2971,12 @@ gv_status gv_incidence(gv_ctx* ctx, const gv_problem* p, int32_t level, int32_t 
         uint32_t* dm = dalloc<uint32_t>(X, (uint64_t)pr.n);
         const unsigned gg = gs_grid(X, (uint64_t)pr.n);
         if (pr.S.fam == GV_POSE5DOF) {
-          k_incidence_pose5<<<gg, 256, 0, X.st>>>(X.dP, (const EntQ64*)X.root, pr.n, C, level, dm);
+          if (f32)
+            k_incidence_pose5<EntQ32><<<gg, 256, 0, X.st>>>(X.dP, (const EntQ32*)X.root, pr.n, X.m64, X.Ntot, C,
+                                                           level, dm, X.drecheck);
+          else
+            k_incidence_pose5<EntQ64><<<gg, 256, 0, X.st>>>(X.dP, (const EntQ64*)X.root, pr.n, X.m64, X.Ntot, C,
+                                                           level, dm, X.drecheck);
         } else if (pr.S.fam == GV_POSE4DOF) {
           if (f32)
             k_incidence_pose<EntQ32><<<gg, 256, 0, X.st>>>(X.dP, (const EntQ32*)X.root, pr.n, X.m64, X.Ntot, C, level,

@@ -185,3 +185,180 @@ def test_edge_cases(ctx):
         ctx.solve(g["family"], wide, g["lo"], g["hi"], g["eps"])
     with pytest.raises(oracle.OracleError):
         oracle.solve(oracle.Problem(g["family"], wide, g["lo"], g["hi"], g["eps"]))
+
+
+# ----------------------------------------------------------------------------
+# Binary32 filter at its thresholds.  Surfaces are placed exactly on, and a
+# few lattice steps from, each sign decision of the test of the children of
+# CELL5: the z-half's low end (|eta| Fh r_max against the z interval's far
+# bound) and high end (|eta| Fl r_min against the near one) for either sign
+# of eta and either f half, the apex guard, and the four cross products of
+# the kappa cone, with xi = 0 and with the edge tangents xi Fl, xi Fh.  The
+# f bounds are dyadic here (f in [0.5, 1.5]), so the ties are exact in
+# binary64 and binary32 alike; the filter must leave them to binary64.
+# ----------------------------------------------------------------------------
+BOX5 = dict(lo=[0.0, 0.0, 0.0, 0.0, 0.5], hi=[200.0, 200.0, 200.0, 2 * math.pi, 1.5],
+            eps=[4.0, 4.0, 4.0, math.radians(2.0), 0.05])
+CELL5 = (3, 0, [1, 1, 3, 5, 2])  # children at level 4: kappa in [0.25, 0.5], f in [0.75, 0.875]
+
+
+def _problem5(W, xi, eta):
+    """Observation columns from normalized lattice values (lo = 0, E = 200 on
+    the metric axes, so eta' = eta); two anchors fix the data bounds of the
+    lattice (|eta'| = 1, apex in a corner of the unit square)."""
+    W = np.concatenate([np.array([[0.0, 0.0, 0.5], [1.0, 1.0, 0.5]]), W])
+    xi = np.concatenate([[0.0, 0.0], xi])
+    eta = np.concatenate([[1.0, -1.0], eta])
+    cols = [W[:, 0] * 200.0, W[:, 1] * 200.0, W[:, 2] * 200.0, xi, eta]
+    return dict(family="pose5dof", cols=cols, **BOX5)
+
+
+def _lattice5():
+    k = oracle.constants(OP(_problem5(np.zeros((0, 3)), np.zeros(0), np.zeros(0))))
+    sW, sW3, sXi, sEta = k["steps"]
+    return dict(sW=sW, sW3=sW3, sXi=sXi, sEta=sEta, padz=k["pad0"][0], padk=k["pad0"][1], Rg=k["Rg"], L=k["L"])
+
+
+def _boxes5(lat):
+    m, sec, cc = CELL5
+    h = 2.0 ** -(m + 1)
+    assert all(m + 1 <= lat["L"][j] for j in range(5))  # every axis splits
+    box = {}
+    for b in (0, 1):
+        box[("X", b)] = ((2 * cc[0] + b) * h, (2 * cc[0] + b + 1) * h)
+        box[("Y", b)] = ((2 * cc[1] + b) * h, (2 * cc[1] + b + 1) * h)
+        box[("Z", b)] = ((2 * cc[2] + b) * h - lat["padz"], (2 * cc[2] + b + 1) * h + lat["padz"])
+        klo = 2 * (2 * cc[3] + b) * h - 1
+        box[("K", b)] = (klo - lat["padk"], klo + 2 * h + lat["padk"])
+        box[("F", b)] = (0.5 + (2 * cc[4] + b) * h, 0.5 + (2 * cc[4] + b + 1) * h)
+    return box, h
+
+
+def _on(x, s):
+    v = x / s
+    assert v == round(v), (x, s)
+    return x
+
+
+def _adversarial5(kind, rng):
+    from fractions import Fraction
+    lat = _lattice5()
+    sW, sW3, sXi, sEta = lat["sW"], lat["sW3"], lat["sXi"], lat["sEta"]
+    box, h = _boxes5(lat)
+    rows = []
+    # legs 3q, 4q and hypotenuse 5q (q a power of two in units of sW): exact
+    # distances; (3q + 4, 4q - 3) is the same distance plus 25 sW^2
+    q = 2.0 ** math.ceil(math.log2(h / (3 * sW)))
+    for bx in (0, 1):
+        for by in (0, 1):
+            Xlo, Xhi = box[("X", bx)]
+            Ylo, Yhi = box[("Y", by)]
+            if kind in ("zlo", "zhi"):
+                far = kind == "zlo"
+                for bf in (0, 1):
+                    Fl, Fh = box[("F", bf)]
+                    F = Fh if far else Fl  # the slope's f end on this side
+                    for bz in (0, 1):
+                        ZL, ZH = box[("Z", bz)]
+                        for sgn in (1.0, -1.0):
+                            for dxy in ((0, 0), (4, -3), (-3, 4)):
+                                d1, d2 = 3 * q * sW + dxy[0] * sW, 4 * q * sW + dxy[1] * sW
+                                W1 = (Xlo if far else Xhi) + d1
+                                W2 = (Ylo if far else Yhi) + d2
+                                eta = _on(0.5, sEta)
+                                T = _on(eta * F * 5 * q * sW, sW3)  # |eta| f r on the z lattice: a tie
+                                for dz in (-1, 0, 1):
+                                    if sgn > 0:
+                                        W3 = (ZH + T if far else ZL + T) + dz * sW3
+                                    else:
+                                        W3 = (ZL - T if far else ZH - T) + dz * sW3
+                                    xi = sXi * int(rng.integers(-64, 65))
+                                    rows.append((W1, W2, W3, xi, sgn * eta))
+            if kind == "guard":
+                for d in (-2, -1, 0, 1, 2):
+                    for bz in (0, 1):
+                        ZL, ZH = box[("Z", bz)]
+                        rows.append((Xhi + lat["Rg"] + d * sW, (Ylo + Yhi) / 2, (ZL + ZH) / 2, 0.0, 0.0))
+            if kind in ("c1", "c2", "c3", "c4"):
+                # V (sector 0) in the open first quadrant: start corner a = (x1, y0), end corner
+                # b = (x0, y1); the edge direction (1 - L t, L + t) with t = xi f
+                for bk in (0, 1):
+                    Llo, Lhi = box[("K", bk)]
+                    L = Llo if kind in ("c1", "c3") else Lhi
+                    for j in (11, 13, 17):
+                        x0 = j * (sW / sXi)
+                        for d in (-2, -1, 0, 1, 2):
+                            W1 = Xhi + x0
+                            W2 = (Yhi + L * (x0 + h)) if kind in ("c1", "c2") else (Ylo + L * x0)
+                            W2 = _on(W2, sW) + d * sW
+                            if W1 > 1.0 or W2 > 1.0 or W2 - Yhi <= 0:
+                                continue
+                            for bz in (0, 1):
+                                ZL, ZH = box[("Z", bz)]
+                                rows.append((W1, W2, (ZL + ZH) / 2, 0.0, 0.0))
+                                # a general xi: the edge of each f half, nearest lattice point
+                                xi = sXi * int(rng.integers(-400, 401))
+                                for bf in (0, 1):
+                                    Fl, Fh = box[("F", bf)]
+                                    tl, th = sorted((xi * Fl, xi * Fh))
+                                    t = Fraction(tl if kind in ("c1", "c3") else th)
+                                    k = Fraction(L)
+                                    num, den = k + t, 1 - k * t
+                                    if kind in ("c1", "c2"):
+                                        W2b = Yhi + float(Fraction(x0 + h) * num / den)
+                                    else:
+                                        W2b = Ylo + float(Fraction(x0) * num / den)
+                                    W2b = round(W2b / sW) * sW + d * sW
+                                    if 0.0 < W2b - Yhi and W2b <= 1.0:
+                                        rows.append((W1, W2b, (ZL + ZH) / 2, xi, 0.0))
+    A = np.array(rows, dtype=np.float64)
+    for col, s in zip(range(5), (sW, sW, sW3, sXi, sEta)):
+        assert np.all(A[:, col] / s == np.round(A[:, col] / s)), kind
+    assert np.all(np.abs(A[:, 4]) <= 1.0) and np.all((A[:, :2] >= 0) & (A[:, :2] <= 1))
+    return A
+
+
+@pytest.mark.parametrize("kind", ["zlo", "zhi", "guard", "c1", "c2", "c3", "c4"])
+def test_binary32_filter_at_the_thresholds(ctx, kind):
+    rng = np.random.default_rng(11)
+    A = _adversarial5(kind, rng)
+    g = _problem5(A[:, :3], A[:, 3], A[:, 4])
+    pr = OP(g)
+    # the anchors fix the lattice; the surfaces are exactly where they were placed
+    k0 = oracle.constants(OP(_problem5(np.zeros((0, 3)), np.zeros(0), np.zeros(0))))
+    assert oracle.constants(pr)["steps"] == k0["steps"]
+    t, f, _ = oracle.parametrize(pr, root_canon=True)
+    assert np.array_equal(t[2:, 0], A[:, 0]) and np.array_equal(t[2:, 1], A[:, 1])
+    assert np.array_equal(f[2:, 0], A[:, 2]) and np.array_equal(t[2:, 2], A[:, 3])
+    assert np.array_equal(t[2:, 3], A[:, 4])
+    m, sec, cc = CELL5
+    _say("filter5", kind, len(A), "surfaces")
+    mo = oracle.cell_masks(pr, m, sec, cc)
+    m64, _, r64 = ctx.incidence(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], m, sec, cc, precision=0)
+    m32, tests, r32 = ctx.incidence(g["family"], g["cols"], g["lo"], g["hi"], g["eps"], m, sec, cc, precision=1)
+    _say("  rechecks", r32, "of", tests, "tests")
+    assert r64 == 0
+    assert np.array_equal(m64, mo)
+    assert np.array_equal(m32, mo)
+    assert r32 > 0
+    assert np.any(mo != 0) and np.any(mo != 0xFFFFFFFF)
+    ro = oracle.solve(pr)
+    for prec in (0, 1):
+        check_same(solve(ctx, g, precision=prec), ro)
+
+
+def test_filter_rechecks_on_the_workload(ctx):
+    """The filter leaves decisions to binary64 on the ordinary workload too,
+    and both precisions give the same result."""
+    g = synth.config("pose5dof_small")
+    r1 = solve(ctx, g, precision=1)
+    r0 = solve(ctx, g, precision=0)
+    _say("rechecks", r1["stats"]["fp64_rechecks"], "of", r1["stats"]["tests"])
+    assert r1["stats"]["fp64_rechecks"] > 0 and r0["stats"]["fp64_rechecks"] == 0
+    check_same(r1, r0)
+    # f reaching below 2^-10: outside the filter's range, binary64 throughout
+    g2 = dict(g, lo=list(g["lo"]))
+    g2["lo"][4] = 2.0 ** -12
+    r1 = solve(ctx, g2, precision=1)
+    assert r1["stats"]["fp64_rechecks"] == 0
+    check_same(r1, solve(ctx, g2, precision=0))
