@@ -502,7 +502,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": ("int32" if g["family"] not in ("pose4dof", "pose5dof")
-                  else ("f32+f64" if args.precision and g["family"] == "pose4dof" else "f64")),
+                  else ("f32+f64" if args.precision else "f64")),
         "data": "synthetic",
         "config": {"workload": args.workload, "description": W["desc"], "n": n, "eps": g["eps"],
                    "canon_c": 1.0, "precision": "fp32_filter" if args.precision else "fp64_plain"},
