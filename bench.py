@@ -532,7 +532,7 @@ def main():
             "description": WORKLOADS["pose5dof_20k"]["desc"], "tests_per_s": p5["tests_per_s"],
             "ms_per_solve": p5["ms_per_solve"], "solves_per_s": p5["solves_per_s"],
             "tests_per_solve": p5["tests_per_solve"], "count": p5["count"], "roofline": p5["roofline"],
-            "golden": p5["golden"], "refine": p5["refine"]}
+            "rechecks_per_solve": p5["rechecks_per_solve"], "golden": p5["golden"], "refine": p5["refine"]}
         if p5["golden"] is not None:
             ok = ok and p5["golden"]["matches"]
     # (the serving leg gets a context of its own, after this one has released
