@@ -198,12 +198,14 @@ static ScratchSlot g_scratch[kMaxDevices];
 
 // Candidate grids of the item-looping kernels, in blocks of four waves per
 // CU.  A slot tries them in turn on its large launches and keeps the one with
-// the lowest event time per byte (the entry bytes the launch reads or
+// the lowest median event time per byte (the entry bytes the launch reads or
 // writes, so levels with different entry sizes compare) once each has
-// kTuneSamples samples.
+// kTuneSamples samples.  The median of 8: with the mean over 4, the levels
+// that happened to fall to a candidate decided its figure (compaction at 4
+// blocks per CU read 0.32 or 0.53 ps/byte in two runs of the same solve).
 constexpr int kTuneCand[] = {2, 4, 8, 16, 32};
 constexpr int kNCand = 5;
-constexpr int kTuneSamples = 4;
+constexpr int kTuneSamples = 8;
 constexpr uint64_t kTuneMinBytes = 256ull << 20;  // smaller launches use the default shape
 constexpr int kLastFam = GV_POSE5DOF;               // family codes run 1..kLastFam
 constexpr int kGridDefault = 8;
@@ -211,6 +213,7 @@ struct gvi_tune_slot {
   int chosen = 0;  // blocks per CU once chosen
   int next = 0;    // next candidate to try
   double ms[kNCand] = {}, units[kNCand] = {};
+  double r[kNCand][kTuneSamples] = {};  // per-sample event time per byte
   int n[kNCand] = {};
 };
 
@@ -608,7 +611,7 @@ struct Run {
   size_t ent_bytes = 0;
   uint64_t chunk_bytes = 0;               // device bytes one materialized chunk may need
   uint64_t first_cells = 262144;          // cells in the first chunk of every expansion
-  uint64_t dive_cells = 16384;            // cells from which the diversified dive goes greedy
+  uint64_t dive_cells = 4096;             // cells from which the diversified dive goes greedy
   bool root_dive = false;                 // greedy dive from the root cells first (the diversified dive subsumes it)
   int grid_env[2] = {0, 0};               // GV_GRID_COUNT / GV_GRID_COMPACT: fixed blocks per CU (experiments)
   uint64_t waits = 0;                     // host waits for the stream, and their time
@@ -843,18 +846,26 @@ void tune_sample(Run& X, int kind, int cand, double ms, uint64_t units) {
   std::lock_guard<std::mutex> g(c->tmu);
   gvi_tune_slot& t = c->tune[X.P0.fam][kind];
   if (t.chosen) return;
+  if (t.n[cand] >= kTuneSamples) return;
   t.ms[cand] += ms;
   t.units[cand] += (double)units;
-  t.n[cand]++;
+  t.r[cand][t.n[cand]++] = ms / std::max(1.0, (double)units);
   for (int k = 0; k < kNCand; k++)
     if (t.n[k] < kTuneSamples) return;
+  double med[kNCand];
+  for (int k = 0; k < kNCand; k++) {
+    double v[kTuneSamples];
+    std::copy(t.r[k], t.r[k] + kTuneSamples, v);
+    std::sort(v, v + kTuneSamples);
+    med[k] = 0.5 * (v[kTuneSamples / 2 - 1] + v[kTuneSamples / 2]);
+  }
   int best = 0;
   for (int k = 1; k < kNCand; k++)
-    if (t.ms[k] / t.units[k] < t.ms[best] / t.units[best]) best = k;
+    if (med[k] < med[best]) best = k;
   t.chosen = kTuneCand[best];
   if (X.trace) {
     std::fprintf(stderr, "gv: autotune family %d %s:", X.P0.fam, kind ? "compaction" : "count");
-    for (int k = 0; k < kNCand; k++) std::fprintf(stderr, " %d:%.3g", kTuneCand[k], t.ms[k] / t.units[k] * 1e9);
+    for (int k = 0; k < kNCand; k++) std::fprintf(stderr, " %d:%.3g", kTuneCand[k], med[k] * 1e9);
     std::fprintf(stderr, " ps/byte -> %d blocks per CU\n", t.chosen);
   }
   tune_save(c);
@@ -1629,10 +1640,17 @@ void epoch_begin(Run& X) {
   // quality on small ones; problems sharing an epoch each keep that width
   // (262144: the hardest problems of the 256-problem pose set find their
   // bound in the first chunk; 65536 left one solving 8x longer)
-  X.first_cells = 262144ull * (uint64_t)np;
-  if (const char* fc = std::getenv("GV_FIRST_CELLS")) X.first_cells = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
-  X.dive_cells = 16384ull * (uint64_t)np;
-  if (const char* dc = std::getenv("GV_DIVE_CELLS")) X.dive_cells = std::strtoull(dc, nullptr, 10);
+  // diversified dive: greedy from the first level holding 4096 cells per
+  // problem (16384 expanded the 32-child 5-DoF levels once more, to 131072
+  // cells, before going greedy: 2.2x the solve time on pose5dof_20k, the
+  // same bound; the 4-DoF and serving searches are unchanged, the plane
+  // search 3% faster; 1024 made the 256-problem pose set 2x slower)
+  // (GV_FIRST_CELLS, GV_DIVE_CELLS: per-problem values)
+  uint64_t fc1 = 262144, dc1 = 4096;
+  if (const char* fc = std::getenv("GV_FIRST_CELLS")) fc1 = std::max<uint64_t>(1, std::strtoull(fc, nullptr, 10));
+  if (const char* dc = std::getenv("GV_DIVE_CELLS")) dc1 = std::strtoull(dc, nullptr, 10);
+  X.first_cells = fc1 * (uint64_t)np;
+  X.dive_cells = dc1 * (uint64_t)np;
   if (const char* rd = std::getenv("GV_ROOT_DIVE")) X.root_dive = atoi(rd) != 0;
   HIPCHK(hipSetDevice(X.ctx->device));
   X.dP = dalloc<ProbC>(X, np);

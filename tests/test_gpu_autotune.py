@@ -85,7 +85,7 @@ def test_autotune_cache_and_results(tmp_path, name):
     with Env(GV_TUNE_MIN_BYTES=0):
         c = gvote.Context(0, autotune_cache=path)
         try:
-            for i in range(12):
+            for i in range(24):
                 _say("tune", name, i)
                 assert same(solve(c, g), r0)
                 kinds = {k for (_, _, f, k, _) in read_lines(path) if f == fam}
