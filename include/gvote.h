@@ -38,8 +38,10 @@
  *                                        reference focal length over the true
  *                                        one.  Box as POSE4DOF plus lo[4] <
  *                                        hi[4] with lo[4] > 0; eps[4] is the f
- *                                        tolerance.  Tested in binary64 in both
- *                                        precision modes.  GV_EINVAL unless
+ *                                        tolerance.  GV_FP32_FILTER applies
+ *                                        where f stays within [2^-10, 2^10]
+ *                                        and the lattice fits binary32, else
+ *                                        binary64 throughout.  GV_EINVAL unless
  *                                        2 atan(1 + 2 eps[3]) + atan(max|xi|
  *                                        hi[4]) < 3.1 (the directions one cell
  *                                        admits then span less than pi).
@@ -90,8 +92,10 @@ typedef enum { GV_LINE2D = 1, GV_PLANE3D = 2, GV_RAY3D = 3, GV_POSE4DOF = 4, GV_
 /* GV_FP64_PLAIN: every predicate decision in binary64.
  * GV_FP32_FILTER: binary32 evaluation with a certified forward-error bound;
  * only decisions inside the bound are re-evaluated in binary64, so every
- * decision (hence every count) equals the binary64 one.  For the linear
- * families both modes evaluate the same exact small-integer predicate. */
+ * decision (hence every count) equals the binary64 one (pose families, where
+ * the problem's lattice values fit binary32; else binary64 throughout).  For
+ * the linear families both modes evaluate the same exact small-integer
+ * predicate. */
 typedef enum { GV_FP64_PLAIN = 0, GV_FP32_FILTER = 1 } gv_precision;
 
 typedef struct gv_ctx gv_ctx;
