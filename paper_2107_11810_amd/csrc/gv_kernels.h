@@ -448,18 +448,44 @@ __device__ inline uint32_t pose_mask64(const ProbC& P, const LevelC& lv, const P
   return pose_children<4, ALL>(lv, nch, zbits, kbits);
 }
 
-// binary32 mask with binary64 recheck of undecided halves (the binary64
-// child boxes are built only when a recheck needs them)
+// One child half's bounds in binary64, computed as pose_level_boxes does
+// (bit-equal values): x, y by (bx, by), the z or kappa interval by bq.
+__device__ inline void pose_half_bounds(const ProbC& P, const LevelC& lv, const Cell& C, int m, int bx, int by,
+                                        int bq, bool kap, double& x0, double& x1, double& y0, double& y1,
+                                        double& qlo, double& qhi) {
+  const int m1 = m + 1;
+  const int32_t cx = lv.split[0] ? 2 * C.c[0] + bx : C.c[0];
+  const int32_t cy = lv.split[1] ? 2 * C.c[1] + by : C.c[1];
+  const double hx = ldexp(1.0, -min(m1, P.L[0])), hy = ldexp(1.0, -min(m1, P.L[1]));
+  x0 = (double)cx * hx;
+  x1 = (double)(cx + 1) * hx;
+  y0 = (double)cy * hy;
+  y1 = (double)(cy + 1) * hy;
+  if (kap) {
+    const int32_t ck = lv.split[3] ? 2 * C.c[3] + bq : C.c[3];
+    const double hk = ldexp(1.0, -min(m1, P.L[3]));
+    const double Klo = 2.0 * ((double)ck * hk) - 1.0, Khi = 2.0 * ((double)(ck + 1) * hk) - 1.0;
+    qlo = Klo - P.padk;
+    qhi = Khi + P.padk;
+  } else {
+    const int32_t cz = lv.split[2] ? 2 * C.c[2] + bq : C.c[2];
+    const double hz = ldexp(1.0, -min(m1, P.L[2]));
+    const double Zlo = (double)cz * hz, Zhi = (double)(cz + 1) * hz;
+    qlo = Zlo - P.padz;  // ZL
+    qhi = Zhi + P.padz;  // ZH
+  }
+}
+
+// binary32 mask; the undecided halves (bit index xy | b << 2 of zund /
+// kund) are then recomputed in binary64 one at a time, from the entry's
+// binary64 root values and the child's bounds
 template <bool ALL, typename EQ>
 __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const Cell& C, int m, const float* Bf,
                                        int sector, const EQ& e, const double* __restrict__ m64,
                                        uint64_t n_root, uint32_t& nrecheck) {
   const uint32_t nch = ALL ? 16u : 1u << lv.abits;
-  PoseLevel B;
-  uint32_t zbits = 0, kbits = 0;
+  uint32_t zbits = 0, kbits = 0, zund = 0, kund = 0;
   // Bf layout: Xlo[2] Xhi[2] Ylo[2] Yhi[2] ZH[2] ZL[2] Llo[2] Lhi[2]
-  bool have64 = false;
-  double W1 = 0, W2 = 0, W3 = 0, xi = 0, eta = 0;
   // terms shared by the four (x, y) parts
   const ZPre<float> zp[2] = {zpre<float>(e.W3, e.eta, Bf[8], Bf[10]), zpre<float>(e.W3, e.eta, Bf[9], Bf[11])};
   const KEdge<float> ke[2] = {kedge<float>(e.xi, Bf[12], Bf[14]), kedge<float>(e.xi, Bf[13], Bf[15])};
@@ -471,41 +497,47 @@ __device__ inline uint32_t pose_mask32(const ProbC& P, const LevelC& lv, const C
     if (!ALL && ((bx && !lv.split[0]) || (by && !lv.split[1]))) continue;
     VBox<float> v = pose_vbox<float>(e.W1, e.W2, Bf[0 + bx], Bf[2 + bx], Bf[4 + by], Bf[6 + by], sector);
     float rmin2 = rmin2_of(v), rmax2 = rmax2_of(v);
-    bool zp_[2] = {false, false}, zu[2] = {false, false}, kp[2] = {false, false}, ku[2] = {false, false};
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       if (!ALL && b && !lv.split[2]) continue;
-      zp_[b] = zhalf32m(zp[b], rmin2, rmax2, zu[b]);
+      bool u;
+      const uint32_t bit = 1u << (xy | (b << 2));
+      if (zhalf32m(zp[b], rmin2, rmax2, u)) zbits |= bit;
+      if (u) zund |= bit;
     }
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       if (!ALL && b && !lv.split[3]) continue;
-      kp[b] = khalf32m(v, rmin2, P.Rg2f, ke[b], kSl[b], kSh[b], ku[b]);
+      bool u;
+      const uint32_t bit = 1u << (xy | (b << 2));
+      if (khalf32m(v, rmin2, P.Rg2f, ke[b], kSl[b], kSh[b], u)) kbits |= bit;
+      if (u) kund |= bit;
     }
-    bool need = zu[0] || zu[1] || ku[0] || ku[1];
-    if (need) {
-      if (!have64) {
-        const uint64_t r = e.ridx;
-        W1 = m64[r];
-        W2 = m64[n_root + r];
-        W3 = m64[2 * n_root + r];
-        xi = m64[3 * n_root + r];
-        eta = m64[4 * n_root + r];
-        pose_level_boxes(P, lv, C, m, B);
-        have64 = true;
-      }
-      VBox<double> vd = pose_vbox<double>(W1, W2, B.Xlo[bx], B.Xhi[bx], B.Ylo[by], B.Yhi[by], sector);
-      double rmin2d = rmin2_of(vd), rmax2d = rmax2_of(vd);
-#pragma unroll
-      for (int b = 0; b < 2; b++) {
-        if (zu[b]) { zp_[b] = zhalf64(W3, eta, rmin2d, rmax2d, B.ZH[b], B.ZL[b]); nrecheck++; }
-        if (ku[b]) { kp[b] = khalf64(vd, rmin2d, P.Rg2, xi, B.Llo[b], B.Lhi[b]); nrecheck++; }
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < 2; b++) {
-      if (zp_[b]) zbits |= 1u << (xy | (b << 2));
-      if (kp[b]) kbits |= 1u << (xy | (b << 2));
+  }
+  if (zund | kund) {
+    const uint64_t r = e.ridx;
+    const double W1 = m64[r], W2 = m64[n_root + r], W3 = m64[2 * n_root + r], xi = m64[3 * n_root + r],
+                 eta = m64[4 * n_root + r];
+    uint32_t und = zund | (kund << 8);
+#pragma unroll 1
+    while (und) {
+      const uint32_t j = (uint32_t)__builtin_ctz(und);
+      und &= und - 1u;
+      const bool kap = j >= 8;
+      const uint32_t i = j & 7u;
+      double x0, x1, y0, y1, qlo, qhi;
+      pose_half_bounds(P, lv, C, m, (int)(i & 1u), (int)((i >> 1) & 1u), (int)((i >> 2) & 1u), kap, x0, x1, y0,
+                       y1, qlo, qhi);
+      const VBox<double> vd = pose_vbox<double>(W1, W2, x0, x1, y0, y1, sector);
+      const double rmin2d = rmin2_of(vd);
+      const bool pass = kap ? khalf64(vd, rmin2d, P.Rg2, xi, qlo, qhi)
+                            : zhalf64(W3, eta, rmin2d, rmax2_of(vd), qhi, qlo);
+      const uint32_t bm = 1u << i;
+      if (kap)
+        kbits = pass ? (kbits | bm) : (kbits & ~bm);
+      else
+        zbits = pass ? (zbits | bm) : (zbits & ~bm);
+      nrecheck++;
     }
   }
   return pose_children<4, ALL>(lv, nch, zbits, kbits);
