@@ -217,10 +217,13 @@ __device__ inline uint32_t pose5_mask32(const ProbC& P, const LevelC& lv, const 
   uint32_t zbits = 0, kbits = 0, zund = 0, kund = 0;
   const ZPre<float> zp[2] = {zpre<float>(e.W3, e.eta, Bf[8], Bf[10]), zpre<float>(e.W3, e.eta, Bf[9], Bf[11])};
   const float a = fabsf(e.eta), axi = fabsf(e.xi);
-#pragma unroll
+  // the two halves of the f interval in turn (not unrolled: both halves'
+  // terms live at once took 156 registers, 142 this way); bounds picked by
+  // selects
+#pragma unroll 1
   for (int bf = 0; bf < 2; bf++) {
     if (!ALL && bf && !lv.split[4]) continue;
-    const float Fl = Bf[16 + bf], Fh = Bf[18 + bf];
+    const float Fl = bf ? Bf[17] : Bf[16], Fh = bf ? Bf[19] : Bf[18];
     const float ah = a * Fh, al = a * Fl;
     const float ah2 = ah * ah, al2 = al * al;
     const KEdge<float> ke[2] = {kedge5<float>(e.xi, Bf[12], Bf[14], Fl, Fh), kedge5<float>(e.xi, Bf[13], Bf[15], Fl, Fh)};
@@ -314,8 +317,13 @@ __device__ inline uint32_t pose5_mask_of(const ProbC& P, const LevelC& lv, const
 static_assert(GV_ITEM / 64 <= 255 && 64 * (GV_ITEM / 64) <= 65535, "per-lane byte counters, 16-bit wave sums");
 // E: EntQ64 (binary64 lists) or EntQ32 / EntQ24 (binary32 filter; m64 holds
 // the binary64 root values for the recheck, n_root their column stride).
+// binary32 lists at 4 waves per SIMD (128 registers, 36 B per lane spilled):
+// 1.94-1.96 against 2.02-2.05 ms of count kernel per pose5dof_20k solve at
+// the 3 waves of its unconstrained 142 registers; binary64 lists keep theirs
+// (capping them spilled 224-448 B per lane and ran slower)
+template <typename E> constexpr int pose5_min_blocks() { return std::is_same<E, EntQ64>::value ? 1 : 4; }
 template <typename E, bool UNIT, bool ALL>
-__global__ void __launch_bounds__(256) k_count_pose5(const ProbC* __restrict__ Ptab, int m, LevelC lv,
+__global__ void __launch_bounds__(256, pose5_min_blocks<E>()) k_count_pose5(const ProbC* __restrict__ Ptab, int m, LevelC lv,
                                                      const Cell* __restrict__ cells, const Item* __restrict__ items,
                                                      const uint32_t* __restrict__ nitems_p, const E* __restrict__ ents,
                                                      const double* __restrict__ m64, uint64_t n_root,
