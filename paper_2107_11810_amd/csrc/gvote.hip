@@ -212,7 +212,6 @@ constexpr int kGridDefault = 8;
 struct gvi_tune_slot {
   int chosen = 0;  // blocks per CU once chosen
   int next = 0;    // next candidate to try
-  double ms[kNCand] = {}, units[kNCand] = {};
   double r[kNCand][kTuneSamples] = {};  // per-sample event time per byte
   int n[kNCand] = {};
 };
@@ -847,8 +846,6 @@ void tune_sample(Run& X, int kind, int cand, double ms, uint64_t units) {
   gvi_tune_slot& t = c->tune[X.P0.fam][kind];
   if (t.chosen) return;
   if (t.n[cand] >= kTuneSamples) return;
-  t.ms[cand] += ms;
-  t.units[cand] += (double)units;
   t.r[cand][t.n[cand]++] = ms / std::max(1.0, (double)units);
   for (int k = 0; k < kNCand; k++)
     if (t.n[k] < kTuneSamples) return;
