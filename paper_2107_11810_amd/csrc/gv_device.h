@@ -20,7 +20,9 @@
 
 #define GV_MAXL 40
 #define GV_MAXD 5
-#define GV_ITEM 1024  // entries per work item (one wave)
+#define GV_ITEM 1024  // most entries per work item (one wave)
+#define GV_ITEM_LOG 10
+static_assert(GV_ITEM == 1 << GV_ITEM_LOG, "item size");
 
 enum { FAM_LINE2D = 1, FAM_PLANE3D = 2, FAM_RAY3D = 3, FAM_POSE4DOF = 4, FAM_SIM2D = 5, FAM_POSE5DOF = 6 };
 // Exact mode of a linear family (quantized once at the root to a fixed
@@ -76,8 +78,8 @@ struct Cell {
   uint32_t _pad;
 };
 
-// A work item: entries [off, off + cnt) of one cell's list, cnt <= GV_ITEM,
-// off - cell offset a multiple of GV_ITEM.
+// A work item: entries [off, off + cnt) of one cell's list; cnt <= 2^ilog
+// <= GV_ITEM, off - cell offset a multiple of 2^ilog (the batch's item size).
 struct Item {
   uint64_t off;
   uint32_t cell, cnt;

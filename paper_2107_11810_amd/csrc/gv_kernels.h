@@ -2,8 +2,8 @@
 //
 // Work decomposition: a batch holds cells of one level, each with a
 // contiguous list of canonical surfaces.  Lists are cut into items of at most
-// GV_ITEM entries that belong to a single cell; one wavefront processes one
-// item, so the cell's child boxes are wave-uniform (scalar registers) and the
+// 2^ilog <= GV_ITEM entries (the batch's item size) that belong to a single
+// cell; one wavefront processes one item, so the cell's child boxes are wave-uniform (scalar registers) and the
 // per-child counts reduce across the wave before a single atomic per child.
 #pragma once
 #include "gv_device.h"
@@ -26,21 +26,24 @@ __device__ inline uint32_t mbcnt64(uint64_t m) {
 }
 
 // ---------------------------------------------------------------------------
-// Items: per cell ceil(len / GV_ITEM) work items.
+// Items: per cell ceil(len / 2^ilog) work items of 2^ilog entries (the last
+// one ragged).
 // ---------------------------------------------------------------------------
-__global__ void k_item_counts(const Cell* __restrict__ cells, uint32_t ncell, uint32_t* __restrict__ nitem) {
+__device__ inline uint32_t items_of(uint32_t len, uint32_t ilog) { return (len + (1u << ilog) - 1u) >> ilog; }
+__global__ void k_item_counts(const Cell* __restrict__ cells, uint32_t ncell, uint32_t ilog,
+                              uint32_t* __restrict__ nitem) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < ncell) nitem[c] = (cells[c].len + GV_ITEM - 1) / GV_ITEM;
+  if (c < ncell) nitem[c] = items_of(cells[c].len, ilog);
 }
-__global__ void k_item_fill(const Cell* __restrict__ cells, uint32_t ncell, const uint32_t* __restrict__ nitem,
-                            const uint32_t* __restrict__ ioff, Item* __restrict__ items, uint32_t* __restrict__ total) {
+__global__ void k_item_fill(const Cell* __restrict__ cells, uint32_t ncell, uint32_t ilog,
+                            const uint32_t* __restrict__ nitem, const uint32_t* __restrict__ ioff,
+                            Item* __restrict__ items, uint32_t* __restrict__ total) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   uint32_t o = ioff[c], k = nitem[c];
   const uint64_t off = cells[c].off;
-  const uint32_t len = cells[c].len;
-  for (uint32_t j = 0; j < k; j++)
-    items[o + j] = Item{off + (uint64_t)j * GV_ITEM, c, min((uint32_t)GV_ITEM, len - j * (uint32_t)GV_ITEM)};
+  const uint32_t len = cells[c].len, isz = 1u << ilog;
+  for (uint32_t j = 0; j < k; j++) items[o + j] = Item{off + (uint64_t)j * isz, c, min(isz, len - j * isz)};
   if (c == ncell - 1) *total = o + k;
 }
 
@@ -105,8 +108,8 @@ __global__ void __launch_bounds__(1024) k_scan_small(const In* __restrict__ in, 
 // Work items of a batch of at most GV_SMALL_N cells: per-cell item counts,
 // their offsets and the items themselves, in one launch.
 __global__ void __launch_bounds__(1024) k_items_small(const Cell* __restrict__ cells, uint32_t ncell,
-                                                      uint32_t* __restrict__ ioff, Item* __restrict__ items,
-                                                      uint32_t* __restrict__ total) {
+                                                      uint32_t ilog, uint32_t* __restrict__ ioff,
+                                                      Item* __restrict__ items, uint32_t* __restrict__ total) {
   __shared__ uint32_t wsum[16];
   const uint32_t b = threadIdx.x * GV_SMALL_PER;
   uint64_t off[GV_SMALL_PER];
@@ -119,16 +122,15 @@ __global__ void __launch_bounds__(1024) k_items_small(const Cell* __restrict__ c
     len[j] = in ? cells[b + j].len : 0u;
   }
 #pragma unroll
-  for (int j = 0; j < GV_SMALL_PER; j++) s += (len[j] + GV_ITEM - 1) / GV_ITEM;
+  for (int j = 0; j < GV_SMALL_PER; j++) s += items_of(len[j], ilog);
   uint32_t tot;
   uint32_t o = block_excl<uint32_t>(s, wsum, tot);
 #pragma unroll
   for (int j = 0; j < GV_SMALL_PER; j++) {
     if (b + j >= ncell) break;
-    const uint32_t k = (len[j] + GV_ITEM - 1) / GV_ITEM;
+    const uint32_t k = items_of(len[j], ilog), isz = 1u << ilog;
     ioff[b + j] = o;
-    for (uint32_t i = 0; i < k; i++)
-      items[o + i] = Item{off[j] + (uint64_t)i * GV_ITEM, b + j, min((uint32_t)GV_ITEM, len[j] - i * (uint32_t)GV_ITEM)};
+    for (uint32_t i = 0; i < k; i++) items[o + i] = Item{off[j] + (uint64_t)i * isz, b + j, min(isz, len[j] - i * isz)};
     o += k;
   }
   if (threadIdx.x == 0) *total = tot;
@@ -336,15 +338,15 @@ __global__ void __launch_bounds__(256) k_count_lin(LevelC lv, const Item* __rest
 
 // Per (cell, child): the cell's count and entries from its items' rows, and
 // each item's offset inside the child's list (exclusive, within the cell).
-// A cell of length len owns ceil(len / GV_ITEM) items from ioff[cell].
+// A cell of length len owns ceil(len / 2^ilog) items from ioff[cell].
 template <int NCH, bool UNIT>
-__global__ void k_cell_scan(const Cell* __restrict__ cells, uint32_t ncell, const uint32_t* __restrict__ ioff,
+__global__ void k_cell_scan(const Cell* __restrict__ cells, uint32_t ncell, uint32_t ilog, const uint32_t* __restrict__ ioff,
                             const uint32_t* __restrict__ icnt, const uint32_t* __restrict__ iw,
                             uint64_t* __restrict__ itemoff, uint32_t* __restrict__ ccnt, uint32_t* __restrict__ cnent) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (uint64_t)ncell * NCH) return;
   const uint32_t c = (uint32_t)(t / NCH), ch = (uint32_t)(t % NCH);
-  const uint32_t i0 = ioff[c], ni = (cells[c].len + GV_ITEM - 1) / GV_ITEM;
+  const uint32_t i0 = ioff[c], ni = items_of(cells[c].len, ilog);
   uint64_t n = 0, w = 0;
   for (uint32_t i = i0; i < i0 + ni; i++) {
     const uint64_t k = (uint64_t)i * NCH + ch;

@@ -209,6 +209,16 @@ constexpr int kTuneSamples = 8;
 constexpr uint64_t kTuneMinBytes = 256ull << 20;  // smaller launches use the default shape
 constexpr int kLastFam = GV_POSE5DOF;               // family codes run 1..kLastFam
 constexpr int kGridDefault = 8;
+// Entries per work item of a 5-DoF batch: GV_ITEM, halved (down to 256)
+// while the batch would give fewer than 16 items per compute unit, so that
+// a small batch spreads over the chip instead of leaving a few waves 16
+// entries of 32 children each per lane (pose5dof_20k: count kernel 1.67-1.71
+// against 1.94-1.96 ms per solve, compaction 0.48 against 0.60).  The other
+// families keep GV_ITEM: smaller items gave nothing there or lost a little
+// (pose4dof_1m 61-62 against 60.6 ms, the 256-problem set 1.00-1.21 s
+// against 1.00 s for items down to 64 or 256 entries, 16 or 64 per CU).
+constexpr uint32_t kItemLogMin5 = 8;
+constexpr uint64_t kItemsPerCu5 = 16;
 struct gvi_tune_slot {
   int chosen = 0;  // blocks per CU once chosen
   int next = 0;    // next candidate to try
@@ -1001,19 +1011,22 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   pa->own_ents = own_ents;
   pa->unit = b.unit;
 
-  // work items: at most GV_ITEM entries of one cell each
+  // work items: at most 2^ilog <= GV_ITEM entries of one cell each
+  uint32_t ilog = GV_ITEM_LOG;
+  if constexpr (FAM == FAM_POSE5DOF)
+    while (ilog > kItemLogMin5 && (b.nent >> ilog) < (uint64_t)X.ctx->n_cu * kItemsPerCu5) ilog--;
   uint32_t* nitem = b.ncell <= GV_SMALL_N ? nullptr : dalloc<uint32_t>(X, b.ncell);
   pa->ioff = dalloc<uint32_t>(X, b.ncell);
-  pa->max_items = b.ncell + b.nent / GV_ITEM + 1;
+  pa->max_items = b.ncell + (b.nent >> ilog) + 1;
   pa->items = dalloc<Item>(X, pa->max_items);
   pa->nitems = dalloc<uint32_t>(X, 1);
   if (b.ncell <= GV_SMALL_N) {
-    k_items_small<<<1, 1024, 0, X.st>>>(b.cells, b.ncell, pa->ioff, pa->items, pa->nitems);
+    k_items_small<<<1, 1024, 0, X.st>>>(b.cells, b.ncell, ilog, pa->ioff, pa->items, pa->nitems);
   } else {
     HIPCHK(hipMemsetAsync(pa->nitems, 0, sizeof(uint32_t), X.st));
-    k_item_counts<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem);
+    k_item_counts<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, ilog, nitem);
     excl_scan(X, nitem, pa->ioff, b.ncell);
-    k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, nitem, pa->ioff, pa->items, pa->nitems);
+    k_item_fill<<<nblk(b.ncell), 256, 0, X.st>>>(b.cells, b.ncell, ilog, nitem, pa->ioff, pa->items, pa->nitems);
   }
   dfree(X, nitem);
   pa->istride = (uint32_t)pa->max_items;
@@ -1111,7 +1124,7 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     // per-cell counts and per-item offsets from the items' rows
     if (!leaf) pa->itemoff = dalloc<uint64_t>(X, (uint64_t)nch * pa->max_items);
 #define GV_CELL_SCAN(U, N)                                                                                      \
-  k_cell_scan<N, U><<<nblk((uint64_t)b.ncell * N), 256, 0, X.st>>>(b.cells, b.ncell, pa->ioff, itemcnt, itemw,  \
+  k_cell_scan<N, U><<<nblk((uint64_t)b.ncell * N), 256, 0, X.st>>>(b.cells, b.ncell, ilog, pa->ioff, itemcnt, itemw, \
                                                                    pa->itemoff, ccnt, pa->cnent)
     switch ((b.unit ? 32 : 0) | nch) {
       case 32 | 2: GV_CELL_SCAN(true, 2); break;
