@@ -1,4 +1,4 @@
-// gv_subtree.h -- device-side search of small subtrees (4-DoF pose).
+// gv_subtree.h -- device-side search of small subtrees (pose families).
 //
 // A persistent kernel over a work queue of (problem, cell) items: every cell
 // of a batch whose list is at most GV_SUB_T entries is taken by one
@@ -14,48 +14,86 @@
 // the pruning bound changes the maximum.
 #pragma once
 #include "gv_kernels.h"
+#include "gv_pose5.h"
 
 #define GV_SUB_T 2048   // longest list a workgroup takes
 #define GV_SUB_WG 256
 
-template <typename E>
-__device__ inline uint32_t sub_mask(const ProbC& P, const LevelC& lv, const Cell& C, int m, const PoseLevel& B,
-                                    const float* Bf, const E& e, const double* __restrict__ m64, uint64_t n_root,
-                                    uint32_t& nre) {
-  if constexpr (sizeof(E) == sizeof(EntQ64)) {
-    return lv.abits == 4 ? pose_mask64<true>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta)
-                         : pose_mask64<false>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
-  } else {
-    return lv.abits == 4 ? pose_mask32<true>(P, lv, C, m, Bf, (int)C.sector, e, m64, n_root, nre)
-                         : pose_mask32<false>(P, lv, C, m, Bf, (int)C.sector, e, m64, n_root, nre);
+// a pose family's cell constants and masks: 16 children and 16-bit masks
+// (4-DoF) or 32 and 32-bit (5-DoF)
+template <int FAM> struct SubFam;
+template <> struct SubFam<FAM_POSE4DOF> {
+  static constexpr int NCH = 16, NBF = 16;
+  using M = uint16_t;
+  using Boxes = PoseLevel;
+  __device__ static void boxes(const ProbC& P, const LevelC& lv, const Cell& C, int m, Boxes& B, float* Bf) {
+    pose_level_boxes(P, lv, C, m, B);
+    for (int b = 0; b < 2; b++) {
+      Bf[0 + b] = (float)B.Xlo[b]; Bf[2 + b] = (float)B.Xhi[b];
+      Bf[4 + b] = (float)B.Ylo[b]; Bf[6 + b] = (float)B.Yhi[b];
+      Bf[8 + b] = (float)B.ZH[b];  Bf[10 + b] = (float)B.ZL[b];
+      Bf[12 + b] = (float)B.Llo[b]; Bf[14 + b] = (float)B.Lhi[b];
+    }
   }
-}
+  template <typename E>
+  __device__ static uint32_t mask(const ProbC& P, const LevelC& lv, const Cell& C, int m, const Boxes& B,
+                                  const float* Bf, const E& e, const double* __restrict__ m64, uint64_t n_root,
+                                  uint32_t& nre) {
+    if constexpr (sizeof(E) == sizeof(EntQ64)) {
+      return lv.abits == 4 ? pose_mask64<true>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta)
+                           : pose_mask64<false>(P, lv, B, (int)C.sector, e.W1, e.W2, e.W3, e.xi, e.eta);
+    } else {
+      return lv.abits == 4 ? pose_mask32<true>(P, lv, C, m, Bf, (int)C.sector, e, m64, n_root, nre)
+                           : pose_mask32<false>(P, lv, C, m, Bf, (int)C.sector, e, m64, n_root, nre);
+    }
+  }
+};
+template <> struct SubFam<FAM_POSE5DOF> {
+  static constexpr int NCH = 32, NBF = GV_P5_NBF;
+  using M = uint32_t;
+  using Boxes = Pose5Level;
+  __device__ static void boxes(const ProbC& P, const LevelC& lv, const Cell& C, int m, Boxes& B, float* Bf) {
+    pose5_level_boxes(P, lv, C, m, B);
+    pose5_boxes32(B, Bf);
+  }
+  template <typename E>
+  __device__ static uint32_t mask(const ProbC& P, const LevelC& lv, const Cell& C, int m, const Boxes& B,
+                                  const float* Bf, const E& e, const double* __restrict__ m64, uint64_t n_root,
+                                  uint32_t& nre) {
+    if (lv.abits == 5) return pose5_mask_of<true>(P, lv, C, m, B, Bf, e, m64, n_root, nre);
+    return pose5_mask_of<false>(P, lv, C, m, B, Bf, e, m64, n_root, nre);
+  }
+};
 
+template <int NCH>
 struct SubFrame {
   Cell c;
   int32_t level, nkept, next, _;
-  uint32_t cnt[16], nent[16];
-  uint8_t order[16];
+  uint32_t cnt[NCH], nent[NCH];
+  uint8_t order[NCH];
 };
 
 // fbuf: per workgroup (nframes - 1) * GV_SUB_T entries (the lists of frames
 // 1..); mbuf: per workgroup nframes * GV_SUB_T pass masks.  nover[0] counts
 // the cells written back to over[], nover[1] their entries.
-template <typename E>
+template <int FAM, typename E>
 __global__ void __launch_bounds__(GV_SUB_WG) k_subtree_pose(
     const ProbC* __restrict__ Ptab, int m0, const Cell* __restrict__ cells, uint32_t ncell,
     const E* __restrict__ ents, const double* __restrict__ m64, uint64_t n_root, unsigned long long* best,
     unsigned long long* __restrict__ rechecks, unsigned long long* __restrict__ tests,
     uint32_t* __restrict__ next_cell, Cell* __restrict__ over, uint32_t* __restrict__ nover,
-    E* __restrict__ fbuf, uint16_t* __restrict__ mbuf, int nframes) {
-  __shared__ SubFrame fr[GV_MAXL + 1];
-  __shared__ uint32_t wcnt[GV_SUB_WG / 64][16], wnent[GV_SUB_WG / 64][16];
+    E* __restrict__ fbuf, typename SubFam<FAM>::M* __restrict__ mbuf, int nframes) {
+  using F = SubFam<FAM>;
+  using M = typename F::M;
+  constexpr int NCH = F::NCH;
+  __shared__ SubFrame<NCH> fr[GV_MAXL + 1];
+  __shared__ uint32_t wcnt[GV_SUB_WG / 64][NCH], wnent[GV_SUB_WG / 64][NCH];
   __shared__ uint32_t wtot[GV_SUB_WG / 64];
   __shared__ uint32_t s_item;
   __shared__ int s_skip;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
   E* const myf = fbuf + (uint64_t)blockIdx.x * (uint64_t)(nframes - 1) * GV_SUB_T;
-  uint16_t* const mym = mbuf + (uint64_t)blockIdx.x * (uint64_t)nframes * GV_SUB_T;
+  M* const mym = mbuf + (uint64_t)blockIdx.x * (uint64_t)nframes * GV_SUB_T;
   uint64_t ntests = 0;
   uint32_t nre = 0;
   for (;;) {
@@ -89,22 +127,16 @@ __global__ void __launch_bounds__(GV_SUB_WG) k_subtree_pose(
         const uint32_t nch = 1u << lv.abits;
         const uint32_t len = C.len;
         const E* list = d == 0 ? ents + C.off : myf + (uint64_t)(d - 1) * GV_SUB_T;
-        uint16_t* masks = mym + (uint64_t)d * GV_SUB_T;
-        if (tid < 16) {
+        M* masks = mym + (uint64_t)d * GV_SUB_T;
+        if (tid < NCH) {
           for (uint32_t w = 0; w < GV_SUB_WG / 64; w++) {
             wcnt[w][tid] = 0;
             wnent[w][tid] = 0;
           }
         }
-        PoseLevel B;
-        pose_level_boxes(P, lv, C, l, B);
-        float Bf[16];
-        for (int b = 0; b < 2; b++) {
-          Bf[0 + b] = (float)B.Xlo[b]; Bf[2 + b] = (float)B.Xhi[b];
-          Bf[4 + b] = (float)B.Ylo[b]; Bf[6 + b] = (float)B.Yhi[b];
-          Bf[8 + b] = (float)B.ZH[b];  Bf[10 + b] = (float)B.ZL[b];
-          Bf[12 + b] = (float)B.Llo[b]; Bf[14 + b] = (float)B.Lhi[b];
-        }
+        typename F::Boxes B;
+        float Bf[F::NBF];
+        F::boxes(P, lv, C, l, B, Bf);
         __syncthreads();
         for (uint32_t base = 0; base < len; base += GV_SUB_WG) {
           const uint32_t j = base + tid;
@@ -112,11 +144,11 @@ __global__ void __launch_bounds__(GV_SUB_WG) k_subtree_pose(
           if (j < len) {
             const E e = list[j];
             w = pose_w(e);
-            mask = sub_mask<E>(P, lv, C, l, B, Bf, e, m64, n_root, nre);
-            masks[j] = (uint16_t)mask;
+            mask = F::template mask<E>(P, lv, C, l, B, Bf, e, m64, n_root, nre);
+            masks[j] = (M)mask;
           }
 #pragma unroll
-          for (int ch = 0; ch < 16; ch++) {
+          for (int ch = 0; ch < NCH; ch++) {
             const bool p = (mask >> ch) & 1u;
             const uint32_t n = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
             uint32_t s = n;  // unit entries: the count is the number of survivors
@@ -198,7 +230,7 @@ __global__ void __launch_bounds__(GV_SUB_WG) k_subtree_pose(
       const uint32_t ch = (uint32_t)(-1 - sk);
       const uint32_t len = fr[d].c.len;
       const E* src = d == 0 ? ents + fr[d].c.off : myf + (uint64_t)(d - 1) * GV_SUB_T;
-      const uint16_t* masks = mym + (uint64_t)d * GV_SUB_T;
+      const M* masks = mym + (uint64_t)d * GV_SUB_T;
       E* dst = myf + (uint64_t)d * GV_SUB_T;
       uint32_t run = 0;
       for (uint32_t base = 0; base < len; base += GV_SUB_WG) {

@@ -1840,22 +1840,24 @@ void start_search(Run& X) {
 // Device search of a batch's small cells (k_subtree_pose); cells with longer
 // lists come back as a batch of the same list buffer for the host-driven
 // path.
-template <typename E>
+template <int FAM, typename E>
 void run_subtree(Run& X, Batch& b) {
+  using M = typename SubFam<FAM>::M;
   const int nframes = X.P0.Lstar - b.level;
   // workgroups: up to four per CU, their frame buffers within an eighth of
   // the epoch's memory budget
-  const uint64_t per_wg = (uint64_t)(nframes - 1) * GV_SUB_T * sizeof(E) + (uint64_t)nframes * GV_SUB_T * 2;
+  const uint64_t per_wg =
+      (uint64_t)(nframes - 1) * GV_SUB_T * sizeof(E) + (uint64_t)nframes * GV_SUB_T * sizeof(M);
   const uint64_t fit = std::max<uint64_t>(1, X.budget / 8 / per_wg);
   const uint32_t G = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(b.ncell, (uint64_t)X.ctx->n_cu * 4u), fit);
   E* fbuf = dalloc<E>(X, (uint64_t)G * (uint64_t)(nframes - 1) * GV_SUB_T);
-  uint16_t* mbuf = dalloc<uint16_t>(X, (uint64_t)G * (uint64_t)nframes * GV_SUB_T);
+  M* mbuf = dalloc<M>(X, (uint64_t)G * (uint64_t)nframes * GV_SUB_T);
   Cell* over = dalloc<Cell>(X, b.ncell);
   uint32_t* ctr = dalloc<uint32_t>(X, 3);
   HIPCHK(hipMemsetAsync(ctr, 0, 3 * sizeof(uint32_t), X.st));
-  k_subtree_pose<E><<<G, GV_SUB_WG, 0, X.st>>>(X.dP, b.level, b.cells, b.ncell, (const E*)b.ents, X.m64, X.Ntot,
-                                                X.dbest, X.drecheck, X.dtests, ctr, over, ctr + 1, fbuf, mbuf,
-                                                nframes);
+  k_subtree_pose<FAM, E><<<G, GV_SUB_WG, 0, X.st>>>(X.dP, b.level, b.cells, b.ncell, (const E*)b.ents, X.m64,
+                                                     X.Ntot, X.dbest, X.drecheck, X.dtests, ctr, over, ctr + 1, fbuf,
+                                                     mbuf, nframes);
   HIPCHK(hipGetLastError());
   uint32_t back[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(back, ctr + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, X.st));
@@ -1884,17 +1886,17 @@ void run_subtree(Run& X, Batch& b) {
 
 template <int FAM, typename E>
 bool subtree_at(Run& X, Batch& b) {
-  if constexpr (FAM != FAM_POSE4DOF) {
+  if constexpr (!fam_pose(FAM)) {
     return false;
   } else {
     if (!X.subtree || X.report || b.level < X.subtree_from || b.level + 1 >= X.P0.Lstar) return false;
     if constexpr (std::is_same<E, EntQ32>::value) {
       if (b.unit && b.level >= 1 && X.q24) {
-        run_subtree<EntQ24>(X, b);
+        run_subtree<FAM, EntQ24>(X, b);
         return true;
       }
     }
-    run_subtree<E>(X, b);
+    run_subtree<FAM, E>(X, b);
     return true;
   }
 }

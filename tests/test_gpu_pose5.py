@@ -362,3 +362,31 @@ def test_filter_rechecks_on_the_workload(ctx):
     r1 = solve(ctx, g2, precision=1)
     assert r1["stats"]["fp64_rechecks"] == 0
     check_same(r1, solve(ctx, g2, precision=0))
+
+
+@pytest.mark.parametrize("family", ["pose5dof", "pose4dof"])
+def test_device_subtree_search_changes_nothing(ctx, family):
+    """The device search of small subtrees (the last levels of both pose
+    families, one workgroup per cell) gives the host-driven search's result
+    (library knob GV_SUBTREE, read when a solve starts), equal to the
+    oracle's."""
+    import os
+    name = "pose5dof_small" if family == "pose5dof" else "pose4dof_small"
+    g = synth.config(name)
+    ro = oracle.solve(OP(g))
+    res = {}
+    for sub in ("1", "0"):
+        old = os.environ.get("GV_SUBTREE")
+        os.environ["GV_SUBTREE"] = sub
+        try:
+            res[sub] = solve(ctx, g)
+        finally:
+            if old is None:
+                del os.environ["GV_SUBTREE"]
+            else:
+                os.environ["GV_SUBTREE"] = old
+    for sub in ("1", "0"):
+        r = res[sub]
+        assert r["count"] == ro["count"] and r["leaf_index"] == ro["leaf_index"] and r["sector"] == ro["sector"]
+        assert np.array_equal(r["inliers"], ro["inliers"])
+    _say("subtree", family, res["1"]["stats"]["tests"], res["0"]["stats"]["tests"])
