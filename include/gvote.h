@@ -115,10 +115,17 @@ typedef struct {
                                  on its large launches with HIP events and
                                  keeps the one with the least time per byte
                                  of list entries moved;
-                                 launches before that use 8.  The choices are
+                                 launches before that use 8.  Once the count
+                                 grid is chosen, the count pass's surface
+                                 tile (entries per work item: 256, 512 or
+                                 1024) is chosen the same way; 1024 until
+                                 then.  The choices are
                                  read from the file at creation (lines
-                                 "arch CUs family kernel blocks" of this
-                                 device) and written to it when made; an
+                                 "arch CUs family choice value" of this
+                                 device; choice 0 count grid, 1 compaction
+                                 grid (value: blocks per CU), 2 count tile
+                                 (value: log2 entries per item)) and written
+                                 to it when made; an
                                  unreadable or unwritable file only means
                                  tuning again.  Results never depend on it. */
   int kernel_timing;          /* 1: time the incidence and compaction kernels

@@ -219,8 +219,18 @@ constexpr int kGridDefault = 8;
 // against 1.00 s for items down to 64 or 256 entries, 16 or 64 per CU).
 constexpr uint32_t kItemLogMin5 = 8;
 constexpr uint64_t kItemsPerCu5 = 16;
+// Surface tile of the count pass: log2 of the entries per work item (256,
+// 512 or 1024), tuned like the grid on batches of at least kTuneMinBytes
+// once the count kernel's grid is chosen, so that every sample runs at that
+// grid.  A sample is the count kernel's event time per entry byte of a
+// batch whose items were cut at the candidate size.
+constexpr int kTileCand[] = {8, 9, 10};
+constexpr int kNTile = 3;
+constexpr int kTuneKinds = 3;  // 0 count grid, 1 compaction grid, 2 count tile
+inline int tune_ncand(int kind) { return kind == 2 ? kNTile : kNCand; }
+inline int tune_value(int kind, int k) { return kind == 2 ? kTileCand[k] : kTuneCand[k]; }
 struct gvi_tune_slot {
-  int chosen = 0;  // blocks per CU once chosen
+  int chosen = 0;  // blocks per CU (kinds 0, 1) or log2 entries per item (kind 2) once chosen
   int next = 0;    // next candidate to try
   double r[kNCand][kTuneSamples] = {};  // per-sample event time per byte
   int n[kNCand] = {};
@@ -263,10 +273,10 @@ struct gv_ctx {
   uint64_t batch_n = 0;
   // packed 8-byte list entries where the lattice bounds allow (GV_PACK=0 off)
   bool pack = true;
-  // launch-shape autotuner: per family (index 1..kLastFam) and kernel
-  // (0 count, 1 compaction)
+  // launch-shape autotuner: per family (index 1..kLastFam) and choice
+  // (0 count grid, 1 compaction grid, 2 count tile)
   std::mutex tmu;
-  gvi_tune_slot tune[kLastFam + 1][2];
+  gvi_tune_slot tune[kLastFam + 1][kTuneKinds];
   bool autotune = true;
   uint64_t tune_min = kTuneMinBytes;  // launches of fewer entry bytes are not tuning samples
   std::string tune_path;   // autotune cache file ("" = keep choices in memory)
@@ -623,6 +633,7 @@ struct Run {
   uint64_t dive_cells = 4096;             // cells from which the diversified dive goes greedy
   bool root_dive = false;                 // greedy dive from the root cells first (the diversified dive subsumes it)
   int grid_env[2] = {0, 0};               // GV_GRID_COUNT / GV_GRID_COMPACT: fixed blocks per CU (experiments)
+  uint32_t tile_env = 0;                  // GV_ITEM_ENTRIES: fixed entries per work item (256, 512 or 1024)
   uint64_t waits = 0;                     // host waits for the stream, and their time
   double wait_ms = 0.0;
   bool trace = false;                     // GV_TRACE=1: one stderr line per expansion
@@ -652,6 +663,7 @@ struct Run {
     int kind;        // 0 count, 1 compaction
     int cand;        // autotuner candidate index, -1 when not a tuning sample
     uint64_t units;  // entry bytes the launch read (count) or wrote (compaction)
+    int tcand;       // count tile candidate index, -1 when not a tile sample
   };
   std::vector<EvRec> ev;
   size_t ev_used = 0;
@@ -805,7 +817,9 @@ uint64_t d2h1(Run& X, const T* p) {
 }
 
 // Autotune cache file: one line per choice,
-//   <arch> <compute units> <family 1..kLastFam> <kernel 0 count | 1 compaction> <blocks per CU>
+//   <arch> <compute units> <family 1..kLastFam> <choice> <value>
+// choice 0: count grid, 1: compaction grid (value: blocks per CU);
+// choice 2: count tile (value: log2 entries per work item)
 void tune_load(gv_ctx* c) {
   if (c->tune_path.empty()) return;
   FILE* f = std::fopen(c->tune_path.c_str(), "r");
@@ -813,9 +827,9 @@ void tune_load(gv_ctx* c) {
   char arch[128];
   int ncu, fam, kind, gpc;
   while (std::fscanf(f, "%127s %d %d %d %d", arch, &ncu, &fam, &kind, &gpc) == 5) {
-    if (c->arch != arch || ncu != c->n_cu || fam < 1 || fam > kLastFam || kind < 0 || kind > 1) continue;
-    for (int k = 0; k < kNCand; k++)
-      if (kTuneCand[k] == gpc) c->tune[fam][kind].chosen = gpc;
+    if (c->arch != arch || ncu != c->n_cu || fam < 1 || fam > kLastFam || kind < 0 || kind >= kTuneKinds) continue;
+    for (int k = 0; k < tune_ncand(kind); k++)
+      if (tune_value(kind, k) == gpc) c->tune[fam][kind].chosen = gpc;
   }
   std::fclose(f);
 }
@@ -829,8 +843,8 @@ void tune_save(gv_ctx* c) {
     char arch[128];
     int ncu, fam, kind, gpc;
     while (std::fscanf(f, "%127s %d %d %d %d", arch, &ncu, &fam, &kind, &gpc) == 5) {
-      const bool mine = c->arch == arch && ncu == c->n_cu && fam >= 1 && fam <= kLastFam && kind >= 0 && kind <= 1 &&
-                        c->tune[fam][kind].chosen;
+      const bool mine = c->arch == arch && ncu == c->n_cu && fam >= 1 && fam <= kLastFam && kind >= 0 &&
+                        kind < kTuneKinds && c->tune[fam][kind].chosen;
       if (!mine) keep.push_back(std::string(arch) + " " + std::to_string(ncu) + " " + std::to_string(fam) + " " +
                                 std::to_string(kind) + " " + std::to_string(gpc));
     }
@@ -841,7 +855,7 @@ void tune_save(gv_ctx* c) {
   if (!f) return;
   for (const std::string& l : keep) std::fprintf(f, "%s\n", l.c_str());
   for (int fam = 1; fam <= kLastFam; fam++)
-    for (int kind = 0; kind < 2; kind++)
+    for (int kind = 0; kind < kTuneKinds; kind++)
       if (c->tune[fam][kind].chosen)
         std::fprintf(f, "%s %d %d %d %d\n", c->arch.c_str(), c->n_cu, fam, kind, c->tune[fam][kind].chosen);
   std::fclose(f);
@@ -857,23 +871,29 @@ void tune_sample(Run& X, int kind, int cand, double ms, uint64_t units) {
   if (t.chosen) return;
   if (t.n[cand] >= kTuneSamples) return;
   t.r[cand][t.n[cand]++] = ms / std::max(1.0, (double)units);
-  for (int k = 0; k < kNCand; k++)
+  const int nc = tune_ncand(kind);
+  for (int k = 0; k < nc; k++)
     if (t.n[k] < kTuneSamples) return;
   double med[kNCand];
-  for (int k = 0; k < kNCand; k++) {
+  for (int k = 0; k < nc; k++) {
     double v[kTuneSamples];
     std::copy(t.r[k], t.r[k] + kTuneSamples, v);
     std::sort(v, v + kTuneSamples);
     med[k] = 0.5 * (v[kTuneSamples / 2 - 1] + v[kTuneSamples / 2]);
   }
   int best = 0;
-  for (int k = 1; k < kNCand; k++)
+  for (int k = 1; k < nc; k++)
     if (med[k] < med[best]) best = k;
-  t.chosen = kTuneCand[best];
+  t.chosen = tune_value(kind, best);
   if (X.trace) {
-    std::fprintf(stderr, "gv: autotune family %d %s:", X.P0.fam, kind ? "compaction" : "count");
-    for (int k = 0; k < kNCand; k++) std::fprintf(stderr, " %d:%.3g", kTuneCand[k], med[k] * 1e9);
-    std::fprintf(stderr, " ps/byte -> %d blocks per CU\n", t.chosen);
+    static const char* what[kTuneKinds] = {"count grid", "compaction grid", "count tile"};
+    std::fprintf(stderr, "gv: autotune family %d %s:", X.P0.fam, what[kind]);
+    for (int k = 0; k < nc; k++)
+      std::fprintf(stderr, " %d:%.3g", kind == 2 ? 1 << tune_value(kind, k) : tune_value(kind, k), med[k] * 1e9);
+    if (kind == 2)
+      std::fprintf(stderr, " ps/byte -> %d entries per item\n", 1 << t.chosen);
+    else
+      std::fprintf(stderr, " ps/byte -> %d blocks per CU\n", t.chosen);
   }
   tune_save(c);
 }
@@ -900,10 +920,27 @@ int grid_pick(Run& X, int kind, uint64_t units, int* cand) {
   return kTuneCand[*cand];
 }
 
-std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind, int cand = -1, uint64_t units = 0) {
+// log2 of the entries per work item of a batch whose count pass reads
+// `units` entry bytes; *cand as in grid_pick.  Samples are taken only once the
+// family's count grid is chosen; the allocation-free solve keeps GV_ITEM.
+uint32_t tile_pick(Run& X, uint64_t units, int* cand) {
+  *cand = -1;
+  if (X.tile_env) return X.tile_env;
+  gv_ctx* c = X.ctx;
+  if (X.fixed || !c->autotune) return GV_ITEM_LOG;
+  std::lock_guard<std::mutex> g(c->tmu);
+  gvi_tune_slot& t = c->tune[X.P0.fam][2];
+  if (t.chosen) return (uint32_t)t.chosen;
+  if (units < c->tune_min || !c->tune[X.P0.fam][0].chosen) return GV_ITEM_LOG;
+  *cand = t.next;
+  t.next = (t.next + 1) % kNTile;
+  return (uint32_t)kTileCand[*cand];
+}
+
+std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind, int cand = -1, uint64_t units = 0, int tcand = -1) {
   gv_ctx* c = X.ctx;
   std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
-  if ((!c->kernel_timing && cand < 0) || X.fixed) return p;
+  if ((!c->kernel_timing && cand < 0 && tcand < 0) || X.fixed) return p;
   std::vector<hipEvent_t>& pool = *X.ev_pool;
   while (pool.size() < 2 * (X.ev_used + 1)) {
     hipEvent_t e;
@@ -914,7 +951,7 @@ std::pair<hipEvent_t, hipEvent_t> ev_begin(Run& X, int kind, int cand = -1, uint
   p.second = pool[2 * X.ev_used + 1];
   X.ev_used++;
   HIPCHK(hipEventRecord(p.first, X.st));
-  X.ev.push_back({p, kind, cand, units});
+  X.ev.push_back({p, kind, cand, units, tcand});
   return p;
 }
 void ev_end(Run& X, std::pair<hipEvent_t, hipEvent_t> p) {
@@ -1011,10 +1048,14 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   pa->own_ents = own_ents;
   pa->unit = b.unit;
 
-  // work items: at most 2^ilog <= GV_ITEM entries of one cell each
-  uint32_t ilog = GV_ITEM_LOG;
+  // work items: at most 2^ilog <= GV_ITEM entries of one cell each (the
+  // count pass's surface tile, autotuned on large batches)
+  const uint64_t tbytes = fam_masked(FAM) ? nlive * (sizeof(E) + sizeof(M)) : nlive * sizeof(E);
+  int tcand;
+  uint32_t ilog = tile_pick(X, tbytes, &tcand);
   if constexpr (FAM == FAM_POSE5DOF)
-    while (ilog > kItemLogMin5 && (b.nent >> ilog) < (uint64_t)X.ctx->n_cu * kItemsPerCu5) ilog--;
+    if (tcand < 0 && !X.tile_env)
+      while (ilog > kItemLogMin5 && (b.nent >> ilog) < (uint64_t)X.ctx->n_cu * kItemsPerCu5) ilog--;
   uint32_t* nitem = b.ncell <= GV_SMALL_N ? nullptr : dalloc<uint32_t>(X, b.ncell);
   pa->ioff = dalloc<uint32_t>(X, b.ncell);
   pa->max_items = b.ncell + (b.nent >> ilog) + 1;
@@ -1050,10 +1091,9 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
     k_zero3<<<gs_grid(X, std::max(nk, ni)), 256, 0, X.st>>>(ccnt, nk, pa->cnent, nk, itemcnt, ni);
   }
   int cand;
-  const uint64_t tbytes = linear ? nlive * sizeof(E) : nlive * (sizeof(E) + sizeof(M));
   const int gpc = grid_pick(X, 0, tbytes, &cand);
   const unsigned grid = (unsigned)std::min<uint64_t>((pa->max_items + 3) / 4, (uint64_t)X.ctx->n_cu * gpc);
-  auto evp = ev_begin(X, 0, cand, tbytes);
+  auto evp = ev_begin(X, 0, cand, tbytes, tcand);
   X.stats.test_launches++;
   X.stats.test_bytes += tbytes;
   if constexpr (FAM == FAM_POSE5DOF) {
@@ -1641,6 +1681,11 @@ void epoch_begin(Run& X) {
   if (const char* cb = std::getenv("GV_CHUNK_BYTES")) X.chunk_bytes = std::max<uint64_t>(4096, std::strtoull(cb, nullptr, 10));
   if (const char* e = std::getenv("GV_GRID_COUNT")) X.grid_env[0] = std::max(1, std::min(64, atoi(e)));
   if (const char* e = std::getenv("GV_GRID_COMPACT")) X.grid_env[1] = std::max(1, std::min(64, atoi(e)));
+  if (const char* e = std::getenv("GV_ITEM_ENTRIES")) {
+    const int v = atoi(e);
+    for (int k = 0; k < kNTile; k++)
+      if (v == 1 << kTileCand[k]) X.tile_env = (uint32_t)kTileCand[k];
+  }
   const uint32_t np = (uint32_t)X.probs.size();
   X.ooff.assign(np + 1, 0);
   for (uint32_t p = 0; p < np; p++) X.ooff[p + 1] = X.ooff[p] + (uint64_t)X.probs[p]->n;
@@ -2240,6 +2285,7 @@ void epoch_finish(Run& X) {
     HIPCHK(hipEventElapsedTime(&ms, e.e.first, e.e.second));
     if (X.ctx->kernel_timing) (e.kind == 0 ? X.stats.test_ms : X.stats.compact_ms) += (double)ms;
     if (e.cand >= 0) tune_sample(X, e.kind, e.cand, (double)ms, e.units);
+    if (e.tcand >= 0) tune_sample(X, 2, e.tcand, (double)ms, e.units);
   }
   if (X.ctx->kernel_timing) X.stats.compact_bytes += d2h1(X, X.dreads) / 8;
   X.stats.fp64_rechecks = rech;

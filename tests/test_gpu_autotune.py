@@ -1,10 +1,11 @@
-"""Launch-shape autotuner and launch grids.
+"""Launch-shape autotuner: launch grids and surface tiles.
 
-The count and compaction kernels loop over list items, so their grid changes
-nothing but speed: results with the autotuner trying its candidates, with
-every fixed grid, and with choices read back from the cache file are all
+The count and compaction kernels loop over list items, so their grid and the
+number of entries per item (the count pass's surface tile) change nothing but
+speed: results with the autotuner trying its candidates, with every fixed
+grid and tile, and with choices read back from the cache file are all
 identical, and equal to the oracle's.  The cache file holds one valid line
-per tuned (family, kernel).
+per tuned (family, choice): 0 count grid, 1 compaction grid, 2 count tile.
 """
 import os
 import sys
@@ -18,6 +19,7 @@ from paper_2107_11810_amd import synth
 pytestmark = pytest.mark.gpu
 
 CANDIDATES = {2, 4, 8, 16, 32}
+TILE_LOGS = {8, 9, 10}
 
 
 def _say(*a):
@@ -85,19 +87,20 @@ def test_autotune_cache_and_results(tmp_path, name):
     with Env(GV_TUNE_MIN_BYTES=0):
         c = gvote.Context(0, autotune_cache=path)
         try:
-            for i in range(24):
+            for i in range(64):
                 _say("tune", name, i)
                 assert same(solve(c, g), r0)
                 kinds = {k for (_, _, f, k, _) in read_lines(path) if f == fam}
-                if kinds == {0, 1}:
+                if kinds == {0, 1, 2}:
                     break
         finally:
             c.close()
     lines = read_lines(path)
     mine = [l for l in lines if l[2] == fam]
-    assert {l[3] for l in mine} == {0, 1}, lines
-    for arch, ncu, f, k, blocks in lines:
-        assert ncu > 0 and f in FAMILY.values() and k in (0, 1) and blocks in CANDIDATES
+    assert {l[3] for l in mine} == {0, 1, 2}, lines
+    for arch, ncu, f, k, v in lines:
+        assert ncu > 0 and f in FAMILY.values() and k in (0, 1, 2)
+        assert v in (TILE_LOGS if k == 2 else CANDIDATES)
     before = open(path).read()
     # choices read back: no more tuning samples, same results, file unchanged
     with Env(GV_TUNE_MIN_BYTES=0):
@@ -127,3 +130,24 @@ def test_fixed_grids_same_result(name, grid):
     d = 4 if g["family"] == "pose4dof" else len(g["lo"])
     for j in range(d):
         assert r["point"][j] == ro["point"][j]
+
+
+@pytest.mark.parametrize("tile", [256, 512])
+@pytest.mark.parametrize("name", ["line2d_small", "plane3d_small", "ray3d_small", "pose4dof_small", "sim2d_small",
+                                  "pose5dof_tiny"])
+def test_fixed_tiles_same_result(name, tile):
+    """Every batch cut into items of `tile` entries (instead of 1024, or the
+    5-DoF family's smaller items for small batches) gives the oracle's
+    result."""
+    from paper_2107_11810_amd import gvote
+    g = synth.config(name)
+    _say("tile", name, tile)
+    ro = oracle.solve(oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"]))
+    with Env(GV_ITEM_ENTRIES=tile):
+        c = gvote.Context(0)
+        try:
+            r = solve(c, g)
+        finally:
+            c.close()
+    assert r["count"] == ro["count"] and r["leaf_index"] == ro["leaf_index"] and r["sector"] == ro["sector"]
+    assert np.array_equal(r["inliers"], ro["inliers"])
