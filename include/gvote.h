@@ -175,6 +175,8 @@ typedef struct {
   double ms_queued;           /* gv_submit: time from submission until a
                                  serving lane admitted the problem (memory
                                  admission); 0 for gv_solve */
+  uint64_t compact_write_bytes; /* with kernel_timing: the part of
+                                 compact_bytes that is child entries written */
 } gv_stats;
 
 typedef struct {

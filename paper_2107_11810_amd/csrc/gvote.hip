@@ -1483,6 +1483,7 @@ bool materialize(Run& X, Parent* pa, uint32_t r0, uint32_t r1, Batch& nb) {
     auto evp = ev_begin(X, 1, cand, nb.nent * sizeof(EO));
     X.stats.compact_launches++;
     X.stats.compact_bytes += nb.nent * sizeof(EO);
+    X.stats.compact_write_bytes += nb.nent * sizeof(EO);
     if constexpr (fam_masked(FAM)) {
       k_compact<FAM, E, EO, M, true><<<grid, 256, 0, X.st>>>(
           lv, pa->cells, pa->items, pa->nitems, pa->ioff, pa->itemoff, pa->istride, (const E*)pa->ents,

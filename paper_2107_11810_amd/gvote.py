@@ -52,7 +52,7 @@ class Stats(ctypes.Structure):
                 ("test_ms", ctypes.c_double), ("compact_ms", ctypes.c_double),
                 ("test_launches", ctypes.c_uint64), ("compact_launches", ctypes.c_uint64),
                 ("test_bytes", ctypes.c_uint64), ("compact_bytes", ctypes.c_uint64),
-                ("ms_queued", ctypes.c_double)]
+                ("ms_queued", ctypes.c_double), ("compact_write_bytes", ctypes.c_uint64)]
 
 
 class Result(ctypes.Structure):
@@ -199,7 +199,7 @@ class Context:
                       "ms_total": s.ms_total, "ms_kernels": s.ms_kernels,
                       "test_ms": s.test_ms, "compact_ms": s.compact_ms, "test_launches": s.test_launches,
                       "compact_launches": s.compact_launches, "test_bytes": s.test_bytes,
-                      "compact_bytes": s.compact_bytes},
+                      "compact_bytes": s.compact_bytes, "compact_write_bytes": s.compact_write_bytes},
         }
 
     def report(self, family, cols, lo, hi, eps, tau, cap=1 << 20, canon_c=0.0, precision=FP32_FILTER, group=0):
