@@ -24,6 +24,13 @@ import os
 import sys
 import time
 
+# HIP gives a process four hardware queues unless told otherwise.  The
+# serving lanes (three streams) and the context's own stream then share
+# them, and a lane whose stream shares a queue waits behind the other's
+# kernels; with eight queues every stream has its own.  Read once, when the
+# process first initializes HIP, so it is set before anything else runs.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 

@@ -257,7 +257,11 @@ gv_status gv_parametrize(gv_ctx *ctx, const gv_problem *p, double *t_out, double
  * gv_problem) and return a ticket.  The first call starts the context's
  * serving lanes (three by default: a host thread, HIP stream and allocator
  * each); a free lane takes queued problems as the memory budget allows, so
- * problems run concurrently on the device.  Results equal gv_solve's. */
+ * problems run concurrently on the device.  Results equal gv_solve's.
+ * The lanes overlap best when each stream has a hardware queue of its own:
+ * HIP gives a process four unless GPU_MAX_HW_QUEUES (read when the process
+ * first initializes HIP) asks for more; eight serve three lanes and the
+ * context's stream. */
 gv_status gv_submit(gv_ctx *ctx, const gv_problem *p, uint64_t *ticket);
 
 /* Wait up to timeout_ms (0: do not wait, <0: forever) for a ticket; on
