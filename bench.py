@@ -28,8 +28,14 @@ import time
 # serving lanes (three streams) and the context's own stream then share
 # them, and a lane whose stream shares a queue waits behind the other's
 # kernels; with eight queues every stream has its own.  Read once, when the
-# process first initializes HIP, so it is set before anything else runs.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# process first initializes HIP, so it is set before anything else runs
+# (raised to eight where the environment asks for fewer).
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+except ValueError:
+    _hwq = 0
+if _hwq < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
