@@ -1297,11 +1297,14 @@ Parent* expand(Run& X, Batch& b, bool own_ents, bool dive) {
   k_select_kept<<<nblk(nk), 256, 0, X.st>>>(keepf, keepscan, ccnt, nk, kcnt, kid, pa->rank_of);
   dfree(X, keepf);
   dfree(X, keepscan);
-  // POSE4DOF keeps count order throughout: its bound keeps improving after
-  // the first descent, and its incidence test (not the list traffic) dominates.
-  // The greedy dive keeps one child per cell and takes them all at once, so
-  // their order changes nothing there: parent order, no sort.
-  pa->sorted = !dive && (X.beam || fam_masked(FAM));
+  // Count order only during the first descent.  After it a chunk is capped
+  // by memory alone, so the kept children of a parent mostly go in one
+  // chunk and their order changes little: the 4-DoF and 5-DoF workloads
+  // count the same tests in parent order, and the sort is saved.  Parent
+  // order also makes a chunk a contiguous range of parents, each read once.
+  // The greedy dive keeps one child per cell and takes them all at once:
+  // parent order, no sort.
+  pa->sorted = !dive && X.beam;
   pa->scount = dalloc<uint32_t>(X, nkept);
   if (!pa->sorted) {
     // after the first descent the bounds are strong: keep parent order so
