@@ -41,6 +41,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def median(xs):
+    v = sorted(xs)
+    h = len(v) // 2
+    return float(v[h]) if len(v) % 2 else 0.5 * (v[h - 1] + v[h])
+
 VALU_FP32_TFLOPS = 157.3
 # binary32 VALU lane-ops: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed)
 VALU_LANE_OPS = 256 * 64 * 2.4e9
@@ -445,6 +452,9 @@ def single_leg(name, args, ctx, warmup, steps):
         "g": g, "sec": sec, "steps": steps, "tests": tests, "results": results, "roofline": roof,
         "tests_per_s": tests / sec, "solves_per_s": steps / sec, "ms_per_solve": 1e3 * sec / steps,
         "tests_per_solve": tests / steps, "count": results[0]["count"],
+        # each solve's own wall time, measured by the library (device-resident inputs to the result
+        # in host memory): the median of the timed solves
+        "ms_per_solve_median": median([r["stats"]["ms_total"] for r in results]),
         "deterministic": len({(r["count"], r["leaf_index"]) for r in results}) == 1, "golden": golden,
         "rechecks_per_solve": sum(r["stats"]["fp64_rechecks"] for r in results) / steps,
     }
@@ -532,6 +542,7 @@ def main():
         "config": {"workload": args.workload, "description": W["desc"], "n": n, "eps": g["eps"],
                    "canon_c": 1.0, "precision": "fp32_filter" if args.precision else "fp64_plain"},
         "solves_per_s": head["solves_per_s"],
+        "ms_per_solve_median": round(head["ms_per_solve_median"], 3),
         "tests_per_solve": head["tests_per_solve"],
         "count": head["count"],
         "deterministic": head["deterministic"],
@@ -545,7 +556,8 @@ def main():
         pl = single_leg("pose4dof_1m", args, ctx, 3, 10)
         out["pose4dof_1m"] = {
             "description": WORKLOADS["pose4dof_1m"]["desc"], "tests_per_s": pl["tests_per_s"],
-            "ms_per_solve": pl["ms_per_solve"], "solves_per_s": pl["solves_per_s"],
+            "ms_per_solve": pl["ms_per_solve"], "ms_per_solve_median": round(pl["ms_per_solve_median"], 3),
+            "solves_per_s": pl["solves_per_s"],
             "tests_per_solve": pl["tests_per_solve"], "count": pl["count"], "roofline": pl["roofline"],
             "rechecks_per_solve": pl["rechecks_per_solve"], "golden": pl["golden"]}
         out["pose4dof_1m"]["refine"] = pl["refine"]
@@ -555,7 +567,8 @@ def main():
         p5 = single_leg("pose5dof_20k", args, ctx, 3, 10)
         out["pose5dof_20k"] = {
             "description": WORKLOADS["pose5dof_20k"]["desc"], "tests_per_s": p5["tests_per_s"],
-            "ms_per_solve": p5["ms_per_solve"], "solves_per_s": p5["solves_per_s"],
+            "ms_per_solve": p5["ms_per_solve"], "ms_per_solve_median": round(p5["ms_per_solve_median"], 3),
+            "solves_per_s": p5["solves_per_s"],
             "tests_per_solve": p5["tests_per_solve"], "count": p5["count"], "roofline": p5["roofline"],
             "rechecks_per_solve": p5["rechecks_per_solve"], "golden": p5["golden"], "refine": p5["refine"]}
         if p5["golden"] is not None:
