@@ -540,7 +540,11 @@ def main():
                   else ("f32+f64" if args.precision else "f64")),
         "data": "synthetic",
         "config": {"workload": args.workload, "description": W["desc"], "n": n, "eps": g["eps"],
-                   "canon_c": 1.0, "precision": "fp32_filter" if args.precision else "fp64_plain"},
+                   "canon_c": 1.0,
+                   # the linear families decide every test exactly on an integer lattice, so the
+                   # precision setting (binary32 filter or binary64) applies to the pose families only
+                   "precision": ("int32_lattice" if g["family"] not in ("pose4dof", "pose5dof")
+                                 else ("fp32_filter" if args.precision else "fp64_plain"))},
         "solves_per_s": head["solves_per_s"],
         "ms_per_solve_median": round(head["ms_per_solve_median"], 3),
         "tests_per_solve": head["tests_per_solve"],
