@@ -289,3 +289,21 @@ def test_block_boundary_parity(ctx, fam, n):
     ro = oracle.solve(OP(g))
     rg = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
     check_same(g, rg, ro)
+
+
+def test_device_work_per_observation_stops_growing_with_n(ctx):
+    """The line-fitting recipe (5% inliers, eps 0.005) at n = 1e4, 1e5 and
+    1e6 on the device: incidence tests per observation change by less than
+    25% from one size to the next (the search is linear in n at fixed eps,
+    Sec. 3.2), and the depth found covers the planted inliers (about 1.8e3
+    tests per observation at every size on MI355X)."""
+    per = []
+    for n in (10_000, 100_000, 1_000_000):
+        g = synth.line2d(seed=101, n=n, n_in=n // 20)
+        _say("linear in n", n)
+        r = ctx.solve(g["family"], g["cols"], g["lo"], g["hi"], g["eps"])
+        per.append(r["stats"]["tests"] / n)
+        _say("  tests per observation", per[-1], "count", r["count"])
+        assert r["count"] >= 0.9 * (n // 20)
+    for a, b in zip(per, per[1:]):
+        assert 0.75 <= b / a <= 1.25, per

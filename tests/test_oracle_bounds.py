@@ -605,3 +605,23 @@ def test_point_near_the_planted_truth(name, seed):
         if g["family"] == "pose4dof" and j == 3:
             diff = min(diff, 2 * math.pi - diff)
         assert diff <= 2 * g["eps"][j] + side, (j, r["point"][j], tr[j])
+
+
+# ----------------------------------------------------------------------------
+# Work linear in n at fixed eps (Sec. 3.2: canonization bounds the number of
+# distinct surfaces a cell can hold, so below the first levels the work per
+# observation stops growing; the paper states the search is linear in n).
+# ----------------------------------------------------------------------------
+def test_work_per_observation_stops_growing_with_n():
+    """The line-fitting recipe (5% inliers, eps 0.005) at n = 4000, 16000 and
+    32000: incidence tests per observation change by less than 15% between
+    sizes (quadratic work would double them with every doubling of n), and the
+    depth found grows in proportion to the planted inliers."""
+    per = []
+    for n in (4000, 16000, 32000):
+        g = synth.line2d(seed=101, n=n, n_in=n // 20)
+        o = oracle.solve(oracle.Problem(g["family"], g["cols"], g["lo"], g["hi"], g["eps"]))
+        per.append(o["tests"] / n)
+        assert o["count"] >= 0.9 * (n // 20), (n, o["count"])
+    for a, b in zip(per, per[1:]):
+        assert 0.85 <= b / a <= 1.15, per
