@@ -368,25 +368,29 @@ def test_filter_rechecks_on_the_workload(ctx):
 def test_device_subtree_search_changes_nothing(ctx, family):
     """The device search of small subtrees (the last levels of both pose
     families, one workgroup per cell) gives the host-driven search's result
-    (library knob GV_SUBTREE, read when a solve starts), equal to the
-    oracle's."""
+    (library knobs GV_SUBTREE and GV_SUBTREE_FROM, read when a solve starts),
+    equal to the oracle's.  From level 2 on, most cells of the upper levels
+    hold more entries than a workgroup takes and go back to the host-driven
+    path, while the small ones are searched to the leaves on the device."""
     import os
     name = "pose5dof_small" if family == "pose5dof" else "pose4dof_small"
     g = synth.config(name)
     ro = oracle.solve(OP(g))
     res = {}
-    for sub in ("1", "0"):
-        old = os.environ.get("GV_SUBTREE")
-        os.environ["GV_SUBTREE"] = sub
+    settings = {"on": {"GV_SUBTREE": "1"}, "off": {"GV_SUBTREE": "0"},
+                "from level 2": {"GV_SUBTREE": "1", "GV_SUBTREE_FROM": "2"}}
+    for key, kv in settings.items():
+        old = {k: os.environ.get(k) for k in kv}
+        os.environ.update(kv)
         try:
-            res[sub] = solve(ctx, g)
+            res[key] = solve(ctx, g)
         finally:
-            if old is None:
-                del os.environ["GV_SUBTREE"]
-            else:
-                os.environ["GV_SUBTREE"] = old
-    for sub in ("1", "0"):
-        r = res[sub]
-        assert r["count"] == ro["count"] and r["leaf_index"] == ro["leaf_index"] and r["sector"] == ro["sector"]
-        assert np.array_equal(r["inliers"], ro["inliers"])
-    _say("subtree", family, res["1"]["stats"]["tests"], res["0"]["stats"]["tests"])
+            for k, v in old.items():
+                if v is None:
+                    del os.environ[k]
+                else:
+                    os.environ[k] = v
+    for key, r in res.items():
+        assert r["count"] == ro["count"] and r["leaf_index"] == ro["leaf_index"] and r["sector"] == ro["sector"], key
+        assert np.array_equal(r["inliers"], ro["inliers"]), key
+    _say("subtree", family, {k: r["stats"]["tests"] for k, r in res.items()})
