@@ -631,6 +631,7 @@ struct Run {
   uint64_t chunk_bytes = 0;               // device bytes one materialized chunk may need
   uint64_t first_cells = 262144;          // cells in the first chunk of every expansion
   uint64_t dive_cells = 4096;             // cells from which the diversified dive goes greedy
+  bool reuse = true;                      // the main search starts at the dive's greedy level (GV_REUSE=0: off)
   bool root_dive = false;                 // greedy dive from the root cells first (the diversified dive subsumes it)
   int grid_env[2] = {0, 0};               // GV_GRID_COUNT / GV_GRID_COMPACT: fixed blocks per CU (experiments)
   uint32_t tile_env = 0;                  // GV_ITEM_ENTRIES: fixed entries per work item (256, 512 or 1024)
@@ -1710,6 +1711,7 @@ void epoch_begin(Run& X) {
   if (const char* dc = std::getenv("GV_DIVE_CELLS")) dc1 = std::strtoull(dc, nullptr, 10);
   X.first_cells = fc1 * (uint64_t)np;
   X.dive_cells = dc1 * (uint64_t)np;
+  if (const char* e = std::getenv("GV_REUSE")) X.reuse = atoi(e) != 0;
   if (const char* rd = std::getenv("GV_ROOT_DIVE")) X.root_dive = atoi(rd) != 0;
   HIPCHK(hipSetDevice(X.ctx->device));
   X.dP = dalloc<ProbC>(X, np);
@@ -1843,6 +1845,15 @@ void start_search(Run& X) {
   // each cell down to a leaf.  Thousands of greedy paths from different
   // coarse cells find a strong bound early where the top-count coarse cells
   // are clutter; like the dive above it only changes bounds, never a result.
+  // When the dive carried every kept child of its full levels, the batch at
+  // which it goes greedy holds every cell of that level that any leaf can be
+  // reached through (cut only against bounds): the main search starts there
+  // instead of expanding the levels above it again.  The result cannot
+  // change (the maximum leaf lies below one of these cells); measured:
+  // pose4dof_1m 53 against 62 ms, eight pose problems of 1e5-1e6 matches
+  // 8-14% faster, the 256-problem set 0.77 against 0.83 s.
+  Batch reuse{};
+  bool have_reuse = false;
   if (X.dive_cells > 0 && !X.report) {
     const bool beam = X.beam;
     Batch b;
@@ -1854,9 +1865,20 @@ void start_search(Run& X) {
     HIPCHK(hipMemcpyAsync(b.cells, dcells, cells.size() * sizeof(Cell), hipMemcpyDeviceToDevice, X.st));
     b.ents = ents;
     bool own = false;
+    bool carried = X.reuse && !X.root_dive && !X.fixed;
     while (true) {
       const bool dv = b.ncell >= X.dive_cells;
-      Parent* pa = expand_at<FAM, E, M>(X, b, own, dv);
+      bool keep = false;
+      if (dv && carried && !have_reuse && b.level > 0) {
+        // the greedy expansion below keeps this batch's entries (not owned)
+        // and frees its own copy of the cell array
+        reuse = b;
+        reuse.cells = dalloc<Cell>(X, b.ncell);
+        HIPCHK(hipMemcpyAsync(reuse.cells, b.cells, (size_t)b.ncell * sizeof(Cell), hipMemcpyDeviceToDevice, X.st));
+        have_reuse = true;
+        keep = true;
+      }
+      Parent* pa = expand_at<FAM, E, M>(X, b, keep ? false : own, dv);
       if (!pa) break;
       uint32_t r1 = pa->nkept;
       if (!dv) {
@@ -1867,6 +1889,7 @@ void start_search(Run& X) {
           plan_chunks(X, pa, ch);
           r1 = ch.front().second;
         }
+        if (r1 != pa->nkept) carried = false;
       }
       pa->pending = 1;
       if (!materialize_at<FAM, E, M>(X, pa, 0, r1, b)) break;
@@ -1876,12 +1899,18 @@ void start_search(Run& X) {
   }
   Task t{};
   t.chunk = false;
-  t.b.level = 0;
-  t.b.ncell = (uint32_t)cells.size();
-  t.b.nent = tot;
-  t.b.unit = unit;
-  t.b.cells = dcells;
-  t.b.ents = ents;
+  if (have_reuse) {
+    t.b = reuse;
+    dfree(X, dcells);
+    dfree(X, ents);
+  } else {
+    t.b.level = 0;
+    t.b.ncell = (uint32_t)cells.size();
+    t.b.nent = tot;
+    t.b.unit = unit;
+    t.b.cells = dcells;
+    t.b.ents = ents;
+  }
   X.stack.push_back(t);
   X.own_first = true;
 }

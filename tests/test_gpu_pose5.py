@@ -394,3 +394,28 @@ def test_device_subtree_search_changes_nothing(ctx, family):
         assert r["count"] == ro["count"] and r["leaf_index"] == ro["leaf_index"] and r["sector"] == ro["sector"], key
         assert np.array_equal(r["inliers"], ro["inliers"]), key
     _say("subtree", family, {k: r["stats"]["tests"] for k, r in res.items()})
+
+
+@pytest.mark.parametrize("name", ["pose4dof_small", "pose5dof_small", "plane3d_small", "line2d_small", "sim2d_small"])
+def test_main_search_from_the_dive_level_changes_nothing(ctx, name):
+    """The main search starting at the level where the diversified dive goes
+    greedy (every cell of that level the dive carried, GV_REUSE=1, the
+    default) and starting at the root (GV_REUSE=0) give the oracle's result."""
+    import os
+    g = synth.config(name)
+    ro = oracle.solve(OP(g))
+    res = {}
+    for v in ("1", "0"):
+        old = os.environ.get("GV_REUSE")
+        os.environ["GV_REUSE"] = v
+        try:
+            res[v] = solve(ctx, g)
+        finally:
+            if old is None:
+                del os.environ["GV_REUSE"]
+            else:
+                os.environ["GV_REUSE"] = old
+    for v, r in res.items():
+        assert r["count"] == ro["count"] and r["leaf_index"] == ro["leaf_index"] and r["sector"] == ro["sector"], v
+        assert np.array_equal(r["inliers"], ro["inliers"]), v
+    _say("reuse", name, {k: r["stats"]["tests"] for k, r in res.items()})
